@@ -1,0 +1,269 @@
+"""ctypes binding of the FP64 C oracle (``pic_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the CPU-baseline leg of the benchmark, never by the library.  The oracle works
+in SI units and FP64; float32 GPU states are widened before they are passed in.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "pic_oracle.c")
+LIB = os.path.join(HERE, "_liboracle.so")
+
+ORC_OK, ORC_EINVAL, ORC_ERANGE, ORC_ECFL, ORC_EOVERFLOW = 0, 1, 2, 3, 4
+W_UNIT = 2.0 ** -20
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA target)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
+            os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "pic_oracle.h"))):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+                               "-ffp-contract=off", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Grid(C.Structure):
+    _fields_ = [("ndim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double * 3), ("bc", C.c_int * 3),
+                ("depth2d", C.c_double), ("quantized", C.c_int)]
+
+
+class _Pot(C.Structure):
+    _fields_ = [("D", C.c_double), ("r0", C.c_double), ("s_rep", C.c_double), ("c_att", C.c_double),
+                ("g_clamp", C.c_double), ("n_floor", C.c_double), ("mass", C.c_double)]
+
+
+class _Diag(C.Structure):
+    _fields_ = [("ke", C.c_double), ("pe", C.c_double), ("px", C.c_double), ("py", C.c_double),
+                ("pz", C.c_double), ("wsum", C.c_double), ("bond", C.c_double), ("step", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        P = C.POINTER
+        d, i64, i32 = C.c_double, C.c_int64, C.c_int32
+        _lib.orc_num_nodes.restype = i64
+        _lib.orc_num_nodes.argtypes = [P(_Grid)]
+        _lib.orc_num_cells.restype = i64
+        _lib.orc_num_cells.argtypes = [P(_Grid)]
+        _lib.orc_deposit.argtypes = [P(_Grid), i64, P(i32), P(d), P(i32), P(i64), P(d)]
+        _lib.orc_density.argtypes = [P(_Grid), P(d), P(d)]
+        _lib.orc_gradient.argtypes = [P(_Grid), P(d), P(d)]
+        _lib.orc_gather.argtypes = [P(_Grid), P(d), P(d), i32, P(d), P(d), P(d)]
+        _lib.orc_neighbour_distances.argtypes = [P(_Pot), d, d, P(d), P(d)]
+        _lib.orc_local_force.argtypes = [P(_Pot), C.c_int, d, P(d), P(d)]
+        _lib.orc_phi_prime.restype = d
+        _lib.orc_phi_prime.argtypes = [P(_Pot), d]
+        _lib.orc_phi.restype = d
+        _lib.orc_phi.argtypes = [P(_Pot), d]
+        _lib.orc_energy_density.restype = d
+        _lib.orc_energy_density.argtypes = [P(_Pot), d]
+        _lib.orc_forces.argtypes = [P(_Grid), P(_Pot), P(d), i64, P(i32), P(d), P(d)]
+        _lib.orc_push_one.argtypes = [P(_Grid), P(_Pot), d, P(d), P(i32), P(d), P(d)]
+        _lib.orc_kick.argtypes = [P(_Grid), P(_Pot), d, d, i64, P(d), P(d)]
+        _lib.orc_run.argtypes = [P(_Grid), P(_Pot), d, i64, P(i32), P(d), P(d), P(i32), C.c_int,
+                                 C.c_int, P(_Diag)]
+        _lib.orc_calibrate_catt.argtypes = [P(_Grid), P(_Pot), d, C.c_int, C.c_int, P(d), P(d), P(d)]
+        _lib.orc_functional.restype = d
+        _lib.orc_functional.argtypes = [P(_Grid), i64, P(i32), P(d), P(i32), d, d]
+    return _lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def grid_struct(grid, quantized: bool = True) -> _Grid:
+    g = _Grid()
+    g.ndim = grid.ndim
+    for d in range(3):
+        g.n[d] = int(grid.n[d])
+        g.h[d] = float(grid.h[d])
+        g.bc[d] = int(grid.bc[d])
+    g.depth2d = float(grid.depth2d) if grid.ndim == 2 else 0.0
+    g.quantized = 1 if quantized else 0
+    return g
+
+
+def pot_struct(pot) -> _Pot:
+    return _Pot(pot.D, pot.r0, pot.s_rep, pot.c_att, pot.g_clamp, pot.n_floor, pot.mass)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"oracle {what} failed with code {code}")
+        self.code = code
+
+
+def _check(rc, what):
+    if rc != ORC_OK:
+        raise OracleError(rc, what)
+
+
+def num_nodes(grid) -> int:
+    return int(lib().orc_num_nodes(C.byref(grid_struct(grid))))
+
+
+def _state(cell, off, wq, vel=None):
+    cell = np.ascontiguousarray(cell, dtype=np.int32)
+    off = np.ascontiguousarray(off, dtype=np.float64)
+    wq = np.ascontiguousarray(wq, dtype=np.int32)
+    out = [cell, off, wq]
+    if vel is not None:
+        out.append(np.ascontiguousarray(vel, dtype=np.float64))
+    return out
+
+
+def deposit(grid, cell, off, wq, quantized: bool = True):
+    """Node sums: int64 array (quantized) or float64 (unquantized), weight units."""
+    cell, off, wq = _state(cell, off, wq)
+    g = grid_struct(grid, quantized)
+    nn = num_nodes(grid)
+    node_f = np.zeros(nn, dtype=np.float64)
+    node_q = np.zeros(nn, dtype=np.int64) if quantized else None
+    rc = lib().orc_deposit(C.byref(g), cell.shape[0], _ptr(cell, C.c_int32), _ptr(off, C.c_double),
+                           _ptr(wq, C.c_int32), _ptr(node_q, C.c_int64) if quantized else None,
+                           _ptr(node_f, C.c_double))
+    _check(rc, "deposit")
+    return node_q if quantized else node_f
+
+
+def density(grid, node_sums):
+    g = grid_struct(grid)
+    nf = np.ascontiguousarray(node_sums, dtype=np.float64)
+    out = np.zeros_like(nf)
+    lib().orc_density(C.byref(g), _ptr(nf, C.c_double), _ptr(out, C.c_double))
+    return out
+
+
+def gradient(grid, dens):
+    g = grid_struct(grid)
+    dens = np.ascontiguousarray(dens, dtype=np.float64)
+    out = np.zeros(grid.ndim * grid.ncells, dtype=np.float64)
+    lib().orc_gradient(C.byref(g), _ptr(dens, C.c_double), _ptr(out, C.c_double))
+    return out.reshape(grid.ndim, grid.ncells)
+
+
+def gather(grid, dens, G, cell: int, f):
+    g = grid_struct(grid)
+    dens = np.ascontiguousarray(dens, dtype=np.float64)
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    fa = np.ascontiguousarray(list(f) + [0.0] * (3 - len(f)), dtype=np.float64)
+    n_p = C.c_double()
+    G_p = np.zeros(3)
+    lib().orc_gather(C.byref(g), _ptr(dens, C.c_double), _ptr(G, C.c_double), int(cell),
+                     _ptr(fa, C.c_double), C.byref(n_p), _ptr(G_p, C.c_double))
+    return n_p.value, G_p[: grid.ndim].copy()
+
+
+def local_force(pot, ndim, n_p, G_p):
+    Gp = np.ascontiguousarray(list(G_p) + [0.0] * (3 - len(G_p)), dtype=np.float64)
+    F = np.zeros(3)
+    lib().orc_local_force(C.byref(pot_struct(pot)), ndim, float(n_p), _ptr(Gp, C.c_double),
+                          _ptr(F, C.c_double))
+    return F[:ndim].copy()
+
+
+def neighbour_distances(pot, n_p, G_pd):
+    rp, rm = C.c_double(), C.c_double()
+    lib().orc_neighbour_distances(C.byref(pot_struct(pot)), float(n_p), float(G_pd), C.byref(rp),
+                                  C.byref(rm))
+    return rp.value, rm.value
+
+
+def phi_prime(pot, r):
+    return lib().orc_phi_prime(C.byref(pot_struct(pot)), float(r))
+
+
+def phi(pot, r):
+    return lib().orc_phi(C.byref(pot_struct(pot)), float(r))
+
+
+def energy_density(pot, n):
+    return lib().orc_energy_density(C.byref(pot_struct(pot)), float(n))
+
+
+def forces(grid, pot, cell, off, wq, quantized: bool = True):
+    """Per-atom force [ndim, N] (newtons) from the deposit of the same particles."""
+    node = deposit(grid, cell, off, wq, quantized).astype(np.float64)
+    cell, off, wq = _state(cell, off, wq)
+    F = np.zeros((grid.ndim, cell.shape[0]), dtype=np.float64)
+    lib().orc_forces(C.byref(grid_struct(grid, quantized)), C.byref(pot_struct(pot)),
+                     _ptr(node, C.c_double), cell.shape[0], _ptr(cell, C.c_int32),
+                     _ptr(off, C.c_double), _ptr(F, C.c_double))
+    return F
+
+
+def push_one(grid, pot, dt, F, cell, f, v):
+    Fa = np.ascontiguousarray(list(F) + [0.0] * (3 - len(F)), dtype=np.float64)
+    c = C.c_int32(int(cell))
+    fa = np.ascontiguousarray(list(f) + [0.0] * (3 - len(f)), dtype=np.float64)
+    va = np.ascontiguousarray(v, dtype=np.float64).copy()
+    rc = lib().orc_push_one(C.byref(grid_struct(grid)), C.byref(pot_struct(pot)), float(dt),
+                            _ptr(Fa, C.c_double), C.byref(c), _ptr(fa, C.c_double),
+                            _ptr(va, C.c_double))
+    _check(rc, "push")
+    return c.value, fa[: grid.ndim].copy(), va
+
+
+def kick(grid, pot, dt, frac, F, vel):
+    vel = np.ascontiguousarray(vel, dtype=np.float64).copy()
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    lib().orc_kick(C.byref(grid_struct(grid)), C.byref(pot_struct(pot)), float(dt), float(frac),
+                   vel.shape[1], _ptr(F, C.c_double), _ptr(vel, C.c_double))
+    return vel
+
+
+DIAG_FIELDS = ("ke", "pe", "px", "py", "pz", "wsum", "bond", "step")
+
+
+def run(grid, pot, dt, cell, off, vel, wq, nsteps, diag_every=0, quantized=True):
+    """Advance a copy of the state nsteps leapfrog cycles (vel = v(n-1/2)).
+    Returns (cell, off, vel, diags) with diags a list of dicts."""
+    cell, off, wq, vel = _state(np.array(cell, copy=True), np.array(off, dtype=np.float64, copy=True),
+                                wq, np.array(vel, dtype=np.float64, copy=True))
+    nd = 0 if diag_every <= 0 else (nsteps + diag_every - 1) // diag_every
+    diags = (_Diag * max(nd, 1))()
+    rc = lib().orc_run(C.byref(grid_struct(grid, quantized)), C.byref(pot_struct(pot)), float(dt),
+                       cell.shape[0], _ptr(cell, C.c_int32), _ptr(off, C.c_double),
+                       _ptr(vel, C.c_double), _ptr(wq, C.c_int32), int(nsteps), int(diag_every),
+                       diags if nd > 0 else None)
+    _check(rc, "run")
+    out = [{k: getattr(diags[i], k) for k in DIAG_FIELDS} for i in range(nd)]
+    return cell, off, vel, out
+
+
+def start_leapfrog(grid, pot, dt, cell, off, vel, wq, quantized=True):
+    """v(-1/2) = v(0) - F(0)/m dt/2."""
+    F = forces(grid, pot, cell, off, wq, quantized)
+    return kick(grid, pot, dt, -0.5, F, vel)
+
+
+def calibrate_catt(grid, pot, n_solid, slab_layers=8, lattice_k=2):
+    c = C.c_double()
+    W = C.c_double()
+    ys = C.c_double()
+    rc = lib().orc_calibrate_catt(C.byref(grid_struct(grid, False)), C.byref(pot_struct(pot)),
+                                  float(n_solid), int(slab_layers), int(lattice_k), C.byref(c),
+                                  C.byref(W), C.byref(ys))
+    _check(rc, "calibrate")
+    return c.value, W.value, ys.value
+
+
+def functional(grid, cell, off, wq, y_s, tau):
+    cell, off, wq = _state(cell, off, wq)
+    return lib().orc_functional(C.byref(grid_struct(grid)), cell.shape[0], _ptr(cell, C.c_int32),
+                                _ptr(off, C.c_double), _ptr(wq, C.c_int32), float(y_s), float(tau))
