@@ -1,0 +1,149 @@
+"""Benchmark of the PIC pair-potential cycle on one MI355X.
+
+One "step" is one full pass of the method over all particles: deposit ->
+density and gradient -> gather -> eq. (1)-(3) force -> leapfrog push (plus
+the diagnostics reductions every 100 steps).  The timed region is
+pic_step(K) with the particles already resident in HBM.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload large|heated|small]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes of the dominant kernel per particle per launch (the
+# particle state read once and written once):
+#   fused gather+force+push: reads cell 4 + off 4*ndim + vel 12, writes the same.
+DEFAULTS = {"large": (200, 10), "heated": (1000, 20), "small": (1000, 20)}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, pot, seconds_hint=10.0):
+    """The FP64 oracle, single thread, on a bounded window of the same workload:
+    a 256-column strip of the slab through the beam centre, periodic in x."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_1502_07722_amd import workloads as W
+
+    g, p = wl.grid, wl.parts
+    nx = g.n[0]
+    width = min(256, nx)
+    x0 = nx // 2 - width // 2
+    i = p.cell.astype(np.int64) % nx
+    rest = p.cell.astype(np.int64) // nx
+    sel = (i >= x0) & (i < x0 + width)
+    cell = ((i[sel] - x0) + width * rest[sel]).astype(np.int32)
+    off = p.off[:, sel]
+    vel = p.vel[:, sel].astype(np.float64)
+    wq = p.wq[sel]
+    gs = W.Grid(ndim=g.ndim, n=(width,) + tuple(g.n[1:]), h=g.h, bc=g.bc, depth2d=g.depth2d)
+    nsample = int(cell.shape[0])
+    t0 = time.perf_counter()
+    O.run(gs, pot, wl.dt, cell, off, vel, wq, 1)
+    t1 = time.perf_counter()
+    steps = max(1, min(8, int(seconds_hint / max(t1 - t0, 1e-3))))
+    t0 = time.perf_counter()
+    O.run(gs, pot, wl.dt, cell, off, vel, wq, steps)
+    dt = time.perf_counter() - t0
+    return {"value": nsample * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{width}x{g.n[1]}-cell strip of the same slab through the beam centre "
+                      f"({nsample} particles), {steps} FP64 steps, single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="large", choices=["large", "heated", "small"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the design notes describe how it would shard).", file=sys.stderr)
+        sys.exit(2)
+    steps = args.steps if args.steps is not None else DEFAULTS[args.workload][0]
+    warmup = args.warmup if args.warmup is not None else DEFAULTS[args.workload][1]
+
+    import numpy as np
+    import torch
+    from paper_1502_07722_amd import binding as B
+    from paper_1502_07722_amd import workloads as W
+
+    t0 = time.perf_counter()
+    wl = W.WORKLOADS[args.workload]()
+    log(f"generated {wl.name}: {wl.parts.n} particles in {time.perf_counter() - t0:.1f} s")
+    c_att, _ = B.pic_calibrate_catt(wl.grid, wl.pot, W.N_SOLID, 8)
+    pot = W.Potential(c_att=c_att)
+    N = wl.parts.n
+    dev = torch.device("cuda:0")
+    dp = B.DeviceParticles.from_host(wl.parts, dev)
+    ctx = B.Context(wl.grid, pot, wl.dt, N, device=dev)
+    ctx.start_leapfrog(dp)
+    torch.cuda.synchronize()
+    log(f"warmup {warmup} steps")
+    if warmup:
+        ctx.pic_step(dp, warmup, 100)
+    torch.cuda.synchronize()
+    log(f"timing {steps} steps")
+    ctx.pic_set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    diags = ctx.pic_step(dp, steps, 100)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timing = ctx.pic_get_timing()
+    ctx.pic_set_timing(False)
+    log(f"{steps} steps in {elapsed:.3f} s; phases {timing}")
+    value = N * steps / elapsed
+
+    nd = wl.grid.ndim
+    bytes_per_particle = 2 * (4 + 4 * nd + 12)
+    ms_fp, nfp = timing.get("force_push", (0.0, 0))
+    avg_s = ms_fp / 1e3 / max(nfp, 1)
+    achieved = bytes_per_particle * N / avg_s / 1e9 if nfp else None
+    roofline = {"bound": "hbm", "kernel": "k_force_push", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                "bytes_per_particle": bytes_per_particle, "avg_launch_ms": avg_s * 1e3,
+                "phases_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in timing.items()}}
+    out = {
+        "metric": "particle-steps/s (deposit+force+push)",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": elapsed / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "particles": N, "cells": list(wl.grid.n[:nd]),
+                   "ppc": int(round(N / (wl.slab_rows * np.prod(wl.grid.n[: nd - 1])))),
+                   "dt_s": wl.dt, "diag_every": 100, "c_att": c_att,
+                   "state": "int32 cell + f32 offsets/velocities, int64 fixed-point deposit"},
+        "roofline": roofline,
+        "energy_check": {"E_first": diags[0]["ke"] + diags[0]["pe"], "E_last": diags[-1]["ke"] + diags[-1]["pe"]}
+        if diags else None,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (FP64 oracle)")
+        out["cpu_baseline"] = cpu_baseline(wl, pot)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

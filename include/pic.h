@@ -1,0 +1,218 @@
+/*
+ * pic.h -- C ABI of the MI355X (gfx950) implementation of the particle-in-cell
+ * pair-potential cycle of Mitchell, Schumacher and Chowdhury, "Modeling crater
+ * formation in femtosecond-pulse laser damage from basic principles"
+ * (arXiv 1502.07722).
+ *
+ * The method (the paper's PIC cycle, Fig. 1 and eqs. (1)-(3)):
+ *   1. deposit   every macroparticle's weight (number of real atoms it stands
+ *                for) onto the nodes around it -> node density;
+ *   2. gradient  the density gradient at the half-node (cell-centred) points;
+ *   3. gather    node density and centre gradient interpolated back to each
+ *                macroparticle with the same linear shape;
+ *   4. geometry  mean spacing rbar = n^(-1/3), its gradient by eq. (1), and the
+ *                distances to the two nearest neighbours per axis by eq. (2)
+ *                (cubic lattice, the paper's assumption);
+ *   5. force     pair force from the altered Lennard-Jones potential, eq. (3):
+ *                repulsive branch (r < r0) scaled by s_rep, attractive branch
+ *                (r >= r0) by the correction factor c_att;
+ *   6. push      leapfrog; in 2D positions have two components and velocities
+ *                three (the paper's 2D PIC).
+ *
+ * Conventions shared by every entry point
+ *   - Cells are numbered cell = i + n[0]*(j + n[1]*k).  A position is the cell
+ *     plus an in-cell offset off[d] in [0, 1) per evolved axis.
+ *   - Nodes sit at integer coordinates.  A periodic axis has n[d] nodes, a
+ *     reflecting axis n[d] + 1 (wall nodes count half a cell volume each).
+ *     node = a0 + nn0*(a1 + nn1*a2), nn_d the node count per axis.
+ *   - Weights are fixed point: wq = round(w * 2^20), w in atoms, 0 <= wq < 2^31.
+ *   - Deposits are int64 fixed-point sums (offsets quantised to 16 bits, the
+ *     weight split axis by axis with the remainder to the lower node), so node
+ *     sums are exact and independent of summation order.
+ *   - Velocities are half-step (leapfrog) velocities v(n - 1/2) between calls.
+ *   - SI units: metres, seconds, kilograms, joules; forces in newtons per atom.
+ *   - Particle arrays are structure-of-arrays: off is [ndim][n] (axis-major),
+ *     vel is [3][n].
+ *
+ * Memory and streams
+ *   - Every device buffer is owned by the caller (device pointers).  The
+ *     library never allocates device memory: pic_init binds a caller-provided
+ *     device workspace of at least pic_workspace_bytes() bytes and a HIP
+ *     stream; all work is enqueued on that stream.
+ *   - Calls are stream-ordered and asynchronous unless stated otherwise.
+ *     pic_step and pic_sync synchronise the stream before returning.
+ *
+ * Errors
+ *   - Every function returns an int status (PIC_OK = 0).  No exception ever
+ *     crosses the ABI.  pic_last_error(ctx) describes the last failure.
+ *   - Argument problems are found on the host before any work is enqueued.
+ *   - Problems found on the device (a particle outside the grid or with an
+ *     offset outside [0, 1), a negative weight, a step of one cell or more)
+ *     set a device error word; that word is read and cleared by pic_step and
+ *     pic_sync, which then return the matching code.  Invalid particles are
+ *     skipped by the kernels, never used to index memory.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_OK 0
+#define PIC_EINVAL 1    /* null pointer, bad dimension, size or parameter */
+#define PIC_ERANGE 2    /* cell outside the grid or offset outside [0, 1) */
+#define PIC_ECFL 3      /* a particle moved one cell or more in one step */
+#define PIC_EOVERFLOW 4 /* negative fixed-point weight */
+#define PIC_EHIP 5      /* a HIP runtime call failed */
+#define PIC_ENOSPACE 6  /* workspace too small, or n above the bound max_n */
+
+/* Grid of cells and nodes (the paper's partial discretisation, Fig. 1A). */
+typedef struct pic_grid {
+  int32_t ndim;    /* 2 or 3 */
+  int32_t n[3];    /* cells per axis (n[2] ignored in 2D); product < 2^31 */
+  double h[3];     /* cell edge per axis, m */
+  int32_t bc[3];   /* per axis: 0 periodic, 1 reflecting walls */
+  double depth2d;  /* 2D only: thickness the plane stands for, m; <= 0 means h[0] */
+} pic_grid_t;
+
+/* Altered Lennard-Jones potential, eq. (3), plus the two guards the method
+ * needs where eq. (2) stops describing a lattice. */
+typedef struct pic_potential {
+  double D;        /* well depth (dissociation energy), J */
+  double r0;       /* equilibrium distance, m */
+  double s_rep;    /* multiplier on the repulsive branch r < r0 (>= 1) */
+  double c_att;    /* multiplier on the attractive branch r >= r0 (> 0) */
+  double g_clamp;  /* |d rbar / dx| is clamped to this (0 < g_clamp < 2) */
+  double n_floor;  /* no force at densities n <= n_floor, m^-3 */
+  double mass;     /* atomic mass, kg */
+} pic_potential_t;
+
+/* Caller-owned device arrays, structure-of-arrays. */
+typedef struct pic_particles {
+  int64_t n;       /* number of macroparticles, 0 <= n <= max_n */
+  int32_t *cell;   /* [n] linear cell index */
+  float *off;      /* [ndim][n] offsets in [0, 1) */
+  float *vel;      /* [3][n] half-step velocities, m/s */
+  int32_t *wq;     /* [n] weight * 2^20 */
+} pic_particles_t;
+
+/* Diagnostics of step n (FP64; the only FP64 arithmetic on the device):
+ *   ke   = sum w m/2 (|v(n-1/2)|^2 + |v(n+1/2)|^2)/2          (J)
+ *   pe   = sum over nodes V_node eps(n_node)                   (J)
+ *          eps: the energy density of the pair potential, eps'(n) = mu(n)
+ *   px.. = sum w m (v(n-1/2) + v(n+1/2))/2                      (kg m/s)
+ *   wsum = sum w (atoms), bond = sum w (1/2) sum_pairs phi(r)   (J)
+ * In 2D, V_node and the energies refer to a slab of thickness depth2d. */
+typedef struct pic_diag {
+  double ke, pe, px, py, pz, wsum, bond;
+  int64_t step;    /* step index within the pic_step call */
+} pic_diag_t;
+
+typedef struct pic_ctx pic_ctx_t;
+
+/* Number of nodes of a grid (0 if the grid is invalid). */
+int64_t pic_num_nodes(const pic_grid_t *grid);
+
+/* Workspace bytes pic_init needs for this grid and at most max_n particles.
+ * Returns 0 if the grid is invalid. */
+size_t pic_workspace_bytes(const pic_grid_t *grid, int64_t max_n);
+
+/* Create a context.  Checks the grid and potential, converts them to the
+ * kernels' reduced units (length r0, energy D), and binds the caller's device
+ * workspace (ws, ws_bytes; 256-byte aligned; must stay valid until
+ * pic_destroy) and HIP stream (hipStream_t, NULL = default stream).
+ * dt is the time step in seconds.  On failure *out is NULL. */
+int pic_init(pic_ctx_t **out, const pic_grid_t *grid, const pic_potential_t *pot, double dt,
+             int64_t max_n, void *ws, size_t ws_bytes, void *stream);
+
+/* Free the host-side context (never the caller's device memory). */
+int pic_destroy(pic_ctx_t *ctx);
+
+/* Text of the last error on this context (never NULL). */
+const char *pic_last_error(const pic_ctx_t *ctx);
+
+/* Wait for the bound stream, then read and clear the device error word. */
+int pic_sync(pic_ctx_t *ctx);
+
+/* Step 1: overwrite node_w[pic_num_nodes] with the int64 fixed-point node
+ * sums of the particles' weights.  Bit-exact and order independent. */
+int pic_deposit(pic_ctx_t *ctx, const pic_particles_t *p, int64_t *node_w);
+
+/* Steps 2-5: per-atom force [ndim][n] (newtons) on every particle from the
+ * node sums node_w (as written by pic_deposit).  If pe_or_null is not NULL it
+ * receives the grid potential energy (pe field only; synchronises). */
+int pic_force(pic_ctx_t *ctx, const pic_particles_t *p, const int64_t *node_w, float *force,
+              pic_diag_t *pe_or_null);
+
+/* v += frac * force / m * dt on the evolved components (frac = -1/2 turns
+ * initial velocities v(0) into the half-step velocities v(-1/2)). */
+int pic_kick(pic_ctx_t *ctx, pic_particles_t *p, const float *force, double frac);
+
+/* Step 6: one leapfrog push with the given force, in place: kick, drift,
+ * carry whole cells, wrap periodic axes, mirror at reflecting walls. */
+int pic_push(pic_ctx_t *ctx, pic_particles_t *p, const float *force);
+
+/* nsteps full cycles (steps 1-6) in place.  The particle order of the arrays
+ * is preserved.  If diag is not NULL it receives one entry per step whose
+ * index (within this call) is a multiple of diag_every (ceil(nsteps /
+ * diag_every) entries, host memory).  Synchronises before returning and
+ * reports device errors.  Results are bit-identical to nsteps rounds of
+ * pic_deposit, pic_force and pic_push. */
+int pic_step(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, pic_diag_t *diag,
+             int32_t diag_every);
+
+/* Tuning of the tiled pic_step (results do not depend on it: node sums are
+ * exact integers and every particle is updated from its own state):
+ *   tile        tile edge in cells, a power of two (2D 8..32, 3D 4..8);
+ *   halo        cells a particle may drift out of its tile between binnings
+ *               before it takes the slower global path (1..4);
+ *   chunk       most particles per work item (1024..2^20);
+ *   sort_every  re-bin particles by tile every this many steps (0 = never).
+ * Grids with more than 65536 x 32768 (2D) or 2048 x 2048 x 512 (3D) cells,
+ * or max_n >= 2^31, use the untiled kernels and reject this call. */
+int pic_set_tiling(pic_ctx_t *ctx, int32_t tile, int32_t halo, int32_t chunk, int32_t sort_every);
+
+/* 1: make pic_step use the untiled kernels (separate deposit, grid pass and
+ * gather+force+push launches per step); 0: the tiled fused step (default). */
+int pic_set_path(pic_ctx_t *ctx, int32_t untiled);
+
+/* Copy the node sums of the final positions of the last tiled pic_step (as
+ * its fused kernel deposited them) into node_w[pic_num_nodes]. */
+int pic_step_nodes(pic_ctx_t *ctx, int64_t *node_w);
+
+/* Per-phase device time of pic_step, measured with HIP events recorded on
+ * the bound stream around each launch (only while timing is on).
+ * Phases: 0 deposit (incl. clearing the node sums), 1 density and gradient
+ * grid pass, 2 gather+force+push (the dominant kernel), 3 particle sort,
+ * 4 diagnostics reductions. */
+#define PIC_NPHASES 8
+typedef struct pic_timing {
+  double ms[PIC_NPHASES];        /* summed kernel time per phase, ms */
+  int64_t launches[PIC_NPHASES]; /* timed launches per phase */
+} pic_timing_t;
+
+/* Turn event timing of pic_step on (1) or off (0); turning it on clears the
+ * accumulated figures.  Timing adds a host-side event harvest every few
+ * hundred launches; leave it off for plain runs. */
+int pic_set_timing(pic_ctx_t *ctx, int32_t on);
+
+/* Accumulated per-phase times since timing was turned on (synchronises). */
+int pic_get_timing(pic_ctx_t *ctx, pic_timing_t *out);
+
+/* Host-side calibration of the attractive correction factor: a flat slab of
+ * density n_solid (slab_layers cells thick) in a grid with this grid's cell
+ * size, a zero-weight atom moved out along the normal (last) axis with unit
+ * attractive multiplier; W = -integral of its normal force from the
+ * outermost repulsive-to-attractive sign change to infinity; c_att = D / W.
+ * Pure host computation, no context needed. */
+int pic_calibrate_catt(const pic_grid_t *grid, const pic_potential_t *pot, double n_solid,
+                       int32_t slab_layers, double *c_att, double *work);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_H */

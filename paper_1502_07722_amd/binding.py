@@ -1,0 +1,265 @@
+"""Thin Python binding of libpic.so (the C ABI in include/pic.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensors) and the HIP stream.  There
+is no fallback: if the library has not been built, importing this module fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+from . import workloads as W
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpic.so")
+
+PIC_OK, PIC_EINVAL, PIC_ERANGE, PIC_ECFL, PIC_EOVERFLOW, PIC_EHIP, PIC_ENOSPACE = range(7)
+_NAMES = {0: "PIC_OK", 1: "PIC_EINVAL", 2: "PIC_ERANGE", 3: "PIC_ECFL", 4: "PIC_EOVERFLOW",
+          5: "PIC_EHIP", 6: "PIC_ENOSPACE"}
+
+
+class pic_grid_t(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("n", C.c_int32 * 3), ("h", C.c_double * 3), ("bc", C.c_int32 * 3),
+                ("depth2d", C.c_double)]
+
+
+class pic_potential_t(C.Structure):
+    _fields_ = [("D", C.c_double), ("r0", C.c_double), ("s_rep", C.c_double), ("c_att", C.c_double),
+                ("g_clamp", C.c_double), ("n_floor", C.c_double), ("mass", C.c_double)]
+
+
+class pic_particles_t(C.Structure):
+    _fields_ = [("n", C.c_int64), ("cell", C.c_void_p), ("off", C.c_void_p), ("vel", C.c_void_p),
+                ("wq", C.c_void_p)]
+
+
+class pic_diag_t(C.Structure):
+    _fields_ = [("ke", C.c_double), ("pe", C.c_double), ("px", C.c_double), ("py", C.c_double),
+                ("pz", C.c_double), ("wsum", C.c_double), ("bond", C.c_double), ("step", C.c_int64)]
+
+
+DIAG_FIELDS = ("ke", "pe", "px", "py", "pz", "wsum", "bond", "step")
+PHASES = ("deposit", "grid", "force_push", "sort", "diag", "p5", "p6", "p7")
+
+
+class pic_timing_t(C.Structure):
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())")
+
+lib = C.CDLL(LIB_PATH)
+_P = C.POINTER
+_vp = C.c_void_p
+lib.pic_num_nodes.restype = C.c_int64
+lib.pic_num_nodes.argtypes = [_P(pic_grid_t)]
+lib.pic_workspace_bytes.restype = C.c_size_t
+lib.pic_workspace_bytes.argtypes = [_P(pic_grid_t), C.c_int64]
+lib.pic_init.argtypes = [_P(_vp), _P(pic_grid_t), _P(pic_potential_t), C.c_double, C.c_int64, _vp, C.c_size_t, _vp]
+lib.pic_destroy.argtypes = [_vp]
+lib.pic_last_error.restype = C.c_char_p
+lib.pic_last_error.argtypes = [_vp]
+lib.pic_sync.argtypes = [_vp]
+lib.pic_deposit.argtypes = [_vp, _P(pic_particles_t), _vp]
+lib.pic_force.argtypes = [_vp, _P(pic_particles_t), _vp, _vp, _P(pic_diag_t)]
+lib.pic_kick.argtypes = [_vp, _P(pic_particles_t), _vp, C.c_double]
+lib.pic_push.argtypes = [_vp, _P(pic_particles_t), _vp]
+lib.pic_step.argtypes = [_vp, _P(pic_particles_t), C.c_int32, _P(pic_diag_t), C.c_int32]
+lib.pic_set_timing.argtypes = [_vp, C.c_int32]
+lib.pic_set_tiling.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+lib.pic_set_path.argtypes = [_vp, C.c_int32]
+lib.pic_step_nodes.argtypes = [_vp, _vp]
+lib.pic_get_timing.argtypes = [_vp, _P(pic_timing_t)]
+lib.pic_calibrate_catt.argtypes = [_P(pic_grid_t), _P(pic_potential_t), C.c_double, C.c_int32, _P(C.c_double),
+                                   _P(C.c_double)]
+
+
+class PicError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def grid_t(grid: W.Grid) -> pic_grid_t:
+    g = pic_grid_t()
+    g.ndim = grid.ndim
+    for d in range(3):
+        g.n[d] = int(grid.n[d])
+        g.h[d] = float(grid.h[d])
+        g.bc[d] = int(grid.bc[d])
+    g.depth2d = float(grid.depth2d) if grid.ndim == 2 else 0.0
+    return g
+
+
+def potential_t(pot: W.Potential) -> pic_potential_t:
+    return pic_potential_t(pot.D, pot.r0, pot.s_rep, pot.c_att, pot.g_clamp, pot.n_floor, pot.mass)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class DeviceParticles:
+    """Caller-owned device arrays in the layout of pic_particles_t."""
+
+    def __init__(self, cell, off, vel, wq):
+        self.cell, self.off, self.vel, self.wq = cell, off, vel, wq
+        for t in (cell, off, vel, wq):
+            assert t.is_cuda and t.is_contiguous()
+        assert cell.dtype == torch.int32 and wq.dtype == torch.int32
+        assert off.dtype == torch.float32 and vel.dtype == torch.float32
+
+    @classmethod
+    def from_host(cls, parts: W.Particles, device="cuda"):
+        return cls(torch.from_numpy(parts.cell).to(device).contiguous(),
+                   torch.from_numpy(parts.off).to(device).contiguous(),
+                   torch.from_numpy(parts.vel).to(device).contiguous(),
+                   torch.from_numpy(parts.wq).to(device).contiguous())
+
+    @property
+    def n(self):
+        return int(self.cell.shape[0])
+
+    def struct(self) -> pic_particles_t:
+        return pic_particles_t(self.n, self.cell.data_ptr(), self.off.data_ptr(), self.vel.data_ptr(),
+                               self.wq.data_ptr())
+
+    def clone(self):
+        return DeviceParticles(self.cell.clone(), self.off.clone(), self.vel.clone(), self.wq.clone())
+
+    def to_host(self):
+        return (self.cell.cpu().numpy(), self.off.cpu().numpy(), self.vel.cpu().numpy(), self.wq.cpu().numpy())
+
+
+def pic_num_nodes(grid: W.Grid) -> int:
+    return int(lib.pic_num_nodes(C.byref(grid_t(grid))))
+
+
+def pic_workspace_bytes(grid: W.Grid, max_n: int) -> int:
+    return int(lib.pic_workspace_bytes(C.byref(grid_t(grid)), int(max_n)))
+
+
+def pic_calibrate_catt(grid: W.Grid, pot: W.Potential, n_solid: float, slab_layers: int = 8):
+    c, w = C.c_double(), C.c_double()
+    rc = lib.pic_calibrate_catt(C.byref(grid_t(grid)), C.byref(potential_t(pot)), float(n_solid),
+                                int(slab_layers), C.byref(c), C.byref(w))
+    if rc:
+        raise PicError(rc, "calibration failed")
+    return c.value, w.value
+
+
+class Context:
+    """One pic_ctx_t with its workspace tensor, bound to a torch stream."""
+
+    def __init__(self, grid: W.Grid, pot: W.Potential, dt: float, max_n: int, device="cuda", stream=None):
+        self.grid, self.pot, self.dt, self.max_n = grid, pot, dt, int(max_n)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = pic_workspace_bytes(grid, max_n)
+        if nbytes == 0:
+            raise PicError(PIC_EINVAL, "invalid grid")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.ctx = C.c_void_p()
+        rc = lib.pic_init(C.byref(self.ctx), C.byref(grid_t(grid)), C.byref(potential_t(pot)), float(dt),
+                          self.max_n, C.c_void_p(self._ws_ptr), nbytes, C.c_void_p(self.stream.cuda_stream))
+        if rc:
+            raise PicError(rc, "pic_init failed")
+        self.nnodes = pic_num_nodes(grid)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            lib.pic_destroy(ctx)
+            self.ctx = None
+
+    def _need(self, t, numel, dtype, what):
+        """Host-side size check of a caller buffer before any launch."""
+        if t is None or not t.is_cuda or not t.is_contiguous() or t.dtype != dtype or t.numel() < numel:
+            raise ValueError(f"{what}: need a contiguous {dtype} device tensor of >= {numel} elements")
+
+    def _parts_ok(self, parts):
+        n = parts.n
+        if parts.off.numel() < self.grid.ndim * n or parts.vel.numel() < 3 * n or parts.wq.numel() < n:
+            raise ValueError("particle arrays are smaller than n")
+
+    def _check(self, rc, what):
+        if rc:
+            raise PicError(rc, f"{what}: {lib.pic_last_error(self.ctx).decode()}")
+
+    def pic_sync(self):
+        self._check(lib.pic_sync(self.ctx), "pic_sync")
+
+    def pic_deposit(self, parts: DeviceParticles, node_w=None):
+        if node_w is None:
+            node_w = torch.empty(self.nnodes, dtype=torch.int64, device=self.device)
+        self._need(node_w, self.nnodes, torch.int64, "node_w")
+        self._parts_ok(parts)
+        s = parts.struct()
+        self._check(lib.pic_deposit(self.ctx, C.byref(s), _ptr(node_w)), "pic_deposit")
+        return node_w
+
+    def pic_force(self, parts: DeviceParticles, node_w, force=None, want_pe=False):
+        if force is None:
+            force = torch.empty((self.grid.ndim, parts.n), dtype=torch.float32, device=self.device)
+        self._need(node_w, self.nnodes, torch.int64, "node_w")
+        self._need(force, self.grid.ndim * parts.n, torch.float32, "force")
+        self._parts_ok(parts)
+        s = parts.struct()
+        d = pic_diag_t()
+        self._check(lib.pic_force(self.ctx, C.byref(s), _ptr(node_w), _ptr(force),
+                                  C.byref(d) if want_pe else None), "pic_force")
+        return (force, d.pe) if want_pe else force
+
+    def pic_kick(self, parts: DeviceParticles, force, frac: float):
+        self._need(force, self.grid.ndim * parts.n, torch.float32, "force")
+        self._parts_ok(parts)
+        s = parts.struct()
+        self._check(lib.pic_kick(self.ctx, C.byref(s), _ptr(force), float(frac)), "pic_kick")
+
+    def pic_push(self, parts: DeviceParticles, force):
+        self._need(force, self.grid.ndim * parts.n, torch.float32, "force")
+        self._parts_ok(parts)
+        s = parts.struct()
+        self._check(lib.pic_push(self.ctx, C.byref(s), _ptr(force)), "pic_push")
+
+    def pic_step(self, parts: DeviceParticles, nsteps: int, diag_every: int = 0):
+        self._parts_ok(parts)
+        s = parts.struct()
+        nd = 0 if diag_every <= 0 else (nsteps + diag_every - 1) // diag_every
+        buf = (pic_diag_t * max(nd, 1))()
+        self._check(lib.pic_step(self.ctx, C.byref(s), int(nsteps), buf if nd else None,
+                                 int(diag_every) if nd else 0), "pic_step")
+        return [{k: getattr(buf[i], k) for k in DIAG_FIELDS} for i in range(nd)]
+
+    def pic_set_tiling(self, tile: int, halo: int, chunk: int, sort_every: int):
+        self._check(lib.pic_set_tiling(self.ctx, tile, halo, chunk, sort_every), "pic_set_tiling")
+
+    def pic_set_path(self, untiled: bool):
+        self._check(lib.pic_set_path(self.ctx, 1 if untiled else 0), "pic_set_path")
+
+    def pic_step_nodes(self, node_w=None):
+        if node_w is None:
+            node_w = torch.empty(self.nnodes, dtype=torch.int64, device=self.device)
+        self._need(node_w, self.nnodes, torch.int64, "node_w")
+        self._check(lib.pic_step_nodes(self.ctx, _ptr(node_w)), "pic_step_nodes")
+        return node_w
+
+    def pic_set_timing(self, on: bool):
+        self._check(lib.pic_set_timing(self.ctx, 1 if on else 0), "pic_set_timing")
+
+    def pic_get_timing(self):
+        t = pic_timing_t()
+        self._check(lib.pic_get_timing(self.ctx, C.byref(t)), "pic_get_timing")
+        return {PHASES[i]: (t.ms[i], t.launches[i]) for i in range(8) if t.launches[i]}
+
+    def start_leapfrog(self, parts: DeviceParticles):
+        """v(0) -> v(-1/2) = v(0) - F(0)/m dt/2."""
+        node = self.pic_deposit(parts)
+        F = self.pic_force(parts, node)
+        self.pic_kick(parts, F, -0.5)
+        return F

@@ -1,0 +1,269 @@
+// Device-side building blocks of the PIC pair-potential cycle (arXiv 1502.07722)
+// for gfx950.  Every kernel -- the separate deposit / force / push kernels and
+// the fused step kernels -- evaluates the method through these functions, so
+// that all paths produce the same bits.  The library is compiled with
+// -ffp-contract=off: every fused multiply-add below is written explicitly.
+//
+// Reduced units inside the kernels: density nh = n r0^3, gradient Gh = dn/dx
+// r0^4, force Fh in units of 12 D / r0.  Positions are (cell, offset in [0,1)).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+enum : uint32_t { ERR_RANGE = 1u, ERR_CFL = 2u, ERR_WEIGHT = 4u };
+
+// Grid constants as the kernels need them.
+struct Geo {
+  int ndim;
+  int n[3];        // cells per axis
+  int nn[3];       // nodes per axis
+  int bc[3];       // 0 periodic, 1 reflecting
+  int ncells;
+  int nnodes;
+  double inv_n0;   // 1 / n[0], for decoding linear cell ids
+  double inv_n1;   // 1 / n[1]
+  float kappa;     // 2^-20 r0^3 / V_cell: weight units -> reduced density
+  float gam[3];    // r0 / (2^(ndim-1) h_d): summed edge differences -> gradient
+  float tau[3];    // dt / h_d: velocity (m/s) -> offset change per step
+};
+
+// Potential constants (reduced units) and the force / velocity scales.
+struct Pot {
+  float nfloor;    // n_floor r0^3
+  float gclamp;
+  float s_rep;
+  float c_att;
+  float beta;      // 12 D / r0: reduced force -> newtons
+  float gv;        // dt / m: newtons -> velocity change per step
+};
+
+// ---------------------------------------------------------------------------
+// Cell ids
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int div_floor_pos(int c, int n, double inv) {
+  // c >= 0; exact floor(c / n) from a double estimate plus one correction
+  int q = (int)((double)c * inv);
+  int r = c - q * n;
+  if (r < 0) q -= 1;
+  else if (r >= n) q += 1;
+  return q;
+}
+
+template <int ND>
+__device__ __forceinline__ void decode_cell(const Geo &g, int c, int idx[3]) {
+  int q = div_floor_pos(c, g.n[0], g.inv_n0);
+  idx[0] = c - q * g.n[0];
+  if (ND == 2) {
+    idx[1] = q;
+    idx[2] = 0;
+  } else {
+    int q2 = div_floor_pos(q, g.n[1], g.inv_n1);
+    idx[1] = q - q2 * g.n[1];
+    idx[2] = q2;
+  }
+}
+
+template <int ND>
+__device__ __forceinline__ int encode_cell(const Geo &g, const int idx[3]) {
+  return ND == 2 ? idx[0] + g.n[0] * idx[1] : idx[0] + g.n[0] * (idx[1] + g.n[1] * idx[2]);
+}
+
+// Stored node along axis d for node coordinate a in [0, n_d]: periodic axes wrap
+// n_d -> 0 (deposit / gather never need other ghosts).
+__device__ __forceinline__ int node_axis(const Geo &g, int d, int a) {
+  return (!g.bc[d] && a == g.n[d]) ? 0 : a;
+}
+
+template <int ND>
+__device__ __forceinline__ int node_index(const Geo &g, int a0, int a1, int a2) {
+  return ND == 2 ? a0 + g.nn[0] * a1 : a0 + g.nn[0] * (a1 + g.nn[1] * a2);
+}
+
+// Reduced density of a stored node: weight sum * kappa, doubled for each
+// reflecting wall the node lies on (half volume there).
+__device__ __forceinline__ float node_density(const Geo &g, long long wsum, int a0, int a1, int a2) {
+  float k = g.kappa;
+  if (g.bc[0] && (a0 == 0 || a0 == g.n[0])) k *= 2.0f;
+  if (g.bc[1] && (a1 == 0 || a1 == g.n[1])) k *= 2.0f;
+  if (g.ndim == 3 && g.bc[2] && (a2 == 0 || a2 == g.n[2])) k *= 2.0f;
+  return (float)wsum * k;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-point deposit: offsets quantised to 16 bits, weight split axis by axis,
+// upper node gets floor(part * u / 2^16), the lower node the rest.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t quant16(float f) {
+  int u = (int)(f * 65536.0f);  // exact scaling; truncation = floor for f >= 0
+  return (uint32_t)min(max(u, 0), 65535);
+}
+
+__device__ __forceinline__ uint32_t split_upper(uint32_t part, uint32_t u) {
+  return (uint32_t)(((uint64_t)part * (uint64_t)u) >> 16);
+}
+
+// Shares of the 2^ND corner nodes; corner bit d set = upper node along d.
+template <int ND>
+__device__ __forceinline__ void deposit_shares(uint32_t W, const float f[3], uint32_t t[8]) {
+  uint32_t ux = quant16(f[0]), uy = quant16(f[1]);
+  uint32_t x1 = split_upper(W, ux), x0 = W - x1;
+  uint32_t t01 = split_upper(x0, uy), t11 = split_upper(x1, uy);
+  uint32_t t00 = x0 - t01, t10 = x1 - t11;
+  if (ND == 2) {
+    t[0] = t00; t[1] = t10; t[2] = t01; t[3] = t11;
+  } else {
+    uint32_t uz = quant16(f[2]);
+    uint32_t a = split_upper(t00, uz), b = split_upper(t10, uz);
+    uint32_t c = split_upper(t01, uz), d = split_upper(t11, uz);
+    t[0] = t00 - a; t[1] = t10 - b; t[2] = t01 - c; t[3] = t11 - d;
+    t[4] = a; t[5] = b; t[6] = c; t[7] = d;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cell-centred gradient from the cell's 2^ND corner densities (corner bit d =
+// upper along d): mean of the edge differences along d, in reduced units.
+// ---------------------------------------------------------------------------
+template <int ND>
+__device__ __forceinline__ void centre_gradient(const Geo &g, const float c[8], float G[3]) {
+  if (ND == 2) {
+    G[0] = g.gam[0] * ((c[1] - c[0]) + (c[3] - c[2]));
+    G[1] = g.gam[1] * ((c[2] - c[0]) + (c[3] - c[1]));
+    G[2] = 0.0f;
+  } else {
+    G[0] = g.gam[0] * (((c[1] - c[0]) + (c[3] - c[2])) + ((c[5] - c[4]) + (c[7] - c[6])));
+    G[1] = g.gam[1] * (((c[2] - c[0]) + (c[3] - c[1])) + ((c[6] - c[4]) + (c[7] - c[5])));
+    G[2] = g.gam[2] * (((c[4] - c[0]) + (c[5] - c[1])) + ((c[6] - c[2]) + (c[7] - c[3])));
+  }
+}
+
+__device__ __forceinline__ float lerpf(float a, float b, float t) { return __builtin_fmaf(t, b - a, a); }
+
+// Multilinear interpolation of 2^ND corner values (corner bit d = upper along d).
+template <int ND>
+__device__ __forceinline__ float interp(const float c[8], const float w[3]) {
+  float a = lerpf(c[0], c[1], w[0]);
+  float b = lerpf(c[2], c[3], w[0]);
+  float lo = lerpf(a, b, w[1]);
+  if (ND == 2) return lo;
+  float e = lerpf(c[4], c[5], w[0]);
+  float f = lerpf(c[6], c[7], w[0]);
+  return lerpf(lo, lerpf(e, f, w[1]), w[2]);
+}
+
+// Centre-interpolation base and weight along one axis: the two nearest centres
+// are at (c0 + 1/2) and (c0 + 3/2) with weight t on the upper one.
+__device__ __forceinline__ void centre_stencil(int i, float f, int &c0, float &t) {
+  if (f >= 0.5f) { c0 = i; t = f - 0.5f; }
+  else { c0 = i - 1; t = f + 0.5f; }
+}
+
+// ---------------------------------------------------------------------------
+// Eq. (1)-(3).  q = n^(1/3) = r0 / rbar;  g = d rbar/dx = -(1/3) Gh / (nh q);
+// s+- = r0 / r+- = q (1 -+ g/2);  phi'(s) = (12 D / r0) M(s) (s^7 - s^13),
+// M = s_rep for r < r0 (s > 1), c_att otherwise;  F = phi'(s+) - phi'(s-).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float dphi_hat(const Pot &P, float s) {
+  float s2 = s * s;
+  float s3 = s2 * s;
+  float s6 = s3 * s3;
+  float s7 = s6 * s;
+  float v = __builtin_fmaf(-s7, s6, s7);  // s^7 - s^13
+  return (s > 1.0f ? P.s_rep : P.c_att) * v;
+}
+
+__device__ __forceinline__ float phi_hat(const Pot &P, float s) {
+  // U / D = s^12 - 2 s^6; altered branches stay continuous at r0
+  float s6 = s * s * s;
+  s6 = s6 * s6;
+  float u = __builtin_fmaf(s6, s6, -2.0f * s6);
+  return s > 1.0f ? __builtin_fmaf(P.s_rep, u, P.s_rep - P.c_att) : P.c_att * u;
+}
+
+template <int ND>
+__device__ __forceinline__ void pair_force(const Pot &P, float nh, const float G[3], float F[3],
+                                           float *bond = nullptr) {
+  F[0] = F[1] = F[2] = 0.0f;
+  if (bond) *bond = 0.0f;
+  if (!(nh > P.nfloor)) return;
+  float q = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(nh) * (1.0f / 3.0f));
+  float rinv = __builtin_amdgcn_rcpf(nh * q);
+  float e = 0.0f;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    float g = (G[d] * rinv) * (-1.0f / 3.0f);
+    g = fminf(fmaxf(g, -P.gclamp), P.gclamp);
+    float hq = 0.5f * q * g;
+    float sp = q - hq;  // +d neighbour (farther when rbar grows towards +d)
+    float sm = q + hq;  // -d neighbour
+    F[d] = dphi_hat(P, sp) - dphi_hat(P, sm);
+    if (bond) e += 0.5f * (phi_hat(P, sp) + phi_hat(P, sm));
+  }
+  if (bond) *bond = e;
+}
+
+// ---------------------------------------------------------------------------
+// Leapfrog push of one particle (kick with the force in newtons, then drift,
+// carry, wrap / mirror).  Returns device error bits.
+// ---------------------------------------------------------------------------
+template <int ND>
+__device__ __forceinline__ uint32_t push_particle(const Geo &g, const Pot &P, const float F[3],
+                                                  int idx[3], float f[3], float v[3]) {
+  uint32_t err = 0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) v[d] = __builtin_fmaf(F[d], P.gv, v[d]);
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    float df = v[d] * g.tau[d];
+    if (!(fabsf(df) < 1.0f)) { err |= ERR_CFL; df = 0.0f; }
+    float x = f[d] + df;
+    int n = g.n[d];
+    if (g.bc[d] && idx[d] == 0 && x < 0.0f) {
+      x = -x;
+      v[d] = -v[d];
+    } else if (g.bc[d] && idx[d] == n - 1 && x >= 1.0f) {
+      x = 2.0f - x;
+      v[d] = -v[d];
+      if (x >= 1.0f) x = 0x1.fffffep-1f;  // exactly on the wall
+    } else if (x >= 1.0f) {
+      x -= 1.0f;
+      idx[d] += 1;
+    } else if (x < 0.0f) {
+      x += 1.0f;
+      idx[d] -= 1;
+      if (x >= 1.0f) { x = 0.0f; idx[d] += 1; }  // rounded onto the node itself
+    }
+    if (!g.bc[d]) {
+      if (idx[d] < 0) idx[d] += n;
+      else if (idx[d] >= n) idx[d] -= n;
+    }
+    if (!(x >= 0.0f && x < 1.0f)) { err |= ERR_RANGE; x = 0.0f; }
+    f[d] = x;
+  }
+  return err;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 block reduction of NF values (wave64 shuffles, then LDS across waves)
+// ---------------------------------------------------------------------------
+template <int NF>
+__device__ __forceinline__ void block_reduce_store(double v[NF], double *__restrict__ out) {
+  __shared__ double red[NF][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int i = 0; i < NF; ++i)
+    for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_down(v[i], o, 64);
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < NF; ++i) red[i][wave] = v[i];
+  __syncthreads();
+  if (threadIdx.x < NF) {
+    double s = 0.0;
+    for (int w = 0; w < nwaves; ++w) s += red[threadIdx.x][w];
+    out[threadIdx.x] = s;
+  }
+}
+
+}  // namespace pic

@@ -1,0 +1,89 @@
+// Internal declarations shared by the C-ABI layer and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/pic.h"
+#include "pic_device.h"
+
+namespace pic {
+
+// FP64 constants of the diagnostics (SI).
+struct DiagC {
+  double D, mass, half_m, wunit, vcell, r0cube, s_rep, c_att;
+};
+
+struct PartPtrs {
+  int64_t n;
+  int *cell;
+  float *off;
+  float *vel;
+  int *wq;
+};
+
+// Internal particle store of the tiled step: binned by tile, packed cell
+// coordinates (2D: i | j << 16; 3D: i | j << 11 | k << 22), SoA with stride cap.
+struct Store {
+  int *pc;
+  float *off;   // [ndim][cap]
+  float *vel;   // [3][cap]
+  int *wq;
+  int *oidx;    // index of the particle in the caller's arrays
+  int64_t cap;
+};
+
+// Tiling of the grid: tiles of 2^lt[d] cells per axis, halo H cells.
+struct TileGeo {
+  int lt[3];
+  int tn[3];
+  int ntiles;
+  int H;
+  int chunk;      // most particles per work item
+  int pshift[3];  // packed-coordinate bit offsets
+  int pmask[3];
+};
+
+struct Item {
+  int tile, start, end, pad;
+};
+
+struct BinBufs {
+  int *counts;      // [ntiles]
+  int *starts;      // [ntiles + 1]
+  int *cursors;     // [ntiles]
+  int *item_start;  // [ntiles]
+  Item *items;      // [max_items]
+  int *num_items;   // [1]
+};
+
+void launch_fill64(hipStream_t s, long long *a, int64_t n);
+void launch_clear_word(hipStream_t s, uint32_t *w);
+void launch_deposit_atomic(hipStream_t s, const Geo &g, const PartPtrs &pp, long long *node, uint32_t *err);
+void launch_grid(hipStream_t s, const Geo &g, const long long *node, float *dens, float *G);
+void launch_force(hipStream_t s, const Geo &g, const Pot &P, const PartPtrs &pp, const float *dens,
+                  const float *G, float *force, uint32_t *err);
+void launch_push(hipStream_t s, const Geo &g, const Pot &P, const PartPtrs &pp, const float *force,
+                 uint32_t *err);
+void launch_kick(hipStream_t s, const Geo &g, const Pot &P, const PartPtrs &pp, const float *force, float frac);
+int launch_force_push(hipStream_t s, const Geo &g, const Pot &P, const DiagC &dc, const PartPtrs &pp,
+                      const float *dens, const float *G, double *partial, bool diag, uint32_t *err);
+int launch_pe_nodes(hipStream_t s, const Geo &g, const DiagC &dc, const long long *node, double *partial);
+void launch_reduce_diag(hipStream_t s, const double *part_p, int nblk_p, const double *part_g, int nblk_g,
+                        pic_diag_t *out, int64_t step);
+
+// tiled path (pic_tiled.hip)
+size_t window_lds_bytes(const TileGeo &tg, int ndim);
+void launch_bin(hipStream_t st, const Geo &g, const TileGeo &tg, const PartPtrs &cp, const Store &src,
+                const Store &dst, int64_t n, const BinBufs &b, bool import, uint32_t *err);
+void launch_export(hipStream_t st, const Geo &g, const TileGeo &tg, const Store &s, int64_t n, const PartPtrs &cp);
+void launch_deposit_tiled(hipStream_t st, const Geo &g, const TileGeo &tg, const Store &s, const BinBufs &b,
+                          int max_items, long long *N);
+void launch_step_tiled(hipStream_t st, const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
+                       const Store &s, const BinBufs &b, int max_items, const long long *Ncur, long long *Nnext,
+                       long long *Nclear, double *partial, bool diag, uint32_t *err);
+void launch_reduce_diag_dev(hipStream_t st, const double *part_p, const int *nblk_p, const double *part_g,
+                            int nblk_g, pic_diag_t *out, int64_t step);
+void launch_fill32(hipStream_t s, int *a, int64_t n);
+
+}  // namespace pic

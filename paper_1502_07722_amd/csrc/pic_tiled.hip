@@ -1,0 +1,655 @@
+// Tiled, fused time step of the PIC pair-potential cycle (arXiv 1502.07722)
+// for gfx950.
+//
+// Particles live in an internal structure-of-arrays store binned by tile (a
+// block of T^ND cells).  Within a tile the order is scrambled by a
+// multiplicative permutation so that the lanes of a wavefront hold particles
+// of different cells (few same-address LDS atomics in the deposit).  A work
+// item is a chunk of one tile's particles.  One kernel launch per step does,
+// per item:
+//   1. stage the node densities of the tile plus a halo (window) from the
+//      int64 node sums of this step into LDS, and the cell-centred gradients;
+//   2. for each particle: gather density and gradient (LDS), eq. (1)-(3)
+//      force, leapfrog push, write the state back, and deposit the new
+//      position into an LDS int64 accumulator;
+//   3. flush the accumulator into the next step's node sums (global int64
+//      atomics), and clear the node buffer of the step after next.
+// Particles that drifted outside the window since the last binning take an
+// equivalent global path (same arithmetic, same bits).  The int64 sums make
+// the result independent of order, tiling and binning period.
+#include "pic_internal.h"
+
+namespace pic {
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int fold_node(const Geo &g, int d, int a) {
+  // node coordinate -> stored node: periodic wrap, mirror across reflecting walls
+  int n = g.n[d];
+  if (!g.bc[d]) {
+    a %= n;
+    return a < 0 ? a + n : a;
+  }
+  int p = 2 * n;
+  a %= p;
+  if (a < 0) a += p;
+  return a > n ? p - a : a;
+}
+
+template <int ND>
+__device__ __forceinline__ void unpack_cell(const TileGeo &tg, int pc, int idx[3]) {
+  idx[0] = pc & tg.pmask[0];
+  idx[1] = (pc >> tg.pshift[1]) & tg.pmask[1];
+  idx[2] = ND == 3 ? (pc >> tg.pshift[2]) : 0;
+}
+
+template <int ND>
+__device__ __forceinline__ int pack_cell(const TileGeo &tg, const int idx[3]) {
+  int pc = idx[0] | (idx[1] << tg.pshift[1]);
+  if (ND == 3) pc |= idx[2] << tg.pshift[2];
+  return pc;
+}
+
+template <int ND>
+__device__ __forceinline__ int tile_of(const TileGeo &tg, const int idx[3]) {
+  int t = (idx[0] >> tg.lt[0]) + tg.tn[0] * (idx[1] >> tg.lt[1]);
+  if (ND == 3) t += tg.tn[0] * tg.tn[1] * (idx[2] >> tg.lt[2]);
+  return t;
+}
+
+// Window coordinate of cell / node coordinate c along axis d for a window whose
+// first node is at coordinate o: periodic axes pick the representative in
+// [lo, lo + n) so that the tile itself is always inside.
+__device__ __forceinline__ int window_coord(const Geo &g, int d, int c, int o, int lo) {
+  int l = c - o;
+  if (!g.bc[d]) {
+    int n = g.n[d];
+    l -= lo;
+    l %= n;
+    if (l < 0) l += n;
+    l += lo;
+  }
+  return l;
+}
+
+// Wave-aggregated atomic add of 1 per lane on counter[key]; returns this lane's
+// rank (old value + position among lanes with the same key).  Every lane of
+// the wavefront must call it; lanes with active == false take part but get -1.
+__device__ __forceinline__ int wave_rank(int *counter, int key, bool active) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(active);
+  int out = -1;
+  while (todo) {
+    int leader = __ffsll((long long)todo) - 1;
+    int lkey = __shfl(key, leader, 64);
+    unsigned long long same = __ballot(active && key == lkey) & todo;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counter[lkey], __popcll(same));
+    base = __shfl(base, leader, 64);
+    if ((same >> lane) & 1ull) out = base + __popcll(same & ((1ull << lane) - 1ull));
+    todo &= ~same;
+  }
+  return out;
+}
+
+// Position of rank r inside a tile of L particles: r -> (r * P) mod L with a
+// prime P that does not divide L (a bijection that spreads same-cell runs).
+__device__ __forceinline__ int scramble(int r, int L) {
+  if (L <= 64) return r;
+  const uint32_t primes[3] = {40009u, 50021u, 60013u};
+  uint32_t P = primes[0];
+  if ((uint32_t)L % P == 0) P = primes[1];
+  if ((uint32_t)L % P == 0) P = primes[2];
+  return (int)(((uint64_t)(uint32_t)r * P) % (uint64_t)L);
+}
+
+// ---------------------------------------------------------------------------
+// Binning: histogram by tile, scan, items, scatter.
+// ---------------------------------------------------------------------------
+// Source of a binning pass: the caller's arrays (linear cells, validated) or
+// the internal store (packed cells).
+template <int ND, bool IMPORT>
+__device__ __forceinline__ int source_tile(const Geo &g, const TileGeo &tg, const PartPtrs &cp, const Store &s,
+                                           int64_t p, int idx[3], uint32_t *err) {
+  if (IMPORT) {
+    int c = cp.cell[p];
+    float f0 = cp.off[p], f1 = cp.off[cp.n + p], f2 = ND == 3 ? cp.off[2 * cp.n + p] : 0.0f;
+    int W = cp.wq[p];
+    uint32_t e = 0;
+    if (c < 0 || c >= g.ncells) e |= ERR_RANGE;
+    if (!(f0 >= 0.0f && f0 < 1.0f) || !(f1 >= 0.0f && f1 < 1.0f)) e |= ERR_RANGE;
+    if (ND == 3 && !(f2 >= 0.0f && f2 < 1.0f)) e |= ERR_RANGE;
+    if (W < 0) e |= ERR_WEIGHT;
+    if (e) {
+      if (err) atomicOr(err, e);
+      return -1;
+    }
+    decode_cell<ND>(g, c, idx);
+  } else {
+    unpack_cell<ND>(tg, s.pc[p], idx);
+  }
+  return tile_of<ND>(tg, idx);
+}
+
+template <int ND, bool IMPORT>
+__global__ void __launch_bounds__(256) k_tile_hist(Geo g, TileGeo tg, PartPtrs cp, Store s, int64_t n,
+                                                   int *__restrict__ counts, uint32_t *__restrict__ err) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int idx[3];
+  int t = p < n ? source_tile<ND, IMPORT>(g, tg, cp, s, p, idx, err) : -1;
+  wave_rank(counts, t < 0 ? 0 : t, t >= 0);
+}
+
+// Single block: exclusive scan of tile counts -> starts; item counts; cursors.
+__global__ void __launch_bounds__(1024) k_tile_scan(int ntiles, int chunk, const int *__restrict__ counts,
+                                                    int *__restrict__ starts, int *__restrict__ item_start,
+                                                    int *__restrict__ cursors, int *__restrict__ num_items) {
+  __shared__ long long s_a[1024], s_b[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int per = (ntiles + nt - 1) / nt;
+  const int lo = tid * per, hi = min(ntiles, lo + per);
+  long long a = 0, b = 0;
+  for (int t = lo; t < hi; ++t) {
+    a += counts[t];
+    b += (counts[t] + chunk - 1) / chunk;
+  }
+  s_a[tid] = a;
+  s_b[tid] = b;
+  __syncthreads();
+  for (int o = 1; o < nt; o <<= 1) {  // Hillis-Steele inclusive scan
+    long long va = tid >= o ? s_a[tid - o] : 0, vb = tid >= o ? s_b[tid - o] : 0;
+    __syncthreads();
+    s_a[tid] += va;
+    s_b[tid] += vb;
+    __syncthreads();
+  }
+  long long ra = tid ? s_a[tid - 1] : 0, rb = tid ? s_b[tid - 1] : 0;
+  for (int t = lo; t < hi; ++t) {
+    starts[t] = (int)ra;
+    item_start[t] = (int)rb;
+    cursors[t] = 0;
+    ra += counts[t];
+    rb += (counts[t] + chunk - 1) / chunk;
+  }
+  if (tid == nt - 1) {
+    starts[ntiles] = (int)s_a[nt - 1];
+    *num_items = (int)s_b[nt - 1];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_tile_items(int ntiles, int chunk, const int *__restrict__ counts,
+                                                    const int *__restrict__ starts,
+                                                    const int *__restrict__ item_start, Item *__restrict__ items) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  int c = counts[t], s = starts[t], b = item_start[t];
+  for (int k = 0; k * chunk < c; ++k) items[b + k] = Item{t, s + k * chunk, s + min(c, (k + 1) * chunk), 0};
+}
+
+template <int ND, bool IMPORT>
+__global__ void __launch_bounds__(256) k_tile_scatter(Geo g, TileGeo tg, PartPtrs cp, Store s, Store d, int64_t n,
+                                                      const int *__restrict__ counts,
+                                                      const int *__restrict__ starts, int *__restrict__ cursors,
+                                                      uint32_t *__restrict__ err) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int idx[3];
+  int t = p < n ? source_tile<ND, IMPORT>(g, tg, cp, s, p, idx, nullptr) : -1;
+  int r = wave_rank(cursors, t < 0 ? 0 : t, t >= 0);
+  if (t < 0) return;
+  int64_t q = starts[t] + scramble(r, counts[t]);
+  if (IMPORT) {
+    d.pc[q] = pack_cell<ND>(tg, idx);
+#pragma unroll
+    for (int k = 0; k < ND; ++k) d.off[k * d.cap + q] = cp.off[k * cp.n + p];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d.vel[k * d.cap + q] = cp.vel[k * cp.n + p];
+    d.wq[q] = cp.wq[p];
+    d.oidx[q] = (int)p;
+  } else {
+    d.pc[q] = s.pc[p];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) d.off[k * d.cap + q] = s.off[k * s.cap + p];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d.vel[k * d.cap + q] = s.vel[k * s.cap + p];
+    d.wq[q] = s.wq[p];
+    d.oidx[q] = s.oidx[p];
+  }
+  (void)err;
+}
+
+template <int ND>
+__global__ void __launch_bounds__(256) k_export(Geo g, TileGeo tg, Store s, int64_t n, PartPtrs cp) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int o = s.oidx[p];
+  int idx[3];
+  unpack_cell<ND>(tg, s.pc[p], idx);
+  cp.cell[o] = encode_cell<ND>(g, idx);
+#pragma unroll
+  for (int k = 0; k < ND; ++k) cp.off[k * cp.n + o] = s.off[k * s.cap + p];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) cp.vel[k * cp.n + o] = s.vel[k * s.cap + p];
+}
+
+// ---------------------------------------------------------------------------
+// Fused step
+// ---------------------------------------------------------------------------
+struct Window {
+  int o[3];   // node coordinate of window node 0 per axis
+  int wn[3];  // window nodes per axis (T + 2H + 3)
+  int nW, nC; // window nodes, window centres
+};
+
+template <int ND>
+__device__ __forceinline__ int win_node(const Window &w, int a0, int a1, int a2) {
+  return ND == 2 ? a0 + w.wn[0] * a1 : a0 + w.wn[0] * (a1 + w.wn[1] * a2);
+}
+template <int ND>
+__device__ __forceinline__ int win_centre(const Window &w, int m0, int m1, int m2) {
+  return ND == 2 ? m0 + (w.wn[0] - 1) * m1 : m0 + (w.wn[0] - 1) * (m1 + (w.wn[1] - 1) * m2);
+}
+
+// Global (window-free) density and gradient at a particle: 3^ND nodes around
+// the two nearest centres per axis, folded like the window (same bits).
+template <int ND>
+__device__ void gather_nodes_global(const Geo &g, const long long *__restrict__ N, const int idx[3],
+                                    const float f[3], float &nh, float Gp[3]) {
+  int c0[3] = {0, 0, 0};
+  float t[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int e = 0; e < ND; ++e) centre_stencil(idx[e], f[e], c0[e], t[e]);
+  float D[27];
+#pragma unroll
+  for (int a2 = 0; a2 < (ND == 3 ? 3 : 1); ++a2)
+#pragma unroll
+    for (int a1 = 0; a1 < 3; ++a1)
+#pragma unroll
+      for (int a0 = 0; a0 < 3; ++a0) {
+        int x = fold_node(g, 0, c0[0] + a0), y = fold_node(g, 1, c0[1] + a1);
+        int z = ND == 3 ? fold_node(g, 2, c0[2] + a2) : 0;
+        D[a0 + 3 * (a1 + 3 * a2)] = node_density(g, N[node_index<ND>(g, x, y, z)], x, y, z);
+      }
+  // cell corners: offset of the cell inside the 3^ND block (0 or 1 per axis)
+  int s0 = idx[0] - c0[0], s1 = idx[1] - c0[1], s2 = ND == 3 ? idx[2] - c0[2] : 0;
+  float cr[8];
+#pragma unroll
+  for (int k = 0; k < (1 << ND); ++k)
+    cr[k] = D[(s0 + (k & 1)) + 3 * ((s1 + ((k >> 1) & 1)) + 3 * (ND == 3 ? s2 + ((k >> 2) & 1) : 0))];
+  nh = interp<ND>(cr, f);
+  float Gc[8][3];
+#pragma unroll
+  for (int m = 0; m < (1 << ND); ++m) {
+    int m0 = m & 1, m1 = (m >> 1) & 1, m2 = ND == 3 ? (m >> 2) & 1 : 0;
+    float c[8];
+#pragma unroll
+    for (int k = 0; k < (1 << ND); ++k)
+      c[k] = D[(m0 + (k & 1)) + 3 * ((m1 + ((k >> 1) & 1)) + 3 * (ND == 3 ? m2 + ((k >> 2) & 1) : 0))];
+    centre_gradient<ND>(g, c, Gc[m]);
+  }
+  Gp[2] = 0.0f;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    float v[8];
+#pragma unroll
+    for (int m = 0; m < (1 << ND); ++m) v[m] = Gc[m][d];
+    Gp[d] = interp<ND>(v, t);
+  }
+}
+
+template <int ND>
+__device__ __forceinline__ void deposit_global(const Geo &g, unsigned long long *__restrict__ N, const int idx[3],
+                                               const uint32_t t[8]) {
+#pragma unroll
+  for (int k = 0; k < (1 << ND); ++k) {
+    if (!t[k]) continue;
+    int x = node_axis(g, 0, idx[0] + (k & 1)), y = node_axis(g, 1, idx[1] + ((k >> 1) & 1));
+    int z = ND == 3 ? node_axis(g, 2, idx[2] + ((k >> 2) & 1)) : 0;
+    atomicAdd(&N[node_index<ND>(g, x, y, z)], (unsigned long long)t[k]);
+  }
+}
+
+template <int ND>
+__device__ __forceinline__ Window make_window(const TileGeo &tg, int tile) {
+  Window w;
+  int tx = tile % tg.tn[0];
+  int r = tile / tg.tn[0];
+  int ty = ND == 2 ? r : r % tg.tn[1];
+  int tz = ND == 2 ? 0 : r / tg.tn[1];
+  w.o[0] = (tx << tg.lt[0]) - tg.H - 1;
+  w.o[1] = (ty << tg.lt[1]) - tg.H - 1;
+  w.o[2] = ND == 3 ? (tz << tg.lt[2]) - tg.H - 1 : 0;
+  w.nW = 1;
+  w.nC = 1;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    w.wn[d] = d < ND ? (1 << tg.lt[d]) + 2 * tg.H + 3 : 1;
+    w.nW *= w.wn[d];
+    w.nC *= d < ND ? w.wn[d] - 1 : 1;
+  }
+  return w;
+}
+
+// Stage the window: densities of the window nodes (folded like the global
+// path) and the centre gradients between them; clear the accumulator.
+template <int ND>
+__device__ __forceinline__ void stage_window(const Geo &g, const Window &w, const long long *__restrict__ N,
+                                             float *dens, float *Gs, unsigned long long *acc) {
+  for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
+    int a0 = k % w.wn[0], r = k / w.wn[0];
+    int a1 = ND == 2 ? r : r % w.wn[1];
+    int a2 = ND == 2 ? 0 : r / w.wn[1];
+    int x = fold_node(g, 0, w.o[0] + a0), y = fold_node(g, 1, w.o[1] + a1);
+    int z = ND == 3 ? fold_node(g, 2, w.o[2] + a2) : 0;
+    dens[k] = node_density(g, N[node_index<ND>(g, x, y, z)], x, y, z);
+    if (acc) acc[k] = 0ull;
+  }
+  __syncthreads();
+  if (!Gs) return;
+  const int wc0 = w.wn[0] - 1, wc1 = w.wn[1] - 1;
+  for (int m = threadIdx.x; m < w.nC; m += blockDim.x) {
+    int m0 = m % wc0, r = m / wc0;
+    int m1 = ND == 2 ? r : r % wc1;
+    int m2 = ND == 2 ? 0 : r / wc1;
+    float c[8], G[3];
+#pragma unroll
+    for (int k = 0; k < (1 << ND); ++k)
+      c[k] = dens[win_node<ND>(w, m0 + (k & 1), m1 + ((k >> 1) & 1), ND == 3 ? m2 + ((k >> 2) & 1) : 0)];
+    centre_gradient<ND>(g, c, G);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) Gs[d * w.nC + m] = G[d];
+  }
+  __syncthreads();
+}
+
+template <int ND>
+__device__ __forceinline__ void flush_window(const Geo &g, const Window &w, const unsigned long long *acc,
+                                             unsigned long long *__restrict__ N) {
+  for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
+    unsigned long long v = acc[k];
+    if (!v) continue;
+    int a0 = k % w.wn[0], r = k / w.wn[0];
+    int a1 = ND == 2 ? r : r % w.wn[1];
+    int a2 = ND == 2 ? 0 : r / w.wn[1];
+    // deposits only ever land on nodes inside the domain; wrap periodic axes
+    int x = fold_node(g, 0, w.o[0] + a0), y = fold_node(g, 1, w.o[1] + a1);
+    int z = ND == 3 ? fold_node(g, 2, w.o[2] + a2) : 0;
+    atomicAdd(&N[node_index<ND>(g, x, y, z)], v);
+  }
+}
+
+__device__ __forceinline__ void clear_share(long long *__restrict__ Z, int nnodes) {
+  if (!Z) return;
+  int share = (nnodes + gridDim.x - 1) / gridDim.x;
+  int lo = blockIdx.x * share, hi = min(nnodes, lo + share);
+  for (int k = lo + threadIdx.x; k < hi; k += blockDim.x) Z[k] = 0;
+}
+
+// Window coordinates of a cell; returns true if inside [lo, hi] on every axis.
+template <int ND>
+__device__ __forceinline__ bool in_window(const Geo &g, const Window &w, const int idx[3], int lo, int hi_off,
+                                          int l[3]) {
+  bool ok = true;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    l[d] = window_coord(g, d, idx[d], w.o[d], lo);
+    ok = ok && l[d] >= lo && l[d] <= w.wn[d] - hi_off;
+  }
+  return ok;
+}
+
+template <int ND, bool DIAG>
+__global__ void __launch_bounds__(256) k_step_tiled(Geo g, Pot P, DiagC dc, TileGeo tg, Store s,
+                                                    const Item *__restrict__ items,
+                                                    const int *__restrict__ num_items,
+                                                    const long long *__restrict__ Ncur,
+                                                    unsigned long long *__restrict__ Nnext,
+                                                    long long *__restrict__ Nclear, double *__restrict__ partial,
+                                                    uint32_t *__restrict__ err) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  clear_share(Nclear, g.nnodes);
+  if ((int)blockIdx.x >= *num_items) return;
+  const Item it = items[blockIdx.x];
+  const Window w = make_window<ND>(tg, it.tile);
+  unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
+  float *dens = reinterpret_cast<float *>(acc + w.nW);
+  float *Gs = dens + w.nW;
+  stage_window<ND>(g, w, Ncur, dens, Gs, acc);
+
+  double a_ke = 0.0, a_px = 0.0, a_py = 0.0, a_pz = 0.0, a_w = 0.0, a_b = 0.0;
+  uint32_t e_all = 0;
+  const int64_t cap = s.cap;
+  for (int p = it.start + threadIdx.x; p < it.end; p += blockDim.x) {
+    const int pc = s.pc[p];
+    float f[3] = {s.off[p], s.off[cap + p], ND == 3 ? s.off[2 * cap + p] : 0.0f};
+    float v[3] = {s.vel[p], s.vel[cap + p], (ND == 3 || DIAG) ? s.vel[2 * cap + p] : 0.0f};
+    const int W = s.wq[p];
+    int idx[3];
+    unpack_cell<ND>(tg, pc, idx);
+    // gather
+    float nh, Gp[3];
+    int l[3];
+    if (in_window<ND>(g, w, idx, 1, 3, l)) {
+      float cr[8];
+#pragma unroll
+      for (int k = 0; k < (1 << ND); ++k)
+        cr[k] = dens[win_node<ND>(w, l[0] + (k & 1), l[1] + ((k >> 1) & 1), ND == 3 ? l[2] + ((k >> 2) & 1) : 0)];
+      nh = interp<ND>(cr, f);
+      int c0[3] = {0, 0, 0};
+      float t[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int e = 0; e < ND; ++e) centre_stencil(l[e], f[e], c0[e], t[e]);
+      Gp[2] = 0.0f;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        float vv[8];
+#pragma unroll
+        for (int k = 0; k < (1 << ND); ++k)
+          vv[k] = Gs[d * w.nC + win_centre<ND>(w, c0[0] + (k & 1), c0[1] + ((k >> 1) & 1),
+                                               ND == 3 ? c0[2] + ((k >> 2) & 1) : 0)];
+        Gp[d] = interp<ND>(vv, t);
+      }
+    } else {
+      gather_nodes_global<ND>(g, Ncur, idx, f, nh, Gp);
+    }
+    float Fh[3], bond = 0.0f;
+    pair_force<ND>(P, nh, Gp, Fh, DIAG ? &bond : nullptr);
+    float F[3] = {Fh[0] * P.beta, Fh[1] * P.beta, ND == 3 ? Fh[2] * P.beta : 0.0f};
+    if (DIAG) {
+      double wgt = (double)W * dc.wunit, vo2 = 0.0, vn2 = 0.0, pm[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        float vn = d < ND ? __builtin_fmaf(F[d], P.gv, v[d]) : v[d];
+        vo2 += (double)v[d] * v[d];
+        vn2 += (double)vn * vn;
+        pm[d] = wgt * dc.mass * 0.5 * ((double)v[d] + (double)vn);
+      }
+      a_ke += wgt * dc.half_m * 0.5 * (vo2 + vn2);
+      a_px += pm[0];
+      a_py += pm[1];
+      a_pz += pm[2];
+      a_w += wgt;
+      a_b += wgt * (double)bond * dc.D;
+    }
+    e_all |= push_particle<ND>(g, P, F, idx, f, v);
+    const int pc2 = pack_cell<ND>(tg, idx);
+    if (pc2 != pc) s.pc[p] = pc2;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      s.off[d * cap + p] = f[d];
+      s.vel[d * cap + p] = v[d];
+    }
+    // deposit the new position into the next step's node sums
+    uint32_t tq[8];
+    deposit_shares<ND>((uint32_t)W, f, tq);
+    if (in_window<ND>(g, w, idx, 0, 2, l)) {
+#pragma unroll
+      for (int k = 0; k < (1 << ND); ++k)
+        if (tq[k])
+          atomicAdd(&acc[win_node<ND>(w, l[0] + (k & 1), l[1] + ((k >> 1) & 1), ND == 3 ? l[2] + ((k >> 2) & 1) : 0)],
+                    (unsigned long long)tq[k]);
+    } else {
+      deposit_global<ND>(g, Nnext, idx, tq);
+    }
+  }
+  if (e_all) atomicOr(err, e_all);
+  __syncthreads();
+  flush_window<ND>(g, w, acc, Nnext);
+  if (DIAG) {
+    double v6[6] = {a_ke, a_px, a_py, a_pz, a_w, a_b};
+    block_reduce_store<6>(v6, partial + (int64_t)blockIdx.x * 8);
+  }
+}
+
+// Deposit only (the node sums of the current positions), same tiling.
+template <int ND>
+__global__ void __launch_bounds__(256) k_deposit_tiled(Geo g, TileGeo tg, Store s, const Item *__restrict__ items,
+                                                       const int *__restrict__ num_items,
+                                                       unsigned long long *__restrict__ N) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if ((int)blockIdx.x >= *num_items) return;
+  const Item it = items[blockIdx.x];
+  const Window w = make_window<ND>(tg, it.tile);
+  unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
+  for (int k = threadIdx.x; k < w.nW; k += blockDim.x) acc[k] = 0ull;
+  __syncthreads();
+  const int64_t cap = s.cap;
+  for (int p = it.start + threadIdx.x; p < it.end; p += blockDim.x) {
+    float f[3] = {s.off[p], s.off[cap + p], ND == 3 ? s.off[2 * cap + p] : 0.0f};
+    int idx[3], l[3];
+    unpack_cell<ND>(tg, s.pc[p], idx);
+    uint32_t tq[8];
+    deposit_shares<ND>((uint32_t)s.wq[p], f, tq);
+    if (in_window<ND>(g, w, idx, 0, 2, l)) {
+#pragma unroll
+      for (int k = 0; k < (1 << ND); ++k)
+        if (tq[k])
+          atomicAdd(&acc[win_node<ND>(w, l[0] + (k & 1), l[1] + ((k >> 1) & 1), ND == 3 ? l[2] + ((k >> 2) & 1) : 0)],
+                    (unsigned long long)tq[k]);
+    } else {
+      deposit_global<ND>(g, N, idx, tq);
+    }
+  }
+  __syncthreads();
+  flush_window<ND>(g, w, acc, N);
+}
+
+__global__ void __launch_bounds__(256) k_reduce_diag_dev(const double *__restrict__ part_p,
+                                                         const int *__restrict__ nblk_p_dev,
+                                                         const double *__restrict__ part_g, int nblk_g,
+                                                         pic_diag_t *__restrict__ out, int64_t step) {
+  const int nblk_p = *nblk_p_dev;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblk_p; b += blockDim.x)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc[i] += part_p[(int64_t)b * 8 + i];
+  for (int b = threadIdx.x; b < nblk_g; b += blockDim.x) acc[6] += part_g[(int64_t)b * 8];
+  __shared__ double res[8];
+  block_reduce_store<7>(acc, res);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out->ke = res[0];
+    out->px = res[1];
+    out->py = res[2];
+    out->pz = res[3];
+    out->wsum = res[4];
+    out->bond = res[5];
+    out->pe = res[6];
+    out->step = step;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+size_t window_lds_bytes(const TileGeo &tg, int ndim) {
+  size_t nW = 1, nC = 1;
+  for (int d = 0; d < ndim; ++d) {
+    size_t wn = (size_t)(1 << tg.lt[d]) + 2 * tg.H + 3;
+    nW *= wn;
+    nC *= wn - 1;
+  }
+  return nW * 8 + nW * 4 + nC * 4 * ndim;
+}
+
+void launch_bin(hipStream_t st, const Geo &g, const TileGeo &tg, const PartPtrs &cp, const Store &src,
+                const Store &dst, int64_t n, const BinBufs &b, bool import, uint32_t *err) {
+  launch_fill32(st, b.counts, tg.ntiles);
+  if (n > 0) {
+    if (g.ndim == 2) {
+      if (import) k_tile_hist<2, true><<<nblk(n), 256, 0, st>>>(g, tg, cp, src, n, b.counts, err);
+      else k_tile_hist<2, false><<<nblk(n), 256, 0, st>>>(g, tg, cp, src, n, b.counts, err);
+    } else {
+      if (import) k_tile_hist<3, true><<<nblk(n), 256, 0, st>>>(g, tg, cp, src, n, b.counts, err);
+      else k_tile_hist<3, false><<<nblk(n), 256, 0, st>>>(g, tg, cp, src, n, b.counts, err);
+    }
+  }
+  k_tile_scan<<<1, 1024, 0, st>>>(tg.ntiles, tg.chunk, b.counts, b.starts, b.item_start, b.cursors, b.num_items);
+  k_tile_items<<<nblk(tg.ntiles), 256, 0, st>>>(tg.ntiles, tg.chunk, b.counts, b.starts, b.item_start, b.items);
+  if (n > 0) {
+    if (g.ndim == 2) {
+      if (import)
+        k_tile_scatter<2, true><<<nblk(n), 256, 0, st>>>(g, tg, cp, src, dst, n, b.counts, b.starts, b.cursors, err);
+      else
+        k_tile_scatter<2, false><<<nblk(n), 256, 0, st>>>(g, tg, cp, src, dst, n, b.counts, b.starts, b.cursors, err);
+    } else {
+      if (import)
+        k_tile_scatter<3, true><<<nblk(n), 256, 0, st>>>(g, tg, cp, src, dst, n, b.counts, b.starts, b.cursors, err);
+      else
+        k_tile_scatter<3, false><<<nblk(n), 256, 0, st>>>(g, tg, cp, src, dst, n, b.counts, b.starts, b.cursors, err);
+    }
+  }
+}
+
+void launch_export(hipStream_t st, const Geo &g, const TileGeo &tg, const Store &s, int64_t n, const PartPtrs &cp) {
+  if (n <= 0) return;
+  if (g.ndim == 2) k_export<2><<<nblk(n), 256, 0, st>>>(g, tg, s, n, cp);
+  else k_export<3><<<nblk(n), 256, 0, st>>>(g, tg, s, n, cp);
+}
+
+void launch_deposit_tiled(hipStream_t st, const Geo &g, const TileGeo &tg, const Store &s, const BinBufs &b,
+                          int max_items, long long *N) {
+  if (max_items <= 0) return;
+  size_t lds = 0;
+  {
+    size_t nW = 1;
+    for (int d = 0; d < g.ndim; ++d) nW *= (size_t)(1 << tg.lt[d]) + 2 * tg.H + 3;
+    lds = nW * 8;
+  }
+  if (g.ndim == 2)
+    k_deposit_tiled<2><<<max_items, 256, lds, st>>>(g, tg, s, b.items, b.num_items, (unsigned long long *)N);
+  else
+    k_deposit_tiled<3><<<max_items, 256, lds, st>>>(g, tg, s, b.items, b.num_items, (unsigned long long *)N);
+}
+
+void launch_step_tiled(hipStream_t st, const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
+                       const Store &s, const BinBufs &b, int max_items, const long long *Ncur, long long *Nnext,
+                       long long *Nclear, double *partial, bool diag, uint32_t *err) {
+  if (max_items <= 0) return;
+  size_t lds = window_lds_bytes(tg, g.ndim);
+  unsigned long long *nn = (unsigned long long *)Nnext;
+  if (g.ndim == 2) {
+    if (diag)
+      k_step_tiled<2, true><<<max_items, 256, lds, st>>>(g, P, dc, tg, s, b.items, b.num_items, Ncur, nn, Nclear,
+                                                         partial, err);
+    else
+      k_step_tiled<2, false><<<max_items, 256, lds, st>>>(g, P, dc, tg, s, b.items, b.num_items, Ncur, nn, Nclear,
+                                                          partial, err);
+  } else {
+    if (diag)
+      k_step_tiled<3, true><<<max_items, 256, lds, st>>>(g, P, dc, tg, s, b.items, b.num_items, Ncur, nn, Nclear,
+                                                         partial, err);
+    else
+      k_step_tiled<3, false><<<max_items, 256, lds, st>>>(g, P, dc, tg, s, b.items, b.num_items, Ncur, nn, Nclear,
+                                                          partial, err);
+  }
+}
+
+void launch_reduce_diag_dev(hipStream_t st, const double *part_p, const int *nblk_p, const double *part_g,
+                            int nblk_g, pic_diag_t *out, int64_t step) {
+  k_reduce_diag_dev<<<1, 256, 0, st>>>(part_p, nblk_p, part_g, nblk_g, out, step);
+}
+
+}  // namespace pic

@@ -87,9 +87,9 @@ class Particles:
     off: np.ndarray           # float32 [ndim, N], each in [0, 1)
     vel: np.ndarray           # float32 [3, N], m/s
     wq: np.ndarray            # int32 [N], weight * 2**20
-    xi: Optional[np.ndarray] = None      # float64 [3, N] kick noise (None without laser)
+    xi: Optional[np.ndarray] = None      # float32 [3, N] kick noise (None without laser)
     sigma: Optional[np.ndarray] = None   # float64 [N] kick std per component, m/s
-    v_thermal: Optional[np.ndarray] = None  # float64 [3, N] before the kick
+    v_thermal: Optional[np.ndarray] = None  # float32 [3, N] before the kick
 
     @property
     def n(self) -> int:
@@ -161,11 +161,12 @@ def make_slab(ndim: int, n: tuple, slab_layers: int, ppc: int, h: float, seed: i
     w = atoms_per_cell / ppc
     wq = np.full(N, weight_q(w), dtype=np.int32)
     sig_th = math.sqrt(KB * T / pot.mass) if T > 0 else 0.0
-    v_th = rng_mb.standard_normal((3, N)) * sig_th
+    v_th = rng_mb.standard_normal((3, N), dtype=np.float32)
+    v_th *= np.float32(sig_th)
     xi = sigma = None
     vel = v_th
     if fluence_Jcm2 > 0.0:
-        xi = rng_kick.standard_normal((3, N))
+        xi = rng_kick.standard_normal((3, N), dtype=np.float32)
         nx = n[0]
         i = cell.astype(np.int64) % nx
         layer = cell.astype(np.int64) // lateral
@@ -174,8 +175,8 @@ def make_slab(ndim: int, n: tuple, slab_layers: int, ppc: int, h: float, seed: i
         y_s = slab_layers * h
         x_c = (x_c_cells if x_c_cells is not None else nx / 2.0) * h
         sigma = heating_sigma(x, y_s - y, fluence_Jcm2 * 1e4, R_cells * h, x_c, delta=delta, mass=pot.mass)
-        vel = v_th + sigma[None, :] * xi
-    parts = Particles(cell=cell, off=off, vel=vel.astype(np.float32), wq=wq,
+        vel = (v_th + sigma[None, :] * xi).astype(np.float32)
+    parts = Particles(cell=cell, off=off, vel=np.ascontiguousarray(vel, dtype=np.float32), wq=wq,
                       xi=xi, sigma=sigma, v_thermal=v_th if xi is not None else None)
     return grid, parts
 
