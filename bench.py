@@ -20,10 +20,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes of the dominant kernel per particle per launch (the
-# particle state read once and written once):
-#   fused gather+force+push: reads cell 4 + off 4*ndim + vel 12, writes the same.
-DEFAULTS = {"large": (200, 10), "heated": (1000, 20), "small": (1000, 20)}
+# Algorithmic bytes of one launch of the dominant (fused) kernel: each
+# particle's state read once and written once -- reads cell 4 + offsets
+# 4*ndim + velocity 12 + weight 4, writes cell 4 + offsets 4*ndim + velocity
+# 12: 52 B in 2D, 60 B in 3D -- plus 16 B per node (int64 sums written once
+# and read once).
+DEFAULTS = {"large": (2000, 20), "heated": (5000, 20), "small": (200, 20)}
 
 
 def log(msg):
@@ -69,6 +71,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="large", choices=["large", "heated", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a plain 1 GiB device copy first (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -82,6 +86,13 @@ def main():
     from paper_1502_07722_amd import binding as B
     from paper_1502_07722_amd import workloads as W
 
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)  # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.perf_counter()
     wl = W.WORKLOADS[args.workload]()
     log(f"generated {wl.name}: {wl.parts.n} particles in {time.perf_counter() - t0:.1f} s")
@@ -110,14 +121,18 @@ def main():
     value = N * steps / elapsed
 
     nd = wl.grid.ndim
-    bytes_per_particle = 2 * (4 + 4 * nd + 12)
+    bytes_per_particle = 4 + 4 * nd + 12 + 4 + 4 + 4 * nd + 12
+    nnodes = B.pic_num_nodes(wl.grid)
+    launch_bytes = bytes_per_particle * N + 16 * nnodes
     ms_fp, nfp = timing.get("force_push", (0.0, 0))
     avg_s = ms_fp / 1e3 / max(nfp, 1)
-    achieved = bytes_per_particle * N / avg_s / 1e9 if nfp else None
-    roofline = {"bound": "hbm", "kernel": "k_force_push", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
-                "bytes_per_particle": bytes_per_particle, "avg_launch_ms": avg_s * 1e3,
-                "phases_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in timing.items()}}
+    achieved = launch_bytes / avg_s / 1e9 if nfp else None
+    roofline = {"bound": "hbm", "kernel": "k_step_tiled (fused gather+force+push+deposit)", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                "traffic": None, "bytes_per_launch": launch_bytes, "bytes_per_particle": bytes_per_particle,
+                "bytes_per_node": 16, "avg_launch_ms": avg_s * 1e3,
+                "phases_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in timing.items() if isinstance(v, tuple)},
+                "drifters_last_step": timing.get("drifters_last"), "items_last_step": timing.get("items_last")}
     out = {
         "metric": "particle-steps/s (deposit+force+push)",
         "value": value,

@@ -170,10 +170,12 @@ int pic_step(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, pic_diag_t *dia
  *   tile        tile edge in cells, a power of two (2D 8..32, 3D 4..8);
  *   halo        cells a particle may drift out of its tile between binnings
  *               before it takes the slower global path (1..4);
- *   chunk       most particles per work item (1024..2^20);
+ *   chunk       most particles per work item (1024..32768);
  *   sort_every  re-bin particles by tile every this many steps (0 = never).
  * Grids with more than 65536 x 32768 (2D) or 2048 x 2048 x 512 (3D) cells,
- * or max_n >= 2^31, use the untiled kernels and reject this call. */
+ * or max_n >= 2^30, use the untiled kernels and reject this call.  A tiling
+ * whose window (tile + 2 halo + 3 nodes) is longer than a periodic axis is
+ * rejected too. */
 int pic_set_tiling(pic_ctx_t *ctx, int32_t tile, int32_t halo, int32_t chunk, int32_t sort_every);
 
 /* 1: make pic_step use the untiled kernels (separate deposit, grid pass and
@@ -187,12 +189,16 @@ int pic_step_nodes(pic_ctx_t *ctx, int64_t *node_w);
 /* Per-phase device time of pic_step, measured with HIP events recorded on
  * the bound stream around each launch (only while timing is on).
  * Phases: 0 deposit (incl. clearing the node sums), 1 density and gradient
- * grid pass, 2 gather+force+push (the dominant kernel), 3 particle sort,
- * 4 diagnostics reductions. */
+ * grid pass, 2 gather+force+push (the dominant kernel: in the tiled step the
+ * fused kernel), 3 re-binning by tile, 4 diagnostics reductions, 5 import of
+ * the caller's arrays into the binned store and export back, 6 the tiled
+ * step's drifter kernel (particles outside their tile window). */
 #define PIC_NPHASES 8
 typedef struct pic_timing {
   double ms[PIC_NPHASES];        /* summed kernel time per phase, ms */
   int64_t launches[PIC_NPHASES]; /* timed launches per phase */
+  int64_t drifters_last;         /* drifters in the last step of the last tiled pic_step */
+  int64_t items_last;            /* work items of that step */
 } pic_timing_t;
 
 /* Turn event timing of pic_step on (1) or off (0); turning it on clears the

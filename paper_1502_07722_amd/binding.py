@@ -42,11 +42,12 @@ class pic_diag_t(C.Structure):
 
 
 DIAG_FIELDS = ("ke", "pe", "px", "py", "pz", "wsum", "bond", "step")
-PHASES = ("deposit", "grid", "force_push", "sort", "diag", "p5", "p6", "p7")
+PHASES = ("deposit", "grid", "force_push", "sort", "diag", "import_export", "drifters", "p7")
 
 
 class pic_timing_t(C.Structure):
-    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8), ("drifters_last", C.c_int64),
+                ("items_last", C.c_int64)]
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())")
@@ -255,7 +256,10 @@ class Context:
     def pic_get_timing(self):
         t = pic_timing_t()
         self._check(lib.pic_get_timing(self.ctx, C.byref(t)), "pic_get_timing")
-        return {PHASES[i]: (t.ms[i], t.launches[i]) for i in range(8) if t.launches[i]}
+        out = {PHASES[i]: (t.ms[i], t.launches[i]) for i in range(8) if t.launches[i]}
+        out["drifters_last"] = t.drifters_last
+        out["items_last"] = t.items_last
+        return out
 
     def start_leapfrog(self, parts: DeviceParticles):
         """v(0) -> v(-1/2) = v(0) - F(0)/m dt/2."""

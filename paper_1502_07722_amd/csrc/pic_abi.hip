@@ -45,7 +45,7 @@ bool grid_sizes(const pic_grid_t *g, Sizes *s, std::string *why) {
 
 // Tiled fast path limits: packed cell coordinates and tile sizes.
 bool tiled_supported(const pic_grid_t *g, int64_t max_n) {
-  if (max_n >= (int64_t(1) << 31)) return false;
+  if (max_n >= (int64_t(1) << 30)) return false;  // 32-bit byte offsets into the store
   if (g->ndim == 2) return g->n[0] <= 65536 && g->n[1] <= 32768;
   return g->n[0] <= 2048 && g->n[1] <= 2048 && g->n[2] <= 512;
 }
@@ -64,11 +64,12 @@ int64_t max_items_for(const pic_grid_t *g, int lt, int64_t max_n, int chunk) {
 }
 
 constexpr int kMinChunk = 1024;
+constexpr int kMaxChunkHost = 32768;  // the fused kernel keeps a per-item outlier bitmask in LDS
 
 struct Layout {
   size_t err, diag, partial, partial_pe, node, dens, G, total;
   bool tiled;
-  size_t store[2], bins, items, n3[3];
+  size_t store[2], bins, items, n3[3], drift;
   int64_t tiles_max, items_max;
 };
 
@@ -80,7 +81,8 @@ Layout make_layout(const pic_grid_t *g, const Sizes &s, int ndim, int64_t max_n)
   L.tiled = tiled_supported(g, max_n);
   L.tiles_max = L.tiled ? tiles_for(g, min_tile_log2(ndim)) : 0;
   L.items_max = L.tiled ? max_items_for(g, min_tile_log2(ndim), max_n, kMinChunk) : 0;
-  const int64_t partial_blocks = std::max<int64_t>(std::max<int64_t>(blocks_of(max_n), L.items_max), 1);
+  const int64_t partial_blocks =
+      std::max<int64_t>(std::max<int64_t>(blocks_of(max_n), L.items_max + kDriftBlocks), 1);
   L.err = o; o = align_up(o + sizeof(uint32_t));
   L.diag = o; o = align_up(o + sizeof(pic_diag_t) * kDiagCap);
   L.partial = o; o = align_up(o + sizeof(double) * 8 * (size_t)partial_blocks);
@@ -93,6 +95,7 @@ Layout make_layout(const pic_grid_t *g, const Sizes &s, int ndim, int64_t max_n)
     L.bins = o; o = align_up(o + sizeof(int) * (size_t)(4 * L.tiles_max + 2));
     L.items = o; o = align_up(o + sizeof(Item) * (size_t)L.items_max);
     for (int k = 0; k < 3; ++k) { L.n3[k] = o; o = align_up(o + sizeof(long long) * (size_t)s.nnodes); }
+    L.drift = o; o = align_up(o + sizeof(int) * (size_t)(std::max<int64_t>(max_n, 1) + 2));
   }
   L.total = o;
   return L;
@@ -125,10 +128,12 @@ struct pic_ctx {
   Store st[2]{};
   BinBufs bb{};
   long long *n3[3]{};
+  int *drift = nullptr;  // [2 counters][max_n list]
   int64_t tiles_cap = 0, items_cap = 0;
   int sort_every = 0;
   bool force_untiled = false;
   long long *last_nodes = nullptr;
+  int last_step = 0;
   // event timing of pic_step phases
   bool timing = false;
   pic_timing_t tacc{};
@@ -235,7 +240,7 @@ static int apply_tiling(pic_ctx_t *c, int lt, int halo, int chunk, int sort_ever
   const int nd = c->grid.ndim;
   if (lt < min_tile_log2(nd) || lt > max_tile_log2(nd)) return fail(c, PIC_EINVAL, "tile edge out of range");
   if (halo < 1 || halo > 4) return fail(c, PIC_EINVAL, "halo must be 1..4 cells");
-  if (chunk < kMinChunk || chunk > (1 << 20)) return fail(c, PIC_EINVAL, "chunk out of range");
+  if (chunk < kMinChunk || chunk > kMaxChunkHost) return fail(c, PIC_EINVAL, "chunk out of range");
   if (sort_every < 0) return fail(c, PIC_EINVAL, "sort_every must be >= 0");
   TileGeo &T = c->tg;
   T.ntiles = 1;
@@ -248,6 +253,9 @@ static int apply_tiling(pic_ctx_t *c, int lt, int halo, int chunk, int sort_ever
   T.chunk = chunk;
   TileGeo probe = T;
   if (window_lds_bytes(probe, nd) > 64 * 1024) return fail(c, PIC_EINVAL, "tile window does not fit in LDS");
+  for (int d = 0; d < nd; ++d)  // periodic axes must hold a whole window (single-wrap window coordinates)
+    if (!c->grid.bc[d] && c->grid.n[d] < (1 << lt) + 2 * halo + 3)
+      return fail(c, PIC_EINVAL, "a periodic axis is shorter than the tile window");
   c->sort_every = sort_every;
   return PIC_OK;
 }
@@ -357,6 +365,7 @@ int pic_init(pic_ctx_t **out, const pic_grid_t *grid, const pic_potential_t *pot
     c->bb.num_items = bi + 4 * L.tiles_max + 1;
     c->bb.items = reinterpret_cast<Item *>(c->ws + L.items);
     for (int k = 0; k < 3; ++k) c->n3[k] = reinterpret_cast<long long *>(c->ws + L.n3[k]);
+    c->drift = reinterpret_cast<int *>(c->ws + L.drift);
     c->tiles_cap = L.tiles_max;
     c->items_cap = L.items_max;
     TileGeo &T = c->tg;
@@ -373,11 +382,16 @@ int pic_init(pic_ctx_t **out, const pic_grid_t *grid, const pic_potential_t *pot
     return PIC_EHIP;
   }
   if (c->tiled) {
-    int rc = g.ndim == 2 ? apply_tiling(c, 4, 2, 8192, 32) : apply_tiling(c, 3, 1, 4096, 16);
-    if (rc) {
-      delete c;
-      return rc;
+    // default tiling; smaller tiles for small periodic grids; untiled if none fits
+    int rc = PIC_EINVAL;
+    if (g.ndim == 2) {
+      for (int lt = 4; lt >= 3 && rc; --lt) rc = apply_tiling(c, lt, 2, 8192, 32);
+      if (rc) rc = apply_tiling(c, 3, 1, 8192, 32);
+    } else {
+      for (int lt = 3; lt >= 2 && rc; --lt) rc = apply_tiling(c, lt, 1, 4096, 16);
     }
+    if (rc) c->tiled = false;
+    c->last_error.clear();
   }
   *out = c;
   return PIC_OK;
@@ -412,6 +426,16 @@ int pic_get_timing(pic_ctx_t *ctx, pic_timing_t *out) {
   if (!ctx || !out) return PIC_EINVAL;
   harvest_events(ctx);
   *out = ctx->tacc;
+  out->drifters_last = out->items_last = 0;
+  if (ctx->tiled && ctx->last_nodes) {
+    int h[3] = {0, 0, 0};
+    (void)hipMemcpyAsync(&h[0], ctx->drift, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+    (void)hipMemcpyAsync(&h[2], ctx->bb.num_items, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+    int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "stream synchronize");
+    if (rc) return rc;
+    out->drifters_last = h[(ctx->last_step + 1) & 1];
+    out->items_last = h[2];
+  }
   return PIC_OK;
 }
 
@@ -545,7 +569,7 @@ int step_tiled(pic_ctx_t *ctx, const PartPtrs &pp, int32_t nsteps, DiagSink &ds,
   const Store none{};
   // bring the caller's particles into the binned store; stop on invalid input
   {
-    PhaseTimer t(ctx, 3);
+    PhaseTimer t(ctx, 5);
     launch_bin(ctx->stream, g, ctx->tg, pp, none, ctx->st[cur], n, ctx->bb, true, ctx->err);
   }
   int rc = check_launch(ctx, "binning");
@@ -554,6 +578,7 @@ int step_tiled(pic_ctx_t *ctx, const PartPtrs &pp, int32_t nsteps, DiagSink &ds,
   const int64_t max_items = max_items_now(ctx, n);
   launch_fill64(ctx->stream, ctx->n3[0], ctx->sz.nnodes);
   launch_fill64(ctx->stream, ctx->n3[1], ctx->sz.nnodes);
+  launch_fill32(ctx->stream, ctx->drift, 2);
   {
     PhaseTimer t(ctx, 0);
     launch_deposit_tiled(ctx->stream, g, ctx->tg, ctx->st[cur], ctx->bb, (int)max_items, ctx->n3[0]);
@@ -566,6 +591,7 @@ int step_tiled(pic_ctx_t *ctx, const PartPtrs &pp, int32_t nsteps, DiagSink &ds,
     }
     const bool want = ds.host && (s % diag_every) == 0;
     long long *Nc = ctx->n3[s % 3], *Nn = ctx->n3[(s + 1) % 3], *Nz = ctx->n3[(s + 2) % 3];
+    const Drift dr{ctx->drift + 2, ctx->drift + (s & 1), ctx->drift + ((s + 1) & 1), (int)ctx->items_cap};
     int nbg = 0;
     if (want) {
       PhaseTimer t(ctx, 4);
@@ -574,20 +600,26 @@ int step_tiled(pic_ctx_t *ctx, const PartPtrs &pp, int32_t nsteps, DiagSink &ds,
     {
       PhaseTimer t(ctx, 2);
       launch_step_tiled(ctx->stream, g, ctx->P, ctx->dc, ctx->tg, ctx->st[cur], ctx->bb, (int)max_items, Nc, Nn,
-                        Nz, ctx->partial, want, ctx->err);
+                        Nz, dr, ctx->partial, want, ctx->err);
+    }
+    {
+      PhaseTimer t(ctx, 6);
+      launch_drifters(ctx->stream, g, ctx->P, ctx->dc, ctx->tg, ctx->st[cur], Nc, Nn, dr, ctx->partial, want,
+                      ctx->err);
     }
     if (want) {
       PhaseTimer t(ctx, 4);
-      launch_reduce_diag_dev(ctx->stream, ctx->partial, ctx->bb.num_items, ctx->partial_pe, nbg, ds.next(), s);
+      launch_reduce_diag_dev(ctx->stream, ctx->partial, ctx->bb.num_items, dr, ctx->partial_pe, nbg, ds.next(), s);
     }
     if ((rc = check_launch(ctx, "tiled step"))) return rc;
     if (want && (rc = ds.advance())) return rc;
   }
   {
-    PhaseTimer t(ctx, 3);
+    PhaseTimer t(ctx, 5);
     launch_export(ctx->stream, g, ctx->tg, ctx->st[cur], n, pp);
   }
   ctx->last_nodes = ctx->n3[nsteps % 3];
+  ctx->last_step = nsteps - 1;
   return check_launch(ctx, "export");
 }
 

@@ -208,7 +208,10 @@ __device__ __forceinline__ void pair_force(const Pot &P, float nh, const float G
 // Leapfrog push of one particle (kick with the force in newtons, then drift,
 // carry, wrap / mirror).  Returns device error bits.
 // ---------------------------------------------------------------------------
-template <int ND>
+// INTERIOR: the caller guarantees the particle is at least one cell away from
+// every wall and from the periodic seam, so no mirror or wrap can occur; the
+// carry arithmetic is the same, so both variants give the same bits.
+template <int ND, bool INTERIOR = false>
 __device__ __forceinline__ uint32_t push_particle(const Geo &g, const Pot &P, const float F[3],
                                                   int idx[3], float f[3], float v[3]) {
   uint32_t err = 0;
@@ -217,30 +220,35 @@ __device__ __forceinline__ uint32_t push_particle(const Geo &g, const Pot &P, co
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     float df = v[d] * g.tau[d];
-    if (!(fabsf(df) < 1.0f)) { err |= ERR_CFL; df = 0.0f; }
-    float x = f[d] + df;
-    int n = g.n[d];
-    if (g.bc[d] && idx[d] == 0 && x < 0.0f) {
-      x = -x;
-      v[d] = -v[d];
-    } else if (g.bc[d] && idx[d] == n - 1 && x >= 1.0f) {
-      x = 2.0f - x;
-      v[d] = -v[d];
-      if (x >= 1.0f) x = 0x1.fffffep-1f;  // exactly on the wall
-    } else if (x >= 1.0f) {
-      x -= 1.0f;
-      idx[d] += 1;
-    } else if (x < 0.0f) {
-      x += 1.0f;
-      idx[d] -= 1;
-      if (x >= 1.0f) { x = 0.0f; idx[d] += 1; }  // rounded onto the node itself
+    const bool cfl = !(fabsf(df) < 1.0f);
+    err |= cfl ? ERR_CFL : 0u;
+    df = cfl ? 0.0f : df;
+    const float x = f[d] + df;
+    const bool up = x >= 1.0f, down = x < 0.0f;
+    // carry one cell; a tiny negative x can round x + 1 up to 1: that is the node itself
+    float xc = up ? x - 1.0f : (down ? x + 1.0f : x);
+    int ic = idx[d] + (up ? 1 : (down ? -1 : 0));
+    const bool tie = down && xc >= 1.0f;
+    xc = tie ? 0.0f : xc;
+    ic = tie ? idx[d] : ic;
+    float xn = xc;
+    if (!INTERIOR) {
+      const int n = g.n[d];
+      const bool wall_lo = g.bc[d] && idx[d] == 0 && down;
+      const bool wall_hi = g.bc[d] && idx[d] == n - 1 && up;
+      if (!g.bc[d]) ic = ic < 0 ? ic + n : (ic >= n ? ic - n : ic);
+      // mirror at reflecting walls (2 - x is exact for x in [1, 2))
+      float xm = wall_lo ? -x : 2.0f - x;
+      xm = (wall_hi && xm >= 1.0f) ? 0x1.fffffep-1f : xm;  // exactly on the top wall
+      const bool wall = wall_lo || wall_hi;
+      xn = wall ? xm : xc;
+      ic = wall ? idx[d] : ic;
+      v[d] = wall ? -v[d] : v[d];
     }
-    if (!g.bc[d]) {
-      if (idx[d] < 0) idx[d] += n;
-      else if (idx[d] >= n) idx[d] -= n;
-    }
-    if (!(x >= 0.0f && x < 1.0f)) { err |= ERR_RANGE; x = 0.0f; }
-    f[d] = x;
+    idx[d] = ic;
+    const bool bad = !(xn >= 0.0f && xn < 1.0f);
+    err |= bad ? ERR_RANGE : 0u;
+    f[d] = bad ? 0.0f : xn;
   }
   return err;
 }

@@ -48,6 +48,16 @@ struct Item {
   int tile, start, end, pad;
 };
 
+// Drifter list of the fused step: particle indices outside their tile window.
+// Two counters alternate between steps; a step clears the next one's.
+constexpr int kDriftBlocks = 256;
+struct Drift {
+  int *list;          // [max_n]
+  int *count;         // this step's counter
+  int *count_next;    // next step's counter
+  int partial_offset; // diagnostics partials of the drifter kernel start here (in blocks)
+};
+
 struct BinBufs {
   int *counts;      // [ntiles]
   int *starts;      // [ntiles + 1]
@@ -81,9 +91,12 @@ void launch_deposit_tiled(hipStream_t st, const Geo &g, const TileGeo &tg, const
                           int max_items, long long *N);
 void launch_step_tiled(hipStream_t st, const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
                        const Store &s, const BinBufs &b, int max_items, const long long *Ncur, long long *Nnext,
-                       long long *Nclear, double *partial, bool diag, uint32_t *err);
-void launch_reduce_diag_dev(hipStream_t st, const double *part_p, const int *nblk_p, const double *part_g,
-                            int nblk_g, pic_diag_t *out, int64_t step);
+                       long long *Nclear, const Drift &dr, double *partial, bool diag, uint32_t *err);
+void launch_drifters(hipStream_t st, const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
+                     const Store &s, const long long *Ncur, long long *Nnext, const Drift &dr, double *partial,
+                     bool diag, uint32_t *err);
+void launch_reduce_diag_dev(hipStream_t st, const double *part_p, const int *nblk_p, const Drift &dr,
+                            const double *part_g, int nblk_g, pic_diag_t *out, int64_t step);
 void launch_fill32(hipStream_t s, int *a, int64_t n);
 
 }  // namespace pic

@@ -25,16 +25,17 @@ namespace pic {
 // Small helpers
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int fold_node(const Geo &g, int d, int a) {
-  // node coordinate -> stored node: periodic wrap, mirror across reflecting walls
-  int n = g.n[d];
+  // node coordinate -> stored node: periodic wrap, mirror across reflecting
+  // walls.  Callers stay within a few cells of the domain, so conditional
+  // wraps replace integer division.
+  const int n = g.n[d];
   if (!g.bc[d]) {
-    a %= n;
-    return a < 0 ? a + n : a;
+    while (a < 0) a += n;
+    while (a >= n) a -= n;
+    return a;
   }
-  int p = 2 * n;
-  a %= p;
-  if (a < 0) a += p;
-  return a > n ? p - a : a;
+  while (a < 0 || a > n) a = a < 0 ? -a : 2 * n - a;
+  return a;
 }
 
 template <int ND>
@@ -60,15 +61,15 @@ __device__ __forceinline__ int tile_of(const TileGeo &tg, const int idx[3]) {
 
 // Window coordinate of cell / node coordinate c along axis d for a window whose
 // first node is at coordinate o: periodic axes pick the representative in
-// [lo, lo + n) so that the tile itself is always inside.
+// [lo, lo + n).  The tiled path only runs when every periodic axis is at least
+// as long as the window, so c - o lies in [lo - n, lo + 2n) and one
+// conditional add or subtract is enough.
 __device__ __forceinline__ int window_coord(const Geo &g, int d, int c, int o, int lo) {
   int l = c - o;
   if (!g.bc[d]) {
-    int n = g.n[d];
-    l -= lo;
-    l %= n;
-    if (l < 0) l += n;
-    l += lo;
+    const int n = g.n[d];
+    l = l < lo ? l + n : l;
+    l = l >= lo + n ? l - n : l;
   }
   return l;
 }
@@ -197,7 +198,9 @@ __global__ void __launch_bounds__(256) k_tile_scatter(Geo g, TileGeo tg, PartPtr
   int t = p < n ? source_tile<ND, IMPORT>(g, tg, cp, s, p, idx, nullptr) : -1;
   int r = wave_rank(cursors, t < 0 ? 0 : t, t >= 0);
   if (t < 0) return;
-  int64_t q = starts[t] + scramble(r, counts[t]);
+  // import scrambles each tile once; later re-binnings keep the (already
+  // scrambled) order of their input runs and write coalesced
+  int64_t q = starts[t] + (IMPORT ? scramble(r, counts[t]) : r);
   if (IMPORT) {
     d.pc[q] = pack_cell<ND>(tg, idx);
 #pragma unroll
@@ -250,41 +253,36 @@ __device__ __forceinline__ int win_centre(const Window &w, int m0, int m1, int m
   return ND == 2 ? m0 + (w.wn[0] - 1) * m1 : m0 + (w.wn[0] - 1) * (m1 + (w.wn[1] - 1) * m2);
 }
 
-// Global (window-free) density and gradient at a particle: 3^ND nodes around
-// the two nearest centres per axis, folded like the window (same bits).
+// Global (window-free) density and gradient at a particle: the node densities
+// around the two nearest centres per axis, folded like the window (so the
+// values are the same bits as the window's).  Only particles that left their
+// tile window since the last binning come here.
 template <int ND>
-__device__ void gather_nodes_global(const Geo &g, const long long *__restrict__ N, const int idx[3],
-                                    const float f[3], float &nh, float Gp[3]) {
+__device__ __forceinline__ void gather_nodes_global(const Geo &g, const long long *__restrict__ N, const int idx[3],
+                                                    const float f[3], float &nh, float Gp[3]) {
+  float cr[8];
+#pragma unroll
+  for (int k = 0; k < (1 << ND); ++k) {
+    int x = fold_node(g, 0, idx[0] + (k & 1)), y = fold_node(g, 1, idx[1] + ((k >> 1) & 1));
+    int z = ND == 3 ? fold_node(g, 2, idx[2] + ((k >> 2) & 1)) : 0;
+    cr[k] = node_density(g, N[node_index<ND>(g, x, y, z)], x, y, z);
+  }
+  nh = interp<ND>(cr, f);
   int c0[3] = {0, 0, 0};
   float t[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int e = 0; e < ND; ++e) centre_stencil(idx[e], f[e], c0[e], t[e]);
-  float D[27];
-#pragma unroll
-  for (int a2 = 0; a2 < (ND == 3 ? 3 : 1); ++a2)
-#pragma unroll
-    for (int a1 = 0; a1 < 3; ++a1)
-#pragma unroll
-      for (int a0 = 0; a0 < 3; ++a0) {
-        int x = fold_node(g, 0, c0[0] + a0), y = fold_node(g, 1, c0[1] + a1);
-        int z = ND == 3 ? fold_node(g, 2, c0[2] + a2) : 0;
-        D[a0 + 3 * (a1 + 3 * a2)] = node_density(g, N[node_index<ND>(g, x, y, z)], x, y, z);
-      }
-  // cell corners: offset of the cell inside the 3^ND block (0 or 1 per axis)
-  int s0 = idx[0] - c0[0], s1 = idx[1] - c0[1], s2 = ND == 3 ? idx[2] - c0[2] : 0;
-  float cr[8];
-#pragma unroll
-  for (int k = 0; k < (1 << ND); ++k)
-    cr[k] = D[(s0 + (k & 1)) + 3 * ((s1 + ((k >> 1) & 1)) + 3 * (ND == 3 ? s2 + ((k >> 2) & 1) : 0))];
-  nh = interp<ND>(cr, f);
   float Gc[8][3];
 #pragma unroll
   for (int m = 0; m < (1 << ND); ++m) {
-    int m0 = m & 1, m1 = (m >> 1) & 1, m2 = ND == 3 ? (m >> 2) & 1 : 0;
     float c[8];
 #pragma unroll
-    for (int k = 0; k < (1 << ND); ++k)
-      c[k] = D[(m0 + (k & 1)) + 3 * ((m1 + ((k >> 1) & 1)) + 3 * (ND == 3 ? m2 + ((k >> 2) & 1) : 0))];
+    for (int k = 0; k < (1 << ND); ++k) {
+      int x = fold_node(g, 0, c0[0] + (m & 1) + (k & 1));
+      int y = fold_node(g, 1, c0[1] + ((m >> 1) & 1) + ((k >> 1) & 1));
+      int z = ND == 3 ? fold_node(g, 2, c0[2] + ((m >> 2) & 1) + ((k >> 2) & 1)) : 0;
+      c[k] = node_density(g, N[node_index<ND>(g, x, y, z)], x, y, z);
+    }
     centre_gradient<ND>(g, c, Gc[m]);
   }
   Gp[2] = 0.0f;
@@ -357,7 +355,7 @@ __device__ __forceinline__ void stage_window(const Geo &g, const Window &w, cons
       c[k] = dens[win_node<ND>(w, m0 + (k & 1), m1 + ((k >> 1) & 1), ND == 3 ? m2 + ((k >> 2) & 1) : 0)];
     centre_gradient<ND>(g, c, G);
 #pragma unroll
-    for (int d = 0; d < ND; ++d) Gs[d * w.nC + m] = G[d];
+    for (int d = 0; d < ND; ++d) Gs[m * ND + d] = G[d];
   }
   __syncthreads();
 }
@@ -398,107 +396,256 @@ __device__ __forceinline__ bool in_window(const Geo &g, const Window &w, const i
   return ok;
 }
 
+constexpr int kMaxChunk = 32768;  // items are at most this many particles (outlier bitmask in LDS)
+
+// Per-array views of the store with 32-bit element offsets (the tiled path
+// keeps max_n < 2^30, so byte offsets fit in 32 bits).
+struct StoreView {
+  int *pc;
+  float *off[3];
+  float *vel[3];
+  const int *wq;
+};
+
+__device__ __forceinline__ StoreView view_of(const Store &s) {
+  StoreView v;
+  v.pc = s.pc;
+  v.wq = s.wq;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    v.off[d] = s.off + d * s.cap;
+    v.vel[d] = s.vel + d * s.cap;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T &at(T *base, int p) {
+  return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (uint32_t)p * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T &at(const T *base, int p) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (uint32_t)p * (uint32_t)sizeof(T));
+}
+
+// One particle's state in registers.
+struct PState {
+  int pc;
+  float f[3];
+  float v[3];
+  int W;
+};
+
+template <int ND, bool DIAG>
+__device__ __forceinline__ void load_state(const StoreView &sv, int p, bool live, PState &q) {
+  q.pc = 0;
+  q.W = 0;
+  q.f[0] = q.f[1] = q.f[2] = 0.0f;
+  q.v[0] = q.v[1] = q.v[2] = 0.0f;
+  if (live) {
+    q.pc = at(sv.pc, p);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      q.f[d] = at(sv.off[d], p);
+      q.v[d] = at(sv.vel[d], p);
+    }
+    if (ND == 2 && DIAG) q.v[2] = at(sv.vel[2], p);
+    q.W = at(sv.wq, p);
+  }
+}
+
+// Force, push, state write-back and the new position's deposit shares of one
+// particle, given its gathered density and gradient.
+template <int ND, bool DIAG, bool INTERIOR>
+__device__ __forceinline__ void advance_particle(const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
+                                                 const StoreView &sv, int p, int pc, int idx[3], float f[3],
+                                                 float v[3], int W, float nh, const float Gp[3], uint32_t tq[8],
+                                                 uint32_t &err, double acc6[6]) {
+  float Fh[3], bond = 0.0f;
+  pair_force<ND>(P, nh, Gp, Fh, DIAG ? &bond : nullptr);
+  float F[3] = {Fh[0] * P.beta, Fh[1] * P.beta, ND == 3 ? Fh[2] * P.beta : 0.0f};
+  if (DIAG) {
+    double wgt = (double)W * dc.wunit, vo2 = 0.0, vn2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      float vn = d < ND ? __builtin_fmaf(F[d], P.gv, v[d]) : v[d];
+      vo2 += (double)v[d] * v[d];
+      vn2 += (double)vn * vn;
+      acc6[1 + d] += wgt * dc.mass * 0.5 * ((double)v[d] + (double)vn);
+    }
+    acc6[0] += wgt * dc.half_m * 0.5 * (vo2 + vn2);
+    acc6[4] += wgt;
+    acc6[5] += wgt * (double)bond * dc.D;
+  }
+  err |= push_particle<ND, INTERIOR>(g, P, F, idx, f, v);
+  const int pc2 = pack_cell<ND>(tg, idx);
+  if (pc2 != pc) at(sv.pc, p) = pc2;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    at(sv.off[d], p) = f[d];
+    at(sv.vel[d], p) = v[d];
+  }
+  deposit_shares<ND>((uint32_t)W, f, tq);
+}
+
+// Wave-aggregated append of the active lanes' values to a global list.
+__device__ __forceinline__ void wave_append(int *list, int *count, int value, bool active) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long m = __ballot(active);
+  if (!m) return;
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(count, __popcll(m));
+  base = __shfl(base, leader, 64);
+  if (active) list[base + __popcll(m & ((1ull << lane) - 1ull))] = value;
+}
+
+// Window coordinates of a cell for the item loop: an interior window never
+// touches the periodic seam, so a plain difference is exact there.
+template <int ND, bool INTERIOR>
+__device__ __forceinline__ bool item_window(const Geo &g, const Window &w, const int idx[3], int lo, int hi_off,
+                                            int l[3]) {
+  if (!INTERIOR) return in_window<ND>(g, w, idx, lo, hi_off, l);
+  bool ok = true;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    l[d] = idx[d] - w.o[d];
+    ok = ok && l[d] >= lo && l[d] <= w.wn[d] - hi_off;
+  }
+  return ok;
+}
+
+// The particles of one item whose cells lie in the tile window (drifters are
+// appended to the global list).  Loads for the next round are issued before
+// the current round is computed.
+template <int ND, bool DIAG, bool INTERIOR>
+__device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
+                                         const StoreView &sv, const Item &it, const Window &w, const float *dens,
+                                         const float *Gs, unsigned long long *acc,
+                                         unsigned long long *__restrict__ Nnext, int *__restrict__ olist,
+                                         int *__restrict__ ocount, uint32_t &e_all, double acc6[6]) {
+  PState cur, nxt;
+  int p = it.start + (int)threadIdx.x;
+  load_state<ND, DIAG>(sv, p, p < it.end, cur);
+  for (int base = it.start; base < it.end; base += blockDim.x) {
+    const int pn = p + (int)blockDim.x;
+    load_state<ND, DIAG>(sv, pn, pn < it.end, nxt);
+    const bool live = p < it.end;
+    int idx[3], l[3];
+    unpack_cell<ND>(tg, cur.pc, idx);
+    const bool inside = live && item_window<ND, INTERIOR>(g, w, idx, 1, 3, l);
+    wave_append(olist, ocount, p, live && !inside);
+    if (inside) {
+      float cr[8];
+#pragma unroll
+      for (int k = 0; k < (1 << ND); ++k)
+        cr[k] = dens[win_node<ND>(w, l[0] + (k & 1), l[1] + ((k >> 1) & 1), ND == 3 ? l[2] + ((k >> 2) & 1) : 0)];
+      const float nh = interp<ND>(cr, cur.f);
+      int c0[3] = {0, 0, 0};
+      float t[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int e = 0; e < ND; ++e) centre_stencil(l[e], cur.f[e], c0[e], t[e]);
+      float Gp[3] = {0.f, 0.f, 0.f};
+      float vv[3][8];
+#pragma unroll
+      for (int k = 0; k < (1 << ND); ++k) {
+        const int m =
+            win_centre<ND>(w, c0[0] + (k & 1), c0[1] + ((k >> 1) & 1), ND == 3 ? c0[2] + ((k >> 2) & 1) : 0);
+        if (ND == 2) {
+          const float2 gg = *reinterpret_cast<const float2 *>(&Gs[2 * m]);
+          vv[0][k] = gg.x;
+          vv[1][k] = gg.y;
+        } else {
+#pragma unroll
+          for (int d = 0; d < ND; ++d) vv[d][k] = Gs[m * ND + d];
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < ND; ++d) Gp[d] = interp<ND>(vv[d], t);
+      uint32_t tq[8];
+      advance_particle<ND, DIAG, INTERIOR>(g, P, dc, tg, sv, p, cur.pc, idx, cur.f, cur.v, cur.W, nh, Gp, tq,
+                                           e_all, acc6);
+      // a sub-cell move keeps the new cell inside the deposit window
+      if (item_window<ND, INTERIOR>(g, w, idx, 0, 2, l)) {
+#pragma unroll
+        for (int k = 0; k < (1 << ND); ++k)
+          if (tq[k])
+            atomicAdd(&acc[win_node<ND>(w, l[0] + (k & 1), l[1] + ((k >> 1) & 1),
+                                        ND == 3 ? l[2] + ((k >> 2) & 1) : 0)],
+                      (unsigned long long)tq[k]);
+      } else {
+        deposit_global<ND>(g, Nnext, idx, tq);
+      }
+    }
+    cur = nxt;
+    p = pn;
+  }
+}
+
 template <int ND, bool DIAG>
 __global__ void __launch_bounds__(256) k_step_tiled(Geo g, Pot P, DiagC dc, TileGeo tg, Store s,
                                                     const Item *__restrict__ items,
                                                     const int *__restrict__ num_items,
                                                     const long long *__restrict__ Ncur,
                                                     unsigned long long *__restrict__ Nnext,
-                                                    long long *__restrict__ Nclear, double *__restrict__ partial,
-                                                    uint32_t *__restrict__ err) {
+                                                    long long *__restrict__ Nclear, int *__restrict__ olist,
+                                                    int *__restrict__ ocount, int *__restrict__ ocount_next,
+                                                    double *__restrict__ partial, uint32_t *__restrict__ err) {
   extern __shared__ __align__(16) unsigned char smem[];
   clear_share(Nclear, g.nnodes);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ocount_next = 0;  // next step's drifter count
   if ((int)blockIdx.x >= *num_items) return;
   const Item it = items[blockIdx.x];
   const Window w = make_window<ND>(tg, it.tile);
   unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
   float *dens = reinterpret_cast<float *>(acc + w.nW);
   float *Gs = dens + w.nW;
-  stage_window<ND>(g, w, Ncur, dens, Gs, acc);
+  stage_window<ND>(g, w, Ncur, dens, Gs, acc);  // ends with a barrier
 
-  double a_ke = 0.0, a_px = 0.0, a_py = 0.0, a_pz = 0.0, a_w = 0.0, a_b = 0.0;
+  // interior windows: no wall and no periodic seam within reach of any
+  // particle the item loop handles
+  bool interior = true;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) interior = interior && w.o[d] >= 0 && w.o[d] + w.wn[d] <= g.n[d] + 1;
+  double acc6[6] = {0, 0, 0, 0, 0, 0};
   uint32_t e_all = 0;
-  const int64_t cap = s.cap;
-  for (int p = it.start + threadIdx.x; p < it.end; p += blockDim.x) {
-    const int pc = s.pc[p];
-    float f[3] = {s.off[p], s.off[cap + p], ND == 3 ? s.off[2 * cap + p] : 0.0f};
-    float v[3] = {s.vel[p], s.vel[cap + p], (ND == 3 || DIAG) ? s.vel[2 * cap + p] : 0.0f};
-    const int W = s.wq[p];
-    int idx[3];
-    unpack_cell<ND>(tg, pc, idx);
-    // gather
-    float nh, Gp[3];
-    int l[3];
-    if (in_window<ND>(g, w, idx, 1, 3, l)) {
-      float cr[8];
-#pragma unroll
-      for (int k = 0; k < (1 << ND); ++k)
-        cr[k] = dens[win_node<ND>(w, l[0] + (k & 1), l[1] + ((k >> 1) & 1), ND == 3 ? l[2] + ((k >> 2) & 1) : 0)];
-      nh = interp<ND>(cr, f);
-      int c0[3] = {0, 0, 0};
-      float t[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-      for (int e = 0; e < ND; ++e) centre_stencil(l[e], f[e], c0[e], t[e]);
-      Gp[2] = 0.0f;
-#pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        float vv[8];
-#pragma unroll
-        for (int k = 0; k < (1 << ND); ++k)
-          vv[k] = Gs[d * w.nC + win_centre<ND>(w, c0[0] + (k & 1), c0[1] + ((k >> 1) & 1),
-                                               ND == 3 ? c0[2] + ((k >> 2) & 1) : 0)];
-        Gp[d] = interp<ND>(vv, t);
-      }
-    } else {
-      gather_nodes_global<ND>(g, Ncur, idx, f, nh, Gp);
-    }
-    float Fh[3], bond = 0.0f;
-    pair_force<ND>(P, nh, Gp, Fh, DIAG ? &bond : nullptr);
-    float F[3] = {Fh[0] * P.beta, Fh[1] * P.beta, ND == 3 ? Fh[2] * P.beta : 0.0f};
-    if (DIAG) {
-      double wgt = (double)W * dc.wunit, vo2 = 0.0, vn2 = 0.0, pm[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        float vn = d < ND ? __builtin_fmaf(F[d], P.gv, v[d]) : v[d];
-        vo2 += (double)v[d] * v[d];
-        vn2 += (double)vn * vn;
-        pm[d] = wgt * dc.mass * 0.5 * ((double)v[d] + (double)vn);
-      }
-      a_ke += wgt * dc.half_m * 0.5 * (vo2 + vn2);
-      a_px += pm[0];
-      a_py += pm[1];
-      a_pz += pm[2];
-      a_w += wgt;
-      a_b += wgt * (double)bond * dc.D;
-    }
-    e_all |= push_particle<ND>(g, P, F, idx, f, v);
-    const int pc2 = pack_cell<ND>(tg, idx);
-    if (pc2 != pc) s.pc[p] = pc2;
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-      s.off[d * cap + p] = f[d];
-      s.vel[d * cap + p] = v[d];
-    }
-    // deposit the new position into the next step's node sums
-    uint32_t tq[8];
-    deposit_shares<ND>((uint32_t)W, f, tq);
-    if (in_window<ND>(g, w, idx, 0, 2, l)) {
-#pragma unroll
-      for (int k = 0; k < (1 << ND); ++k)
-        if (tq[k])
-          atomicAdd(&acc[win_node<ND>(w, l[0] + (k & 1), l[1] + ((k >> 1) & 1), ND == 3 ? l[2] + ((k >> 2) & 1) : 0)],
-                    (unsigned long long)tq[k]);
-    } else {
-      deposit_global<ND>(g, Nnext, idx, tq);
-    }
-  }
+  const StoreView sv = view_of(s);
+  if (interior)
+    run_item<ND, DIAG, true>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nnext, olist, ocount, e_all, acc6);
+  else
+    run_item<ND, DIAG, false>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nnext, olist, ocount, e_all, acc6);
   if (e_all) atomicOr(err, e_all);
   __syncthreads();
   flush_window<ND>(g, w, acc, Nnext);
-  if (DIAG) {
-    double v6[6] = {a_ke, a_px, a_py, a_pz, a_w, a_b};
-    block_reduce_store<6>(v6, partial + (int64_t)blockIdx.x * 8);
+  if (DIAG) block_reduce_store<6>(acc6, partial + (int64_t)blockIdx.x * 8);
+}
+
+// Drifters (particles outside their tile window since the last binning):
+// the same cycle through the global node sums.
+template <int ND, bool DIAG>
+__global__ void __launch_bounds__(256) k_outliers(Geo g, Pot P, DiagC dc, TileGeo tg, Store s,
+                                                  const int *__restrict__ olist, const int *__restrict__ ocount,
+                                                  const long long *__restrict__ Ncur,
+                                                  unsigned long long *__restrict__ Nnext,
+                                                  double *__restrict__ partial, uint32_t *__restrict__ err) {
+  const int n = *ocount;
+  double acc6[6] = {0, 0, 0, 0, 0, 0};
+  uint32_t e_all = 0;
+  const StoreView sv = view_of(s);
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const int p = olist[k];
+    PState q;
+    load_state<ND, DIAG>(sv, p, true, q);
+    int idx[3];
+    unpack_cell<ND>(tg, q.pc, idx);
+    float nh, Gp[3];
+    gather_nodes_global<ND>(g, Ncur, idx, q.f, nh, Gp);
+    uint32_t tq[8];
+    advance_particle<ND, DIAG, false>(g, P, dc, tg, sv, p, q.pc, idx, q.f, q.v, q.W, nh, Gp, tq, e_all, acc6);
+    deposit_global<ND>(g, Nnext, idx, tq);
   }
+  if (e_all) atomicOr(err, e_all);
+  if (DIAG) block_reduce_store<6>(acc6, partial + (int64_t)blockIdx.x * 8);
 }
 
 // Deposit only (the node sums of the current positions), same tiling.
@@ -536,6 +683,7 @@ __global__ void __launch_bounds__(256) k_deposit_tiled(Geo g, TileGeo tg, Store 
 
 __global__ void __launch_bounds__(256) k_reduce_diag_dev(const double *__restrict__ part_p,
                                                          const int *__restrict__ nblk_p_dev,
+                                                         const double *__restrict__ part_o, int nblk_o,
                                                          const double *__restrict__ part_g, int nblk_g,
                                                          pic_diag_t *__restrict__ out, int64_t step) {
   const int nblk_p = *nblk_p_dev;
@@ -543,6 +691,9 @@ __global__ void __launch_bounds__(256) k_reduce_diag_dev(const double *__restric
   for (int b = threadIdx.x; b < nblk_p; b += blockDim.x)
 #pragma unroll
     for (int i = 0; i < 6; ++i) acc[i] += part_p[(int64_t)b * 8 + i];
+  for (int b = threadIdx.x; b < nblk_o; b += blockDim.x)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc[i] += part_o[(int64_t)b * 8 + i];
   for (int b = threadIdx.x; b < nblk_g; b += blockDim.x) acc[6] += part_g[(int64_t)b * 8];
   __shared__ double res[8];
   block_reduce_store<7>(acc, res);
@@ -626,30 +777,40 @@ void launch_deposit_tiled(hipStream_t st, const Geo &g, const TileGeo &tg, const
 
 void launch_step_tiled(hipStream_t st, const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
                        const Store &s, const BinBufs &b, int max_items, const long long *Ncur, long long *Nnext,
-                       long long *Nclear, double *partial, bool diag, uint32_t *err) {
+                       long long *Nclear, const Drift &dr, double *partial, bool diag, uint32_t *err) {
   if (max_items <= 0) return;
   size_t lds = window_lds_bytes(tg, g.ndim);
   unsigned long long *nn = (unsigned long long *)Nnext;
+#define PIC_STEP_LAUNCH(ND_, DIAG_)                                                                              \
+  k_step_tiled<ND_, DIAG_><<<max_items, 256, lds, st>>>(g, P, dc, tg, s, b.items, b.num_items, Ncur, nn, Nclear, \
+                                                         dr.list, dr.count, dr.count_next, partial, err)
   if (g.ndim == 2) {
-    if (diag)
-      k_step_tiled<2, true><<<max_items, 256, lds, st>>>(g, P, dc, tg, s, b.items, b.num_items, Ncur, nn, Nclear,
-                                                         partial, err);
-    else
-      k_step_tiled<2, false><<<max_items, 256, lds, st>>>(g, P, dc, tg, s, b.items, b.num_items, Ncur, nn, Nclear,
-                                                          partial, err);
+    if (diag) { PIC_STEP_LAUNCH(2, true); } else { PIC_STEP_LAUNCH(2, false); }
   } else {
-    if (diag)
-      k_step_tiled<3, true><<<max_items, 256, lds, st>>>(g, P, dc, tg, s, b.items, b.num_items, Ncur, nn, Nclear,
-                                                         partial, err);
-    else
-      k_step_tiled<3, false><<<max_items, 256, lds, st>>>(g, P, dc, tg, s, b.items, b.num_items, Ncur, nn, Nclear,
-                                                          partial, err);
+    if (diag) { PIC_STEP_LAUNCH(3, true); } else { PIC_STEP_LAUNCH(3, false); }
   }
+#undef PIC_STEP_LAUNCH
 }
 
-void launch_reduce_diag_dev(hipStream_t st, const double *part_p, const int *nblk_p, const double *part_g,
-                            int nblk_g, pic_diag_t *out, int64_t step) {
-  k_reduce_diag_dev<<<1, 256, 0, st>>>(part_p, nblk_p, part_g, nblk_g, out, step);
+void launch_drifters(hipStream_t st, const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
+                     const Store &s, const long long *Ncur, long long *Nnext, const Drift &dr, double *partial,
+                     bool diag, uint32_t *err) {
+  unsigned long long *nn = (unsigned long long *)Nnext;
+  double *part_o = partial + (int64_t)dr.partial_offset * 8;
+#define PIC_DRIFT_LAUNCH(ND_, DIAG_) \
+  k_outliers<ND_, DIAG_><<<kDriftBlocks, 256, 0, st>>>(g, P, dc, tg, s, dr.list, dr.count, Ncur, nn, part_o, err)
+  if (g.ndim == 2) {
+    if (diag) { PIC_DRIFT_LAUNCH(2, true); } else { PIC_DRIFT_LAUNCH(2, false); }
+  } else {
+    if (diag) { PIC_DRIFT_LAUNCH(3, true); } else { PIC_DRIFT_LAUNCH(3, false); }
+  }
+#undef PIC_DRIFT_LAUNCH
+}
+
+void launch_reduce_diag_dev(hipStream_t st, const double *part_p, const int *nblk_p, const Drift &dr,
+                            const double *part_g, int nblk_g, pic_diag_t *out, int64_t step) {
+  k_reduce_diag_dev<<<1, 256, 0, st>>>(part_p, nblk_p, part_p + (int64_t)dr.partial_offset * 8, kDriftBlocks,
+                                       part_g, nblk_g, out, step);
 }
 
 }  // namespace pic
