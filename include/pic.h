@@ -171,7 +171,11 @@ int pic_step(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, pic_diag_t *dia
  *   halo        cells a particle may drift out of its tile between binnings
  *               before it takes the slower global path (1..4);
  *   chunk       most particles per work item (1024..32768);
- *   sort_every  re-bin particles by tile every this many steps (0 = never).
+ *   sort_every  re-bin particles by tile every this many steps; 0 = never;
+ *               -1 = adaptive (default): every 32 steps the drifter count of
+ *               the previous check is read back without stalling, and the
+ *               particles are re-binned once more than n/2048 have drifted
+ *               out of their tile window, or after 1024 steps.
  * Grids with more than 65536 x 32768 (2D) or 2048 x 2048 x 512 (3D) cells,
  * or max_n >= 2^30, use the untiled kernels and reject this call.  A tiling
  * whose window (tile + 2 halo + 3 nodes) is longer than a periodic axis is

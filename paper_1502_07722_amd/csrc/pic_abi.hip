@@ -64,6 +64,9 @@ int64_t max_items_for(const pic_grid_t *g, int lt, int64_t max_n, int chunk) {
 }
 
 constexpr int kMinChunk = 1024;
+constexpr int kDriftCheck = 32;      // adaptive re-binning looks at the drifter count this often
+constexpr int kDriftFraction = 2048; // and re-bins once drifters exceed n / kDriftFraction
+constexpr int kMaxBinPeriod = 1024;  // or after this many steps
 constexpr int kMaxChunkHost = 32768;  // the fused kernel keeps a per-item outlier bitmask in LDS
 
 struct Layout {
@@ -130,7 +133,10 @@ struct pic_ctx {
   long long *n3[3]{};
   int *drift = nullptr;  // [2 counters][max_n list]
   int64_t tiles_cap = 0, items_cap = 0;
-  int sort_every = 0;
+  int sort_every = 0;           // > 0 fixed period, 0 never, < 0 adaptive
+  int *h_drift = nullptr;       // pinned host copy of a drifter count (adaptive re-binning)
+  hipEvent_t drift_ev = nullptr;
+  bool drift_pending = false;
   bool force_untiled = false;
   long long *last_nodes = nullptr;
   int last_step = 0;
@@ -241,7 +247,7 @@ static int apply_tiling(pic_ctx_t *c, int lt, int halo, int chunk, int sort_ever
   if (lt < min_tile_log2(nd) || lt > max_tile_log2(nd)) return fail(c, PIC_EINVAL, "tile edge out of range");
   if (halo < 1 || halo > 4) return fail(c, PIC_EINVAL, "halo must be 1..4 cells");
   if (chunk < kMinChunk || chunk > kMaxChunkHost) return fail(c, PIC_EINVAL, "chunk out of range");
-  if (sort_every < 0) return fail(c, PIC_EINVAL, "sort_every must be >= 0");
+  if (sort_every < -1) return fail(c, PIC_EINVAL, "sort_every must be >= -1");
   TileGeo &T = c->tg;
   T.ntiles = 1;
   for (int d = 0; d < 3; ++d) {
@@ -385,13 +391,18 @@ int pic_init(pic_ctx_t **out, const pic_grid_t *grid, const pic_potential_t *pot
     // default tiling; smaller tiles for small periodic grids; untiled if none fits
     int rc = PIC_EINVAL;
     if (g.ndim == 2) {
-      for (int lt = 4; lt >= 3 && rc; --lt) rc = apply_tiling(c, lt, 2, 8192, 32);
-      if (rc) rc = apply_tiling(c, 3, 1, 8192, 32);
+      for (int lt = 4; lt >= 3 && rc; --lt) rc = apply_tiling(c, lt, 2, 8192, -1);
+      if (rc) rc = apply_tiling(c, 3, 1, 8192, -1);
     } else {
-      for (int lt = 3; lt >= 2 && rc; --lt) rc = apply_tiling(c, lt, 1, 4096, 16);
+      for (int lt = 3; lt >= 2 && rc; --lt) rc = apply_tiling(c, lt, 1, 4096, -1);
     }
     if (rc) c->tiled = false;
     c->last_error.clear();
+    if (c->tiled && (hipHostMalloc((void **)&c->h_drift, 16, hipHostMallocDefault) != hipSuccess ||
+                     hipEventCreateWithFlags(&c->drift_ev, hipEventDisableTiming) != hipSuccess)) {
+      c->h_drift = nullptr;
+      c->tiled = false;
+    }
   }
   *out = c;
   return PIC_OK;
@@ -408,6 +419,9 @@ int pic_set_tiling(pic_ctx_t *ctx, int32_t tile, int32_t halo, int32_t chunk, in
 
 int pic_destroy(pic_ctx_t *ctx) {
   if (!ctx) return PIC_OK;
+  if (ctx->drift_ev) (void)hipEventSynchronize(ctx->drift_ev);
+  if (ctx->drift_ev) (void)hipEventDestroy(ctx->drift_ev);
+  if (ctx->h_drift) (void)hipHostFree(ctx->h_drift);
   harvest_events(ctx);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
@@ -583,11 +597,30 @@ int step_tiled(pic_ctx_t *ctx, const PartPtrs &pp, int32_t nsteps, DiagSink &ds,
     PhaseTimer t(ctx, 0);
     launch_deposit_tiled(ctx->stream, g, ctx->tg, ctx->st[cur], ctx->bb, (int)max_items, ctx->n3[0]);
   }
+  int since_bin = 0;
+  ctx->drift_pending = false;
   for (int32_t s = 0; s < nsteps; ++s) {
-    if (s > 0 && ctx->sort_every > 0 && s % ctx->sort_every == 0) {
+    bool rebin = false;
+    if (ctx->sort_every > 0) {
+      rebin = s > 0 && s % ctx->sort_every == 0;
+    } else if (ctx->sort_every < 0 && s > 0 && s % kDriftCheck == 0) {
+      // adaptive: look at the drifter count copied kDriftCheck steps ago (long
+      // finished, so the host does not stall), then post a copy of this one
+      if (ctx->drift_pending) {
+        (void)hipEventSynchronize(ctx->drift_ev);
+        rebin = (int64_t)ctx->h_drift[0] * kDriftFraction > n || since_bin >= kMaxBinPeriod;
+      }
+      const int last = (s - 1) & 1;  // counter of the previous step
+      (void)hipMemcpyAsync(ctx->h_drift, ctx->drift + last, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+      (void)hipEventRecord(ctx->drift_ev, ctx->stream);
+      ctx->drift_pending = true;
+    }
+    ++since_bin;
+    if (rebin) {
       PhaseTimer t(ctx, 3);
       launch_bin(ctx->stream, g, ctx->tg, pp, ctx->st[cur], ctx->st[1 - cur], n, ctx->bb, false, ctx->err);
       cur = 1 - cur;
+      since_bin = 0;
     }
     const bool want = ds.host && (s % diag_every) == 0;
     long long *Nc = ctx->n3[s % 3], *Nn = ctx->n3[(s + 1) % 3], *Nz = ctx->n3[(s + 2) % 3];
