@@ -25,7 +25,7 @@ HBM_PEAK_GBS = 8000.0
 # 4*ndim + velocity 12 + weight 4, writes cell 4 + offsets 4*ndim + velocity
 # 12: 52 B in 2D, 60 B in 3D -- plus 16 B per node (int64 sums written once
 # and read once).
-DEFAULTS = {"large": (2000, 20), "heated": (5000, 20), "small": (200, 20)}
+DEFAULTS = {"large": (2000, 20), "heated": (5000, 20), "small": (200, 20), "sweep": (1000, 12)}
 
 
 def log(msg):
@@ -64,12 +64,80 @@ def cpu_baseline(wl, pot, seconds_hint=10.0):
                       f"({nsample} particles), {steps} FP64 steps, single thread"}
 
 
+def run_sweep(steps, warmup, log_fn=log):
+    """The intensity sweep: 24 slabs of uneven size (0.2-5 J/cm^2).  Plain: a
+    loop over the slabs, one context each, per-step launches, default tiles,
+    no graph.  Batched: one context over all slabs, autotuned tiles, graph
+    replay on a created stream.  Both start from the same state; their final
+    states must be bit-identical."""
+    import torch
+    from paper_1502_07722_amd import binding as B
+    from paper_1502_07722_amd import workloads as W
+
+    t0 = time.perf_counter()
+    wls = W.cfg_sweep()
+    N = sum(w.parts.n for w in wls)
+    log_fn(f"sweep: {len(wls)} slabs, {N} particles, generated in {time.perf_counter() - t0:.1f} s")
+    c_att, _ = B.pic_calibrate_catt(wls[0].grid, wls[0].pot, W.N_SOLID, 8)
+    pot = W.Potential(c_att=c_att)
+    dt = wls[0].dt
+    # starting states: v(-1/2) from each slab's own force
+    starts = []
+    for w in wls:
+        ctx = B.Context(w.grid, pot, dt, w.parts.n)
+        dp = B.DeviceParticles.from_host(w.parts)
+        ctx.start_leapfrog(dp)
+        starts.append(dp)
+        del ctx
+    torch.cuda.synchronize()
+    # plain loop
+    plain_ctx = [B.Context(w.grid, pot, dt, w.parts.n) for w in wls]
+    plain = [s.clone() for s in starts]
+    for c, p in zip(plain_ctx, plain):
+        c.pic_step(p, warmup)
+    plain = [s.clone() for s in starts]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, p in zip(plain_ctx, plain):
+        c.pic_step(p, steps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    del plain_ctx
+    log_fn(f"plain loop: {steps} steps x {len(wls)} slabs in {t_plain:.3f} s")
+    # batched
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        bctx = B.BatchContext([w.grid for w in wls], pot, dt, [w.parts.n for w in wls], stream=stream)
+        tuning = bctx.pic_autotune(starts, 6)
+        log_fn(f"autotuned tiling {tuning}")
+        batch = [s.clone() for s in starts]
+        bctx.pic_step_batch(batch, warmup)
+        batch = [s.clone() for s in starts]
+        stream.synchronize()
+        t0 = time.perf_counter()
+        bctx.pic_step_batch(batch, steps)
+        stream.synchronize()
+        t_batch = time.perf_counter() - t0
+    log_fn(f"batched: {steps} steps in {t_batch:.3f} s")
+    same = all(torch.equal(a.cell, b.cell) and torch.equal(a.off, b.off) and torch.equal(a.vel, b.vel)
+               for a, b in zip(plain, batch))
+    return {"workload": f"sweep of {len(wls)} slabs, widths 256-2048, depths 128-512 rows, 16-32 ppc, "
+                        f"0.2-5 J/cm^2, {steps} steps",
+            "particles": N, "steps": steps,
+            "plain_particle_steps_per_s": N * steps / t_plain,
+            "batched_particle_steps_per_s": N * steps / t_batch,
+            "speedup": t_plain / t_batch, "bit_identical": bool(same), "tuning": tuning,
+            "slab_particles": [w.parts.n for w in wls]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="large", choices=["large", "heated", "small"])
+    ap.add_argument("--workload", default="large", choices=["large", "heated", "small", "sweep"])
+    ap.add_argument("--with-sweep", action="store_true",
+                    help="also run the batched intensity sweep (plain loop vs batched) into the same line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration for rocprofv3 --pmc)")
@@ -85,6 +153,16 @@ def main():
     import torch
     from paper_1502_07722_amd import binding as B
     from paper_1502_07722_amd import workloads as W
+
+    if args.workload == "sweep":
+        res = run_sweep(steps, warmup)
+        out = {"metric": "particle-steps/s (deposit+force+push), batched intensity sweep",
+               "value": res["batched_particle_steps_per_s"], "unit": "particle-steps/s", "n_gpus": 1,
+               "steps": steps, "warmup": warmup, "ms_per_step": None, "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": res["workload"]}, "sweep": res}
+        print(json.dumps(out), flush=True)
+        return
 
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
@@ -154,6 +232,10 @@ def main():
         "energy_check": {"E_first": diags[0]["ke"] + diags[0]["pe"], "E_last": diags[-1]["ke"] + diags[-1]["pe"]}
         if diags else None,
     }
+    del ctx, dp
+    torch.cuda.empty_cache()
+    if args.with_sweep:
+        out["sweep"] = run_sweep(*DEFAULTS["sweep"])
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, pot)

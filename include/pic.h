@@ -172,7 +172,7 @@ int pic_step(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, pic_diag_t *dia
  *               before it takes the slower global path (1..4);
  *   chunk       most particles per work item (1024..32768);
  *   sort_every  re-bin particles by tile every this many steps; 0 = never;
- *               -1 = adaptive (default): every 32 steps the drifter count of
+ *               -1 = adaptive (default): every 48 steps the drifter count of
  *               the previous check is read back without stalling, and the
  *               particles are re-binned once more than n/2048 have drifted
  *               out of their tile window, or after 1024 steps.
@@ -187,7 +187,8 @@ int pic_set_tiling(pic_ctx_t *ctx, int32_t tile, int32_t halo, int32_t chunk, in
 int pic_set_path(pic_ctx_t *ctx, int32_t untiled);
 
 /* Copy the node sums of the final positions of the last tiled pic_step (as
- * its fused kernel deposited them) into node_w[pic_num_nodes]. */
+ * its fused kernel deposited them) into node_w (pic_num_nodes entries; for a
+ * batch, every slab's nodes one after another). */
 int pic_step_nodes(pic_ctx_t *ctx, int64_t *node_w);
 
 /* Per-phase device time of pic_step, measured with HIP events recorded on
@@ -196,7 +197,9 @@ int pic_step_nodes(pic_ctx_t *ctx, int64_t *node_w);
  * grid pass, 2 gather+force+push (the dominant kernel: in the tiled step the
  * fused kernel), 3 re-binning by tile, 4 diagnostics reductions, 5 import of
  * the caller's arrays into the binned store and export back, 6 the tiled
- * step's drifter kernel (particles outside their tile window). */
+ * step's drifter kernel (particles outside their tile window), 7 graph
+ * replays (blocks of 6 steps; graphs are not used while timing is on, so
+ * the per-kernel phases above are measured launch by launch). */
 #define PIC_NPHASES 8
 typedef struct pic_timing {
   double ms[PIC_NPHASES];        /* summed kernel time per phase, ms */
@@ -212,6 +215,51 @@ int pic_set_timing(pic_ctx_t *ctx, int32_t on);
 
 /* Accumulated per-phase times since timing was turned on (synchronises). */
 int pic_get_timing(pic_ctx_t *ctx, pic_timing_t *out);
+
+/* ---------------------------------------------------------------------------
+ * Batches: several independent slabs (e.g. one per absorbed fluence of a
+ * damage-threshold sweep) advanced together.  Every step of every slab is one
+ * persistent launch of the fused kernel (plus the drifter kernel); steady
+ * stretches of steps are replayed from a captured HIP graph.  Each slab's
+ * result is bit-identical to advancing it alone.
+ * ------------------------------------------------------------------------- */
+
+/* Workspace bytes for nslab grids (all 2D or all 3D) holding at most max_n[k]
+ * particles each; 0 if a grid is invalid or the batch cannot be tiled. */
+size_t pic_workspace_bytes_batch(const pic_grid_t *grids, int32_t nslab, const int64_t *max_n);
+
+/* Create a context over nslab slabs sharing one potential and time step.  A
+ * batched context supports pic_step_batch, tiling, graph and timing calls;
+ * the single-slab calls (pic_deposit, pic_force, pic_kick, pic_push,
+ * pic_step) return PIC_EINVAL on it. */
+int pic_init_batch(pic_ctx_t **out, const pic_grid_t *grids, int32_t nslab, const pic_potential_t *pot,
+                   double dt, const int64_t *max_n, void *ws, size_t ws_bytes, void *stream);
+
+/* nsteps cycles of every slab; parts[k] are slab k's arrays (order kept).
+ * diag (optional, host) is [nslab][ceil(nsteps / diag_every)].  Synchronises
+ * and reports device errors like pic_step. */
+int pic_step_batch(pic_ctx_t *ctx, pic_particles_t *parts, int32_t nsteps, pic_diag_t *diag,
+                   int32_t diag_every);
+
+/* Current tiling (any output pointer may be NULL). */
+int pic_get_tiling(pic_ctx_t *ctx, int32_t *tile, int32_t *halo, int32_t *chunk, int32_t *sort_every);
+
+/* 1 (default): replay blocks of 6 plain steps (no diagnostics, no re-binning
+ * decision) from captured HIP graphs; 0: launch every step.  Graphs are only
+ * captured on a context bound to a created stream (never the NULL stream). */
+int pic_set_graph(pic_ctx_t *ctx, int32_t on);
+
+/* Autotuner: probes tile edge x chunk candidates (halo 2 in 2D, 1 in 3D;
+ * re-binning policy unchanged) on the caller's particles for probe_steps
+ * steps each, timed with events, and keeps the fastest tiling.  The
+ * particles are copied into the internal store for every probe: the caller's
+ * arrays are only read.  Results never depend on the tiling. */
+typedef struct pic_tuning {
+  int32_t tile, halo, chunk;
+  int32_t candidates;   /* tilings that were timed */
+  double ms_per_step;   /* best probe, ms per step */
+} pic_tuning_t;
+int pic_autotune(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t probe_steps, pic_tuning_t *out);
 
 /* Host-side calibration of the attractive correction factor: a flat slab of
  * density n_solid (slab_layers cells thick) in a grid with this grid's cell

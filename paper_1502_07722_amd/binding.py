@@ -42,7 +42,12 @@ class pic_diag_t(C.Structure):
 
 
 DIAG_FIELDS = ("ke", "pe", "px", "py", "pz", "wsum", "bond", "step")
-PHASES = ("deposit", "grid", "force_push", "sort", "diag", "import_export", "drifters", "p7")
+PHASES = ("deposit", "grid", "force_push", "sort", "diag", "import_export", "drifters", "graph")
+
+
+class pic_tuning_t(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("halo", C.c_int32), ("chunk", C.c_int32), ("candidates", C.c_int32),
+                ("ms_per_step", C.c_double)]
 
 
 class pic_timing_t(C.Structure):
@@ -71,6 +76,14 @@ lib.pic_push.argtypes = [_vp, _P(pic_particles_t), _vp]
 lib.pic_step.argtypes = [_vp, _P(pic_particles_t), C.c_int32, _P(pic_diag_t), C.c_int32]
 lib.pic_set_timing.argtypes = [_vp, C.c_int32]
 lib.pic_set_tiling.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+lib.pic_get_tiling.argtypes = [_vp, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32), _P(C.c_int32)]
+lib.pic_set_graph.argtypes = [_vp, C.c_int32]
+lib.pic_autotune.argtypes = [_vp, _P(pic_particles_t), C.c_int32, _P(pic_tuning_t)]
+lib.pic_workspace_bytes_batch.restype = C.c_size_t
+lib.pic_workspace_bytes_batch.argtypes = [_P(pic_grid_t), C.c_int32, _P(C.c_int64)]
+lib.pic_init_batch.argtypes = [_P(_vp), _P(pic_grid_t), C.c_int32, _P(pic_potential_t), C.c_double, _P(C.c_int64),
+                               _vp, C.c_size_t, _vp]
+lib.pic_step_batch.argtypes = [_vp, _P(pic_particles_t), C.c_int32, _P(pic_diag_t), C.c_int32]
 lib.pic_set_path.argtypes = [_vp, C.c_int32]
 lib.pic_step_nodes.argtypes = [_vp, _vp]
 lib.pic_get_timing.argtypes = [_vp, _P(pic_timing_t)]
@@ -240,6 +253,23 @@ class Context:
     def pic_set_tiling(self, tile: int, halo: int, chunk: int, sort_every: int):
         self._check(lib.pic_set_tiling(self.ctx, tile, halo, chunk, sort_every), "pic_set_tiling")
 
+    def pic_get_tiling(self):
+        v = [C.c_int32() for _ in range(4)]
+        self._check(lib.pic_get_tiling(self.ctx, *[C.byref(x) for x in v]), "pic_get_tiling")
+        return tuple(x.value for x in v)
+
+    def pic_autotune(self, parts, probe_steps: int = 10):
+        """parts: one DeviceParticles (single slab) or a list (batch)."""
+        plist = parts if isinstance(parts, (list, tuple)) else [parts]
+        arr = (pic_particles_t * len(plist))(*[p.struct() for p in plist])
+        t = pic_tuning_t()
+        self._check(lib.pic_autotune(self.ctx, arr, int(probe_steps), C.byref(t)), "pic_autotune")
+        return {"tile": t.tile, "halo": t.halo, "chunk": t.chunk, "candidates": t.candidates,
+                "ms_per_step": t.ms_per_step}
+
+    def pic_set_graph(self, on: bool):
+        self._check(lib.pic_set_graph(self.ctx, 1 if on else 0), "pic_set_graph")
+
     def pic_set_path(self, untiled: bool):
         self._check(lib.pic_set_path(self.ctx, 1 if untiled else 0), "pic_set_path")
 
@@ -267,3 +297,44 @@ class Context:
         F = self.pic_force(parts, node)
         self.pic_kick(parts, F, -0.5)
         return F
+
+
+class BatchContext(Context):
+    """A pic_ctx_t over several slabs (pic_init_batch / pic_step_batch)."""
+
+    def __init__(self, grids, pot: W.Potential, dt: float, max_n, device="cuda", stream=None):
+        self.grids, self.pot, self.dt = list(grids), pot, dt
+        self.grid = self.grids[0]
+        self.nslab = len(self.grids)
+        self.max_ns = [int(m) for m in max_n]
+        self.max_n = max(self.max_ns)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        gs = (pic_grid_t * self.nslab)(*[grid_t(g) for g in self.grids])
+        mn = (C.c_int64 * self.nslab)(*self.max_ns)
+        nbytes = int(lib.pic_workspace_bytes_batch(gs, self.nslab, mn))
+        if nbytes == 0:
+            raise PicError(PIC_EINVAL, "invalid batch")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self._ws_ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.ctx = C.c_void_p()
+        rc = lib.pic_init_batch(C.byref(self.ctx), gs, self.nslab, C.byref(potential_t(pot)), float(dt), mn,
+                                C.c_void_p(self._ws_ptr), nbytes, C.c_void_p(self.stream.cuda_stream))
+        if rc:
+            raise PicError(rc, "pic_init_batch failed")
+        self.nnodes = sum(pic_num_nodes(g) for g in self.grids)
+
+    def pic_step_batch(self, parts_list, nsteps: int, diag_every: int = 0):
+        if len(parts_list) != self.nslab:
+            raise ValueError("one particle set per slab")
+        for p, m in zip(parts_list, self.max_ns):
+            self._parts_ok(p)
+            if p.n > m:
+                raise ValueError("particle count above the slab's max_n")
+        arr = (pic_particles_t * self.nslab)(*[p.struct() for p in parts_list])
+        nd = 0 if diag_every <= 0 else (nsteps + diag_every - 1) // diag_every
+        buf = (pic_diag_t * max(nd * self.nslab, 1))()
+        self._check(lib.pic_step_batch(self.ctx, arr, int(nsteps), buf if nd else None,
+                                       int(diag_every) if nd else 0), "pic_step_batch")
+        return [[{k: getattr(buf[s * nd + i], k) for k in DIAG_FIELDS} for i in range(nd)]
+                for s in range(self.nslab)]

@@ -1,6 +1,7 @@
 // C ABI of the PIC pair-potential library (declared in include/pic.h):
 // argument validation, unit conversion, workspace carving, stream-ordered
-// launches and device-error reporting.
+// launches, graph replay and device-error reporting.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -14,7 +15,14 @@ using namespace pic;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kDiagCap = 1024;  // device diag entries buffered between host copies
+constexpr int kDiagCap = 1024;        // device diag entries buffered between host copies
+constexpr int kMinChunk = 1024;
+constexpr int kMaxChunk = 32768;
+constexpr int kDriftCheck = 48;       // adaptive re-binning looks at the drifter count this often
+constexpr int kDriftFraction = 2048;  // and re-bins once drifters exceed n / kDriftFraction
+constexpr int kMaxBinPeriod = 1024;   // or after this many steps
+constexpr int kGraphSteps = 6;        // a replayed graph holds this many steps (node buffers x counters)
+constexpr int kMaxSlabs = 1024;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t blocks_of(int64_t n) { return (n + 255) / 256; }
@@ -43,9 +51,19 @@ bool grid_sizes(const pic_grid_t *g, Sizes *s, std::string *why) {
   return true;
 }
 
-// Tiled fast path limits: packed cell coordinates and tile sizes.
-bool tiled_supported(const pic_grid_t *g, int64_t max_n) {
-  if (max_n >= (int64_t(1) << 30)) return false;  // 32-bit byte offsets into the store
+pic_grid_t normalised(const pic_grid_t &in) {
+  pic_grid_t g = in;
+  if (g.ndim == 2) {
+    g.n[2] = 1;
+    g.bc[2] = 0;
+    g.h[2] = g.depth2d > 0 ? g.depth2d : g.h[0];
+    g.depth2d = g.h[2];
+  }
+  return g;
+}
+
+// Tiled path limits: packed cell coordinates.
+bool tiled_supported(const pic_grid_t *g) {
   if (g->ndim == 2) return g->n[0] <= 65536 && g->n[1] <= 32768;
   return g->n[0] <= 2048 && g->n[1] <= 2048 && g->n[2] <= 512;
 }
@@ -59,91 +77,151 @@ int64_t tiles_for(const pic_grid_t *g, int lt) {
   return t;
 }
 
-int64_t max_items_for(const pic_grid_t *g, int lt, int64_t max_n, int chunk) {
-  return tiles_for(g, lt) + (max_n + chunk - 1) / chunk;
-}
-
-constexpr int kMinChunk = 1024;
-constexpr int kDriftCheck = 32;      // adaptive re-binning looks at the drifter count this often
-constexpr int kDriftFraction = 2048; // and re-bins once drifters exceed n / kDriftFraction
-constexpr int kMaxBinPeriod = 1024;  // or after this many steps
-constexpr int kMaxChunkHost = 32768;  // the fused kernel keeps a per-item outlier bitmask in LDS
-
 struct Layout {
   size_t err, diag, partial, partial_pe, node, dens, G, total;
   bool tiled;
-  size_t store[2], bins, items, n3[3], drift;
-  int64_t tiles_max, items_max;
+  size_t store[2], bins, items, n3[3], drift, dacc, slabs, offs;
+  int64_t tiles_max, items_max, cap, nodes, pe_blocks;
 };
 
 size_t store_bytes(int ndim, int64_t cap) { return align_up((size_t)cap * 4 * (4 + ndim + 3)); }
 
-Layout make_layout(const pic_grid_t *g, const Sizes &s, int ndim, int64_t max_n) {
+// Workspace of a context of nslab slabs (the untiled single-slab buffers only
+// when nslab == 1).
+Layout make_layout(const pic_grid_t *grids, int nslab, const int64_t *max_n) {
   Layout L{};
+  const int nd = grids[0].ndim;
+  L.tiled = true;
+  int64_t cells1 = 0;
+  for (int k = 0; k < nslab; ++k) {
+    Sizes s;
+    grid_sizes(&grids[k], &s, nullptr);
+    L.nodes += s.nnodes;
+    L.cap += max_n[k];
+    L.pe_blocks += std::max<int64_t>(blocks_of(s.nnodes), 1);
+    L.tiles_max += tiles_for(&grids[k], min_tile_log2(nd));
+    L.tiled = L.tiled && tiled_supported(&grids[k]);
+    cells1 = s.ncells;
+  }
+  // 32-bit store slots and byte offsets, 32-bit node indices
+  L.tiled = L.tiled && L.cap < (int64_t(1) << 30) && L.nodes < (int64_t(1) << 31);
+  L.items_max = L.tiled ? L.tiles_max + (L.cap + kMinChunk - 1) / kMinChunk + nslab : 0;
+  const int64_t partial_blocks = std::max<int64_t>(std::max<int64_t>(blocks_of(L.cap), L.items_max), 1);
   size_t o = 0;
-  L.tiled = tiled_supported(g, max_n);
-  L.tiles_max = L.tiled ? tiles_for(g, min_tile_log2(ndim)) : 0;
-  L.items_max = L.tiled ? max_items_for(g, min_tile_log2(ndim), max_n, kMinChunk) : 0;
-  const int64_t partial_blocks =
-      std::max<int64_t>(std::max<int64_t>(blocks_of(max_n), L.items_max + kDriftBlocks), 1);
   L.err = o; o = align_up(o + sizeof(uint32_t));
   L.diag = o; o = align_up(o + sizeof(pic_diag_t) * kDiagCap);
   L.partial = o; o = align_up(o + sizeof(double) * 8 * (size_t)partial_blocks);
-  L.partial_pe = o; o = align_up(o + sizeof(double) * 8 * (size_t)std::max<int64_t>(blocks_of(s.nnodes), 1));
-  L.node = o; o = align_up(o + sizeof(long long) * (size_t)s.nnodes);
-  L.dens = o; o = align_up(o + sizeof(float) * (size_t)s.nnodes);
-  L.G = o; o = align_up(o + sizeof(float) * (size_t)s.ncells * ndim);
+  L.partial_pe = o; o = align_up(o + sizeof(double) * 8 * (size_t)L.pe_blocks);
+  if (nslab == 1) {
+    L.node = o; o = align_up(o + sizeof(long long) * (size_t)L.nodes);
+    L.dens = o; o = align_up(o + sizeof(float) * (size_t)L.nodes);
+    L.G = o; o = align_up(o + sizeof(float) * (size_t)cells1 * nd);
+  }
   if (L.tiled) {
-    for (int k = 0; k < 2; ++k) { L.store[k] = o; o += store_bytes(ndim, std::max<int64_t>(max_n, 1)); }
-    L.bins = o; o = align_up(o + sizeof(int) * (size_t)(4 * L.tiles_max + 2));
+    const int64_t cap = std::max<int64_t>(L.cap, 1);
+    for (int k = 0; k < 2; ++k) { L.store[k] = o; o += store_bytes(nd, cap); }
+    L.bins = o; o = align_up(o + sizeof(int) * (size_t)(4 * L.tiles_max + 4));
     L.items = o; o = align_up(o + sizeof(Item) * (size_t)L.items_max);
-    for (int k = 0; k < 3; ++k) { L.n3[k] = o; o = align_up(o + sizeof(long long) * (size_t)s.nnodes); }
-    L.drift = o; o = align_up(o + sizeof(int) * (size_t)(std::max<int64_t>(max_n, 1) + 2));
+    for (int k = 0; k < 3; ++k) { L.n3[k] = o; o = align_up(o + sizeof(long long) * (size_t)L.nodes); }
+    L.drift = o; o = align_up(o + sizeof(int) * (size_t)(cap + 4));
+    L.dacc = o; o = align_up(o + sizeof(double) * 8 * (size_t)nslab);
+    L.slabs = o; o = align_up(o + sizeof(SlabDesc) * (size_t)nslab);
+    L.offs = o; o = align_up(o + sizeof(int) * (size_t)(2 * (nslab + 1)));
   }
   L.total = o;
   return L;
 }
 
+bool valid_potential(const pic_potential_t *pot) {
+  if (!pot) return false;
+  const pic_potential_t &P = *pot;
+  return P.D > 0 && P.r0 > 0 && P.s_rep > 0 && P.c_att > 0 && P.g_clamp > 0 && P.g_clamp < 2 &&
+         P.n_floor >= 0 && P.mass > 0 && std::isfinite(P.s_rep) && std::isfinite(P.c_att) &&
+         std::isfinite(P.D) && std::isfinite(P.r0) && std::isfinite(P.mass);
+}
+
+// Grid constants in the kernels' reduced units.
+Geo make_geo(const pic_grid_t &g, const pic_potential_t &P, double dt, const Sizes &s) {
+  Geo G;
+  std::memset(&G, 0, sizeof(G));
+  const double V = g.h[0] * g.h[1] * g.h[2];
+  const double r3 = P.r0 * P.r0 * P.r0;
+  G.ndim = g.ndim;
+  for (int d = 0; d < 3; ++d) {
+    G.n[d] = d < g.ndim ? g.n[d] : 1;
+    G.bc[d] = d < g.ndim ? g.bc[d] : 0;
+    G.nn[d] = d < g.ndim ? g.n[d] + g.bc[d] : 1;
+    G.gam[d] = d < g.ndim ? (float)(P.r0 / ((g.ndim == 2 ? 2.0 : 4.0) * g.h[d])) : 0.0f;
+    G.tau[d] = d < g.ndim ? (float)(dt / g.h[d]) : 0.0f;
+  }
+  G.ncells = (int)s.ncells;
+  G.nnodes = (int)s.nnodes;
+  G.inv_n0 = 1.0 / G.n[0];
+  G.inv_n1 = 1.0 / G.n[1];
+  G.kappa = (float)(std::ldexp(1.0, -20) * r3 / V);
+  return G;
+}
+
+DiagC make_diag(const pic_grid_t &g, const pic_potential_t &P) {
+  const double V = g.h[0] * g.h[1] * g.h[2];
+  return DiagC{P.D, P.mass, 0.5 * P.mass, std::ldexp(1.0, -20), V, P.r0 * P.r0 * P.r0, P.s_rep, P.c_att};
+}
+
 }  // namespace
 
 struct pic_ctx {
-  pic_grid_t grid;
-  pic_potential_t pot;
-  double dt;
-  int64_t max_n;
-  Sizes sz;
-  char *ws;
-  hipStream_t stream;
-  Geo geo;
-  Pot P;
-  DiagC dc;
-  uint32_t *err;
-  pic_diag_t *diag_dev;
-  double *partial;
-  double *partial_pe;
-  long long *node;
-  float *dens;
-  float *G;
+  // problem
+  int nslab = 1;
+  int ndim = 2;
+  std::vector<pic_grid_t> grids;
+  std::vector<int64_t> max_n;
+  std::vector<Sizes> sizes;
+  pic_potential_t pot{};
+  double dt = 0;
+  char *ws = nullptr;
+  hipStream_t stream = nullptr;
+  Pot P{};
+  std::vector<DiagC> dcs;  // per slab (cell volume)
+  // shared buffers
+  uint32_t *err = nullptr;
+  pic_diag_t *diag_dev = nullptr;
+  double *partial = nullptr;
+  double *partial_pe = nullptr;
+  std::vector<int> pe_off;  // first energy-partial block of each slab
   std::string last_error;
-  // tiled fast path
+  // untiled single-slab path
+  Geo geo{};
+  long long *node = nullptr;
+  float *dens = nullptr;
+  float *G = nullptr;
+  bool force_untiled = false;
+  // tiled path
   bool tiled = false;
-  TileGeo tg{};
+  int lt = 4, halo = 2, chunk = 8192, sort_every = -1;
+  std::vector<SlabDesc> sd;  // host copy of the slab table
+  SlabDesc *sd_dev = nullptr;
+  int *part_offs_dev = nullptr, *tile_offs_dev = nullptr;
+  int ntiles = 0, nnodes = 0;
+  int64_t cap = 0, items_cap = 0;
   Store st[2]{};
   BinBufs bb{};
   long long *n3[3]{};
-  int *drift = nullptr;  // [2 counters][max_n list]
-  int64_t tiles_cap = 0, items_cap = 0;
-  int sort_every = 0;           // > 0 fixed period, 0 never, < 0 adaptive
-  int *h_drift = nullptr;       // pinned host copy of a drifter count (adaptive re-binning)
+  int *drift = nullptr;  // [count0, count1, work0, work1][list]
+  double *dacc = nullptr;
+  int grid_blocks = 0;   // persistent grid of the fused kernel
+  int *h_drift = nullptr;
   hipEvent_t drift_ev = nullptr;
   bool drift_pending = false;
-  bool force_untiled = false;
   long long *last_nodes = nullptr;
   int last_step = 0;
+  // graph replay of steady steps
+  bool use_graph = true;
+  hipGraphExec_t graph[2]{};
+  std::vector<int64_t> graph_key;
   // event timing of pic_step phases
   bool timing = false;
   pic_timing_t tacc{};
-  std::vector<hipEvent_t> ev_pool;           // free events
+  std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
 };
 
@@ -201,14 +279,12 @@ static int hip_check(pic_ctx_t *ctx, hipError_t e, const char *what) {
   return fail(ctx, PIC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-static int check_launch(pic_ctx_t *ctx, const char *what) {
-  return hip_check(ctx, hipGetLastError(), what);
-}
+static int check_launch(pic_ctx_t *ctx, const char *what) { return hip_check(ctx, hipGetLastError(), what); }
 
-static int check_particles(pic_ctx_t *ctx, const pic_particles_t *p, bool need_vel, bool need_wq) {
+static int check_particles(pic_ctx_t *ctx, const pic_particles_t *p, int64_t max_n, bool need_vel, bool need_wq) {
   if (!p) return fail(ctx, PIC_EINVAL, "particles is NULL");
   if (p->n < 0) return fail(ctx, PIC_EINVAL, "particle count is negative");
-  if (p->n > ctx->max_n) return fail(ctx, PIC_ENOSPACE, "particle count exceeds max_n of the context");
+  if (p->n > max_n) return fail(ctx, PIC_ENOSPACE, "particle count exceeds max_n of the context");
   if (p->n == 0) return PIC_OK;
   if (!p->cell || !p->off) return fail(ctx, PIC_EINVAL, "cell or off is NULL");
   if (need_vel && !p->vel) return fail(ctx, PIC_EINVAL, "vel is NULL");
@@ -216,9 +292,7 @@ static int check_particles(pic_ctx_t *ctx, const pic_particles_t *p, bool need_v
   return PIC_OK;
 }
 
-static PartPtrs ptrs(const pic_particles_t *p) {
-  return PartPtrs{p->n, p->cell, p->off, p->vel, p->wq};
-}
+static PartPtrs ptrs(const pic_particles_t *p) { return PartPtrs{p->n, p->cell, p->off, p->vel, p->wq}; }
 
 // Read and clear the device error word; map it to a status.
 static int read_device_error(pic_ctx_t *ctx) {
@@ -241,160 +315,198 @@ static int read_device_error(pic_ctx_t *ctx) {
   return PIC_OK;
 }
 
-// Apply a tiling (tile edge 2^lt cells, halo, chunk, binning period).
+static void drop_graphs(pic_ctx_t *c) {
+  for (auto &g : c->graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  c->graph_key.clear();
+}
+
+// Apply a tiling to every slab (tile edge 2^lt cells, halo, chunk, re-binning
+// period) and upload the slab table.
 static int apply_tiling(pic_ctx_t *c, int lt, int halo, int chunk, int sort_every) {
-  const int nd = c->grid.ndim;
+  const int nd = c->ndim;
   if (lt < min_tile_log2(nd) || lt > max_tile_log2(nd)) return fail(c, PIC_EINVAL, "tile edge out of range");
   if (halo < 1 || halo > 4) return fail(c, PIC_EINVAL, "halo must be 1..4 cells");
-  if (chunk < kMinChunk || chunk > kMaxChunkHost) return fail(c, PIC_EINVAL, "chunk out of range");
+  if (chunk < kMinChunk || chunk > kMaxChunk) return fail(c, PIC_EINVAL, "chunk out of range");
   if (sort_every < -1) return fail(c, PIC_EINVAL, "sort_every must be >= -1");
-  TileGeo &T = c->tg;
-  T.ntiles = 1;
-  for (int d = 0; d < 3; ++d) {
-    T.lt[d] = d < nd ? lt : 0;
-    T.tn[d] = d < nd ? (c->grid.n[d] + (1 << lt) - 1) >> lt : 1;
-    T.ntiles *= T.tn[d];
-  }
+  TileGeo T{};
+  for (int d = 0; d < 3; ++d) T.lt[d] = d < nd ? lt : 0;
   T.H = halo;
   T.chunk = chunk;
-  TileGeo probe = T;
-  if (window_lds_bytes(probe, nd) > 64 * 1024) return fail(c, PIC_EINVAL, "tile window does not fit in LDS");
-  for (int d = 0; d < nd; ++d)  // periodic axes must hold a whole window (single-wrap window coordinates)
-    if (!c->grid.bc[d] && c->grid.n[d] < (1 << lt) + 2 * halo + 3)
-      return fail(c, PIC_EINVAL, "a periodic axis is shorter than the tile window");
+  T.pshift[0] = 0;
+  T.pshift[1] = nd == 2 ? 16 : 11;
+  T.pshift[2] = nd == 2 ? 31 : 22;
+  T.pmask[0] = nd == 2 ? 0xFFFF : 0x7FF;
+  T.pmask[1] = nd == 2 ? 0x7FFF : 0x7FF;
+  T.pmask[2] = nd == 2 ? 0 : 0x1FF;
+  if (window_lds_bytes(T, nd) > 64 * 1024) return fail(c, PIC_EINVAL, "tile window does not fit in LDS");
+  std::vector<SlabDesc> sd(c->nslab);
+  int tiles = 0, nodes = 0;
+  for (int k = 0; k < c->nslab; ++k) {
+    const pic_grid_t &g = c->grids[k];
+    for (int d = 0; d < nd; ++d)  // periodic axes must hold a whole window (single-wrap window coordinates)
+      if (!g.bc[d] && g.n[d] < (1 << lt) + 2 * halo + 3)
+        return fail(c, PIC_EINVAL, "a periodic axis is shorter than the tile window");
+    SlabDesc &s = sd[k];
+    s.g = make_geo(g, c->pot, c->dt, c->sizes[k]);
+    s.tg = T;
+    s.tg.ntiles = 1;
+    for (int d = 0; d < 3; ++d) {
+      s.tg.tn[d] = d < nd ? (g.n[d] + (1 << lt) - 1) >> lt : 1;
+      s.tg.ntiles *= s.tg.tn[d];
+    }
+    s.node_off = nodes;
+    s.tile_off = tiles;
+    s.part_off = k < (int)c->sd.size() ? c->sd[k].part_off : 0;
+    s.part_n = k < (int)c->sd.size() ? c->sd[k].part_n : 0;
+    nodes += (int)c->sizes[k].nnodes;
+    tiles += s.tg.ntiles;
+  }
+  c->sd = sd;
+  c->ntiles = tiles;
+  c->nnodes = nodes;
+  c->lt = lt;
+  c->halo = halo;
+  c->chunk = chunk;
   c->sort_every = sort_every;
+  std::vector<int> toffs(c->nslab + 1);
+  for (int k = 0; k < c->nslab; ++k) toffs[k] = sd[k].tile_off;
+  toffs[c->nslab] = tiles;
+  int rc = hip_check(c, hipMemcpy(c->sd_dev, sd.data(), sizeof(SlabDesc) * c->nslab, hipMemcpyHostToDevice),
+                     "upload slab table");
+  if (!rc)
+    rc = hip_check(c, hipMemcpy(c->tile_offs_dev, toffs.data(), sizeof(int) * toffs.size(), hipMemcpyHostToDevice),
+                   "upload tile offsets");
+  if (rc) return rc;
+  c->grid_blocks = 0;
+  drop_graphs(c);
   return PIC_OK;
 }
 
-static int64_t max_items_now(const pic_ctx_t *c, int64_t n) {
-  return (int64_t)c->tg.ntiles + (n + c->tg.chunk - 1) / c->tg.chunk;
+// Per-call store layout: slab k owns slots [part_off_k, part_off_k + n_k).
+static int bind_counts(pic_ctx_t *c, const pic_particles_t *parts) {
+  std::vector<int> poffs(c->nslab + 1);
+  int64_t off = 0;
+  for (int k = 0; k < c->nslab; ++k) {
+    c->sd[k].part_off = (int)off;
+    c->sd[k].part_n = (int)parts[k].n;
+    poffs[k] = (int)off;
+    off += parts[k].n;
+  }
+  poffs[c->nslab] = (int)off;
+  int rc = hip_check(c, hipMemcpyAsync(c->sd_dev, c->sd.data(), sizeof(SlabDesc) * c->nslab,
+                                       hipMemcpyHostToDevice, c->stream),
+                     "upload slab table");
+  if (!rc)
+    rc = hip_check(c, hipMemcpyAsync(c->part_offs_dev, poffs.data(), sizeof(int) * poffs.size(),
+                                     hipMemcpyHostToDevice, c->stream),
+                   "upload slot offsets");
+  if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
+  return rc;
 }
 
-extern "C" {
-
-int64_t pic_num_nodes(const pic_grid_t *grid) {
-  Sizes s;
-  return grid_sizes(grid, &s, nullptr) ? s.nnodes : 0;
+static Batch batch_of(const pic_ctx_t *c, int64_t nparts) {
+  return Batch{c->sd_dev, c->part_offs_dev, c->tile_offs_dev, c->nslab, c->ntiles, c->nnodes, (int)nparts};
 }
 
-size_t pic_workspace_bytes(const pic_grid_t *grid, int64_t max_n) {
-  Sizes s;
-  if (!grid_sizes(grid, &s, nullptr) || max_n < 0) return 0;
-  return make_layout(grid, s, grid->ndim, max_n).total;
-}
-
-int pic_init(pic_ctx_t **out, const pic_grid_t *grid, const pic_potential_t *pot, double dt, int64_t max_n,
-             void *ws, size_t ws_bytes, void *stream) {
+// Create a context for nslab slabs; shared by pic_init and pic_init_batch.
+static int init_common(pic_ctx_t **out, const pic_grid_t *grids_in, int nslab, const pic_potential_t *pot,
+                       double dt, const int64_t *max_n, void *ws, size_t ws_bytes, void *stream) {
   if (!out) return PIC_EINVAL;
   *out = nullptr;
-  Sizes s;
-  std::string why;
-  if (!grid_sizes(grid, &s, &why)) return PIC_EINVAL;
-  if (!pot) return PIC_EINVAL;
-  const pic_potential_t &P = *pot;
-  if (!(P.D > 0) || !(P.r0 > 0) || !(P.s_rep > 0) || !(P.c_att > 0) || !(P.g_clamp > 0) || !(P.g_clamp < 2) ||
-      !(P.n_floor >= 0) || !(P.mass > 0) || !std::isfinite(P.s_rep) || !std::isfinite(P.c_att))
-    return PIC_EINVAL;
+  if (!grids_in || !max_n || nslab < 1 || nslab > kMaxSlabs) return PIC_EINVAL;
+  std::vector<pic_grid_t> grids(nslab);
+  std::vector<Sizes> sizes(nslab);
+  for (int k = 0; k < nslab; ++k) {
+    if (!grid_sizes(&grids_in[k], &sizes[k], nullptr)) return PIC_EINVAL;
+    if (grids_in[k].ndim != grids_in[0].ndim) return PIC_EINVAL;
+    if (max_n[k] < 0 || max_n[k] >= (int64_t(1) << 40)) return PIC_EINVAL;
+    grids[k] = normalised(grids_in[k]);
+  }
+  if (!valid_potential(pot)) return PIC_EINVAL;
   if (!(dt > 0) || !std::isfinite(dt)) return PIC_EINVAL;
-  if (max_n < 0 || max_n >= (int64_t(1) << 40)) return PIC_EINVAL;
-  Layout L = make_layout(grid, s, grid->ndim, max_n);
+  Layout L = make_layout(grids.data(), nslab, max_n);
+  if (nslab > 1 && !L.tiled) return PIC_EINVAL;  // batches need the tiled path
   if (!ws || ws_bytes < L.total) return PIC_ENOSPACE;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return PIC_EINVAL;
 
   pic_ctx_t *c = new pic_ctx_t();
-  c->grid = *grid;
-  if (c->grid.ndim == 2) {
-    c->grid.n[2] = 1;
-    c->grid.bc[2] = 0;
-    c->grid.h[2] = c->grid.depth2d > 0 ? c->grid.depth2d : c->grid.h[0];
-    c->grid.depth2d = c->grid.h[2];
-  }
-  c->pot = P;
+  c->nslab = nslab;
+  c->ndim = grids[0].ndim;
+  c->grids = grids;
+  c->max_n.assign(max_n, max_n + nslab);
+  c->sizes = sizes;
+  c->pot = *pot;
   c->dt = dt;
-  c->max_n = max_n;
-  c->sz = s;
   c->ws = static_cast<char *>(ws);
   c->stream = static_cast<hipStream_t>(stream);
-
-  const pic_grid_t &g = c->grid;
-  const double V = g.h[0] * g.h[1] * g.h[2];
+  const pic_potential_t &P = *pot;
   const double r3 = P.r0 * P.r0 * P.r0;
-  Geo &G = c->geo;
-  std::memset(&G, 0, sizeof(G));
-  G.ndim = g.ndim;
-  for (int d = 0; d < 3; ++d) {
-    G.n[d] = d < g.ndim ? g.n[d] : 1;
-    G.bc[d] = d < g.ndim ? g.bc[d] : 0;
-    G.nn[d] = d < g.ndim ? g.n[d] + g.bc[d] : 1;
-    G.gam[d] = d < g.ndim ? (float)(P.r0 / ((g.ndim == 2 ? 2.0 : 4.0) * g.h[d])) : 0.0f;
-    G.tau[d] = d < g.ndim ? (float)(dt / g.h[d]) : 0.0f;
+  c->P.nfloor = (float)(P.n_floor * r3);
+  c->P.gclamp = (float)P.g_clamp;
+  c->P.s_rep = (float)P.s_rep;
+  c->P.c_att = (float)P.c_att;
+  c->P.beta = (float)(12.0 * P.D / P.r0);
+  c->P.gv = (float)(dt / P.mass);
+  int pe = 0;
+  for (int k = 0; k < nslab; ++k) {
+    c->dcs.push_back(make_diag(grids[k], P));
+    c->pe_off.push_back(pe);
+    pe += (int)std::max<int64_t>(blocks_of(sizes[k].nnodes), 1);
   }
-  G.ncells = (int)s.ncells;
-  G.nnodes = (int)s.nnodes;
-  G.inv_n0 = 1.0 / G.n[0];
-  G.inv_n1 = 1.0 / G.n[1];
-  G.kappa = (float)(std::ldexp(1.0, -20) * r3 / V);
-  Pot &K = c->P;
-  K.nfloor = (float)(P.n_floor * r3);
-  K.gclamp = (float)P.g_clamp;
-  K.s_rep = (float)P.s_rep;
-  K.c_att = (float)P.c_att;
-  K.beta = (float)(12.0 * P.D / P.r0);
-  K.gv = (float)(dt / P.mass);
-  c->dc = DiagC{P.D, P.mass, 0.5 * P.mass, std::ldexp(1.0, -20), V, r3, P.s_rep, P.c_att};
-
   c->err = reinterpret_cast<uint32_t *>(c->ws + L.err);
   c->diag_dev = reinterpret_cast<pic_diag_t *>(c->ws + L.diag);
   c->partial = reinterpret_cast<double *>(c->ws + L.partial);
   c->partial_pe = reinterpret_cast<double *>(c->ws + L.partial_pe);
-  c->node = reinterpret_cast<long long *>(c->ws + L.node);
-  c->dens = reinterpret_cast<float *>(c->ws + L.dens);
-  c->G = reinterpret_cast<float *>(c->ws + L.G);
+  if (nslab == 1) {
+    c->geo = make_geo(grids[0], P, dt, sizes[0]);
+    c->node = reinterpret_cast<long long *>(c->ws + L.node);
+    c->dens = reinterpret_cast<float *>(c->ws + L.dens);
+    c->G = reinterpret_cast<float *>(c->ws + L.G);
+  }
   c->tiled = L.tiled;
   if (L.tiled) {
-    const int64_t cap = std::max<int64_t>(max_n, 1);
+    const int64_t cap = std::max<int64_t>(L.cap, 1);
+    c->cap = cap;
+    c->items_cap = L.items_max;
     for (int k = 0; k < 2; ++k) {
       char *b = c->ws + L.store[k];
       Store &S = c->st[k];
       S.cap = cap;
       S.pc = reinterpret_cast<int *>(b);
       S.off = reinterpret_cast<float *>(b + 4 * cap);
-      S.vel = reinterpret_cast<float *>(b + 4 * cap * (1 + g.ndim));
-      S.wq = reinterpret_cast<int *>(b + 4 * cap * (4 + g.ndim));
-      S.oidx = reinterpret_cast<int *>(b + 4 * cap * (5 + g.ndim));
+      S.vel = reinterpret_cast<float *>(b + 4 * cap * (1 + c->ndim));
+      S.wq = reinterpret_cast<int *>(b + 4 * cap * (4 + c->ndim));
+      S.oidx = reinterpret_cast<int *>(b + 4 * cap * (5 + c->ndim));
     }
     int *bi = reinterpret_cast<int *>(c->ws + L.bins);
+    const int64_t T = L.tiles_max;
     c->bb.counts = bi;
-    c->bb.starts = bi + L.tiles_max;
-    c->bb.cursors = bi + 2 * L.tiles_max + 1;
-    c->bb.item_start = bi + 3 * L.tiles_max + 1;
-    c->bb.num_items = bi + 4 * L.tiles_max + 1;
+    c->bb.starts = bi + T;
+    c->bb.cursors = bi + 2 * T + 1;
+    c->bb.item_start = bi + 3 * T + 1;
+    c->bb.num_items = bi + 4 * T + 2;
     c->bb.items = reinterpret_cast<Item *>(c->ws + L.items);
     for (int k = 0; k < 3; ++k) c->n3[k] = reinterpret_cast<long long *>(c->ws + L.n3[k]);
     c->drift = reinterpret_cast<int *>(c->ws + L.drift);
-    c->tiles_cap = L.tiles_max;
-    c->items_cap = L.items_max;
-    TileGeo &T = c->tg;
-    T.pshift[0] = 0;
-    T.pshift[1] = g.ndim == 2 ? 16 : 11;
-    T.pshift[2] = g.ndim == 2 ? 31 : 22;
-    T.pmask[0] = g.ndim == 2 ? 0xFFFF : 0x7FF;
-    T.pmask[1] = g.ndim == 2 ? 0x7FFF : 0x7FF;
-    T.pmask[2] = g.ndim == 2 ? 0 : 0x1FF;
-  }
-  launch_clear_word(c->stream, c->err);
-  if (hipGetLastError() != hipSuccess) {
-    delete c;
-    return PIC_EHIP;
-  }
-  if (c->tiled) {
-    // default tiling; smaller tiles for small periodic grids; untiled if none fits
+    c->dacc = reinterpret_cast<double *>(c->ws + L.dacc);
+    c->sd_dev = reinterpret_cast<SlabDesc *>(c->ws + L.slabs);
+    c->part_offs_dev = reinterpret_cast<int *>(c->ws + L.offs);
+    c->tile_offs_dev = c->part_offs_dev + nslab + 1;
+    // default tiling: 16^2 (2D) / 8^3 (3D) tiles, smaller where a periodic axis is short
     int rc = PIC_EINVAL;
-    if (g.ndim == 2) {
-      for (int lt = 4; lt >= 3 && rc; --lt) rc = apply_tiling(c, lt, 2, 8192, -1);
-      if (rc) rc = apply_tiling(c, 3, 1, 8192, -1);
+    if (c->ndim == 2) {
+      for (int lt = 4; lt >= 3 && rc && rc != PIC_EHIP; --lt) rc = apply_tiling(c, lt, 2, 8192, -1);
+      if (rc && rc != PIC_EHIP) rc = apply_tiling(c, 3, 1, 8192, -1);
     } else {
-      for (int lt = 3; lt >= 2 && rc; --lt) rc = apply_tiling(c, lt, 1, 4096, -1);
+      for (int lt = 3; lt >= 2 && rc && rc != PIC_EHIP; --lt) rc = apply_tiling(c, lt, 1, 4096, -1);
+    }
+    if (rc == PIC_EHIP) {
+      delete c;
+      return PIC_EHIP;
     }
     if (rc) c->tiled = false;
     c->last_error.clear();
@@ -403,18 +515,309 @@ int pic_init(pic_ctx_t **out, const pic_grid_t *grid, const pic_potential_t *pot
       c->h_drift = nullptr;
       c->tiled = false;
     }
+    if (!c->tiled && nslab > 1) {
+      delete c;
+      return PIC_EINVAL;
+    }
+  }
+  launch_clear_word(c->stream, c->err);
+  if (c->tiled) launch_fill64(c->stream, reinterpret_cast<long long *>(c->dacc), 8 * nslab);
+  if (hipGetLastError() != hipSuccess) {
+    delete c;
+    return PIC_EHIP;
   }
   *out = c;
   return PIC_OK;
 }
 
-int pic_set_tiling(pic_ctx_t *ctx, int32_t tile, int32_t halo, int32_t chunk, int32_t sort_every) {
-  if (!ctx) return PIC_EINVAL;
-  if (!ctx->tiled) return fail(ctx, PIC_EINVAL, "this grid uses the untiled path");
-  int lt = 0;
-  while ((1 << lt) < tile) ++lt;
-  if ((1 << lt) != tile) return fail(ctx, PIC_EINVAL, "tile edge must be a power of two");
-  return apply_tiling(ctx, lt, halo, chunk, sort_every);
+namespace {
+
+// Diagnostics: device entries (step-major, slab-minor) copied out in blocks
+// into the caller's [nslab][ndiag] array.
+struct DiagSink {
+  pic_ctx_t *ctx;
+  pic_diag_t *host;
+  int64_t ndiag;
+  int slot = 0;
+  int64_t step_index = 0;  // diag steps already copied
+  std::vector<pic_diag_t> stage;
+  int flush() {
+    if (!slot) return PIC_OK;
+    stage.resize(slot);
+    int r = hip_check(ctx, hipMemcpyAsync(stage.data(), ctx->diag_dev, sizeof(pic_diag_t) * slot,
+                                          hipMemcpyDeviceToHost, ctx->stream),
+                      "copy diagnostics");
+    if (r) return r;
+    r = hip_check(ctx, hipStreamSynchronize(ctx->stream), "stream synchronize");
+    if (r) return r;
+    const int ns = ctx->nslab;
+    for (int e = 0; e < slot; ++e) host[(int64_t)(e % ns) * ndiag + step_index + e / ns] = stage[e];
+    step_index += slot / ns;
+    slot = 0;
+    return PIC_OK;
+  }
+  pic_diag_t *next() { return ctx->diag_dev + slot; }
+  int advance(int entries) {
+    slot += entries;
+    return slot + ctx->nslab > kDiagCap ? flush() : PIC_OK;
+  }
+};
+
+int step_untiled(pic_ctx_t *ctx, const PartPtrs &pp, int32_t nsteps, DiagSink &ds, int32_t diag_every) {
+  for (int32_t s = 0; s < nsteps; ++s) {
+    const bool want = ds.host && (s % diag_every) == 0;
+    {
+      PhaseTimer t(ctx, 0);
+      launch_fill64(ctx->stream, ctx->node, ctx->sizes[0].nnodes);
+      launch_deposit_atomic(ctx->stream, ctx->geo, pp, ctx->node, ctx->err);
+    }
+    {
+      PhaseTimer t(ctx, 1);
+      launch_grid(ctx->stream, ctx->geo, ctx->node, ctx->dens, ctx->G);
+    }
+    int nbg = 0, nbp = 0;
+    if (want) {
+      PhaseTimer t(ctx, 4);
+      nbg = launch_pe_nodes(ctx->stream, ctx->geo, ctx->dcs[0], ctx->node, ctx->partial_pe);
+    }
+    {
+      PhaseTimer t(ctx, 2);
+      nbp = launch_force_push(ctx->stream, ctx->geo, ctx->P, ctx->dcs[0], pp, ctx->dens, ctx->G, ctx->partial, want,
+                              ctx->err);
+    }
+    if (want) {
+      PhaseTimer t(ctx, 4);
+      launch_reduce_diag(ctx->stream, ctx->partial, nbp, ctx->partial_pe, nbg, ds.next(), s);
+    }
+    int rc = check_launch(ctx, "step");
+    if (rc) return rc;
+    if (want && (rc = ds.advance(1))) return rc;
+  }
+  return PIC_OK;
+}
+
+Drift drift_of(pic_ctx_t *c, int s) {
+  return Drift{c->drift + 4, c->drift + (s & 1), c->drift + ((s + 1) & 1), c->drift + 2 + (s & 1),
+               c->drift + 2 + ((s + 1) & 1)};
+}
+
+// The launches of one tiled step (fused kernel, then drifters).
+void enqueue_step(pic_ctx_t *c, const Batch &b, const Store &st, int s, bool diag) {
+  long long *Nc = c->n3[s % 3], *Nn = c->n3[(s + 1) % 3], *Nz = c->n3[(s + 2) % 3];
+  const Drift dr = drift_of(c, s);
+  {
+    PhaseTimer t(c, 2);
+    launch_step_tiled(c->stream, c->ndim, c->sd[0].tg, c->P, c->dcs[0], b, st, c->bb, c->grid_blocks, Nc, Nn, Nz,
+                      dr, c->partial, diag, c->err);
+  }
+  {
+    PhaseTimer t(c, 6);
+    launch_drifters(c->stream, c->ndim, c->P, c->dcs[0], b, st, Nc, Nn, dr, c->dacc, diag, c->err);
+  }
+}
+
+// Graph of kGraphSteps plain steps starting at a step index that is a
+// multiple of kGraphSteps (node buffers cycle with period 3, counters 2).
+int graph_for(pic_ctx_t *c, const Batch &b, int cur, hipGraphExec_t *out) {
+  std::vector<int64_t> key = {b.nparts, c->lt, c->halo, c->chunk, c->grid_blocks, c->nslab};
+  for (const SlabDesc &s : c->sd) {
+    key.push_back(s.part_off);
+    key.push_back(s.part_n);
+  }
+  if (c->graph_key != key) {
+    drop_graphs(c);
+    c->graph_key = key;
+  }
+  if (c->graph[cur]) {
+    *out = c->graph[cur];
+    return PIC_OK;
+  }
+  const bool timing = c->timing;
+  c->timing = false;  // no event records inside a capture
+  hipGraph_t g = nullptr;
+  int rc = hip_check(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  if (rc) {
+    c->timing = timing;
+    return rc;
+  }
+  for (int s = 0; s < kGraphSteps; ++s) enqueue_step(c, b, c->st[cur], s, false);
+  rc = hip_check(c, hipStreamEndCapture(c->stream, &g), "end capture");
+  c->timing = timing;
+  if (rc) return rc;
+  rc = hip_check(c, hipGraphInstantiate(&c->graph[cur], g, nullptr, nullptr, 0), "instantiate graph");
+  (void)hipGraphDestroy(g);
+  if (rc) return rc;
+  *out = c->graph[cur];
+  return PIC_OK;
+}
+
+// Steps [s, s + kGraphSteps) are plain: no diagnostics, no re-binning and no
+// adaptive check inside, and s is a multiple of kGraphSteps.
+bool plain_block(const pic_ctx_t *c, int s, int nsteps, int since_bin, bool diag, int diag_every) {
+  if (s % kGraphSteps || s + kGraphSteps > nsteps) return false;
+  if (since_bin + kGraphSteps >= kMaxBinPeriod) return false;
+  for (int k = 0; k < kGraphSteps; ++k) {
+    const int t = s + k;
+    if (diag && t % diag_every == 0) return false;
+    if (c->sort_every > 0 && t > 0 && t % c->sort_every == 0) return false;
+    if (c->sort_every < 0 && t > 0 && t % kDriftCheck == 0) return false;
+  }
+  return true;
+}
+
+int step_tiled(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t nsteps, DiagSink &ds, int32_t diag_every,
+               bool export_back = true, float *probe_ms = nullptr) {
+  const int nd = ctx->ndim;
+  int rc = bind_counts(ctx, parts);
+  if (rc) return rc;
+  int64_t n = 0;
+  std::vector<PartPtrs> cps(ctx->nslab);
+  for (int k = 0; k < ctx->nslab; ++k) {
+    cps[k] = ptrs(&parts[k]);
+    n += parts[k].n;
+  }
+  const Batch b = batch_of(ctx, n);
+  if (!ctx->grid_blocks) {
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) ncu = 256;
+    ctx->grid_blocks = ncu * step_kernel_blocks_per_cu(nd, ctx->sd[0].tg);
+  }
+  int cur = 0;
+  // bring the caller's particles into the binned store; stop on invalid input
+  {
+    PhaseTimer t(ctx, 5);
+    launch_import(ctx->stream, nd, ctx->sd.data(), cps.data(), ctx->nslab, ctx->bb, b, ctx->chunk, ctx->st[cur],
+                  ctx->err);
+  }
+  if ((rc = check_launch(ctx, "binning"))) return rc;
+  if ((rc = read_device_error(ctx))) return rc;
+  const int64_t max_items = (int64_t)ctx->ntiles + (n + ctx->chunk - 1) / ctx->chunk;
+  launch_fill64(ctx->stream, ctx->n3[0], ctx->nnodes);
+  launch_fill64(ctx->stream, ctx->n3[1], ctx->nnodes);
+  launch_fill32(ctx->stream, ctx->drift, 4);
+  {
+    PhaseTimer t(ctx, 0);
+    launch_deposit_tiled(ctx->stream, nd, ctx->sd[0].tg, b, ctx->st[cur], ctx->bb, (int)max_items, ctx->n3[0]);
+  }
+  int since_bin = 0;
+  ctx->drift_pending = false;
+  hipEvent_t pa = nullptr, pb = nullptr;
+  if (probe_ms) {
+    pa = take_event(ctx);
+    pb = take_event(ctx);
+    if (!pa || !pb) return fail(ctx, PIC_EHIP, "event creation failed");
+    (void)hipEventRecord(pa, ctx->stream);
+  }
+  for (int32_t s = 0; s < nsteps;) {
+    // graphs need a capturable stream: never the legacy default (NULL) stream
+    if (ctx->use_graph && !ctx->timing && ctx->stream != nullptr &&
+        plain_block(ctx, s, nsteps, since_bin, ds.host != nullptr, diag_every)) {
+      hipGraphExec_t ge = nullptr;
+      if ((rc = graph_for(ctx, b, cur, &ge))) return rc;
+      {
+        PhaseTimer t(ctx, 7);
+        rc = hip_check(ctx, hipGraphLaunch(ge, ctx->stream), "graph launch");
+      }
+      if (rc) return rc;
+      s += kGraphSteps;
+      since_bin += kGraphSteps;
+      continue;
+    }
+    bool rebin = false;
+    if (ctx->sort_every > 0) {
+      rebin = s > 0 && s % ctx->sort_every == 0;
+    } else if (ctx->sort_every < 0 && s > 0 && s % kDriftCheck == 0) {
+      // adaptive: look at the drifter count copied kDriftCheck steps ago (long
+      // finished, so the host does not stall), then post a copy of this one
+      if (ctx->drift_pending) {
+        (void)hipEventSynchronize(ctx->drift_ev);
+        rebin = (int64_t)ctx->h_drift[0] * kDriftFraction > n || since_bin >= kMaxBinPeriod;
+      }
+      const int last = (s - 1) & 1;  // drifter counter of the previous step
+      (void)hipMemcpyAsync(ctx->h_drift, ctx->drift + last, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+      (void)hipEventRecord(ctx->drift_ev, ctx->stream);
+      ctx->drift_pending = true;
+    }
+    if (rebin) {
+      PhaseTimer t(ctx, 3);
+      launch_rebin(ctx->stream, nd, ctx->bb, b, ctx->chunk, ctx->st[cur], ctx->st[1 - cur]);
+      cur = 1 - cur;
+      since_bin = 0;
+    }
+    const bool want = ds.host && (s % diag_every) == 0;
+    if (want) {
+      PhaseTimer t(ctx, 4);
+      for (int k = 0; k < ctx->nslab; ++k)
+        launch_pe_nodes(ctx->stream, ctx->sd[k].g, ctx->dcs[k], ctx->n3[s % 3] + ctx->sd[k].node_off,
+                        ctx->partial_pe + (int64_t)ctx->pe_off[k] * 8);
+    }
+    enqueue_step(ctx, b, ctx->st[cur], s, want);
+    if (want) {
+      PhaseTimer t(ctx, 4);
+      for (int k = 0; k < ctx->nslab; ++k) {
+        const int nbg = (int)std::max<int64_t>(blocks_of(ctx->sizes[k].nnodes), 1);
+        launch_reduce_diag_slab(ctx->stream, ctx->partial, ctx->bb.item_start, ctx->sd[k].tile_off,
+                                ctx->sd[k].tile_off + ctx->sd[k].tg.ntiles, ctx->dacc + 8 * k,
+                                ctx->partial_pe + (int64_t)ctx->pe_off[k] * 8, nbg, ds.next() + k, s);
+      }
+    }
+    if ((rc = check_launch(ctx, "tiled step"))) return rc;
+    if (want && (rc = ds.advance(ctx->nslab))) return rc;
+    ++s;
+    ++since_bin;
+  }
+  if (probe_ms) {
+    (void)hipEventRecord(pb, ctx->stream);
+    rc = hip_check(ctx, hipEventSynchronize(pb), "probe sync");
+    if (!rc) rc = hip_check(ctx, hipEventElapsedTime(probe_ms, pa, pb), "probe time");
+    ctx->ev_pool.push_back(pa);
+    ctx->ev_pool.push_back(pb);
+    if (rc) return rc;
+  }
+  if (export_back) {
+    PhaseTimer t(ctx, 5);
+    for (int k = 0; k < ctx->nslab; ++k) launch_export(ctx->stream, nd, ctx->sd[k], ctx->st[cur], cps[k]);
+  }
+  ctx->last_nodes = ctx->n3[nsteps % 3];
+  ctx->last_step = nsteps - 1;
+  return check_launch(ctx, "export");
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t pic_num_nodes(const pic_grid_t *grid) {
+  Sizes s;
+  return grid_sizes(grid, &s, nullptr) ? s.nnodes : 0;
+}
+
+size_t pic_workspace_bytes_batch(const pic_grid_t *grids, int32_t nslab, const int64_t *max_n) {
+  if (!grids || !max_n || nslab < 1 || nslab > kMaxSlabs) return 0;
+  std::vector<pic_grid_t> g(nslab);
+  for (int k = 0; k < nslab; ++k) {
+    Sizes s;
+    if (!grid_sizes(&grids[k], &s, nullptr) || max_n[k] < 0 || grids[k].ndim != grids[0].ndim) return 0;
+    g[k] = normalised(grids[k]);
+  }
+  Layout L = make_layout(g.data(), nslab, max_n);
+  if (nslab > 1 && !L.tiled) return 0;
+  return L.total;
+}
+
+size_t pic_workspace_bytes(const pic_grid_t *grid, int64_t max_n) {
+  return pic_workspace_bytes_batch(grid, 1, &max_n);
+}
+
+int pic_init(pic_ctx_t **out, const pic_grid_t *grid, const pic_potential_t *pot, double dt, int64_t max_n,
+             void *ws, size_t ws_bytes, void *stream) {
+  return init_common(out, grid, 1, pot, dt, &max_n, ws, ws_bytes, stream);
+}
+
+int pic_init_batch(pic_ctx_t **out, const pic_grid_t *grids, int32_t nslab, const pic_potential_t *pot, double dt,
+                   const int64_t *max_n, void *ws, size_t ws_bytes, void *stream) {
+  return init_common(out, grids, nslab, pot, dt, max_n, ws, ws_bytes, stream);
 }
 
 int pic_destroy(pic_ctx_t *ctx) {
@@ -422,10 +825,18 @@ int pic_destroy(pic_ctx_t *ctx) {
   if (ctx->drift_ev) (void)hipEventSynchronize(ctx->drift_ev);
   if (ctx->drift_ev) (void)hipEventDestroy(ctx->drift_ev);
   if (ctx->h_drift) (void)hipHostFree(ctx->h_drift);
+  drop_graphs(ctx);
   harvest_events(ctx);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
   return PIC_OK;
+}
+
+const char *pic_last_error(const pic_ctx_t *ctx) { return ctx ? ctx->last_error.c_str() : "context is NULL"; }
+
+int pic_sync(pic_ctx_t *ctx) {
+  if (!ctx) return PIC_EINVAL;
+  return read_device_error(ctx);
 }
 
 int pic_set_timing(pic_ctx_t *ctx, int32_t on) {
@@ -447,27 +858,63 @@ int pic_get_timing(pic_ctx_t *ctx, pic_timing_t *out) {
     (void)hipMemcpyAsync(&h[2], ctx->bb.num_items, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
     int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "stream synchronize");
     if (rc) return rc;
-    out->drifters_last = h[(ctx->last_step + 1) & 1];
+    out->drifters_last = h[ctx->last_step & 1];
     out->items_last = h[2];
   }
   return PIC_OK;
 }
 
-const char *pic_last_error(const pic_ctx_t *ctx) {
-  return ctx ? ctx->last_error.c_str() : "context is NULL";
+int pic_set_tiling(pic_ctx_t *ctx, int32_t tile, int32_t halo, int32_t chunk, int32_t sort_every) {
+  if (!ctx) return PIC_EINVAL;
+  if (!ctx->tiled) return fail(ctx, PIC_EINVAL, "this grid uses the untiled path");
+  int lt = 0;
+  while ((1 << lt) < tile) ++lt;
+  if (tile < 1 || (1 << lt) != tile) return fail(ctx, PIC_EINVAL, "tile edge must be a power of two");
+  const int old_lt = ctx->lt, old_h = ctx->halo, old_c = ctx->chunk, old_s = ctx->sort_every;
+  int rc = apply_tiling(ctx, lt, halo, chunk, sort_every);
+  if (rc && rc != PIC_EHIP) {
+    std::string why = ctx->last_error;
+    apply_tiling(ctx, old_lt, old_h, old_c, old_s);  // keep the previous (valid) tiling
+    ctx->last_error = why;
+  }
+  return rc;
 }
 
-int pic_sync(pic_ctx_t *ctx) {
+int pic_get_tiling(pic_ctx_t *ctx, int32_t *tile, int32_t *halo, int32_t *chunk, int32_t *sort_every) {
   if (!ctx) return PIC_EINVAL;
-  return read_device_error(ctx);
+  if (!ctx->tiled) return fail(ctx, PIC_EINVAL, "this grid uses the untiled path");
+  if (tile) *tile = 1 << ctx->lt;
+  if (halo) *halo = ctx->halo;
+  if (chunk) *chunk = ctx->chunk;
+  if (sort_every) *sort_every = ctx->sort_every;
+  return PIC_OK;
+}
+
+int pic_set_path(pic_ctx_t *ctx, int32_t untiled) {
+  if (!ctx) return PIC_EINVAL;
+  if (untiled && ctx->nslab > 1) return fail(ctx, PIC_EINVAL, "batched contexts have only the tiled path");
+  ctx->force_untiled = untiled != 0;
+  return PIC_OK;
+}
+
+int pic_set_graph(pic_ctx_t *ctx, int32_t on) {
+  if (!ctx) return PIC_EINVAL;
+  ctx->use_graph = on != 0;
+  if (!on) drop_graphs(ctx);
+  return PIC_OK;
+}
+
+static int single_slab(pic_ctx_t *ctx) {
+  return ctx->nslab == 1 ? PIC_OK : fail(ctx, PIC_EINVAL, "this call needs a single-slab context");
 }
 
 int pic_deposit(pic_ctx_t *ctx, const pic_particles_t *p, int64_t *node_w) {
   if (!ctx) return PIC_EINVAL;
-  int rc = check_particles(ctx, p, false, true);
+  int rc = single_slab(ctx);
+  if (!rc) rc = check_particles(ctx, p, ctx->max_n[0], false, true);
   if (rc) return rc;
   if (!node_w) return fail(ctx, PIC_EINVAL, "node_w is NULL");
-  launch_fill64(ctx->stream, reinterpret_cast<long long *>(node_w), ctx->sz.nnodes);
+  launch_fill64(ctx->stream, reinterpret_cast<long long *>(node_w), ctx->sizes[0].nnodes);
   launch_deposit_atomic(ctx->stream, ctx->geo, ptrs(p), reinterpret_cast<long long *>(node_w), ctx->err);
   return check_launch(ctx, "deposit");
 }
@@ -475,7 +922,8 @@ int pic_deposit(pic_ctx_t *ctx, const pic_particles_t *p, int64_t *node_w) {
 int pic_force(pic_ctx_t *ctx, const pic_particles_t *p, const int64_t *node_w, float *force,
               pic_diag_t *pe_or_null) {
   if (!ctx) return PIC_EINVAL;
-  int rc = check_particles(ctx, p, false, false);
+  int rc = single_slab(ctx);
+  if (!rc) rc = check_particles(ctx, p, ctx->max_n[0], false, false);
   if (rc) return rc;
   if (!node_w) return fail(ctx, PIC_EINVAL, "node_w is NULL");
   if (p->n > 0 && !force) return fail(ctx, PIC_EINVAL, "force is NULL");
@@ -484,7 +932,7 @@ int pic_force(pic_ctx_t *ctx, const pic_particles_t *p, const int64_t *node_w, f
   launch_force(ctx->stream, ctx->geo, ctx->P, ptrs(p), ctx->dens, ctx->G, force, ctx->err);
   rc = check_launch(ctx, "force");
   if (rc || !pe_or_null) return rc;
-  int nb = launch_pe_nodes(ctx->stream, ctx->geo, ctx->dc, nw, ctx->partial_pe);
+  int nb = launch_pe_nodes(ctx->stream, ctx->geo, ctx->dcs[0], nw, ctx->partial_pe);
   launch_reduce_diag(ctx->stream, ctx->partial, 0, ctx->partial_pe, nb, ctx->diag_dev, 0);
   rc = check_launch(ctx, "potential energy");
   if (rc) return rc;
@@ -501,7 +949,8 @@ int pic_force(pic_ctx_t *ctx, const pic_particles_t *p, const int64_t *node_w, f
 
 int pic_kick(pic_ctx_t *ctx, pic_particles_t *p, const float *force, double frac) {
   if (!ctx) return PIC_EINVAL;
-  int rc = check_particles(ctx, p, true, false);
+  int rc = single_slab(ctx);
+  if (!rc) rc = check_particles(ctx, p, ctx->max_n[0], true, false);
   if (rc) return rc;
   if (p->n > 0 && !force) return fail(ctx, PIC_EINVAL, "force is NULL");
   if (!std::isfinite(frac)) return fail(ctx, PIC_EINVAL, "frac must be finite");
@@ -511,182 +960,100 @@ int pic_kick(pic_ctx_t *ctx, pic_particles_t *p, const float *force, double frac
 
 int pic_push(pic_ctx_t *ctx, pic_particles_t *p, const float *force) {
   if (!ctx) return PIC_EINVAL;
-  int rc = check_particles(ctx, p, true, false);
+  int rc = single_slab(ctx);
+  if (!rc) rc = check_particles(ctx, p, ctx->max_n[0], true, false);
   if (rc) return rc;
   if (p->n > 0 && !force) return fail(ctx, PIC_EINVAL, "force is NULL");
   launch_push(ctx->stream, ctx->geo, ctx->P, ptrs(p), force, ctx->err);
   return check_launch(ctx, "push");
 }
 
-namespace {
-
-struct DiagSink {
-  pic_ctx_t *ctx;
-  pic_diag_t *host;
-  int slot = 0;
-  int64_t copied = 0;
-  int flush() {
-    if (!slot) return PIC_OK;
-    int r = hip_check(ctx, hipMemcpyAsync(host + copied, ctx->diag_dev, sizeof(pic_diag_t) * slot,
-                                          hipMemcpyDeviceToHost, ctx->stream),
-                      "copy diagnostics");
-    if (r) return r;
-    r = hip_check(ctx, hipStreamSynchronize(ctx->stream), "stream synchronize");
-    copied += slot;
-    slot = 0;
-    return r;
-  }
-  pic_diag_t *next() { return ctx->diag_dev + slot; }
-  int advance() {
-    ++slot;
-    return slot == kDiagCap ? flush() : PIC_OK;
-  }
-};
-
-int step_untiled(pic_ctx_t *ctx, const PartPtrs &pp, int32_t nsteps, DiagSink &ds, int32_t diag_every) {
-  for (int32_t s = 0; s < nsteps; ++s) {
-    const bool want = ds.host && (s % diag_every) == 0;
-    {
-      PhaseTimer t(ctx, 0);
-      launch_fill64(ctx->stream, ctx->node, ctx->sz.nnodes);
-      launch_deposit_atomic(ctx->stream, ctx->geo, pp, ctx->node, ctx->err);
-    }
-    {
-      PhaseTimer t(ctx, 1);
-      launch_grid(ctx->stream, ctx->geo, ctx->node, ctx->dens, ctx->G);
-    }
-    int nbg = 0, nbp = 0;
-    if (want) {
-      PhaseTimer t(ctx, 4);
-      nbg = launch_pe_nodes(ctx->stream, ctx->geo, ctx->dc, ctx->node, ctx->partial_pe);
-    }
-    {
-      PhaseTimer t(ctx, 2);
-      nbp = launch_force_push(ctx->stream, ctx->geo, ctx->P, ctx->dc, pp, ctx->dens, ctx->G, ctx->partial, want,
-                              ctx->err);
-    }
-    if (want) {
-      PhaseTimer t(ctx, 4);
-      launch_reduce_diag(ctx->stream, ctx->partial, nbp, ctx->partial_pe, nbg, ds.next(), s);
-    }
-    int rc = check_launch(ctx, "step");
-    if (rc) return rc;
-    if (want && (rc = ds.advance())) return rc;
-  }
-  return PIC_OK;
-}
-
-int step_tiled(pic_ctx_t *ctx, const PartPtrs &pp, int32_t nsteps, DiagSink &ds, int32_t diag_every) {
-  const Geo &g = ctx->geo;
-  const int64_t n = pp.n;
-  int cur = 0;
-  const Store none{};
-  // bring the caller's particles into the binned store; stop on invalid input
-  {
-    PhaseTimer t(ctx, 5);
-    launch_bin(ctx->stream, g, ctx->tg, pp, none, ctx->st[cur], n, ctx->bb, true, ctx->err);
-  }
-  int rc = check_launch(ctx, "binning");
-  if (rc) return rc;
-  if ((rc = read_device_error(ctx))) return rc;
-  const int64_t max_items = max_items_now(ctx, n);
-  launch_fill64(ctx->stream, ctx->n3[0], ctx->sz.nnodes);
-  launch_fill64(ctx->stream, ctx->n3[1], ctx->sz.nnodes);
-  launch_fill32(ctx->stream, ctx->drift, 2);
-  {
-    PhaseTimer t(ctx, 0);
-    launch_deposit_tiled(ctx->stream, g, ctx->tg, ctx->st[cur], ctx->bb, (int)max_items, ctx->n3[0]);
-  }
-  int since_bin = 0;
-  ctx->drift_pending = false;
-  for (int32_t s = 0; s < nsteps; ++s) {
-    bool rebin = false;
-    if (ctx->sort_every > 0) {
-      rebin = s > 0 && s % ctx->sort_every == 0;
-    } else if (ctx->sort_every < 0 && s > 0 && s % kDriftCheck == 0) {
-      // adaptive: look at the drifter count copied kDriftCheck steps ago (long
-      // finished, so the host does not stall), then post a copy of this one
-      if (ctx->drift_pending) {
-        (void)hipEventSynchronize(ctx->drift_ev);
-        rebin = (int64_t)ctx->h_drift[0] * kDriftFraction > n || since_bin >= kMaxBinPeriod;
-      }
-      const int last = (s - 1) & 1;  // counter of the previous step
-      (void)hipMemcpyAsync(ctx->h_drift, ctx->drift + last, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
-      (void)hipEventRecord(ctx->drift_ev, ctx->stream);
-      ctx->drift_pending = true;
-    }
-    ++since_bin;
-    if (rebin) {
-      PhaseTimer t(ctx, 3);
-      launch_bin(ctx->stream, g, ctx->tg, pp, ctx->st[cur], ctx->st[1 - cur], n, ctx->bb, false, ctx->err);
-      cur = 1 - cur;
-      since_bin = 0;
-    }
-    const bool want = ds.host && (s % diag_every) == 0;
-    long long *Nc = ctx->n3[s % 3], *Nn = ctx->n3[(s + 1) % 3], *Nz = ctx->n3[(s + 2) % 3];
-    const Drift dr{ctx->drift + 2, ctx->drift + (s & 1), ctx->drift + ((s + 1) & 1), (int)ctx->items_cap};
-    int nbg = 0;
-    if (want) {
-      PhaseTimer t(ctx, 4);
-      nbg = launch_pe_nodes(ctx->stream, g, ctx->dc, Nc, ctx->partial_pe);
-    }
-    {
-      PhaseTimer t(ctx, 2);
-      launch_step_tiled(ctx->stream, g, ctx->P, ctx->dc, ctx->tg, ctx->st[cur], ctx->bb, (int)max_items, Nc, Nn,
-                        Nz, dr, ctx->partial, want, ctx->err);
-    }
-    {
-      PhaseTimer t(ctx, 6);
-      launch_drifters(ctx->stream, g, ctx->P, ctx->dc, ctx->tg, ctx->st[cur], Nc, Nn, dr, ctx->partial, want,
-                      ctx->err);
-    }
-    if (want) {
-      PhaseTimer t(ctx, 4);
-      launch_reduce_diag_dev(ctx->stream, ctx->partial, ctx->bb.num_items, dr, ctx->partial_pe, nbg, ds.next(), s);
-    }
-    if ((rc = check_launch(ctx, "tiled step"))) return rc;
-    if (want && (rc = ds.advance())) return rc;
-  }
-  {
-    PhaseTimer t(ctx, 5);
-    launch_export(ctx->stream, g, ctx->tg, ctx->st[cur], n, pp);
-  }
-  ctx->last_nodes = ctx->n3[nsteps % 3];
-  ctx->last_step = nsteps - 1;
-  return check_launch(ctx, "export");
-}
-
-}  // namespace
-
-int pic_step(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, pic_diag_t *diag, int32_t diag_every) {
+int pic_step_batch(pic_ctx_t *ctx, pic_particles_t *parts, int32_t nsteps, pic_diag_t *diag, int32_t diag_every) {
   if (!ctx) return PIC_EINVAL;
-  int rc = check_particles(ctx, p, true, true);
+  if (!parts) return fail(ctx, PIC_EINVAL, "particles is NULL");
+  int rc = PIC_OK;
+  for (int k = 0; k < ctx->nslab && !rc; ++k) rc = check_particles(ctx, &parts[k], ctx->max_n[k], true, true);
   if (rc) return rc;
   if (nsteps < 0) return fail(ctx, PIC_EINVAL, "nsteps is negative");
   if (diag && diag_every < 1) return fail(ctx, PIC_EINVAL, "diag_every must be >= 1");
-  DiagSink ds{ctx, diag};
-  const PartPtrs pp = ptrs(p);
+  const int64_t ndiag = diag ? (nsteps + diag_every - 1) / diag_every : 0;
+  DiagSink ds{ctx, diag, ndiag};
   ctx->last_nodes = nullptr;
-  rc = (ctx->tiled && !ctx->force_untiled) ? step_tiled(ctx, pp, nsteps, ds, diag_every)
-                                           : step_untiled(ctx, pp, nsteps, ds, diag_every);
+  if (ctx->tiled && !ctx->force_untiled) rc = step_tiled(ctx, parts, nsteps, ds, diag_every);
+  else rc = step_untiled(ctx, ptrs(&parts[0]), nsteps, ds, diag_every);
   if (rc) return rc;
   if (diag && (rc = ds.flush())) return rc;
+  return read_device_error(ctx);
+}
+
+int pic_step(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, pic_diag_t *diag, int32_t diag_every) {
+  if (!ctx) return PIC_EINVAL;
+  int rc = single_slab(ctx);
+  if (rc) return rc;
+  return pic_step_batch(ctx, p, nsteps, diag, diag_every);
+}
+
+int pic_autotune(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t probe_steps, pic_tuning_t *out) {
+  if (!ctx) return PIC_EINVAL;
+  if (!ctx->tiled) return fail(ctx, PIC_EINVAL, "this grid uses the untiled path");
+  if (!parts || probe_steps < 1) return fail(ctx, PIC_EINVAL, "need particles and probe_steps >= 1");
+  int rc = PIC_OK;
+  for (int k = 0; k < ctx->nslab && !rc; ++k) rc = check_particles(ctx, &parts[k], ctx->max_n[k], true, true);
+  if (rc) return rc;
+  const int nd = ctx->ndim;
+  const int halo = nd == 2 ? 2 : 1;
+  const int lts[3] = {nd == 2 ? 3 : 2, nd == 2 ? 4 : 3, nd == 2 ? 5 : 3};
+  const int chunks[4] = {2048, 4096, 8192, 16384};
+  const int old_lt = ctx->lt, old_h = ctx->halo, old_c = ctx->chunk, old_s = ctx->sort_every;
+  const bool old_timing = ctx->timing;
+  ctx->timing = false;
+  float best = 1e30f;
+  int best_lt = old_lt, best_c = old_c, tried = 0;
+  pic_particles_t *pp = const_cast<pic_particles_t *>(parts);
+  for (int i = 0; i < 3; ++i) {
+    if (i > 0 && lts[i] == lts[i - 1]) continue;
+    for (int c : chunks) {
+      if (apply_tiling(ctx, lts[i], halo, c, old_s)) continue;  // does not fit this grid
+      DiagSink ds{ctx, nullptr, 0};
+      float ms = 0.f;
+      // the store is scratch: the caller's arrays are read, never written
+      rc = step_tiled(ctx, pp, probe_steps, ds, 1, false, &ms);
+      if (rc) break;
+      ++tried;
+      if (ms < best) {
+        best = ms;
+        best_lt = lts[i];
+        best_c = c;
+      }
+    }
+    if (rc) break;
+  }
+  ctx->timing = old_timing;
+  ctx->last_nodes = nullptr;
+  int rc2 = apply_tiling(ctx, rc || !tried ? old_lt : best_lt, rc || !tried ? old_h : halo,
+                         rc || !tried ? old_c : best_c, old_s);
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (!tried) return fail(ctx, PIC_EINVAL, "no tiling fits this grid");
+  if (out) {
+    out->tile = 1 << best_lt;
+    out->halo = halo;
+    out->chunk = best_c;
+    out->candidates = tried;
+    out->ms_per_step = best / probe_steps;
+  }
   return read_device_error(ctx);
 }
 
 int pic_step_nodes(pic_ctx_t *ctx, int64_t *node_w) {
   if (!ctx || !node_w) return PIC_EINVAL;
   if (!ctx->last_nodes) return fail(ctx, PIC_EINVAL, "no tiled pic_step has run on this context");
-  return hip_check(ctx, hipMemcpyAsync(node_w, ctx->last_nodes, sizeof(long long) * (size_t)ctx->sz.nnodes,
+  return hip_check(ctx, hipMemcpyAsync(node_w, ctx->last_nodes, sizeof(long long) * (size_t)ctx->nnodes,
                                        hipMemcpyDeviceToDevice, ctx->stream),
                    "copy node sums");
 }
 
-int pic_set_path(pic_ctx_t *ctx, int32_t untiled) {
-  if (!ctx) return PIC_EINVAL;
-  ctx->force_untiled = untiled != 0;
-  return PIC_OK;
-}
+}  // extern "C"
 
 // ---------------------------------------------------------------------------
 // Host calibration of the attractive correction factor (FP64).  The slab's
@@ -741,8 +1108,8 @@ double simpson(const Slab &s, double a, double b, double fa, double fm, double f
 
 }  // namespace
 
-int pic_calibrate_catt(const pic_grid_t *grid, const pic_potential_t *pot, double n_solid, int32_t slab_layers,
-                       double *c_att, double *work) {
+extern "C" int pic_calibrate_catt(const pic_grid_t *grid, const pic_potential_t *pot, double n_solid,
+                                  int32_t slab_layers, double *c_att, double *work) {
   Sizes sz;
   if (!grid_sizes(grid, &sz, nullptr) || !pot || !(n_solid > 0) || slab_layers < 2 || !c_att) return PIC_EINVAL;
   Slab s{slab_layers, grid->h[grid->ndim - 1], n_solid, *pot};
@@ -778,5 +1145,3 @@ int pic_calibrate_catt(const pic_grid_t *grid, const pic_potential_t *pot, doubl
   if (work) *work = W;
   return PIC_OK;
 }
-
-}  // extern "C"

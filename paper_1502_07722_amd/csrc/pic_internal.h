@@ -44,25 +44,49 @@ struct TileGeo {
   int pmask[3];
 };
 
-struct Item {
-  int tile, start, end, pad;
+// One slab of a (possibly batched) context: grid, tiling, and where its
+// nodes, tiles and store slots start in the concatenated arrays.
+struct SlabDesc {
+  Geo g;
+  TileGeo tg;
+  int node_off;
+  int tile_off;
+  int part_off;
+  int part_n;
 };
 
-// Drifter list of the fused step: particle indices outside their tile window.
-// Two counters alternate between steps; a step clears the next one's.
+// Device-side slab tables, passed by value to the kernels.
+struct Batch {
+  const SlabDesc *slabs;  // [nslab]
+  const int *part_offs;   // [nslab + 1] first store slot of each slab
+  const int *tile_offs;   // [nslab + 1] first tile of each slab
+  int nslab;
+  int ntiles;
+  int nnodes;
+  int nparts;
+};
+
+struct Item {
+  int tile, start, end, slab;
+};
+
+// Drifter list of the fused step: particle slots outside their tile window,
+// and the persistent kernel's work counter.  Counters alternate between
+// steps; a step clears the next step's pair.
 constexpr int kDriftBlocks = 256;
 struct Drift {
-  int *list;          // [max_n]
-  int *count;         // this step's counter
-  int *count_next;    // next step's counter
-  int partial_offset; // diagnostics partials of the drifter kernel start here (in blocks)
+  int *list;        // [store capacity]
+  int *count;       // this step's drifter counter
+  int *count_next;  // next step's
+  int *work;        // this step's work-item counter
+  int *work_next;   // next step's
 };
 
 struct BinBufs {
   int *counts;      // [ntiles]
   int *starts;      // [ntiles + 1]
   int *cursors;     // [ntiles]
-  int *item_start;  // [ntiles]
+  int *item_start;  // [ntiles + 1]
   Item *items;      // [max_items]
   int *num_items;   // [1]
 };
@@ -84,19 +108,22 @@ void launch_reduce_diag(hipStream_t s, const double *part_p, int nblk_p, const d
 
 // tiled path (pic_tiled.hip)
 size_t window_lds_bytes(const TileGeo &tg, int ndim);
-void launch_bin(hipStream_t st, const Geo &g, const TileGeo &tg, const PartPtrs &cp, const Store &src,
-                const Store &dst, int64_t n, const BinBufs &b, bool import, uint32_t *err);
-void launch_export(hipStream_t st, const Geo &g, const TileGeo &tg, const Store &s, int64_t n, const PartPtrs &cp);
-void launch_deposit_tiled(hipStream_t st, const Geo &g, const TileGeo &tg, const Store &s, const BinBufs &b,
-                          int max_items, long long *N);
-void launch_step_tiled(hipStream_t st, const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
-                       const Store &s, const BinBufs &b, int max_items, const long long *Ncur, long long *Nnext,
+void launch_import(hipStream_t st, int ndim, const SlabDesc *sd_host, const PartPtrs *cp, int nslab,
+                   const BinBufs &bb, const Batch &b, int chunk, const Store &dst, uint32_t *err);
+void launch_rebin(hipStream_t st, int ndim, const BinBufs &bb, const Batch &b, int chunk, const Store &src,
+                  const Store &dst);
+void launch_export(hipStream_t st, int ndim, const SlabDesc &sd, const Store &s, const PartPtrs &cp);
+void launch_deposit_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Batch &b, const Store &s,
+                          const BinBufs &bb, int max_items, long long *N);
+void launch_step_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const DiagC &dc, const Batch &b,
+                       const Store &s, const BinBufs &bb, int grid, const long long *Ncur, long long *Nnext,
                        long long *Nclear, const Drift &dr, double *partial, bool diag, uint32_t *err);
-void launch_drifters(hipStream_t st, const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
-                     const Store &s, const long long *Ncur, long long *Nnext, const Drift &dr, double *partial,
-                     bool diag, uint32_t *err);
-void launch_reduce_diag_dev(hipStream_t st, const double *part_p, const int *nblk_p, const Drift &dr,
-                            const double *part_g, int nblk_g, pic_diag_t *out, int64_t step);
+void launch_drifters(hipStream_t st, int ndim, const Pot &P, const DiagC &dc, const Batch &b, const Store &s,
+                     const long long *Ncur, long long *Nnext, const Drift &dr, double *dacc, bool diag,
+                     uint32_t *err);
+void launch_reduce_diag_slab(hipStream_t st, const double *part_p, const int *item_start, int tile_lo, int tile_hi,
+                             double *dacc_k, const double *part_g, int nblk_g, pic_diag_t *out, int64_t step);
+int step_kernel_blocks_per_cu(int ndim, const TileGeo &tg);
 void launch_fill32(hipStream_t s, int *a, int64_t n);
 
 }  // namespace pic

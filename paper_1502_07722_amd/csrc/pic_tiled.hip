@@ -1,22 +1,25 @@
 // Tiled, fused time step of the PIC pair-potential cycle (arXiv 1502.07722)
 // for gfx950.
 //
-// Particles live in an internal structure-of-arrays store binned by tile (a
-// block of T^ND cells).  Within a tile the order is scrambled by a
-// multiplicative permutation so that the lanes of a wavefront hold particles
-// of different cells (few same-address LDS atomics in the deposit).  A work
-// item is a chunk of one tile's particles.  One kernel launch per step does,
-// per item:
+// A context advances one or more independent slabs (grids).  Particles live
+// in an internal structure-of-arrays store binned by tile (a block of T^ND
+// cells of one slab).  Within a tile the order is scrambled once, at import,
+// by a multiplicative permutation, so that the lanes of a wavefront hold
+// particles of different cells (few same-address LDS atomics in the deposit).
+// A work item is a chunk of one tile's particles.  Each step is one
+// persistent launch whose blocks pull items from an atomic counter; per item:
 //   1. stage the node densities of the tile plus a halo (window) from the
 //      int64 node sums of this step into LDS, and the cell-centred gradients;
 //   2. for each particle: gather density and gradient (LDS), eq. (1)-(3)
 //      force, leapfrog push, write the state back, and deposit the new
 //      position into an LDS int64 accumulator;
 //   3. flush the accumulator into the next step's node sums (global int64
-//      atomics), and clear the node buffer of the step after next.
-// Particles that drifted outside the window since the last binning take an
-// equivalent global path (same arithmetic, same bits).  The int64 sums make
-// the result independent of order, tiling and binning period.
+//      atomics); every block also clears its share of the node buffer of the
+//      step after next.
+// Particles that drifted outside their window since the last binning go to a
+// list that a second small kernel advances through the global node sums with
+// the same arithmetic (same bits).  The int64 sums make the result
+// independent of order, tiling, binning period and batching.
 #include "pic_internal.h"
 
 namespace pic {
@@ -103,136 +106,6 @@ __device__ __forceinline__ int scramble(int r, int L) {
   if ((uint32_t)L % P == 0) P = primes[1];
   if ((uint32_t)L % P == 0) P = primes[2];
   return (int)(((uint64_t)(uint32_t)r * P) % (uint64_t)L);
-}
-
-// ---------------------------------------------------------------------------
-// Binning: histogram by tile, scan, items, scatter.
-// ---------------------------------------------------------------------------
-// Source of a binning pass: the caller's arrays (linear cells, validated) or
-// the internal store (packed cells).
-template <int ND, bool IMPORT>
-__device__ __forceinline__ int source_tile(const Geo &g, const TileGeo &tg, const PartPtrs &cp, const Store &s,
-                                           int64_t p, int idx[3], uint32_t *err) {
-  if (IMPORT) {
-    int c = cp.cell[p];
-    float f0 = cp.off[p], f1 = cp.off[cp.n + p], f2 = ND == 3 ? cp.off[2 * cp.n + p] : 0.0f;
-    int W = cp.wq[p];
-    uint32_t e = 0;
-    if (c < 0 || c >= g.ncells) e |= ERR_RANGE;
-    if (!(f0 >= 0.0f && f0 < 1.0f) || !(f1 >= 0.0f && f1 < 1.0f)) e |= ERR_RANGE;
-    if (ND == 3 && !(f2 >= 0.0f && f2 < 1.0f)) e |= ERR_RANGE;
-    if (W < 0) e |= ERR_WEIGHT;
-    if (e) {
-      if (err) atomicOr(err, e);
-      return -1;
-    }
-    decode_cell<ND>(g, c, idx);
-  } else {
-    unpack_cell<ND>(tg, s.pc[p], idx);
-  }
-  return tile_of<ND>(tg, idx);
-}
-
-template <int ND, bool IMPORT>
-__global__ void __launch_bounds__(256) k_tile_hist(Geo g, TileGeo tg, PartPtrs cp, Store s, int64_t n,
-                                                   int *__restrict__ counts, uint32_t *__restrict__ err) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int idx[3];
-  int t = p < n ? source_tile<ND, IMPORT>(g, tg, cp, s, p, idx, err) : -1;
-  wave_rank(counts, t < 0 ? 0 : t, t >= 0);
-}
-
-// Single block: exclusive scan of tile counts -> starts; item counts; cursors.
-__global__ void __launch_bounds__(1024) k_tile_scan(int ntiles, int chunk, const int *__restrict__ counts,
-                                                    int *__restrict__ starts, int *__restrict__ item_start,
-                                                    int *__restrict__ cursors, int *__restrict__ num_items) {
-  __shared__ long long s_a[1024], s_b[1024];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int per = (ntiles + nt - 1) / nt;
-  const int lo = tid * per, hi = min(ntiles, lo + per);
-  long long a = 0, b = 0;
-  for (int t = lo; t < hi; ++t) {
-    a += counts[t];
-    b += (counts[t] + chunk - 1) / chunk;
-  }
-  s_a[tid] = a;
-  s_b[tid] = b;
-  __syncthreads();
-  for (int o = 1; o < nt; o <<= 1) {  // Hillis-Steele inclusive scan
-    long long va = tid >= o ? s_a[tid - o] : 0, vb = tid >= o ? s_b[tid - o] : 0;
-    __syncthreads();
-    s_a[tid] += va;
-    s_b[tid] += vb;
-    __syncthreads();
-  }
-  long long ra = tid ? s_a[tid - 1] : 0, rb = tid ? s_b[tid - 1] : 0;
-  for (int t = lo; t < hi; ++t) {
-    starts[t] = (int)ra;
-    item_start[t] = (int)rb;
-    cursors[t] = 0;
-    ra += counts[t];
-    rb += (counts[t] + chunk - 1) / chunk;
-  }
-  if (tid == nt - 1) {
-    starts[ntiles] = (int)s_a[nt - 1];
-    *num_items = (int)s_b[nt - 1];
-  }
-}
-
-__global__ void __launch_bounds__(256) k_tile_items(int ntiles, int chunk, const int *__restrict__ counts,
-                                                    const int *__restrict__ starts,
-                                                    const int *__restrict__ item_start, Item *__restrict__ items) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ntiles) return;
-  int c = counts[t], s = starts[t], b = item_start[t];
-  for (int k = 0; k * chunk < c; ++k) items[b + k] = Item{t, s + k * chunk, s + min(c, (k + 1) * chunk), 0};
-}
-
-template <int ND, bool IMPORT>
-__global__ void __launch_bounds__(256) k_tile_scatter(Geo g, TileGeo tg, PartPtrs cp, Store s, Store d, int64_t n,
-                                                      const int *__restrict__ counts,
-                                                      const int *__restrict__ starts, int *__restrict__ cursors,
-                                                      uint32_t *__restrict__ err) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int idx[3];
-  int t = p < n ? source_tile<ND, IMPORT>(g, tg, cp, s, p, idx, nullptr) : -1;
-  int r = wave_rank(cursors, t < 0 ? 0 : t, t >= 0);
-  if (t < 0) return;
-  // import scrambles each tile once; later re-binnings keep the (already
-  // scrambled) order of their input runs and write coalesced
-  int64_t q = starts[t] + (IMPORT ? scramble(r, counts[t]) : r);
-  if (IMPORT) {
-    d.pc[q] = pack_cell<ND>(tg, idx);
-#pragma unroll
-    for (int k = 0; k < ND; ++k) d.off[k * d.cap + q] = cp.off[k * cp.n + p];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) d.vel[k * d.cap + q] = cp.vel[k * cp.n + p];
-    d.wq[q] = cp.wq[p];
-    d.oidx[q] = (int)p;
-  } else {
-    d.pc[q] = s.pc[p];
-#pragma unroll
-    for (int k = 0; k < ND; ++k) d.off[k * d.cap + q] = s.off[k * s.cap + p];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) d.vel[k * d.cap + q] = s.vel[k * s.cap + p];
-    d.wq[q] = s.wq[p];
-    d.oidx[q] = s.oidx[p];
-  }
-  (void)err;
-}
-
-template <int ND>
-__global__ void __launch_bounds__(256) k_export(Geo g, TileGeo tg, Store s, int64_t n, PartPtrs cp) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  int o = s.oidx[p];
-  int idx[3];
-  unpack_cell<ND>(tg, s.pc[p], idx);
-  cp.cell[o] = encode_cell<ND>(g, idx);
-#pragma unroll
-  for (int k = 0; k < ND; ++k) cp.off[k * cp.n + o] = s.off[k * s.cap + p];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) cp.vel[k * cp.n + o] = s.vel[k * s.cap + p];
 }
 
 // ---------------------------------------------------------------------------
@@ -396,7 +269,6 @@ __device__ __forceinline__ bool in_window(const Geo &g, const Window &w, const i
   return ok;
 }
 
-constexpr int kMaxChunk = 32768;  // items are at most this many particles (outlier bitmask in LDS)
 
 // Per-array views of the store with 32-bit element offsets (the tiled path
 // keeps max_n < 2^30, so byte offsets fit in 32 bits).
@@ -488,6 +360,176 @@ __device__ __forceinline__ void advance_particle(const Geo &g, const Pot &P, con
   deposit_shares<ND>((uint32_t)W, f, tq);
 }
 
+// ---------------------------------------------------------------------------
+// Slab tables: a context advances one or more independent slabs (grids) in the
+// same launches.  Store slots, tiles and node arrays of the slabs are
+// concatenated; small offset tables map a slot or tile back to its slab.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_slab(const int *__restrict__ offs, int nslab, int x) {
+  int lo = 0, hi = nslab - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (offs[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Binning: histogram by tile, scan, items, scatter.
+// ---------------------------------------------------------------------------
+// Import: the caller's arrays of one slab (linear cells, validated).
+template <int ND>
+__device__ __forceinline__ int import_tile(const SlabDesc &sd, const PartPtrs &cp, int64_t p, int idx[3],
+                                           uint32_t *err) {
+  const Geo &g = sd.g;
+  int c = cp.cell[p];
+  float f0 = cp.off[p], f1 = cp.off[cp.n + p], f2 = ND == 3 ? cp.off[2 * cp.n + p] : 0.0f;
+  int W = cp.wq[p];
+  uint32_t e = 0;
+  if (c < 0 || c >= g.ncells) e |= ERR_RANGE;
+  if (!(f0 >= 0.0f && f0 < 1.0f) || !(f1 >= 0.0f && f1 < 1.0f)) e |= ERR_RANGE;
+  if (ND == 3 && !(f2 >= 0.0f && f2 < 1.0f)) e |= ERR_RANGE;
+  if (W < 0) e |= ERR_WEIGHT;
+  if (e) {
+    if (err) atomicOr(err, e);
+    return -1;
+  }
+  decode_cell<ND>(g, c, idx);
+  return sd.tile_off + tile_of<ND>(sd.tg, idx);
+}
+
+template <int ND>
+__global__ void __launch_bounds__(256) k_import_hist(SlabDesc sd, PartPtrs cp, int *__restrict__ counts,
+                                                     uint32_t *__restrict__ err) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int idx[3];
+  int t = p < cp.n ? import_tile<ND>(sd, cp, p, idx, err) : -1;
+  wave_rank(counts, t < 0 ? 0 : t, t >= 0);
+}
+
+template <int ND>
+__global__ void __launch_bounds__(256) k_import_scatter(SlabDesc sd, PartPtrs cp, Store d,
+                                                        const int *__restrict__ counts,
+                                                        const int *__restrict__ starts, int *__restrict__ cursors) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int idx[3];
+  int t = p < cp.n ? import_tile<ND>(sd, cp, p, idx, nullptr) : -1;
+  int r = wave_rank(cursors, t < 0 ? 0 : t, t >= 0);
+  if (t < 0) return;
+  const int64_t q = starts[t] + scramble(r, counts[t]);  // scrambled once, at import
+  d.pc[q] = pack_cell<ND>(sd.tg, idx);
+#pragma unroll
+  for (int k = 0; k < ND; ++k) d.off[k * d.cap + q] = cp.off[k * cp.n + p];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) d.vel[k * d.cap + q] = cp.vel[k * cp.n + p];
+  d.wq[q] = cp.wq[p];
+  d.oidx[q] = (int)p;
+}
+
+// Re-binning of the store: the slab of a slot comes from the slot ranges.
+template <int ND>
+__device__ __forceinline__ int store_tile(const Batch &b, const Store &s, int p, int idx[3]) {
+  const int k = find_slab(b.part_offs, b.nslab, p);
+  const TileGeo tg = b.slabs[k].tg;
+  unpack_cell<ND>(tg, s.pc[p], idx);
+  return b.slabs[k].tile_off + tile_of<ND>(tg, idx);
+}
+
+template <int ND>
+__global__ void __launch_bounds__(256) k_rebin_hist(Batch b, Store s, int *__restrict__ counts) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  int idx[3];
+  int t = p < b.nparts ? store_tile<ND>(b, s, p, idx) : -1;
+  wave_rank(counts, t < 0 ? 0 : t, t >= 0);
+}
+
+template <int ND>
+__global__ void __launch_bounds__(256) k_rebin_scatter(Batch b, Store s, Store d, const int *__restrict__ starts,
+                                                       int *__restrict__ cursors) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  int idx[3];
+  int t = p < b.nparts ? store_tile<ND>(b, s, p, idx) : -1;
+  // ranks keep the (already scrambled) order of each wavefront's run: coalesced writes
+  int r = wave_rank(cursors, t < 0 ? 0 : t, t >= 0);
+  if (t < 0) return;
+  const int64_t q = starts[t] + r;
+  d.pc[q] = s.pc[p];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) d.off[k * d.cap + q] = s.off[k * s.cap + p];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) d.vel[k * d.cap + q] = s.vel[k * s.cap + p];
+  d.wq[q] = s.wq[p];
+  d.oidx[q] = s.oidx[p];
+}
+
+// Single block: exclusive scans of tile counts -> starts, and of items per
+// tile -> item_start (both with a final total entry); clears the cursors.
+__global__ void __launch_bounds__(1024) k_tile_scan(int ntiles, int chunk, const int *__restrict__ counts,
+                                                    int *__restrict__ starts, int *__restrict__ item_start,
+                                                    int *__restrict__ cursors, int *__restrict__ num_items) {
+  __shared__ long long s_a[1024], s_b[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int per = (ntiles + nt - 1) / nt;
+  const int lo = tid * per, hi = min(ntiles, lo + per);
+  long long a = 0, b = 0;
+  for (int t = lo; t < hi; ++t) {
+    a += counts[t];
+    b += (counts[t] + chunk - 1) / chunk;
+  }
+  s_a[tid] = a;
+  s_b[tid] = b;
+  __syncthreads();
+  for (int o = 1; o < nt; o <<= 1) {  // Hillis-Steele inclusive scan
+    long long va = tid >= o ? s_a[tid - o] : 0, vb = tid >= o ? s_b[tid - o] : 0;
+    __syncthreads();
+    s_a[tid] += va;
+    s_b[tid] += vb;
+    __syncthreads();
+  }
+  long long ra = tid ? s_a[tid - 1] : 0, rb = tid ? s_b[tid - 1] : 0;
+  for (int t = lo; t < hi; ++t) {
+    starts[t] = (int)ra;
+    item_start[t] = (int)rb;
+    cursors[t] = 0;
+    ra += counts[t];
+    rb += (counts[t] + chunk - 1) / chunk;
+  }
+  if (tid == nt - 1) {
+    starts[ntiles] = (int)s_a[nt - 1];
+    item_start[ntiles] = (int)s_b[nt - 1];
+    *num_items = (int)s_b[nt - 1];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_tile_items(Batch b, int chunk, const int *__restrict__ counts,
+                                                    const int *__restrict__ starts,
+                                                    const int *__restrict__ item_start, Item *__restrict__ items) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= b.ntiles) return;
+  const int slab = find_slab(b.tile_offs, b.nslab, t);
+  int c = counts[t], s = starts[t], i0 = item_start[t];
+  for (int k = 0; k * chunk < c; ++k) items[i0 + k] = Item{t, s + k * chunk, s + min(c, (k + 1) * chunk), slab};
+}
+
+template <int ND>
+__global__ void __launch_bounds__(256) k_export(SlabDesc sd, Store s, PartPtrs cp) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= sd.part_n) return;
+  const int64_t p = sd.part_off + k;
+  const int o = s.oidx[p];
+  int idx[3];
+  unpack_cell<ND>(sd.tg, s.pc[p], idx);
+  cp.cell[o] = encode_cell<ND>(sd.g, idx);
+#pragma unroll
+  for (int d = 0; d < ND; ++d) cp.off[d * cp.n + o] = s.off[d * s.cap + p];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) cp.vel[d * cp.n + o] = s.vel[d * s.cap + p];
+}
+
+// ---------------------------------------------------------------------------
+// The fused step kernel
+// ---------------------------------------------------------------------------
 // Wave-aggregated append of the active lanes' values to a global list.
 __device__ __forceinline__ void wave_append(int *list, int *count, int value, bool active) {
   const int lane = threadIdx.x & 63;
@@ -582,81 +624,106 @@ __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC
   }
 }
 
+// Persistent: a fixed grid pulls work items (chunks of one tile of one slab)
+// from an atomic counter until the step's items are done.  Every block also
+// clears its share of the node buffer two steps ahead.
 template <int ND, bool DIAG>
-__global__ void __launch_bounds__(256) k_step_tiled(Geo g, Pot P, DiagC dc, TileGeo tg, Store s,
+__global__ void __launch_bounds__(256) k_step_tiled(Pot P, DiagC dc, Batch b, Store s,
                                                     const Item *__restrict__ items,
                                                     const int *__restrict__ num_items,
                                                     const long long *__restrict__ Ncur,
                                                     unsigned long long *__restrict__ Nnext,
-                                                    long long *__restrict__ Nclear, int *__restrict__ olist,
-                                                    int *__restrict__ ocount, int *__restrict__ ocount_next,
+                                                    long long *__restrict__ Nclear, Drift dr,
                                                     double *__restrict__ partial, uint32_t *__restrict__ err) {
   extern __shared__ __align__(16) unsigned char smem[];
-  clear_share(Nclear, g.nnodes);
-  if (blockIdx.x == 0 && threadIdx.x == 0) *ocount_next = 0;  // next step's drifter count
-  if ((int)blockIdx.x >= *num_items) return;
-  const Item it = items[blockIdx.x];
-  const Window w = make_window<ND>(tg, it.tile);
-  unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
-  float *dens = reinterpret_cast<float *>(acc + w.nW);
-  float *Gs = dens + w.nW;
-  stage_window<ND>(g, w, Ncur, dens, Gs, acc);  // ends with a barrier
-
-  // interior windows: no wall and no periodic seam within reach of any
-  // particle the item loop handles
-  bool interior = true;
-#pragma unroll
-  for (int d = 0; d < ND; ++d) interior = interior && w.o[d] >= 0 && w.o[d] + w.wn[d] <= g.n[d] + 1;
-  double acc6[6] = {0, 0, 0, 0, 0, 0};
-  uint32_t e_all = 0;
+  __shared__ int s_item;
+  clear_share(Nclear, b.nnodes);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *dr.count_next = 0;  // the next step's drifter count and work counter
+    *dr.work_next = 0;
+  }
+  const int nit = *num_items;
   const StoreView sv = view_of(s);
-  if (interior)
-    run_item<ND, DIAG, true>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nnext, olist, ocount, e_all, acc6);
-  else
-    run_item<ND, DIAG, false>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nnext, olist, ocount, e_all, acc6);
+  uint32_t e_all = 0;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(dr.work, 1);
+    __syncthreads();
+    const int bi = __builtin_amdgcn_readfirstlane(s_item);
+    if (bi >= nit) break;
+    const Item it = items[bi];
+    const SlabDesc &sd = b.slabs[it.slab];
+    const Geo g = sd.g;
+    const TileGeo tg = sd.tg;
+    const Window w = make_window<ND>(tg, it.tile - sd.tile_off);
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
+    float *dens = reinterpret_cast<float *>(acc + w.nW);
+    float *Gs = dens + w.nW;
+    unsigned long long *Nn = Nnext + sd.node_off;
+    stage_window<ND>(g, w, Ncur + sd.node_off, dens, Gs, acc);  // ends with a barrier
+    // interior windows: no wall and no periodic seam within reach of any
+    // particle the item loop handles
+    bool interior = true;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) interior = interior && w.o[d] >= 0 && w.o[d] + w.wn[d] <= g.n[d] + 1;
+    double acc6[6] = {0, 0, 0, 0, 0, 0};
+    if (interior)
+      run_item<ND, DIAG, true>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dr.list, dr.count, e_all, acc6);
+    else
+      run_item<ND, DIAG, false>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dr.list, dr.count, e_all, acc6);
+    __syncthreads();
+    flush_window<ND>(g, w, acc, Nn);
+    if (DIAG) block_reduce_store<6>(acc6, partial + (int64_t)bi * 8);
+    __syncthreads();  // LDS and s_item are reused by the next item
+  }
   if (e_all) atomicOr(err, e_all);
-  __syncthreads();
-  flush_window<ND>(g, w, acc, Nnext);
-  if (DIAG) block_reduce_store<6>(acc6, partial + (int64_t)blockIdx.x * 8);
 }
 
 // Drifters (particles outside their tile window since the last binning):
-// the same cycle through the global node sums.
+// the same cycle through the global node sums of their slab.
 template <int ND, bool DIAG>
-__global__ void __launch_bounds__(256) k_outliers(Geo g, Pot P, DiagC dc, TileGeo tg, Store s,
-                                                  const int *__restrict__ olist, const int *__restrict__ ocount,
+__global__ void __launch_bounds__(256) k_outliers(Pot P, DiagC dc, Batch b, Store s, Drift dr,
                                                   const long long *__restrict__ Ncur,
                                                   unsigned long long *__restrict__ Nnext,
-                                                  double *__restrict__ partial, uint32_t *__restrict__ err) {
-  const int n = *ocount;
-  double acc6[6] = {0, 0, 0, 0, 0, 0};
+                                                  double *__restrict__ dacc, uint32_t *__restrict__ err) {
+  const int n = *dr.count;
   uint32_t e_all = 0;
   const StoreView sv = view_of(s);
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-    const int p = olist[k];
+    const int p = dr.list[k];
+    const int slab = find_slab(b.part_offs, b.nslab, p);
+    const SlabDesc &sd = b.slabs[slab];
+    const Geo g = sd.g;
+    const TileGeo tg = sd.tg;
     PState q;
     load_state<ND, DIAG>(sv, p, true, q);
     int idx[3];
     unpack_cell<ND>(tg, q.pc, idx);
     float nh, Gp[3];
-    gather_nodes_global<ND>(g, Ncur, idx, q.f, nh, Gp);
+    gather_nodes_global<ND>(g, Ncur + sd.node_off, idx, q.f, nh, Gp);
     uint32_t tq[8];
+    double acc6[6] = {0, 0, 0, 0, 0, 0};
     advance_particle<ND, DIAG, false>(g, P, dc, tg, sv, p, q.pc, idx, q.f, q.v, q.W, nh, Gp, tq, e_all, acc6);
-    deposit_global<ND>(g, Nnext, idx, tq);
+    deposit_global<ND>(g, Nnext + sd.node_off, idx, tq);
+    if (DIAG)
+#pragma unroll
+      for (int i = 0; i < 6; ++i) atomicAdd(&dacc[slab * 8 + i], acc6[i]);
   }
   if (e_all) atomicOr(err, e_all);
-  if (DIAG) block_reduce_store<6>(acc6, partial + (int64_t)blockIdx.x * 8);
 }
 
-// Deposit only (the node sums of the current positions), same tiling.
+// Node sums of the current positions (the first step's input), same tiling.
 template <int ND>
-__global__ void __launch_bounds__(256) k_deposit_tiled(Geo g, TileGeo tg, Store s, const Item *__restrict__ items,
+__global__ void __launch_bounds__(256) k_deposit_tiled(Batch b, Store s, const Item *__restrict__ items,
                                                        const int *__restrict__ num_items,
                                                        unsigned long long *__restrict__ N) {
   extern __shared__ __align__(16) unsigned char smem[];
   if ((int)blockIdx.x >= *num_items) return;
   const Item it = items[blockIdx.x];
-  const Window w = make_window<ND>(tg, it.tile);
+  const SlabDesc &sd = b.slabs[it.slab];
+  const Geo g = sd.g;
+  const TileGeo tg = sd.tg;
+  const Window w = make_window<ND>(tg, it.tile - sd.tile_off);
+  unsigned long long *Ns = N + sd.node_off;
   unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
   for (int k = threadIdx.x; k < w.nW; k += blockDim.x) acc[k] = 0ull;
   __syncthreads();
@@ -674,26 +741,28 @@ __global__ void __launch_bounds__(256) k_deposit_tiled(Geo g, TileGeo tg, Store 
           atomicAdd(&acc[win_node<ND>(w, l[0] + (k & 1), l[1] + ((k >> 1) & 1), ND == 3 ? l[2] + ((k >> 2) & 1) : 0)],
                     (unsigned long long)tq[k]);
     } else {
-      deposit_global<ND>(g, N, idx, tq);
+      deposit_global<ND>(g, Ns, idx, tq);
     }
   }
   __syncthreads();
-  flush_window<ND>(g, w, acc, N);
+  flush_window<ND>(g, w, acc, Ns);
 }
 
-__global__ void __launch_bounds__(256) k_reduce_diag_dev(const double *__restrict__ part_p,
-                                                         const int *__restrict__ nblk_p_dev,
-                                                         const double *__restrict__ part_o, int nblk_o,
-                                                         const double *__restrict__ part_g, int nblk_g,
-                                                         pic_diag_t *__restrict__ out, int64_t step) {
-  const int nblk_p = *nblk_p_dev;
+// One slab's diagnostics: its items' block partials (a contiguous item range),
+// its drifters' accumulator (cleared after reading) and its node energy partials.
+__global__ void __launch_bounds__(256) k_reduce_diag_slab(const double *__restrict__ part_p,
+                                                          const int *__restrict__ item_start, int tile_lo,
+                                                          int tile_hi, double *__restrict__ dacc_k,
+                                                          const double *__restrict__ part_g, int nblk_g,
+                                                          pic_diag_t *__restrict__ out, int64_t step) {
+  const int lo = item_start[tile_lo], hi = item_start[tile_hi];
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int b = threadIdx.x; b < nblk_p; b += blockDim.x)
+  for (int b = lo + threadIdx.x; b < hi; b += blockDim.x)
 #pragma unroll
     for (int i = 0; i < 6; ++i) acc[i] += part_p[(int64_t)b * 8 + i];
-  for (int b = threadIdx.x; b < nblk_o; b += blockDim.x)
+  if (threadIdx.x == 0)
 #pragma unroll
-    for (int i = 0; i < 6; ++i) acc[i] += part_o[(int64_t)b * 8 + i];
+    for (int i = 0; i < 6; ++i) acc[i] += dacc_k[i];
   for (int b = threadIdx.x; b < nblk_g; b += blockDim.x) acc[6] += part_g[(int64_t)b * 8];
   __shared__ double res[8];
   block_reduce_store<7>(acc, res);
@@ -707,6 +776,8 @@ __global__ void __launch_bounds__(256) k_reduce_diag_dev(const double *__restric
     out->bond = res[5];
     out->pe = res[6];
     out->step = step;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) dacc_k[i] = 0.0;
   }
 }
 
@@ -725,92 +796,90 @@ size_t window_lds_bytes(const TileGeo &tg, int ndim) {
   return nW * 8 + nW * 4 + nC * 4 * ndim;
 }
 
-void launch_bin(hipStream_t st, const Geo &g, const TileGeo &tg, const PartPtrs &cp, const Store &src,
-                const Store &dst, int64_t n, const BinBufs &b, bool import, uint32_t *err) {
-  launch_fill32(st, b.counts, tg.ntiles);
-  if (n > 0) {
-    if (g.ndim == 2) {
-      if (import) k_tile_hist<2, true><<<nblk(n), 256, 0, st>>>(g, tg, cp, src, n, b.counts, err);
-      else k_tile_hist<2, false><<<nblk(n), 256, 0, st>>>(g, tg, cp, src, n, b.counts, err);
-    } else {
-      if (import) k_tile_hist<3, true><<<nblk(n), 256, 0, st>>>(g, tg, cp, src, n, b.counts, err);
-      else k_tile_hist<3, false><<<nblk(n), 256, 0, st>>>(g, tg, cp, src, n, b.counts, err);
-    }
-  }
-  k_tile_scan<<<1, 1024, 0, st>>>(tg.ntiles, tg.chunk, b.counts, b.starts, b.item_start, b.cursors, b.num_items);
-  k_tile_items<<<nblk(tg.ntiles), 256, 0, st>>>(tg.ntiles, tg.chunk, b.counts, b.starts, b.item_start, b.items);
-  if (n > 0) {
-    if (g.ndim == 2) {
-      if (import)
-        k_tile_scatter<2, true><<<nblk(n), 256, 0, st>>>(g, tg, cp, src, dst, n, b.counts, b.starts, b.cursors, err);
-      else
-        k_tile_scatter<2, false><<<nblk(n), 256, 0, st>>>(g, tg, cp, src, dst, n, b.counts, b.starts, b.cursors, err);
-    } else {
-      if (import)
-        k_tile_scatter<3, true><<<nblk(n), 256, 0, st>>>(g, tg, cp, src, dst, n, b.counts, b.starts, b.cursors, err);
-      else
-        k_tile_scatter<3, false><<<nblk(n), 256, 0, st>>>(g, tg, cp, src, dst, n, b.counts, b.starts, b.cursors, err);
-    }
-  }
+#define PIC_ND(nd_, ...)    \
+  do {                      \
+    if ((nd_) == 2) {       \
+      constexpr int ND = 2; \
+      __VA_ARGS__;          \
+    } else {                \
+      constexpr int ND = 3; \
+      __VA_ARGS__;          \
+    }                       \
+  } while (0)
+
+void launch_import(hipStream_t st, int ndim, const SlabDesc *sd_host, const PartPtrs *cp, int nslab,
+                   const BinBufs &bb, const Batch &b, int chunk, const Store &dst, uint32_t *err) {
+  launch_fill32(st, bb.counts, b.ntiles);
+  for (int k = 0; k < nslab; ++k)
+    if (cp[k].n > 0) PIC_ND(ndim, (k_import_hist<ND><<<nblk(cp[k].n), 256, 0, st>>>(sd_host[k], cp[k], bb.counts, err)));
+  k_tile_scan<<<1, 1024, 0, st>>>(b.ntiles, chunk, bb.counts, bb.starts, bb.item_start, bb.cursors, bb.num_items);
+  k_tile_items<<<nblk(b.ntiles), 256, 0, st>>>(b, chunk, bb.counts, bb.starts, bb.item_start, bb.items);
+  for (int k = 0; k < nslab; ++k)
+    if (cp[k].n > 0)
+      PIC_ND(ndim, (k_import_scatter<ND><<<nblk(cp[k].n), 256, 0, st>>>(sd_host[k], cp[k], dst, bb.counts, bb.starts,
+                                                                        bb.cursors)));
 }
 
-void launch_export(hipStream_t st, const Geo &g, const TileGeo &tg, const Store &s, int64_t n, const PartPtrs &cp) {
-  if (n <= 0) return;
-  if (g.ndim == 2) k_export<2><<<nblk(n), 256, 0, st>>>(g, tg, s, n, cp);
-  else k_export<3><<<nblk(n), 256, 0, st>>>(g, tg, s, n, cp);
+void launch_rebin(hipStream_t st, int ndim, const BinBufs &bb, const Batch &b, int chunk, const Store &src,
+                  const Store &dst) {
+  launch_fill32(st, bb.counts, b.ntiles);
+  if (b.nparts > 0) PIC_ND(ndim, (k_rebin_hist<ND><<<nblk(b.nparts), 256, 0, st>>>(b, src, bb.counts)));
+  k_tile_scan<<<1, 1024, 0, st>>>(b.ntiles, chunk, bb.counts, bb.starts, bb.item_start, bb.cursors, bb.num_items);
+  k_tile_items<<<nblk(b.ntiles), 256, 0, st>>>(b, chunk, bb.counts, bb.starts, bb.item_start, bb.items);
+  if (b.nparts > 0)
+    PIC_ND(ndim, (k_rebin_scatter<ND><<<nblk(b.nparts), 256, 0, st>>>(b, src, dst, bb.starts, bb.cursors)));
 }
 
-void launch_deposit_tiled(hipStream_t st, const Geo &g, const TileGeo &tg, const Store &s, const BinBufs &b,
-                          int max_items, long long *N) {
+void launch_export(hipStream_t st, int ndim, const SlabDesc &sd, const Store &s, const PartPtrs &cp) {
+  if (sd.part_n <= 0) return;
+  PIC_ND(ndim, (k_export<ND><<<nblk(sd.part_n), 256, 0, st>>>(sd, s, cp)));
+}
+
+void launch_deposit_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Batch &b, const Store &s,
+                          const BinBufs &bb, int max_items, long long *N) {
   if (max_items <= 0) return;
-  size_t lds = 0;
-  {
-    size_t nW = 1;
-    for (int d = 0; d < g.ndim; ++d) nW *= (size_t)(1 << tg.lt[d]) + 2 * tg.H + 3;
-    lds = nW * 8;
-  }
-  if (g.ndim == 2)
-    k_deposit_tiled<2><<<max_items, 256, lds, st>>>(g, tg, s, b.items, b.num_items, (unsigned long long *)N);
-  else
-    k_deposit_tiled<3><<<max_items, 256, lds, st>>>(g, tg, s, b.items, b.num_items, (unsigned long long *)N);
+  size_t nW = 1;
+  for (int d = 0; d < ndim; ++d) nW *= (size_t)(1 << tg.lt[d]) + 2 * tg.H + 3;
+  PIC_ND(ndim, (k_deposit_tiled<ND><<<max_items, 256, nW * 8, st>>>(b, s, bb.items, bb.num_items,
+                                                                      (unsigned long long *)N)));
 }
 
-void launch_step_tiled(hipStream_t st, const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
-                       const Store &s, const BinBufs &b, int max_items, const long long *Ncur, long long *Nnext,
+void launch_step_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const DiagC &dc, const Batch &b,
+                       const Store &s, const BinBufs &bb, int grid, const long long *Ncur, long long *Nnext,
                        long long *Nclear, const Drift &dr, double *partial, bool diag, uint32_t *err) {
-  if (max_items <= 0) return;
-  size_t lds = window_lds_bytes(tg, g.ndim);
+  if (grid <= 0) return;
+  const size_t lds = window_lds_bytes(tg, ndim);
   unsigned long long *nn = (unsigned long long *)Nnext;
-#define PIC_STEP_LAUNCH(ND_, DIAG_)                                                                              \
-  k_step_tiled<ND_, DIAG_><<<max_items, 256, lds, st>>>(g, P, dc, tg, s, b.items, b.num_items, Ncur, nn, Nclear, \
-                                                         dr.list, dr.count, dr.count_next, partial, err)
-  if (g.ndim == 2) {
-    if (diag) { PIC_STEP_LAUNCH(2, true); } else { PIC_STEP_LAUNCH(2, false); }
-  } else {
-    if (diag) { PIC_STEP_LAUNCH(3, true); } else { PIC_STEP_LAUNCH(3, false); }
-  }
-#undef PIC_STEP_LAUNCH
+  if (diag)
+    PIC_ND(ndim, (k_step_tiled<ND, true><<<grid, 256, lds, st>>>(P, dc, b, s, bb.items, bb.num_items, Ncur, nn,
+                                                                   Nclear, dr, partial, err)));
+  else
+    PIC_ND(ndim, (k_step_tiled<ND, false><<<grid, 256, lds, st>>>(P, dc, b, s, bb.items, bb.num_items, Ncur, nn,
+                                                                    Nclear, dr, partial, err)));
 }
 
-void launch_drifters(hipStream_t st, const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
-                     const Store &s, const long long *Ncur, long long *Nnext, const Drift &dr, double *partial,
-                     bool diag, uint32_t *err) {
+void launch_drifters(hipStream_t st, int ndim, const Pot &P, const DiagC &dc, const Batch &b, const Store &s,
+                     const long long *Ncur, long long *Nnext, const Drift &dr, double *dacc, bool diag,
+                     uint32_t *err) {
   unsigned long long *nn = (unsigned long long *)Nnext;
-  double *part_o = partial + (int64_t)dr.partial_offset * 8;
-#define PIC_DRIFT_LAUNCH(ND_, DIAG_) \
-  k_outliers<ND_, DIAG_><<<kDriftBlocks, 256, 0, st>>>(g, P, dc, tg, s, dr.list, dr.count, Ncur, nn, part_o, err)
-  if (g.ndim == 2) {
-    if (diag) { PIC_DRIFT_LAUNCH(2, true); } else { PIC_DRIFT_LAUNCH(2, false); }
-  } else {
-    if (diag) { PIC_DRIFT_LAUNCH(3, true); } else { PIC_DRIFT_LAUNCH(3, false); }
-  }
-#undef PIC_DRIFT_LAUNCH
+  if (diag)
+    PIC_ND(ndim, (k_outliers<ND, true><<<kDriftBlocks, 256, 0, st>>>(P, dc, b, s, dr, Ncur, nn, dacc, err)));
+  else
+    PIC_ND(ndim, (k_outliers<ND, false><<<kDriftBlocks, 256, 0, st>>>(P, dc, b, s, dr, Ncur, nn, dacc, err)));
 }
 
-void launch_reduce_diag_dev(hipStream_t st, const double *part_p, const int *nblk_p, const Drift &dr,
-                            const double *part_g, int nblk_g, pic_diag_t *out, int64_t step) {
-  k_reduce_diag_dev<<<1, 256, 0, st>>>(part_p, nblk_p, part_p + (int64_t)dr.partial_offset * 8, kDriftBlocks,
-                                       part_g, nblk_g, out, step);
+void launch_reduce_diag_slab(hipStream_t st, const double *part_p, const int *item_start, int tile_lo, int tile_hi,
+                             double *dacc_k, const double *part_g, int nblk_g, pic_diag_t *out, int64_t step) {
+  k_reduce_diag_slab<<<1, 256, 0, st>>>(part_p, item_start, tile_lo, tile_hi, dacc_k, part_g, nblk_g, out, step);
+}
+
+int step_kernel_blocks_per_cu(int ndim, const TileGeo &tg) {
+  int nb = 0;
+  const size_t lds = window_lds_bytes(tg, ndim);
+  hipError_t e;
+  if (ndim == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_tiled<2, false>, 256, lds);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_tiled<3, false>, 256, lds);
+  return e == hipSuccess && nb > 0 ? nb : 4;
 }
 
 }  // namespace pic

@@ -339,3 +339,80 @@ def test_binding_refuses_undersized_buffers():
         ctx.pic_force(dp, node, torch.empty((2, 5), dtype=torch.float32, device="cuda"))
     with pytest.raises(ValueError):
         ctx.pic_push(dp, torch.empty((2, 5), dtype=torch.float32, device="cuda"))
+
+
+# ------------------------------------------------------------------ batches and graphs
+def _sweep(scale=0.1, nslab=6):
+    wls = W.cfg_sweep(nslab=nslab, scale=scale)
+    return [(w.grid, w.parts) for w in wls]
+
+
+def test_batched_step_is_bit_identical_to_each_slab_alone():
+    """Slabs of uneven size advanced in one batched context (persistent
+    launches over all slabs' items) give every slab exactly the bits it gets
+    alone; per-slab diagnostics agree to FP64 summation order."""
+    pot = W.Potential(c_att=0.27)
+    slabs = _sweep()
+    banner(f"batch of {len(slabs)} slabs, N={[p.n for _, p in slabs]}")
+    alone = []
+    for grid, parts in slabs:
+        ctx = B.Context(grid, pot, DT, parts.n)
+        dp = B.DeviceParticles.from_host(parts)
+        diags = ctx.pic_step(dp, 30, 10)
+        alone.append((dp.to_host(), diags))
+    bctx = B.BatchContext([g for g, _ in slabs], pot, DT, [p.n for _, p in slabs])
+    dps = [B.DeviceParticles.from_host(p) for _, p in slabs]
+    bd = bctx.pic_step_batch(dps, 30, 10)
+    for k, (dp, (ref, rdiag)) in enumerate(zip(dps, alone)):
+        for x, y in zip(dp.to_host(), ref):
+            assert np.array_equal(x, y), f"slab {k}"
+        assert len(bd[k]) == len(rdiag) == 3
+        for a, b in zip(bd[k], rdiag):
+            for f in ("ke", "pe", "px", "py", "pz", "wsum", "bond"):
+                assert a[f] == pytest.approx(b[f], rel=1e-12, abs=1e-30), (k, f)
+
+
+def test_graph_replay_matches_eager_launches():
+    """Graph replays of 6-step blocks, interleaved with eager diagnostic steps
+    and several pic_step calls (host syncs in between), reproduce the eager
+    launches bit for bit on a created stream."""
+    pot = W.Potential(c_att=0.27)
+    grid, parts = W.make_slab(2, (96, 64), 32, 16, H, 61, fluence_Jcm2=2.0, R_cells=20)
+    stream = torch.cuda.Stream()
+    banner(f"graph replay N={parts.n}")
+    out = []
+    for graph in (False, True):
+        with torch.cuda.stream(stream):
+            ctx = B.Context(grid, pot, DT, parts.n, stream=stream)
+            ctx.pic_set_graph(graph)
+            dp = B.DeviceParticles.from_host(parts)
+            diags = []
+            for _ in range(4):
+                diags += ctx.pic_step(dp, 37, 10)
+            stream.synchronize()
+            out.append((dp.to_host(), diags))
+    for x, y in zip(out[0][0], out[1][0]):
+        assert np.array_equal(x, y)
+    for a, b in zip(out[0][1], out[1][1]):
+        assert a["ke"] == pytest.approx(b["ke"], rel=1e-12)
+
+
+def test_autotune_reads_only_and_keeps_results_identical():
+    pot = W.Potential(c_att=0.27)
+    grid, parts = W.make_slab(2, (96, 64), 32, 16, H, 71, fluence_Jcm2=1.0, R_cells=20)
+    banner(f"autotune N={parts.n}")
+    ctx = B.Context(grid, pot, DT, parts.n)
+    dp = B.DeviceParticles.from_host(parts)
+    before = dp.to_host()
+    tuning = ctx.pic_autotune(dp, 4)
+    for x, y in zip(dp.to_host(), before):
+        assert np.array_equal(x, y)  # probes never write the caller's arrays
+    assert tuning["candidates"] >= 4 and tuning["tile"] in (8, 16, 32)
+    assert ctx.pic_get_tiling()[:3] == (tuning["tile"], tuning["halo"], tuning["chunk"])
+    ctx.pic_step(dp, 20)
+    ref_ctx = B.Context(grid, pot, DT, parts.n)
+    ref = B.DeviceParticles.from_host(parts)
+    ref_ctx.pic_set_path(True)
+    ref_ctx.pic_step(ref, 20)
+    for x, y in zip(dp.to_host(), ref.to_host()):
+        assert np.array_equal(x, y)
