@@ -28,6 +28,29 @@ HBM_PEAK_GBS = 8000.0
 DEFAULTS = {"large": (2000, 20), "heated": (5000, 20), "small": (200, 20), "sweep": (1000, 12)}
 
 
+COUNTERS = {"large": "profiles/k_step_tiled_slab2d_4096x2048_32ppc.counters.json"}
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the fused kernel from the committed FETCH_SIZE /
+    WRITE_SIZE runs (scaled by a plain copy kernel), or None when there are no
+    counters for this workload or the kernel's sources changed since."""
+    import hashlib
+    name = COUNTERS.get(workload)
+    if name is None or not os.path.exists(os.path.join(ROOT, name)):
+        return None
+    with open(os.path.join(ROOT, name)) as fh:
+        rec = json.load(fh)
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(f.encode())
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -136,8 +159,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="large", choices=["large", "heated", "small", "sweep"])
-    ap.add_argument("--with-sweep", action="store_true",
-                    help="also run the batched intensity sweep (plain loop vs batched) into the same line")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the batched intensity sweep (plain loop vs batched) reported in the same line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration for rocprofv3 --pmc)")
@@ -205,9 +228,12 @@ def main():
     ms_fp, nfp = timing.get("force_push", (0.0, 0))
     avg_s = ms_fp / 1e3 / max(nfp, 1)
     achieved = launch_bytes / avg_s / 1e9 if nfp else None
+    traffic = measured_traffic(args.workload)
     roofline = {"bound": "hbm", "kernel": "k_step_tiled (fused gather+force+push+deposit)", "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                "traffic": None, "bytes_per_launch": launch_bytes, "bytes_per_particle": bytes_per_particle,
+                "traffic": traffic,
+                "traffic_gbs": traffic / avg_s / 1e9 if (traffic and nfp) else None,
+                "bytes_per_launch": launch_bytes, "bytes_per_particle": bytes_per_particle,
                 "bytes_per_node": 16, "avg_launch_ms": avg_s * 1e3,
                 "phases_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in timing.items() if isinstance(v, tuple)},
                 "drifters_last_step": timing.get("drifters_last"), "items_last_step": timing.get("items_last")}
@@ -234,7 +260,7 @@ def main():
     }
     del ctx, dp
     torch.cuda.empty_cache()
-    if args.with_sweep:
+    if not args.no_sweep and args.workload == "large":
         out["sweep"] = run_sweep(*DEFAULTS["sweep"])
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle)")
