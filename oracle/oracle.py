@@ -267,3 +267,22 @@ def functional(grid, cell, off, wq, y_s, tau):
     cell, off, wq = _state(cell, off, wq)
     return lib().orc_functional(C.byref(grid_struct(grid)), cell.shape[0], _ptr(cell, C.c_int32),
                                 _ptr(off, C.c_double), _ptr(wq, C.c_int32), float(y_s), float(tau))
+
+
+def heated_start(v_thermal, xi, sigma_ref, fluence_ref, fluence):
+    """v(0) = v_th + sigma(F) xi with the kick std proportional to sqrt(F)
+    (absorbed energy per atom proportional to the fluence)."""
+    s = np.asarray(sigma_ref, dtype=np.float64) * np.sqrt(fluence / fluence_ref)
+    return np.asarray(v_thermal, dtype=np.float64) + s[None, :] * np.asarray(xi, dtype=np.float64)
+
+
+def crater_objective(grid, pot, dt, nsteps, cell, off, v_thermal, xi, sigma_ref, fluence_ref, fluence, wq,
+                     y_s, tau, quantized=False):
+    """J = sum_p w_p sigmoid((y_p(T) - y_s)/tau) after nsteps from the heated
+    start, v(-1/2) = v(0) - F(0)/m dt/2.  Unquantized by default: the
+    fixed-point deposit is piecewise constant in the positions."""
+    v0 = heated_start(v_thermal, xi, sigma_ref, fluence_ref, fluence)
+    off = np.asarray(off, dtype=np.float64)
+    vh = start_leapfrog(grid, pot, dt, cell, off, v0, wq, quantized)
+    c, o, _, _ = run(grid, pot, dt, cell, off, vh, wq, nsteps, quantized=quantized)
+    return functional(grid, c, o, wq, y_s, tau)
