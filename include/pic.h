@@ -270,6 +270,54 @@ int pic_autotune(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t probe_ste
 int pic_calibrate_catt(const pic_grid_t *grid, const pic_potential_t *pot, double n_solid,
                        int32_t slab_layers, double *c_att, double *work);
 
+/* ---------------------------------------------------------------------------
+ * Reverse mode (adjoint) of the cycle above, for gradients of a functional J
+ * of the final state with respect to the potential parameters and the
+ * initial state.  The paper gives no derivatives: these are the exact
+ * derivatives of steps 1-6 as implemented, with the fixed-point deposit
+ * differentiated as the plain linear (CIC) deposit it approximates to 2^-16
+ * cells, the clamp of eq. (1)'s gradient and the density floor with zero
+ * derivative where they act, and the branch switch of eq. (3) at r = r0
+ * (where U' = 0) taken from the side the forward pass took.
+ *
+ * Cotangents (device arrays, float, same particle order as the state):
+ *   lam_x  [ndim][n]  dJ/d(offset): per cell of displacement along each axis;
+ *   lam_v  [3][n]     dJ/dv, s/m;
+ *   nbar   [nodes]    dJ/d(n r0^3): cotangent of the node density in units of
+ *                     r0^-3;
+ *   dtheta [4]        device doubles, ACCUMULATED (+=): dJ/dD (1/J), dJ/dr0
+ *                     (1/m), dJ/ds_rep, dJ/dc_att.
+ * Single-slab contexts only.  Stream-ordered and asynchronous; device errors
+ * (invalid particles) are reported by the next pic_sync or pic_step.
+ * Scatters to nodes use float atomics, so nbar, lam_x and dtheta carry
+ * FP32 summation-order noise (the forward path stays bit-exact).
+ * ------------------------------------------------------------------------- */
+
+/* One reverse leapfrog step.  state holds x(n) and v(n - 1/2) (the state
+ * before forward step n), node_w its node sums (pic_deposit of state).
+ * In:  lam_x = dJ/dx(n+1) without the deposit term of step n+1,
+ *      nbar_next = nbar of step n+1 (NULL when J does not depend on the
+ *      densities of step n+1, e.g. the last step), lam_v = dJ/dv(n + 1/2).
+ * Out: lam_x = dJ/dx(n) without the deposit term of step n, lam_v =
+ *      dJ/dv(n - 1/2), nbar = nbar of step n (overwritten), dtheta += the
+ *      parameter terms of step n.
+ * The particle's forward step is recomputed from state and node_w (same bits
+ * as pic_push), including which walls mirror it.  After the last reverse
+ * step, pic_deposit_vjp completes lam_x of the initial state. */
+int pic_adjoint_step(pic_ctx_t *ctx, const pic_particles_t *state, const int64_t *node_w, const float *nbar_next,
+                     float *lam_x, float *lam_v, float *nbar, double *dtheta);
+
+/* VJP of steps 2-5 (pic_force) at state with node sums node_w:
+ * force_bar [ndim][n] = dJ/dF (1/N per atom) ->
+ * lam_x += the gather terms, nbar = the node-density cotangent (overwritten;
+ * add its deposit term with pic_deposit_vjp), dtheta += parameter terms. */
+int pic_force_vjp(pic_ctx_t *ctx, const pic_particles_t *state, const int64_t *node_w, const float *force_bar,
+                  float *lam_x, float *nbar, double *dtheta);
+
+/* VJP of step 1 with respect to the positions: lam_x += w * sum over the
+ * particle's 2^ndim nodes of nbar * d(density share)/d(offset). */
+int pic_deposit_vjp(pic_ctx_t *ctx, const pic_particles_t *state, const float *nbar, float *lam_x);
+
 #ifdef __cplusplus
 }
 #endif

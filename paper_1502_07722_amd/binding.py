@@ -87,6 +87,9 @@ lib.pic_step_batch.argtypes = [_vp, _P(pic_particles_t), C.c_int32, _P(pic_diag_
 lib.pic_set_path.argtypes = [_vp, C.c_int32]
 lib.pic_step_nodes.argtypes = [_vp, _vp]
 lib.pic_get_timing.argtypes = [_vp, _P(pic_timing_t)]
+lib.pic_adjoint_step.argtypes = [_vp, _P(pic_particles_t), _vp, _vp, _vp, _vp, _vp, _vp]
+lib.pic_force_vjp.argtypes = [_vp, _P(pic_particles_t), _vp, _vp, _vp, _vp, _vp]
+lib.pic_deposit_vjp.argtypes = [_vp, _P(pic_particles_t), _vp, _vp]
 lib.pic_calibrate_catt.argtypes = [_P(pic_grid_t), _P(pic_potential_t), C.c_double, C.c_int32, _P(C.c_double),
                                    _P(C.c_double)]
 
@@ -290,6 +293,52 @@ class Context:
         out["drifters_last"] = t.drifters_last
         out["items_last"] = t.items_last
         return out
+
+    # reverse mode -----------------------------------------------------------
+    def _adj_bufs(self, parts, lam_x, lam_v, nbar, dtheta):
+        nd, n = self.grid.ndim, parts.n
+        if lam_x is not None:
+            self._need(lam_x, nd * n, torch.float32, "lam_x")
+        if lam_v is not None:
+            self._need(lam_v, 3 * n, torch.float32, "lam_v")
+        if nbar is None:
+            nbar = torch.empty(self.nnodes, dtype=torch.float32, device=self.device)
+        self._need(nbar, self.nnodes, torch.float32, "nbar")
+        if dtheta is None:
+            dtheta = torch.zeros(4, dtype=torch.float64, device=self.device)
+        self._need(dtheta, 4, torch.float64, "dtheta")
+        return nbar, dtheta
+
+    def pic_adjoint_step(self, state: DeviceParticles, node_w, nbar_next, lam_x, lam_v, nbar=None, dtheta=None):
+        """One reverse step; lam_x and lam_v are updated in place.  Returns
+        (nbar, dtheta) with dtheta accumulated."""
+        self._need(node_w, self.nnodes, torch.int64, "node_w")
+        if nbar_next is not None:
+            self._need(nbar_next, self.nnodes, torch.float32, "nbar_next")
+        self._parts_ok(state)
+        nbar, dtheta = self._adj_bufs(state, lam_x, lam_v, nbar, dtheta)
+        s = state.struct()
+        self._check(lib.pic_adjoint_step(self.ctx, C.byref(s), _ptr(node_w),
+                                         _ptr(nbar_next) if nbar_next is not None else None,
+                                         _ptr(lam_x), _ptr(lam_v), _ptr(nbar), _ptr(dtheta)), "pic_adjoint_step")
+        return nbar, dtheta
+
+    def pic_force_vjp(self, state: DeviceParticles, node_w, force_bar, lam_x, nbar=None, dtheta=None):
+        self._need(node_w, self.nnodes, torch.int64, "node_w")
+        self._need(force_bar, self.grid.ndim * state.n, torch.float32, "force_bar")
+        self._parts_ok(state)
+        nbar, dtheta = self._adj_bufs(state, lam_x, None, nbar, dtheta)
+        s = state.struct()
+        self._check(lib.pic_force_vjp(self.ctx, C.byref(s), _ptr(node_w), _ptr(force_bar), _ptr(lam_x),
+                                      _ptr(nbar), _ptr(dtheta)), "pic_force_vjp")
+        return nbar, dtheta
+
+    def pic_deposit_vjp(self, state: DeviceParticles, nbar, lam_x):
+        self._need(nbar, self.nnodes, torch.float32, "nbar")
+        self._need(lam_x, self.grid.ndim * state.n, torch.float32, "lam_x")
+        self._parts_ok(state)
+        s = state.struct()
+        self._check(lib.pic_deposit_vjp(self.ctx, C.byref(s), _ptr(nbar), _ptr(lam_x)), "pic_deposit_vjp")
 
     def start_leapfrog(self, parts: DeviceParticles):
         """v(0) -> v(-1/2) = v(0) - F(0)/m dt/2."""

@@ -78,7 +78,7 @@ int64_t tiles_for(const pic_grid_t *g, int lt) {
 }
 
 struct Layout {
-  size_t err, diag, partial, partial_pe, node, dens, G, total;
+  size_t err, diag, partial, partial_pe, node, dens, G, Gbar, total;
   bool tiled;
   size_t store[2], bins, items, n3[3], drift, dacc, slabs, offs;
   int64_t tiles_max, items_max, cap, nodes, pe_blocks;
@@ -116,6 +116,7 @@ Layout make_layout(const pic_grid_t *grids, int nslab, const int64_t *max_n) {
     L.node = o; o = align_up(o + sizeof(long long) * (size_t)L.nodes);
     L.dens = o; o = align_up(o + sizeof(float) * (size_t)L.nodes);
     L.G = o; o = align_up(o + sizeof(float) * (size_t)cells1 * nd);
+    L.Gbar = o; o = align_up(o + sizeof(float) * (size_t)cells1 * nd);
   }
   if (L.tiled) {
     const int64_t cap = std::max<int64_t>(L.cap, 1);
@@ -194,6 +195,7 @@ struct pic_ctx {
   long long *node = nullptr;
   float *dens = nullptr;
   float *G = nullptr;
+  float *Gbar = nullptr;  // centre-gradient cotangent (reverse mode)
   bool force_untiled = false;
   // tiled path
   bool tiled = false;
@@ -466,6 +468,7 @@ static int init_common(pic_ctx_t **out, const pic_grid_t *grids_in, int nslab, c
     c->node = reinterpret_cast<long long *>(c->ws + L.node);
     c->dens = reinterpret_cast<float *>(c->ws + L.dens);
     c->G = reinterpret_cast<float *>(c->ws + L.G);
+    c->Gbar = reinterpret_cast<float *>(c->ws + L.Gbar);
   }
   c->tiled = L.tiled;
   if (L.tiled) {
@@ -966,6 +969,59 @@ int pic_push(pic_ctx_t *ctx, pic_particles_t *p, const float *force) {
   if (p->n > 0 && !force) return fail(ctx, PIC_EINVAL, "force is NULL");
   launch_push(ctx->stream, ctx->geo, ctx->P, ptrs(p), force, ctx->err);
   return check_launch(ctx, "push");
+}
+
+// ---------------------------------------------------------------------------
+// Reverse mode on caller arrays
+// ---------------------------------------------------------------------------
+// Shared tail of the two particle VJPs: nbar gets the gradient transpose, the
+// per-block parameter partials are summed into dtheta.
+static int adjoint_common(pic_ctx_t *ctx, const pic_particles_t *p, const int64_t *node_w, const float *nbar_next,
+                          const float *fbar, float *lam_x, float *lam_v, float *nbar, double *dtheta,
+                          bool force_only, const char *what) {
+  if (!node_w) return fail(ctx, PIC_EINVAL, "node_w is NULL");
+  if (!nbar) return fail(ctx, PIC_EINVAL, "nbar is NULL");
+  if (!dtheta) return fail(ctx, PIC_EINVAL, "dtheta is NULL");
+  if (p->n > 0 && (!lam_x || (!force_only && !lam_v) || (force_only && !fbar)))
+    return fail(ctx, PIC_EINVAL, "a cotangent array is NULL");
+  const Geo &g = ctx->geo;
+  launch_grid(ctx->stream, g, reinterpret_cast<const long long *>(node_w), ctx->dens, ctx->G);
+  launch_fillf(ctx->stream, nbar, g.nnodes);
+  launch_fillf(ctx->stream, ctx->Gbar, (int64_t)g.ncells * g.ndim);
+  const int nb = launch_adjoint(ctx->stream, g, ctx->P, ptrs(p), ctx->dens, ctx->G, nbar_next, fbar, lam_x, lam_v,
+                                nbar, ctx->Gbar, ctx->partial, ctx->err, force_only);
+  launch_gradient_vjp(ctx->stream, g, ctx->Gbar, nbar);
+  if (nb > 0) launch_reduce_theta(ctx->stream, ctx->partial, nb, 1.0 / ctx->pot.D, 1.0 / ctx->pot.r0, dtheta);
+  return check_launch(ctx, what);
+}
+
+int pic_adjoint_step(pic_ctx_t *ctx, const pic_particles_t *state, const int64_t *node_w, const float *nbar_next,
+                     float *lam_x, float *lam_v, float *nbar, double *dtheta) {
+  if (!ctx) return PIC_EINVAL;
+  int rc = single_slab(ctx);
+  if (!rc) rc = check_particles(ctx, state, ctx->max_n[0], true, true);
+  if (rc) return rc;
+  return adjoint_common(ctx, state, node_w, nbar_next, nullptr, lam_x, lam_v, nbar, dtheta, false, "adjoint step");
+}
+
+int pic_force_vjp(pic_ctx_t *ctx, const pic_particles_t *state, const int64_t *node_w, const float *force_bar,
+                  float *lam_x, float *nbar, double *dtheta) {
+  if (!ctx) return PIC_EINVAL;
+  int rc = single_slab(ctx);
+  if (!rc) rc = check_particles(ctx, state, ctx->max_n[0], false, false);
+  if (rc) return rc;
+  return adjoint_common(ctx, state, node_w, nullptr, force_bar, lam_x, nullptr, nbar, dtheta, true, "force vjp");
+}
+
+int pic_deposit_vjp(pic_ctx_t *ctx, const pic_particles_t *state, const float *nbar, float *lam_x) {
+  if (!ctx) return PIC_EINVAL;
+  int rc = single_slab(ctx);
+  if (!rc) rc = check_particles(ctx, state, ctx->max_n[0], false, true);
+  if (rc) return rc;
+  if (!nbar) return fail(ctx, PIC_EINVAL, "nbar is NULL");
+  if (state->n > 0 && !lam_x) return fail(ctx, PIC_EINVAL, "lam_x is NULL");
+  launch_deposit_vjp(ctx->stream, ctx->geo, ptrs(state), nbar, lam_x, ctx->err);
+  return check_launch(ctx, "deposit vjp");
 }
 
 int pic_step_batch(pic_ctx_t *ctx, pic_particles_t *parts, int32_t nsteps, pic_diag_t *diag, int32_t diag_every) {

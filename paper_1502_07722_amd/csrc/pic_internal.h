@@ -126,4 +126,14 @@ void launch_reduce_diag_slab(hipStream_t st, const double *part_p, const int *it
 int step_kernel_blocks_per_cu(int ndim, const TileGeo &tg);
 void launch_fill32(hipStream_t s, int *a, int64_t n);
 
+// reverse mode on caller arrays (pic_adjoint.hip)
+void launch_fillf(hipStream_t st, float *a, int64_t n);
+int launch_adjoint(hipStream_t st, const Geo &g, const Pot &P, const PartPtrs &p, const float *dens, const float *G,
+                   const float *nbar_next, const float *fbar, float *lam_x, float *lam_v, float *nbar, float *Gbar,
+                   double *partial, uint32_t *err, bool force_only);
+void launch_gradient_vjp(hipStream_t st, const Geo &g, const float *Gbar, float *nbar);
+void launch_deposit_vjp(hipStream_t st, const Geo &g, const PartPtrs &p, const float *nbar, float *lam_x,
+                        uint32_t *err);
+void launch_reduce_theta(hipStream_t st, const double *partial, int nblocks, double s0, double s1, double *dtheta);
+
 }  // namespace pic
