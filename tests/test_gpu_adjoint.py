@@ -52,9 +52,25 @@ def _advance(B, ctx, dp, k):
     torch.cuda.synchronize()
 
 
-def _theta(pot):
-    return {k: torch.tensor(float(getattr(pot, k)), dtype=torch.float64, requires_grad=True)
+def _host(dp):
+    from types import SimpleNamespace
+    cell, off, vel, wq = dp.to_host()
+    return SimpleNamespace(cell=cell, off=off, vel=vel, wq=wq)
+
+
+def _theta(pot, n):
+    """Per-particle parameter leaves: their gradients are each particle's
+    contribution, whose absolute sum bounds the rounding of the total."""
+    return {k: torch.full((n,), float(getattr(pot, k)), dtype=torch.float64, requires_grad=True)
             for k in ("D", "r0", "s_rep", "c_att")}
+
+
+def _check_theta(dth, th):
+    for i, k in enumerate(("D", "r0", "s_rep", "c_att")):
+        t = th[k].grad.numpy()
+        ref, l1 = t.sum(), np.abs(t).sum()
+        got = dth[i].item()
+        assert abs(got - ref) <= 1e-4 * abs(ref) + 2e-5 * l1, (k, got, ref, l1)
 
 
 def _close(gpu, ref, rel, what):
@@ -63,6 +79,22 @@ def _close(gpu, ref, rel, what):
     scale = np.abs(ref).max()
     err = np.abs(gpu - ref).max()
     assert err <= rel * scale, f"{what}: max err {err:.3e} vs scale {scale:.3e}"
+
+
+def _forces_at(geo, th, pot, idx, f, w, node_w):
+    """Reference force with the GPU's exact node sums as values and the plain
+    CIC deposit's derivative (straight-through): both sides then evaluate
+    eq. (3)'s branch switch at r = r0 and the clamp of eq. (1) on the same
+    side.  Solid-density particles sit at rbar ~ r0, right at the branch
+    switch, so a 1e-5 difference in the densities would otherwise flip the
+    derivative of a few particles."""
+    N_cic = R.deposit(geo, idx, f, w)
+    N_gpu = torch.as_tensor(node_w.cpu().numpy(), dtype=torch.float64) * R.WUNIT
+    N = N_cic + (N_gpu - N_cic.detach())
+    dens = R.density(geo, N)
+    G = R.centre_gradient(geo, dens)
+    n_p, Gp = R.gather(geo, dens, G, idx, f)
+    return R.pair_force(th, pot.n_floor, pot.g_clamp, n_p, Gp)
 
 
 def _ref_state(grid, host):
@@ -79,7 +111,7 @@ def test_force_vjp_matches_autograd(B, nd):
     dp = B.DeviceParticles.from_host(parts)
     ctx.start_leapfrog(dp)
     _advance(B, ctx, dp, 10)
-    host = dp.to_host()
+    host = _host(dp)
     node = ctx.pic_deposit(dp)
     rng = np.random.default_rng(5)
     fbar = rng.standard_normal((nd, parts.n)).astype(np.float32) * np.float32(1e9)
@@ -88,17 +120,14 @@ def test_force_vjp_matches_autograd(B, nd):
     ctx.pic_deposit_vjp(dp, nbar, lam_x)
     ctx.pic_sync()
     geo, idx, f = _ref_state(grid, host)
-    th = _theta(pot)
+    th = _theta(pot, parts.n)
     w = torch.as_tensor(host.wq, dtype=torch.float64) * R.WUNIT
-    F = R.forces(geo, th, pot.n_floor, pot.g_clamp, idx, f, w)
+    F = _forces_at(geo, th, pot, idx, f, w, node)
     L = sum((F[d] * torch.as_tensor(fbar[d], dtype=torch.float64)).sum() for d in range(nd))
     L.backward()
     for d in range(nd):
         _close(lam_x[d].cpu().numpy(), f[d].grad.numpy(), 1e-4, f"lam_x[{d}]")
-    ref_th = np.array([th[k].grad.item() for k in ("D", "r0", "s_rep", "c_att")])
-    _close(dth.cpu().numpy(), ref_th, 1e-4, "dtheta")
-    for i in range(4):
-        assert abs(dth[i].item() - ref_th[i]) <= 1e-4 * abs(ref_th[i]) + 1e-7 * np.abs(ref_th).max(), i
+    _check_theta(dth, th)
 
 
 @pytest.mark.parametrize("nd", [2, 3])
@@ -109,7 +138,7 @@ def test_adjoint_step_matches_autograd(B, nd):
     dp = B.DeviceParticles.from_host(parts)
     ctx.start_leapfrog(dp)
     _advance(B, ctx, dp, 10)
-    host = dp.to_host()
+    host = _host(dp)
     node = ctx.pic_deposit(dp)
     rng = np.random.default_rng(6)
     n, nnodes = parts.n, B.pic_num_nodes(grid)
@@ -124,9 +153,10 @@ def test_adjoint_step_matches_autograd(B, nd):
     # reference: L = lx . x(n+1) + lv . v(n+1/2) + nb . (n(n+1) r0^3)
     geo, idx, f = _ref_state(grid, host)
     v = [torch.as_tensor(host.vel[d], dtype=torch.float64).requires_grad_(True) for d in range(3)]
-    th = _theta(pot)
+    th = _theta(pot, parts.n)
     w = torch.as_tensor(host.wq, dtype=torch.float64) * R.WUNIT
-    idx2, f2, v2 = R.step(geo, th, pot.n_floor, pot.g_clamp, dt, pot.mass, idx, f, v, w)
+    F = _forces_at(geo, th, pot, idx, f, w, node)
+    idx2, f2, v2 = R.push(geo, dt, pot.mass, F, idx, f, v)
     dens2 = R.density(geo, R.deposit(geo, idx2, f2, w)) * pot.r0 ** 3
     L = sum((f2[d] * torch.as_tensor(lx[d], dtype=torch.float64)).sum() for d in range(nd))
     L = L + sum((v2[d] * torch.as_tensor(lv[d], dtype=torch.float64)).sum() for d in range(3))
@@ -136,10 +166,7 @@ def test_adjoint_step_matches_autograd(B, nd):
         _close(lam_x[d].cpu().numpy(), f[d].grad.numpy(), 1e-4, f"lam_x[{d}]")
     for d in range(3):
         _close(lam_v[d].cpu().numpy(), v[d].grad.numpy(), 1e-4, f"lam_v[{d}]")
-    ref_th = np.array([th[k].grad.item() for k in ("D", "r0", "s_rep", "c_att")])
-    for i in range(4):
-        assert abs(dth[i].item() - ref_th[i]) <= 1e-4 * abs(ref_th[i]) + 1e-6 * np.abs(ref_th).max(), \
-            (i, dth.cpu().numpy(), ref_th)
+    _check_theta(dth, th)
 
 
 def _per_step_gradient(B, grid, parts, pot, dt, nsteps, y_s, tau):
@@ -160,7 +187,7 @@ def _per_step_gradient(B, grid, parts, pot, dt, nsteps, y_s, tau):
     for _ in range(nsteps):
         _advance(B, ctx, dp, 1)
         states.append(dp.clone())
-    final = states[-1].to_host()
+    final = _host(states[-1])
     # dJ/d(offset) of J = sum w sigmoid((y - y_s)/tau) on the normal axis
     ax = nd - 1
     cell = final.cell.astype(np.int64)
@@ -203,10 +230,12 @@ def test_whole_gradient_matches_oracle_finite_differences(B):
     for k, v in got.items():
         fd = alt["dJ"][k]["0.0001"]
         fd_err = abs(alt["dJ"][k]["0.001"] - fd)
+        print(f"dJ/d{k}: adjoint {v:.9e} finite difference {fd:.9e} rel {abs(v - fd) / abs(fd):.2e}")
         assert abs(v - fd) <= 1e-4 * abs(fd) + fd_err, (k, v, fd, fd_err)
     un = gold["potentials"]["unaltered"]
     pot1 = W.Potential(c_att=un["c_att"])
     _, dth1, _ = _per_step_gradient(B, grid, parts, pot1, wl.dt, nsteps, y_s, tau)
     fd = un["dJ"]["r0"]["0.0001"]
     fd_err = abs(un["dJ"]["r0"]["0.001"] - fd)
+    print(f"dJ/dr0: adjoint {dth1[1]:.9e} finite difference {fd:.9e} rel {abs(dth1[1] - fd) / abs(fd):.2e}")
     assert abs(dth1[1] - fd) <= 1e-4 * abs(fd) + fd_err, (dth1[1], fd, fd_err)
