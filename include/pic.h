@@ -318,6 +318,38 @@ int pic_force_vjp(pic_ctx_t *ctx, const pic_particles_t *state, const int64_t *n
  * particle's 2^ndim nodes of nbar * d(density share)/d(offset). */
 int pic_deposit_vjp(pic_ctx_t *ctx, const pic_particles_t *state, const float *nbar, float *lam_x);
 
+/* Recorded trajectories: the checkpointed reverse sweep at full speed.
+ *
+ * pic_forward_record runs nsteps cycles like pic_step (same bits), keeping
+ * the particles in the library's tile-binned order for the whole run (no
+ * re-binning; particles that leave their tile take the slower global path)
+ * and copying the state into record before every step that is a multiple of
+ * every (checkpoints, in the binned order).  record is caller-owned device
+ * memory of pic_record_bytes() bytes, 256-byte aligned; the final state is
+ * written back to p in the caller's order.
+ *
+ * pic_backward_record then runs the whole reverse sweep for that run: for
+ * each checkpoint segment, from the last, it recomputes the segment's states
+ * and node sums out of place into scratch (pic_backward_bytes() bytes,
+ * caller-owned device memory, 256-byte aligned) and applies the reverse step
+ * of pic_adjoint_step to each, last step first.
+ * In:  lam_x [ndim][n] = dJ/d(offset) of the final state, lam_v [3][n] =
+ *      dJ/dv(nsteps - 1/2) (caller order; J must not depend on the final
+ *      node densities).
+ * Out: lam_x = complete dJ/d(offset) of the initial state, lam_v =
+ *      dJ/dv(-1/2); dtheta (device, 4 doubles) += dJ/d(D, r0, s_rep, c_att).
+ * p supplies the particle count (its arrays are not read).  The context, its
+ * tiling, nsteps, every and record must be those of the pic_forward_record
+ * call, otherwise PIC_EINVAL.  Single-slab contexts on the tiled path only.
+ * Synchronises and reports device errors. */
+size_t pic_record_bytes(pic_ctx_t *ctx, int32_t nsteps, int32_t every);
+size_t pic_backward_bytes(pic_ctx_t *ctx, int32_t every);
+int pic_forward_record(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, int32_t every, void *record,
+                       size_t record_bytes);
+int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps, int32_t every,
+                        const void *record, size_t record_bytes, void *scratch, size_t scratch_bytes, float *lam_x,
+                        float *lam_v, double *dtheta);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,107 @@
+"""torch.autograd bindings of the hand-written reverse mode.
+
+Two Functions, both thin wrappers of the C ABI (every step of the cycle and of
+its reverse runs in the library's kernels):
+
+  Force       off(0), theta -> per-atom force (pic_deposit + pic_force);
+              backward by pic_force_vjp + pic_deposit_vjp.
+  Trajectory  off(0), v(-1/2), theta -> off(T), v(T - 1/2) over nsteps
+              cycles (pic_forward_record, checkpoints every `every` steps);
+              backward by pic_backward_record, which recomputes each segment
+              between checkpoints and sweeps it in reverse.
+
+theta is a float64 tensor (D, r0, s_rep, c_att) holding the context's
+potential; it is there to receive dJ/dtheta.  Cell indices are integer
+outputs without gradient.
+
+crater_objective() composes them into the paper's experiment (Sec. 3): a
+slab heated by an absorbed fluence F (kick std proportional to sqrt(F)),
+the leapfrog start v(-1/2) = v(0) - F(0)/m dt/2, nsteps cycles, and the
+smooth crater functional J = sum_p w_p sigmoid((y_p(T) - y_s) / tau) (the
+weight no longer below the initial surface, on the normal axis).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import binding as B
+
+THETA_KEYS = ("D", "r0", "s_rep", "c_att")
+
+
+def theta_of(pot, device="cuda"):
+    return torch.tensor([float(getattr(pot, k)) for k in THETA_KEYS], dtype=torch.float64, device=device)
+
+
+def _check_theta(ctx: B.Context, theta):
+    want = theta_of(ctx.pot, "cpu")
+    if not torch.equal(theta.detach().cpu(), want):
+        raise ValueError("theta must hold the context's potential (D, r0, s_rep, c_att)")
+
+
+class Force(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, off, theta, ctx: B.Context, cell, wq):
+        _check_theta(ctx, theta)
+        n = cell.shape[0]
+        vel = torch.zeros((3, n), dtype=torch.float32, device=off.device)
+        dp = B.DeviceParticles(cell, off.detach().contiguous(), vel, wq)
+        node = ctx.pic_deposit(dp)
+        F = ctx.pic_force(dp, node)
+        fctx.pic = (ctx, dp, node)
+        fctx.theta_dev = theta.device
+        return F
+
+    @staticmethod
+    def backward(fctx, gF):
+        ctx, dp, node = fctx.pic
+        lam_x = torch.zeros_like(dp.off)
+        nbar, dth = ctx.pic_force_vjp(dp, node, gF.contiguous().float(), lam_x)
+        ctx.pic_deposit_vjp(dp, nbar, lam_x)
+        return lam_x, dth.to(fctx.theta_dev), None, None, None
+
+
+class Trajectory(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, off0, vel0, theta, ctx: B.Context, cell0, wq, nsteps: int, every: int):
+        _check_theta(ctx, theta)
+        dp = B.DeviceParticles(cell0.clone(), off0.detach().contiguous().clone(),
+                               vel0.detach().contiguous().clone(), wq)
+        rec = ctx.pic_forward_record(dp, nsteps, every)
+        fctx.pic = (ctx, dp, rec)
+        fctx.theta_dev = theta.device
+        fctx.mark_non_differentiable(dp.cell)
+        return dp.off, dp.vel, dp.cell
+
+    @staticmethod
+    def backward(fctx, g_off, g_vel, _g_cell):
+        ctx, dp, rec = fctx.pic
+        lam_x = torch.zeros_like(dp.off) if g_off is None else g_off.contiguous().float().clone()
+        lam_v = torch.zeros_like(dp.vel) if g_vel is None else g_vel.contiguous().float().clone()
+        dth = ctx.pic_backward_record(dp, rec, lam_x, lam_v)
+        return lam_x, lam_v, dth.to(fctx.theta_dev), None, None, None, None, None
+
+
+def crater_objective(ctx: B.Context, cell, off0, v_thermal, xi, sigma_ref, fluence_ref, fluence, wq, theta,
+                     nsteps: int, every: int, y_s: float, tau: float):
+    """J(theta, F) on device tensors (cell int32 [n], off0 float32 [ndim][n],
+    v_thermal / xi float32 [3][n], sigma_ref float32 [n], wq int32 [n]);
+    fluence is a float64 scalar tensor.  Returns (J, final offsets, cells)."""
+    grid, pot, dt = ctx.grid, ctx.pot, ctx.dt
+    nd = grid.ndim
+    scale = torch.sqrt(fluence / fluence_ref).float()
+    v0 = v_thermal + (sigma_ref * scale)[None, :] * xi
+    F0 = Force.apply(off0, theta, ctx, cell, wq)
+    kick = torch.zeros_like(v0)
+    kick[:nd] = F0 * (0.5 * dt / pot.mass)
+    vh = v0 - kick
+    offT, velT, cellT = Trajectory.apply(off0, vh, theta, ctx, cell, wq, nsteps, every)
+    ax = nd - 1
+    lateral = 1
+    for d in range(ax):
+        lateral *= grid.n[d]
+    layer = torch.div(cellT.long(), lateral, rounding_mode="floor").double()
+    y = (layer + offT[ax].double()) * grid.h[ax]
+    w = wq.double() * 2.0 ** -20
+    J = (w * torch.sigmoid((y - y_s) / tau)).sum()
+    return J, offT, cellT

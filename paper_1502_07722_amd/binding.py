@@ -90,6 +90,13 @@ lib.pic_get_timing.argtypes = [_vp, _P(pic_timing_t)]
 lib.pic_adjoint_step.argtypes = [_vp, _P(pic_particles_t), _vp, _vp, _vp, _vp, _vp, _vp]
 lib.pic_force_vjp.argtypes = [_vp, _P(pic_particles_t), _vp, _vp, _vp, _vp, _vp]
 lib.pic_deposit_vjp.argtypes = [_vp, _P(pic_particles_t), _vp, _vp]
+lib.pic_record_bytes.argtypes = [_vp, C.c_int32, C.c_int32]
+lib.pic_record_bytes.restype = C.c_size_t
+lib.pic_backward_bytes.argtypes = [_vp, C.c_int32]
+lib.pic_backward_bytes.restype = C.c_size_t
+lib.pic_forward_record.argtypes = [_vp, _P(pic_particles_t), C.c_int32, C.c_int32, _vp, C.c_size_t]
+lib.pic_backward_record.argtypes = [_vp, _P(pic_particles_t), C.c_int32, C.c_int32, _vp, C.c_size_t, _vp,
+                                    C.c_size_t, _vp, _vp, _vp]
 lib.pic_calibrate_catt.argtypes = [_P(pic_grid_t), _P(pic_potential_t), C.c_double, C.c_int32, _P(C.c_double),
                                    _P(C.c_double)]
 
@@ -339,6 +346,42 @@ class Context:
         self._parts_ok(state)
         s = state.struct()
         self._check(lib.pic_deposit_vjp(self.ctx, C.byref(s), _ptr(nbar), _ptr(lam_x)), "pic_deposit_vjp")
+
+    def _aligned(self, nbytes):
+        """A caller-owned device buffer of nbytes, 256-byte aligned: (tensor, ptr)."""
+        t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=self.device)
+        return t, (t.data_ptr() + 255) // 256 * 256
+
+    def pic_forward_record(self, parts: DeviceParticles, nsteps: int, every: int):
+        """nsteps cycles in place with checkpoints every `every` steps; returns
+        the record (an opaque device buffer) for pic_backward_record."""
+        self._parts_ok(parts)
+        nbytes = lib.pic_record_bytes(self.ctx, int(nsteps), int(every))
+        if nbytes == 0:
+            raise PicError(PIC_EINVAL, "recorded runs need a single-slab context on the tiled path")
+        buf, ptr = self._aligned(nbytes)
+        s = parts.struct()
+        self._check(lib.pic_forward_record(self.ctx, C.byref(s), int(nsteps), int(every), C.c_void_p(ptr), nbytes),
+                    "pic_forward_record")
+        return {"buf": buf, "ptr": ptr, "bytes": nbytes, "nsteps": int(nsteps), "every": int(every)}
+
+    def pic_backward_record(self, parts: DeviceParticles, record, lam_x, lam_v, dtheta=None):
+        """Reverse sweep of a recorded run; lam_x and lam_v (caller order) are
+        replaced by the initial-state cotangents.  Returns dtheta (+=)."""
+        self._parts_ok(parts)
+        self._need(lam_x, self.grid.ndim * parts.n, torch.float32, "lam_x")
+        self._need(lam_v, 3 * parts.n, torch.float32, "lam_v")
+        if dtheta is None:
+            dtheta = torch.zeros(4, dtype=torch.float64, device=self.device)
+        self._need(dtheta, 4, torch.float64, "dtheta")
+        nbytes = lib.pic_backward_bytes(self.ctx, record["every"])
+        scratch, sptr = self._aligned(nbytes)
+        s = parts.struct()
+        self._check(lib.pic_backward_record(self.ctx, C.byref(s), record["nsteps"], record["every"],
+                                            C.c_void_p(record["ptr"]), record["bytes"], C.c_void_p(sptr), nbytes,
+                                            _ptr(lam_x), _ptr(lam_v), _ptr(dtheta)), "pic_backward_record")
+        del scratch
+        return dtheta
 
     def start_leapfrog(self, parts: DeviceParticles):
         """v(0) -> v(-1/2) = v(0) - F(0)/m dt/2."""

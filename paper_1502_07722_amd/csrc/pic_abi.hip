@@ -216,6 +216,8 @@ struct pic_ctx {
   bool drift_pending = false;
   long long *last_nodes = nullptr;
   int last_step = 0;
+  // recorded trajectories (reverse mode)
+  std::vector<int64_t> rec_key;  // configuration of the last pic_forward_record
   // graph replay of steady steps
   bool use_graph = true;
   hipGraphExec_t graph[2]{};
@@ -599,6 +601,14 @@ int step_untiled(pic_ctx_t *ctx, const PartPtrs &pp, int32_t nsteps, DiagSink &d
   return PIC_OK;
 }
 
+void ensure_grid_blocks(pic_ctx_t *c) {
+  if (c->grid_blocks) return;
+  int dev = 0, ncu = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) ncu = 256;
+  c->grid_blocks = ncu * step_kernel_blocks_per_cu(c->ndim, c->sd[0].tg);
+}
+
 Drift drift_of(pic_ctx_t *c, int s) {
   return Drift{c->drift + 4, c->drift + (s & 1), c->drift + ((s + 1) & 1), c->drift + 2 + (s & 1),
                c->drift + 2 + ((s + 1) & 1)};
@@ -610,12 +620,12 @@ void enqueue_step(pic_ctx_t *c, const Batch &b, const Store &st, int s, bool dia
   const Drift dr = drift_of(c, s);
   {
     PhaseTimer t(c, 2);
-    launch_step_tiled(c->stream, c->ndim, c->sd[0].tg, c->P, c->dcs[0], b, st, c->bb, c->grid_blocks, Nc, Nn, Nz,
-                      dr, c->partial, diag, c->err);
+    launch_step_tiled(c->stream, c->ndim, c->sd[0].tg, c->P, c->dcs[0], b, st, st, c->bb, c->grid_blocks, Nc, Nn,
+                      Nz, dr, c->partial, diag, c->err);
   }
   {
     PhaseTimer t(c, 6);
-    launch_drifters(c->stream, c->ndim, c->P, c->dcs[0], b, st, Nc, Nn, dr, c->dacc, diag, c->err);
+    launch_drifters(c->stream, c->ndim, c->P, c->dcs[0], b, st, st, Nc, Nn, dr, c->dacc, diag, c->err);
   }
 }
 
@@ -680,12 +690,7 @@ int step_tiled(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t nsteps, Dia
     n += parts[k].n;
   }
   const Batch b = batch_of(ctx, n);
-  if (!ctx->grid_blocks) {
-    int dev = 0, ncu = 0;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) ncu = 256;
-    ctx->grid_blocks = ncu * step_kernel_blocks_per_cu(nd, ctx->sd[0].tg);
-  }
+  ensure_grid_blocks(ctx);
   int cur = 0;
   // bring the caller's particles into the binned store; stop on invalid input
   {
@@ -1022,6 +1027,217 @@ int pic_deposit_vjp(pic_ctx_t *ctx, const pic_particles_t *state, const float *n
   if (state->n > 0 && !lam_x) return fail(ctx, PIC_EINVAL, "lam_x is NULL");
   launch_deposit_vjp(ctx->stream, ctx->geo, ptrs(state), nbar, lam_x, ctx->err);
   return check_launch(ctx, "deposit vjp");
+}
+
+// ---------------------------------------------------------------------------
+// Recorded trajectories: forward with checkpoints in the store's order, and
+// the reverse sweep that recomputes each segment out of place and runs the
+// tiled reverse kernel over it.
+// ---------------------------------------------------------------------------
+// Record (device, caller-owned): wq [cap], oidx [cap], the work items of the
+// binning, their count, then one state (pc, off, vel) per checkpoint.
+struct RecLayout {
+  size_t wq, oidx, items, nitems, ckpt0, state, total;
+  int nck;
+};
+
+static size_t state_bytes_of(int nd, int64_t cap) { return align_up((size_t)cap * 4 * (1 + nd + 3)); }
+
+static RecLayout rec_layout(const pic_ctx_t *c, int nsteps, int every) {
+  RecLayout R{};
+  const int64_t cap = c->cap;
+  R.nck = (nsteps + every - 1) / every;
+  size_t o = 0;
+  R.wq = o; o = align_up(o + 4 * (size_t)cap);
+  R.oidx = o; o = align_up(o + 4 * (size_t)cap);
+  R.items = o; o = align_up(o + sizeof(Item) * (size_t)c->items_cap);
+  R.nitems = o; o = align_up(o + sizeof(int));
+  R.ckpt0 = o;
+  R.state = state_bytes_of(c->ndim, cap);
+  R.total = o + R.state * (size_t)R.nck;
+  return R;
+}
+
+// A store whose per-particle state lives at base (wq / oidx from ref).
+static Store state_at(const pic_ctx_t *c, char *base, const Store &ref) {
+  Store S = ref;
+  const int64_t cap = c->cap;
+  S.pc = reinterpret_cast<int *>(base);
+  S.off = reinterpret_cast<float *>(base + 4 * cap);
+  S.vel = reinterpret_cast<float *>(base + 4 * cap * (1 + c->ndim));
+  return S;
+}
+
+static int copy_state(pic_ctx_t *c, const Store &dst, const Store &src) {
+  const size_t cap = (size_t)c->cap;
+  hipError_t e = hipMemcpyAsync(dst.pc, src.pc, 4 * cap, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dst.off, src.off, 4 * cap * c->ndim, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst.vel, src.vel, 4 * cap * 3, hipMemcpyDeviceToDevice, c->stream);
+  return hip_check(c, e, "copy state");
+}
+
+static int recorded_ok(pic_ctx_t *c, const pic_particles_t *p, int nsteps, int every) {
+  if (!c->tiled || c->nslab != 1 || c->force_untiled)
+    return fail(c, PIC_EINVAL, "recorded trajectories need a single-slab context on the tiled path");
+  if (nsteps < 1 || every < 1) return fail(c, PIC_EINVAL, "nsteps and every must be >= 1");
+  return check_particles(c, p, c->max_n[0], true, true);
+}
+
+static std::vector<int64_t> rec_key_of(const pic_ctx_t *c, int64_t n, int nsteps, int every, const void *rec) {
+  return {n, nsteps, every, c->lt, c->halo, c->chunk, (int64_t)reinterpret_cast<uintptr_t>(rec)};
+}
+
+size_t pic_record_bytes(pic_ctx_t *ctx, int32_t nsteps, int32_t every) {
+  if (!ctx || !ctx->tiled || ctx->nslab != 1 || nsteps < 1 || every < 1) return 0;
+  return rec_layout(ctx, nsteps, every).total;
+}
+
+size_t pic_backward_bytes(pic_ctx_t *ctx, int32_t every) {
+  if (!ctx || !ctx->tiled || ctx->nslab != 1 || every < 1) return 0;
+  const size_t cap = (size_t)ctx->cap, nn = (size_t)ctx->nnodes;
+  return state_bytes_of(ctx->ndim, ctx->cap) * (size_t)every + align_up(8 * nn) * (size_t)(every + 1) +
+         align_up(4 * cap * ctx->ndim) + align_up(4 * cap * 3) + 2 * align_up(4 * nn);
+}
+
+int pic_forward_record(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, int32_t every, void *record,
+                       size_t record_bytes) {
+  if (!ctx) return PIC_EINVAL;
+  int rc = recorded_ok(ctx, p, nsteps, every);
+  if (rc) return rc;
+  const RecLayout R = rec_layout(ctx, nsteps, every);
+  if (!record || record_bytes < R.total) return fail(ctx, PIC_ENOSPACE, "record buffer too small");
+  if (reinterpret_cast<uintptr_t>(record) % kAlign) return fail(ctx, PIC_EINVAL, "record must be 256-byte aligned");
+  char *rec = static_cast<char *>(record);
+  const int nd = ctx->ndim;
+  if ((rc = bind_counts(ctx, p))) return rc;
+  const int64_t n = p->n;
+  const Batch b = batch_of(ctx, n);
+  ensure_grid_blocks(ctx);
+  const PartPtrs cp = ptrs(p);
+  launch_import(ctx->stream, nd, ctx->sd.data(), &cp, 1, ctx->bb, b, ctx->chunk, ctx->st[0], ctx->err);
+  if ((rc = check_launch(ctx, "binning"))) return rc;
+  if ((rc = read_device_error(ctx))) return rc;
+  const Store &S = ctx->st[0];
+  hipError_t e = hipMemcpyAsync(rec + R.wq, S.wq, 4 * (size_t)ctx->cap, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(rec + R.oidx, S.oidx, 4 * (size_t)ctx->cap, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(rec + R.items, ctx->bb.items, sizeof(Item) * (size_t)ctx->items_cap, hipMemcpyDeviceToDevice,
+                       ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(rec + R.nitems, ctx->bb.num_items, sizeof(int), hipMemcpyDeviceToDevice, ctx->stream);
+  if ((rc = hip_check(ctx, e, "save binning"))) return rc;
+  const int64_t max_items = (int64_t)ctx->ntiles + (n + ctx->chunk - 1) / ctx->chunk;
+  launch_fill64(ctx->stream, ctx->n3[0], ctx->nnodes);
+  launch_fill64(ctx->stream, ctx->n3[1], ctx->nnodes);
+  launch_fill32(ctx->stream, ctx->drift, 4);
+  launch_deposit_tiled(ctx->stream, nd, ctx->sd[0].tg, b, S, ctx->bb, (int)max_items, ctx->n3[0]);
+  // no re-binning inside a recorded run: the store order stays the record's
+  for (int32_t s = 0; s < nsteps; ++s) {
+    if (s % every == 0 && (rc = copy_state(ctx, state_at(ctx, rec + R.ckpt0 + R.state * (s / every), S), S)))
+      return rc;
+    enqueue_step(ctx, b, S, s, false);
+    if ((rc = check_launch(ctx, "recorded step"))) return rc;
+  }
+  launch_export(ctx->stream, nd, ctx->sd[0], S, cp);
+  ctx->last_nodes = ctx->n3[nsteps % 3];
+  ctx->last_step = nsteps - 1;
+  if ((rc = check_launch(ctx, "export"))) return rc;
+  if ((rc = read_device_error(ctx))) return rc;
+  ctx->rec_key = rec_key_of(ctx, n, nsteps, every, record);
+  return PIC_OK;
+}
+
+int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps, int32_t every,
+                        const void *record, size_t record_bytes, void *scratch, size_t scratch_bytes, float *lam_x,
+                        float *lam_v, double *dtheta) {
+  if (!ctx) return PIC_EINVAL;
+  int rc = recorded_ok(ctx, p, nsteps, every);
+  if (rc) return rc;
+  const RecLayout R = rec_layout(ctx, nsteps, every);
+  if (!record || record_bytes < R.total) return fail(ctx, PIC_ENOSPACE, "record buffer too small");
+  if (ctx->rec_key != rec_key_of(ctx, p->n, nsteps, every, record))
+    return fail(ctx, PIC_EINVAL, "record was not written by pic_forward_record with these arguments and tiling");
+  const size_t need = pic_backward_bytes(ctx, every);
+  if (!scratch || scratch_bytes < need) return fail(ctx, PIC_ENOSPACE, "scratch buffer too small");
+  if (reinterpret_cast<uintptr_t>(scratch) % kAlign) return fail(ctx, PIC_EINVAL, "scratch must be 256-byte aligned");
+  if (!dtheta) return fail(ctx, PIC_EINVAL, "dtheta is NULL");
+  if (p->n > 0 && (!lam_x || !lam_v)) return fail(ctx, PIC_EINVAL, "lam_x or lam_v is NULL");
+  const int nd = ctx->ndim;
+  const int64_t n = p->n, cap = ctx->cap;
+  const size_t nn = (size_t)ctx->nnodes;
+  char *rec = const_cast<char *>(static_cast<const char *>(record));
+  char *scr = static_cast<char *>(scratch);
+  // scratch: states of one segment, node sums of one segment (+1), cotangents
+  const size_t sb = state_bytes_of(nd, cap);
+  char *traj = scr;
+  long long *N0 = reinterpret_cast<long long *>(traj + sb * (size_t)every);
+  auto Nk = [&](int k) { return reinterpret_cast<long long *>(reinterpret_cast<char *>(N0) + align_up(8 * nn) * k); };
+  float *lx = reinterpret_cast<float *>(reinterpret_cast<char *>(N0) + align_up(8 * nn) * (size_t)(every + 1));
+  float *lv = reinterpret_cast<float *>(reinterpret_cast<char *>(lx) + align_up(4 * (size_t)cap * nd));
+  float *nbA = reinterpret_cast<float *>(reinterpret_cast<char *>(lv) + align_up(4 * (size_t)cap * 3));
+  float *nbB = reinterpret_cast<float *>(reinterpret_cast<char *>(nbA) + align_up(4 * nn));
+  if ((rc = bind_counts(ctx, p))) return rc;
+  const Batch b = batch_of(ctx, n);
+  ensure_grid_blocks(ctx);
+  // the record's binning and constant per-particle data back into the store
+  Store &S = ctx->st[0];
+  hipError_t e = hipMemcpyAsync(S.wq, rec + R.wq, 4 * (size_t)cap, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(S.oidx, rec + R.oidx, 4 * (size_t)cap, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->bb.items, rec + R.items, sizeof(Item) * (size_t)ctx->items_cap, hipMemcpyDeviceToDevice,
+                       ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->bb.num_items, rec + R.nitems, sizeof(int), hipMemcpyDeviceToDevice, ctx->stream);
+  if ((rc = hip_check(ctx, e, "restore binning"))) return rc;
+  ctx->last_nodes = nullptr;
+  drop_graphs(ctx);
+  const int64_t max_items = (int64_t)ctx->ntiles + (n + ctx->chunk - 1) / ctx->chunk;
+  launch_to_store(ctx->stream, b, S, nd, lam_x, n, lx);
+  launch_to_store(ctx->stream, b, S, 3, lam_v, n, lv);
+  const Geo &g = ctx->geo;
+  const float *nbar_next = nullptr;
+  float *nb_cur = nbA, *nb_other = nbB;
+  for (int j = R.nck - 1; j >= 0; --j) {
+    const int s0 = j * every, len = std::min(every, nsteps - s0);
+    auto slot = [&](int k) {
+      return k == 0 ? state_at(ctx, rec + R.ckpt0 + R.state * j, S) : state_at(ctx, traj + sb * k, S);
+    };
+    // recompute the segment's states (out of place) and node sums
+    launch_fill64(ctx->stream, Nk(0), ctx->nnodes);
+    if (len > 1) launch_fill64(ctx->stream, Nk(1), ctx->nnodes);
+    launch_fill32(ctx->stream, ctx->drift, 4);
+    launch_deposit_tiled(ctx->stream, nd, ctx->sd[0].tg, b, slot(0), ctx->bb, (int)max_items, Nk(0));
+    for (int k = 0; k + 1 < len; ++k) {
+      const Drift dr = drift_of(ctx, k);
+      const Store in = slot(k), out = slot(k + 1);
+      launch_step_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, ctx->dcs[0], b, in, out, ctx->bb, ctx->grid_blocks,
+                        Nk(k), Nk(k + 1), Nk(k + 2), dr, ctx->partial, false, ctx->err);
+      launch_drifters(ctx->stream, nd, ctx->P, ctx->dcs[0], b, in, out, Nk(k), Nk(k + 1), dr, ctx->dacc, false,
+                      ctx->err);
+    }
+    if ((rc = check_launch(ctx, "recompute"))) return rc;
+    // reverse steps of the segment
+    for (int k = len - 1; k >= 0; --k) {
+      launch_grid(ctx->stream, g, Nk(k), ctx->dens, ctx->G);
+      launch_fillf(ctx->stream, nb_cur, ctx->nnodes);
+      launch_fillf(ctx->stream, ctx->Gbar, (int64_t)g.ncells * nd);
+      launch_adjoint_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), ctx->bb, (int)max_items, ctx->dens,
+                           ctx->G, nbar_next, lx, lv, nb_cur, ctx->Gbar, ctx->partial, ctx->err);
+      launch_gradient_vjp(ctx->stream, g, ctx->Gbar, nb_cur);
+      launch_reduce_theta(ctx->stream, ctx->partial, (int)max_items, 1.0 / ctx->pot.D, 1.0 / ctx->pot.r0, dtheta);
+      nbar_next = nb_cur;
+      std::swap(nb_cur, nb_other);
+      if ((rc = check_launch(ctx, "reverse step"))) return rc;
+    }
+  }
+  // deposit term of the initial positions, back to the caller's order
+  launch_deposit_vjp_store(ctx->stream, nd, b, state_at(ctx, rec + R.ckpt0, S), nbar_next, lx);
+  launch_from_store(ctx->stream, b, S, nd, lx, n, lam_x);
+  launch_from_store(ctx->stream, b, S, 3, lv, n, lam_v);
+  if ((rc = check_launch(ctx, "reverse sweep"))) return rc;
+  return read_device_error(ctx);
 }
 
 int pic_step_batch(pic_ctx_t *ctx, pic_particles_t *parts, int32_t nsteps, pic_diag_t *diag, int32_t diag_every) {

@@ -23,231 +23,9 @@
 // or by the deposit VJP at the end.  The fixed-point deposit is
 // differentiated as the plain CIC deposit it approximates to 2^-16 cells.
 #include "pic_internal.h"
+#include "pic_adjoint_dev.h"
 
 namespace pic {
-
-// ---------------------------------------------------------------------------
-// Derivative helpers
-// ---------------------------------------------------------------------------
-// d/dw_e of the multilinear interpolation interp<ND>(c, w).
-template <int ND>
-__device__ __forceinline__ void interp_grad(const float c[8], const float w[3], float dv[3]) {
-  const float d01 = c[1] - c[0], d23 = c[3] - c[2];
-  const float a = lerpf(c[0], c[1], w[0]), b = lerpf(c[2], c[3], w[0]);
-  if (ND == 2) {
-    dv[0] = lerpf(d01, d23, w[1]);
-    dv[1] = b - a;
-    dv[2] = 0.0f;
-  } else {
-    const float d45 = c[5] - c[4], d67 = c[7] - c[6];
-    const float e = lerpf(c[4], c[5], w[0]), f = lerpf(c[6], c[7], w[0]);
-    dv[0] = lerpf(lerpf(d01, d23, w[1]), lerpf(d45, d67, w[1]), w[2]);
-    dv[1] = lerpf(b - a, f - e, w[2]);
-    dv[2] = lerpf(e, f, w[1]) - lerpf(a, b, w[1]);
-  }
-}
-
-// Corner weights of the multilinear interpolation (corner bit d = upper along d).
-template <int ND>
-__device__ __forceinline__ void corner_weights(const float w[3], float S[8]) {
-#pragma unroll
-  for (int k = 0; k < (1 << ND); ++k) {
-    float s = (k & 1) ? w[0] : 1.0f - w[0];
-    s *= ((k >> 1) & 1) ? w[1] : 1.0f - w[1];
-    if (ND == 3) s *= ((k >> 2) & 1) ? w[2] : 1.0f - w[2];
-    S[k] = s;
-  }
-}
-
-// Stored cell and sign of the (possibly ghost) centre m for component d:
-// periodic axes wrap, reflecting axes mirror and negate the normal part.
-template <int ND>
-__device__ __forceinline__ int centre_ref(const Geo &g, int d, int m0, int m1, int m2, float &sign) {
-  int m[3] = {m0, m1, m2};
-  sign = 1.0f;
-#pragma unroll
-  for (int e = 0; e < ND; ++e) {
-    if (m[e] < 0) {
-      if (g.bc[e]) { m[e] = 0; sign = (e == d) ? -sign : sign; }
-      else m[e] += g.n[e];
-    } else if (m[e] >= g.n[e]) {
-      if (g.bc[e]) { m[e] = g.n[e] - 1; sign = (e == d) ? -sign : sign; }
-      else m[e] -= g.n[e];
-    }
-  }
-  return encode_cell<ND>(g, m);
-}
-
-template <int ND>
-__device__ __forceinline__ int corner_node(const Geo &g, const int idx[3], int k, float &kfac) {
-  const int a0 = node_axis(g, 0, idx[0] + (k & 1));
-  const int a1 = node_axis(g, 1, idx[1] + ((k >> 1) & 1));
-  const int a2 = ND == 3 ? node_axis(g, 2, idx[2] + ((k >> 2) & 1)) : 0;
-  kfac = node_density(g, 1ll, a0, a1, a2);  // kappa, doubled per wall
-  return node_index<ND>(g, a0, a1, a2);
-}
-
-// Eq. (1)-(3) reversed.  mu: cotangent of the reduced force Fh per axis.
-// Returns the cotangents of the gathered reduced density (an) and gradient
-// (aG), and adds the parameter terms: th[0] = sum mu Fh (-> dJ/dD = th0 / D),
-// th[1] = sum mu (s dFh/ds - Fh) (-> dJ/dr0 = th1 / r0), th[2] = dJ/ds_rep,
-// th[3] = dJ/dc_att.  The clamp of g and the density floor have zero
-// derivative where they act.
-template <int ND>
-__device__ __forceinline__ void pair_force_vjp(const Pot &P, float nh, const float G[3], const float mu[3],
-                                               float &an, float aG[3], float th[4]) {
-  an = 0.0f;
-  aG[0] = aG[1] = aG[2] = 0.0f;
-  if (!(nh > P.nfloor)) return;
-  const float q = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(nh) * (1.0f / 3.0f));
-  const float rinv = __builtin_amdgcn_rcpf(nh * q);
-  const float inv_n = __builtin_amdgcn_rcpf(nh);
-  const float dqdn = q * inv_n * (1.0f / 3.0f);
-#pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    const float graw = (G[d] * rinv) * (-1.0f / 3.0f);
-    const float g = fminf(fmaxf(graw, -P.gclamp), P.gclamp);
-    const bool free_g = graw > -P.gclamp && graw < P.gclamp;
-    const float hq = 0.5f * q * g;
-    const float sp = q - hq, sm = q + hq;
-    float k_p, dk_p, k_m, dk_m;
-    {
-      const float s2 = sp * sp, s6 = s2 * s2 * s2, s7 = s6 * sp, s12 = s6 * s6;
-      k_p = __builtin_fmaf(-s7, s6, s7);
-      dk_p = __builtin_fmaf(-13.0f, s12, 7.0f * s6);
-    }
-    {
-      const float s2 = sm * sm, s6 = s2 * s2 * s2, s7 = s6 * sm, s12 = s6 * s6;
-      k_m = __builtin_fmaf(-s7, s6, s7);
-      dk_m = __builtin_fmaf(-13.0f, s12, 7.0f * s6);
-    }
-    const bool rp = sp > 1.0f, rm = sm > 1.0f;  // repulsive branch (r < r0)
-    const float Mp = rp ? P.s_rep : P.c_att, Mm = rm ? P.s_rep : P.c_att;
-    const float A = Mp * dk_p, B = Mm * dk_m;
-    const float Fh = Mp * k_p - Mm * k_m;
-    const float dFdq = A * (1.0f - 0.5f * g) - B * (1.0f + 0.5f * g);
-    const float dFdg = -0.5f * q * (A + B);
-    const float dgdn = free_g ? (-4.0f / 3.0f) * g * inv_n : 0.0f;
-    const float dgdG = free_g ? (-1.0f / 3.0f) * rinv : 0.0f;
-    const float m = mu[d];
-    an += m * (dFdq * dqdn + dFdg * dgdn);
-    aG[d] = m * dFdg * dgdG;
-    th[0] += m * Fh;
-    th[1] += m * (A * sp - B * sm - Fh);
-    th[2] += m * ((rp ? k_p : 0.0f) - (rm ? k_m : 0.0f));
-    th[3] += m * ((rp ? 0.0f : k_p) - (rm ? 0.0f : k_m));
-  }
-}
-
-// Gather of n and G at (idx, f) with the corner values kept for the VJP.
-template <int ND>
-struct GatherState {
-  float cr[8];      // node densities at the cell corners
-  float vv[3][8];   // centre values per component
-  int cidx[8];      // stored cell of each stencil centre
-  float csign[3][8];
-  float t[3];       // centre-stencil weights
-  int c0[3];
-  float nh, Gp[3];
-};
-
-template <int ND>
-__device__ __forceinline__ void gather_for_vjp(const Geo &g, const float *__restrict__ dens,
-                                               const float *__restrict__ G, const int idx[3], const float f[3],
-                                               GatherState<ND> &s) {
-  const int x1 = node_axis(g, 0, idx[0] + 1), y1 = node_axis(g, 1, idx[1] + 1);
-  if (ND == 2) {
-    s.cr[0] = dens[node_index<2>(g, idx[0], idx[1], 0)];
-    s.cr[1] = dens[node_index<2>(g, x1, idx[1], 0)];
-    s.cr[2] = dens[node_index<2>(g, idx[0], y1, 0)];
-    s.cr[3] = dens[node_index<2>(g, x1, y1, 0)];
-  } else {
-    const int z1 = node_axis(g, 2, idx[2] + 1);
-    s.cr[0] = dens[node_index<3>(g, idx[0], idx[1], idx[2])];
-    s.cr[1] = dens[node_index<3>(g, x1, idx[1], idx[2])];
-    s.cr[2] = dens[node_index<3>(g, idx[0], y1, idx[2])];
-    s.cr[3] = dens[node_index<3>(g, x1, y1, idx[2])];
-    s.cr[4] = dens[node_index<3>(g, idx[0], idx[1], z1)];
-    s.cr[5] = dens[node_index<3>(g, x1, idx[1], z1)];
-    s.cr[6] = dens[node_index<3>(g, idx[0], y1, z1)];
-    s.cr[7] = dens[node_index<3>(g, x1, y1, z1)];
-  }
-  s.nh = interp<ND>(s.cr, f);
-  s.c0[2] = 0;
-  s.t[2] = 0.0f;
-#pragma unroll
-  for (int e = 0; e < ND; ++e) centre_stencil(idx[e], f[e], s.c0[e], s.t[e]);
-  s.Gp[2] = 0.0f;
-#pragma unroll
-  for (int k = 0; k < (1 << ND); ++k) {
-    const int m0 = s.c0[0] + (k & 1), m1 = s.c0[1] + ((k >> 1) & 1), m2 = ND == 3 ? s.c0[2] + ((k >> 2) & 1) : 0;
-    float sg;
-    s.cidx[k] = centre_ref<ND>(g, 0, m0, m1, m2, sg);
-    s.csign[0][k] = sg;
-#pragma unroll
-    for (int d = 1; d < ND; ++d) {
-      (void)centre_ref<ND>(g, d, m0, m1, m2, sg);
-      s.csign[d][k] = sg;
-    }
-#pragma unroll
-    for (int d = 0; d < ND; ++d) s.vv[d][k] = s.csign[d][k] * G[(int64_t)d * g.ncells + s.cidx[k]];
-  }
-#pragma unroll
-  for (int d = 0; d < ND; ++d) s.Gp[d] = interp<ND>(s.vv[d], s.t);
-}
-
-// Direct position term and scatters of the gather VJP.
-template <int ND>
-__device__ __forceinline__ void gather_vjp(const Geo &g, const int idx[3], const float f[3], const GatherState<ND> &s,
-                                           float an, const float aG[3], float lf[3], float *__restrict__ nbar,
-                                           float *__restrict__ Gbar) {
-  float dn[3];
-  interp_grad<ND>(s.cr, f, dn);
-#pragma unroll
-  for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(an, dn[e], lf[e]);
-#pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    float dg[3];
-    interp_grad<ND>(s.vv[d], s.t, dg);
-#pragma unroll
-    for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(aG[d], dg[e], lf[e]);
-  }
-  float S[8];
-  if (an != 0.0f) {
-    corner_weights<ND>(f, S);
-#pragma unroll
-    for (int k = 0; k < (1 << ND); ++k) {
-      float kf;
-      const int node = corner_node<ND>(g, idx, k, kf);
-      atomicAdd(&nbar[node], an * S[k]);
-    }
-  }
-  corner_weights<ND>(s.t, S);
-#pragma unroll
-  for (int d = 0; d < ND; ++d)
-    if (aG[d] != 0.0f)
-#pragma unroll
-      for (int k = 0; k < (1 << ND); ++k)
-        atomicAdd(&Gbar[(int64_t)d * g.ncells + s.cidx[k]], aG[d] * S[k] * s.csign[d][k]);
-}
-
-// Deposit term: lam_x += W sum_k kfac_k nbar_k dS_k/dx at (idx, f).
-template <int ND>
-__device__ __forceinline__ void deposit_term(const Geo &g, const float *__restrict__ nbar, const int idx[3],
-                                             const float f[3], int W, float lf[3]) {
-  float c[8];
-#pragma unroll
-  for (int k = 0; k < (1 << ND); ++k) {
-    float kf;
-    const int node = corner_node<ND>(g, idx, k, kf);
-    c[k] = kf * nbar[node];
-  }
-  float dd[3];
-  interp_grad<ND>(c, f, dd);
-  const float w = (float)W;
-#pragma unroll
-  for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(w, dd[e], lf[e]);
-}
 
 // ---------------------------------------------------------------------------
 // Kernels on caller arrays
@@ -280,30 +58,13 @@ __global__ void __launch_bounds__(256) k_adjoint(Geo g, Pot P, int64_t n, const 
       gather_for_vjp<ND>(g, dens, G, idx, f, gs);
       float mu[3] = {0.f, 0.f, 0.f}, lf[3] = {0.f, 0.f, 0.f};
       if (MODE == 0) {
-        float v[3] = {vel[p], vel[n + p], vel[2 * n + p]};
-        float Fh[3];
-        pair_force<ND>(P, gs.nh, gs.Gp, Fh);
-        const float F[3] = {Fh[0] * P.beta, Fh[1] * P.beta, ND == 3 ? Fh[2] * P.beta : 0.0f};
-        float vpre[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) vpre[d] = d < ND ? __builtin_fmaf(F[d], P.gv, v[d]) : v[d];
-        int idx2[3] = {idx[0], idx[1], idx[2]};
-        float f2[3] = {f[0], f[1], f[2]}, v2[3] = {v[0], v[1], v[2]};
-        e = push_particle<ND>(g, P, F, idx2, f2, v2);
-        if (e) atomicOr(err, e);
+        const float v[3] = {vel[p], vel[n + p], vel[2 * n + p]};
         float ln[3] = {lam_x[p], lam_x[n + p], ND == 3 ? lam_x[2 * n + p] : 0.0f};
-        if (nbar_next) deposit_term<ND>(g, nbar_next, idx2, f2, wq[p], ln);
         float lv[3] = {lam_v[p], lam_v[n + p], lam_v[2 * n + p]};
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-          const float s = (v2[d] == vpre[d]) ? 1.0f : -1.0f;  // mirrored at a wall
-          lv[d] = s * __builtin_fmaf(g.tau[d], ln[d], lv[d]);
-          lf[d] = s * ln[d];
-        }
+        e = reverse_push<ND>(g, P, idx, f, v, nbar_next ? wq[p] : 0, gs.nh, gs.Gp, nbar_next, ln, lv, lf, mu);
+        if (e) atomicOr(err, e);
 #pragma unroll
         for (int d = 0; d < 3; ++d) lam_v[(int64_t)d * n + p] = lv[d];
-#pragma unroll
-        for (int d = 0; d < ND; ++d) mu[d] = (lv[d] * P.gv) * P.beta;
       } else {
 #pragma unroll
         for (int d = 0; d < ND; ++d) {

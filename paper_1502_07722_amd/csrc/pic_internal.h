@@ -115,16 +115,31 @@ void launch_rebin(hipStream_t st, int ndim, const BinBufs &bb, const Batch &b, i
 void launch_export(hipStream_t st, int ndim, const SlabDesc &sd, const Store &s, const PartPtrs &cp);
 void launch_deposit_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Batch &b, const Store &s,
                           const BinBufs &bb, int max_items, long long *N);
+// s: the state read; o: where the next state is written (o == s: in place)
 void launch_step_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const DiagC &dc, const Batch &b,
-                       const Store &s, const BinBufs &bb, int grid, const long long *Ncur, long long *Nnext,
-                       long long *Nclear, const Drift &dr, double *partial, bool diag, uint32_t *err);
+                       const Store &s, const Store &o, const BinBufs &bb, int grid, const long long *Ncur,
+                       long long *Nnext, long long *Nclear, const Drift &dr, double *partial, bool diag,
+                       uint32_t *err);
 void launch_drifters(hipStream_t st, int ndim, const Pot &P, const DiagC &dc, const Batch &b, const Store &s,
-                     const long long *Ncur, long long *Nnext, const Drift &dr, double *dacc, bool diag,
-                     uint32_t *err);
+                     const Store &o, const long long *Ncur, long long *Nnext, const Drift &dr, double *dacc,
+                     bool diag, uint32_t *err);
 void launch_reduce_diag_slab(hipStream_t st, const double *part_p, const int *item_start, int tile_lo, int tile_hi,
                              double *dacc_k, const double *part_g, int nblk_g, pic_diag_t *out, int64_t step);
 int step_kernel_blocks_per_cu(int ndim, const TileGeo &tg);
 void launch_fill32(hipStream_t s, int *a, int64_t n);
+
+// reverse mode in the store (pic_tiled.hip); lx [ndim][cap], lv [3][cap]
+size_t adjoint_lds_bytes(const TileGeo &tg, int ndim);
+void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
+                          const BinBufs &bb, int max_items, const float *dens, const float *G,
+                          const float *nbar_next, float *lx, float *lv, float *nbar, float *Gbar, double *partial,
+                          uint32_t *err);
+void launch_deposit_vjp_store(hipStream_t st, int ndim, const Batch &b, const Store &s, const float *nbar,
+                              float *lx);
+void launch_to_store(hipStream_t st, const Batch &b, const Store &s, int k, const float *src, int64_t n,
+                     float *dst);
+void launch_from_store(hipStream_t st, const Batch &b, const Store &s, int k, const float *src, int64_t n,
+                       float *dst);
 
 // reverse mode on caller arrays (pic_adjoint.hip)
 void launch_fillf(hipStream_t st, float *a, int64_t n);

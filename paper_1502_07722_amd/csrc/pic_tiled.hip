@@ -21,6 +21,7 @@
 // the same arithmetic (same bits).  The int64 sums make the result
 // independent of order, tiling, binning period and batching.
 #include "pic_internal.h"
+#include "pic_adjoint_dev.h"
 
 namespace pic {
 
@@ -273,20 +274,28 @@ __device__ __forceinline__ bool in_window(const Geo &g, const Window &w, const i
 // Per-array views of the store with 32-bit element offsets (the tiled path
 // keeps max_n < 2^30, so byte offsets fit in 32 bits).
 struct StoreView {
-  int *pc;
-  float *off[3];
-  float *vel[3];
+  const int *pc;
+  const float *off[3];
+  const float *vel[3];
   const int *wq;
+  int *pc_o;           // outputs: the same arrays (in place) or the next
+  float *off_o[3];     // state's arrays (out of place, when a trajectory
+  float *vel_o[3];     // is recorded)
+  bool inplace;
 };
 
-__device__ __forceinline__ StoreView view_of(const Store &s) {
+__device__ __forceinline__ StoreView view_of(const Store &s, const Store &o) {
   StoreView v;
   v.pc = s.pc;
   v.wq = s.wq;
+  v.pc_o = o.pc;
+  v.inplace = s.pc == o.pc;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     v.off[d] = s.off + d * s.cap;
     v.vel[d] = s.vel + d * s.cap;
+    v.off_o[d] = o.off + d * o.cap;
+    v.vel_o[d] = o.vel + d * o.cap;
   }
   return v;
 }
@@ -351,12 +360,14 @@ __device__ __forceinline__ void advance_particle(const Geo &g, const Pot &P, con
   }
   err |= push_particle<ND, INTERIOR>(g, P, F, idx, f, v);
   const int pc2 = pack_cell<ND>(tg, idx);
-  if (pc2 != pc) at(sv.pc, p) = pc2;
+  if (pc2 != pc || !sv.inplace) at(sv.pc_o, p) = pc2;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    at(sv.off[d], p) = f[d];
-    at(sv.vel[d], p) = v[d];
+    at(sv.off_o[d], p) = f[d];
+    at(sv.vel_o[d], p) = v[d];
   }
+  // 2D: v_z is never changed; an out-of-place step still carries it over
+  if (ND == 2 && !sv.inplace) at(sv.vel_o[2], p) = DIAG ? v[2] : at(sv.vel[2], p);
   deposit_shares<ND>((uint32_t)W, f, tq);
 }
 
@@ -628,7 +639,7 @@ __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC
 // from an atomic counter until the step's items are done.  Every block also
 // clears its share of the node buffer two steps ahead.
 template <int ND, bool DIAG>
-__global__ void __launch_bounds__(256) k_step_tiled(Pot P, DiagC dc, Batch b, Store s,
+__global__ void __launch_bounds__(256) k_step_tiled(Pot P, DiagC dc, Batch b, Store s, Store o,
                                                     const Item *__restrict__ items,
                                                     const int *__restrict__ num_items,
                                                     const long long *__restrict__ Ncur,
@@ -643,7 +654,7 @@ __global__ void __launch_bounds__(256) k_step_tiled(Pot P, DiagC dc, Batch b, St
     *dr.work_next = 0;
   }
   const int nit = *num_items;
-  const StoreView sv = view_of(s);
+  const StoreView sv = view_of(s, o);
   uint32_t e_all = 0;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(dr.work, 1);
@@ -681,13 +692,13 @@ __global__ void __launch_bounds__(256) k_step_tiled(Pot P, DiagC dc, Batch b, St
 // Drifters (particles outside their tile window since the last binning):
 // the same cycle through the global node sums of their slab.
 template <int ND, bool DIAG>
-__global__ void __launch_bounds__(256) k_outliers(Pot P, DiagC dc, Batch b, Store s, Drift dr,
+__global__ void __launch_bounds__(256) k_outliers(Pot P, DiagC dc, Batch b, Store s, Store o, Drift dr,
                                                   const long long *__restrict__ Ncur,
                                                   unsigned long long *__restrict__ Nnext,
                                                   double *__restrict__ dacc, uint32_t *__restrict__ err) {
   const int n = *dr.count;
   uint32_t e_all = 0;
-  const StoreView sv = view_of(s);
+  const StoreView sv = view_of(s, o);
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
     const int p = dr.list[k];
     const int slab = find_slab(b.part_offs, b.nslab, p);
@@ -782,6 +793,176 @@ __global__ void __launch_bounds__(256) k_reduce_diag_slab(const double *__restri
 }
 
 // ---------------------------------------------------------------------------
+// Reverse mode in the store (recorded trajectories).  One block per item;
+// the node and cell-centre cotangents of the item's particles accumulate in
+// an LDS window laid out like the forward window (same origin, same folding),
+// the centre cotangents are mapped to the window nodes by the transpose of
+// the window's edge-difference stencil, and the window is flushed into the
+// global node cotangent with the forward's fold (periodic wrap, mirror across
+// reflecting walls), which makes the flush the exact transpose of the
+// forward's window staging.  Particles outside their window take the global
+// scatters (folded centres with the sign of the mirrored normal component).
+// The gathers read the step's global density and gradient grids, which hold
+// the same bits as the forward windows.
+// ---------------------------------------------------------------------------
+template <int ND>
+__global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, const Item *__restrict__ items,
+                                                       const int *__restrict__ num_items,
+                                                       const float *__restrict__ dens, const float *__restrict__ G,
+                                                       const float *__restrict__ nbar_next, float *__restrict__ lx,
+                                                       float *__restrict__ lv, float *__restrict__ nbar,
+                                                       float *__restrict__ Gbar, double *__restrict__ partial,
+                                                       uint32_t *__restrict__ err) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if ((int)blockIdx.x >= *num_items) {
+    if (threadIdx.x < 4) partial[(int64_t)blockIdx.x * 8 + threadIdx.x] = 0.0;
+    return;
+  }
+  const Item it = items[blockIdx.x];
+  const SlabDesc &sd = b.slabs[it.slab];
+  const Geo g = sd.g;
+  const TileGeo tg = sd.tg;
+  const Window w = make_window<ND>(tg, it.tile - sd.tile_off);
+  float *nw = reinterpret_cast<float *>(smem);  // [nW] node cotangents
+  float *gw = nw + w.nW;                         // [nC][ND] centre cotangents
+  for (int k = threadIdx.x; k < w.nW + w.nC * ND; k += blockDim.x) nw[k] = 0.0f;
+  __syncthreads();
+  const int cap = (int)s.cap;
+  const StoreView sv = view_of(s, s);
+  uint32_t e_all = 0;
+  double thd[4] = {0, 0, 0, 0};
+  for (int p = it.start + (int)threadIdx.x; p < it.end; p += blockDim.x) {
+    PState q;
+    load_state<ND, true>(sv, p, true, q);
+    int idx[3];
+    unpack_cell<ND>(tg, q.pc, idx);
+    GatherState<ND> gs;
+    gather_for_vjp<ND>(g, dens, G, idx, q.f, gs);
+    float ln[3] = {lx[p], lx[cap + p], ND == 3 ? lx[2 * cap + p] : 0.0f};
+    float lvv[3] = {lv[p], lv[cap + p], lv[2 * cap + p]};
+    float lf[3] = {0.f, 0.f, 0.f}, mu[3] = {0.f, 0.f, 0.f};
+    e_all |= reverse_push<ND>(g, P, idx, q.f, q.v, q.W, gs.nh, gs.Gp, nbar_next, ln, lvv, lf, mu);
+    float an, aG[3], th[4] = {0.f, 0.f, 0.f, 0.f};
+    pair_force_vjp<ND>(P, gs.nh, gs.Gp, mu, an, aG, th);
+    int l[3];
+    if (in_window<ND>(g, w, idx, 1, 3, l)) {
+      // direct position terms (as gather_vjp), scatters into the window
+      float dn[3];
+      interp_grad<ND>(gs.cr, q.f, dn);
+#pragma unroll
+      for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(an, dn[e], lf[e]);
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        float dg[3];
+        interp_grad<ND>(gs.vv[d], gs.t, dg);
+#pragma unroll
+        for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(aG[d], dg[e], lf[e]);
+      }
+      float S[8];
+      if (an != 0.0f) {
+        corner_weights<ND>(q.f, S);
+#pragma unroll
+        for (int k = 0; k < (1 << ND); ++k)
+          atomicAdd(&nw[win_node<ND>(w, l[0] + (k & 1), l[1] + ((k >> 1) & 1), ND == 3 ? l[2] + ((k >> 2) & 1) : 0)],
+                    an * S[k]);
+      }
+      corner_weights<ND>(gs.t, S);
+      int m[3] = {0, 0, 0};
+#pragma unroll
+      for (int e = 0; e < ND; ++e) m[e] = l[e] + (gs.c0[e] - idx[e]);  // window cell of the lower centre
+#pragma unroll
+      for (int k = 0; k < (1 << ND); ++k) {
+        const int c = win_centre<ND>(w, m[0] + (k & 1), m[1] + ((k >> 1) & 1), ND == 3 ? m[2] + ((k >> 2) & 1) : 0);
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+          if (aG[d] != 0.0f) atomicAdd(&gw[c * ND + d], aG[d] * S[k]);
+      }
+    } else {
+      gather_vjp<ND>(g, idx, q.f, gs, an, aG, lf, nbar, Gbar);
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) lx[d * cap + p] = lf[d];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lv[d * cap + p] = lvv[d];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) thd[i] += th[i];
+  }
+  __syncthreads();
+  // window centres -> window nodes (transpose of the staged gradient), flush
+  const int wc0 = w.wn[0] - 1, wc1 = w.wn[1] - 1;
+  for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
+    int a[3];
+    a[0] = k % w.wn[0];
+    const int r = k / w.wn[0];
+    a[1] = ND == 2 ? r : r % w.wn[1];
+    a[2] = ND == 2 ? 0 : r / w.wn[1];
+    float acc = nw[k];
+#pragma unroll
+    for (int bb = 0; bb < (1 << ND); ++bb) {
+      int m[3] = {0, 0, 0};
+      bool ok = true;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        m[d] = a[d] - ((bb >> d) & 1);
+        ok = ok && m[d] >= 0 && m[d] < w.wn[d] - 1;
+      }
+      if (!ok) continue;
+      const int c = ND == 2 ? m[0] + wc0 * m[1] : m[0] + wc0 * (m[1] + wc1 * m[2]);
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        const float v = g.gam[d] * gw[c * ND + d];
+        acc += ((bb >> d) & 1) ? v : -v;
+      }
+    }
+    if (acc != 0.0f) {
+      const int x = fold_node(g, 0, w.o[0] + a[0]), y = fold_node(g, 1, w.o[1] + a[1]);
+      const int z = ND == 3 ? fold_node(g, 2, w.o[2] + a[2]) : 0;
+      atomicAdd(&nbar[sd.node_off + node_index<ND>(g, x, y, z)], acc);
+    }
+  }
+  if (e_all) atomicOr(err, e_all);
+  block_reduce_store<4>(thd, partial + (int64_t)blockIdx.x * 8);
+}
+
+// lam_x += the deposit term at the store's positions (the last reverse step).
+template <int ND>
+__global__ void __launch_bounds__(256) k_deposit_vjp_store(Batch b, Store s, const float *__restrict__ nbar,
+                                                           float *__restrict__ lx) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= b.nparts) return;
+  const SlabDesc &sd = b.slabs[find_slab(b.part_offs, b.nslab, p)];
+  const int cap = (int)s.cap;
+  const StoreView sv = view_of(s, s);
+  PState q;
+  load_state<ND, false>(sv, p, true, q);
+  int idx[3];
+  unpack_cell<ND>(sd.tg, q.pc, idx);
+  float lf[3] = {lx[p], lx[cap + p], ND == 3 ? lx[2 * cap + p] : 0.0f};
+  deposit_term<ND>(sd.g, nbar + sd.node_off, idx, q.f, q.W, lf);
+#pragma unroll
+  for (int d = 0; d < ND; ++d) lx[d * cap + p] = lf[d];
+}
+
+// Cotangents between the caller's order and the store's: slot p of the store
+// holds caller particle part_off + oidx[p] of its slab (k arrays of stride
+// cap in the store, stride n in the caller's arrays).
+__global__ void __launch_bounds__(256) k_to_store(Batch b, Store s, int k, const float *__restrict__ src, int64_t n,
+                                                  float *__restrict__ dst) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= b.nparts) return;
+  const int o = s.oidx[p];
+  for (int d = 0; d < k; ++d) dst[(int64_t)d * s.cap + p] = src[(int64_t)d * n + o];
+}
+
+__global__ void __launch_bounds__(256) k_from_store(Batch b, Store s, int k, const float *__restrict__ src, int64_t n,
+                                                    float *__restrict__ dst) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= b.nparts) return;
+  const int o = s.oidx[p];
+  for (int d = 0; d < k; ++d) dst[(int64_t)d * n + o] = src[(int64_t)d * s.cap + p];
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
@@ -845,32 +1026,69 @@ void launch_deposit_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Bat
 }
 
 void launch_step_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const DiagC &dc, const Batch &b,
-                       const Store &s, const BinBufs &bb, int grid, const long long *Ncur, long long *Nnext,
-                       long long *Nclear, const Drift &dr, double *partial, bool diag, uint32_t *err) {
+                       const Store &s, const Store &o, const BinBufs &bb, int grid, const long long *Ncur,
+                       long long *Nnext, long long *Nclear, const Drift &dr, double *partial, bool diag,
+                       uint32_t *err) {
   if (grid <= 0) return;
   const size_t lds = window_lds_bytes(tg, ndim);
   unsigned long long *nn = (unsigned long long *)Nnext;
   if (diag)
-    PIC_ND(ndim, (k_step_tiled<ND, true><<<grid, 256, lds, st>>>(P, dc, b, s, bb.items, bb.num_items, Ncur, nn,
+    PIC_ND(ndim, (k_step_tiled<ND, true><<<grid, 256, lds, st>>>(P, dc, b, s, o, bb.items, bb.num_items, Ncur, nn,
                                                                    Nclear, dr, partial, err)));
   else
-    PIC_ND(ndim, (k_step_tiled<ND, false><<<grid, 256, lds, st>>>(P, dc, b, s, bb.items, bb.num_items, Ncur, nn,
+    PIC_ND(ndim, (k_step_tiled<ND, false><<<grid, 256, lds, st>>>(P, dc, b, s, o, bb.items, bb.num_items, Ncur, nn,
                                                                     Nclear, dr, partial, err)));
 }
 
 void launch_drifters(hipStream_t st, int ndim, const Pot &P, const DiagC &dc, const Batch &b, const Store &s,
-                     const long long *Ncur, long long *Nnext, const Drift &dr, double *dacc, bool diag,
-                     uint32_t *err) {
+                     const Store &o, const long long *Ncur, long long *Nnext, const Drift &dr, double *dacc,
+                     bool diag, uint32_t *err) {
   unsigned long long *nn = (unsigned long long *)Nnext;
   if (diag)
-    PIC_ND(ndim, (k_outliers<ND, true><<<kDriftBlocks, 256, 0, st>>>(P, dc, b, s, dr, Ncur, nn, dacc, err)));
+    PIC_ND(ndim, (k_outliers<ND, true><<<kDriftBlocks, 256, 0, st>>>(P, dc, b, s, o, dr, Ncur, nn, dacc, err)));
   else
-    PIC_ND(ndim, (k_outliers<ND, false><<<kDriftBlocks, 256, 0, st>>>(P, dc, b, s, dr, Ncur, nn, dacc, err)));
+    PIC_ND(ndim, (k_outliers<ND, false><<<kDriftBlocks, 256, 0, st>>>(P, dc, b, s, o, dr, Ncur, nn, dacc, err)));
 }
 
 void launch_reduce_diag_slab(hipStream_t st, const double *part_p, const int *item_start, int tile_lo, int tile_hi,
                              double *dacc_k, const double *part_g, int nblk_g, pic_diag_t *out, int64_t step) {
   k_reduce_diag_slab<<<1, 256, 0, st>>>(part_p, item_start, tile_lo, tile_hi, dacc_k, part_g, nblk_g, out, step);
+}
+
+size_t adjoint_lds_bytes(const TileGeo &tg, int ndim) {
+  size_t nW = 1, nC = 1;
+  for (int d = 0; d < ndim; ++d) {
+    size_t wn = (size_t)(1 << tg.lt[d]) + 2 * tg.H + 3;
+    nW *= wn;
+    nC *= wn - 1;
+  }
+  return (nW + nC * ndim) * 4;
+}
+
+void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
+                          const BinBufs &bb, int max_items, const float *dens, const float *G,
+                          const float *nbar_next, float *lx, float *lv, float *nbar, float *Gbar, double *partial,
+                          uint32_t *err) {
+  if (max_items <= 0) return;
+  const size_t lds = adjoint_lds_bytes(tg, ndim);
+  PIC_ND(ndim, (k_adjoint_tiled<ND><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, dens, G, nbar_next,
+                                                                   lx, lv, nbar, Gbar, partial, err)));
+}
+
+void launch_deposit_vjp_store(hipStream_t st, int ndim, const Batch &b, const Store &s, const float *nbar,
+                              float *lx) {
+  if (b.nparts <= 0) return;
+  PIC_ND(ndim, (k_deposit_vjp_store<ND><<<nblk(b.nparts), 256, 0, st>>>(b, s, nbar, lx)));
+}
+
+void launch_to_store(hipStream_t st, const Batch &b, const Store &s, int k, const float *src, int64_t n,
+                     float *dst) {
+  if (b.nparts > 0) k_to_store<<<nblk(b.nparts), 256, 0, st>>>(b, s, k, src, n, dst);
+}
+
+void launch_from_store(hipStream_t st, const Batch &b, const Store &s, int k, const float *src, int64_t n,
+                       float *dst) {
+  if (b.nparts > 0) k_from_store<<<nblk(b.nparts), 256, 0, st>>>(b, s, k, src, n, dst);
 }
 
 int step_kernel_blocks_per_cu(int ndim, const TileGeo &tg) {

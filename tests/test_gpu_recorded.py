@@ -1,0 +1,163 @@
+"""GPU tests of the recorded reverse sweep (pic_forward_record /
+pic_backward_record) and of the torch.autograd Functions built on it.
+
+* The recorded forward produces the same bits as pic_step.
+* The recorded sweep (checkpoints, out-of-place recompute, tiled reverse
+  kernel) agrees with the chain of per-step pic_adjoint_step calls on caller
+  arrays, which the adjoint parity tests pin to the FP64 references; the two
+  differ only in the order of float atomic sums (nodes, centres, parameter
+  partials), hence 1e-4 of each array's largest magnitude and 1e-5 relative
+  on dtheta.
+* The autograd crater gradient on the 16^3, 400-step case with checkpoints
+  every 20 steps matches central finite differences of the FP64 C oracle
+  (tests/golden/adjoint_fd_16cube.json) within the 1e-4 target.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1502_07722_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_16cube.json")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1502_07722_amd import binding
+    return binding
+
+
+def _case(nd):
+    if nd == 3:
+        wl = W.cfg_adjoint_3d(n=16, layers=8)
+        return wl.grid, wl.parts, wl.dt
+    grid, parts = W.make_slab(2, (64, 48), 24, 12, W.H_CELL, 31, fluence_Jcm2=3.0, R_cells=20.0)
+    return grid, parts, W.DT
+
+
+def _seed_cotangents(grid, dp):
+    """dJ/d(offset) of the crater functional at the state in dp."""
+    nd = grid.ndim
+    ax = nd - 1
+    lateral = int(np.prod(grid.n[:ax]))
+    cell = dp.cell.long()
+    y = (torch.div(cell, lateral, rounding_mode="floor").double() + dp.off[ax].double()) * grid.h[ax]
+    y_s = (grid.n[ax] // 2) * grid.h[ax]
+    s = torch.sigmoid((y - y_s) / grid.h[ax])
+    w = dp.wq.double() * 2.0 ** -20
+    lam_x = torch.zeros_like(dp.off)
+    lam_x[ax] = (w * s * (1 - s)).float()
+    lam_v = torch.zeros_like(dp.vel)
+    return lam_x, lam_v
+
+
+@pytest.mark.parametrize("nd", [2, 3])
+def test_recorded_forward_equals_pic_step(B, nd):
+    grid, parts, dt = _case(nd)
+    pot = W.Potential(c_att=0.27)
+    ctx = B.Context(grid, pot, dt, parts.n)
+    a = B.DeviceParticles.from_host(parts)
+    ctx.start_leapfrog(a)
+    b = a.clone()
+    ctx.pic_step(a, 37)
+    ctx.pic_forward_record(b, 37, 10)
+    torch.cuda.synchronize()
+    assert torch.equal(a.cell, b.cell) and torch.equal(a.off, b.off) and torch.equal(a.vel, b.vel)
+
+
+@pytest.mark.parametrize("nd", [2, 3])
+def test_recorded_sweep_matches_per_step_chain(B, nd):
+    grid, parts, dt = _case(nd)
+    pot = W.Potential(c_att=0.27)
+    nsteps, every = 30, 8  # a ragged last segment
+    ctx = B.Context(grid, pot, dt, parts.n)
+    dp = B.DeviceParticles.from_host(parts)
+    ctx.start_leapfrog(dp)
+    start = dp.clone()
+    # per-step chain on caller arrays
+    states = [dp.clone()]
+    for _ in range(nsteps):
+        node = ctx.pic_deposit(dp)
+        F = ctx.pic_force(dp, node)
+        ctx.pic_push(dp, F)
+        states.append(dp.clone())
+    lam_x, lam_v = _seed_cotangents(grid, states[-1])
+    lx_ref, lv_ref = lam_x.clone(), lam_v.clone()
+    dth_ref = torch.zeros(4, dtype=torch.float64, device="cuda")
+    nbar_next = None
+    for k in range(nsteps - 1, -1, -1):
+        node = ctx.pic_deposit(states[k])
+        nbar, _ = ctx.pic_adjoint_step(states[k], node, nbar_next, lx_ref, lv_ref, dtheta=dth_ref)
+        nbar_next = nbar
+    ctx.pic_deposit_vjp(states[0], nbar_next, lx_ref)
+    ctx.pic_sync()
+    # recorded
+    rec_state = start.clone()
+    rec = ctx.pic_forward_record(rec_state, nsteps, every)
+    assert torch.equal(rec_state.off, states[-1].off) and torch.equal(rec_state.cell, states[-1].cell)
+    lx, lv = lam_x.clone(), lam_v.clone()
+    dth = ctx.pic_backward_record(rec_state, rec, lx, lv)
+    torch.cuda.synchronize()
+    for d in range(nd):
+        ref = lx_ref[d].double().cpu().numpy()
+        assert np.abs(lx[d].double().cpu().numpy() - ref).max() <= 1e-4 * np.abs(ref).max(), d
+    for d in range(3):
+        ref = lv_ref[d].double().cpu().numpy()
+        got = lv[d].double().cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-4 * max(np.abs(ref).max(), 1e-30), d
+    got, ref = dth.cpu().numpy(), dth_ref.cpu().numpy()
+    assert np.all(np.abs(got - ref) <= 1e-5 * np.abs(ref) + 1e-12), (got, ref)
+
+
+def test_backward_refuses_a_foreign_record(B):
+    grid, parts, dt = _case(3)
+    pot = W.Potential(c_att=0.27)
+    ctx = B.Context(grid, pot, dt, parts.n)
+    dp = B.DeviceParticles.from_host(parts)
+    rec = ctx.pic_forward_record(dp, 12, 4)
+    lam_x = torch.zeros_like(dp.off)
+    lam_v = torch.zeros_like(dp.vel)
+    bad = dict(rec, nsteps=11)
+    with pytest.raises(B.PicError):
+        ctx.pic_backward_record(dp, bad, lam_x, lam_v)
+    ctx.pic_set_tiling(4, 1, 2048, -1)  # a different tiling invalidates the record
+    with pytest.raises(B.PicError):
+        ctx.pic_backward_record(dp, rec, lam_x, lam_v)
+
+
+def test_autograd_crater_gradient_matches_oracle_finite_differences(B):
+    from paper_1502_07722_amd import autograd as A
+    with open(GOLDEN) as fh:
+        gold = json.load(fh)
+    wl = W.cfg_adjoint_3d(n=16, layers=8)
+    grid, p = wl.grid, wl.parts
+    nsteps, y_s, tau, fref = gold["nsteps"], gold["y_s"], gold["tau"], gold["fluence"]
+    dev = torch.device("cuda")
+    cell = torch.from_numpy(p.cell).to(dev)
+    off0 = torch.from_numpy(p.off).to(dev)
+    vth = torch.from_numpy(p.v_thermal).to(dev)
+    xi = torch.from_numpy(p.xi).to(dev)
+    sig = torch.from_numpy(p.sigma.astype(np.float32)).to(dev)
+    wq = torch.from_numpy(p.wq).to(dev)
+    for name, keys in (("altered", ("D", "s_rep", "c_att", "F")), ("unaltered", ("r0",))):
+        rec = gold["potentials"][name]
+        pot = W.Potential(c_att=rec["c_att"])
+        ctx = B.Context(grid, pot, wl.dt, p.n)
+        theta = A.theta_of(pot).requires_grad_(True)
+        fl = torch.tensor(fref, dtype=torch.float64, device=dev, requires_grad=True)
+        J, _, _ = A.crater_objective(ctx, cell, off0, vth, xi, sig, fref, fl, wq, theta, nsteps, 20, y_s, tau)
+        J.backward()
+        assert abs(J.item() - rec["J"]) <= 1e-5 * abs(rec["J"])
+        got = dict(zip(A.THETA_KEYS, theta.grad.cpu().numpy()))
+        got["F"] = fl.grad.item()
+        for k in keys:
+            fd = rec["dJ"][k]["0.0001"]
+            fd_err = abs(rec["dJ"][k]["0.001"] - fd)
+            print(f"[{name}] dJ/d{k}: autograd {got[k]:.9e} finite difference {fd:.9e} "
+                  f"rel {abs(got[k] - fd) / abs(fd):.2e}")
+            assert abs(got[k] - fd) <= 1e-4 * abs(fd) + fd_err, (k, got[k], fd)
