@@ -25,7 +25,7 @@ HBM_PEAK_GBS = 8000.0
 # 4*ndim + velocity 12 + weight 4, writes cell 4 + offsets 4*ndim + velocity
 # 12: 52 B in 2D, 60 B in 3D -- plus 16 B per node (int64 sums written once
 # and read once).
-DEFAULTS = {"large": (2000, 20), "heated": (5000, 20), "small": (200, 20), "sweep": (1000, 12)}
+DEFAULTS = {"large": (2000, 20), "heated": (5000, 20), "small": (200, 20), "sweep": (1000, 12), "adjoint": (400, 1)}
 
 
 COUNTERS = {"large": "profiles/k_step_tiled_slab2d_4096x2048_32ppc.counters.json"}
@@ -153,14 +153,86 @@ def run_sweep(steps, warmup, log_fn=log):
             "slab_particles": [w.parts.n for w in wls]}
 
 
+def run_adjoint(log_fn=log, every=20):
+    """The 3D adjoint workload: 128^3 cells of 2 nm, slab in the lower 64
+    layers, 8 ppc, 1.5 J/cm^2, 400 steps.  Forward = pic_step over the 400
+    steps from v(-1/2).  Gradient = torch.autograd through the crater
+    functional: recorded forward (checkpoints every 20 steps) + reverse sweep
+    (segment recompute + reverse steps) + the start and heating terms."""
+    import numpy as np
+    import torch
+    from paper_1502_07722_amd import autograd as A
+    from paper_1502_07722_amd import binding as B
+    from paper_1502_07722_amd import workloads as W
+
+    t0 = time.perf_counter()
+    wl = W.cfg_adjoint_3d()
+    g, p = wl.grid, wl.parts
+    log_fn(f"adjoint workload {wl.name}: {p.n} particles, generated in {time.perf_counter() - t0:.1f} s")
+    c_att, _ = B.pic_calibrate_catt(g, wl.pot, W.N_SOLID, 8)
+    pot = W.Potential(c_att=c_att)
+    nsteps = wl.steps
+    dev = torch.device("cuda:0")
+    cell = torch.from_numpy(p.cell).to(dev)
+    off0 = torch.from_numpy(p.off).to(dev)
+    vth = torch.from_numpy(p.v_thermal).to(dev)
+    xi = torch.from_numpy(p.xi).to(dev)
+    sig = torch.from_numpy(p.sigma.astype(np.float32)).to(dev)
+    wq = torch.from_numpy(p.wq).to(dev)
+    ctx = B.Context(g, pot, wl.dt, p.n, device=dev)
+    y_s = wl.slab_rows * g.h[2]
+    tau = g.h[2]
+    fref = wl.fluence
+    # plain forward: the same start state, pic_step over nsteps
+    dp = B.DeviceParticles(cell.clone(), off0.clone(), (vth + sig[None, :] * xi).contiguous(), wq)
+    ctx.start_leapfrog(dp)
+    warm = dp.clone()
+    ctx.pic_step(warm, 20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.pic_step(dp, nsteps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    del warm
+
+    def grad_once():
+        theta = A.theta_of(pot).requires_grad_(True)
+        fl = torch.tensor(fref, dtype=torch.float64, device=dev, requires_grad=True)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        J, _, _ = A.crater_objective(ctx, cell, off0, vth, xi, sig, fref, fl, wq, theta, nsteps, every, y_s, tau)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        return J.item(), theta.grad.cpu().numpy(), fl.grad.item(), tb - ta, tc - tb
+
+    grad_once()  # warm-up (allocations, code objects)
+    J, gth, gF, t_rec, t_bwd = grad_once()
+    log_fn(f"adjoint: forward {t_fwd * 1e3:.1f} ms, recorded forward {t_rec * 1e3:.1f} ms, "
+           f"backward {t_bwd * 1e3:.1f} ms")
+    del ctx
+    torch.cuda.empty_cache()
+    return {"workload": f"{wl.name}: 128^3 cells, slab 64 layers, 8 ppc, 1.5 J/cm^2, {nsteps} steps, "
+                        f"checkpoint every {every}",
+            "particles": int(p.n), "steps": nsteps, "checkpoint_every": every,
+            "forward_s": t_fwd, "recorded_forward_s": t_rec, "backward_s": t_bwd,
+            "adjoint_over_forward": t_bwd / t_fwd, "gradient_over_forward": (t_rec + t_bwd) / t_fwd,
+            "forward_particle_steps_per_s": p.n * nsteps / t_fwd,
+            "J": J, "dJ_dtheta": {k: float(v) for k, v in zip(A.THETA_KEYS, gth)}, "dJ_dfluence": gF}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="large", choices=["large", "heated", "small", "sweep"])
+    ap.add_argument("--workload", default="large", choices=["large", "heated", "small", "sweep", "adjoint"])
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the batched intensity sweep (plain loop vs batched) reported in the same line")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the 3D adjoint timing (gradient vs forward cost) reported in the same line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration for rocprofv3 --pmc)")
@@ -176,6 +248,16 @@ def main():
     import torch
     from paper_1502_07722_amd import binding as B
     from paper_1502_07722_amd import workloads as W
+
+    if args.workload == "adjoint":
+        res = run_adjoint()
+        out = {"metric": "adjoint time / forward time (400 steps, checkpoint every 20)",
+               "value": res["adjoint_over_forward"], "unit": "ratio", "n_gpus": 1, "steps": res["steps"],
+               "warmup": 1, "ms_per_step": res["backward_s"] / res["steps"] * 1e3, "higher_is_better": False,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": res["workload"]}, "adjoint": res}
+        print(json.dumps(out), flush=True)
+        return
 
     if args.workload == "sweep":
         res = run_sweep(steps, warmup)
@@ -262,6 +344,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_sweep and args.workload == "large":
         out["sweep"] = run_sweep(*DEFAULTS["sweep"])
+    if not args.no_adjoint and args.workload == "large":
+        out["adjoint"] = run_adjoint()
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, pot)

@@ -1196,6 +1196,7 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
   const int64_t max_items = (int64_t)ctx->ntiles + (n + ctx->chunk - 1) / ctx->chunk;
   launch_to_store(ctx->stream, b, S, nd, lam_x, n, lx);
   launch_to_store(ctx->stream, b, S, 3, lam_v, n, lv);
+  launch_fill64(ctx->stream, reinterpret_cast<long long *>(ctx->dacc), 8);
   const Geo &g = ctx->geo;
   const float *nbar_next = nullptr;
   float *nb_cur = nbA, *nb_other = nbB;
@@ -1223,10 +1224,12 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
       launch_grid(ctx->stream, g, Nk(k), ctx->dens, ctx->G);
       launch_fillf(ctx->stream, nb_cur, ctx->nnodes);
       launch_fillf(ctx->stream, ctx->Gbar, (int64_t)g.ncells * nd);
-      launch_adjoint_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), ctx->bb, (int)max_items, ctx->dens,
-                           ctx->G, nbar_next, lx, lv, nb_cur, ctx->Gbar, ctx->partial, ctx->err);
+      launch_adjoint_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), ctx->bb, (int)max_items, Nk(k),
+                           ctx->dens, ctx->G, nbar_next, lx, lv, nb_cur, ctx->Gbar, ctx->drift + 4, ctx->drift,
+                           ctx->partial, ctx->dacc, ctx->err);
       launch_gradient_vjp(ctx->stream, g, ctx->Gbar, nb_cur);
-      launch_reduce_theta(ctx->stream, ctx->partial, (int)max_items, 1.0 / ctx->pot.D, 1.0 / ctx->pot.r0, dtheta);
+      launch_reduce_theta(ctx->stream, ctx->partial, (int)max_items, 1.0 / ctx->pot.D, 1.0 / ctx->pot.r0, dtheta,
+                          ctx->dacc);
       nbar_next = nb_cur;
       std::swap(nb_cur, nb_other);
       if ((rc = check_launch(ctx, "reverse step"))) return rc;

@@ -150,7 +150,8 @@ __global__ void k_fillf(float *__restrict__ a, int64_t n) {
 
 // Fixed-order sum of the per-block parameter partials into dtheta (+=).
 __global__ void __launch_bounds__(256) k_reduce_theta(const double *__restrict__ partial, int nblocks,
-                                                      double s0, double s1, double *__restrict__ dtheta) {
+                                                      double s0, double s1, double *__restrict__ dtheta,
+                                                      double *__restrict__ extra) {
   __shared__ double red[4][256];
   double acc[4] = {0, 0, 0, 0};
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
@@ -167,7 +168,12 @@ __global__ void __launch_bounds__(256) k_reduce_theta(const double *__restrict__
   }
   if (threadIdx.x < 4) {
     const double scale = threadIdx.x == 0 ? s0 : (threadIdx.x == 1 ? s1 : 1.0);
-    dtheta[threadIdx.x] += red[threadIdx.x][0] * scale;
+    double v = red[threadIdx.x][0];
+    if (extra) {
+      v += extra[threadIdx.x];
+      extra[threadIdx.x] = 0.0;
+    }
+    dtheta[threadIdx.x] += v * scale;
   }
 }
 
@@ -216,8 +222,9 @@ void launch_deposit_vjp(hipStream_t st, const Geo &g, const PartPtrs &p, const f
                        lam_x, err);
 }
 
-void launch_reduce_theta(hipStream_t st, const double *partial, int nblocks, double s0, double s1, double *dtheta) {
-  hipLaunchKernelGGL(k_reduce_theta, dim3(1), dim3(256), 0, st, partial, nblocks, s0, s1, dtheta);
+void launch_reduce_theta(hipStream_t st, const double *partial, int nblocks, double s0, double s1, double *dtheta,
+                         double *extra) {
+  hipLaunchKernelGGL(k_reduce_theta, dim3(1), dim3(256), 0, st, partial, nblocks, s0, s1, dtheta, extra);
 }
 
 }  // namespace pic

@@ -232,34 +232,58 @@ __device__ __forceinline__ void deposit_term(const Geo &g, const float *__restri
   for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(w, dd[e], lf[e]);
 }
 
-// Reverse drift and kick of one particle.  The forward step from (idx, f, v)
-// with the gathered (nh, Gp) is recomputed (same bits as the forward push,
-// including which walls mirror the particle); ln = lam_x(n+1) without its
-// deposit term, completed here from nbar_next when given; lv = lam_v(n+1/2)
-// in, lam_v(n-1/2) out.  Returns the push error bits, the position term lf of
-// lam_x(n) and the cotangent mu of the reduced force.
+// The forward step of one particle recomputed from (idx, f, v) with the
+// gathered (nh, Gp): same bits as the forward push, and which axes a wall
+// mirrored (sign -1).
+struct PushRecord {
+  int idx2[3];
+  float f2[3];
+  float sgn[3];
+};
+
+template <int ND>
+__device__ __forceinline__ uint32_t recompute_push(const Geo &g, const Pot &P, const int idx[3], const float f[3],
+                                                   const float v[3], float nh, const float Gp[3], PushRecord &r) {
+  float Fh[3];
+  pair_force<ND>(P, nh, Gp, Fh);
+  const float F[3] = {Fh[0] * P.beta, Fh[1] * P.beta, ND == 3 ? Fh[2] * P.beta : 0.0f};
+  float vpre[3], v2[3] = {v[0], v[1], v[2]};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    vpre[d] = d < ND ? __builtin_fmaf(F[d], P.gv, v[d]) : v[d];
+    r.idx2[d] = idx[d];
+    r.f2[d] = f[d];
+  }
+  const uint32_t e = push_particle<ND>(g, P, F, r.idx2, r.f2, v2);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) r.sgn[d] = (d < ND && v2[d] != vpre[d]) ? -1.0f : 1.0f;
+  return e;
+}
+
+// Reverse drift and kick: ln = complete lam_x(n+1), lv = lam_v(n+1/2) in,
+// lam_v(n-1/2) out; lf = position term of lam_x(n); mu = cotangent of the
+// reduced force.
+template <int ND>
+__device__ __forceinline__ void reverse_drift_kick(const Geo &g, const Pot &P, const PushRecord &r, const float ln[3],
+                                                   float lv[3], float lf[3], float mu[3]) {
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    lv[d] = r.sgn[d] * __builtin_fmaf(g.tau[d], ln[d], lv[d]);
+    lf[d] = r.sgn[d] * ln[d];
+    mu[d] = (lv[d] * P.gv) * P.beta;
+  }
+}
+
+// Both, with the deposit term of step n+1 taken from the global nbar_next.
 template <int ND>
 __device__ __forceinline__ uint32_t reverse_push(const Geo &g, const Pot &P, const int idx[3], const float f[3],
                                                  const float v[3], int W, float nh, const float Gp[3],
                                                  const float *__restrict__ nbar_next, float ln[3], float lv[3],
                                                  float lf[3], float mu[3]) {
-  float Fh[3];
-  pair_force<ND>(P, nh, Gp, Fh);
-  const float F[3] = {Fh[0] * P.beta, Fh[1] * P.beta, ND == 3 ? Fh[2] * P.beta : 0.0f};
-  float vpre[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) vpre[d] = d < ND ? __builtin_fmaf(F[d], P.gv, v[d]) : v[d];
-  int idx2[3] = {idx[0], idx[1], idx[2]};
-  float f2[3] = {f[0], f[1], f[2]}, v2[3] = {v[0], v[1], v[2]};
-  const uint32_t e = push_particle<ND>(g, P, F, idx2, f2, v2);
-  if (nbar_next) deposit_term<ND>(g, nbar_next, idx2, f2, W, ln);
-#pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    const float s = (v2[d] == vpre[d]) ? 1.0f : -1.0f;  // mirrored at a wall
-    lv[d] = s * __builtin_fmaf(g.tau[d], ln[d], lv[d]);
-    lf[d] = s * ln[d];
-    mu[d] = (lv[d] * P.gv) * P.beta;
-  }
+  PushRecord r;
+  const uint32_t e = recompute_push<ND>(g, P, idx, f, v, nh, Gp, r);
+  if (nbar_next) deposit_term<ND>(g, nbar_next, r.idx2, r.f2, W, ln);
+  reverse_drift_kick<ND>(g, P, r, ln, lv, lf, mu);
   return e;
 }
 

@@ -131,9 +131,9 @@ void launch_fill32(hipStream_t s, int *a, int64_t n);
 // reverse mode in the store (pic_tiled.hip); lx [ndim][cap], lv [3][cap]
 size_t adjoint_lds_bytes(const TileGeo &tg, int ndim);
 void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
-                          const BinBufs &bb, int max_items, const float *dens, const float *G,
-                          const float *nbar_next, float *lx, float *lv, float *nbar, float *Gbar, double *partial,
-                          uint32_t *err);
+                          const BinBufs &bb, int max_items, const long long *N, const float *dens, const float *G,
+                          const float *nbar_next, float *lx, float *lv, float *nbar, float *Gbar, int *dlist,
+                          int *dcount, double *partial, double *dacc, uint32_t *err);
 void launch_deposit_vjp_store(hipStream_t st, int ndim, const Batch &b, const Store &s, const float *nbar,
                               float *lx);
 void launch_to_store(hipStream_t st, const Batch &b, const Store &s, int k, const float *src, int64_t n,
@@ -149,6 +149,9 @@ int launch_adjoint(hipStream_t st, const Geo &g, const Pot &P, const PartPtrs &p
 void launch_gradient_vjp(hipStream_t st, const Geo &g, const float *Gbar, float *nbar);
 void launch_deposit_vjp(hipStream_t st, const Geo &g, const PartPtrs &p, const float *nbar, float *lam_x,
                         uint32_t *err);
-void launch_reduce_theta(hipStream_t st, const double *partial, int nblocks, double s0, double s1, double *dtheta);
+// dtheta[0..3] += scale * (sum of the block partials + extra[0..3]); extra
+// (nullable) is cleared
+void launch_reduce_theta(hipStream_t st, const double *partial, int nblocks, double s0, double s1, double *dtheta,
+                         double *extra = nullptr);
 
 }  // namespace pic

@@ -793,26 +793,34 @@ __global__ void __launch_bounds__(256) k_reduce_diag_slab(const double *__restri
 }
 
 // ---------------------------------------------------------------------------
-// Reverse mode in the store (recorded trajectories).  One block per item;
-// the node and cell-centre cotangents of the item's particles accumulate in
-// an LDS window laid out like the forward window (same origin, same folding),
-// the centre cotangents are mapped to the window nodes by the transpose of
-// the window's edge-difference stencil, and the window is flushed into the
-// global node cotangent with the forward's fold (periodic wrap, mirror across
-// reflecting walls), which makes the flush the exact transpose of the
-// forward's window staging.  Particles outside their window take the global
-// scatters (folded centres with the sign of the mirrored normal component).
-// The gathers read the step's global density and gradient grids, which hold
-// the same bits as the forward windows.
+// Reverse mode in the store (recorded trajectories).  One block per item.
+// The item's window (same origin and folding as the forward window) is
+// staged in LDS twice: the node densities of step n, and the next step's node
+// cotangent times the node's density factor.  Per particle, the 3^ND window
+// nodes around its centre stencil give the 2^ND centre gradients through the
+// forward's own centre_gradient (same bits as the forward), and the
+// cotangents of the gathered density and gradient go back to those 3^ND
+// nodes (the transpose of that stencil) in registers, then into an LDS node
+// accumulator; the accumulator is flushed into the global node cotangent with
+// the window's fold (periodic wrap, mirror across reflecting walls): the
+// exact transpose of the forward's window staging.  Particles outside their
+// window take the global path (global density / gradient grids, scatters to
+// the global node and centre cotangents).
 // ---------------------------------------------------------------------------
+template <int ND>
+__device__ __forceinline__ constexpr int b3(int a0, int a1, int a2) {
+  return ND == 2 ? a0 + 3 * a1 : a0 + 3 * (a1 + 3 * a2);
+}
+
 template <int ND>
 __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, const Item *__restrict__ items,
                                                        const int *__restrict__ num_items,
-                                                       const float *__restrict__ dens, const float *__restrict__ G,
+                                                       const long long *__restrict__ Ncur,
                                                        const float *__restrict__ nbar_next, float *__restrict__ lx,
                                                        float *__restrict__ lv, float *__restrict__ nbar,
-                                                       float *__restrict__ Gbar, double *__restrict__ partial,
-                                                       uint32_t *__restrict__ err) {
+                                                       int *__restrict__ dlist, int *__restrict__ dcount,
+                                                       double *__restrict__ partial, uint32_t *__restrict__ err) {
+  constexpr int K3 = ND == 2 ? 9 : 27;
   extern __shared__ __align__(16) unsigned char smem[];
   if ((int)blockIdx.x >= *num_items) {
     if (threadIdx.x < 4) partial[(int64_t)blockIdx.x * 8 + threadIdx.x] = 0.0;
@@ -823,105 +831,205 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
   const Geo g = sd.g;
   const TileGeo tg = sd.tg;
   const Window w = make_window<ND>(tg, it.tile - sd.tile_off);
-  float *nw = reinterpret_cast<float *>(smem);  // [nW] node cotangents
-  float *gw = nw + w.nW;                         // [nC][ND] centre cotangents
-  for (int k = threadIdx.x; k < w.nW + w.nC * ND; k += blockDim.x) nw[k] = 0.0f;
+  float *dw = reinterpret_cast<float *>(smem);  // [nW] node densities of step n
+  float *nx = dw + w.nW;                         // [nW] kfac * nbar of step n+1
+  float *acc = nx + w.nW;                        // [nW] node cotangent of step n
+  const long long *N = Ncur + sd.node_off;
+  const float *nbn = nbar_next ? nbar_next + sd.node_off : nullptr;
+  for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
+    const int a0 = k % w.wn[0], r = k / w.wn[0];
+    const int a1 = ND == 2 ? r : r % w.wn[1];
+    const int a2 = ND == 2 ? 0 : r / w.wn[1];
+    const int x = fold_node(g, 0, w.o[0] + a0), y = fold_node(g, 1, w.o[1] + a1);
+    const int z = ND == 3 ? fold_node(g, 2, w.o[2] + a2) : 0;
+    const int node = node_index<ND>(g, x, y, z);
+    dw[k] = node_density(g, N[node], x, y, z);
+    nx[k] = nbn ? node_density(g, 1ll, x, y, z) * nbn[node] : 0.0f;
+    acc[k] = 0.0f;
+  }
   __syncthreads();
   const int cap = (int)s.cap;
   const StoreView sv = view_of(s, s);
   uint32_t e_all = 0;
   double thd[4] = {0, 0, 0, 0};
-  for (int p = it.start + (int)threadIdx.x; p < it.end; p += blockDim.x) {
+  for (int base = it.start; base < it.end; base += blockDim.x) {
+    const int p = base + (int)threadIdx.x;
+    const bool live = p < it.end;
     PState q;
-    load_state<ND, true>(sv, p, true, q);
-    int idx[3];
+    load_state<ND, true>(sv, p, live, q);
+    int idx[3], l[3];
     unpack_cell<ND>(tg, q.pc, idx);
-    GatherState<ND> gs;
-    gather_for_vjp<ND>(g, dens, G, idx, q.f, gs);
-    float ln[3] = {lx[p], lx[cap + p], ND == 3 ? lx[2 * cap + p] : 0.0f};
-    float lvv[3] = {lv[p], lv[cap + p], lv[2 * cap + p]};
-    float lf[3] = {0.f, 0.f, 0.f}, mu[3] = {0.f, 0.f, 0.f};
-    e_all |= reverse_push<ND>(g, P, idx, q.f, q.v, q.W, gs.nh, gs.Gp, nbar_next, ln, lvv, lf, mu);
-    float an, aG[3], th[4] = {0.f, 0.f, 0.f, 0.f};
-    pair_force_vjp<ND>(P, gs.nh, gs.Gp, mu, an, aG, th);
-    int l[3];
-    if (in_window<ND>(g, w, idx, 1, 3, l)) {
-      // direct position terms (as gather_vjp), scatters into the window
+    const bool inside = live && in_window<ND>(g, w, idx, 1, 3, l);
+    wave_append(dlist, dcount, p, live && !inside);  // the global path, in a kernel of its own
+    if (inside) {
+      float ln[3] = {lx[p], lx[cap + p], ND == 3 ? lx[2 * cap + p] : 0.0f};
+      float lvv[3] = {lv[p], lv[cap + p], lv[2 * cap + p]};
+      float lf[3] = {0.f, 0.f, 0.f}, mu[3] = {0.f, 0.f, 0.f};
+      float an, aG[3], th[4] = {0.f, 0.f, 0.f, 0.f};
+      // gather from the window: own-cell corners and the 3^ND stencil block
+      float cr[8];
+#pragma unroll
+      for (int k = 0; k < (1 << ND); ++k)
+        cr[k] = dw[win_node<ND>(w, l[0] + (k & 1), l[1] + ((k >> 1) & 1), ND == 3 ? l[2] + ((k >> 2) & 1) : 0)];
+      const float nh = interp<ND>(cr, q.f);
+      int B[3] = {0, 0, 0};
+      float t[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int e = 0; e < ND; ++e) centre_stencil(l[e], q.f[e], B[e], t[e]);
+      float d3[K3];
+#pragma unroll
+      for (int a = 0; a < K3; ++a)
+        d3[a] = dw[win_node<ND>(w, B[0] + a % 3, B[1] + (a / 3) % 3, ND == 3 ? B[2] + a / 9 : 0)];
+      float vv[3][8];
+#pragma unroll
+      for (int k = 0; k < (1 << ND); ++k) {
+        float c[8], Gc[3];
+#pragma unroll
+        for (int j = 0; j < (1 << ND); ++j)
+          c[j] = d3[b3<ND>((k & 1) + (j & 1), ((k >> 1) & 1) + ((j >> 1) & 1),
+                           ND == 3 ? ((k >> 2) & 1) + ((j >> 2) & 1) : 0)];
+        centre_gradient<ND>(g, c, Gc);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) vv[d][k] = Gc[d];
+      }
+      float Gp[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int d = 0; d < ND; ++d) Gp[d] = interp<ND>(vv[d], t);
+      // forward step recomputed; deposit term of step n+1 from the window
+      PushRecord r;
+      e_all |= recompute_push<ND>(g, P, idx, q.f, q.v, nh, Gp, r);
+      if (nbn) {
+        int l2[3] = {0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < ND; ++e) {
+          int dlt = r.idx2[e] - idx[e];
+          dlt = dlt > 1 ? dlt - g.n[e] : (dlt < -1 ? dlt + g.n[e] : dlt);  // across the periodic seam
+          l2[e] = l[e] + dlt;
+        }
+        float c[8], dd[3];
+#pragma unroll
+        for (int k = 0; k < (1 << ND); ++k)
+          c[k] = nx[win_node<ND>(w, l2[0] + (k & 1), l2[1] + ((k >> 1) & 1), ND == 3 ? l2[2] + ((k >> 2) & 1) : 0)];
+        interp_grad<ND>(c, r.f2, dd);
+        const float wgt = (float)q.W;
+#pragma unroll
+        for (int e = 0; e < ND; ++e) ln[e] = __builtin_fmaf(wgt, dd[e], ln[e]);
+      }
+      reverse_drift_kick<ND>(g, P, r, ln, lvv, lf, mu);
+      pair_force_vjp<ND>(P, nh, Gp, mu, an, aG, th);
+      // direct position terms
       float dn[3];
-      interp_grad<ND>(gs.cr, q.f, dn);
+      interp_grad<ND>(cr, q.f, dn);
 #pragma unroll
       for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(an, dn[e], lf[e]);
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
         float dg[3];
-        interp_grad<ND>(gs.vv[d], gs.t, dg);
+        interp_grad<ND>(vv[d], t, dg);
 #pragma unroll
         for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(aG[d], dg[e], lf[e]);
       }
-      float S[8];
-      if (an != 0.0f) {
-        corner_weights<ND>(q.f, S);
+      // cotangents back to the 3^ND block: gradient stencil, then own corners
+      float a3[K3];
 #pragma unroll
-        for (int k = 0; k < (1 << ND); ++k)
-          atomicAdd(&nw[win_node<ND>(w, l[0] + (k & 1), l[1] + ((k >> 1) & 1), ND == 3 ? l[2] + ((k >> 2) & 1) : 0)],
-                    an * S[k]);
-      }
-      corner_weights<ND>(gs.t, S);
-      int m[3] = {0, 0, 0};
-#pragma unroll
-      for (int e = 0; e < ND; ++e) m[e] = l[e] + (gs.c0[e] - idx[e]);  // window cell of the lower centre
+      for (int a = 0; a < K3; ++a) a3[a] = 0.0f;
+      float T[8];
+      corner_weights<ND>(t, T);
 #pragma unroll
       for (int k = 0; k < (1 << ND); ++k) {
-        const int c = win_centre<ND>(w, m[0] + (k & 1), m[1] + ((k >> 1) & 1), ND == 3 ? m[2] + ((k >> 2) & 1) : 0);
+        float wd[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int d = 0; d < ND; ++d)
-          if (aG[d] != 0.0f) atomicAdd(&gw[c * ND + d], aG[d] * S[k]);
+        for (int d = 0; d < ND; ++d) wd[d] = aG[d] * T[k] * g.gam[d];
+#pragma unroll
+        for (int j = 0; j < (1 << ND); ++j) {
+          float v = 0.0f;
+#pragma unroll
+          for (int d = 0; d < ND; ++d) v += ((j >> d) & 1) ? wd[d] : -wd[d];
+          a3[b3<ND>((k & 1) + (j & 1), ((k >> 1) & 1) + ((j >> 1) & 1),
+                    ND == 3 ? ((k >> 2) & 1) + ((j >> 2) & 1) : 0)] += v;
+        }
       }
-    } else {
-      gather_vjp<ND>(g, idx, q.f, gs, an, aG, lf, nbar, Gbar);
+      float u[3][3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const int o = e < ND ? l[e] - B[e] : 0;  // own cell's lower node in the block: 0 or 1
+        const float fe = e < ND ? q.f[e] : 0.0f;
+        u[e][0] = o == 0 ? 1.0f - fe : 0.0f;
+        u[e][1] = o == 0 ? fe : 1.0f - fe;
+        u[e][2] = o == 0 ? 0.0f : fe;
+      }
+#pragma unroll
+      for (int a = 0; a < K3; ++a) {
+        const float sh = u[0][a % 3] * u[1][(a / 3) % 3] * (ND == 3 ? u[2][a / 9] : 1.0f);
+        a3[a] = __builtin_fmaf(an, sh, a3[a]);
+      }
+#pragma unroll
+      for (int a = 0; a < K3; ++a)
+        if (a3[a] != 0.0f)
+          atomicAdd(&acc[win_node<ND>(w, B[0] + a % 3, B[1] + (a / 3) % 3, ND == 3 ? B[2] + a / 9 : 0)], a3[a]);
+#pragma unroll
+      for (int d = 0; d < ND; ++d) lx[d * cap + p] = lf[d];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) lv[d * cap + p] = lvv[d];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) thd[i] += th[i];
     }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
+    const float v = acc[k];
+    if (v == 0.0f) continue;
+    const int a0 = k % w.wn[0], r = k / w.wn[0];
+    const int a1 = ND == 2 ? r : r % w.wn[1];
+    const int a2 = ND == 2 ? 0 : r / w.wn[1];
+    const int x = fold_node(g, 0, w.o[0] + a0), y = fold_node(g, 1, w.o[1] + a1);
+    const int z = ND == 3 ? fold_node(g, 2, w.o[2] + a2) : 0;
+    atomicAdd(&nbar[sd.node_off + node_index<ND>(g, x, y, z)], v);
+  }
+  if (e_all) atomicOr(err, e_all);
+  block_reduce_store<4>(thd, partial + (int64_t)blockIdx.x * 8);
+}
+
+// The reverse step of the particles outside their window: global density and
+// gradient grids, global scatters; parameter terms into dacc[0..3].
+template <int ND>
+__global__ void __launch_bounds__(256) k_adjoint_drifters(Pot P, Batch b, Store s, const int *__restrict__ dlist,
+                                                          const int *__restrict__ dcount,
+                                                          const float *__restrict__ dens_g,
+                                                          const float *__restrict__ G_g,
+                                                          const float *__restrict__ nbar_next,
+                                                          float *__restrict__ lx, float *__restrict__ lv,
+                                                          float *__restrict__ nbar, float *__restrict__ Gbar,
+                                                          double *__restrict__ dacc, uint32_t *__restrict__ err) {
+  const int n = *dcount;
+  const int cap = (int)s.cap;
+  const StoreView sv = view_of(s, s);
+  uint32_t e_all = 0;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const int p = dlist[k];
+    const SlabDesc &sd = b.slabs[find_slab(b.part_offs, b.nslab, p)];
+    const Geo g = sd.g;
+    PState q;
+    load_state<ND, true>(sv, p, true, q);
+    int idx[3];
+    unpack_cell<ND>(sd.tg, q.pc, idx);
+    float ln[3] = {lx[p], lx[cap + p], ND == 3 ? lx[2 * cap + p] : 0.0f};
+    float lvv[3] = {lv[p], lv[cap + p], lv[2 * cap + p]};
+    float lf[3] = {0.f, 0.f, 0.f}, mu[3] = {0.f, 0.f, 0.f};
+    float an, aG[3], th[4] = {0.f, 0.f, 0.f, 0.f};
+    GatherState<ND> gs;
+    gather_for_vjp<ND>(g, dens_g, G_g, idx, q.f, gs);
+    e_all |= reverse_push<ND>(g, P, idx, q.f, q.v, q.W, gs.nh, gs.Gp, nbar_next, ln, lvv, lf, mu);
+    pair_force_vjp<ND>(P, gs.nh, gs.Gp, mu, an, aG, th);
+    gather_vjp<ND>(g, idx, q.f, gs, an, aG, lf, nbar, Gbar);
 #pragma unroll
     for (int d = 0; d < ND; ++d) lx[d * cap + p] = lf[d];
 #pragma unroll
     for (int d = 0; d < 3; ++d) lv[d * cap + p] = lvv[d];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) thd[i] += th[i];
-  }
-  __syncthreads();
-  // window centres -> window nodes (transpose of the staged gradient), flush
-  const int wc0 = w.wn[0] - 1, wc1 = w.wn[1] - 1;
-  for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
-    int a[3];
-    a[0] = k % w.wn[0];
-    const int r = k / w.wn[0];
-    a[1] = ND == 2 ? r : r % w.wn[1];
-    a[2] = ND == 2 ? 0 : r / w.wn[1];
-    float acc = nw[k];
-#pragma unroll
-    for (int bb = 0; bb < (1 << ND); ++bb) {
-      int m[3] = {0, 0, 0};
-      bool ok = true;
-#pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        m[d] = a[d] - ((bb >> d) & 1);
-        ok = ok && m[d] >= 0 && m[d] < w.wn[d] - 1;
-      }
-      if (!ok) continue;
-      const int c = ND == 2 ? m[0] + wc0 * m[1] : m[0] + wc0 * (m[1] + wc1 * m[2]);
-#pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        const float v = g.gam[d] * gw[c * ND + d];
-        acc += ((bb >> d) & 1) ? v : -v;
-      }
-    }
-    if (acc != 0.0f) {
-      const int x = fold_node(g, 0, w.o[0] + a[0]), y = fold_node(g, 1, w.o[1] + a[1]);
-      const int z = ND == 3 ? fold_node(g, 2, w.o[2] + a[2]) : 0;
-      atomicAdd(&nbar[sd.node_off + node_index<ND>(g, x, y, z)], acc);
-    }
+    for (int i = 0; i < 4; ++i) atomicAdd(&dacc[i], (double)th[i]);
   }
   if (e_all) atomicOr(err, e_all);
-  block_reduce_store<4>(thd, partial + (int64_t)blockIdx.x * 8);
 }
 
 // lam_x += the deposit term at the store's positions (the last reverse step).
@@ -1062,17 +1170,21 @@ size_t adjoint_lds_bytes(const TileGeo &tg, int ndim) {
     nW *= wn;
     nC *= wn - 1;
   }
-  return (nW + nC * ndim) * 4;
+  (void)nC;
+  return 3 * nW * 4;
 }
 
 void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
-                          const BinBufs &bb, int max_items, const float *dens, const float *G,
-                          const float *nbar_next, float *lx, float *lv, float *nbar, float *Gbar, double *partial,
-                          uint32_t *err) {
+                          const BinBufs &bb, int max_items, const long long *N, const float *dens, const float *G,
+                          const float *nbar_next, float *lx, float *lv, float *nbar, float *Gbar, int *dlist,
+                          int *dcount, double *partial, double *dacc, uint32_t *err) {
   if (max_items <= 0) return;
   const size_t lds = adjoint_lds_bytes(tg, ndim);
-  PIC_ND(ndim, (k_adjoint_tiled<ND><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, dens, G, nbar_next,
-                                                                   lx, lv, nbar, Gbar, partial, err)));
+  launch_fill32(st, dcount, 1);
+  PIC_ND(ndim, (k_adjoint_tiled<ND><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, N, nbar_next, lx,
+                                                                   lv, nbar, dlist, dcount, partial, err)));
+  PIC_ND(ndim, (k_adjoint_drifters<ND><<<kDriftBlocks, 256, 0, st>>>(P, b, s, dlist, dcount, dens, G, nbar_next, lx,
+                                                                       lv, nbar, Gbar, dacc, err)));
 }
 
 void launch_deposit_vjp_store(hipStream_t st, int ndim, const Batch &b, const Store &s, const float *nbar,
