@@ -153,7 +153,7 @@ def run_sweep(steps, warmup, log_fn=log):
             "slab_particles": [w.parts.n for w in wls]}
 
 
-def run_adjoint(log_fn=log, every=20):
+def run_adjoint(log_fn=log, every=20, steps=None):
     """The 3D adjoint workload: 128^3 cells of 2 nm, slab in the lower 64
     layers, 8 ppc, 1.5 J/cm^2, 400 steps.  Forward = pic_step over the 400
     steps from v(-1/2).  Gradient = torch.autograd through the crater
@@ -171,7 +171,7 @@ def run_adjoint(log_fn=log, every=20):
     log_fn(f"adjoint workload {wl.name}: {p.n} particles, generated in {time.perf_counter() - t0:.1f} s")
     c_att, _ = B.pic_calibrate_catt(g, wl.pot, W.N_SOLID, 8)
     pot = W.Potential(c_att=c_att)
-    nsteps = wl.steps
+    nsteps = wl.steps if steps is None else steps
     dev = torch.device("cuda:0")
     cell = torch.from_numpy(p.cell).to(dev)
     off0 = torch.from_numpy(p.off).to(dev)
@@ -250,8 +250,8 @@ def main():
     from paper_1502_07722_amd import workloads as W
 
     if args.workload == "adjoint":
-        res = run_adjoint()
-        out = {"metric": "adjoint time / forward time (400 steps, checkpoint every 20)",
+        res = run_adjoint(steps=args.steps)
+        out = {"metric": f"adjoint time / forward time ({res['steps']} steps, checkpoint every 20)",
                "value": res["adjoint_over_forward"], "unit": "ratio", "n_gpus": 1, "steps": res["steps"],
                "warmup": 1, "ms_per_step": res["backward_s"] / res["steps"] * 1e3, "higher_is_better": False,
                "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",

@@ -80,7 +80,7 @@ int64_t tiles_for(const pic_grid_t *g, int lt) {
 struct Layout {
   size_t err, diag, partial, partial_pe, node, dens, G, Gbar, total;
   bool tiled;
-  size_t store[2], bins, items, n3[3], drift, dacc, slabs, offs;
+  size_t store[2], bins, items, n3[3], drift, dacc, amax, slabs, offs;
   int64_t tiles_max, items_max, cap, nodes, pe_blocks;
 };
 
@@ -126,6 +126,7 @@ Layout make_layout(const pic_grid_t *grids, int nslab, const int64_t *max_n) {
     for (int k = 0; k < 3; ++k) { L.n3[k] = o; o = align_up(o + sizeof(long long) * (size_t)L.nodes); }
     L.drift = o; o = align_up(o + sizeof(int) * (size_t)(cap + 4));
     L.dacc = o; o = align_up(o + sizeof(double) * 8 * (size_t)nslab);
+    L.amax = o; o = align_up(o + sizeof(uint32_t) * 2);
     L.slabs = o; o = align_up(o + sizeof(SlabDesc) * (size_t)nslab);
     L.offs = o; o = align_up(o + sizeof(int) * (size_t)(2 * (nslab + 1)));
   }
@@ -210,6 +211,7 @@ struct pic_ctx {
   long long *n3[3]{};
   int *drift = nullptr;  // [count0, count1, work0, work1][list]
   double *dacc = nullptr;
+  uint32_t *amax = nullptr;  // [2] largest node-cotangent contribution, this / previous reverse step
   int grid_blocks = 0;   // persistent grid of the fused kernel
   int *h_drift = nullptr;
   hipEvent_t drift_ev = nullptr;
@@ -498,6 +500,7 @@ static int init_common(pic_ctx_t **out, const pic_grid_t *grids_in, int nslab, c
     for (int k = 0; k < 3; ++k) c->n3[k] = reinterpret_cast<long long *>(c->ws + L.n3[k]);
     c->drift = reinterpret_cast<int *>(c->ws + L.drift);
     c->dacc = reinterpret_cast<double *>(c->ws + L.dacc);
+    c->amax = reinterpret_cast<uint32_t *>(c->ws + L.amax);
     c->sd_dev = reinterpret_cast<SlabDesc *>(c->ws + L.slabs);
     c->part_offs_dev = reinterpret_cast<int *>(c->ws + L.offs);
     c->tile_offs_dev = c->part_offs_dev + nslab + 1;
@@ -1221,12 +1224,17 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
     if ((rc = check_launch(ctx, "recompute"))) return rc;
     // reverse steps of the segment
     for (int k = len - 1; k >= 0; --k) {
+      const int step = s0 + k;
+      uint32_t *amax_prev = ctx->amax + (step & 1), *amax_cur = ctx->amax + ((step + 1) & 1);
+      if (step == nsteps - 1)  // seed the fixed-point scale of the first reverse step
+        launch_adjoint_scale(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), ctx->bb, (int)max_items, Nk(k),
+                             nbar_next, lx, lv, amax_prev);
       launch_grid(ctx->stream, g, Nk(k), ctx->dens, ctx->G);
       launch_fillf(ctx->stream, nb_cur, ctx->nnodes);
       launch_fillf(ctx->stream, ctx->Gbar, (int64_t)g.ncells * nd);
       launch_adjoint_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), ctx->bb, (int)max_items, Nk(k),
                            ctx->dens, ctx->G, nbar_next, lx, lv, nb_cur, ctx->Gbar, ctx->drift + 4, ctx->drift,
-                           ctx->partial, ctx->dacc, ctx->err);
+                           amax_prev, amax_cur, ctx->partial, ctx->dacc, ctx->err);
       launch_gradient_vjp(ctx->stream, g, ctx->Gbar, nb_cur);
       launch_reduce_theta(ctx->stream, ctx->partial, (int)max_items, 1.0 / ctx->pot.D, 1.0 / ctx->pot.r0, dtheta,
                           ctx->dacc);

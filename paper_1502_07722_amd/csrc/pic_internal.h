@@ -133,7 +133,13 @@ size_t adjoint_lds_bytes(const TileGeo &tg, int ndim);
 void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
                           const BinBufs &bb, int max_items, const long long *N, const float *dens, const float *G,
                           const float *nbar_next, float *lx, float *lv, float *nbar, float *Gbar, int *dlist,
-                          int *dcount, double *partial, double *dacc, uint32_t *err);
+                          int *dcount, const uint32_t *amax_prev, uint32_t *amax_cur, double *partial, double *dacc,
+                          uint32_t *err);
+// largest node-cotangent contribution of a reverse step, measured only (the
+// fixed-point scale of the first reverse step); lx, lv are read only
+void launch_adjoint_scale(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
+                          const BinBufs &bb, int max_items, const long long *N, const float *nbar_next, float *lx,
+                          float *lv, uint32_t *amax);
 void launch_deposit_vjp_store(hipStream_t st, int ndim, const Batch &b, const Store &s, const float *nbar,
                               float *lx);
 void launch_to_store(hipStream_t st, const Batch &b, const Store &s, int k, const float *src, int64_t n,

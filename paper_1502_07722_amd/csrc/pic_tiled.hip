@@ -808,32 +808,68 @@ __global__ void __launch_bounds__(256) k_reduce_diag_slab(const double *__restri
 // the global node and centre cotangents).
 // ---------------------------------------------------------------------------
 template <int ND>
+__device__ __forceinline__ void load_adjoint_state(const StoreView &sv, const float *__restrict__ lx,
+                                                   const float *__restrict__ lv, int cap, int p, bool on, PState &st,
+                                                   float a[3], float c[3]) {
+  load_state<ND, true>(sv, p, on, st);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    a[d] = (on && d < ND) ? lx[d * cap + p] : 0.0f;
+    c[d] = on ? lv[d * cap + p] : 0.0f;
+  }
+}
+
+template <int ND>
 __device__ __forceinline__ constexpr int b3(int a0, int a1, int a2) {
   return ND == 2 ? a0 + 3 * a1 : a0 + 3 * (a1 + 3 * a2);
 }
 
-template <int ND>
+// Node cotangents accumulate in LDS as int64 fixed point: float atomic adds
+// on LDS are more than an order of magnitude slower than integer ones on this
+// chip.  The scale is a power of two set from the largest single contribution
+// of the previous reverse step (amax_prev, float bits): values up to 256
+// times that fit with 2^11 of headroom for the sum of a node's contributions
+// and a resolution of 2^-44 of it; a larger value (a sudden jump) takes a
+// global float atomic instead.  MAXONLY: only measure the largest
+// contribution (seeds the scale of the first reverse step).
+__device__ __forceinline__ int adj_scale_exp(uint32_t amax_bits) {
+  const float m = __uint_as_float(amax_bits);
+  if (!(m > 0.0f)) return 100;  // nothing seen: every nonzero value takes the float path
+  int e;
+  (void)frexpf(m, &e);  // m < 2^e
+  return min(max(44 - e, -100), 100);
+}
+
+template <int ND, bool MAXONLY>
 __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, const Item *__restrict__ items,
                                                        const int *__restrict__ num_items,
                                                        const long long *__restrict__ Ncur,
                                                        const float *__restrict__ nbar_next, float *__restrict__ lx,
                                                        float *__restrict__ lv, float *__restrict__ nbar,
                                                        int *__restrict__ dlist, int *__restrict__ dcount,
+                                                       const uint32_t *__restrict__ amax_prev,
+                                                       uint32_t *__restrict__ amax_cur,
                                                        double *__restrict__ partial, uint32_t *__restrict__ err) {
   constexpr int K3 = ND == 2 ? 9 : 27;
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t s_amax;
   if ((int)blockIdx.x >= *num_items) {
-    if (threadIdx.x < 4) partial[(int64_t)blockIdx.x * 8 + threadIdx.x] = 0.0;
+    if (!MAXONLY && threadIdx.x < 4) partial[(int64_t)blockIdx.x * 8 + threadIdx.x] = 0.0;
     return;
   }
+  const int sexp = MAXONLY ? 0 : adj_scale_exp(*amax_prev);
+  const float to_fix = ldexpf(1.0f, sexp);             // exact power of two (sexp within float range)
+  const float lim = ldexpf(1.0f, 52 - sexp);           // larger values: global float atomics
+  float vmax = 0.0f;
   const Item it = items[blockIdx.x];
   const SlabDesc &sd = b.slabs[it.slab];
   const Geo g = sd.g;
   const TileGeo tg = sd.tg;
   const Window w = make_window<ND>(tg, it.tile - sd.tile_off);
-  float *dw = reinterpret_cast<float *>(smem);  // [nW] node densities of step n
-  float *nx = dw + w.nW;                         // [nW] kfac * nbar of step n+1
-  float *acc = nx + w.nW;                        // [nW] node cotangent of step n
+  unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);  // [nW] node cotangent, fixed point
+  float *dw = reinterpret_cast<float *>(acc + w.nW);  // [nW] node densities of step n
+  float *nx = dw + w.nW;                              // [nW] kfac * nbar of step n+1
+  if (threadIdx.x == 0) s_amax = 0u;
   const long long *N = Ncur + sd.node_off;
   const float *nbn = nbar_next ? nbar_next + sd.node_off : nullptr;
   for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
@@ -845,25 +881,24 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
     const int node = node_index<ND>(g, x, y, z);
     dw[k] = node_density(g, N[node], x, y, z);
     nx[k] = nbn ? node_density(g, 1ll, x, y, z) * nbn[node] : 0.0f;
-    acc[k] = 0.0f;
+    acc[k] = 0ull;
   }
   __syncthreads();
   const int cap = (int)s.cap;
   const StoreView sv = view_of(s, s);
   uint32_t e_all = 0;
-  double thd[4] = {0, 0, 0, 0};
+  float thf[4] = {0.f, 0.f, 0.f, 0.f};  // this thread's parameter terms (chunk / 256 particles at most)
   for (int base = it.start; base < it.end; base += blockDim.x) {
     const int p = base + (int)threadIdx.x;
     const bool live = p < it.end;
     PState q;
-    load_state<ND, true>(sv, p, live, q);
+    float ln[3], lvv[3];
+    load_adjoint_state<ND>(sv, lx, lv, cap, p, live, q, ln, lvv);
     int idx[3], l[3];
     unpack_cell<ND>(tg, q.pc, idx);
     const bool inside = live && in_window<ND>(g, w, idx, 1, 3, l);
-    wave_append(dlist, dcount, p, live && !inside);  // the global path, in a kernel of its own
+    if (!MAXONLY) wave_append(dlist, dcount, p, live && !inside);  // the global path, in a kernel of its own
     if (inside) {
-      float ln[3] = {lx[p], lx[cap + p], ND == 3 ? lx[2 * cap + p] : 0.0f};
-      float lvv[3] = {lv[p], lv[cap + p], lv[2 * cap + p]};
       float lf[3] = {0.f, 0.f, 0.f}, mu[3] = {0.f, 0.f, 0.f};
       float an, aG[3], th[4] = {0.f, 0.f, 0.f, 0.f};
       // gather from the window: own-cell corners and the 3^ND stencil block
@@ -872,29 +907,36 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
       for (int k = 0; k < (1 << ND); ++k)
         cr[k] = dw[win_node<ND>(w, l[0] + (k & 1), l[1] + ((k >> 1) & 1), ND == 3 ? l[2] + ((k >> 2) & 1) : 0)];
       const float nh = interp<ND>(cr, q.f);
+      float dn[3];  // d nh / d offset, taken now so that cr dies here
+      interp_grad<ND>(cr, q.f, dn);
       int B[3] = {0, 0, 0};
       float t[3] = {0.f, 0.f, 0.f};
 #pragma unroll
       for (int e = 0; e < ND; ++e) centre_stencil(l[e], q.f[e], B[e], t[e]);
-      float d3[K3];
+      float Gp[3] = {0.f, 0.f, 0.f}, dG[3][3];
+      {
+        float d3[K3];
 #pragma unroll
-      for (int a = 0; a < K3; ++a)
-        d3[a] = dw[win_node<ND>(w, B[0] + a % 3, B[1] + (a / 3) % 3, ND == 3 ? B[2] + a / 9 : 0)];
-      float vv[3][8];
+        for (int a = 0; a < K3; ++a)
+          d3[a] = dw[win_node<ND>(w, B[0] + a % 3, B[1] + (a / 3) % 3, ND == 3 ? B[2] + a / 9 : 0)];
+        float vv[3][8];
 #pragma unroll
-      for (int k = 0; k < (1 << ND); ++k) {
-        float c[8], Gc[3];
+        for (int k = 0; k < (1 << ND); ++k) {
+          float c[8], Gc[3];
 #pragma unroll
-        for (int j = 0; j < (1 << ND); ++j)
-          c[j] = d3[b3<ND>((k & 1) + (j & 1), ((k >> 1) & 1) + ((j >> 1) & 1),
-                           ND == 3 ? ((k >> 2) & 1) + ((j >> 2) & 1) : 0)];
-        centre_gradient<ND>(g, c, Gc);
+          for (int j = 0; j < (1 << ND); ++j)
+            c[j] = d3[b3<ND>((k & 1) + (j & 1), ((k >> 1) & 1) + ((j >> 1) & 1),
+                             ND == 3 ? ((k >> 2) & 1) + ((j >> 2) & 1) : 0)];
+          centre_gradient<ND>(g, c, Gc);
 #pragma unroll
-        for (int d = 0; d < ND; ++d) vv[d][k] = Gc[d];
+          for (int d = 0; d < ND; ++d) vv[d][k] = Gc[d];
+        }
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          Gp[d] = interp<ND>(vv[d], t);
+          interp_grad<ND>(vv[d], t, dG[d]);  // d Gp / d offset; vv dies here
+        }
       }
-      float Gp[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-      for (int d = 0; d < ND; ++d) Gp[d] = interp<ND>(vv[d], t);
       // forward step recomputed; deposit term of step n+1 from the window
       PushRecord r;
       e_all |= recompute_push<ND>(g, P, idx, q.f, q.v, nh, Gp, r);
@@ -918,17 +960,12 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
       reverse_drift_kick<ND>(g, P, r, ln, lvv, lf, mu);
       pair_force_vjp<ND>(P, nh, Gp, mu, an, aG, th);
       // direct position terms
-      float dn[3];
-      interp_grad<ND>(cr, q.f, dn);
 #pragma unroll
       for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(an, dn[e], lf[e]);
 #pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        float dg[3];
-        interp_grad<ND>(vv[d], t, dg);
+      for (int d = 0; d < ND; ++d)
 #pragma unroll
-        for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(aG[d], dg[e], lf[e]);
-      }
+        for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(aG[d], dG[d][e], lf[e]);
       // cotangents back to the 3^ND block: gradient stencil, then own corners
       float a3[K3];
 #pragma unroll
@@ -964,21 +1001,40 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
         a3[a] = __builtin_fmaf(an, sh, a3[a]);
       }
 #pragma unroll
-      for (int a = 0; a < K3; ++a)
-        if (a3[a] != 0.0f)
-          atomicAdd(&acc[win_node<ND>(w, B[0] + a % 3, B[1] + (a / 3) % 3, ND == 3 ? B[2] + a / 9 : 0)], a3[a]);
+      for (int a = 0; a < K3; ++a) vmax = fmaxf(vmax, fabsf(a3[a]));
+      if (!MAXONLY) {
 #pragma unroll
-      for (int d = 0; d < ND; ++d) lx[d * cap + p] = lf[d];
+        for (int a = 0; a < K3; ++a) {
+          if (a3[a] == 0.0f) continue;
+          const int k = win_node<ND>(w, B[0] + a % 3, B[1] + (a / 3) % 3, ND == 3 ? B[2] + a / 9 : 0);
+          if (fabsf(a3[a]) < lim) {
+            atomicAdd(&acc[k], (unsigned long long)__float2ll_rn(a3[a] * to_fix));
+          } else {
+            const int x = fold_node(g, 0, w.o[0] + B[0] + a % 3), y = fold_node(g, 1, w.o[1] + B[1] + (a / 3) % 3);
+            const int z = ND == 3 ? fold_node(g, 2, w.o[2] + B[2] + a / 9) : 0;
+            atomicAdd(&nbar[sd.node_off + node_index<ND>(g, x, y, z)], a3[a]);
+          }
+        }
 #pragma unroll
-      for (int d = 0; d < 3; ++d) lv[d * cap + p] = lvv[d];
+        for (int d = 0; d < ND; ++d) lx[d * cap + p] = lf[d];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) thd[i] += th[i];
+        for (int d = 0; d < 3; ++d) lv[d * cap + p] = lvv[d];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) thf[i] += th[i];
+      }
     }
   }
+  // largest single contribution of this block (the next step's scale)
+  for (int o = 32; o > 0; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(&s_amax, __float_as_uint(vmax));
   __syncthreads();
+  if (threadIdx.x == 0) atomicMax(amax_cur, s_amax);
+  if (MAXONLY) return;
+  const double from_fix = ldexp(1.0, -sexp);
   for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
-    const float v = acc[k];
-    if (v == 0.0f) continue;
+    const long long iv = (long long)acc[k];
+    if (iv == 0) continue;
+    const float v = (float)((double)iv * from_fix);
     const int a0 = k % w.wn[0], r = k / w.wn[0];
     const int a1 = ND == 2 ? r : r % w.wn[1];
     const int a2 = ND == 2 ? 0 : r / w.wn[1];
@@ -987,6 +1043,7 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
     atomicAdd(&nbar[sd.node_off + node_index<ND>(g, x, y, z)], v);
   }
   if (e_all) atomicOr(err, e_all);
+  double thd[4] = {thf[0], thf[1], thf[2], thf[3]};
   block_reduce_store<4>(thd, partial + (int64_t)blockIdx.x * 8);
 }
 
@@ -1171,20 +1228,34 @@ size_t adjoint_lds_bytes(const TileGeo &tg, int ndim) {
     nC *= wn - 1;
   }
   (void)nC;
-  return 3 * nW * 4;
+  return nW * (8 + 4 + 4);
 }
 
 void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
                           const BinBufs &bb, int max_items, const long long *N, const float *dens, const float *G,
                           const float *nbar_next, float *lx, float *lv, float *nbar, float *Gbar, int *dlist,
-                          int *dcount, double *partial, double *dacc, uint32_t *err) {
+                          int *dcount, const uint32_t *amax_prev, uint32_t *amax_cur, double *partial, double *dacc,
+                          uint32_t *err) {
   if (max_items <= 0) return;
   const size_t lds = adjoint_lds_bytes(tg, ndim);
   launch_fill32(st, dcount, 1);
-  PIC_ND(ndim, (k_adjoint_tiled<ND><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, N, nbar_next, lx,
-                                                                   lv, nbar, dlist, dcount, partial, err)));
+  launch_fill32(st, reinterpret_cast<int *>(amax_cur), 1);
+  PIC_ND(ndim, (k_adjoint_tiled<ND, false><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, N, nbar_next,
+                                                                          lx, lv, nbar, dlist, dcount, amax_prev,
+                                                                          amax_cur, partial, err)));
   PIC_ND(ndim, (k_adjoint_drifters<ND><<<kDriftBlocks, 256, 0, st>>>(P, b, s, dlist, dcount, dens, G, nbar_next, lx,
                                                                        lv, nbar, Gbar, dacc, err)));
+}
+
+void launch_adjoint_scale(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
+                          const BinBufs &bb, int max_items, const long long *N, const float *nbar_next, float *lx,
+                          float *lv, uint32_t *amax) {
+  if (max_items <= 0) return;
+  const size_t lds = adjoint_lds_bytes(tg, ndim);
+  launch_fill32(st, reinterpret_cast<int *>(amax), 1);
+  PIC_ND(ndim, (k_adjoint_tiled<ND, true><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, N, nbar_next,
+                                                                         lx, lv, nullptr, nullptr, nullptr, amax, amax,
+                                                                         nullptr, nullptr)));
 }
 
 void launch_deposit_vjp_store(hipStream_t st, int ndim, const Batch &b, const Store &s, const float *nbar,
