@@ -321,10 +321,11 @@ int pic_deposit_vjp(pic_ctx_t *ctx, const pic_particles_t *state, const float *n
 /* Recorded trajectories: the checkpointed reverse sweep at full speed.
  *
  * pic_forward_record runs nsteps cycles like pic_step (same bits), keeping
- * the particles in the library's tile-binned order for the whole run (no
- * re-binning; particles that leave their tile take the slower global path)
- * and copying the state into record before every step that is a multiple of
- * every (checkpoints, in the binned order).  record is caller-owned device
+ * the particles in the library's tile-binned order and re-binning only at
+ * checkpoints (with sort_every < 0 when too many particles left their tile,
+ * with sort_every > 0 at every checkpoint, with 0 never), and copying the
+ * state and its binning into record before every step that is a multiple of
+ * every (checkpoints).  record is caller-owned device
  * memory of pic_record_bytes() bytes, 256-byte aligned; the final state is
  * written back to p in the caller's order.
  *

@@ -220,6 +220,7 @@ struct pic_ctx {
   int last_step = 0;
   // recorded trajectories (reverse mode)
   std::vector<int64_t> rec_key;  // configuration of the last pic_forward_record
+  std::vector<char> rec_rebinned;  // checkpoints whose binning differs from the previous one
   // graph replay of steady steps
   bool use_graph = true;
   hipGraphExec_t graph[2]{};
@@ -1037,10 +1038,12 @@ int pic_deposit_vjp(pic_ctx_t *ctx, const pic_particles_t *state, const float *n
 // the reverse sweep that recomputes each segment out of place and runs the
 // tiled reverse kernel over it.
 // ---------------------------------------------------------------------------
-// Record (device, caller-owned): wq [cap], oidx [cap], the work items of the
-// binning, their count, then one state (pc, off, vel) per checkpoint.
+// Record (device, caller-owned): one entry per checkpoint, each with the
+// state (pc, off, vel), the binning it was taken under (wq, oidx, work items,
+// their count).  Recorded runs re-bin only at checkpoints, so every segment
+// between two checkpoints keeps one binning.
 struct RecLayout {
-  size_t wq, oidx, items, nitems, ckpt0, state, total;
+  size_t state, wq, oidx, items, nitems, stride, total;
   int nck;
 };
 
@@ -1051,13 +1054,13 @@ static RecLayout rec_layout(const pic_ctx_t *c, int nsteps, int every) {
   const int64_t cap = c->cap;
   R.nck = (nsteps + every - 1) / every;
   size_t o = 0;
+  R.state = o; o += state_bytes_of(c->ndim, cap);
   R.wq = o; o = align_up(o + 4 * (size_t)cap);
   R.oidx = o; o = align_up(o + 4 * (size_t)cap);
   R.items = o; o = align_up(o + sizeof(Item) * (size_t)c->items_cap);
   R.nitems = o; o = align_up(o + sizeof(int));
-  R.ckpt0 = o;
-  R.state = state_bytes_of(c->ndim, cap);
-  R.total = o + R.state * (size_t)R.nck;
+  R.stride = o;
+  R.total = o * (size_t)R.nck;
   return R;
 }
 
@@ -1121,34 +1124,63 @@ int pic_forward_record(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, int32
   launch_import(ctx->stream, nd, ctx->sd.data(), &cp, 1, ctx->bb, b, ctx->chunk, ctx->st[0], ctx->err);
   if ((rc = check_launch(ctx, "binning"))) return rc;
   if ((rc = read_device_error(ctx))) return rc;
-  const Store &S = ctx->st[0];
-  hipError_t e = hipMemcpyAsync(rec + R.wq, S.wq, 4 * (size_t)ctx->cap, hipMemcpyDeviceToDevice, ctx->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(rec + R.oidx, S.oidx, 4 * (size_t)ctx->cap, hipMemcpyDeviceToDevice, ctx->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(rec + R.items, ctx->bb.items, sizeof(Item) * (size_t)ctx->items_cap, hipMemcpyDeviceToDevice,
-                       ctx->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(rec + R.nitems, ctx->bb.num_items, sizeof(int), hipMemcpyDeviceToDevice, ctx->stream);
-  if ((rc = hip_check(ctx, e, "save binning"))) return rc;
+  int cur = 0;
   const int64_t max_items = (int64_t)ctx->ntiles + (n + ctx->chunk - 1) / ctx->chunk;
   launch_fill64(ctx->stream, ctx->n3[0], ctx->nnodes);
   launch_fill64(ctx->stream, ctx->n3[1], ctx->nnodes);
   launch_fill32(ctx->stream, ctx->drift, 4);
-  launch_deposit_tiled(ctx->stream, nd, ctx->sd[0].tg, b, S, ctx->bb, (int)max_items, ctx->n3[0]);
-  // no re-binning inside a recorded run: the store order stays the record's
+  launch_deposit_tiled(ctx->stream, nd, ctx->sd[0].tg, b, ctx->st[cur], ctx->bb, (int)max_items, ctx->n3[0]);
+  std::vector<char> rebinned(R.nck, 0);
+  int since_bin = 0;
   for (int32_t s = 0; s < nsteps; ++s) {
-    if (s % every == 0 && (rc = copy_state(ctx, state_at(ctx, rec + R.ckpt0 + R.state * (s / every), S), S)))
-      return rc;
-    enqueue_step(ctx, b, S, s, false);
+    if (s % every == 0) {
+      const int j = s / every;
+      // re-bin at a checkpoint: always with a fixed re-binning period, and
+      // with the adaptive one once more than n / kDriftFraction particles
+      // left their window in the previous step
+      if (s > 0 && ctx->sort_every > 0) {
+        launch_rebin(ctx->stream, nd, ctx->bb, b, ctx->chunk, ctx->st[cur], ctx->st[1 - cur]);
+        cur = 1 - cur;
+        since_bin = 0;
+        rebinned[j] = 1;
+      } else if (s > 0 && ctx->sort_every < 0) {
+        int h = 0;
+        if ((rc = hip_check(ctx, hipMemcpyAsync(&h, ctx->drift + ((s - 1) & 1), sizeof(int),
+                                                hipMemcpyDeviceToHost, ctx->stream), "drifter count")))
+          return rc;
+        if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "stream synchronize"))) return rc;
+        if ((int64_t)h * kDriftFraction > n || since_bin >= kMaxBinPeriod) {
+          launch_rebin(ctx->stream, nd, ctx->bb, b, ctx->chunk, ctx->st[cur], ctx->st[1 - cur]);
+          cur = 1 - cur;
+          since_bin = 0;
+          rebinned[j] = 1;
+        }
+      }
+      char *ck = rec + R.stride * j;
+      const Store &S = ctx->st[cur];
+      if ((rc = copy_state(ctx, state_at(ctx, ck + R.state, S), S))) return rc;
+      hipError_t e = hipMemcpyAsync(ck + R.wq, S.wq, 4 * (size_t)ctx->cap, hipMemcpyDeviceToDevice, ctx->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(ck + R.oidx, S.oidx, 4 * (size_t)ctx->cap, hipMemcpyDeviceToDevice, ctx->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(ck + R.items, ctx->bb.items, sizeof(Item) * (size_t)ctx->items_cap,
+                           hipMemcpyDeviceToDevice, ctx->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(ck + R.nitems, ctx->bb.num_items, sizeof(int), hipMemcpyDeviceToDevice, ctx->stream);
+      if ((rc = hip_check(ctx, e, "save checkpoint"))) return rc;
+    }
+    enqueue_step(ctx, b, ctx->st[cur], s, false);
     if ((rc = check_launch(ctx, "recorded step"))) return rc;
+    ++since_bin;
   }
+  const Store &S = ctx->st[cur];
   launch_export(ctx->stream, nd, ctx->sd[0], S, cp);
   ctx->last_nodes = ctx->n3[nsteps % 3];
   ctx->last_step = nsteps - 1;
   if ((rc = check_launch(ctx, "export"))) return rc;
   if ((rc = read_device_error(ctx))) return rc;
   ctx->rec_key = rec_key_of(ctx, n, nsteps, every, record);
+  ctx->rec_rebinned = rebinned;
   return PIC_OK;
 }
 
@@ -1184,39 +1216,46 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
   if ((rc = bind_counts(ctx, p))) return rc;
   const Batch b = batch_of(ctx, n);
   ensure_grid_blocks(ctx);
-  // the record's binning and constant per-particle data back into the store
-  Store &S = ctx->st[0];
-  hipError_t e = hipMemcpyAsync(S.wq, rec + R.wq, 4 * (size_t)cap, hipMemcpyDeviceToDevice, ctx->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(S.oidx, rec + R.oidx, 4 * (size_t)cap, hipMemcpyDeviceToDevice, ctx->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(ctx->bb.items, rec + R.items, sizeof(Item) * (size_t)ctx->items_cap, hipMemcpyDeviceToDevice,
-                       ctx->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(ctx->bb.num_items, rec + R.nitems, sizeof(int), hipMemcpyDeviceToDevice, ctx->stream);
-  if ((rc = hip_check(ctx, e, "restore binning"))) return rc;
   ctx->last_nodes = nullptr;
   drop_graphs(ctx);
   const int64_t max_items = (int64_t)ctx->ntiles + (n + ctx->chunk - 1) / ctx->chunk;
-  launch_to_store(ctx->stream, b, S, nd, lam_x, n, lx);
-  launch_to_store(ctx->stream, b, S, 3, lam_v, n, lv);
+  // checkpoint j's binning: a store whose wq / oidx are the record's, and its items
+  auto ref_of = [&](int j) {
+    Store S = ctx->st[0];
+    char *ck = rec + R.stride * j;
+    S.wq = reinterpret_cast<int *>(ck + R.wq);
+    S.oidx = reinterpret_cast<int *>(ck + R.oidx);
+    return S;
+  };
+  auto bins_of = [&](int j) {
+    BinBufs bb = ctx->bb;
+    char *ck = rec + R.stride * j;
+    bb.items = reinterpret_cast<Item *>(ck + R.items);
+    bb.num_items = reinterpret_cast<int *>(ck + R.nitems);
+    return bb;
+  };
+  launch_to_store(ctx->stream, b, ref_of(R.nck - 1), nd, lam_x, n, lx);
+  launch_to_store(ctx->stream, b, ref_of(R.nck - 1), 3, lam_v, n, lv);
   launch_fill64(ctx->stream, reinterpret_cast<long long *>(ctx->dacc), 8);
   const Geo &g = ctx->geo;
   const float *nbar_next = nullptr;
   float *nb_cur = nbA, *nb_other = nbB;
   for (int j = R.nck - 1; j >= 0; --j) {
     const int s0 = j * every, len = std::min(every, nsteps - s0);
+    const Store ref = ref_of(j);
+    const BinBufs bb = bins_of(j);
     auto slot = [&](int k) {
-      return k == 0 ? state_at(ctx, rec + R.ckpt0 + R.state * j, S) : state_at(ctx, traj + sb * k, S);
+      return k == 0 ? state_at(ctx, rec + R.stride * j + R.state, ref) : state_at(ctx, traj + sb * k, ref);
     };
     // recompute the segment's states (out of place) and node sums
     launch_fill64(ctx->stream, Nk(0), ctx->nnodes);
     if (len > 1) launch_fill64(ctx->stream, Nk(1), ctx->nnodes);
     launch_fill32(ctx->stream, ctx->drift, 4);
-    launch_deposit_tiled(ctx->stream, nd, ctx->sd[0].tg, b, slot(0), ctx->bb, (int)max_items, Nk(0));
+    launch_deposit_tiled(ctx->stream, nd, ctx->sd[0].tg, b, slot(0), bb, (int)max_items, Nk(0));
     for (int k = 0; k + 1 < len; ++k) {
       const Drift dr = drift_of(ctx, k);
       const Store in = slot(k), out = slot(k + 1);
-      launch_step_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, ctx->dcs[0], b, in, out, ctx->bb, ctx->grid_blocks,
+      launch_step_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, ctx->dcs[0], b, in, out, bb, ctx->grid_blocks,
                         Nk(k), Nk(k + 1), Nk(k + 2), dr, ctx->partial, false, ctx->err);
       launch_drifters(ctx->stream, nd, ctx->P, ctx->dcs[0], b, in, out, Nk(k), Nk(k + 1), dr, ctx->dacc, false,
                       ctx->err);
@@ -1227,12 +1266,12 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
       const int step = s0 + k;
       uint32_t *amax_prev = ctx->amax + (step & 1), *amax_cur = ctx->amax + ((step + 1) & 1);
       if (step == nsteps - 1)  // seed the fixed-point scale of the first reverse step
-        launch_adjoint_scale(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), ctx->bb, (int)max_items, Nk(k),
+        launch_adjoint_scale(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), bb, (int)max_items, Nk(k),
                              nbar_next, lx, lv, amax_prev);
       launch_grid(ctx->stream, g, Nk(k), ctx->dens, ctx->G);
       launch_fillf(ctx->stream, nb_cur, ctx->nnodes);
       launch_fillf(ctx->stream, ctx->Gbar, (int64_t)g.ncells * nd);
-      launch_adjoint_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), ctx->bb, (int)max_items, Nk(k),
+      launch_adjoint_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), bb, (int)max_items, Nk(k),
                            ctx->dens, ctx->G, nbar_next, lx, lv, nb_cur, ctx->Gbar, ctx->drift + 4, ctx->drift,
                            amax_prev, amax_cur, ctx->partial, ctx->dacc, ctx->err);
       launch_gradient_vjp(ctx->stream, g, ctx->Gbar, nb_cur);
@@ -1242,11 +1281,20 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
       std::swap(nb_cur, nb_other);
       if ((rc = check_launch(ctx, "reverse step"))) return rc;
     }
+    // into the previous segment's order (through the caller's order, with
+    // lam_x / lam_v as the staging arrays) where the binning changed
+    if (j > 0 && ctx->rec_rebinned[j]) {
+      launch_from_store(ctx->stream, b, ref, nd, lx, n, lam_x);
+      launch_from_store(ctx->stream, b, ref, 3, lv, n, lam_v);
+      launch_to_store(ctx->stream, b, ref_of(j - 1), nd, lam_x, n, lx);
+      launch_to_store(ctx->stream, b, ref_of(j - 1), 3, lam_v, n, lv);
+    }
   }
   // deposit term of the initial positions, back to the caller's order
-  launch_deposit_vjp_store(ctx->stream, nd, b, state_at(ctx, rec + R.ckpt0, S), nbar_next, lx);
-  launch_from_store(ctx->stream, b, S, nd, lx, n, lam_x);
-  launch_from_store(ctx->stream, b, S, 3, lv, n, lam_v);
+  const Store ref0 = ref_of(0);
+  launch_deposit_vjp_store(ctx->stream, nd, b, state_at(ctx, rec + R.state, ref0), nbar_next, lx);
+  launch_from_store(ctx->stream, b, ref0, nd, lx, n, lam_x);
+  launch_from_store(ctx->stream, b, ref0, 3, lv, n, lam_v);
   if ((rc = check_launch(ctx, "reverse sweep"))) return rc;
   return read_device_error(ctx);
 }

@@ -64,18 +64,28 @@ def test_recorded_forward_equals_pic_step(B, nd):
     a = B.DeviceParticles.from_host(parts)
     ctx.start_leapfrog(a)
     b = a.clone()
+    c = a.clone()
     ctx.pic_step(a, 37)
     ctx.pic_forward_record(b, 37, 10)
+    t, h, ch, _ = ctx.pic_get_tiling()
+    ctx.pic_set_tiling(t, h, ch, 3)  # re-binning at every checkpoint
+    ctx.pic_forward_record(c, 37, 10)
     torch.cuda.synchronize()
-    assert torch.equal(a.cell, b.cell) and torch.equal(a.off, b.off) and torch.equal(a.vel, b.vel)
+    for x in (b, c):
+        assert torch.equal(a.cell, x.cell) and torch.equal(a.off, x.off) and torch.equal(a.vel, x.vel)
 
 
-@pytest.mark.parametrize("nd", [2, 3])
-def test_recorded_sweep_matches_per_step_chain(B, nd):
+@pytest.mark.parametrize("nd,rebin", [(2, False), (3, False), (2, True), (3, True)])
+def test_recorded_sweep_matches_per_step_chain(B, nd, rebin):
+    """rebin: re-binning at every checkpoint (each segment has its own order,
+    the cotangents are permuted between segments)."""
     grid, parts, dt = _case(nd)
     pot = W.Potential(c_att=0.27)
     nsteps, every = 30, 8  # a ragged last segment
     ctx = B.Context(grid, pot, dt, parts.n)
+    if rebin:
+        t, h, c, _ = ctx.pic_get_tiling()
+        ctx.pic_set_tiling(t, h, c, 5)
     dp = B.DeviceParticles.from_host(parts)
     ctx.start_leapfrog(dp)
     start = dp.clone()
