@@ -1237,6 +1237,7 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
   launch_to_store(ctx->stream, b, ref_of(R.nck - 1), nd, lam_x, n, lx);
   launch_to_store(ctx->stream, b, ref_of(R.nck - 1), 3, lam_v, n, lv);
   launch_fill64(ctx->stream, reinterpret_cast<long long *>(ctx->dacc), 8);
+  launch_fill64(ctx->stream, reinterpret_cast<long long *>(ctx->partial), 8 * max_items);
   const Geo &g = ctx->geo;
   const float *nbar_next = nullptr;
   float *nb_cur = nbA, *nb_other = nbB;
@@ -1268,15 +1269,11 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
       if (step == nsteps - 1)  // seed the fixed-point scale of the first reverse step
         launch_adjoint_scale(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), bb, (int)max_items, Nk(k),
                              nbar_next, lx, lv, amax_prev);
-      launch_grid(ctx->stream, g, Nk(k), ctx->dens, ctx->G);
+      launch_density(ctx->stream, g, Nk(k), ctx->dens);
       launch_fillf(ctx->stream, nb_cur, ctx->nnodes);
-      launch_fillf(ctx->stream, ctx->Gbar, (int64_t)g.ncells * nd);
       launch_adjoint_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), bb, (int)max_items, Nk(k),
-                           ctx->dens, ctx->G, nbar_next, lx, lv, nb_cur, ctx->Gbar, ctx->drift + 4, ctx->drift,
-                           amax_prev, amax_cur, ctx->partial, ctx->dacc, ctx->err);
-      launch_gradient_vjp(ctx->stream, g, ctx->Gbar, nb_cur);
-      launch_reduce_theta(ctx->stream, ctx->partial, (int)max_items, 1.0 / ctx->pot.D, 1.0 / ctx->pot.r0, dtheta,
-                          ctx->dacc);
+                           ctx->dens, nbar_next, lx, lv, nb_cur, ctx->drift + 4, ctx->drift, amax_prev, amax_cur,
+                           ctx->partial, ctx->dacc, ctx->err);
       nbar_next = nb_cur;
       std::swap(nb_cur, nb_other);
       if ((rc = check_launch(ctx, "reverse step"))) return rc;
@@ -1290,6 +1287,9 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
       launch_to_store(ctx->stream, b, ref_of(j - 1), 3, lam_v, n, lv);
     }
   }
+  // parameter terms summed over the sweep (fixed order over the items)
+  launch_reduce_theta(ctx->stream, ctx->partial, (int)max_items, 1.0 / ctx->pot.D, 1.0 / ctx->pot.r0, dtheta,
+                      ctx->dacc);
   // deposit term of the initial positions, back to the caller's order
   const Store ref0 = ref_of(0);
   launch_deposit_vjp_store(ctx->stream, nd, b, state_at(ctx, rec + R.state, ref0), nbar_next, lx);

@@ -130,11 +130,15 @@ void launch_fill32(hipStream_t s, int *a, int64_t n);
 
 // reverse mode in the store (pic_tiled.hip); lx [ndim][cap], lv [3][cap]
 size_t adjoint_lds_bytes(const TileGeo &tg, int ndim);
+// partial: per-item parameter sums, ACCUMULATED over the calls (clear once);
+// dens: the global node densities of the step (for particles outside their
+// window)
 void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
-                          const BinBufs &bb, int max_items, const long long *N, const float *dens, const float *G,
-                          const float *nbar_next, float *lx, float *lv, float *nbar, float *Gbar, int *dlist,
-                          int *dcount, const uint32_t *amax_prev, uint32_t *amax_cur, double *partial, double *dacc,
+                          const BinBufs &bb, int max_items, const long long *N, const float *dens,
+                          const float *nbar_next, float *lx, float *lv, float *nbar, int *dlist, int *dcount,
+                          const uint32_t *amax_prev, uint32_t *amax_cur, double *partial, double *dacc,
                           uint32_t *err);
+void launch_density(hipStream_t s, const Geo &g, const long long *node, float *dens);
 // largest node-cotangent contribution of a reverse step, measured only (the
 // fixed-point scale of the first reverse step); lx, lv are read only
 void launch_adjoint_scale(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,

@@ -840,6 +840,171 @@ __device__ __forceinline__ int adj_scale_exp(uint32_t amax_bits) {
   return min(max(44 - e, -100), 100);
 }
 
+// Node values at frame coordinates: an LDS window (frame = window), or the
+// global node arrays (frame = global node coordinates, folded like the
+// window: periodic wrap, mirror across reflecting walls).
+template <int ND>
+struct WinRead {
+  const float *a;
+  int s1, s2;  // window strides
+  __device__ __forceinline__ float operator()(int x, int y, int z) const {
+    return a[x + s1 * y + (ND == 3 ? s2 * z : 0)];
+  }
+};
+
+template <int ND>
+__device__ __forceinline__ int folded_node(const Geo &g, int x, int y, int z) {
+  return node_index<ND>(g, fold_node(g, 0, x), fold_node(g, 1, y), ND == 3 ? fold_node(g, 2, z) : 0);
+}
+
+template <int ND>
+struct GlobalDens {
+  const float *d;
+  const Geo *g;
+  __device__ __forceinline__ float operator()(int x, int y, int z) const { return d[folded_node<ND>(*g, x, y, z)]; }
+};
+
+template <int ND>
+struct GlobalNext {  // kfac * nbar of step n+1 at a (real) node
+  const float *nb;
+  const Geo *g;
+  __device__ __forceinline__ float operator()(int x, int y, int z) const {
+    const int a = fold_node(*g, 0, x), b = fold_node(*g, 1, y), c = ND == 3 ? fold_node(*g, 2, z) : 0;
+    return node_density(*g, 1ll, a, b, c) * nb[node_index<ND>(*g, a, b, c)];
+  }
+};
+
+// The reverse step of one particle from a 3^ND block of node densities (the
+// nodes around its 2^ND nearest cell centres).  l: frame coordinates of the
+// own cell's lower node.  The 2^ND centre gradients come from the block
+// through the forward's own centre_gradient (same bits as the forward's
+// window), the forward step is recomputed, the deposit term of step n+1 is
+// read at the new position through `next` when has_next, and the cotangents
+// of the gathered density and gradient go back to the block: a3 (node
+// cotangents of the block, first node at frame coordinates B).
+template <int ND, class Dens, class Next>
+__device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P, const int idx[3], const int l[3],
+                                                     const PState &q, const Dens &dens, bool has_next,
+                                                     const Next &next, float ln[3], float lvv[3], float lf[3],
+                                                     float th[4], int B[3], float a3[ND == 2 ? 9 : 27]) {
+  constexpr int K3 = ND == 2 ? 9 : 27;
+  float cr[8];
+#pragma unroll
+  for (int k = 0; k < (1 << ND); ++k)
+    cr[k] = dens(l[0] + (k & 1), l[1] + ((k >> 1) & 1), ND == 3 ? l[2] + ((k >> 2) & 1) : 0);
+  const float nh = interp<ND>(cr, q.f);
+  float dn[3];  // d nh / d offset, taken now so that cr dies here
+  interp_grad<ND>(cr, q.f, dn);
+  float t[3] = {0.f, 0.f, 0.f};
+  B[2] = 0;
+#pragma unroll
+  for (int e = 0; e < ND; ++e) centre_stencil(l[e], q.f[e], B[e], t[e]);
+  float Gp[3] = {0.f, 0.f, 0.f}, dG[3][3];
+  {
+    float d3[K3];
+#pragma unroll
+    for (int a = 0; a < K3; ++a) d3[a] = dens(B[0] + a % 3, B[1] + (a / 3) % 3, ND == 3 ? B[2] + a / 9 : 0);
+    float vv[3][8];
+#pragma unroll
+    for (int k = 0; k < (1 << ND); ++k) {
+      float c[8], Gc[3];
+#pragma unroll
+      for (int j = 0; j < (1 << ND); ++j)
+        c[j] = d3[b3<ND>((k & 1) + (j & 1), ((k >> 1) & 1) + ((j >> 1) & 1),
+                         ND == 3 ? ((k >> 2) & 1) + ((j >> 2) & 1) : 0)];
+      centre_gradient<ND>(g, c, Gc);
+#pragma unroll
+      for (int d = 0; d < ND; ++d) vv[d][k] = Gc[d];
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      Gp[d] = interp<ND>(vv[d], t);
+      interp_grad<ND>(vv[d], t, dG[d]);  // d Gp / d offset; vv dies here
+    }
+  }
+  PushRecord r;
+  const uint32_t e_push = recompute_push<ND>(g, P, idx, q.f, q.v, nh, Gp, r);
+  if (has_next) {
+    int l2[3] = {0, 0, 0};
+#pragma unroll
+    for (int e = 0; e < ND; ++e) {
+      int dlt = r.idx2[e] - idx[e];
+      dlt = dlt > 1 ? dlt - g.n[e] : (dlt < -1 ? dlt + g.n[e] : dlt);  // across the periodic seam
+      l2[e] = l[e] + dlt;
+    }
+    float c[8], dd[3];
+#pragma unroll
+    for (int k = 0; k < (1 << ND); ++k)
+      c[k] = next(l2[0] + (k & 1), l2[1] + ((k >> 1) & 1), ND == 3 ? l2[2] + ((k >> 2) & 1) : 0);
+    interp_grad<ND>(c, r.f2, dd);
+    const float wgt = (float)q.W;
+#pragma unroll
+    for (int e = 0; e < ND; ++e) ln[e] = __builtin_fmaf(wgt, dd[e], ln[e]);
+  }
+  float mu[3] = {0.f, 0.f, 0.f}, an, aG[3];
+  reverse_drift_kick<ND>(g, P, r, ln, lvv, lf, mu);
+  pair_force_vjp<ND>(P, nh, Gp, mu, an, aG, th);
+#pragma unroll
+  for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(an, dn[e], lf[e]);
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+#pragma unroll
+    for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(aG[d], dG[d][e], lf[e]);
+  // cotangents back to the block: gradient stencil, then own corners
+#pragma unroll
+  for (int a = 0; a < K3; ++a) a3[a] = 0.0f;
+  float T[8];
+  corner_weights<ND>(t, T);
+#pragma unroll
+  for (int k = 0; k < (1 << ND); ++k) {
+    float wd[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int d = 0; d < ND; ++d) wd[d] = aG[d] * T[k] * g.gam[d];
+#pragma unroll
+    for (int j = 0; j < (1 << ND); ++j) {
+      float v = 0.0f;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) v += ((j >> d) & 1) ? wd[d] : -wd[d];
+      a3[b3<ND>((k & 1) + (j & 1), ((k >> 1) & 1) + ((j >> 1) & 1), ND == 3 ? ((k >> 2) & 1) + ((j >> 2) & 1) : 0)] +=
+          v;
+    }
+  }
+  float u[3][3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int o = e < ND ? l[e] - B[e] : 0;  // own cell's lower node in the block: 0 or 1
+    const float fe = e < ND ? q.f[e] : 0.0f;
+    u[e][0] = o == 0 ? 1.0f - fe : 0.0f;
+    u[e][1] = o == 0 ? fe : 1.0f - fe;
+    u[e][2] = o == 0 ? 0.0f : fe;
+  }
+#pragma unroll
+  for (int a = 0; a < K3; ++a) {
+    const float sh = u[0][a % 3] * u[1][(a / 3) % 3] * (ND == 3 ? u[2][a / 9] : 1.0f);
+    a3[a] = __builtin_fmaf(an, sh, a3[a]);
+  }
+  return e_push;
+}
+
+// Adds NF per-thread values, summed over the block, into out[0..NF).
+template <int NF>
+__device__ __forceinline__ void block_reduce_add(double v[NF], double *__restrict__ out) {
+  __shared__ double red[NF][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int i = 0; i < NF; ++i)
+    for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_down(v[i], o, 64);
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < NF; ++i) red[i][wave] = v[i];
+  __syncthreads();
+  if (threadIdx.x < NF) {
+    double s = 0.0;
+    for (int w = 0; w < nwaves; ++w) s += red[threadIdx.x][w];
+    out[threadIdx.x] += s;
+  }
+}
+
 template <int ND, bool MAXONLY>
 __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, const Item *__restrict__ items,
                                                        const int *__restrict__ num_items,
@@ -853,13 +1018,10 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
   constexpr int K3 = ND == 2 ? 9 : 27;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t s_amax;
-  if ((int)blockIdx.x >= *num_items) {
-    if (!MAXONLY && threadIdx.x < 4) partial[(int64_t)blockIdx.x * 8 + threadIdx.x] = 0.0;
-    return;
-  }
+  if ((int)blockIdx.x >= *num_items) return;
   const int sexp = MAXONLY ? 0 : adj_scale_exp(*amax_prev);
-  const float to_fix = ldexpf(1.0f, sexp);             // exact power of two (sexp within float range)
-  const float lim = ldexpf(1.0f, 52 - sexp);           // larger values: global float atomics
+  const float to_fix = ldexpf(1.0f, sexp);    // exact power of two (sexp within float range)
+  const float lim = ldexpf(1.0f, 52 - sexp);  // larger values: global float atomics
   float vmax = 0.0f;
   const Item it = items[blockIdx.x];
   const SlabDesc &sd = b.slabs[it.slab];
@@ -884,6 +1046,8 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
     acc[k] = 0ull;
   }
   __syncthreads();
+  const WinRead<ND> dens{dw, w.wn[0], w.wn[0] * w.wn[1]};
+  const WinRead<ND> next{nx, w.wn[0], w.wn[0] * w.wn[1]};
   const int cap = (int)s.cap;
   const StoreView sv = view_of(s, s);
   uint32_t e_all = 0;
@@ -899,120 +1063,20 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
     const bool inside = live && in_window<ND>(g, w, idx, 1, 3, l);
     if (!MAXONLY) wave_append(dlist, dcount, p, live && !inside);  // the global path, in a kernel of its own
     if (inside) {
-      float lf[3] = {0.f, 0.f, 0.f}, mu[3] = {0.f, 0.f, 0.f};
-      float an, aG[3], th[4] = {0.f, 0.f, 0.f, 0.f};
-      // gather from the window: own-cell corners and the 3^ND stencil block
-      float cr[8];
-#pragma unroll
-      for (int k = 0; k < (1 << ND); ++k)
-        cr[k] = dw[win_node<ND>(w, l[0] + (k & 1), l[1] + ((k >> 1) & 1), ND == 3 ? l[2] + ((k >> 2) & 1) : 0)];
-      const float nh = interp<ND>(cr, q.f);
-      float dn[3];  // d nh / d offset, taken now so that cr dies here
-      interp_grad<ND>(cr, q.f, dn);
-      int B[3] = {0, 0, 0};
-      float t[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-      for (int e = 0; e < ND; ++e) centre_stencil(l[e], q.f[e], B[e], t[e]);
-      float Gp[3] = {0.f, 0.f, 0.f}, dG[3][3];
-      {
-        float d3[K3];
-#pragma unroll
-        for (int a = 0; a < K3; ++a)
-          d3[a] = dw[win_node<ND>(w, B[0] + a % 3, B[1] + (a / 3) % 3, ND == 3 ? B[2] + a / 9 : 0)];
-        float vv[3][8];
-#pragma unroll
-        for (int k = 0; k < (1 << ND); ++k) {
-          float c[8], Gc[3];
-#pragma unroll
-          for (int j = 0; j < (1 << ND); ++j)
-            c[j] = d3[b3<ND>((k & 1) + (j & 1), ((k >> 1) & 1) + ((j >> 1) & 1),
-                             ND == 3 ? ((k >> 2) & 1) + ((j >> 2) & 1) : 0)];
-          centre_gradient<ND>(g, c, Gc);
-#pragma unroll
-          for (int d = 0; d < ND; ++d) vv[d][k] = Gc[d];
-        }
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-          Gp[d] = interp<ND>(vv[d], t);
-          interp_grad<ND>(vv[d], t, dG[d]);  // d Gp / d offset; vv dies here
-        }
-      }
-      // forward step recomputed; deposit term of step n+1 from the window
-      PushRecord r;
-      e_all |= recompute_push<ND>(g, P, idx, q.f, q.v, nh, Gp, r);
-      if (nbn) {
-        int l2[3] = {0, 0, 0};
-#pragma unroll
-        for (int e = 0; e < ND; ++e) {
-          int dlt = r.idx2[e] - idx[e];
-          dlt = dlt > 1 ? dlt - g.n[e] : (dlt < -1 ? dlt + g.n[e] : dlt);  // across the periodic seam
-          l2[e] = l[e] + dlt;
-        }
-        float c[8], dd[3];
-#pragma unroll
-        for (int k = 0; k < (1 << ND); ++k)
-          c[k] = nx[win_node<ND>(w, l2[0] + (k & 1), l2[1] + ((k >> 1) & 1), ND == 3 ? l2[2] + ((k >> 2) & 1) : 0)];
-        interp_grad<ND>(c, r.f2, dd);
-        const float wgt = (float)q.W;
-#pragma unroll
-        for (int e = 0; e < ND; ++e) ln[e] = __builtin_fmaf(wgt, dd[e], ln[e]);
-      }
-      reverse_drift_kick<ND>(g, P, r, ln, lvv, lf, mu);
-      pair_force_vjp<ND>(P, nh, Gp, mu, an, aG, th);
-      // direct position terms
-#pragma unroll
-      for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(an, dn[e], lf[e]);
-#pragma unroll
-      for (int d = 0; d < ND; ++d)
-#pragma unroll
-        for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(aG[d], dG[d][e], lf[e]);
-      // cotangents back to the 3^ND block: gradient stencil, then own corners
-      float a3[K3];
-#pragma unroll
-      for (int a = 0; a < K3; ++a) a3[a] = 0.0f;
-      float T[8];
-      corner_weights<ND>(t, T);
-#pragma unroll
-      for (int k = 0; k < (1 << ND); ++k) {
-        float wd[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-        for (int d = 0; d < ND; ++d) wd[d] = aG[d] * T[k] * g.gam[d];
-#pragma unroll
-        for (int j = 0; j < (1 << ND); ++j) {
-          float v = 0.0f;
-#pragma unroll
-          for (int d = 0; d < ND; ++d) v += ((j >> d) & 1) ? wd[d] : -wd[d];
-          a3[b3<ND>((k & 1) + (j & 1), ((k >> 1) & 1) + ((j >> 1) & 1),
-                    ND == 3 ? ((k >> 2) & 1) + ((j >> 2) & 1) : 0)] += v;
-        }
-      }
-      float u[3][3];
-#pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        const int o = e < ND ? l[e] - B[e] : 0;  // own cell's lower node in the block: 0 or 1
-        const float fe = e < ND ? q.f[e] : 0.0f;
-        u[e][0] = o == 0 ? 1.0f - fe : 0.0f;
-        u[e][1] = o == 0 ? fe : 1.0f - fe;
-        u[e][2] = o == 0 ? 0.0f : fe;
-      }
-#pragma unroll
-      for (int a = 0; a < K3; ++a) {
-        const float sh = u[0][a % 3] * u[1][(a / 3) % 3] * (ND == 3 ? u[2][a / 9] : 1.0f);
-        a3[a] = __builtin_fmaf(an, sh, a3[a]);
-      }
+      float lf[3] = {0.f, 0.f, 0.f}, th[4] = {0.f, 0.f, 0.f, 0.f}, a3[K3];
+      int B[3];
+      e_all |= adjoint_on_block<ND>(g, P, idx, l, q, dens, nbn != nullptr, next, ln, lvv, lf, th, B, a3);
 #pragma unroll
       for (int a = 0; a < K3; ++a) vmax = fmaxf(vmax, fabsf(a3[a]));
       if (!MAXONLY) {
 #pragma unroll
         for (int a = 0; a < K3; ++a) {
           if (a3[a] == 0.0f) continue;
-          const int k = win_node<ND>(w, B[0] + a % 3, B[1] + (a / 3) % 3, ND == 3 ? B[2] + a / 9 : 0);
+          const int ax = B[0] + a % 3, ay = B[1] + (a / 3) % 3, az = ND == 3 ? B[2] + a / 9 : 0;
           if (fabsf(a3[a]) < lim) {
-            atomicAdd(&acc[k], (unsigned long long)__float2ll_rn(a3[a] * to_fix));
+            atomicAdd(&acc[win_node<ND>(w, ax, ay, az)], (unsigned long long)__float2ll_rn(a3[a] * to_fix));
           } else {
-            const int x = fold_node(g, 0, w.o[0] + B[0] + a % 3), y = fold_node(g, 1, w.o[1] + B[1] + (a / 3) % 3);
-            const int z = ND == 3 ? fold_node(g, 2, w.o[2] + B[2] + a / 9) : 0;
-            atomicAdd(&nbar[sd.node_off + node_index<ND>(g, x, y, z)], a3[a]);
+            atomicAdd(&nbar[sd.node_off + folded_node<ND>(g, w.o[0] + ax, w.o[1] + ay, w.o[2] + az)], a3[a]);
           }
         }
 #pragma unroll
@@ -1034,30 +1098,29 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
   for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
     const long long iv = (long long)acc[k];
     if (iv == 0) continue;
-    const float v = (float)((double)iv * from_fix);
     const int a0 = k % w.wn[0], r = k / w.wn[0];
     const int a1 = ND == 2 ? r : r % w.wn[1];
     const int a2 = ND == 2 ? 0 : r / w.wn[1];
-    const int x = fold_node(g, 0, w.o[0] + a0), y = fold_node(g, 1, w.o[1] + a1);
-    const int z = ND == 3 ? fold_node(g, 2, w.o[2] + a2) : 0;
-    atomicAdd(&nbar[sd.node_off + node_index<ND>(g, x, y, z)], v);
+    atomicAdd(&nbar[sd.node_off + folded_node<ND>(g, w.o[0] + a0, w.o[1] + a1, w.o[2] + a2)],
+              (float)((double)iv * from_fix));
   }
   if (e_all) atomicOr(err, e_all);
   double thd[4] = {thf[0], thf[1], thf[2], thf[3]};
-  block_reduce_store<4>(thd, partial + (int64_t)blockIdx.x * 8);
+  block_reduce_add<4>(thd, partial + (int64_t)blockIdx.x * 8);  // accumulates over the sweep
 }
 
-// The reverse step of the particles outside their window: global density and
-// gradient grids, global scatters; parameter terms into dacc[0..3].
+// The reverse step of the particles outside their window: the same block
+// computation on the global densities (folded like the window), scatters as
+// global float atomics; parameter terms into dacc[0..3].
 template <int ND>
 __global__ void __launch_bounds__(256) k_adjoint_drifters(Pot P, Batch b, Store s, const int *__restrict__ dlist,
                                                           const int *__restrict__ dcount,
                                                           const float *__restrict__ dens_g,
-                                                          const float *__restrict__ G_g,
                                                           const float *__restrict__ nbar_next,
                                                           float *__restrict__ lx, float *__restrict__ lv,
-                                                          float *__restrict__ nbar, float *__restrict__ Gbar,
-                                                          double *__restrict__ dacc, uint32_t *__restrict__ err) {
+                                                          float *__restrict__ nbar, double *__restrict__ dacc,
+                                                          uint32_t *__restrict__ err) {
+  constexpr int K3 = ND == 2 ? 9 : 27;
   const int n = *dcount;
   const int cap = (int)s.cap;
   const StoreView sv = view_of(s, s);
@@ -1067,18 +1130,20 @@ __global__ void __launch_bounds__(256) k_adjoint_drifters(Pot P, Batch b, Store 
     const SlabDesc &sd = b.slabs[find_slab(b.part_offs, b.nslab, p)];
     const Geo g = sd.g;
     PState q;
-    load_state<ND, true>(sv, p, true, q);
+    float ln[3], lvv[3];
+    load_adjoint_state<ND>(sv, lx, lv, cap, p, true, q, ln, lvv);
     int idx[3];
     unpack_cell<ND>(sd.tg, q.pc, idx);
-    float ln[3] = {lx[p], lx[cap + p], ND == 3 ? lx[2 * cap + p] : 0.0f};
-    float lvv[3] = {lv[p], lv[cap + p], lv[2 * cap + p]};
-    float lf[3] = {0.f, 0.f, 0.f}, mu[3] = {0.f, 0.f, 0.f};
-    float an, aG[3], th[4] = {0.f, 0.f, 0.f, 0.f};
-    GatherState<ND> gs;
-    gather_for_vjp<ND>(g, dens_g, G_g, idx, q.f, gs);
-    e_all |= reverse_push<ND>(g, P, idx, q.f, q.v, q.W, gs.nh, gs.Gp, nbar_next, ln, lvv, lf, mu);
-    pair_force_vjp<ND>(P, gs.nh, gs.Gp, mu, an, aG, th);
-    gather_vjp<ND>(g, idx, q.f, gs, an, aG, lf, nbar, Gbar);
+    const GlobalDens<ND> dens{dens_g + sd.node_off, &g};
+    const GlobalNext<ND> next{nbar_next ? nbar_next + sd.node_off : nullptr, &g};
+    float lf[3] = {0.f, 0.f, 0.f}, th[4] = {0.f, 0.f, 0.f, 0.f}, a3[K3];
+    int B[3];
+    e_all |= adjoint_on_block<ND>(g, P, idx, idx, q, dens, nbar_next != nullptr, next, ln, lvv, lf, th, B, a3);
+#pragma unroll
+    for (int a = 0; a < K3; ++a)
+      if (a3[a] != 0.0f)
+        atomicAdd(&nbar[sd.node_off + folded_node<ND>(g, B[0] + a % 3, B[1] + (a / 3) % 3, ND == 3 ? B[2] + a / 9 : 0)],
+                  a3[a]);
 #pragma unroll
     for (int d = 0; d < ND; ++d) lx[d * cap + p] = lf[d];
 #pragma unroll
@@ -1232,9 +1297,9 @@ size_t adjoint_lds_bytes(const TileGeo &tg, int ndim) {
 }
 
 void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
-                          const BinBufs &bb, int max_items, const long long *N, const float *dens, const float *G,
-                          const float *nbar_next, float *lx, float *lv, float *nbar, float *Gbar, int *dlist,
-                          int *dcount, const uint32_t *amax_prev, uint32_t *amax_cur, double *partial, double *dacc,
+                          const BinBufs &bb, int max_items, const long long *N, const float *dens,
+                          const float *nbar_next, float *lx, float *lv, float *nbar, int *dlist, int *dcount,
+                          const uint32_t *amax_prev, uint32_t *amax_cur, double *partial, double *dacc,
                           uint32_t *err) {
   if (max_items <= 0) return;
   const size_t lds = adjoint_lds_bytes(tg, ndim);
@@ -1243,8 +1308,8 @@ void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot
   PIC_ND(ndim, (k_adjoint_tiled<ND, false><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, N, nbar_next,
                                                                           lx, lv, nbar, dlist, dcount, amax_prev,
                                                                           amax_cur, partial, err)));
-  PIC_ND(ndim, (k_adjoint_drifters<ND><<<kDriftBlocks, 256, 0, st>>>(P, b, s, dlist, dcount, dens, G, nbar_next, lx,
-                                                                       lv, nbar, Gbar, dacc, err)));
+  PIC_ND(ndim, (k_adjoint_drifters<ND><<<kDriftBlocks, 256, 0, st>>>(P, b, s, dlist, dcount, dens, nbar_next, lx, lv,
+                                                                       nbar, dacc, err)));
 }
 
 void launch_adjoint_scale(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
