@@ -886,7 +886,7 @@ template <int ND, class Dens, class Next>
 __device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P, const int idx[3], const int l[3],
                                                      const PState &q, const Dens &dens, bool has_next,
                                                      const Next &next, float ln[3], float lvv[3], float lf[3],
-                                                     float th[4], int B[3], float a3[ND == 2 ? 9 : 27]) {
+                                                     float th[4], int B[3], float t[3], float &an, float aG[3]) {
   constexpr int K3 = ND == 2 ? 9 : 27;
   float cr[8];
 #pragma unroll
@@ -895,7 +895,7 @@ __device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P,
   const float nh = interp<ND>(cr, q.f);
   float dn[3];  // d nh / d offset, taken now so that cr dies here
   interp_grad<ND>(cr, q.f, dn);
-  float t[3] = {0.f, 0.f, 0.f};
+  t[0] = t[1] = t[2] = 0.0f;
   B[2] = 0;
 #pragma unroll
   for (int e = 0; e < ND; ++e) centre_stencil(l[e], q.f[e], B[e], t[e]);
@@ -941,7 +941,7 @@ __device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P,
 #pragma unroll
     for (int e = 0; e < ND; ++e) ln[e] = __builtin_fmaf(wgt, dd[e], ln[e]);
   }
-  float mu[3] = {0.f, 0.f, 0.f}, an, aG[3];
+  float mu[3] = {0.f, 0.f, 0.f};
   reverse_drift_kick<ND>(g, P, r, ln, lvv, lf, mu);
   pair_force_vjp<ND>(P, nh, Gp, mu, an, aG, th);
 #pragma unroll
@@ -950,7 +950,17 @@ __device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P,
   for (int d = 0; d < ND; ++d)
 #pragma unroll
     for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(aG[d], dG[d][e], lf[e]);
-  // cotangents back to the block: gradient stencil, then own corners
+  return e_push;
+}
+
+// The cotangents of a particle's gathered density (an) and gradient (aG) on
+// its 3^ND node block: the transpose of the centre-gradient stencil
+// (weights t), then the own cell's corners (offsets f, own lower node l).
+template <int ND>
+__device__ __forceinline__ void block_cotangents(const Geo &g, const int l[3], const int B[3], const float f[3],
+                                                 const float t[3], float an, const float aG[3],
+                                                 float a3[ND == 2 ? 9 : 27]) {
+  constexpr int K3 = ND == 2 ? 9 : 27;
 #pragma unroll
   for (int a = 0; a < K3; ++a) a3[a] = 0.0f;
   float T[8];
@@ -973,7 +983,7 @@ __device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P,
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     const int o = e < ND ? l[e] - B[e] : 0;  // own cell's lower node in the block: 0 or 1
-    const float fe = e < ND ? q.f[e] : 0.0f;
+    const float fe = e < ND ? f[e] : 0.0f;
     u[e][0] = o == 0 ? 1.0f - fe : 0.0f;
     u[e][1] = o == 0 ? fe : 1.0f - fe;
     u[e][2] = o == 0 ? 0.0f : fe;
@@ -983,7 +993,6 @@ __device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P,
     const float sh = u[0][a % 3] * u[1][(a / 3) % 3] * (ND == 3 ? u[2][a / 9] : 1.0f);
     a3[a] = __builtin_fmaf(an, sh, a3[a]);
   }
-  return e_push;
 }
 
 // Adds NF per-thread values, summed over the block, into out[0..NF).
@@ -1063,9 +1072,19 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
     const bool inside = live && in_window<ND>(g, w, idx, 1, 3, l);
     if (!MAXONLY) wave_append(dlist, dcount, p, live && !inside);  // the global path, in a kernel of its own
     if (inside) {
-      float lf[3] = {0.f, 0.f, 0.f}, th[4] = {0.f, 0.f, 0.f, 0.f}, a3[K3];
+      float lf[3] = {0.f, 0.f, 0.f}, th[4] = {0.f, 0.f, 0.f, 0.f}, t[3], an, aG[3];
       int B[3];
-      e_all |= adjoint_on_block<ND>(g, P, idx, l, q, dens, nbn != nullptr, next, ln, lvv, lf, th, B, a3);
+      e_all |= adjoint_on_block<ND>(g, P, idx, l, q, dens, nbn != nullptr, next, ln, lvv, lf, th, B, t, an, aG);
+      if (!MAXONLY) {  // the particle's cotangents and parameter terms, before its node block
+#pragma unroll
+        for (int d = 0; d < ND; ++d) lx[d * cap + p] = lf[d];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) lv[d * cap + p] = lvv[d];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) thf[i] += th[i];
+      }
+      float a3[K3];
+      block_cotangents<ND>(g, l, B, q.f, t, an, aG, a3);
 #pragma unroll
       for (int a = 0; a < K3; ++a) vmax = fmaxf(vmax, fabsf(a3[a]));
       if (!MAXONLY) {
@@ -1079,12 +1098,6 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
             atomicAdd(&nbar[sd.node_off + folded_node<ND>(g, w.o[0] + ax, w.o[1] + ay, w.o[2] + az)], a3[a]);
           }
         }
-#pragma unroll
-        for (int d = 0; d < ND; ++d) lx[d * cap + p] = lf[d];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) lv[d * cap + p] = lvv[d];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) thf[i] += th[i];
       }
     }
   }
@@ -1136,9 +1149,10 @@ __global__ void __launch_bounds__(256) k_adjoint_drifters(Pot P, Batch b, Store 
     unpack_cell<ND>(sd.tg, q.pc, idx);
     const GlobalDens<ND> dens{dens_g + sd.node_off, &g};
     const GlobalNext<ND> next{nbar_next ? nbar_next + sd.node_off : nullptr, &g};
-    float lf[3] = {0.f, 0.f, 0.f}, th[4] = {0.f, 0.f, 0.f, 0.f}, a3[K3];
+    float lf[3] = {0.f, 0.f, 0.f}, th[4] = {0.f, 0.f, 0.f, 0.f}, t[3], an, aG[3], a3[K3];
     int B[3];
-    e_all |= adjoint_on_block<ND>(g, P, idx, idx, q, dens, nbar_next != nullptr, next, ln, lvv, lf, th, B, a3);
+    e_all |= adjoint_on_block<ND>(g, P, idx, idx, q, dens, nbar_next != nullptr, next, ln, lvv, lf, th, B, t, an, aG);
+    block_cotangents<ND>(g, idx, B, q.f, t, an, aG, a3);
 #pragma unroll
     for (int a = 0; a < K3; ++a)
       if (a3[a] != 0.0f)
