@@ -212,6 +212,8 @@ def run_adjoint(log_fn=log, every=20, steps=None):
     J, gth, gF, t_rec, t_bwd = grad_once()
     log_fn(f"adjoint: forward {t_fwd * 1e3:.1f} ms, recorded forward {t_rec * 1e3:.1f} ms, "
            f"backward {t_bwd * 1e3:.1f} ms")
+    step_bytes = 60 * p.n + 16 * B.pic_num_nodes(g)  # 3D algorithmic bytes per step
+    fwd_gbs = step_bytes * nsteps / t_fwd / 1e9
     del ctx
     torch.cuda.empty_cache()
     return {"workload": f"{wl.name}: 128^3 cells, slab 64 layers, 8 ppc, 1.5 J/cm^2, {nsteps} steps, "
@@ -220,7 +222,79 @@ def run_adjoint(log_fn=log, every=20, steps=None):
             "forward_s": t_fwd, "recorded_forward_s": t_rec, "backward_s": t_bwd,
             "adjoint_over_forward": t_bwd / t_fwd, "gradient_over_forward": (t_rec + t_bwd) / t_fwd,
             "forward_particle_steps_per_s": p.n * nsteps / t_fwd,
+            "forward_roofline": {"achieved_gbs": fwd_gbs, "frac": fwd_gbs / HBM_PEAK_GBS,
+                                 "basis": "60 B/particle + 16 B/node per step, whole step"},
             "J": J, "dJ_dtheta": {k: float(v) for k, v in zip(A.THETA_KEYS, gth)}, "dJ_dfluence": gF}
+
+
+def run_slab(name, steps, warmup, log_fn=log):
+    """One single-slab workload through pic_step: (result, workload, potential,
+    diagnostics).  The timed region is one pic_step call of `steps` steps
+    with diagnostics every 100 steps, particles resident in HBM."""
+    import numpy as np
+    import torch
+    from paper_1502_07722_amd import binding as B
+    from paper_1502_07722_amd import workloads as W
+
+    t0 = time.perf_counter()
+    wl = W.WORKLOADS[name]()
+    log_fn(f"generated {wl.name}: {wl.parts.n} particles in {time.perf_counter() - t0:.1f} s")
+    c_att, _ = B.pic_calibrate_catt(wl.grid, wl.pot, W.N_SOLID, 8)
+    pot = W.Potential(c_att=c_att)
+    N = wl.parts.n
+    dev = torch.device("cuda:0")
+    # a created stream: plain steps replay as HIP graphs there
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        dp = B.DeviceParticles.from_host(wl.parts, dev)
+        ctx = B.Context(wl.grid, pot, wl.dt, N, device=dev, stream=stream)
+        ctx.start_leapfrog(dp)
+        tuning = ctx.pic_autotune(dp, 6)
+        log_fn(f"{wl.name}: autotuned tiling {tuning}")
+        start = dp.clone()
+        if warmup:
+            ctx.pic_step(dp, warmup, 100)
+        dp = start.clone()
+        stream.synchronize()
+        log_fn(f"{wl.name}: timing {steps} steps")
+        t0 = time.perf_counter()
+        diags = ctx.pic_step(dp, steps, 100)
+        stream.synchronize()
+        elapsed = time.perf_counter() - t0
+        # the same run again with HIP events on every launch (no graphs):
+        # the fused kernel's average duration for the roofline
+        dp = start.clone()
+        ctx.pic_set_timing(True)
+        stream.synchronize()
+        t1 = time.perf_counter()
+        ctx.pic_step(dp, steps, 100)
+        stream.synchronize()
+        elapsed_events = time.perf_counter() - t1
+        timing = ctx.pic_get_timing()
+        ctx.pic_set_timing(False)
+    log_fn(f"{steps} steps in {elapsed:.3f} s (with per-launch events {elapsed_events:.3f} s); phases {timing}")
+    nd = wl.grid.ndim
+    bytes_per_particle = 4 + 4 * nd + 12 + 4 + 4 + 4 * nd + 12
+    nnodes = B.pic_num_nodes(wl.grid)
+    launch_bytes = bytes_per_particle * N + 16 * nnodes
+    ms_fp, nfp = timing.get("force_push", (0.0, 0))
+    avg_s = ms_fp / 1e3 / max(nfp, 1)
+    achieved = launch_bytes / avg_s / 1e9 if nfp else None
+    traffic = measured_traffic(name)
+    roofline = {"bound": "hbm", "kernel": "k_step_tiled (fused gather+force+push+deposit)", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                "traffic": traffic,
+                "traffic_gbs": traffic / avg_s / 1e9 if (traffic and nfp) else None,
+                "bytes_per_launch": launch_bytes, "bytes_per_particle": bytes_per_particle,
+                "bytes_per_node": 16, "avg_launch_ms": avg_s * 1e3,
+                "phases_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in timing.items() if isinstance(v, tuple)},
+                "drifters_last_step": timing.get("drifters_last"), "items_last_step": timing.get("items_last")}
+    res = {"workload": wl.name, "particles": N, "value": N * steps / elapsed, "ms_per_step": elapsed / steps * 1e3,
+           "elapsed_s": elapsed, "roofline": roofline, "c_att": c_att, "tiling": tuning,
+           "ms_per_step_with_events": elapsed_events / steps * 1e3}
+    del ctx, dp, start
+    torch.cuda.empty_cache()
+    return res, wl, pot, diags
 
 
 def main():
@@ -233,6 +307,8 @@ def main():
                     help="skip the batched intensity sweep (plain loop vs batched) reported in the same line")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the 3D adjoint timing (gradient vs forward cost) reported in the same line")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the small and heated single-slab configs reported in the same line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration for rocprofv3 --pmc)")
@@ -276,49 +352,10 @@ def main():
             torch.mul(src, 1.0, out=dst)  # reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         del src, dst
-    t0 = time.perf_counter()
-    wl = W.WORKLOADS[args.workload]()
-    log(f"generated {wl.name}: {wl.parts.n} particles in {time.perf_counter() - t0:.1f} s")
-    c_att, _ = B.pic_calibrate_catt(wl.grid, wl.pot, W.N_SOLID, 8)
-    pot = W.Potential(c_att=c_att)
-    N = wl.parts.n
-    dev = torch.device("cuda:0")
-    dp = B.DeviceParticles.from_host(wl.parts, dev)
-    ctx = B.Context(wl.grid, pot, wl.dt, N, device=dev)
-    ctx.start_leapfrog(dp)
-    torch.cuda.synchronize()
-    log(f"warmup {warmup} steps")
-    if warmup:
-        ctx.pic_step(dp, warmup, 100)
-    torch.cuda.synchronize()
-    log(f"timing {steps} steps")
-    ctx.pic_set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    diags = ctx.pic_step(dp, steps, 100)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    timing = ctx.pic_get_timing()
-    ctx.pic_set_timing(False)
-    log(f"{steps} steps in {elapsed:.3f} s; phases {timing}")
-    value = N * steps / elapsed
-
-    nd = wl.grid.ndim
-    bytes_per_particle = 4 + 4 * nd + 12 + 4 + 4 + 4 * nd + 12
-    nnodes = B.pic_num_nodes(wl.grid)
-    launch_bytes = bytes_per_particle * N + 16 * nnodes
-    ms_fp, nfp = timing.get("force_push", (0.0, 0))
-    avg_s = ms_fp / 1e3 / max(nfp, 1)
-    achieved = launch_bytes / avg_s / 1e9 if nfp else None
-    traffic = measured_traffic(args.workload)
-    roofline = {"bound": "hbm", "kernel": "k_step_tiled (fused gather+force+push+deposit)", "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                "traffic": traffic,
-                "traffic_gbs": traffic / avg_s / 1e9 if (traffic and nfp) else None,
-                "bytes_per_launch": launch_bytes, "bytes_per_particle": bytes_per_particle,
-                "bytes_per_node": 16, "avg_launch_ms": avg_s * 1e3,
-                "phases_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in timing.items() if isinstance(v, tuple)},
-                "drifters_last_step": timing.get("drifters_last"), "items_last_step": timing.get("items_last")}
+    res, wl, pot, diags = run_slab(args.workload, steps, warmup)
+    value, N, nd, c_att = res["value"], wl.parts.n, wl.grid.ndim, res["c_att"]
+    roofline = res["roofline"]
+    elapsed = res["elapsed_s"]
     out = {
         "metric": "particle-steps/s (deposit+force+push)",
         "value": value,
@@ -334,14 +371,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "particles": N, "cells": list(wl.grid.n[:nd]),
                    "ppc": int(round(N / (wl.slab_rows * np.prod(wl.grid.n[: nd - 1])))),
-                   "dt_s": wl.dt, "diag_every": 100, "c_att": c_att,
+                   "dt_s": wl.dt, "diag_every": 100, "c_att": c_att, "tiling": res["tiling"],
                    "state": "int32 cell + f32 offsets/velocities, int64 fixed-point deposit"},
         "roofline": roofline,
         "energy_check": {"E_first": diags[0]["ke"] + diags[0]["pe"], "E_last": diags[-1]["ke"] + diags[-1]["pe"]}
         if diags else None,
     }
-    del ctx, dp
-    torch.cuda.empty_cache()
+    if args.workload == "large" and not args.no_configs:
+        # the other single-slab configs, each with its own roofline fraction
+        out["configs"] = {}
+        for name in ("small", "heated"):
+            r, _, _, _ = run_slab(name, *DEFAULTS[name])
+            out["configs"][name] = {k: r[k] for k in ("workload", "particles", "value", "ms_per_step")}
+            out["configs"][name]["roofline_frac"] = r["roofline"]["frac"]
+            out["configs"][name]["roofline_achieved_gbs"] = r["roofline"]["achieved"]
     if not args.no_sweep and args.workload == "large":
         out["sweep"] = run_sweep(*DEFAULTS["sweep"])
     if not args.no_adjoint and args.workload == "large":

@@ -197,7 +197,7 @@ class Context:
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx:
+        if ctx and lib is not None:  # the module may already be torn down at exit
             lib.pic_destroy(ctx)
             self.ctx = None
 

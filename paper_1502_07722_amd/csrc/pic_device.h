@@ -100,8 +100,14 @@ __device__ __forceinline__ uint32_t quant16(float f) {
   return (uint32_t)min(max(u, 0), 65535);
 }
 
+// floor(part * u / 2^16) for part < 2^31, u < 2^16, from two 16 x 16-bit
+// products (full-rate 24-bit multiplies): part * u = ph u 2^16 + pl u, and the
+// first term is a multiple of 2^16, so the floor splits exactly.
 __device__ __forceinline__ uint32_t split_upper(uint32_t part, uint32_t u) {
-  return (uint32_t)(((uint64_t)part * (uint64_t)u) >> 16);
+  const uint32_t ph = part >> 16, pl = part & 0xffffu;
+  const uint32_t hi = (uint32_t)__umul24(ph, u);  // < 2^31
+  const uint32_t lo = (uint32_t)__umul24(pl, u);  // < 2^32: unsigned before the shift
+  return hi + (lo >> 16);
 }
 
 // Shares of the 2^ND corner nodes; corner bit d set = upper node along d.
