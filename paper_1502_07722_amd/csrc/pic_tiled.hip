@@ -281,7 +281,6 @@ struct StoreView {
   int *pc_o;           // outputs: the same arrays (in place) or the next
   float *off_o[3];     // state's arrays (out of place, when a trajectory
   float *vel_o[3];     // is recorded)
-  bool inplace;
 };
 
 __device__ __forceinline__ StoreView view_of(const Store &s, const Store &o) {
@@ -289,7 +288,6 @@ __device__ __forceinline__ StoreView view_of(const Store &s, const Store &o) {
   v.pc = s.pc;
   v.wq = s.wq;
   v.pc_o = o.pc;
-  v.inplace = s.pc == o.pc;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     v.off[d] = s.off + d * s.cap;
@@ -337,7 +335,9 @@ __device__ __forceinline__ void load_state(const StoreView &sv, int p, bool live
 
 // Force, push, state write-back and the new position's deposit shares of one
 // particle, given its gathered density and gradient.
-template <int ND, bool DIAG, bool INTERIOR>
+// OUT: the next state goes to the view's output arrays (a recorded
+// trajectory); otherwise in place.
+template <int ND, bool DIAG, bool INTERIOR, bool OUT>
 __device__ __forceinline__ void advance_particle(const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
                                                  const StoreView &sv, int p, int pc, int idx[3], float f[3],
                                                  float v[3], int W, float nh, const float Gp[3], uint32_t tq[8],
@@ -360,14 +360,14 @@ __device__ __forceinline__ void advance_particle(const Geo &g, const Pot &P, con
   }
   err |= push_particle<ND, INTERIOR>(g, P, F, idx, f, v);
   const int pc2 = pack_cell<ND>(tg, idx);
-  if (pc2 != pc || !sv.inplace) at(sv.pc_o, p) = pc2;
+  if (pc2 != pc || OUT) at(sv.pc_o, p) = pc2;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     at(sv.off_o[d], p) = f[d];
     at(sv.vel_o[d], p) = v[d];
   }
   // 2D: v_z is never changed; an out-of-place step still carries it over
-  if (ND == 2 && !sv.inplace) at(sv.vel_o[2], p) = DIAG ? v[2] : at(sv.vel[2], p);
+  if (ND == 2 && OUT) at(sv.vel_o[2], p) = DIAG ? v[2] : at(sv.vel[2], p);
   deposit_shares<ND>((uint32_t)W, f, tq);
 }
 
@@ -571,7 +571,7 @@ __device__ __forceinline__ bool item_window(const Geo &g, const Window &w, const
 // The particles of one item whose cells lie in the tile window (drifters are
 // appended to the global list).  Loads for the next round are issued before
 // the current round is computed.
-template <int ND, bool DIAG, bool INTERIOR>
+template <int ND, bool DIAG, bool INTERIOR, bool OUT>
 __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
                                          const StoreView &sv, const Item &it, const Window &w, const float *dens,
                                          const float *Gs, unsigned long long *acc,
@@ -616,7 +616,7 @@ __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC
 #pragma unroll
       for (int d = 0; d < ND; ++d) Gp[d] = interp<ND>(vv[d], t);
       uint32_t tq[8];
-      advance_particle<ND, DIAG, INTERIOR>(g, P, dc, tg, sv, p, cur.pc, idx, cur.f, cur.v, cur.W, nh, Gp, tq,
+      advance_particle<ND, DIAG, INTERIOR, OUT>(g, P, dc, tg, sv, p, cur.pc, idx, cur.f, cur.v, cur.W, nh, Gp, tq,
                                            e_all, acc6);
       // a sub-cell move keeps the new cell inside the deposit window
       if (item_window<ND, INTERIOR>(g, w, idx, 0, 2, l)) {
@@ -638,7 +638,7 @@ __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC
 // Persistent: a fixed grid pulls work items (chunks of one tile of one slab)
 // from an atomic counter until the step's items are done.  Every block also
 // clears its share of the node buffer two steps ahead.
-template <int ND, bool DIAG>
+template <int ND, bool DIAG, bool OUT>
 __global__ void __launch_bounds__(256) k_step_tiled(Pot P, DiagC dc, Batch b, Store s, Store o,
                                                     const Item *__restrict__ items,
                                                     const int *__restrict__ num_items,
@@ -678,9 +678,9 @@ __global__ void __launch_bounds__(256) k_step_tiled(Pot P, DiagC dc, Batch b, St
     for (int d = 0; d < ND; ++d) interior = interior && w.o[d] >= 0 && w.o[d] + w.wn[d] <= g.n[d] + 1;
     double acc6[6] = {0, 0, 0, 0, 0, 0};
     if (interior)
-      run_item<ND, DIAG, true>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dr.list, dr.count, e_all, acc6);
+      run_item<ND, DIAG, true, OUT>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dr.list, dr.count, e_all, acc6);
     else
-      run_item<ND, DIAG, false>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dr.list, dr.count, e_all, acc6);
+      run_item<ND, DIAG, false, OUT>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dr.list, dr.count, e_all, acc6);
     __syncthreads();
     flush_window<ND>(g, w, acc, Nn);
     if (DIAG) block_reduce_store<6>(acc6, partial + (int64_t)bi * 8);
@@ -691,7 +691,7 @@ __global__ void __launch_bounds__(256) k_step_tiled(Pot P, DiagC dc, Batch b, St
 
 // Drifters (particles outside their tile window since the last binning):
 // the same cycle through the global node sums of their slab.
-template <int ND, bool DIAG>
+template <int ND, bool DIAG, bool OUT>
 __global__ void __launch_bounds__(256) k_outliers(Pot P, DiagC dc, Batch b, Store s, Store o, Drift dr,
                                                   const long long *__restrict__ Ncur,
                                                   unsigned long long *__restrict__ Nnext,
@@ -713,7 +713,7 @@ __global__ void __launch_bounds__(256) k_outliers(Pot P, DiagC dc, Batch b, Stor
     gather_nodes_global<ND>(g, Ncur + sd.node_off, idx, q.f, nh, Gp);
     uint32_t tq[8];
     double acc6[6] = {0, 0, 0, 0, 0, 0};
-    advance_particle<ND, DIAG, false>(g, P, dc, tg, sv, p, q.pc, idx, q.f, q.v, q.W, nh, Gp, tq, e_all, acc6);
+    advance_particle<ND, DIAG, false, OUT>(g, P, dc, tg, sv, p, q.pc, idx, q.f, q.v, q.W, nh, Gp, tq, e_all, acc6);
     deposit_global<ND>(g, Nnext + sd.node_off, idx, tq);
     if (DIAG)
 #pragma unroll
@@ -1276,22 +1276,30 @@ void launch_step_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P
   if (grid <= 0) return;
   const size_t lds = window_lds_bytes(tg, ndim);
   unsigned long long *nn = (unsigned long long *)Nnext;
-  if (diag)
-    PIC_ND(ndim, (k_step_tiled<ND, true><<<grid, 256, lds, st>>>(P, dc, b, s, o, bb.items, bb.num_items, Ncur, nn,
-                                                                   Nclear, dr, partial, err)));
+  const bool out = s.pc != o.pc;
+  if (out)
+    PIC_ND(ndim, (k_step_tiled<ND, false, true><<<grid, 256, lds, st>>>(P, dc, b, s, o, bb.items, bb.num_items, Ncur,
+                                                                          nn, Nclear, dr, partial, err)));
+  else if (diag)
+    PIC_ND(ndim, (k_step_tiled<ND, true, false><<<grid, 256, lds, st>>>(P, dc, b, s, o, bb.items, bb.num_items, Ncur,
+                                                                          nn, Nclear, dr, partial, err)));
   else
-    PIC_ND(ndim, (k_step_tiled<ND, false><<<grid, 256, lds, st>>>(P, dc, b, s, o, bb.items, bb.num_items, Ncur, nn,
-                                                                    Nclear, dr, partial, err)));
+    PIC_ND(ndim, (k_step_tiled<ND, false, false><<<grid, 256, lds, st>>>(P, dc, b, s, o, bb.items, bb.num_items, Ncur,
+                                                                           nn, Nclear, dr, partial, err)));
 }
 
 void launch_drifters(hipStream_t st, int ndim, const Pot &P, const DiagC &dc, const Batch &b, const Store &s,
                      const Store &o, const long long *Ncur, long long *Nnext, const Drift &dr, double *dacc,
                      bool diag, uint32_t *err) {
   unsigned long long *nn = (unsigned long long *)Nnext;
-  if (diag)
-    PIC_ND(ndim, (k_outliers<ND, true><<<kDriftBlocks, 256, 0, st>>>(P, dc, b, s, o, dr, Ncur, nn, dacc, err)));
+  const bool out = s.pc != o.pc;
+  if (out)
+    PIC_ND(ndim, (k_outliers<ND, false, true><<<kDriftBlocks, 256, 0, st>>>(P, dc, b, s, o, dr, Ncur, nn, dacc, err)));
+  else if (diag)
+    PIC_ND(ndim, (k_outliers<ND, true, false><<<kDriftBlocks, 256, 0, st>>>(P, dc, b, s, o, dr, Ncur, nn, dacc, err)));
   else
-    PIC_ND(ndim, (k_outliers<ND, false><<<kDriftBlocks, 256, 0, st>>>(P, dc, b, s, o, dr, Ncur, nn, dacc, err)));
+    PIC_ND(ndim,
+           (k_outliers<ND, false, false><<<kDriftBlocks, 256, 0, st>>>(P, dc, b, s, o, dr, Ncur, nn, dacc, err)));
 }
 
 void launch_reduce_diag_slab(hipStream_t st, const double *part_p, const int *item_start, int tile_lo, int tile_hi,
@@ -1357,8 +1365,8 @@ int step_kernel_blocks_per_cu(int ndim, const TileGeo &tg) {
   int nb = 0;
   const size_t lds = window_lds_bytes(tg, ndim);
   hipError_t e;
-  if (ndim == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_tiled<2, false>, 256, lds);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_tiled<3, false>, 256, lds);
+  if (ndim == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_tiled<2, false, false>, 256, lds);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_tiled<3, false, false>, 256, lds);
   return e == hipSuccess && nb > 0 ? nb : 4;
 }
 
