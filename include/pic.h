@@ -249,9 +249,11 @@ int pic_get_tiling(pic_ctx_t *ctx, int32_t *tile, int32_t *halo, int32_t *chunk,
  * captured on a context bound to a created stream (never the NULL stream). */
 int pic_set_graph(pic_ctx_t *ctx, int32_t on);
 
-/* Autotuner: probes tile edge x chunk candidates (halo 2 in 2D, 1 in 3D;
- * re-binning policy unchanged) on the caller's particles for probe_steps
- * steps each, timed with events, and keeps the fastest tiling.  The
+/* Autotuner: probes tile edge x chunk candidates (tile 8, 16, 32 in 2D and
+ * 4, 8 in 3D; chunk 1024 to 16384; halo 2 in 2D, 1 in 3D; re-binning policy
+ * unchanged) on the caller's particles for probe_steps steps each, launched
+ * step by step (no graph capture inside a probe), timed with events, and
+ * keeps the fastest tiling.  The
  * particles are copied into the internal store for every probe: the caller's
  * arrays are only read.  Results never depend on the tiling. */
 typedef struct pic_tuning {

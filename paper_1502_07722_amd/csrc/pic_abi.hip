@@ -1334,10 +1334,11 @@ int pic_autotune(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t probe_ste
   const int nd = ctx->ndim;
   const int halo = nd == 2 ? 2 : 1;
   const int lts[3] = {nd == 2 ? 3 : 2, nd == 2 ? 4 : 3, nd == 2 ? 5 : 3};
-  const int chunks[4] = {2048, 4096, 8192, 16384};
+  const int chunks[5] = {1024, 2048, 4096, 8192, 16384};
   const int old_lt = ctx->lt, old_h = ctx->halo, old_c = ctx->chunk, old_s = ctx->sort_every;
-  const bool old_timing = ctx->timing;
+  const bool old_timing = ctx->timing, old_graph = ctx->use_graph;
   ctx->timing = false;
+  ctx->use_graph = false;  // a graph capture per candidate would land inside its timed probe
   float best = 1e30f;
   int best_lt = old_lt, best_c = old_c, tried = 0;
   pic_particles_t *pp = const_cast<pic_particles_t *>(parts);
@@ -1360,6 +1361,7 @@ int pic_autotune(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t probe_ste
     if (rc) break;
   }
   ctx->timing = old_timing;
+  ctx->use_graph = old_graph;
   ctx->last_nodes = nullptr;
   int rc2 = apply_tiling(ctx, rc || !tried ? old_lt : best_lt, rc || !tried ? old_h : halo,
                          rc || !tried ? old_c : best_c, old_s);
