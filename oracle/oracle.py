@@ -286,3 +286,16 @@ def crater_objective(grid, pot, dt, nsteps, cell, off, v_thermal, xi, sigma_ref,
     vh = start_leapfrog(grid, pot, dt, cell, off, v0, wq, quantized)
     c, o, _, _ = run(grid, pot, dt, cell, off, vh, wq, nsteps, quantized=quantized)
     return functional(grid, c, o, wq, y_s, tau)
+
+
+def forces_from_nodes(grid, pot, node_sums, cell, off, quantized: bool = True):
+    """Per-atom force [ndim, N] (newtons) of the given particles from node sums
+    of the whole grid (int64 weight units, e.g. the deposit of every
+    particle), not only of the particles passed."""
+    node = np.ascontiguousarray(node_sums, dtype=np.float64)
+    cell, off, _ = _state(cell, off, np.zeros(len(cell), np.int32))
+    F = np.zeros((grid.ndim, cell.shape[0]), dtype=np.float64)
+    lib().orc_forces(C.byref(grid_struct(grid, quantized)), C.byref(pot_struct(pot)),
+                     _ptr(node, C.c_double), cell.shape[0], _ptr(cell, C.c_int32),
+                     _ptr(off, C.c_double), _ptr(F, C.c_double))
+    return F

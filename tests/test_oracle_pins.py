@@ -489,6 +489,18 @@ def test_functional_limits():
     assert J == pytest.approx(1 / (1 + math.exp(18)) + 0.5 + 1 / (1 + math.exp(-18)), rel=1e-12)
 
 
+def test_forces_from_full_node_sums_equal_forces_of_the_whole_state():
+    """The sampled-particle force helper (used for full-size parity) is the
+    same computation as the whole-state force, restricted to a subset."""
+    wl = W.cfg_small_slab()
+    g, p = wl.grid, wl.parts
+    node = O.deposit(g, p.cell, p.off.astype(np.float64), p.wq)
+    F_all = O.forces(g, POT, p.cell, p.off.astype(np.float64), p.wq)
+    s = np.arange(0, p.n, 37)
+    F_s = O.forces_from_nodes(g, POT, node, p.cell[s], p.off[:, s].astype(np.float64))
+    assert np.array_equal(F_s, F_all[:, s])
+
+
 # ---------------------------------------------------------------- energy (P14, the paper's claim)
 @pytest.mark.slow
 def test_energy_drift_bound_on_a_hot_quiet_lattice():
