@@ -8,7 +8,10 @@ its reverse runs in the library's kernels):
   Trajectory  off(0), v(-1/2), theta -> off(T), v(T - 1/2) over nsteps
               cycles (pic_forward_record, checkpoints every `every` steps);
               backward by pic_backward_record, which recomputes each segment
-              between checkpoints and sweeps it in reverse.
+              between checkpoints and sweeps it in reverse.  Grids too small
+              for tiles take the same checkpointed scheme through the
+              per-step calls (pic_deposit / pic_force / pic_push forward,
+              pic_adjoint_step backward).
 
 theta is a float64 tensor (D, r0, s_rep, c_att) holding the context's
 potential; it is there to receive dJ/dtheta.  Cell indices are integer
@@ -61,24 +64,52 @@ class Force(torch.autograd.Function):
         return lam_x, dth.to(fctx.theta_dev), None, None, None
 
 
+def _step_untiled(ctx: B.Context, dp):
+    node = ctx.pic_deposit(dp)
+    F = ctx.pic_force(dp, node)
+    ctx.pic_push(dp, F)
+
+
 class Trajectory(torch.autograd.Function):
     @staticmethod
     def forward(fctx, off0, vel0, theta, ctx: B.Context, cell0, wq, nsteps: int, every: int):
         _check_theta(ctx, theta)
         dp = B.DeviceParticles(cell0.clone(), off0.detach().contiguous().clone(),
                                vel0.detach().contiguous().clone(), wq)
-        rec = ctx.pic_forward_record(dp, nsteps, every)
-        fctx.pic = (ctx, dp, rec)
+        if B.lib.pic_record_bytes(ctx.ctx, int(nsteps), int(every)):
+            rec = ctx.pic_forward_record(dp, nsteps, every)
+        else:  # untiled context: checkpoints in the caller's order
+            rec = []
+            for s in range(nsteps):
+                if s % every == 0:
+                    rec.append(dp.clone())
+                _step_untiled(ctx, dp)
+        fctx.pic = (ctx, dp, rec, int(nsteps), int(every))
         fctx.theta_dev = theta.device
         fctx.mark_non_differentiable(dp.cell)
         return dp.off, dp.vel, dp.cell
 
     @staticmethod
     def backward(fctx, g_off, g_vel, _g_cell):
-        ctx, dp, rec = fctx.pic
+        ctx, dp, rec, nsteps, every = fctx.pic
         lam_x = torch.zeros_like(dp.off) if g_off is None else g_off.contiguous().float().clone()
         lam_v = torch.zeros_like(dp.vel) if g_vel is None else g_vel.contiguous().float().clone()
-        dth = ctx.pic_backward_record(dp, rec, lam_x, lam_v)
+        if isinstance(rec, dict):
+            dth = ctx.pic_backward_record(dp, rec, lam_x, lam_v)
+        else:
+            dth = torch.zeros(4, dtype=torch.float64, device=dp.off.device)
+            nbar_next = None
+            for j in range(len(rec) - 1, -1, -1):
+                s0 = j * every
+                states = [rec[j].clone()]
+                for _ in range(min(every, nsteps - s0) - 1):
+                    nxt = states[-1].clone()
+                    _step_untiled(ctx, nxt)
+                    states.append(nxt)
+                for st in reversed(states):
+                    node = ctx.pic_deposit(st)
+                    nbar_next, _ = ctx.pic_adjoint_step(st, node, nbar_next, lam_x, lam_v, dtheta=dth)
+            ctx.pic_deposit_vjp(rec[0], nbar_next, lam_x)
         return lam_x, lam_v, dth.to(fctx.theta_dev), None, None, None, None, None
 
 

@@ -171,3 +171,38 @@ def test_autograd_crater_gradient_matches_oracle_finite_differences(B):
             print(f"[{name}] dJ/d{k}: autograd {got[k]:.9e} finite difference {fd:.9e} "
                   f"rel {abs(got[k] - fd) / abs(fd):.2e}")
             assert abs(got[k] - fd) <= 1e-4 * abs(fd) + fd_err, (k, got[k], fd)
+
+
+def test_autograd_on_a_grid_too_small_for_tiles(B):
+    """A 6^3 grid has no 3D tiling: the Trajectory Function takes the
+    checkpointed per-step chain; its gradient matches the differentiable FP64
+    reference (oracle/autograd_ref.py)."""
+    from oracle import autograd_ref as R
+    from paper_1502_07722_amd import autograd as A
+    wl = W.cfg_adjoint_3d(n=6, layers=3)
+    g, p = wl.grid, wl.parts
+    nsteps, y_s, tau, fref = 12, wl.slab_rows * g.h[2], g.h[2], wl.fluence
+    dev = torch.device("cuda")
+    # r0 on the unaltered potential: with c_att != s_rep its derivative jumps
+    # where a neighbour distance crosses r0, which solid-density particles do
+    for c_att, keys in ((0.27, ("D", "s_rep", "c_att")), (1.0, ("r0",))):
+        pot = W.Potential(c_att=c_att)
+        ctx = B.Context(g, pot, wl.dt, p.n)
+        assert B.lib.pic_record_bytes(ctx.ctx, nsteps, 5) == 0  # untiled
+        theta = A.theta_of(pot).requires_grad_(True)
+        fl = torch.tensor(fref, dtype=torch.float64, device=dev, requires_grad=True)
+        J, _, _ = A.crater_objective(ctx, torch.from_numpy(p.cell).to(dev), torch.from_numpy(p.off).to(dev),
+                                     torch.from_numpy(p.v_thermal).to(dev), torch.from_numpy(p.xi).to(dev),
+                                     torch.from_numpy(p.sigma.astype(np.float32)).to(dev), fref, fl,
+                                     torch.from_numpy(p.wq).to(dev), theta, nsteps, 5, y_s, tau)
+        J.backward()
+        Jr, th, flr, _, _ = R.crater_objective(g, pot, wl.dt, nsteps, p.cell, p.off, p.v_thermal, p.xi, p.sigma,
+                                               fref, p.wq, y_s, tau)
+        Jr.backward()
+        assert abs(J.item() - Jr.item()) <= 1e-5 * abs(Jr.item())
+        for k in keys:
+            i = A.THETA_KEYS.index(k)
+            ref = th[k].grad.item()
+            assert abs(theta.grad[i].item() - ref) <= 1e-3 * abs(ref), (k, theta.grad[i].item(), ref)
+        if c_att != 1.0:
+            assert abs(fl.grad.item() - flr.grad.item()) <= 1e-3 * abs(flr.grad.item())
