@@ -179,15 +179,21 @@ def run_adjoint(log_fn=log, every=20, steps=None):
     xi = torch.from_numpy(p.xi).to(dev)
     sig = torch.from_numpy(p.sigma.astype(np.float32)).to(dev)
     wq = torch.from_numpy(p.wq).to(dev)
-    ctx = B.Context(g, pot, wl.dt, p.n, device=dev)
+    # both the forward and the gradient run on a created stream (the forward
+    # replays plain steps as HIP graphs there) with autotuned tiles
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
+    ctx = B.Context(g, pot, wl.dt, p.n, device=dev, stream=stream)
     y_s = wl.slab_rows * g.h[2]
     tau = g.h[2]
     fref = wl.fluence
     # plain forward: the same start state, pic_step over nsteps
     dp = B.DeviceParticles(cell.clone(), off0.clone(), (vth + sig[None, :] * xi).contiguous(), wq)
     ctx.start_leapfrog(dp)
+    tuning = ctx.pic_autotune(dp, 6)
+    log_fn(f"adjoint workload: autotuned tiling {tuning}")
     warm = dp.clone()
-    ctx.pic_step(warm, 20)
+    ctx.pic_step(warm, nsteps)  # the same run once untimed: every graph captured
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.pic_step(dp, nsteps)
@@ -214,12 +220,14 @@ def run_adjoint(log_fn=log, every=20, steps=None):
            f"backward {t_bwd * 1e3:.1f} ms")
     step_bytes = 60 * p.n + 16 * B.pic_num_nodes(g)  # 3D algorithmic bytes per step
     fwd_gbs = step_bytes * nsteps / t_fwd / 1e9
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(torch.cuda.default_stream(dev))
     del ctx
     torch.cuda.empty_cache()
     return {"workload": f"{wl.name}: 128^3 cells, slab 64 layers, 8 ppc, 1.5 J/cm^2, {nsteps} steps, "
                         f"checkpoint every {every}",
             "particles": int(p.n), "steps": nsteps, "checkpoint_every": every,
-            "forward_s": t_fwd, "recorded_forward_s": t_rec, "backward_s": t_bwd,
+            "tiling": tuning, "forward_s": t_fwd, "recorded_forward_s": t_rec, "backward_s": t_bwd,
             "adjoint_over_forward": t_bwd / t_fwd, "gradient_over_forward": (t_rec + t_bwd) / t_fwd,
             "forward_particle_steps_per_s": p.n * nsteps / t_fwd,
             "forward_roofline": {"achieved_gbs": fwd_gbs, "frac": fwd_gbs / HBM_PEAK_GBS,

@@ -77,7 +77,7 @@ static int64_t node_at(const orc_grid *g, const int a[3]) {
 
 /* Volume a node represents: cell volume, halved for each reflecting wall the
  * node lies on.  2D: the grid stands for a slab of thickness depth2d (the
- * paper's 2D targets are "effectively infinitely long" in the third axis). */
+ * paper treats its 2D targets as unbounded along the third axis). */
 static double node_volume(const orc_grid *g, int64_t k) {
   double V = g->h[0] * g->h[1] * (g->ndim == 3 ? g->h[2] : g->depth2d);
   for (int d = 0; d < g->ndim; ++d) {
@@ -90,8 +90,8 @@ static double node_volume(const orc_grid *g, int64_t k) {
 }
 
 /* ------------------------------------------------------------------------- */
-/* Deposit: "interpolating the weight (ie. number of actual particles        */
-/* represented) of each macroparticle to the nearest surrounding nodes".     */
+/* Deposit (method section, Fig. 1A): each macroparticle's weight -- the     */
+/* number of atoms it stands for -- is shared among the nodes around it.     */
 /* Reading: linear (cloud-in-cell) weights, 2^d nodes.  Quantized mode is the */
 /* fixed-point rule: 16-bit offsets u = floor(f * 2^16), and the weight is    */
 /* split axis by axis, upper part = floor(part * u / 2^16), lower = the rest, */
@@ -157,8 +157,9 @@ void orc_density(const orc_grid *g, const double *node_f, double *dens) {
 }
 
 /* ------------------------------------------------------------------------- */
-/* "The density at the nodes is then used to calculate a density gradient at */
-/* the half-node (cell-centered) positions."  Reading: component d at a cell  */
+/* Gradient (method section): from the node densities the method forms a    */
+/* density gradient at the cell centres, half a node spacing from the nodes. */
+/* Reading: component d at a cell                                             */
 /* centre is the mean of the node differences along the cell's 2^(d-1) edges  */
 /* parallel to d, divided by the cell edge.                                   */
 /* ------------------------------------------------------------------------- */
@@ -207,8 +208,8 @@ static double centre_gradient(const orc_grid *g, const double *G, int d, const i
 }
 
 /* ------------------------------------------------------------------------- */
-/* "This node density and density gradient is interpolated in a self-        */
-/* consistent fashion back to the macroparticles."  Reading: the same linear  */
+/* Gather (method section): density and gradient go back to each           */
+/* macroparticle with the same shape that deposited it.  Reading: the linear */
 /* shape as the deposit -- node density from the cell's 2^d corner nodes, the */
 /* gradient from the 2^d nearest cell centres.                                */
 /* ------------------------------------------------------------------------- */
@@ -464,9 +465,9 @@ int orc_run(const orc_grid *g, const orc_pot *p, double dt, int64_t np, int32_t 
 }
 
 /* ------------------------------------------------------------------------- */
-/* Attractive correction ("a multiplicative correction factor for the force   */
-/* is calculated by integrating over the force applied to a single atom       */
-/* leaving the target, traveling out to infinity").  Reading: build a flat    */
+/* Attractive correction (method section, after eq. 3): a factor on the     */
+/* attractive force, set from the work the force does on one atom that      */
+/* leaves the target and goes to infinity.  Reading: build a flat            */
 /* slab of solid density as a commensurate lattice (lattice_k^d particles per */
 /* cell) on a grid of the given cell size, move a zero-weight test atom along */
 /* the surface normal with unit attractive multiplier, take W = -integral of  */
