@@ -353,6 +353,70 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
                         const void *record, size_t record_bytes, void *scratch, size_t scratch_bytes, float *lam_x,
                         float *lam_v, double *dtheta);
 
+/* ---------------------------------------------------------------------------
+ * Crater measurement (results section, Figs. 3-4 and eq. (5)).  The paper
+ * shows densities in units of the solid density with nothing below 1 % of
+ * it (the thin gas there leaves the crater unchanged), measures the crater's
+ * width and depth once the surface has settled, and converts width and beam
+ * diameter into a threshold fluence by eq. (5): F_th = F exp(-(Gamma/a)^2).
+ * How width and depth are read off the map is this library's reading:
+ *   - a column is the line of nodes along the normal (last) axis that share
+ *     their lateral indices; its equivalent solid thickness t is the weight
+ *     of its nodes at or above the cut-off divided by n_solid times the
+ *     column's cross-section (the thickness its atoms would have at solid
+ *     density);
+ *   - depth = the largest deficit y_s - t, y_s the initial surface height;
+ *   - columns with deficit >= depth_min are cratered; the crater diameter
+ *     Gamma is their total lateral length (2D) or the diameter of the circle
+ *     of their total lateral area (3D); a column on a reflecting lateral wall
+ *     counts half (a quarter on two);
+ *   - eq. (5) with a the beam diameter at which the fluence falls to 1/e of
+ *     its peak (sqrt(2) R for a Gaussian of 1/e^2 radius R).
+ * ------------------------------------------------------------------------- */
+typedef struct pic_crater_spec {
+  double n_solid;    /* solid number density, m^-3: the density unit (> 0) */
+  double cut;        /* nodes below cut * n_solid count as empty (>= 0; the paper's figures: 0.01) */
+  double depth_min;  /* a column is cratered when its deficit is at least this, m (> 0) */
+} pic_crater_spec_t;
+
+typedef struct pic_crater {
+  double depth;      /* largest deficit y_s - t over the slab's columns, m */
+  double width;      /* crater diameter Gamma, m */
+  double t_min;      /* thinnest column's equivalent solid thickness, m */
+  double t_max;      /* thickest column's, m */
+  double f_th;       /* eq. (5) threshold fluence, J/m^2; 0 without fluence and beam diameter */
+  int64_t ncols;     /* cratered columns */
+} pic_crater_t;
+
+/* Columns of one grid: the product of the lateral axes' node counts. */
+int64_t pic_num_columns(const pic_grid_t *grid);
+
+/* Measure every slab of the context on node sums node_w (device, int64, all
+ * slabs' nodes one after another as pic_deposit / pic_step_nodes lay them
+ * out).  Host arrays, one entry per slab: y_s (initial surface height along
+ * the normal axis, m), fluence (peak absorbed fluence, J/m^2) and beam_d
+ * (beam diameter, m), the last two NULL when eq. (5) is not wanted.
+ * Device outputs, caller-owned: col_w [sum of pic_num_columns] receives
+ * each column's kept weight (int64, weight units; overwritten), rho
+ * [nodes] (may be NULL) the density map in units of n_solid with zeros
+ * below the cut-off (float, rounded from FP64), out [nslab] the results.
+ * Node densities and the cut-off decision are FP64; column sums are exact.
+ * Stream-ordered and asynchronous; PIC_EINVAL for NULL or invalid
+ * arguments.  The kernels read node_w once: a call costs about 8 bytes per
+ * node (12 with rho) plus 16 per column. */
+int pic_crater(pic_ctx_t *ctx, const int64_t *node_w, const pic_crater_spec_t *spec, const double *y_s,
+               const double *fluence, const double *beam_d, float *rho, int64_t *col_w, pic_crater_t *out);
+
+/* Threshold fluence over a sweep of n fluences with measured crater
+ * diameters (host arrays; slabs with width <= 0 are left out):
+ * f_th_fixed = geometric mean of the per-slab eq. (5) values at beam
+ * diameter beam_d (the least-squares ln F_th with a held fixed);
+ * f_th_fit and beam_d_fit from the least-squares line Gamma^2 = a^2 ln F -
+ * a^2 ln F_th.  Outputs are NaN when fewer than one (fixed) or two distinct
+ * fluences (fit) remain, or the fitted slope is not positive.  Host only. */
+int pic_threshold_fit(int32_t n, const double *fluence, const double *width, double beam_d, double *f_th_fixed,
+                      double *f_th_fit, double *beam_d_fit);
+
 #ifdef __cplusplus
 }
 #endif

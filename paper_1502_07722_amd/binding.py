@@ -54,6 +54,17 @@ class pic_timing_t(C.Structure):
     _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8), ("drifters_last", C.c_int64),
                 ("items_last", C.c_int64)]
 
+class pic_crater_spec_t(C.Structure):
+    _fields_ = [("n_solid", C.c_double), ("cut", C.c_double), ("depth_min", C.c_double)]
+
+
+class pic_crater_t(C.Structure):
+    _fields_ = [("depth", C.c_double), ("width", C.c_double), ("t_min", C.c_double), ("t_max", C.c_double),
+                ("f_th", C.c_double), ("ncols", C.c_int64)]
+
+
+CRATER_FIELDS = ("depth", "width", "t_min", "t_max", "f_th", "ncols")
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())")
 
@@ -99,6 +110,12 @@ lib.pic_backward_record.argtypes = [_vp, _P(pic_particles_t), C.c_int32, C.c_int
                                     C.c_size_t, _vp, _vp, _vp]
 lib.pic_calibrate_catt.argtypes = [_P(pic_grid_t), _P(pic_potential_t), C.c_double, C.c_int32, _P(C.c_double),
                                    _P(C.c_double)]
+lib.pic_num_columns.restype = C.c_int64
+lib.pic_num_columns.argtypes = [_P(pic_grid_t)]
+lib.pic_crater.argtypes = [_vp, _vp, _P(pic_crater_spec_t), _P(C.c_double), _P(C.c_double), _P(C.c_double), _vp,
+                           _vp, _vp]
+lib.pic_threshold_fit.argtypes = [C.c_int32, _P(C.c_double), _P(C.c_double), C.c_double, _P(C.c_double),
+                                  _P(C.c_double), _P(C.c_double)]
 
 
 class PicError(RuntimeError):
@@ -175,8 +192,27 @@ def pic_calibrate_catt(grid: W.Grid, pot: W.Potential, n_solid: float, slab_laye
     return c.value, w.value
 
 
+def pic_num_columns(grid: W.Grid) -> int:
+    return int(lib.pic_num_columns(C.byref(grid_t(grid))))
+
+
+def pic_threshold_fit(fluences, widths, beam_d: float):
+    """(fixed-diameter estimate, fitted estimate, fitted diameter) of the
+    threshold fluence over a sweep (NaN where undetermined)."""
+    n = len(fluences)
+    F = (C.c_double * max(n, 1))(*[float(x) for x in fluences])
+    G = (C.c_double * max(n, 1))(*[float(x) for x in widths])
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    rc = lib.pic_threshold_fit(n, F, G, float(beam_d), C.byref(a), C.byref(b), C.byref(c))
+    if rc:
+        raise PicError(rc, "pic_threshold_fit failed")
+    return a.value, b.value, c.value
+
+
 class Context:
     """One pic_ctx_t with its workspace tensor, bound to a torch stream."""
+
+    nslab = 1
 
     def __init__(self, grid: W.Grid, pot: W.Potential, dt: float, max_n: int, device="cuda", stream=None):
         self.grid, self.pot, self.dt, self.max_n = grid, pot, dt, int(max_n)
@@ -289,6 +325,61 @@ class Context:
         self._need(node_w, self.nnodes, torch.int64, "node_w")
         self._check(lib.pic_step_nodes(self.ctx, _ptr(node_w)), "pic_step_nodes")
         return node_w
+
+    def _grids(self):
+        return getattr(self, "grids", None) or [self.grid]
+
+    def crater_buffers(self, want_rho: bool = False):
+        """Device outputs of pic_crater: (col_w, rho or None, out)."""
+        ncols = sum(pic_num_columns(g) for g in self._grids())
+        col_w = torch.empty(ncols, dtype=torch.int64, device=self.device)
+        rho = torch.empty(self.nnodes, dtype=torch.float32, device=self.device) if want_rho else None
+        out = torch.empty(self.nslab * C.sizeof(pic_crater_t), dtype=torch.uint8, device=self.device)
+        return col_w, rho, out
+
+    def pic_crater_launch(self, node_w, n_solid: float, y_s, cut: float = 0.01, depth_min=None, fluence=None,
+                          beam_d=None, bufs=None):
+        """Enqueue pic_crater (asynchronous); returns the device buffers
+        (col_w, rho, out).  Per-slab arguments are sequences of nslab values
+        (a scalar is taken for every slab); depth_min defaults to one cell
+        along the normal axis."""
+        grids = self._grids()
+        k = self.nslab
+
+        def per_slab(v):
+            v = list(v) if hasattr(v, "__len__") else [v] * k
+            if len(v) != k:
+                raise ValueError("one value per slab")
+            return (C.c_double * k)(*[float(x) for x in v])
+
+        if depth_min is None:
+            depth_min = grids[0].h[grids[0].ndim - 1]
+        col_w, rho, out = bufs if bufs is not None else self.crater_buffers()
+        self._need(node_w, self.nnodes, torch.int64, "node_w")
+        self._need(col_w, sum(pic_num_columns(g) for g in grids), torch.int64, "col_w")
+        if rho is not None:
+            self._need(rho, self.nnodes, torch.float32, "rho")
+        self._need(out, k * C.sizeof(pic_crater_t), torch.uint8, "out")
+        spec = pic_crater_spec_t(float(n_solid), float(cut), float(depth_min))
+        F = per_slab(fluence) if fluence is not None else None
+        A = per_slab(beam_d) if beam_d is not None else None
+        self._check(lib.pic_crater(self.ctx, _ptr(node_w), C.byref(spec), per_slab(y_s), F, A, _ptr(rho),
+                                   _ptr(col_w), _ptr(out)), "pic_crater")
+        return col_w, rho, out
+
+    def crater_results(self, out):
+        """Unpack pic_crater's device results (waits for the bound stream)."""
+        self.stream.synchronize()
+        raw = bytes(out.cpu().numpy().tobytes())
+        recs = (pic_crater_t * self.nslab).from_buffer_copy(raw[: self.nslab * C.sizeof(pic_crater_t)])
+        return [{f: getattr(r, f) for f in CRATER_FIELDS} for r in recs]
+
+    def pic_crater(self, node_w, n_solid: float, y_s, cut: float = 0.01, depth_min=None, fluence=None,
+                   beam_d=None, want_rho: bool = False):
+        """Crater measurement of every slab: (per-slab result dicts, col_w, rho)."""
+        bufs = self.crater_buffers(want_rho)
+        col_w, rho, out = self.pic_crater_launch(node_w, n_solid, y_s, cut, depth_min, fluence, beam_d, bufs)
+        return self.crater_results(out), col_w, rho
 
     def pic_set_timing(self, on: bool):
         self._check(lib.pic_set_timing(self.ctx, 1 if on else 0), "pic_set_timing")

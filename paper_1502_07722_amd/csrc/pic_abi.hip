@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "pic_crater.h"
 #include "pic_internal.h"
 
 using namespace pic;
@@ -1384,6 +1385,111 @@ int pic_step_nodes(pic_ctx_t *ctx, int64_t *node_w) {
   return hip_check(ctx, hipMemcpyAsync(node_w, ctx->last_nodes, sizeof(long long) * (size_t)ctx->nnodes,
                                        hipMemcpyDeviceToDevice, ctx->stream),
                    "copy node sums");
+}
+
+int64_t pic_num_columns(const pic_grid_t *grid) {
+  Sizes s;
+  if (!grid_sizes(grid, &s, nullptr)) return 0;
+  int64_t c = 1;
+  for (int d = 0; d < grid->ndim - 1; ++d) c *= grid->n[d] + grid->bc[d];
+  return c;
+}
+
+int pic_crater(pic_ctx_t *ctx, const int64_t *node_w, const pic_crater_spec_t *spec, const double *y_s,
+               const double *fluence, const double *beam_d, float *rho, int64_t *col_w, pic_crater_t *out) {
+  if (!ctx) return PIC_EINVAL;
+  if (!node_w || !spec || !y_s || !col_w || !out) return fail(ctx, PIC_EINVAL, "pic_crater: NULL argument");
+  if (!(spec->n_solid > 0) || !std::isfinite(spec->n_solid) || !(spec->cut >= 0) || !std::isfinite(spec->cut) ||
+      !(spec->depth_min > 0) || !std::isfinite(spec->depth_min))
+    return fail(ctx, PIC_EINVAL, "pic_crater: n_solid and depth_min must be > 0, cut >= 0");
+  if ((fluence == nullptr) != (beam_d == nullptr))
+    return fail(ctx, PIC_EINVAL, "pic_crater: fluence and beam_d go together");
+  std::vector<CraterSlab> tab(ctx->nslab);
+  long long node_off = 0, col_off = 0;
+  for (int k = 0; k < ctx->nslab; ++k) {
+    const pic_grid_t &g = ctx->grids[k];  // normalised: h[2] is the 2D depth
+    CraterSlab &c = tab[k];
+    c = CraterSlab{};
+    c.ndim = g.ndim;
+    for (int d = 0; d < 3; ++d) {
+      c.nn[d] = d < g.ndim ? g.n[d] + g.bc[d] : 1;
+      c.bc[d] = d < g.ndim ? g.bc[d] : 0;
+    }
+    c.rows = c.nn[g.ndim - 1];
+    c.ncols = (int)(ctx->sizes[k].nnodes / c.rows);
+    c.node_off = node_off;
+    c.col_off = col_off;
+    c.V = g.h[0] * g.h[1] * g.h[2];
+    c.area = g.ndim == 2 ? g.h[0] * g.h[2] : g.h[0] * g.h[1];
+    c.lat = g.ndim == 2 ? g.h[0] : g.h[0] * g.h[1];
+    if (!std::isfinite(y_s[k])) return fail(ctx, PIC_EINVAL, "pic_crater: y_s must be finite");
+    c.y_s = y_s[k];
+    c.fluence = fluence ? fluence[k] : 0.0;
+    c.beam_d = beam_d ? beam_d[k] : 0.0;
+    if (!(c.fluence >= 0) || !(c.beam_d >= 0) || !std::isfinite(c.fluence) || !std::isfinite(c.beam_d))
+      return fail(ctx, PIC_EINVAL, "pic_crater: fluence and beam_d must be finite and >= 0");
+    node_off += ctx->sizes[k].nnodes;
+    col_off += c.ncols;
+  }
+  const CraterArgs a{spec->n_solid, spec->cut, spec->depth_min};
+  launch_fill64(ctx->stream, reinterpret_cast<long long *>(col_w), col_off);
+  for (int k0 = 0; k0 < ctx->nslab; k0 += kCraterSlabs) {
+    CraterBatch b{};
+    b.n = std::min(kCraterSlabs, ctx->nslab - k0);
+    int max_cols = 0, max_rows = 0;
+    for (int i = 0; i < b.n; ++i) {
+      b.s[i] = tab[k0 + i];
+      max_cols = std::max(max_cols, b.s[i].ncols);
+      max_rows = std::max(max_rows, b.s[i].rows);
+    }
+    launch_crater_columns(ctx->stream, b, max_cols, max_rows, a, reinterpret_cast<const long long *>(node_w), rho,
+                          reinterpret_cast<long long *>(col_w));
+    launch_crater_reduce(ctx->stream, b, a, reinterpret_cast<const long long *>(col_w), out + k0);
+  }
+  return check_launch(ctx, "crater kernels");
+}
+
+int pic_threshold_fit(int32_t n, const double *fluence, const double *width, double beam_d, double *f_th_fixed,
+                      double *f_th_fit, double *beam_d_fit) {
+  if (n < 0 || (n > 0 && (!fluence || !width)) || !f_th_fixed || !f_th_fit || !beam_d_fit) return PIC_EINVAL;
+  const double nan = std::nan("");
+  *f_th_fixed = *f_th_fit = *beam_d_fit = nan;
+  std::vector<double> x, y;
+  for (int i = 0; i < n; ++i) {
+    if (!(width[i] > 0)) continue;
+    if (!(fluence[i] > 0)) return PIC_EINVAL;
+    x.push_back(std::log(fluence[i]));
+    y.push_back(width[i] * width[i]);
+  }
+  const size_t m = x.size();
+  if (m >= 1 && beam_d > 0) {
+    // mean of ln F_th,i = ln F_i - Gamma_i^2 / a^2
+    double s = 0;
+    for (size_t i = 0; i < m; ++i) s += x[i] - y[i] / (beam_d * beam_d);
+    *f_th_fixed = std::exp(s / (double)m);
+  }
+  if (m >= 2) {
+    double xm = 0, ym = 0;
+    for (size_t i = 0; i < m; ++i) {
+      xm += x[i];
+      ym += y[i];
+    }
+    xm /= (double)m;
+    ym /= (double)m;
+    double sxx = 0, sxy = 0;
+    for (size_t i = 0; i < m; ++i) {
+      sxx += (x[i] - xm) * (x[i] - xm);
+      sxy += (x[i] - xm) * (y[i] - ym);
+    }
+    if (sxx > 0) {
+      const double slope = sxy / sxx, icpt = ym - slope * xm;
+      if (slope > 0) {
+        *beam_d_fit = std::sqrt(slope);
+        *f_th_fit = std::exp(-icpt / slope);
+      }
+    }
+  }
+  return PIC_OK;
 }
 
 }  // extern "C"

@@ -3,7 +3,9 @@ configuration bench.py times (a created stream with graph replay, autotuned
 tiles), on outputs the FP64 oracle can compute one by one:
 
 * after K fused steps, the node sums of the GPU state (int64, the whole
-  grid) equal the oracle's fixed-point deposit of that state bit for bit;
+  grid) equal the oracle's fixed-point deposit of that state bit for bit,
+  and the crater measurement on them (density map, column sums, depth,
+  width, eq. (5)) matches the oracle's (rules in tests/crater_check.py);
 * one more GPU step, for 20,000 sampled particles, matches the oracle's
   eq. (1)-(3) force from those full node sums followed by its leapfrog push
   (FP64): positions to 1e-5 cells, velocities to 1e-5 of the largest speed;
@@ -15,8 +17,11 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import crater as CR
 from oracle import oracle as O
 from paper_1502_07722_amd import workloads as W
+
+from crater_check import check_slab
 
 pytestmark = pytest.mark.gpu
 
@@ -50,13 +55,20 @@ def test_full_size_nodes_and_sampled_step_match_oracle(B, name):
         ctx.start_leapfrog(dp)
         ctx.pic_autotune(dp, 6)
         ctx.pic_step(dp, 20)
-        nodes = ctx.pic_step_nodes().cpu().numpy()
+        nodes_dev = ctx.pic_step_nodes()
+        nodes = nodes_dev.cpu().numpy()
         cell, off, vel, wq = dp.to_host()
+        y_s = wl.slab_rows * g.h[g.ndim - 1]
+        beam_d = CR.beam_diameter(200.0 * g.h[0])
+        res, col_w, rho = ctx.pic_crater(nodes_dev, W.N_SOLID, y_s, 0.01, 0.5 * g.h[g.ndim - 1], wl.fluence,
+                                         beam_d, want_rho=True)
+        col_w, rho = col_w.cpu().numpy(), rho.cpu().numpy()
         ctx.pic_step(dp, 1)
         cell1, off1, vel1, _ = dp.to_host()
     stream.synchronize()
     ref = O.deposit(g, cell, off.astype(np.float64), wq)
     assert np.array_equal(nodes, ref), "full-grid node sums differ from the oracle's deposit"
+    check_slab(g, ref, res[0], col_w, rho, W.N_SOLID, y_s, 0.01, 0.5 * g.h[g.ndim - 1], wl.fluence, beam_d)
     rng = np.random.default_rng(12)
     s = rng.choice(p.n, 20000, replace=False)
     F = O.forces_from_nodes(g, pot, ref, cell[s], off[:, s].astype(np.float64))
