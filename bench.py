@@ -51,6 +51,11 @@ def measured_traffic(workload):
     return rec["traffic_bytes_per_launch"]
 
 
+def _finite(x):
+    """JSON has no NaN: undetermined figures are reported as null."""
+    return x if x == x and abs(x) != float("inf") else None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -141,6 +146,12 @@ def run_sweep(steps, warmup, log_fn=log):
         bctx.pic_step_batch(batch, steps)
         stream.synchronize()
         t_batch = time.perf_counter() - t0
+        # crater of every slab at the end of the run and the threshold over the sweep
+        ys = [w.slab_rows * w.grid.h[1] for w in wls]
+        Fs = [w.fluence for w in wls]
+        a = 2.0 ** 0.5 * 200.0 * W.H_CELL
+        cr, _, _ = bctx.pic_crater(bctx.pic_step_nodes(), W.N_SOLID, ys, 0.01, 0.5 * W.H_CELL, Fs, [a] * len(wls))
+        fixed, fit, a_fit = B.pic_threshold_fit(Fs, [r["width"] for r in cr], a)
     log_fn(f"batched: {steps} steps in {t_batch:.3f} s")
     same = all(torch.equal(a.cell, b.cell) and torch.equal(a.off, b.off) and torch.equal(a.vel, b.vel)
                for a, b in zip(plain, batch))
@@ -150,7 +161,12 @@ def run_sweep(steps, warmup, log_fn=log):
             "plain_particle_steps_per_s": N * steps / t_plain,
             "batched_particle_steps_per_s": N * steps / t_batch,
             "speedup": t_plain / t_batch, "bit_identical": bool(same), "tuning": tuning,
-            "slab_particles": [w.parts.n for w in wls]}
+            "slab_particles": [w.parts.n for w in wls],
+            "crater_end_of_run": {"note": f"after {steps} fs the surface has not settled: the measurement path, "
+                                          "not a threshold claim",
+                                  "width_m": [r["width"] for r in cr], "depth_m": [r["depth"] for r in cr],
+                                  "f_th_fixed_Jm2": _finite(fixed), "f_th_fit_Jm2": _finite(fit),
+                                  "beam_d_fit_m": _finite(a_fit)}}
 
 
 def run_adjoint(log_fn=log, every=20, steps=None):
@@ -235,6 +251,48 @@ def run_adjoint(log_fn=log, every=20, steps=None):
             "J": J, "dJ_dtheta": {k: float(v) for k, v in zip(A.THETA_KEYS, gth)}, "dJ_dfluence": gF}
 
 
+def measure_crater(ctx, wl, stream, log_fn=log, calls=20):
+    """Crater measurement (density map with the 1 % cut-off, column sums,
+    depth, width, eq. 5) on the node sums of the last pic_step, timed with
+    HIP events on the context's stream over back-to-back calls."""
+    import torch
+    from paper_1502_07722_amd import binding as B
+    from paper_1502_07722_amd import workloads as W
+
+    g = wl.grid
+    ax = g.ndim - 1
+    nodes = ctx.pic_step_nodes()
+    bufs = ctx.crater_buffers(want_rho=True)
+    y_s = wl.slab_rows * g.h[ax]
+    beam_d = 2.0 ** 0.5 * 200.0 * g.h[0]  # 1/e diameter of the heating profile (1/e^2 radius 200 cells)
+    args = (nodes, W.N_SOLID, y_s, 0.01, 0.5 * g.h[ax], wl.fluence or None, beam_d if wl.fluence else None, bufs)
+    for _ in range(3):
+        ctx.pic_crater_launch(*args)
+    # the calls are captured into one graph so that host-side argument
+    # marshalling does not leave the GPU idle between them
+    graph = torch.cuda.CUDAGraph()
+    stream.synchronize()
+    with torch.cuda.graph(graph, stream=stream):
+        for _ in range(calls):
+            ctx.pic_crater_launch(*args)
+    graph.replay()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    graph.replay()
+    b.record(stream)
+    b.synchronize()
+    us = a.elapsed_time(b) / calls * 1e3
+    ctx.pic_crater_launch(*args)  # eager call: the results below come from it
+    res = ctx.crater_results(bufs[2])[0]
+    nn, nc = B.pic_num_nodes(g), B.pic_num_columns(g)
+    nbytes = 12 * nn + 24 * nc  # node sums read, float map written; column sums cleared, added, read
+    gbs = nbytes / (us * 1e-6) / 1e9
+    log_fn(f"crater: {us:.1f} us per call, {gbs:.0f} GB/s; {res}")
+    return {"result": res, "us_per_call": us, "bytes_per_call": nbytes, "achieved_gbs": gbs,
+            "frac": gbs / HBM_PEAK_GBS, "basis": "12 B per node + 24 B per column; clear + column pass + reduction",
+            "y_s": y_s, "beam_d": beam_d}
+
+
 def run_slab(name, steps, warmup, log_fn=log):
     """One single-slab workload through pic_step: (result, workload, potential,
     diagnostics).  The timed region is one pic_step call of `steps` steps
@@ -280,6 +338,7 @@ def run_slab(name, steps, warmup, log_fn=log):
         elapsed_events = time.perf_counter() - t1
         timing = ctx.pic_get_timing()
         ctx.pic_set_timing(False)
+        crater = measure_crater(ctx, wl, stream, log_fn)
     log_fn(f"{steps} steps in {elapsed:.3f} s (with per-launch events {elapsed_events:.3f} s); phases {timing}")
     nd = wl.grid.ndim
     bytes_per_particle = 4 + 4 * nd + 12 + 4 + 4 + 4 * nd + 12
@@ -299,7 +358,7 @@ def run_slab(name, steps, warmup, log_fn=log):
                 "drifters_last_step": timing.get("drifters_last"), "items_last_step": timing.get("items_last")}
     res = {"workload": wl.name, "particles": N, "value": N * steps / elapsed, "ms_per_step": elapsed / steps * 1e3,
            "elapsed_s": elapsed, "roofline": roofline, "c_att": c_att, "tiling": tuning,
-           "ms_per_step_with_events": elapsed_events / steps * 1e3}
+           "ms_per_step_with_events": elapsed_events / steps * 1e3, "crater": crater}
     del ctx, dp, start
     torch.cuda.empty_cache()
     return res, wl, pot, diags

@@ -399,11 +399,14 @@ int64_t pic_num_columns(const pic_grid_t *grid);
  * Device outputs, caller-owned: col_w [sum of pic_num_columns] receives
  * each column's kept weight (int64, weight units; overwritten), rho
  * [nodes] (may be NULL) the density map in units of n_solid with zeros
- * below the cut-off (float, rounded from FP64), out [nslab] the results.
- * Node densities and the cut-off decision are FP64; column sums are exact.
- * Stream-ordered and asynchronous; PIC_EINVAL for NULL or invalid
- * arguments.  The kernels read node_w once: a call costs about 8 bytes per
- * node (12 with rho) plus 16 per column. */
+ * below the cut-off (float: the node sum times a float scale, within 2e-7
+ * of the FP64 density), out [nslab] the results.
+ * The cut-off decision is the FP64 one, (N 2^-20 / V) / n_solid >= cut
+ * with V the node volume; the host turns it into an exact integer bound on
+ * the node sum N.  Column sums are exact.  Stream-ordered and asynchronous;
+ * PIC_EINVAL for NULL or invalid arguments (also a cut whose bound passes
+ * 2^52 weight units).  The kernels read node_w once: a call costs about 8
+ * bytes per node (12 with rho) plus 24 per column. */
 int pic_crater(pic_ctx_t *ctx, const int64_t *node_w, const pic_crater_spec_t *spec, const double *y_s,
                const double *fluence, const double *beam_d, float *rho, int64_t *col_w, pic_crater_t *out);
 

@@ -1387,6 +1387,29 @@ int pic_step_nodes(pic_ctx_t *ctx, int64_t *node_w) {
                    "copy node sums");
 }
 
+}  // extern "C"
+
+namespace {
+
+// Smallest node sum N >= 0 whose FP64 density (N * 2^-20 / V) / n_solid is
+// at least cut, or -1 when it would pass 2^52 (beyond any node sum, and
+// where N is no longer exact in a double).  The density grows with N, so
+// the step from a close estimate to the exact edge is a few units.
+long long cut_threshold(double V, double n_solid, double cut) {
+  auto kept = [&](long long N) { return ((double)N * 0x1p-20 / V) / n_solid >= cut; };
+  if (kept(0)) return 0;
+  const double est = std::ceil(cut * n_solid * V * 0x1p20);
+  if (!(est < 0x1p52)) return -1;
+  long long N = (long long)est;
+  for (int i = 0; i < 1024 && N > 0 && kept(N - 1); ++i) --N;
+  for (int i = 0; i < 1024 && !kept(N); ++i) ++N;
+  return kept(N) && (N == 0 || !kept(N - 1)) ? N : -1;
+}
+
+}  // namespace
+
+extern "C" {
+
 int64_t pic_num_columns(const pic_grid_t *grid) {
   Sizes s;
   if (!grid_sizes(grid, &s, nullptr)) return 0;
@@ -1419,8 +1442,15 @@ int pic_crater(pic_ctx_t *ctx, const int64_t *node_w, const pic_crater_spec_t *s
     c.ncols = (int)(ctx->sizes[k].nnodes / c.rows);
     c.node_off = node_off;
     c.col_off = col_off;
-    c.V = g.h[0] * g.h[1] * g.h[2];
-    c.area = g.ndim == 2 ? g.h[0] * g.h[2] : g.h[0] * g.h[1];
+    const double V = g.h[0] * g.h[1] * g.h[2];
+    double Vw = V;
+    for (int w = 0; w < 4; ++w, Vw *= 0.5) {
+      c.keep_min[w] = cut_threshold(Vw, spec->n_solid, spec->cut);
+      if (c.keep_min[w] < 0) return fail(ctx, PIC_EINVAL, "pic_crater: cut is too large for int64 node sums");
+      c.map_scale[w] = (float)(0x1p-20 / Vw / spec->n_solid);
+    }
+    const double area = g.ndim == 2 ? g.h[0] * g.h[2] : g.h[0] * g.h[1];
+    c.t_scale = 0x1p-20 / (spec->n_solid * area);
     c.lat = g.ndim == 2 ? g.h[0] : g.h[0] * g.h[1];
     if (!std::isfinite(y_s[k])) return fail(ctx, PIC_EINVAL, "pic_crater: y_s must be finite");
     c.y_s = y_s[k];

@@ -17,16 +17,18 @@ struct CraterSlab {
   int nn[3];           // nodes per axis, fastest first (nn[ndim - 1] = rows)
   int bc[3];           // 1: reflecting walls on that axis (their nodes have half volume)
   int ndim, ncols, rows, pad;
-  double V;            // node volume away from walls (cell volume), m^3
-  double area;         // column cross-section away from lateral walls, m^2
-  double lat;          // lateral measure of a column away from walls: dx (2D), dx*dy (3D)
+  long long keep_min[4];  // by walls touched (0-3): smallest node sum at or above the cut-off
+  float map_scale[4];     // by walls touched: density map = node sum * this (units of n_solid)
+  double t_scale;         // thickness = column sum * t_scale * 2^(lateral walls), m
+  double lat;             // lateral measure of a column away from walls: dx (2D), dx*dy (3D)
   double y_s;          // initial surface height, m
   double fluence;      // peak absorbed fluence for eq. (5), J/m^2 (0: none)
   double beam_d;       // beam diameter for eq. (5), m (0: none)
 };
 
 constexpr int kCraterSlabs = 16;  // slabs per launch (the table travels as a kernel argument)
-constexpr int kCraterRows = 32;   // node rows per thread in the column pass
+constexpr int kCraterRows = 16;   // node rows per thread in the column pass (a launch-shape sweep's best)
+constexpr int kCraterReduceThreads = 1024;
 
 struct CraterBatch {
   CraterSlab s[kCraterSlabs];

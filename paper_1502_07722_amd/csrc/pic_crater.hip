@@ -10,9 +10,12 @@
 //    the initial surface, the deepest deficit, the cratered columns (deficit
 //    >= depth_min), the crater diameter, and eq. (5).
 //
-// The density of a node is formed in FP64 as (N * 2^-20 / V) / n_solid,
-// V the node volume (halved once per wall the node lies on); the cut-off
-// decision is taken on that value.
+// The cut-off is defined on the FP64 density (N * 2^-20 / V) / n_solid, V
+// the node volume (halved once per wall the node lies on).  That value
+// grows with the integer node sum N, so the host turns the decision into the
+// smallest kept N per wall count and the kernel compares integers: the same
+// decision, with no FP64 division per node.  The float map is N times a
+// float scale (two roundings).
 #include <cmath>
 
 #include "pic_crater.h"
@@ -48,7 +51,7 @@ __global__ void __launch_bounds__(256) k_crater_columns(CraterBatch b, CraterArg
   long long Nv[kCraterRows];
 #pragma unroll
   for (int q = 0; q < kCraterRows; ++q)
-    Nv[q] = r0 + q < r1 ? __builtin_nontemporal_load(src + (long long)s.ncols * (r0 + q)) : 0;
+    Nv[q] = r0 + q < r1 ? src[(long long)s.ncols * (r0 + q)] : 0;
   long long sum = 0;
 #pragma unroll
   for (int q = 0; q < kCraterRows; ++q) {
@@ -56,12 +59,8 @@ __global__ void __launch_bounds__(256) k_crater_columns(CraterBatch b, CraterArg
     if (r >= r1) break;
     const long long N = Nv[q];
     const int walls = lw + ((s.bc[ax] && (r == 0 || r == s.rows - 1)) ? 1 : 0);
-    double V = s.V;
-    for (int w = 0; w < walls; ++w) V *= 0.5;
-    const double dens = (double)N * 0x1p-20 / V;
-    const double rr = dens / a.n_solid;
-    const bool keep = rr >= a.cut;
-    if (rho) rho[s.node_off + col + (long long)s.ncols * r] = keep ? (float)rr : 0.f;
+    const bool keep = N >= s.keep_min[walls];
+    if (rho) rho[s.node_off + col + (long long)s.ncols * r] = keep ? (float)N * s.map_scale[walls] : 0.f;
     if (keep) sum += N;
   }
   if (sum) atomicAdd(col_w + s.col_off + col, (unsigned long long)sum);
@@ -71,7 +70,7 @@ template <typename T, typename Op>
 __device__ inline T block_reduce(T v, T *lds, Op op) {
   lds[threadIdx.x] = v;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = kCraterReduceThreads / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) lds[threadIdx.x] = op(lds[threadIdx.x], lds[threadIdx.x + w]);
     __syncthreads();
   }
@@ -80,19 +79,19 @@ __device__ inline T block_reduce(T v, T *lds, Op op) {
   return r;
 }
 
-// One block of 256 threads per slab of the batch.
-__global__ void __launch_bounds__(256) k_crater_reduce(CraterBatch b, CraterArgs a, const long long *col_w,
-                                                        pic_crater_t *out) {
-  __shared__ double ld[256];
-  __shared__ long long ll[256];
+// One block per slab of the batch.
+__global__ void __launch_bounds__(kCraterReduceThreads) k_crater_reduce(CraterBatch b, CraterArgs a,
+                                                                         const long long *col_w, pic_crater_t *out) {
+  __shared__ double ld[kCraterReduceThreads];
+  __shared__ long long ll[kCraterReduceThreads];
   const CraterSlab &s = b.s[blockIdx.x];
   double tmin = INFINITY, tmax = -INFINITY;
   long long hits = 0, units = 0;  // units: quarter columns (lateral wall columns count half, corners a quarter)
-  for (int c = threadIdx.x; c < s.ncols; c += 256) {
+  const long long *cw = col_w + s.col_off;
+#pragma unroll 4
+  for (int c = threadIdx.x; c < s.ncols; c += kCraterReduceThreads) {
     const int lw = lateral_walls(s, c);
-    double A = s.area;
-    for (int w = 0; w < lw; ++w) A *= 0.5;
-    const double t = (double)col_w[s.col_off + c] * 0x1p-20 / (a.n_solid * A);
+    const double t = (double)cw[c] * s.t_scale * (double)(1 << lw);
     tmin = fmin(tmin, t);
     tmax = fmax(tmax, t);
     if (s.y_s - t >= a.depth_min) {
@@ -135,7 +134,7 @@ void launch_crater_columns(hipStream_t st, const CraterBatch &b, int max_ncols, 
 void launch_crater_reduce(hipStream_t st, const CraterBatch &b, CraterArgs a, const long long *col_w,
                           pic_crater_t *out) {
   if (b.n < 1) return;
-  k_crater_reduce<<<b.n, 256, 0, st>>>(b, a, col_w, out);
+  k_crater_reduce<<<b.n, kCraterReduceThreads, 0, st>>>(b, a, col_w, out);
 }
 
 }  // namespace pic

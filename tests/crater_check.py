@@ -1,8 +1,9 @@
 """Comparison of the library's crater measurement with the FP64 oracle
 (oracle/crater.py), shared by the GPU tests.
 
-* density map: bit-exact (both sides form (N 2^-20 / V) / n_solid in FP64
-  and round it to float32, zero below the cut-off);
+* density map: zero exactly where the oracle's FP64 density is below the
+  cut-off, elsewhere within 2e-7 of it (the library scales the integer
+  node sum in float: three roundings of 2^-24);
 * column sums: bit-exact against the integer sum of the node weights the
   oracle keeps;
 * thickness, depth, t_min, t_max, eq. (5): 1e-12 relative (the oracle sums
@@ -29,8 +30,8 @@ def check_slab(grid, node_sums, got, col_w, rho, n_solid, y_s, cut, depth_min, f
     dens = O.density(grid, node_sums) / n_solid
     keep = dens >= cut
     if rho is not None:
-        want = np.where(keep, dens, 0.0).astype(np.float32)
-        assert np.array_equal(rho.view(np.uint32), want.view(np.uint32)), "density map differs"
+        assert np.array_equal(rho == 0, ~keep | (node_sums == 0)), "density map cut differs"
+        assert np.allclose(rho, np.where(keep, dens, 0.0), rtol=2e-7, atol=0), "density map differs"
     cols = len(ref["thickness"])
     S = np.where(keep, node_sums, 0).reshape(-1, cols).sum(axis=0)
     assert np.array_equal(col_w, S), "column sums differ"
