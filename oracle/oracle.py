@@ -38,7 +38,8 @@ class _Grid(C.Structure):
 
 class _Pot(C.Structure):
     _fields_ = [("D", C.c_double), ("r0", C.c_double), ("s_rep", C.c_double), ("c_att", C.c_double),
-                ("g_clamp", C.c_double), ("n_floor", C.c_double), ("mass", C.c_double)]
+                ("g_clamp", C.c_double), ("n_floor", C.c_double), ("mass", C.c_double), ("kind", C.c_int),
+                ("alpha", C.c_double)]
 
 
 class _Diag(C.Structure):
@@ -71,6 +72,8 @@ def lib():
         _lib.orc_phi.argtypes = [P(_Pot), d]
         _lib.orc_energy_density.restype = d
         _lib.orc_energy_density.argtypes = [P(_Pot), d]
+        _lib.orc_energy_density_quad.restype = d
+        _lib.orc_energy_density_quad.argtypes = [P(_Pot), d]
         _lib.orc_forces.argtypes = [P(_Grid), P(_Pot), P(d), i64, P(i32), P(d), P(d)]
         _lib.orc_push_one.argtypes = [P(_Grid), P(_Pot), d, P(d), P(i32), P(d), P(d)]
         _lib.orc_kick.argtypes = [P(_Grid), P(_Pot), d, d, i64, P(d), P(d)]
@@ -99,7 +102,8 @@ def grid_struct(grid, quantized: bool = True) -> _Grid:
 
 
 def pot_struct(pot) -> _Pot:
-    return _Pot(pot.D, pot.r0, pot.s_rep, pot.c_att, pot.g_clamp, pot.n_floor, pot.mass)
+    return _Pot(pot.D, pot.r0, pot.s_rep, pot.c_att, pot.g_clamp, pot.n_floor, pot.mass,
+                int(getattr(pot, "kind", 0)), float(getattr(pot, "alpha", 0.0)))
 
 
 class OracleError(RuntimeError):
@@ -194,6 +198,11 @@ def phi(pot, r):
 
 def energy_density(pot, n):
     return lib().orc_energy_density(C.byref(pot_struct(pot)), float(n))
+
+
+def energy_density_quad(pot, n):
+    """The energy density by quadrature of mu (any kind of pair potential)."""
+    return lib().orc_energy_density_quad(C.byref(pot_struct(pot)), float(n))
 
 
 def forces(grid, pot, cell, off, wq, quantized: bool = True):

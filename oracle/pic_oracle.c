@@ -255,22 +255,39 @@ void orc_gather(const orc_grid *g, const double *dens, const double *G, int32_t 
 }
 
 /* ------------------------------------------------------------------------- */
-/* Eq. (3): U(r) = D((r0/r)^12 - 2 (r0/r)^6).  The altered potential: the     */
-/* repulsive branch (r < r0) is scaled by s_rep (the paper's infinite wall is */
-/* the s_rep -> infinity limit), the attractive branch (r >= r0) by the       */
-/* correction factor c_att.  U'(r0) = 0, so the force is continuous at r0.    */
+/* Eq. (3): U(r) = D((r0/r)^12 - 2 (r0/r)^6).  The method works with any pair */
+/* potential (the paper names the Morse potential among them); kind 1 is     */
+/* Morse, U(r) = D(e^2 - 2e), e = exp(-a (r - r0)): the same well depth D at  */
+/* the same equilibrium distance r0.  The altered potential: the repulsive   */
+/* branch (r < r0) is scaled by s_rep (the paper's infinite wall is the      */
+/* s_rep -> infinity limit), the attractive branch (r >= r0) by the          */
+/* correction factor c_att.  U'(r0) = 0, so the force is continuous at r0.   */
 /* ------------------------------------------------------------------------- */
 
-double orc_phi_prime(const orc_pot *p, double r) {
+static double base_u(const orc_pot *p, double r) {
+  if (p->kind == 1) {
+    double e = exp(-p->alpha * (r - p->r0));
+    return p->D * (e * e - 2.0 * e);
+  }
   double x = p->r0 / r;
-  double x6 = pow(x, 6.0), x12 = pow(x, 12.0);
-  double du = -(12.0 * p->D / r) * (x12 - x6);
-  return (r < p->r0 ? p->s_rep : p->c_att) * du;
+  return p->D * (pow(x, 12.0) - 2.0 * pow(x, 6.0));
+}
+
+static double base_du(const orc_pot *p, double r) {
+  if (p->kind == 1) {
+    double e = exp(-p->alpha * (r - p->r0));
+    return -2.0 * p->alpha * p->D * (e * e - e);
+  }
+  double x = p->r0 / r;
+  return -(12.0 * p->D / r) * (pow(x, 12.0) - pow(x, 6.0));
+}
+
+double orc_phi_prime(const orc_pot *p, double r) {
+  return (r < p->r0 ? p->s_rep : p->c_att) * base_du(p, r);
 }
 
 double orc_phi(const orc_pot *p, double r) {
-  double x = p->r0 / r;
-  double u = p->D * (pow(x, 12.0) - 2.0 * pow(x, 6.0));
+  double u = base_u(p, r);
   if (r >= p->r0) return p->c_att * u;
   /* continuous at r0: s*U(r) + (s - c)*D */
   return p->s_rep * u + (p->s_rep - p->c_att) * p->D;
@@ -323,7 +340,42 @@ static double local_bond_energy(const orc_pot *p, int ndim, double n_p, const do
  * varying density the force above is -grad mu).  For the plain L-J branch
  * eps(n) = D (13/5 r0^12 n^5 - 14/3 r0^6 n^3); the branch multipliers switch
  * at n0 = r0^-3 with continuity of eps and its slope. */
+/* mu(n) = phi(rbar) - rbar phi'(rbar), rbar = n^(-1/3) */
+static double chem_potential(const orc_pot *p, double n) {
+  if (!(n > 0.0)) return 0.0;
+  double rb = pow(n, -1.0 / 3.0);
+  return orc_phi(p, rb) - rb * orc_phi_prime(p, rb);
+}
+
+static double simpson_step(const orc_pot *p, double a, double b, double fa, double fm, double fb, double whole,
+                           double tol, int depth) {
+  double m = 0.5 * (a + b);
+  double lm = chem_potential(p, 0.5 * (a + m)), rm = chem_potential(p, 0.5 * (m + b));
+  double left = (m - a) / 6.0 * (fa + 4.0 * lm + fm), right = (b - m) / 6.0 * (fm + 4.0 * rm + fb);
+  double diff = left + right - whole;
+  if (depth <= 0 || fabs(diff) <= 15.0 * tol) return left + right + diff / 15.0;
+  return simpson_step(p, a, m, fa, lm, fm, left, 0.5 * tol, depth - 1) +
+         simpson_step(p, m, b, fm, rm, fb, right, 0.5 * tol, depth - 1);
+}
+
+static double integrate_mu(const orc_pot *p, double a, double b) {
+  if (!(b > a)) return 0.0;
+  double fa = chem_potential(p, a), fb = chem_potential(p, b), fm = chem_potential(p, 0.5 * (a + b));
+  double whole = (b - a) / 6.0 * (fa + 4.0 * fm + fb);
+  double scale = p->D * (b - a) * (1.0 + fabs(p->s_rep) + fabs(p->c_att));
+  return simpson_step(p, a, b, fa, fm, fb, whole, 1e-15 * scale, 48);
+}
+
+/* The integral of mu from 0 to n, split where the branch multiplier switches
+ * (n0 = r0^-3, where mu has a kink). */
+double orc_energy_density_quad(const orc_pot *p, double n) {
+  const double n0 = 1.0 / (p->r0 * p->r0 * p->r0);
+  if (n <= n0) return integrate_mu(p, 0.0, n);
+  return integrate_mu(p, 0.0, n0) + integrate_mu(p, n0, n);
+}
+
 double orc_energy_density(const orc_pot *p, double n) {
+  if (p->kind != 0) return orc_energy_density_quad(p, n);
   const double r6 = pow(p->r0, 6.0), r12 = r6 * r6;
   const double n0 = 1.0 / (p->r0 * p->r0 * p->r0);
   double lj = p->D * (13.0 / 5.0 * r12 * pow(n, 5.0) - 14.0 / 3.0 * r6 * pow(n, 3.0));

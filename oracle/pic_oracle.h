@@ -41,6 +41,8 @@ typedef struct {
 
 typedef struct {
   double D, r0, s_rep, c_att, g_clamp, n_floor, mass;
+  int kind;      /* pair potential U: 0 eq. (3) Lennard-Jones, 1 Morse */
+  double alpha;  /* Morse width a, 1/m (kind 1) */
 } orc_pot;
 
 typedef struct {
@@ -70,6 +72,9 @@ void orc_local_force(const orc_pot *p, int ndim, double n_p, const double *G_p, 
 double orc_phi_prime(const orc_pot *p, double r);
 double orc_phi(const orc_pot *p, double r);
 double orc_energy_density(const orc_pot *p, double n);
+/* The same energy density by adaptive quadrature of mu from 0 to n, for any
+ * kind (the Morse energy density has no closed form). */
+double orc_energy_density_quad(const orc_pot *p, double n);
 
 /* Forces on np particles for a given deposit (node_f in 2^-20 atom units). */
 void orc_forces(const orc_grid *g, const orc_pot *p, const double *node_f, int64_t np,

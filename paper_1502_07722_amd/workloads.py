@@ -39,10 +39,20 @@ D_CU = 0.4093 * EV               # J, L-J well depth (placeholder Cu value; an i
 W_SHIFT = 20                     # weights are carried as wq = round(w * 2**W_SHIFT)
 
 
+KIND_LJ, KIND_MORSE = 0, 1
+# Morse copper (Girifalco and Weizer, Phys. Rev. 114, 687 (1959)): well depth
+# and width; the equilibrium distance is set like the L-J one (R0_CU).
+D_MORSE_CU = 0.3429 * EV         # J
+ALPHA_MORSE_CU = 1.3588e10       # 1/m
+
+
 @dataclasses.dataclass
 class Potential:
-    """Altered Lennard-Jones pair potential parameters (paper eq. (3) and the
-    paragraph on the altered potential and the attractive correction)."""
+    """Altered pair potential parameters (paper eq. (3) and the paragraph on
+    the altered potential and the attractive correction).  kind 0 is the
+    paper's Lennard-Jones eq. (3); kind 1 the Morse potential
+    D(e^2 - 2e), e = exp(-alpha (r - r0)), which the paper names as an
+    alternative."""
     D: float = D_CU
     r0: float = R0_CU
     s_rep: float = 1.0        # multiplier on the repulsive branch (r < r0)
@@ -50,6 +60,15 @@ class Potential:
     g_clamp: float = 1.0      # clamp on |d rbar/dx| in eq. (2)
     n_floor: float = 1e-6 * N_SOLID   # below this density the force is zero
     mass: float = M_CU
+    kind: int = KIND_LJ
+    alpha: float = 0.0        # Morse width, 1/m (kind 1)
+
+
+def morse_cu(**kw) -> Potential:
+    """The Morse copper potential at the L-J equilibrium distance."""
+    args = dict(D=D_MORSE_CU, kind=KIND_MORSE, alpha=ALPHA_MORSE_CU)
+    args.update(kw)
+    return Potential(**args)
 
 
 @dataclasses.dataclass
