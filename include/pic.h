@@ -79,8 +79,16 @@ typedef struct pic_grid {
   double depth2d;  /* 2D only: thickness the plane stands for, m; <= 0 means h[0] */
 } pic_grid_t;
 
-/* Altered Lennard-Jones potential, eq. (3), plus the two guards the method
- * needs where eq. (2) stops describing a lattice. */
+/* Altered pair potential plus the two guards the method needs where eq. (2)
+ * stops describing a lattice.  The pair potential U is the paper's
+ * Lennard-Jones eq. (3), or the Morse potential, which the paper names among
+ * the potentials its density-to-distance map works with:
+ *   PIC_POT_LJ     U(r) = D ((r0/r)^12 - 2 (r0/r)^6)
+ *   PIC_POT_MORSE  U(r) = D (e^2 - 2e),  e = exp(-alpha (r - r0))
+ * Both have their minimum -D at r0 (U'(r0) = 0), where the two branch
+ * multipliers switch.  The reverse-mode entry points support PIC_POT_LJ. */
+#define PIC_POT_LJ 0
+#define PIC_POT_MORSE 1
 typedef struct pic_potential {
   double D;        /* well depth (dissociation energy), J */
   double r0;       /* equilibrium distance, m */
@@ -89,6 +97,8 @@ typedef struct pic_potential {
   double g_clamp;  /* |d rbar / dx| is clamped to this (0 < g_clamp < 2) */
   double n_floor;  /* no force at densities n <= n_floor, m^-3 */
   double mass;     /* atomic mass, kg */
+  int32_t kind;    /* PIC_POT_LJ or PIC_POT_MORSE */
+  double alpha;    /* Morse width, 1/m (> 0 for PIC_POT_MORSE; unused otherwise) */
 } pic_potential_t;
 
 /* Caller-owned device arrays, structure-of-arrays. */

@@ -138,9 +138,36 @@ Layout make_layout(const pic_grid_t *grids, int nslab, const int64_t *max_n) {
 bool valid_potential(const pic_potential_t *pot) {
   if (!pot) return false;
   const pic_potential_t &P = *pot;
+  if (P.kind != PIC_POT_LJ && P.kind != PIC_POT_MORSE) return false;
+  if (P.kind == PIC_POT_MORSE && !(P.alpha > 0 && std::isfinite(P.alpha))) return false;
   return P.D > 0 && P.r0 > 0 && P.s_rep > 0 && P.c_att > 0 && P.g_clamp > 0 && P.g_clamp < 2 &&
          P.n_floor >= 0 && P.mass > 0 && std::isfinite(P.s_rep) && std::isfinite(P.c_att) &&
          std::isfinite(P.D) && std::isfinite(P.r0) && std::isfinite(P.mass);
+}
+
+// Nodes and weights of the 16-point Gauss-Legendre rule: the roots of P_16
+// by Newton's method from the usual cosine estimates, w = 2 / ((1 - x^2) P'^2).
+Quad16 gauss_legendre16() {
+  Quad16 q{};
+  const int n = 16;
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;  // Legendre recurrence up to P_n
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    q.x[i] = x;
+    q.w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  return q;
 }
 
 // Grid constants in the kernels' reduced units.
@@ -167,7 +194,8 @@ Geo make_geo(const pic_grid_t &g, const pic_potential_t &P, double dt, const Siz
 
 DiagC make_diag(const pic_grid_t &g, const pic_potential_t &P) {
   const double V = g.h[0] * g.h[1] * g.h[2];
-  return DiagC{P.D, P.mass, 0.5 * P.mass, std::ldexp(1.0, -20), V, P.r0 * P.r0 * P.r0, P.s_rep, P.c_att};
+  return DiagC{P.D, P.mass, 0.5 * P.mass, std::ldexp(1.0, -20), V, P.r0 * P.r0 * P.r0, P.s_rep, P.c_att,
+               P.kind, P.kind == PIC_POT_MORSE ? P.alpha * P.r0 : 0.0};
 }
 
 }  // namespace
@@ -185,6 +213,7 @@ struct pic_ctx {
   hipStream_t stream = nullptr;
   Pot P{};
   std::vector<DiagC> dcs;  // per slab (cell volume)
+  Quad16 quad{};           // Gauss-Legendre rule of the Morse energy density
   // shared buffers
   uint32_t *err = nullptr;
   pic_diag_t *diag_dev = nullptr;
@@ -459,6 +488,10 @@ static int init_common(pic_ctx_t **out, const pic_grid_t *grids_in, int nslab, c
   c->P.c_att = (float)P.c_att;
   c->P.beta = (float)(12.0 * P.D / P.r0);
   c->P.gv = (float)(dt / P.mass);
+  c->P.kind = P.kind;
+  c->P.mAl2 = P.kind == PIC_POT_MORSE ? (float)(P.alpha * P.r0 * M_LOG2E) : 0.0f;
+  c->P.mA6 = P.kind == PIC_POT_MORSE ? (float)(P.alpha * P.r0 / 6.0) : 0.0f;
+  c->quad = gauss_legendre16();
   int pe = 0;
   for (int k = 0; k < nslab; ++k) {
     c->dcs.push_back(make_diag(grids[k], P));
@@ -588,7 +621,7 @@ int step_untiled(pic_ctx_t *ctx, const PartPtrs &pp, int32_t nsteps, DiagSink &d
     int nbg = 0, nbp = 0;
     if (want) {
       PhaseTimer t(ctx, 4);
-      nbg = launch_pe_nodes(ctx->stream, ctx->geo, ctx->dcs[0], ctx->node, ctx->partial_pe);
+      nbg = launch_pe_nodes(ctx->stream, ctx->geo, ctx->dcs[0], ctx->quad, ctx->node, ctx->partial_pe);
     }
     {
       PhaseTimer t(ctx, 2);
@@ -762,7 +795,7 @@ int step_tiled(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t nsteps, Dia
     if (want) {
       PhaseTimer t(ctx, 4);
       for (int k = 0; k < ctx->nslab; ++k)
-        launch_pe_nodes(ctx->stream, ctx->sd[k].g, ctx->dcs[k], ctx->n3[s % 3] + ctx->sd[k].node_off,
+        launch_pe_nodes(ctx->stream, ctx->sd[k].g, ctx->dcs[k], ctx->quad, ctx->n3[s % 3] + ctx->sd[k].node_off,
                         ctx->partial_pe + (int64_t)ctx->pe_off[k] * 8);
     }
     enqueue_step(ctx, b, ctx->st[cur], s, want);
@@ -945,7 +978,7 @@ int pic_force(pic_ctx_t *ctx, const pic_particles_t *p, const int64_t *node_w, f
   launch_force(ctx->stream, ctx->geo, ctx->P, ptrs(p), ctx->dens, ctx->G, force, ctx->err);
   rc = check_launch(ctx, "force");
   if (rc || !pe_or_null) return rc;
-  int nb = launch_pe_nodes(ctx->stream, ctx->geo, ctx->dcs[0], nw, ctx->partial_pe);
+  int nb = launch_pe_nodes(ctx->stream, ctx->geo, ctx->dcs[0], ctx->quad, nw, ctx->partial_pe);
   launch_reduce_diag(ctx->stream, ctx->partial, 0, ctx->partial_pe, nb, ctx->diag_dev, 0);
   rc = check_launch(ctx, "potential energy");
   if (rc) return rc;
@@ -989,6 +1022,7 @@ int pic_push(pic_ctx_t *ctx, pic_particles_t *p, const float *force) {
 static int adjoint_common(pic_ctx_t *ctx, const pic_particles_t *p, const int64_t *node_w, const float *nbar_next,
                           const float *fbar, float *lam_x, float *lam_v, float *nbar, double *dtheta,
                           bool force_only, const char *what) {
+  if (ctx->pot.kind != PIC_POT_LJ) return fail(ctx, PIC_EINVAL, "reverse mode supports the Lennard-Jones potential only");
   if (!node_w) return fail(ctx, PIC_EINVAL, "node_w is NULL");
   if (!nbar) return fail(ctx, PIC_EINVAL, "nbar is NULL");
   if (!dtheta) return fail(ctx, PIC_EINVAL, "dtheta is NULL");
@@ -1189,6 +1223,7 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
                         const void *record, size_t record_bytes, void *scratch, size_t scratch_bytes, float *lam_x,
                         float *lam_v, double *dtheta) {
   if (!ctx) return PIC_EINVAL;
+  if (ctx->pot.kind != PIC_POT_LJ) return fail(ctx, PIC_EINVAL, "reverse mode supports the Lennard-Jones potential only");
   int rc = recorded_ok(ctx, p, nsteps, every);
   if (rc) return rc;
   const RecLayout R = rec_layout(ctx, nsteps, every);
@@ -1542,8 +1577,14 @@ struct Slab {
     return (node(m + 1) - node(m)) / h;
   }
   double dphi(double r) const {
-    double x6 = std::pow(pot.r0 / r, 6);
-    double u = 12.0 * pot.D / r * (x6 - x6 * x6);
+    double u;
+    if (pot.kind == PIC_POT_MORSE) {
+      const double e = std::exp(-pot.alpha * (r - pot.r0));
+      u = 2.0 * pot.alpha * pot.D * (e - e * e);
+    } else {
+      const double x6 = std::pow(pot.r0 / r, 6);
+      u = 12.0 * pot.D / r * (x6 - x6 * x6);
+    }
     return r < pot.r0 ? pot.s_rep * u : u;  // unit attractive multiplier
   }
   // normal force on a zero-weight atom at normal coordinate y (cells)
@@ -1580,7 +1621,8 @@ double simpson(const Slab &s, double a, double b, double fa, double fm, double f
 extern "C" int pic_calibrate_catt(const pic_grid_t *grid, const pic_potential_t *pot, double n_solid,
                                   int32_t slab_layers, double *c_att, double *work) {
   Sizes sz;
-  if (!grid_sizes(grid, &sz, nullptr) || !pot || !(n_solid > 0) || slab_layers < 2 || !c_att) return PIC_EINVAL;
+  if (!grid_sizes(grid, &sz, nullptr) || !valid_potential(pot) || !(n_solid > 0) || slab_layers < 2 || !c_att)
+    return PIC_EINVAL;
   Slab s{slab_layers, grid->h[grid->ndim - 1], n_solid, *pot};
   const double y0 = 0.5 * slab_layers, y1 = slab_layers + 1.0;
   const int nscan = 8192;

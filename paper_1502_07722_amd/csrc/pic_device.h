@@ -37,6 +37,9 @@ struct Pot {
   float c_att;
   float beta;      // 12 D / r0: reduced force -> newtons
   float gv;        // dt / m: newtons -> velocity change per step
+  int kind;        // pair potential: 0 Lennard-Jones eq. (3), 1 Morse
+  float mAl2;      // Morse: alpha r0 log2(e)
+  float mA6;       // Morse: alpha r0 / 6
 };
 
 // ---------------------------------------------------------------------------
@@ -171,20 +174,39 @@ __device__ __forceinline__ void centre_stencil(int i, float f, int &c0, float &t
 // s+- = r0 / r+- = q (1 -+ g/2);  phi'(s) = (12 D / r0) M(s) (s^7 - s^13),
 // M = s_rep for r < r0 (s > 1), c_att otherwise;  F = phi'(s+) - phi'(s-).
 // ---------------------------------------------------------------------------
+// Morse in the same units: r / r0 = 1/s, e = exp(-alpha r0 (1/s - 1)),
+// U'(r) / (12 D / r0) = (alpha r0 / 6) e (1 - e), U / D = e (e - 2).  The kind
+// is a kernel argument, so the branch is uniform across the wavefront.
+__device__ __forceinline__ float morse_e(const Pot &P, float s) {
+  return __builtin_amdgcn_exp2f(__builtin_fmaf(-P.mAl2, __builtin_amdgcn_rcpf(s), P.mAl2));
+}
+
 __device__ __forceinline__ float dphi_hat(const Pot &P, float s) {
-  float s2 = s * s;
-  float s3 = s2 * s;
-  float s6 = s3 * s3;
-  float s7 = s6 * s;
-  float v = __builtin_fmaf(-s7, s6, s7);  // s^7 - s^13
+  float v;
+  if (P.kind == 1) {
+    const float e = morse_e(P, s);
+    v = P.mA6 * __builtin_fmaf(-e, e, e);  // (alpha r0 / 6) (e - e^2)
+  } else {
+    float s2 = s * s;
+    float s3 = s2 * s;
+    float s6 = s3 * s3;
+    float s7 = s6 * s;
+    v = __builtin_fmaf(-s7, s6, s7);  // s^7 - s^13
+  }
   return (s > 1.0f ? P.s_rep : P.c_att) * v;
 }
 
 __device__ __forceinline__ float phi_hat(const Pot &P, float s) {
-  // U / D = s^12 - 2 s^6; altered branches stay continuous at r0
-  float s6 = s * s * s;
-  s6 = s6 * s6;
-  float u = __builtin_fmaf(s6, s6, -2.0f * s6);
+  // U / D; altered branches stay continuous at r0
+  float u;
+  if (P.kind == 1) {
+    const float e = morse_e(P, s);
+    u = e * (e - 2.0f);
+  } else {
+    float s6 = s * s * s;
+    s6 = s6 * s6;
+    u = __builtin_fmaf(s6, s6, -2.0f * s6);  // s^12 - 2 s^6
+  }
   return s > 1.0f ? __builtin_fmaf(P.s_rep, u, P.s_rep - P.c_att) : P.c_att * u;
 }
 

@@ -12,6 +12,14 @@ namespace pic {
 // FP64 constants of the diagnostics (SI).
 struct DiagC {
   double D, mass, half_m, wunit, vcell, r0cube, s_rep, c_att;
+  int kind;   // pair potential: 0 Lennard-Jones (closed-form energy density), 1 Morse
+  double mA;  // Morse: alpha r0
+};
+
+// 16-point Gauss-Legendre rule on [-1, 1] (the Morse energy density is an
+// integral with no closed form).
+struct Quad16 {
+  double x[16], w[16];
 };
 
 struct PartPtrs {
@@ -102,7 +110,8 @@ void launch_push(hipStream_t s, const Geo &g, const Pot &P, const PartPtrs &pp, 
 void launch_kick(hipStream_t s, const Geo &g, const Pot &P, const PartPtrs &pp, const float *force, float frac);
 int launch_force_push(hipStream_t s, const Geo &g, const Pot &P, const DiagC &dc, const PartPtrs &pp,
                       const float *dens, const float *G, double *partial, bool diag, uint32_t *err);
-int launch_pe_nodes(hipStream_t s, const Geo &g, const DiagC &dc, const long long *node, double *partial);
+int launch_pe_nodes(hipStream_t s, const Geo &g, const DiagC &dc, const Quad16 &q, const long long *node,
+                    double *partial);
 void launch_reduce_diag(hipStream_t s, const double *part_p, int nblk_p, const double *part_g, int nblk_g,
                         pic_diag_t *out, int64_t step);
 

@@ -288,16 +288,42 @@ __global__ void __launch_bounds__(256) k_force_push(Geo g, Pot P, DiagC dc, int6
   if (DIAG) block_reduce_store<6>(acc, partial + (int64_t)blockIdx.x * 8);
 }
 
+// Chemical potential mu / D of the Morse potential at reduced density x > 0:
+// rho = x^(-1/3) = rbar / r0, mu = M (U - rbar U') / D plus the altered
+// branch's constant above x = 1 (M = c_att below, s_rep above).
+__device__ __forceinline__ double mu_morse(const DiagC &dc, double x) {
+  const double rho = pow(x, -1.0 / 3.0);
+  const double e = exp(-dc.mA * (rho - 1.0));
+  const double u = e * (e - 2.0);                 // U / D
+  const double du = 2.0 * dc.mA * e * (1.0 - e);  // r0 U'(r) / D
+  return x <= 1.0 ? dc.c_att * (u - rho * du) : dc.s_rep * (u - rho * du) + (dc.s_rep - dc.c_att);
+}
+
+__device__ __forceinline__ double gauss16(const DiagC &dc, const Quad16 &q, double a, double b) {
+  const double h = 0.5 * (b - a), m = 0.5 * (a + b);
+  double acc = 0.0;
+  for (int i = 0; i < 16; ++i) acc += q.w[i] * mu_morse(dc, m + h * q.x[i]);
+  return h * acc;
+}
+
 // Energy density of the pair potential in units of D r0^-3 at reduced density x:
-// e'(x) = mu: plain L-J e(x) = 13/5 x^5 - 14/3 x^3, branches switch at x = 1.
-__device__ __forceinline__ double eps_hat(const DiagC &dc, double x) {
+// e'(x) = mu: plain L-J e(x) = 13/5 x^5 - 14/3 x^3, branches switch at x = 1;
+// Morse: the integral of mu from 0 to x (Gauss-Legendre, split at x = 1 where
+// mu has a kink).
+__device__ __forceinline__ double eps_hat(const DiagC &dc, const Quad16 &q, double x) {
+  if (dc.kind == 1) {
+    if (!(x > 0.0)) return 0.0;
+    double e = gauss16(dc, q, 0.0, fmin(x, 1.0));
+    if (x > 1.0) e += gauss16(dc, q, 1.0, x);
+    return e;
+  }
   auto lj = [](double y) { return (13.0 / 5.0) * y * y * y * y * y - (14.0 / 3.0) * y * y * y; };
   if (x <= 1.0) return dc.c_att * lj(x);
   return dc.c_att * lj(1.0) + dc.s_rep * (lj(x) - lj(1.0)) + (dc.s_rep - dc.c_att) * (x - 1.0);
 }
 
 template <int ND>
-__global__ void __launch_bounds__(256) k_pe_nodes(Geo g, DiagC dc, const long long *__restrict__ node,
+__global__ void __launch_bounds__(256) k_pe_nodes(Geo g, DiagC dc, Quad16 q, const long long *__restrict__ node,
                                                   double *__restrict__ partial) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   double acc[1] = {0.0};
@@ -311,7 +337,7 @@ __global__ void __launch_bounds__(256) k_pe_nodes(Geo g, DiagC dc, const long lo
     if (g.bc[1] && (a1 == 0 || a1 == g.n[1])) V *= 0.5;
     if (ND == 3 && g.bc[2] && (a2 == 0 || a2 == g.n[2])) V *= 0.5;
     double x = (double)node[k] * dc.wunit * dc.r0cube / V;
-    acc[0] = V * eps_hat(dc, x) * dc.D / dc.r0cube;
+    acc[0] = V * eps_hat(dc, q, x) * dc.D / dc.r0cube;
   }
   block_reduce_store<1>(acc, partial + (int64_t)blockIdx.x * 8);
 }
@@ -414,9 +440,10 @@ int launch_force_push(hipStream_t s, const Geo &g, const Pot &P, const DiagC &dc
   return (int)nb;
 }
 
-int launch_pe_nodes(hipStream_t s, const Geo &g, const DiagC &dc, const long long *node, double *partial) {
+int launch_pe_nodes(hipStream_t s, const Geo &g, const DiagC &dc, const Quad16 &q, const long long *node,
+                    double *partial) {
   unsigned nb = nblocks(g.nnodes);
-  PIC_DISPATCH(g.ndim, (k_pe_nodes<ND><<<nb, 256, 0, s>>>(g, dc, node, partial)));
+  PIC_DISPATCH(g.ndim, (k_pe_nodes<ND><<<nb, 256, 0, s>>>(g, dc, q, node, partial)));
   return (int)nb;
 }
 
