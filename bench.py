@@ -10,6 +10,7 @@ pic_step(K) with the particles already resident in HBM.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -25,7 +26,7 @@ HBM_PEAK_GBS = 8000.0
 # 4*ndim + velocity 12 + weight 4, writes cell 4 + offsets 4*ndim + velocity
 # 12: 52 B in 2D, 60 B in 3D -- plus 16 B per node (int64 sums written once
 # and read once).
-DEFAULTS = {"large": (2000, 20), "heated": (5000, 20), "small": (200, 20), "sweep": (1000, 12), "adjoint": (400, 1)}
+DEFAULTS = {"large": (2000, 20), "large_morse": (500, 20), "heated": (5000, 20), "small": (200, 20), "sweep": (1000, 12), "adjoint": (400, 1)}
 
 
 COUNTERS = {"large": "profiles/k_step_tiled_slab2d_4096x2048_32ppc.counters.json"}
@@ -293,10 +294,11 @@ def measure_crater(ctx, wl, stream, log_fn=log, calls=20):
             "y_s": y_s, "beam_d": beam_d}
 
 
-def run_slab(name, steps, warmup, log_fn=log):
+def run_slab(name, steps, warmup, log_fn=log, morse=False):
     """One single-slab workload through pic_step: (result, workload, potential,
     diagnostics).  The timed region is one pic_step call of `steps` steps
-    with diagnostics every 100 steps, particles resident in HBM."""
+    with diagnostics every 100 steps, particles resident in HBM.  morse: the
+    Morse pair potential (copper) instead of eq. (3)."""
     import numpy as np
     import torch
     from paper_1502_07722_amd import binding as B
@@ -305,8 +307,9 @@ def run_slab(name, steps, warmup, log_fn=log):
     t0 = time.perf_counter()
     wl = W.WORKLOADS[name]()
     log_fn(f"generated {wl.name}: {wl.parts.n} particles in {time.perf_counter() - t0:.1f} s")
-    c_att, _ = B.pic_calibrate_catt(wl.grid, wl.pot, W.N_SOLID, 8)
-    pot = W.Potential(c_att=c_att)
+    base = W.morse_cu() if morse else wl.pot
+    c_att, _ = B.pic_calibrate_catt(wl.grid, base, W.N_SOLID, 8)
+    pot = dataclasses.replace(base, c_att=c_att)
     N = wl.parts.n
     dev = torch.device("cuda:0")
     # a created stream: plain steps replay as HIP graphs there
@@ -356,7 +359,8 @@ def run_slab(name, steps, warmup, log_fn=log):
                 "bytes_per_node": 16, "avg_launch_ms": avg_s * 1e3,
                 "phases_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in timing.items() if isinstance(v, tuple)},
                 "drifters_last_step": timing.get("drifters_last"), "items_last_step": timing.get("items_last")}
-    res = {"workload": wl.name, "particles": N, "value": N * steps / elapsed, "ms_per_step": elapsed / steps * 1e3,
+    res = {"workload": wl.name + ("_morse" if morse else ""), "particles": N, "value": N * steps / elapsed,
+           "ms_per_step": elapsed / steps * 1e3, "potential": "morse" if morse else "lennard-jones",
            "elapsed_s": elapsed, "roofline": roofline, "c_att": c_att, "tiling": tuning,
            "ms_per_step_with_events": elapsed_events / steps * 1e3, "crater": crater}
     del ctx, dp, start
@@ -452,6 +456,12 @@ def main():
             out["configs"][name] = {k: r[k] for k in ("workload", "particles", "value", "ms_per_step")}
             out["configs"][name]["roofline_frac"] = r["roofline"]["frac"]
             out["configs"][name]["roofline_achieved_gbs"] = r["roofline"]["achieved"]
+        # the same large slab with the Morse pair potential (the paper names it as an alternative)
+        r, _, _, _ = run_slab("large", *DEFAULTS["large_morse"], morse=True)
+        out["configs"]["large_morse"] = {k: r[k] for k in ("workload", "particles", "value", "ms_per_step",
+                                                           "potential", "c_att")}
+        out["configs"]["large_morse"]["roofline_frac"] = r["roofline"]["frac"]
+        out["configs"]["large_morse"]["roofline_achieved_gbs"] = r["roofline"]["achieved"]
     if not args.no_sweep and args.workload == "large":
         out["sweep"] = run_sweep(*DEFAULTS["sweep"])
     if not args.no_adjoint and args.workload == "large":
