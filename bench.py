@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0
 # 4*ndim + velocity 12 + weight 4, writes cell 4 + offsets 4*ndim + velocity
 # 12: 52 B in 2D, 60 B in 3D -- plus 16 B per node (int64 sums written once
 # and read once).
-DEFAULTS = {"large": (2000, 20), "large_morse": (500, 20), "heated": (5000, 20), "small": (200, 20), "sweep": (1000, 12), "adjoint": (400, 1)}
+DEFAULTS = {"large": (2000, 20), "large_morse": (500, 20), "convergence": (5000, 0), "heated": (5000, 20), "small": (200, 20), "sweep": (1000, 12), "adjoint": (400, 1)}
 
 
 COUNTERS = {"large": "profiles/k_step_tiled_slab2d_4096x2048_32ppc.counters.json"}
@@ -373,7 +373,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="large", choices=["large", "heated", "small", "sweep", "adjoint"])
+    ap.add_argument("--workload", default="large",
+                    choices=["large", "heated", "small", "sweep", "adjoint", "convergence"])
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the batched intensity sweep (plain loop vs batched) reported in the same line")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -403,6 +404,24 @@ def main():
                "warmup": 1, "ms_per_step": res["backward_s"] / res["steps"] * 1e3, "higher_is_better": False,
                "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
                "config": {"workload": res["workload"]}, "adjoint": res}
+        print(json.dumps(out), flush=True)
+        return
+
+    if args.workload == "convergence":
+        from paper_1502_07722_amd import convergence as CV
+        t0 = time.perf_counter()
+        res = CV.run_all(steps=steps, log_fn=log)
+        wall = time.perf_counter() - t0
+        rows = [r for v in res.values() for r in v]
+        ps = sum(r["particles"] * r["steps"] for r in rows)
+        t_run = sum(r["particles"] * r["steps"] / r["particle_steps_per_s"] for r in rows)
+        out = {"metric": "particle-steps/s (deposit+force+push), convergence studies",
+               "value": ps / t_run, "unit": "particle-steps/s", "n_gpus": 1, "steps": steps, "warmup": 0,
+               "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "f32", "data": "synthetic",
+               "config": {"workload": "convergence studies: ppc 4-3600 at 10 nm cells; cells 10-2 nm at 64 ppc; "
+                                      "s_rep 1-32 with quiet start; 640x320 nm box, 160 nm slab, 3 J/cm^2"},
+               "wall_s": wall, "convergence": res}
         print(json.dumps(out), flush=True)
         return
 

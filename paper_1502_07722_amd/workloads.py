@@ -159,24 +159,42 @@ def heating_sigma(x, y_depth, fluence, R, x_c, delta=15e-9, n_s=N_SOLID, mass=M_
 def make_slab(ndim: int, n: tuple, slab_layers: int, ppc: int, h: float, seed: int,
               fluence_Jcm2: float = 0.0, R_cells: float = 200.0, x_c_cells: Optional[float] = None,
               delta: float = 15e-9, T: float = 300.0, pot: Optional[Potential] = None,
-              bc: Optional[tuple] = None) -> tuple:
+              bc: Optional[tuple] = None, quiet: float = -1.0, depth2d: float = 0.0) -> tuple:
     """A copper slab filling the lowest ``slab_layers`` layers along the normal
     (last) axis, exactly ``ppc`` macroparticles per cell, uniform-random
     offsets, Maxwellian velocities at ``T`` plus the optional heating kick.
+
+    quiet >= 0: quiet-start loading instead of uniform-random offsets: the
+    cell's ppc = k^ndim macroparticles sit on a k^ndim sub-lattice, each moved
+    by quiet * (u - 1/2) of the sub-spacing per axis (u uniform in [0, 1);
+    quiet = 0 is the exact sub-lattice, whose deposit is uniform).
+
+    depth2d > 0 (2D): the thickness the plane stands for (default one cell
+    edge); it sets the atoms per macroparticle, not the density.
 
     Particles are emitted cell by cell in linear cell order."""
     pot = pot or Potential()
     n = tuple(list(n) + [1] * (3 - len(n)))
     if bc is None:
         bc = (0, 1, 0) if ndim == 2 else (0, 0, 1)
-    grid = Grid(ndim=ndim, n=n, h=(h, h, h), bc=bc)
+    grid = Grid(ndim=ndim, n=n, h=(h, h, h), bc=bc, depth2d=depth2d if ndim == 2 else 0.0)
     rng_pos, rng_mb, rng_kick = _streams(seed)
     lateral = int(np.prod(n[: ndim - 1]))
     ncell_slab = lateral * slab_layers
     N = ncell_slab * ppc
     cell = np.repeat(np.arange(ncell_slab, dtype=np.int64), ppc).astype(np.int32)
-    off = _uniform_f32(rng_pos, (ndim, N))
-    atoms_per_cell = N_SOLID * h ** 3
+    if quiet >= 0.0:
+        k = int(round(ppc ** (1.0 / ndim)))
+        if k ** ndim != ppc or not quiet <= 1.0:
+            raise ValueError("quiet start needs ppc = k^ndim and 0 <= quiet <= 1")
+        sub = np.stack(np.meshgrid(*[np.arange(k)] * ndim, indexing="ij"), axis=0).reshape(ndim, ppc)
+        base = np.tile(sub, (1, ncell_slab)).astype(np.float64)
+        u = rng_pos.random((ndim, N))
+        off = ((base + 0.5 + quiet * (u - 0.5)) / k).astype(np.float32)
+        off = np.minimum(off, np.float32(np.nextafter(np.float32(1), np.float32(0))))
+    else:
+        off = _uniform_f32(rng_pos, (ndim, N))
+    atoms_per_cell = N_SOLID * h ** 3 if ndim == 3 else N_SOLID * h * h * grid.depth2d
     w = atoms_per_cell / ppc
     wq = np.full(N, weight_q(w), dtype=np.int32)
     sig_th = math.sqrt(KB * T / pot.mass) if T > 0 else 0.0

@@ -1,0 +1,65 @@
+"""GPU: one case of the convergence studies (paper_1502_07722_amd/
+convergence.py) against the same case run by the FP64 oracle, observable by
+observable, and a quick pass over all three studies.
+
+Bars: c_att (host calibration) 1e-9; KE ratio and largest node density
+1e-4 relative; energy drift within 1e-4 of |E| / KE (the energy bar of the
+100-step parity tests, expressed in the drift's units); beam-spot deficit
+within 1e-3 nm.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import crater as CR
+from oracle import oracle as O
+from paper_1502_07722_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def test_study_case_matches_oracle():
+    from paper_1502_07722_amd import convergence as CV
+    case = CV.Case(h_nm=10.0, ppc=16, box_nm=(320.0, 160.0), slab_nm=80.0, steps=100, fluence_Jcm2=3.0,
+                   R_nm=100.0, quiet=0.5)
+    print(f"[convergence] GPU {case.label}", flush=True)
+    got = CV.run_case(case)
+    nx, ny, layers = CV._cells(case)
+    h = case.h_nm * 1e-9
+    grid, parts = W.make_slab(2, (nx, ny), layers, case.ppc, h, case.seed, fluence_Jcm2=case.fluence_Jcm2,
+                              R_cells=case.R_nm / case.h_nm, quiet=case.quiet, depth2d=case.depth_nm * 1e-9)
+    c_att, _, _ = O.calibrate_catt(grid, W.Potential(s_rep=case.s_rep), W.N_SOLID, 8)
+    assert abs(c_att - got["c_att"]) <= 1e-9 * c_att
+    pot = W.Potential(s_rep=case.s_rep, c_att=c_att)
+    every = max(case.steps // 10, 1)
+    v0 = O.start_leapfrog(grid, pot, case.dt, parts.cell, parts.off, parts.vel, parts.wq)
+    c2, o2, _, od = O.run(grid, pot, case.dt, parts.cell, parts.off, v0, parts.wq, case.steps, diag_every=every)
+    nodes = O.deposit(grid, c2, o2, parts.wq)
+    y_s = layers * h
+    t = CR.column_thickness(grid, nodes, W.N_SOLID, 0.01)
+    x = (np.arange(nx) - nx / 2.0) * h
+    spot = np.abs(x) <= case.R_nm * 1e-9
+    ref = {"ke_ratio": od[-1]["ke"] / od[0]["ke"],
+           "drift": (od[-1]["ke"] + od[-1]["pe"] - od[0]["ke"] - od[0]["pe"]) / od[0]["ke"],
+           "deficit_nm": float(np.mean(y_s - t[spot])) * 1e9,
+           "rho_max": float(CR.solid_density(grid, nodes, W.N_SOLID).max())}
+    print(f"[convergence] library {[got[k] for k in ref]} oracle {list(ref.values())}", flush=True)
+    assert got["ke_ratio"] == pytest.approx(ref["ke_ratio"], rel=1e-4)
+    assert got["rho_max"] == pytest.approx(ref["rho_max"], rel=1e-4)
+    e_over_ke = abs(od[0]["ke"] + od[0]["pe"]) / od[0]["ke"]
+    assert abs(got["drift"] - ref["drift"]) <= 1e-4 * e_over_ke
+    assert abs(got["deficit_nm"] - ref["deficit_nm"]) <= 1e-3
+
+
+def test_quick_pass_over_the_three_studies():
+    from paper_1502_07722_amd import convergence as CV
+    out = CV.run_all(steps=200, small=True, log_fn=lambda m: print(f"[convergence] {m}", flush=True))
+    for name, rows in out.items():
+        assert len(rows) == 2, name
+        for r in rows:
+            for k in CV.OBSERVABLES:
+                assert math.isfinite(r[k]), (name, k)
+            assert r["particle_steps_per_s"] > 0
+        assert all(v == 0.0 for v in rows[-1]["diff_vs_finest"].values())
