@@ -39,7 +39,7 @@ class _Grid(C.Structure):
 class _Pot(C.Structure):
     _fields_ = [("D", C.c_double), ("r0", C.c_double), ("s_rep", C.c_double), ("c_att", C.c_double),
                 ("g_clamp", C.c_double), ("n_floor", C.c_double), ("mass", C.c_double), ("kind", C.c_int),
-                ("alpha", C.c_double)]
+                ("lattice", C.c_int), ("alpha", C.c_double)]
 
 
 class _Diag(C.Structure):
@@ -72,6 +72,8 @@ def lib():
         _lib.orc_phi.argtypes = [P(_Pot), d]
         _lib.orc_energy_density.restype = d
         _lib.orc_energy_density.argtypes = [P(_Pot), d]
+        _lib.orc_hcp_direction.restype = None
+        _lib.orc_hcp_direction.argtypes = [C.c_int, P(d)]
         _lib.orc_energy_density_quad.restype = d
         _lib.orc_energy_density_quad.argtypes = [P(_Pot), d]
         _lib.orc_forces.argtypes = [P(_Grid), P(_Pot), P(d), i64, P(i32), P(d), P(d)]
@@ -103,7 +105,7 @@ def grid_struct(grid, quantized: bool = True) -> _Grid:
 
 def pot_struct(pot) -> _Pot:
     return _Pot(pot.D, pot.r0, pot.s_rep, pot.c_att, pot.g_clamp, pot.n_floor, pot.mass,
-                int(getattr(pot, "kind", 0)), float(getattr(pot, "alpha", 0.0)))
+                int(getattr(pot, "kind", 0)), int(getattr(pot, "lattice", 0)), float(getattr(pot, "alpha", 0.0)))
 
 
 class OracleError(RuntimeError):
@@ -198,6 +200,17 @@ def phi(pot, r):
 
 def energy_density(pot, n):
     return lib().orc_energy_density(C.byref(pot_struct(pot)), float(n))
+
+
+def hcp_directions():
+    """The 12 nearest-neighbour unit vectors of the oracle's hexagonal
+    close-packed lattice, (basal 1, basal 2, c) axes, shape [12, 3]."""
+    out = np.zeros((12, 3))
+    for k in range(12):
+        u = (C.c_double * 3)()
+        lib().orc_hcp_direction(k, u)
+        out[k] = list(u)
+    return out
 
 
 def energy_density_quad(pot, n):

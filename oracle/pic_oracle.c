@@ -312,9 +312,58 @@ void orc_neighbour_distances(const orc_pot *p, double n_p, double G_pd, double *
   *r_minus = rbar / (1.0 + 0.5 * g); /* eq. (2), neighbour on the -d side */
 }
 
+/* Hexagonal close-packed lattice (the paper notes the construction adapts to
+ * it).  Reading: the 12 nearest neighbours of the ideal lattice (c/a =
+ * sqrt(8/3)), c axis along the normal (last) axis, a basal axis along x;
+ * nearest-neighbour distance a = 2^(1/6) rbar (atomic volume a^3/sqrt(2)).
+ * The midpoint rule of eq. (2) along neighbour direction u: the pair
+ * distance equals the local spacing half-way, d = 2^(1/6) (rbar + (d/2)
+ * grad(rbar).u), so d = 2^(1/6) rbar / (1 - q/2) with q = 2^(1/6) grad(rbar).u
+ * clamped to [-g_clamp, g_clamp] (the cubic rule is c = 1, u = +-e_d).  The
+ * force is the sum of the 12 pair forces phi'(d) u.  In 2D the second basal
+ * axis is the one the plane does not resolve: its density gradient is zero
+ * and its force component is dropped (the lattice and its mirror image in
+ * that axis give the same in-plane force and opposite out-of-plane ones). */
+#define HCP_C 1.1224620483093730 /* 2^(1/6) */
+void orc_hcp_direction(int k, double u[3]) { /* basal 1, basal 2, c */
+  if (k < 6) {
+    double t = acos(-1.0) / 3.0 * k;
+    u[0] = cos(t); u[1] = sin(t); u[2] = 0.0;
+  } else {
+    double t = acos(-1.0) * (1.0 / 6.0 + 2.0 / 3.0 * ((k - 6) % 3));
+    u[0] = cos(t) / sqrt(3.0); u[1] = sin(t) / sqrt(3.0); u[2] = (k < 9 ? 1.0 : -1.0) * sqrt(2.0 / 3.0);
+  }
+}
+
+/* neighbour k's direction in grid axes (evolved components; 2D: x, normal) */
+static void hcp_grid_direction(int ndim, int k, double v[3]) {
+  double u[3];
+  orc_hcp_direction(k, u);
+  if (ndim == 3) { v[0] = u[0]; v[1] = u[1]; v[2] = u[2]; }
+  else { v[0] = u[0]; v[1] = u[2]; v[2] = 0.0; }
+}
+
+static double hcp_distance(const orc_pot *p, int ndim, double n_p, const double *G_p, const double *v) {
+  double rbar = pow(n_p, -1.0 / 3.0), gu = 0.0;
+  for (int d = 0; d < ndim; ++d) gu += -(1.0 / 3.0) * G_p[d] * pow(n_p, -4.0 / 3.0) * v[d]; /* eq. (1) */
+  double q = HCP_C * gu;
+  if (q > p->g_clamp) q = p->g_clamp;
+  if (q < -p->g_clamp) q = -p->g_clamp;
+  return HCP_C * rbar / (1.0 - 0.5 * q);
+}
+
 void orc_local_force(const orc_pot *p, int ndim, double n_p, const double *G_p, double *F) {
   for (int d = 0; d < ndim; ++d) F[d] = 0.0;
   if (!(n_p > p->n_floor)) return;
+  if (p->lattice == 1) {
+    for (int k = 0; k < 12; ++k) {
+      double v[3];
+      hcp_grid_direction(ndim, k, v);
+      double f = orc_phi_prime(p, hcp_distance(p, ndim, n_p, G_p, v));
+      for (int d = 0; d < ndim; ++d) F[d] += f * v[d];
+    }
+    return;
+  }
   for (int d = 0; d < ndim; ++d) {
     double r_plus, r_minus;
     orc_neighbour_distances(p, n_p, G_p[d], &r_plus, &r_minus);
@@ -322,11 +371,19 @@ void orc_local_force(const orc_pot *p, int ndim, double n_p, const double *G_p, 
   }
 }
 
-/* Per-atom bond energy of the same construction: (1/2) sum over the 2*ndim
- * neighbour pairs of phi(r). */
+/* Per-atom bond energy of the same construction: (1/2) sum over the
+ * neighbour pairs of phi(r) (cubic: 2*ndim, hexagonal: 12). */
 static double local_bond_energy(const orc_pot *p, int ndim, double n_p, const double *G_p) {
   if (!(n_p > p->n_floor)) return 0.0;
   double e = 0.0;
+  if (p->lattice == 1) {
+    for (int k = 0; k < 12; ++k) {
+      double v[3];
+      hcp_grid_direction(ndim, k, v);
+      e += 0.5 * orc_phi(p, hcp_distance(p, ndim, n_p, G_p, v));
+    }
+    return e;
+  }
   for (int d = 0; d < ndim; ++d) {
     double r_plus, r_minus;
     orc_neighbour_distances(p, n_p, G_p[d], &r_plus, &r_minus);
@@ -340,10 +397,17 @@ static double local_bond_energy(const orc_pot *p, int ndim, double n_p, const do
  * varying density the force above is -grad mu).  For the plain L-J branch
  * eps(n) = D (13/5 r0^12 n^5 - 14/3 r0^6 n^3); the branch multipliers switch
  * at n0 = r0^-3 with continuity of eps and its slope. */
-/* mu(n) = phi(rbar) - rbar phi'(rbar), rbar = n^(-1/3) */
+/* mu(n) = phi(rbar) - rbar phi'(rbar), rbar = n^(-1/3); hexagonal lattice:
+ * mu = 2 (phi(a) - a phi'(a)), a = 2^(1/6) rbar: the 12 bonds (sum of u u^T
+ * = 4 I) give the small-gradient force 2^(4/3) rbar phi''(a) grad(rbar),
+ * which is -grad mu. */
 static double chem_potential(const orc_pot *p, double n) {
   if (!(n > 0.0)) return 0.0;
   double rb = pow(n, -1.0 / 3.0);
+  if (p->lattice == 1) {
+    double a = HCP_C * rb;
+    return 2.0 * (orc_phi(p, a) - a * orc_phi_prime(p, a));
+  }
   return orc_phi(p, rb) - rb * orc_phi_prime(p, rb);
 }
 
@@ -362,20 +426,22 @@ static double integrate_mu(const orc_pot *p, double a, double b) {
   if (!(b > a)) return 0.0;
   double fa = chem_potential(p, a), fb = chem_potential(p, b), fm = chem_potential(p, 0.5 * (a + b));
   double whole = (b - a) / 6.0 * (fa + 4.0 * fm + fb);
-  double scale = p->D * (b - a) * (1.0 + fabs(p->s_rep) + fabs(p->c_att));
-  return simpson_step(p, a, b, fa, fm, fb, whole, 1e-15 * scale, 48);
+  /* tolerance relative to the integrand's size on the interval, so that the
+   * recursion ends where mu grows steeply (compressed densities) */
+  double big = fmax(fmax(fabs(fa), fabs(fb)), fmax(fabs(fm), p->D));
+  return simpson_step(p, a, b, fa, fm, fb, whole, 1e-14 * big * (b - a), 40);
 }
 
 /* The integral of mu from 0 to n, split where the branch multiplier switches
- * (n0 = r0^-3, where mu has a kink). */
+ * (n0 = r0^-3, sqrt(2) r0^-3 on the hexagonal lattice; mu has a kink). */
 double orc_energy_density_quad(const orc_pot *p, double n) {
-  const double n0 = 1.0 / (p->r0 * p->r0 * p->r0);
+  const double n0 = (p->lattice == 1 ? sqrt(2.0) : 1.0) / (p->r0 * p->r0 * p->r0);
   if (n <= n0) return integrate_mu(p, 0.0, n);
   return integrate_mu(p, 0.0, n0) + integrate_mu(p, n0, n);
 }
 
 double orc_energy_density(const orc_pot *p, double n) {
-  if (p->kind != 0) return orc_energy_density_quad(p, n);
+  if (p->kind != 0 || p->lattice != 0) return orc_energy_density_quad(p, n);
   const double r6 = pow(p->r0, 6.0), r12 = r6 * r6;
   const double n0 = 1.0 / (p->r0 * p->r0 * p->r0);
   double lj = p->D * (13.0 / 5.0 * r12 * pow(n, 5.0) - 14.0 / 3.0 * r6 * pow(n, 3.0));

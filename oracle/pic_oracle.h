@@ -42,6 +42,7 @@ typedef struct {
 typedef struct {
   double D, r0, s_rep, c_att, g_clamp, n_floor, mass;
   int kind;      /* pair potential U: 0 eq. (3) Lennard-Jones, 1 Morse */
+  int lattice;   /* assumed lattice: 0 cubic (eq. 1-2 per axis), 1 hexagonal close-packed */
   double alpha;  /* Morse width a, 1/m (kind 1) */
 } orc_pot;
 
@@ -72,6 +73,9 @@ void orc_local_force(const orc_pot *p, int ndim, double n_p, const double *G_p, 
 double orc_phi_prime(const orc_pot *p, double r);
 double orc_phi(const orc_pot *p, double r);
 double orc_energy_density(const orc_pot *p, double n);
+/* Unit vector to nearest neighbour k (0-11) of the ideal hexagonal
+ * close-packed lattice, in (basal 1, basal 2, c) axes. */
+void orc_hcp_direction(int k, double u[3]);
 /* The same energy density by adaptive quadrature of mu from 0 to n, for any
  * kind (the Morse energy density has no closed form). */
 double orc_energy_density_quad(const orc_pot *p, double n);

@@ -62,6 +62,22 @@ class Potential:
     mass: float = M_CU
     kind: int = KIND_LJ
     alpha: float = 0.0        # Morse width, 1/m (kind 1)
+    lattice: int = 0          # 0 cubic (eqs. (1)-(2) per axis), 1 hexagonal close-packed
+
+
+LATTICE_CUBIC, LATTICE_HCP = 0, 1
+HCP_C = 2.0 ** (1.0 / 6.0)       # nearest-neighbour distance / rbar on a close-packed lattice
+
+
+def hcp(pot: Optional["Potential"] = None, **kw) -> "Potential":
+    """The pair potential on the hexagonal close-packed lattice with r0 at the
+    close-packed nearest-neighbour distance of solid copper, 2^(1/6)
+    n_s^(-1/3), so that the solid sits at the potential minimum as it does on
+    the cubic lattice."""
+    pot = pot or Potential()
+    args = dict(lattice=LATTICE_HCP, r0=HCP_C * R0_CU)
+    args.update(kw)
+    return dataclasses.replace(pot, **args)
 
 
 def morse_cu(**kw) -> Potential:
