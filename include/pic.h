@@ -86,9 +86,23 @@ typedef struct pic_grid {
  *   PIC_POT_LJ     U(r) = D ((r0/r)^12 - 2 (r0/r)^6)
  *   PIC_POT_MORSE  U(r) = D (e^2 - 2e),  e = exp(-alpha (r - r0))
  * Both have their minimum -D at r0 (U'(r0) = 0), where the two branch
- * multipliers switch.  The reverse-mode entry points support PIC_POT_LJ. */
+ * multipliers switch.
+ * The assumed lattice (method section: the paper takes a cubic lattice and
+ * notes the construction adapts to hexagonal close packing):
+ *   PIC_LATTICE_CUBIC  one neighbour pair per evolved axis, eqs. (1)-(2);
+ *   PIC_LATTICE_HCP    the 12 neighbours of an ideal HCP crystal, c axis on
+ *                      the normal (last) axis, a basal axis on x, at
+ *                      d = 2^(1/6) rbar / (1 - q/2), q = 2^(1/6) grad(rbar).u
+ *                      clamped to +-g_clamp (eq. (2)'s midpoint rule along
+ *                      each neighbour direction u); force = sum of phi'(d) u.
+ *                      In 2D the unresolved basal axis carries no gradient and
+ *                      its force component is dropped.  Solid density sits at
+ *                      the potential minimum when r0 = 2^(1/6) n_solid^(-1/3).
+ * The reverse-mode entry points support PIC_POT_LJ on the cubic lattice. */
 #define PIC_POT_LJ 0
 #define PIC_POT_MORSE 1
+#define PIC_LATTICE_CUBIC 0
+#define PIC_LATTICE_HCP 1
 typedef struct pic_potential {
   double D;        /* well depth (dissociation energy), J */
   double r0;       /* equilibrium distance, m */
@@ -98,6 +112,7 @@ typedef struct pic_potential {
   double n_floor;  /* no force at densities n <= n_floor, m^-3 */
   double mass;     /* atomic mass, kg */
   int32_t kind;    /* PIC_POT_LJ or PIC_POT_MORSE */
+  int32_t lattice; /* PIC_LATTICE_CUBIC or PIC_LATTICE_HCP */
   double alpha;    /* Morse width, 1/m (> 0 for PIC_POT_MORSE; unused otherwise) */
 } pic_potential_t;
 

@@ -29,7 +29,7 @@ class pic_grid_t(C.Structure):
 class pic_potential_t(C.Structure):
     _fields_ = [("D", C.c_double), ("r0", C.c_double), ("s_rep", C.c_double), ("c_att", C.c_double),
                 ("g_clamp", C.c_double), ("n_floor", C.c_double), ("mass", C.c_double), ("kind", C.c_int32),
-                ("alpha", C.c_double)]
+                ("lattice", C.c_int32), ("alpha", C.c_double)]
 
 
 class pic_particles_t(C.Structure):
@@ -138,7 +138,7 @@ def grid_t(grid: W.Grid) -> pic_grid_t:
 
 def potential_t(pot: W.Potential) -> pic_potential_t:
     return pic_potential_t(pot.D, pot.r0, pot.s_rep, pot.c_att, pot.g_clamp, pot.n_floor, pot.mass,
-                           int(pot.kind), float(pot.alpha))
+                           int(pot.kind), int(pot.lattice), float(pot.alpha))
 
 
 def _ptr(t):

@@ -139,6 +139,7 @@ bool valid_potential(const pic_potential_t *pot) {
   if (!pot) return false;
   const pic_potential_t &P = *pot;
   if (P.kind != PIC_POT_LJ && P.kind != PIC_POT_MORSE) return false;
+  if (P.lattice != PIC_LATTICE_CUBIC && P.lattice != PIC_LATTICE_HCP) return false;
   if (P.kind == PIC_POT_MORSE && !(P.alpha > 0 && std::isfinite(P.alpha))) return false;
   return P.D > 0 && P.r0 > 0 && P.s_rep > 0 && P.c_att > 0 && P.g_clamp > 0 && P.g_clamp < 2 &&
          P.n_floor >= 0 && P.mass > 0 && std::isfinite(P.s_rep) && std::isfinite(P.c_att) &&
@@ -195,7 +196,7 @@ Geo make_geo(const pic_grid_t &g, const pic_potential_t &P, double dt, const Siz
 DiagC make_diag(const pic_grid_t &g, const pic_potential_t &P) {
   const double V = g.h[0] * g.h[1] * g.h[2];
   return DiagC{P.D, P.mass, 0.5 * P.mass, std::ldexp(1.0, -20), V, P.r0 * P.r0 * P.r0, P.s_rep, P.c_att,
-               P.kind, P.kind == PIC_POT_MORSE ? P.alpha * P.r0 : 0.0};
+               P.kind, P.kind == PIC_POT_MORSE ? P.alpha * P.r0 : 0.0, P.lattice};
 }
 
 }  // namespace
@@ -491,6 +492,7 @@ static int init_common(pic_ctx_t **out, const pic_grid_t *grids_in, int nslab, c
   c->P.kind = P.kind;
   c->P.mAl2 = P.kind == PIC_POT_MORSE ? (float)(P.alpha * P.r0 * M_LOG2E) : 0.0f;
   c->P.mA6 = P.kind == PIC_POT_MORSE ? (float)(P.alpha * P.r0 / 6.0) : 0.0f;
+  c->P.lattice = P.lattice;
   c->quad = gauss_legendre16();
   int pe = 0;
   for (int k = 0; k < nslab; ++k) {
@@ -1022,7 +1024,8 @@ int pic_push(pic_ctx_t *ctx, pic_particles_t *p, const float *force) {
 static int adjoint_common(pic_ctx_t *ctx, const pic_particles_t *p, const int64_t *node_w, const float *nbar_next,
                           const float *fbar, float *lam_x, float *lam_v, float *nbar, double *dtheta,
                           bool force_only, const char *what) {
-  if (ctx->pot.kind != PIC_POT_LJ) return fail(ctx, PIC_EINVAL, "reverse mode supports the Lennard-Jones potential only");
+  if (ctx->pot.kind != PIC_POT_LJ || ctx->pot.lattice != PIC_LATTICE_CUBIC)
+    return fail(ctx, PIC_EINVAL, "reverse mode supports the Lennard-Jones potential on the cubic lattice only");
   if (!node_w) return fail(ctx, PIC_EINVAL, "node_w is NULL");
   if (!nbar) return fail(ctx, PIC_EINVAL, "nbar is NULL");
   if (!dtheta) return fail(ctx, PIC_EINVAL, "dtheta is NULL");
@@ -1223,7 +1226,8 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
                         const void *record, size_t record_bytes, void *scratch, size_t scratch_bytes, float *lam_x,
                         float *lam_v, double *dtheta) {
   if (!ctx) return PIC_EINVAL;
-  if (ctx->pot.kind != PIC_POT_LJ) return fail(ctx, PIC_EINVAL, "reverse mode supports the Lennard-Jones potential only");
+  if (ctx->pot.kind != PIC_POT_LJ || ctx->pot.lattice != PIC_LATTICE_CUBIC)
+    return fail(ctx, PIC_EINVAL, "reverse mode supports the Lennard-Jones potential on the cubic lattice only");
   int rc = recorded_ok(ctx, p, nsteps, every);
   if (rc) return rc;
   const RecLayout R = rec_layout(ctx, nsteps, every);
@@ -1598,6 +1602,13 @@ struct Slab {
     if (!(n > pot.n_floor)) return 0.0;
     double rbar = std::cbrt(1.0 / n);
     double g = -G / (3.0 * n) * rbar;  // d rbar/dx = -(1/3) n^(-4/3) dn/dx
+    if (pot.lattice == PIC_LATTICE_HCP) {
+      // 3 neighbours at +sqrt(2/3) along the normal and 3 at -sqrt(2/3); the
+      // 6 basal neighbours add nothing along it
+      const double c = std::cbrt(std::sqrt(2.0)), sn = std::sqrt(2.0 / 3.0);
+      const double q = std::min(std::max(c * g * sn, -pot.g_clamp), pot.g_clamp);
+      return 3.0 * sn * (dphi(c * rbar / (1.0 - 0.5 * q)) - dphi(c * rbar / (1.0 + 0.5 * q)));
+    }
     g = std::min(std::max(g, -pot.g_clamp), pot.g_clamp);
     return dphi(rbar / (1.0 - 0.5 * g)) - dphi(rbar / (1.0 + 0.5 * g));
   }

@@ -40,6 +40,7 @@ struct Pot {
   int kind;        // pair potential: 0 Lennard-Jones eq. (3), 1 Morse
   float mAl2;      // Morse: alpha r0 log2(e)
   float mA6;       // Morse: alpha r0 / 6
+  int lattice;     // 0 cubic (eqs. (1)-(2) per axis), 1 hexagonal close-packed
 };
 
 // ---------------------------------------------------------------------------
@@ -175,15 +176,18 @@ __device__ __forceinline__ void centre_stencil(int i, float f, int &c0, float &t
 // M = s_rep for r < r0 (s > 1), c_att otherwise;  F = phi'(s+) - phi'(s-).
 // ---------------------------------------------------------------------------
 // Morse in the same units: r / r0 = 1/s, e = exp(-alpha r0 (1/s - 1)),
-// U'(r) / (12 D / r0) = (alpha r0 / 6) e (1 - e), U / D = e (e - 2).  The kind
-// is a kernel argument, so the branch is uniform across the wavefront.
+// U'(r) / (12 D / r0) = (alpha r0 / 6) e (1 - e), U / D = e (e - 2).  GEN
+// false compiles the Lennard-Jones cubic path alone (the kernels' default
+// instantiation); GEN true adds the runtime choice of potential and lattice
+// (kernel arguments, so the branches are uniform across the wavefront).
 __device__ __forceinline__ float morse_e(const Pot &P, float s) {
   return __builtin_amdgcn_exp2f(__builtin_fmaf(-P.mAl2, __builtin_amdgcn_rcpf(s), P.mAl2));
 }
 
+template <bool GEN = false>
 __device__ __forceinline__ float dphi_hat(const Pot &P, float s) {
   float v;
-  if (P.kind == 1) {
+  if (GEN && P.kind == 1) {
     const float e = morse_e(P, s);
     v = P.mA6 * __builtin_fmaf(-e, e, e);  // (alpha r0 / 6) (e - e^2)
   } else {
@@ -196,10 +200,11 @@ __device__ __forceinline__ float dphi_hat(const Pot &P, float s) {
   return (s > 1.0f ? P.s_rep : P.c_att) * v;
 }
 
+template <bool GEN = false>
 __device__ __forceinline__ float phi_hat(const Pot &P, float s) {
   // U / D; altered branches stay continuous at r0
   float u;
-  if (P.kind == 1) {
+  if (GEN && P.kind == 1) {
     const float e = morse_e(P, s);
     u = e * (e - 2.0f);
   } else {
@@ -210,7 +215,60 @@ __device__ __forceinline__ float phi_hat(const Pot &P, float s) {
   return s > 1.0f ? __builtin_fmaf(P.s_rep, u, P.s_rep - P.c_att) : P.c_att * u;
 }
 
+// Hexagonal close-packed neighbour k along grid direction v (weight w: the
+// number of the 12 neighbours with this in-plane direction): q_k = c g.v with
+// c = 2^(1/6), clamped; s = r0 / d = (q / c) (1 - q_k / 2).
 template <int ND>
+__device__ __forceinline__ void hcp_term(const Pot &P, float qc, const float g[3], float v0, float v1, float v2,
+                                         float w, float F[3], float &e, bool bond) {
+  float gu = g[0] * v0 + g[1] * v1;
+  if (ND == 3) gu = __builtin_fmaf(g[2], v2, gu);
+  float qk = fminf(fmaxf(1.12246204831f * gu, -P.gclamp), P.gclamp);
+  float s = qc * __builtin_fmaf(-0.5f, qk, 1.0f);
+  float f = w * dphi_hat<true>(P, s);
+  F[0] = __builtin_fmaf(f, v0, F[0]);
+  F[1] = __builtin_fmaf(f, v1, F[1]);
+  if (ND == 3) F[2] = __builtin_fmaf(f, v2, F[2]);
+  if (bond) e = __builtin_fmaf(0.5f * w, phi_hat<true>(P, s), e);
+}
+
+// The 12 neighbours in grid axes: 3D (basal 1, basal 2, c) = (x, y, z); 2D
+// (basal 1, c) = (x, y), the basal-2 axis unresolved, so neighbours that
+// differ only there merge (weights 2) and their out-of-plane forces cancel.
+// Rows: v0, v1, v2, weight.  A loop over the table (not unrolled) keeps the
+// register count of the kernels that carry this path next to the cubic one.
+static __constant__ float kHcp3[12][4] = {
+    {1.0f, 0.0f, 0.0f, 1.0f},
+    {0.5f, 0.866025403784439f, 0.0f, 1.0f},
+    {-0.5f, 0.866025403784439f, 0.0f, 1.0f},
+    {-1.0f, 0.0f, 0.0f, 1.0f},
+    {-0.5f, -0.866025403784439f, 0.0f, 1.0f},
+    {0.5f, -0.866025403784439f, 0.0f, 1.0f},
+    {0.5f, 0.288675134594813f, 0.816496580927726f, 1.0f},
+    {-0.5f, 0.288675134594813f, 0.816496580927726f, 1.0f},
+    {0.0f, -0.577350269189626f, 0.816496580927726f, 1.0f},
+    {0.5f, 0.288675134594813f, -0.816496580927726f, 1.0f},
+    {-0.5f, 0.288675134594813f, -0.816496580927726f, 1.0f},
+    {0.0f, -0.577350269189626f, -0.816496580927726f, 1.0f}};
+static __constant__ float kHcp2[10][4] = {
+    {1.0f, 0.0f, 0.0f, 1.0f},  {-1.0f, 0.0f, 0.0f, 1.0f},
+    {0.5f, 0.0f, 0.0f, 2.0f},  {-0.5f, 0.0f, 0.0f, 2.0f},
+    {0.5f, 0.816496580927726f, 0.0f, 1.0f},   {-0.5f, 0.816496580927726f, 0.0f, 1.0f},
+    {0.0f, 0.816496580927726f, 0.0f, 1.0f},   {0.5f, -0.816496580927726f, 0.0f, 1.0f},
+    {-0.5f, -0.816496580927726f, 0.0f, 1.0f}, {0.0f, -0.816496580927726f, 0.0f, 1.0f}};
+
+template <int ND>
+__device__ __forceinline__ void hcp_force(const Pot &P, float q, const float g[3], float F[3], float &e, bool bond) {
+  const float qc = q * 0.890898718140339f;  // q / 2^(1/6)
+  const int n = ND == 3 ? 12 : 10;
+#pragma unroll 1
+  for (int k = 0; k < n; ++k) {
+    const float *v = ND == 3 ? kHcp3[k] : kHcp2[k];
+    hcp_term<ND>(P, qc, g, v[0], v[1], v[2], v[3], F, e, bond);
+  }
+}
+
+template <int ND, bool GEN = false>
 __device__ __forceinline__ void pair_force(const Pot &P, float nh, const float G[3], float F[3],
                                            float *bond = nullptr) {
   F[0] = F[1] = F[2] = 0.0f;
@@ -218,6 +276,14 @@ __device__ __forceinline__ void pair_force(const Pot &P, float nh, const float G
   if (!(nh > P.nfloor)) return;
   float q = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(nh) * (1.0f / 3.0f));
   float rinv = __builtin_amdgcn_rcpf(nh * q);
+  if (GEN && P.lattice == 1) {
+    float g[3] = {0.0f, 0.0f, 0.0f}, e = 0.0f;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) g[d] = (G[d] * rinv) * (-1.0f / 3.0f);
+    hcp_force<ND>(P, q, g, F, e, bond != nullptr);
+    if (bond) *bond = e;
+    return;
+  }
   float e = 0.0f;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
@@ -226,8 +292,8 @@ __device__ __forceinline__ void pair_force(const Pot &P, float nh, const float G
     float hq = 0.5f * q * g;
     float sp = q - hq;  // +d neighbour (farther when rbar grows towards +d)
     float sm = q + hq;  // -d neighbour
-    F[d] = dphi_hat(P, sp) - dphi_hat(P, sm);
-    if (bond) e += 0.5f * (phi_hat(P, sp) + phi_hat(P, sm));
+    F[d] = dphi_hat<GEN>(P, sp) - dphi_hat<GEN>(P, sm);
+    if (bond) e += 0.5f * (phi_hat<GEN>(P, sp) + phi_hat<GEN>(P, sm));
   }
   if (bond) *bond = e;
 }

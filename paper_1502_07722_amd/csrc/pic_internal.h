@@ -12,8 +12,9 @@ namespace pic {
 // FP64 constants of the diagnostics (SI).
 struct DiagC {
   double D, mass, half_m, wunit, vcell, r0cube, s_rep, c_att;
-  int kind;   // pair potential: 0 Lennard-Jones (closed-form energy density), 1 Morse
-  double mA;  // Morse: alpha r0
+  int kind;     // pair potential: 0 Lennard-Jones (closed-form energy density), 1 Morse
+  double mA;    // Morse: alpha r0
+  int lattice;  // 0 cubic, 1 hexagonal close-packed
 };
 
 // 16-point Gauss-Legendre rule on [-1, 1] (the Morse energy density is an

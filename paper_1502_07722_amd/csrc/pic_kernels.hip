@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(256) k_force(Geo g, Pot P, int64_t n, const in
     decode_cell<ND>(g, c, idx);
     float nh, Gp[3];
     gather_global<ND>(g, dens, G, idx, f, nh, Gp);
-    pair_force<ND>(P, nh, Gp, F);
+    pair_force<ND, true>(P, nh, Gp, F);
   }
 #pragma unroll
   for (int d = 0; d < ND; ++d) force[(int64_t)d * n + p] = F[d] * P.beta;
@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(256) k_force_push(Geo g, Pot P, DiagC dc, int6
       decode_cell<ND>(g, c, idx);
       float nh, Gp[3], Fh[3], bond = 0.0f;
       gather_global<ND>(g, dens, G, idx, f, nh, Gp);
-      pair_force<ND>(P, nh, Gp, Fh, DIAG ? &bond : nullptr);
+      pair_force<ND, true>(P, nh, Gp, Fh, DIAG ? &bond : nullptr);
       float F[3] = {Fh[0] * P.beta, Fh[1] * P.beta, ND == 3 ? Fh[2] * P.beta : 0.0f};
       float v[3] = {vel[p], vel[n + p], vel[2 * n + p]};
       if (DIAG) {
@@ -288,15 +288,18 @@ __global__ void __launch_bounds__(256) k_force_push(Geo g, Pot P, DiagC dc, int6
   if (DIAG) block_reduce_store<6>(acc, partial + (int64_t)blockIdx.x * 8);
 }
 
-// Chemical potential mu / D of the Morse potential at reduced density x > 0:
-// rho = x^(-1/3) = rbar / r0, mu = M (U - rbar U') / D plus the altered
-// branch's constant above x = 1 (M = c_att below, s_rep above).
+// Chemical potential mu / D of the Morse potential at reduced density x > 0.
+// Cubic: rho = x^(-1/3) = rbar / r0, mu = M (U - rbar U') / D plus the altered
+// branch's constant above x = 1 (M = c_att below, s_rep above).  Hexagonal:
+// twice that at the neighbour distance a = 2^(1/6) rbar, kink at x = sqrt(2).
 __device__ __forceinline__ double mu_morse(const DiagC &dc, double x) {
-  const double rho = pow(x, -1.0 / 3.0);
+  const bool hcp = dc.lattice == 1;
+  const double rho = (hcp ? 1.122462048309373 : 1.0) * pow(x, -1.0 / 3.0);
   const double e = exp(-dc.mA * (rho - 1.0));
   const double u = e * (e - 2.0);                 // U / D
   const double du = 2.0 * dc.mA * e * (1.0 - e);  // r0 U'(r) / D
-  return x <= 1.0 ? dc.c_att * (u - rho * du) : dc.s_rep * (u - rho * du) + (dc.s_rep - dc.c_att);
+  const double m = (hcp ? 2.0 : 1.0);
+  return rho >= 1.0 ? m * dc.c_att * (u - rho * du) : m * (dc.s_rep * (u - rho * du) + (dc.s_rep - dc.c_att));
 }
 
 __device__ __forceinline__ double gauss16(const DiagC &dc, const Quad16 &q, double a, double b) {
@@ -311,15 +314,19 @@ __device__ __forceinline__ double gauss16(const DiagC &dc, const Quad16 &q, doub
 // Morse: the integral of mu from 0 to x (Gauss-Legendre, split at x = 1 where
 // mu has a kink).
 __device__ __forceinline__ double eps_hat(const DiagC &dc, const Quad16 &q, double x) {
+  const bool hcp = dc.lattice == 1;
+  const double xk = hcp ? 1.4142135623730951 : 1.0;  // where the neighbour distance is r0
   if (dc.kind == 1) {
     if (!(x > 0.0)) return 0.0;
-    double e = gauss16(dc, q, 0.0, fmin(x, 1.0));
-    if (x > 1.0) e += gauss16(dc, q, 1.0, x);
+    double e = gauss16(dc, q, 0.0, fmin(x, xk));
+    if (x > xk) e += gauss16(dc, q, xk, x);
     return e;
   }
-  auto lj = [](double y) { return (13.0 / 5.0) * y * y * y * y * y - (14.0 / 3.0) * y * y * y; };
-  if (x <= 1.0) return dc.c_att * lj(x);
-  return dc.c_att * lj(1.0) + dc.s_rep * (lj(x) - lj(1.0)) + (dc.s_rep - dc.c_att) * (x - 1.0);
+  // L-J: cubic e(x) = 13/5 x^5 - 14/3 x^3; hexagonal 13/10 x^5 - 14/3 x^3
+  const double c5 = hcp ? 13.0 / 10.0 : 13.0 / 5.0, m = hcp ? 2.0 : 1.0;
+  auto lj = [c5](double y) { return c5 * y * y * y * y * y - (14.0 / 3.0) * y * y * y; };
+  if (x <= xk) return dc.c_att * lj(x);
+  return dc.c_att * lj(xk) + dc.s_rep * (lj(x) - lj(xk)) + m * (dc.s_rep - dc.c_att) * (x - xk);
 }
 
 template <int ND>

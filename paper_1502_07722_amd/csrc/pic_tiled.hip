@@ -229,7 +229,7 @@ __device__ __forceinline__ void stage_window(const Geo &g, const Window &w, cons
       c[k] = dens[win_node<ND>(w, m0 + (k & 1), m1 + ((k >> 1) & 1), ND == 3 ? m2 + ((k >> 2) & 1) : 0)];
     centre_gradient<ND>(g, c, G);
 #pragma unroll
-    for (int d = 0; d < ND; ++d) Gs[m * ND + d] = G[d];
+    for (int d = 0; d < ND; ++d) Gs[d * w.nC + m] = G[d];  // one plane per component
   }
   __syncthreads();
 }
@@ -337,13 +337,13 @@ __device__ __forceinline__ void load_state(const StoreView &sv, int p, bool live
 // particle, given its gathered density and gradient.
 // OUT: the next state goes to the view's output arrays (a recorded
 // trajectory); otherwise in place.
-template <int ND, bool DIAG, bool INTERIOR, bool OUT>
+template <int ND, bool DIAG, bool INTERIOR, bool OUT, bool GEN>
 __device__ __forceinline__ void advance_particle(const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
                                                  const StoreView &sv, int p, int pc, int idx[3], float f[3],
                                                  float v[3], int W, float nh, const float Gp[3], uint32_t tq[8],
                                                  uint32_t &err, double acc6[6]) {
   float Fh[3], bond = 0.0f;
-  pair_force<ND>(P, nh, Gp, Fh, DIAG ? &bond : nullptr);
+  pair_force<ND, GEN>(P, nh, Gp, Fh, DIAG ? &bond : nullptr);
   float F[3] = {Fh[0] * P.beta, Fh[1] * P.beta, ND == 3 ? Fh[2] * P.beta : 0.0f};
   if (DIAG) {
     double wgt = (double)W * dc.wunit, vo2 = 0.0, vn2 = 0.0;
@@ -571,7 +571,7 @@ __device__ __forceinline__ bool item_window(const Geo &g, const Window &w, const
 // The particles of one item whose cells lie in the tile window (drifters are
 // appended to the global list).  Loads for the next round are issued before
 // the current round is computed.
-template <int ND, bool DIAG, bool INTERIOR, bool OUT>
+template <int ND, bool DIAG, bool INTERIOR, bool OUT, bool GEN>
 __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
                                          const StoreView &sv, const Item &it, const Window &w, const float *dens,
                                          const float *Gs, unsigned long long *acc,
@@ -604,19 +604,15 @@ __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC
       for (int k = 0; k < (1 << ND); ++k) {
         const int m =
             win_centre<ND>(w, c0[0] + (k & 1), c0[1] + ((k >> 1) & 1), ND == 3 ? c0[2] + ((k >> 2) & 1) : 0);
-        if (ND == 2) {
-          const float2 gg = *reinterpret_cast<const float2 *>(&Gs[2 * m]);
-          vv[0][k] = gg.x;
-          vv[1][k] = gg.y;
-        } else {
+        // component planes: the x-neighbour centres m, m + 1 are adjacent words
+        // (one two-address LDS read per component and corner pair)
 #pragma unroll
-          for (int d = 0; d < ND; ++d) vv[d][k] = Gs[m * ND + d];
-        }
+        for (int d = 0; d < ND; ++d) vv[d][k] = Gs[d * w.nC + m];
       }
 #pragma unroll
       for (int d = 0; d < ND; ++d) Gp[d] = interp<ND>(vv[d], t);
       uint32_t tq[8];
-      advance_particle<ND, DIAG, INTERIOR, OUT>(g, P, dc, tg, sv, p, cur.pc, idx, cur.f, cur.v, cur.W, nh, Gp, tq,
+      advance_particle<ND, DIAG, INTERIOR, OUT, GEN>(g, P, dc, tg, sv, p, cur.pc, idx, cur.f, cur.v, cur.W, nh, Gp, tq,
                                            e_all, acc6);
       // a sub-cell move keeps the new cell inside the deposit window
       if (item_window<ND, INTERIOR>(g, w, idx, 0, 2, l)) {
@@ -638,7 +634,7 @@ __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC
 // Persistent: a fixed grid pulls work items (chunks of one tile of one slab)
 // from an atomic counter until the step's items are done.  Every block also
 // clears its share of the node buffer two steps ahead.
-template <int ND, bool DIAG, bool OUT>
+template <int ND, bool DIAG, bool OUT, bool GEN>
 __global__ void __launch_bounds__(256) k_step_tiled(Pot P, DiagC dc, Batch b, Store s, Store o,
                                                     const Item *__restrict__ items,
                                                     const int *__restrict__ num_items,
@@ -678,9 +674,9 @@ __global__ void __launch_bounds__(256) k_step_tiled(Pot P, DiagC dc, Batch b, St
     for (int d = 0; d < ND; ++d) interior = interior && w.o[d] >= 0 && w.o[d] + w.wn[d] <= g.n[d] + 1;
     double acc6[6] = {0, 0, 0, 0, 0, 0};
     if (interior)
-      run_item<ND, DIAG, true, OUT>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dr.list, dr.count, e_all, acc6);
+      run_item<ND, DIAG, true, OUT, GEN>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dr.list, dr.count, e_all, acc6);
     else
-      run_item<ND, DIAG, false, OUT>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dr.list, dr.count, e_all, acc6);
+      run_item<ND, DIAG, false, OUT, GEN>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dr.list, dr.count, e_all, acc6);
     __syncthreads();
     flush_window<ND>(g, w, acc, Nn);
     if (DIAG) block_reduce_store<6>(acc6, partial + (int64_t)bi * 8);
@@ -691,7 +687,7 @@ __global__ void __launch_bounds__(256) k_step_tiled(Pot P, DiagC dc, Batch b, St
 
 // Drifters (particles outside their tile window since the last binning):
 // the same cycle through the global node sums of their slab.
-template <int ND, bool DIAG, bool OUT>
+template <int ND, bool DIAG, bool OUT, bool GEN>
 __global__ void __launch_bounds__(256) k_outliers(Pot P, DiagC dc, Batch b, Store s, Store o, Drift dr,
                                                   const long long *__restrict__ Ncur,
                                                   unsigned long long *__restrict__ Nnext,
@@ -713,7 +709,8 @@ __global__ void __launch_bounds__(256) k_outliers(Pot P, DiagC dc, Batch b, Stor
     gather_nodes_global<ND>(g, Ncur + sd.node_off, idx, q.f, nh, Gp);
     uint32_t tq[8];
     double acc6[6] = {0, 0, 0, 0, 0, 0};
-    advance_particle<ND, DIAG, false, OUT>(g, P, dc, tg, sv, p, q.pc, idx, q.f, q.v, q.W, nh, Gp, tq, e_all, acc6);
+    advance_particle<ND, DIAG, false, OUT, GEN>(g, P, dc, tg, sv, p, q.pc, idx, q.f, q.v, q.W, nh, Gp, tq, e_all,
+                                                acc6);
     deposit_global<ND>(g, Nnext + sd.node_off, idx, tq);
     if (DIAG)
 #pragma unroll
@@ -1277,15 +1274,23 @@ void launch_step_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P
   const size_t lds = window_lds_bytes(tg, ndim);
   unsigned long long *nn = (unsigned long long *)Nnext;
   const bool out = s.pc != o.pc;
-  if (out)
-    PIC_ND(ndim, (k_step_tiled<ND, false, true><<<grid, 256, lds, st>>>(P, dc, b, s, o, bb.items, bb.num_items, Ncur,
-                                                                          nn, Nclear, dr, partial, err)));
-  else if (diag)
-    PIC_ND(ndim, (k_step_tiled<ND, true, false><<<grid, 256, lds, st>>>(P, dc, b, s, o, bb.items, bb.num_items, Ncur,
-                                                                          nn, Nclear, dr, partial, err)));
-  else
-    PIC_ND(ndim, (k_step_tiled<ND, false, false><<<grid, 256, lds, st>>>(P, dc, b, s, o, bb.items, bb.num_items, Ncur,
-                                                                           nn, Nclear, dr, partial, err)));
+  // GEN: the Morse potential or the hexagonal lattice (runtime choice); the
+  // Lennard-Jones cubic step compiles without either
+  const bool gen = P.kind != 0 || P.lattice != 0;
+#define PIC_STEP(DG, OT, GN)                                                                                      \
+  PIC_ND(ndim, (k_step_tiled<ND, DG, OT, GN><<<grid, 256, lds, st>>>(P, dc, b, s, o, bb.items, bb.num_items, Ncur, \
+                                                                     nn, Nclear, dr, partial, err)))
+  if (out) {
+    if (gen) PIC_STEP(false, true, true);
+    else PIC_STEP(false, true, false);
+  } else if (diag) {
+    if (gen) PIC_STEP(true, false, true);
+    else PIC_STEP(true, false, false);
+  } else {
+    if (gen) PIC_STEP(false, false, true);
+    else PIC_STEP(false, false, false);
+  }
+#undef PIC_STEP
 }
 
 void launch_drifters(hipStream_t st, int ndim, const Pot &P, const DiagC &dc, const Batch &b, const Store &s,
@@ -1293,13 +1298,20 @@ void launch_drifters(hipStream_t st, int ndim, const Pot &P, const DiagC &dc, co
                      bool diag, uint32_t *err) {
   unsigned long long *nn = (unsigned long long *)Nnext;
   const bool out = s.pc != o.pc;
-  if (out)
-    PIC_ND(ndim, (k_outliers<ND, false, true><<<kDriftBlocks, 256, 0, st>>>(P, dc, b, s, o, dr, Ncur, nn, dacc, err)));
-  else if (diag)
-    PIC_ND(ndim, (k_outliers<ND, true, false><<<kDriftBlocks, 256, 0, st>>>(P, dc, b, s, o, dr, Ncur, nn, dacc, err)));
-  else
-    PIC_ND(ndim,
-           (k_outliers<ND, false, false><<<kDriftBlocks, 256, 0, st>>>(P, dc, b, s, o, dr, Ncur, nn, dacc, err)));
+  const bool gen = P.kind != 0 || P.lattice != 0;
+#define PIC_OUTL(DG, OT, GN) \
+  PIC_ND(ndim, (k_outliers<ND, DG, OT, GN><<<kDriftBlocks, 256, 0, st>>>(P, dc, b, s, o, dr, Ncur, nn, dacc, err)))
+  if (out) {
+    if (gen) PIC_OUTL(false, true, true);
+    else PIC_OUTL(false, true, false);
+  } else if (diag) {
+    if (gen) PIC_OUTL(true, false, true);
+    else PIC_OUTL(true, false, false);
+  } else {
+    if (gen) PIC_OUTL(false, false, true);
+    else PIC_OUTL(false, false, false);
+  }
+#undef PIC_OUTL
 }
 
 void launch_reduce_diag_slab(hipStream_t st, const double *part_p, const int *item_start, int tile_lo, int tile_hi,
@@ -1365,8 +1377,8 @@ int step_kernel_blocks_per_cu(int ndim, const TileGeo &tg) {
   int nb = 0;
   const size_t lds = window_lds_bytes(tg, ndim);
   hipError_t e;
-  if (ndim == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_tiled<2, false, false>, 256, lds);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_tiled<3, false, false>, 256, lds);
+  if (ndim == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_tiled<2, false, false, false>, 256, lds);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_tiled<3, false, false, false>, 256, lds);
   return e == hipSuccess && nb > 0 ? nb : 4;
 }
 
