@@ -294,11 +294,12 @@ def measure_crater(ctx, wl, stream, log_fn=log, calls=20):
             "y_s": y_s, "beam_d": beam_d}
 
 
-def run_slab(name, steps, warmup, log_fn=log, morse=False):
+def run_slab(name, steps, warmup, log_fn=log, variant="lj"):
     """One single-slab workload through pic_step: (result, workload, potential,
     diagnostics).  The timed region is one pic_step call of `steps` steps
-    with diagnostics every 100 steps, particles resident in HBM.  morse: the
-    Morse pair potential (copper) instead of eq. (3)."""
+    with diagnostics every 100 steps, particles resident in HBM.  variant:
+    "lj" (eq. (3), cubic lattice), "morse" (the Morse copper potential) or
+    "hcp" (eq. (3) on the hexagonal close-packed lattice)."""
     import numpy as np
     import torch
     from paper_1502_07722_amd import binding as B
@@ -307,7 +308,7 @@ def run_slab(name, steps, warmup, log_fn=log, morse=False):
     t0 = time.perf_counter()
     wl = W.WORKLOADS[name]()
     log_fn(f"generated {wl.name}: {wl.parts.n} particles in {time.perf_counter() - t0:.1f} s")
-    base = W.morse_cu() if morse else wl.pot
+    base = {"lj": wl.pot, "morse": W.morse_cu(), "hcp": W.hcp()}[variant]
     c_att, _ = B.pic_calibrate_catt(wl.grid, base, W.N_SOLID, 8)
     pot = dataclasses.replace(base, c_att=c_att)
     N = wl.parts.n
@@ -359,8 +360,9 @@ def run_slab(name, steps, warmup, log_fn=log, morse=False):
                 "bytes_per_node": 16, "avg_launch_ms": avg_s * 1e3,
                 "phases_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in timing.items() if isinstance(v, tuple)},
                 "drifters_last_step": timing.get("drifters_last"), "items_last_step": timing.get("items_last")}
-    res = {"workload": wl.name + ("_morse" if morse else ""), "particles": N, "value": N * steps / elapsed,
-           "ms_per_step": elapsed / steps * 1e3, "potential": "morse" if morse else "lennard-jones",
+    res = {"workload": wl.name + ("" if variant == "lj" else "_" + variant), "particles": N,
+           "value": N * steps / elapsed, "ms_per_step": elapsed / steps * 1e3,
+           "potential": {"lj": "lennard-jones, cubic", "morse": "morse, cubic", "hcp": "lennard-jones, hcp"}[variant],
            "elapsed_s": elapsed, "roofline": roofline, "c_att": c_att, "tiling": tuning,
            "ms_per_step_with_events": elapsed_events / steps * 1e3, "crater": crater}
     del ctx, dp, start
@@ -475,12 +477,15 @@ def main():
             out["configs"][name] = {k: r[k] for k in ("workload", "particles", "value", "ms_per_step")}
             out["configs"][name]["roofline_frac"] = r["roofline"]["frac"]
             out["configs"][name]["roofline_achieved_gbs"] = r["roofline"]["achieved"]
-        # the same large slab with the Morse pair potential (the paper names it as an alternative)
-        r, _, _, _ = run_slab("large", *DEFAULTS["large_morse"], morse=True)
-        out["configs"]["large_morse"] = {k: r[k] for k in ("workload", "particles", "value", "ms_per_step",
-                                                           "potential", "c_att")}
-        out["configs"]["large_morse"]["roofline_frac"] = r["roofline"]["frac"]
-        out["configs"]["large_morse"]["roofline_achieved_gbs"] = r["roofline"]["achieved"]
+        # the same large slab with the Morse pair potential and on the hexagonal
+        # lattice (the paper names both as alternatives)
+        for variant in ("morse", "hcp"):
+            r, _, _, _ = run_slab("large", *DEFAULTS["large_morse"], variant=variant)
+            key = "large_" + variant
+            out["configs"][key] = {k: r[k] for k in ("workload", "particles", "value", "ms_per_step", "potential",
+                                                      "c_att")}
+            out["configs"][key]["roofline_frac"] = r["roofline"]["frac"]
+            out["configs"][key]["roofline_achieved_gbs"] = r["roofline"]["achieved"]
     if not args.no_sweep and args.workload == "large":
         out["sweep"] = run_sweep(*DEFAULTS["sweep"])
     if not args.no_adjoint and args.workload == "large":

@@ -195,7 +195,7 @@ int pic_step(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, pic_diag_t *dia
  *   tile        tile edge in cells, a power of two (2D 8..32, 3D 4..8);
  *   halo        cells a particle may drift out of its tile between binnings
  *               before it takes the slower global path (1..4);
- *   chunk       most particles per work item (1024..32768);
+ *   chunk       most particles per work item (512..32768);
  *   sort_every  re-bin particles by tile every this many steps; 0 = never;
  *               -1 = adaptive (default): every 48 steps the drifter count of
  *               the previous check is read back without stalling, and the
@@ -275,7 +275,7 @@ int pic_get_tiling(pic_ctx_t *ctx, int32_t *tile, int32_t *halo, int32_t *chunk,
 int pic_set_graph(pic_ctx_t *ctx, int32_t on);
 
 /* Autotuner: probes tile edge x chunk candidates (tile 8, 16, 32 in 2D and
- * 4, 8 in 3D; chunk 1024 to 16384; halo 2 in 2D, 1 in 3D; re-binning policy
+ * 4, 8 in 3D; chunk 512 to 16384; halo 2 in 2D, 1 in 3D; re-binning policy
  * unchanged) on the caller's particles for probe_steps steps each, launched
  * step by step (no graph capture inside a probe), timed with events, and
  * keeps the fastest tiling.  The

@@ -17,7 +17,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kDiagCap = 1024;        // device diag entries buffered between host copies
-constexpr int kMinChunk = 1024;
+constexpr int kMinChunk = 512;
 constexpr int kMaxChunk = 32768;
 constexpr int kDriftCheck = 48;       // adaptive re-binning looks at the drifter count this often
 constexpr int kDriftFraction = 2048;  // and re-bins once drifters exceed n / kDriftFraction
@@ -1374,7 +1374,7 @@ int pic_autotune(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t probe_ste
   const int nd = ctx->ndim;
   const int halo = nd == 2 ? 2 : 1;
   const int lts[3] = {nd == 2 ? 3 : 2, nd == 2 ? 4 : 3, nd == 2 ? 5 : 3};
-  const int chunks[5] = {1024, 2048, 4096, 8192, 16384};
+  const int chunks[6] = {512, 1024, 2048, 4096, 8192, 16384};
   const int old_lt = ctx->lt, old_h = ctx->halo, old_c = ctx->chunk, old_s = ctx->sort_every;
   const bool old_timing = ctx->timing, old_graph = ctx->use_graph;
   ctx->timing = false;
