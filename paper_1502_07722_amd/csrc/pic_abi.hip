@@ -146,6 +146,33 @@ bool valid_potential(const pic_potential_t *pot) {
          std::isfinite(P.D) && std::isfinite(P.r0) && std::isfinite(P.mass);
 }
 
+// Work items of a tiling at a given chunk: sum over tiles of ceil(count / chunk).
+int64_t items_at(const std::vector<int> &counts, int chunk) {
+  int64_t n = 0;
+  for (int c : counts) n += (c + chunk - 1) / chunk;
+  return n;
+}
+
+// Chunks (multiples of 64 in [kMinChunk, kMaxChunk]) whose item count is at
+// most r whole rounds of the persistent grid and fills at least 90 % of the
+// last round, r = 1..8: the smallest such chunk per r.
+std::vector<int> balanced_chunks(const std::vector<int> &counts, int slots) {
+  std::vector<int> out;
+  if (slots < 1) return out;
+  for (int r = 1; r <= 8; ++r) {
+    int lo = kMinChunk, hi = kMaxChunk;
+    if (items_at(counts, hi) > (int64_t)r * slots) continue;
+    while (hi - lo > 64) {  // smallest chunk with items <= r * slots
+      const int mid = (lo + hi) / 2 / 64 * 64;
+      if (mid <= lo) break;
+      (items_at(counts, mid) <= (int64_t)r * slots ? hi : lo) = mid;
+    }
+    const int64_t n = items_at(counts, hi);
+    if (n * 10 >= (int64_t)r * slots * 9 && n > (int64_t)(r - 1) * slots) out.push_back(hi);
+  }
+  return out;
+}
+
 // Nodes and weights of the 16-point Gauss-Legendre rule: the roots of P_16
 // by Newton's method from the usual cosine estimates, w = 2 / ((1 - x^2) P'^2).
 Quad16 gauss_legendre16() {
@@ -1384,7 +1411,9 @@ int pic_autotune(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t probe_ste
   pic_particles_t *pp = const_cast<pic_particles_t *>(parts);
   for (int i = 0; i < 3; ++i) {
     if (i > 0 && lts[i] == lts[i - 1]) continue;
-    for (int c : chunks) {
+    std::vector<int> cand(chunks, chunks + 6);
+    for (size_t ci = 0; ci < cand.size(); ++ci) {
+      const int c = cand[ci];
       if (apply_tiling(ctx, lts[i], halo, c, old_s)) continue;  // does not fit this grid
       DiagSink ds{ctx, nullptr, 0};
       float ms = 0.f;
@@ -1396,6 +1425,16 @@ int pic_autotune(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t probe_ste
         best = ms;
         best_lt = lts[i];
         best_c = c;
+      }
+      if (ci == 0) {
+        // chunks whose item count fills whole rounds of the persistent grid,
+        // from this tiling's particle counts per tile
+        std::vector<int> counts(ctx->ntiles);
+        rc = hip_check(ctx, hipMemcpy(counts.data(), ctx->bb.counts, sizeof(int) * counts.size(),
+                                      hipMemcpyDeviceToHost), "tile counts");
+        if (rc) break;
+        for (int extra : balanced_chunks(counts, ctx->grid_blocks))
+          if (std::find(cand.begin(), cand.end(), extra) == cand.end()) cand.push_back(extra);
       }
     }
     if (rc) break;

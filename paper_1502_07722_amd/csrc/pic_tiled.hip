@@ -519,8 +519,12 @@ __global__ void __launch_bounds__(256) k_tile_items(Batch b, int chunk, const in
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= b.ntiles) return;
   const int slab = find_slab(b.tile_offs, b.nslab, t);
-  int c = counts[t], s = starts[t], i0 = item_start[t];
-  for (int k = 0; k * chunk < c; ++k) items[i0 + k] = Item{t, s + k * chunk, s + min(c, (k + 1) * chunk), slab};
+  // ceil(c / chunk) items of near-equal size (each at most chunk): equal items
+  // let the persistent grid finish its rounds together
+  const int c = counts[t], s = starts[t], i0 = item_start[t];
+  const int m = (c + chunk - 1) / chunk;
+  for (int k = 0; k < m; ++k)
+    items[i0 + k] = Item{t, s + (int)((long long)k * c / m), s + (int)((long long)(k + 1) * c / m), slab};
 }
 
 template <int ND>
