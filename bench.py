@@ -252,6 +252,26 @@ def run_adjoint(log_fn=log, every=20, steps=None):
             "J": J, "dJ_dtheta": {k: float(v) for k, v in zip(A.THETA_KEYS, gth)}, "dJ_dfluence": gF}
 
 
+def copy_ceiling(nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (read + write bytes per second) of a plain
+    1 GiB copy on this GPU: the practical HBM ceiling beside the 8 TB/s peak."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    gbs = 2 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def measure_crater(ctx, wl, stream, log_fn=log, calls=20):
     """Crater measurement (density map with the 1 % cut-off, column sums,
     depth, width, eq. 5) on the node sums of the last pic_step, timed with
@@ -447,6 +467,10 @@ def main():
     res, wl, pot, diags = run_slab(args.workload, steps, warmup)
     value, N, nd, c_att = res["value"], wl.parts.n, wl.grid.ndim, res["c_att"]
     roofline = res["roofline"]
+    ceiling = copy_ceiling()
+    log(f"device copy ceiling {ceiling:.0f} GB/s")
+    roofline["copy_ceiling_gbs"] = ceiling
+    roofline["frac_of_copy"] = roofline["achieved"] / ceiling if roofline["achieved"] else None
     elapsed = res["elapsed_s"]
     out = {
         "metric": "particle-steps/s (deposit+force+push)",
