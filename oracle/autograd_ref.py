@@ -18,7 +18,9 @@ Steps, in the paper's order (Sec. 2, Fig. 1):
             ghosts on reflecting walls: normal component negated)
   eq. (1)   rbar = n^(-1/3), g = d rbar/dx = -(1/3) G n^(-4/3), clamped
   eq. (2)   r(+d) = rbar / (1 - g/2), r(-d) = rbar / (1 + g/2)
-  eq. (3)   F = Phi'(r+) - Phi'(r-), Phi' = s_rep U' (r < r0), c_att U' (r >= r0)
+  eq. (3)   F = Phi'(r+) - Phi'(r-), Phi' = s_rep U' (r < r0), c_att U' (r >= r0);
+            U is Lennard-Jones, or Morse D (e^2 - 2e), e = exp(-alpha (r - r0))
+            (the paper's method takes any pair potential; only U' changes)
   push      leapfrog: v += F/m dt, x += v dt, carry / wrap / mirror
 Functional: J = sum_p w_p sigmoid((y_p - y_s) / tau) on the normal axis.
 """
@@ -180,15 +182,20 @@ def gather(geo: Geometry, dens, G, idx, f):
 
 
 def pair_force(theta: dict, n_floor: float, g_clamp: float, n_p, Gp):
-    """Eq. (1)-(3) per atom, in newtons; zero where n <= n_floor."""
+    """Eq. (1)-(3) per atom, in newtons; zero where n <= n_floor.  theta holds
+    D, r0, s_rep, c_att and, for the Morse potential, alpha."""
     D, r0, s_rep, c_att = theta["D"], theta["r0"], theta["s_rep"], theta["c_att"]
     live = n_p > n_floor
     n_safe = torch.where(live, n_p, torch.ones_like(n_p) * max(n_floor, 1.0))
     rbar = n_safe ** (-1.0 / 3.0)
 
     def dphi(r):
-        x6 = (r0 / r) ** 6
-        du = -(12.0 * D / r) * (x6 * x6 - x6)
+        if "alpha" in theta:  # Morse: U' = 2 D alpha (e - e^2)
+            e = torch.exp(-theta["alpha"] * (r - r0))
+            du = 2.0 * D * theta["alpha"] * (e - e * e)
+        else:
+            x6 = (r0 / r) ** 6
+            du = -(12.0 * D / r) * (x6 * x6 - x6)
         return torch.where(r < r0, s_rep * du, c_att * du)
 
     F = []
@@ -271,13 +278,15 @@ def crater_objective(grid, pot, dt, nsteps, cell, off, v_thermal, xi, sigma_ref,
     sigma proportional to sqrt(F); v(-1/2) = v0 - F(x0)/m dt/2.  Returns (J,
     theta dict, fluence tensor, final state, initial offsets); theta and
     fluence (and the initial offsets with offsets_grad) are leaves with grad."""
+    if getattr(pot, "lattice", 0) != 0:
+        raise ValueError("the differentiable reference covers the cubic neighbour geometry only")
     geo, idx, f = unpack(grid, cell, off)
     if offsets_grad:
         f = [t.clone().requires_grad_(True) for t in f]
     f0 = f
     if theta is None:
-        theta = {k: torch.tensor(float(getattr(pot, k)), dtype=torch.float64, requires_grad=True)
-                 for k in ("D", "r0", "s_rep", "c_att")}
+        keys = ("D", "r0", "s_rep", "c_att") + (("alpha",) if pot.kind == 1 else ())
+        theta = {k: torch.tensor(float(getattr(pot, k)), dtype=torch.float64, requires_grad=True) for k in keys}
     if fluence is None:
         fluence = torch.tensor(float(fluence_ref), dtype=torch.float64, requires_grad=True)
     w = torch.as_tensor(wq, dtype=torch.float64) * WUNIT

@@ -130,3 +130,38 @@ def test_reference_offset_gradients_match_oracle_fd():
         # three to four orders smaller than the normal one and carry the FD's
         # rounding noise (about 1e-12 |J| / h) and kinks of other particles
         assert np.abs(ag - fd).max() <= 1e-5 * np.linalg.norm(fd) + 4e-12 * abs(Jv) / h, (i, ag, fd)
+
+
+# The Morse potential (the method takes any pair potential): the reference's
+# forward cycle against the C oracle, and its gradients -- now including the
+# Morse width alpha -- against central differences of the C oracle.
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_reference_morse_forward_and_gradients_match_oracle(case):
+    grid, p, dt, y_s, tau = CASES[case]()
+    nsteps = 30
+    pot = W.morse_cu(c_att=0.43)
+    J, th, Fl, (idx, f, v), _ = R.crater_objective(grid, pot, dt, nsteps, p.cell, p.off, p.v_thermal, p.xi,
+                                                   p.sigma, FREF, p.wq, y_s, tau)
+    Jc = _oracle_J(grid, p, pot, dt, nsteps, y_s, tau)
+    assert abs(J.item() - Jc) <= 1e-13 * abs(Jc)
+    J.backward()
+    assert set(th) == {"D", "r0", "s_rep", "c_att", "alpha"}
+    for k in ("D", "s_rep", "c_att", "alpha"):
+        fd = _fd(lambda x: _oracle_J(grid, p, dataclasses.replace(pot, **{k: x}), dt, nsteps, y_s, tau),
+                 getattr(pot, k), 1e-3)
+        assert abs(th[k].grad.item() - fd) <= 2e-6 * abs(fd), (k, th[k].grad.item(), fd)
+    fd = _fd(lambda x: _oracle_J(grid, p, pot, dt, nsteps, y_s, tau, fluence=x), FREF, 1e-3)
+    assert abs(Fl.grad.item() - fd) <= 2e-6 * abs(fd), (Fl.grad.item(), fd)
+    # r0 with equal branch multipliers (no kink where a distance crosses r0)
+    pot1 = W.morse_cu(c_att=1.0)
+    J1, th1, _, _, _ = R.crater_objective(grid, pot1, dt, nsteps, p.cell, p.off, p.v_thermal, p.xi, p.sigma,
+                                          FREF, p.wq, y_s, tau)
+    J1.backward()
+    fd = _fd(lambda x: _oracle_J(grid, p, dataclasses.replace(pot1, r0=x), dt, nsteps, y_s, tau), pot1.r0, 1e-4)
+    assert abs(th1["r0"].grad.item() - fd) <= 2e-6 * abs(fd), (th1["r0"].grad.item(), fd)
+
+
+def test_reference_refuses_hexagonal_geometry():
+    grid, p, dt, y_s, tau = _case2d()
+    with pytest.raises(ValueError):
+        R.crater_objective(grid, W.hcp(), dt, 2, p.cell, p.off, p.v_thermal, p.xi, p.sigma, FREF, p.wq, y_s, tau)
