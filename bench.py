@@ -170,12 +170,13 @@ def run_sweep(steps, warmup, log_fn=log):
                                   "beam_d_fit_m": _finite(a_fit)}}
 
 
-def run_adjoint(log_fn=log, every=20, steps=None):
+def run_adjoint(log_fn=log, every=20, steps=None, potential="lj"):
     """The 3D adjoint workload: 128^3 cells of 2 nm, slab in the lower 64
     layers, 8 ppc, 1.5 J/cm^2, 400 steps.  Forward = pic_step over the 400
     steps from v(-1/2).  Gradient = torch.autograd through the crater
     functional: recorded forward (checkpoints every 20 steps) + reverse sweep
-    (segment recompute + reverse steps) + the start and heating terms."""
+    (segment recompute + reverse steps) + the start and heating terms.
+    potential: "lj" (eq. (3)) or "morse" (Morse copper, alpha a parameter)."""
     import numpy as np
     import torch
     from paper_1502_07722_amd import autograd as A
@@ -186,8 +187,9 @@ def run_adjoint(log_fn=log, every=20, steps=None):
     wl = W.cfg_adjoint_3d()
     g, p = wl.grid, wl.parts
     log_fn(f"adjoint workload {wl.name}: {p.n} particles, generated in {time.perf_counter() - t0:.1f} s")
-    c_att, _ = B.pic_calibrate_catt(g, wl.pot, W.N_SOLID, 8)
-    pot = W.Potential(c_att=c_att)
+    base = wl.pot if potential == "lj" else W.morse_cu()
+    c_att, _ = B.pic_calibrate_catt(g, base, W.N_SOLID, 8)
+    pot = dataclasses.replace(base, c_att=c_att)
     nsteps = wl.steps if steps is None else steps
     dev = torch.device("cuda:0")
     cell = torch.from_numpy(p.cell).to(dev)
@@ -242,7 +244,8 @@ def run_adjoint(log_fn=log, every=20, steps=None):
     del ctx
     torch.cuda.empty_cache()
     return {"workload": f"{wl.name}: 128^3 cells, slab 64 layers, 8 ppc, 1.5 J/cm^2, {nsteps} steps, "
-                        f"checkpoint every {every}",
+                        f"checkpoint every {every}" + ("" if potential == "lj" else ", Morse potential"),
+            "potential": "lennard-jones" if potential == "lj" else "morse", "c_att": c_att,
             "particles": int(p.n), "steps": nsteps, "checkpoint_every": every,
             "tiling": tuning, "forward_s": t_fwd, "recorded_forward_s": t_rec, "backward_s": t_bwd,
             "adjoint_over_forward": t_bwd / t_fwd, "gradient_over_forward": (t_rec + t_bwd) / t_fwd,
@@ -421,6 +424,7 @@ def main():
 
     if args.workload == "adjoint":
         res = run_adjoint(steps=args.steps)
+        res["morse"] = run_adjoint(steps=args.steps, potential="morse")
         out = {"metric": f"adjoint time / forward time ({res['steps']} steps, checkpoint every 20)",
                "value": res["adjoint_over_forward"], "unit": "ratio", "n_gpus": 1, "steps": res["steps"],
                "warmup": 1, "ms_per_step": res["backward_s"] / res["steps"] * 1e3, "higher_is_better": False,
@@ -514,6 +518,7 @@ def main():
         out["sweep"] = run_sweep(*DEFAULTS["sweep"])
     if not args.no_adjoint and args.workload == "large":
         out["adjoint"] = run_adjoint()
+        out["adjoint"]["morse"] = run_adjoint(potential="morse")
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, pot)

@@ -312,8 +312,13 @@ int pic_calibrate_catt(const pic_grid_t *grid, const pic_potential_t *pot, doubl
  *   lam_v  [3][n]     dJ/dv, s/m;
  *   nbar   [nodes]    dJ/d(n r0^3): cotangent of the node density in units of
  *                     r0^-3;
- *   dtheta [4]        device doubles, ACCUMULATED (+=): dJ/dD (1/J), dJ/dr0
- *                     (1/m), dJ/ds_rep, dJ/dc_att.
+ *   dtheta [5]        device doubles, ACCUMULATED (+=): dJ/dD (1/J), dJ/dr0
+ *                     (1/m), dJ/ds_rep, dJ/dc_att, dJ/dalpha (m; the Morse
+ *                     width, PIC_POT_MORSE only: slot 4 gets +0 under
+ *                     Lennard-Jones).  The derivatives in D, r0 and alpha
+ *                     hold the other parameters, c_att among them, fixed.
+ * Both pair potentials (any pair potential enters eq. (3) through U' alone);
+ * the cubic neighbour geometry only (PIC_EINVAL for PIC_LATTICE_HCP).
  * Single-slab contexts only.  Stream-ordered and asynchronous; device errors
  * (invalid particles) are reported by the next pic_sync or pic_step.
  * Scatters to nodes use float atomics, so nbar, lam_x and dtheta carry
@@ -365,7 +370,8 @@ int pic_deposit_vjp(pic_ctx_t *ctx, const pic_particles_t *state, const float *n
  *      dJ/dv(nsteps - 1/2) (caller order; J must not depend on the final
  *      node densities).
  * Out: lam_x = complete dJ/d(offset) of the initial state, lam_v =
- *      dJ/dv(-1/2); dtheta (device, 4 doubles) += dJ/d(D, r0, s_rep, c_att).
+ *      dJ/dv(-1/2); dtheta (device, 5 doubles) += dJ/d(D, r0, s_rep, c_att,
+ *      alpha).
  * p supplies the particle count (its arrays are not read).  The context, its
  * tiling, nsteps, every and record must be those of the pic_forward_record
  * call, otherwise PIC_EINVAL.  Single-slab contexts on the tiled path only.

@@ -13,8 +13,9 @@ its reverse runs in the library's kernels):
               per-step calls (pic_deposit / pic_force / pic_push forward,
               pic_adjoint_step backward).
 
-theta is a float64 tensor (D, r0, s_rep, c_att) holding the context's
-potential; it is there to receive dJ/dtheta.  Cell indices are integer
+theta is a float64 tensor (D, r0, s_rep, c_att, alpha) holding the
+context's potential (alpha: the Morse width; its gradient is zero under
+Lennard-Jones); it is there to receive dJ/dtheta.  Cell indices are integer
 outputs without gradient.
 
 crater_objective() composes them into the paper's experiment (Sec. 3): a
@@ -29,7 +30,7 @@ import torch
 
 from . import binding as B
 
-THETA_KEYS = ("D", "r0", "s_rep", "c_att")
+THETA_KEYS = ("D", "r0", "s_rep", "c_att", "alpha")
 
 
 def theta_of(pot, device="cuda"):
@@ -39,7 +40,7 @@ def theta_of(pot, device="cuda"):
 def _check_theta(ctx: B.Context, theta):
     want = theta_of(ctx.pot, "cpu")
     if not torch.equal(theta.detach().cpu(), want):
-        raise ValueError("theta must hold the context's potential (D, r0, s_rep, c_att)")
+        raise ValueError("theta must hold the context's potential (D, r0, s_rep, c_att, alpha)")
 
 
 class Force(torch.autograd.Function):
@@ -97,7 +98,7 @@ class Trajectory(torch.autograd.Function):
         if isinstance(rec, dict):
             dth = ctx.pic_backward_record(dp, rec, lam_x, lam_v)
         else:
-            dth = torch.zeros(4, dtype=torch.float64, device=dp.off.device)
+            dth = torch.zeros(B.NTHETA, dtype=torch.float64, device=dp.off.device)
             nbar_next = None
             for j in range(len(rec) - 1, -1, -1):
                 s0 = j * every

@@ -65,6 +65,7 @@ class pic_crater_t(C.Structure):
 
 
 CRATER_FIELDS = ("depth", "width", "t_min", "t_max", "f_th", "ncols")
+NTHETA = 5  # reverse-mode parameters: D, r0, s_rep, c_att, alpha
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())")
@@ -405,8 +406,8 @@ class Context:
             nbar = torch.empty(self.nnodes, dtype=torch.float32, device=self.device)
         self._need(nbar, self.nnodes, torch.float32, "nbar")
         if dtheta is None:
-            dtheta = torch.zeros(4, dtype=torch.float64, device=self.device)
-        self._need(dtheta, 4, torch.float64, "dtheta")
+            dtheta = torch.zeros(NTHETA, dtype=torch.float64, device=self.device)
+        self._need(dtheta, NTHETA, torch.float64, "dtheta")
         return nbar, dtheta
 
     def pic_adjoint_step(self, state: DeviceParticles, node_w, nbar_next, lam_x, lam_v, nbar=None, dtheta=None):
@@ -465,8 +466,8 @@ class Context:
         self._need(lam_x, self.grid.ndim * parts.n, torch.float32, "lam_x")
         self._need(lam_v, 3 * parts.n, torch.float32, "lam_v")
         if dtheta is None:
-            dtheta = torch.zeros(4, dtype=torch.float64, device=self.device)
-        self._need(dtheta, 4, torch.float64, "dtheta")
+            dtheta = torch.zeros(NTHETA, dtype=torch.float64, device=self.device)
+        self._need(dtheta, NTHETA, torch.float64, "dtheta")
         nbytes = lib.pic_backward_bytes(self.ctx, record["every"])
         scratch, sptr = self._aligned(nbytes)
         s = parts.struct()

@@ -1046,13 +1046,22 @@ int pic_push(pic_ctx_t *ctx, pic_particles_t *p, const float *force) {
 // ---------------------------------------------------------------------------
 // Reverse mode on caller arrays
 // ---------------------------------------------------------------------------
+// Slot scales of the parameter partials: the kernels accumulate D dJ/dD,
+// r0 dJ/dr0, dJ/ds_rep, dJ/dc_att and alpha dJ/dalpha (zero under
+// Lennard-Jones, whose alpha is unused).
+static ThetaScale theta_scale(const pic_ctx_t *ctx) {
+  const pic_potential_t &P = ctx->pot;
+  return ThetaScale{{1.0 / P.D, 1.0 / P.r0, 1.0, 1.0, P.kind == PIC_POT_MORSE ? 1.0 / P.alpha : 0.0}};
+}
+
+static const char *kAdjointLattice = "reverse mode supports the cubic neighbour geometry only";
+
 // Shared tail of the two particle VJPs: nbar gets the gradient transpose, the
 // per-block parameter partials are summed into dtheta.
 static int adjoint_common(pic_ctx_t *ctx, const pic_particles_t *p, const int64_t *node_w, const float *nbar_next,
                           const float *fbar, float *lam_x, float *lam_v, float *nbar, double *dtheta,
                           bool force_only, const char *what) {
-  if (ctx->pot.kind != PIC_POT_LJ || ctx->pot.lattice != PIC_LATTICE_CUBIC)
-    return fail(ctx, PIC_EINVAL, "reverse mode supports the Lennard-Jones potential on the cubic lattice only");
+  if (ctx->pot.lattice != PIC_LATTICE_CUBIC) return fail(ctx, PIC_EINVAL, kAdjointLattice);
   if (!node_w) return fail(ctx, PIC_EINVAL, "node_w is NULL");
   if (!nbar) return fail(ctx, PIC_EINVAL, "nbar is NULL");
   if (!dtheta) return fail(ctx, PIC_EINVAL, "dtheta is NULL");
@@ -1065,7 +1074,7 @@ static int adjoint_common(pic_ctx_t *ctx, const pic_particles_t *p, const int64_
   const int nb = launch_adjoint(ctx->stream, g, ctx->P, ptrs(p), ctx->dens, ctx->G, nbar_next, fbar, lam_x, lam_v,
                                 nbar, ctx->Gbar, ctx->partial, ctx->err, force_only);
   launch_gradient_vjp(ctx->stream, g, ctx->Gbar, nbar);
-  if (nb > 0) launch_reduce_theta(ctx->stream, ctx->partial, nb, 1.0 / ctx->pot.D, 1.0 / ctx->pot.r0, dtheta);
+  if (nb > 0) launch_reduce_theta(ctx->stream, ctx->partial, nb, theta_scale(ctx), dtheta);
   return check_launch(ctx, what);
 }
 
@@ -1253,8 +1262,7 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
                         const void *record, size_t record_bytes, void *scratch, size_t scratch_bytes, float *lam_x,
                         float *lam_v, double *dtheta) {
   if (!ctx) return PIC_EINVAL;
-  if (ctx->pot.kind != PIC_POT_LJ || ctx->pot.lattice != PIC_LATTICE_CUBIC)
-    return fail(ctx, PIC_EINVAL, "reverse mode supports the Lennard-Jones potential on the cubic lattice only");
+  if (ctx->pot.lattice != PIC_LATTICE_CUBIC) return fail(ctx, PIC_EINVAL, kAdjointLattice);
   int rc = recorded_ok(ctx, p, nsteps, every);
   if (rc) return rc;
   const RecLayout R = rec_layout(ctx, nsteps, every);
@@ -1355,8 +1363,7 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
     }
   }
   // parameter terms summed over the sweep (fixed order over the items)
-  launch_reduce_theta(ctx->stream, ctx->partial, (int)max_items, 1.0 / ctx->pot.D, 1.0 / ctx->pot.r0, dtheta,
-                      ctx->dacc);
+  launch_reduce_theta(ctx->stream, ctx->partial, (int)max_items, theta_scale(ctx), dtheta, ctx->dacc);
   // deposit term of the initial positions, back to the caller's order
   const Store ref0 = ref_of(0);
   launch_deposit_vjp_store(ctx->stream, nd, b, state_at(ctx, rec + R.state, ref0), nbar_next, lx);

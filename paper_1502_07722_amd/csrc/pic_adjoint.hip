@@ -5,7 +5,8 @@
 // Cotangents carried per particle: lam_x = dJ/d(offset) per axis (per cell of
 // displacement) and lam_v = dJ/dv (s/m).  Per node: nbar = dJ/d(n r0^3), the
 // cotangent of the reduced node density.  Per cell centre (scratch): Gbar =
-// dJ/d(dn/dx r0^4).  Parameters theta = (D, r0, s_rep, c_att).
+// dJ/d(dn/dx r0^4).  Parameters theta = (D, r0, s_rep, c_att, alpha); alpha,
+// the Morse width, has a zero cotangent under Lennard-Jones.
 //
 // One reverse step n (forward: x(n), v(n-1/2) -> x(n+1), v(n+1/2)):
 //   1. recompute the particle's forward step from x(n) (bit-identical to the
@@ -42,7 +43,7 @@ __global__ void __launch_bounds__(256) k_adjoint(Geo g, Pot P, int64_t n, const 
                                                  float *__restrict__ Gbar, double *__restrict__ partial,
                                                  uint32_t *__restrict__ err) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double thd[4] = {0, 0, 0, 0};
+  double thd[5] = {0, 0, 0, 0, 0};
   if (p < n) {
     int c = cell[p];
     float f[3] = {off[p], off[n + p], ND == 3 ? off[2 * n + p] : 0.0f};
@@ -61,7 +62,8 @@ __global__ void __launch_bounds__(256) k_adjoint(Geo g, Pot P, int64_t n, const 
         const float v[3] = {vel[p], vel[n + p], vel[2 * n + p]};
         float ln[3] = {lam_x[p], lam_x[n + p], ND == 3 ? lam_x[2 * n + p] : 0.0f};
         float lv[3] = {lam_v[p], lam_v[n + p], lam_v[2 * n + p]};
-        e = reverse_push<ND>(g, P, idx, f, v, nbar_next ? wq[p] : 0, gs.nh, gs.Gp, nbar_next, ln, lv, lf, mu);
+        e = reverse_push<ND, true>(g, P, idx, f, v, nbar_next ? wq[p] : 0, gs.nh, gs.Gp, nbar_next, ln, lv, lf,
+                                   mu);
         if (e) atomicOr(err, e);
 #pragma unroll
         for (int d = 0; d < 3; ++d) lam_v[(int64_t)d * n + p] = lv[d];
@@ -72,16 +74,16 @@ __global__ void __launch_bounds__(256) k_adjoint(Geo g, Pot P, int64_t n, const 
           lf[d] = lam_x[(int64_t)d * n + p];
         }
       }
-      float an, aG[3], th[4] = {0.f, 0.f, 0.f, 0.f};
-      pair_force_vjp<ND>(P, gs.nh, gs.Gp, mu, an, aG, th);
+      float an, aG[3], th[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+      pair_force_vjp<ND, true>(P, gs.nh, gs.Gp, mu, an, aG, th);
       gather_vjp<ND>(g, idx, f, gs, an, aG, lf, nbar, Gbar);
 #pragma unroll
       for (int d = 0; d < ND; ++d) lam_x[(int64_t)d * n + p] = lf[d];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) thd[i] = th[i];
+      for (int i = 0; i < 5; ++i) thd[i] = th[i];
     }
   }
-  block_reduce_store<4>(thd, partial + (int64_t)blockIdx.x * 8);
+  block_reduce_store<5>(thd, partial + (int64_t)blockIdx.x * 8);
 }
 
 // nbar_k += sum over the cells c touching node k of gam_d Gbar_c[d] (+1 if k is
@@ -148,26 +150,26 @@ __global__ void k_fillf(float *__restrict__ a, int64_t n) {
   if (i < n) a[i] = 0.0f;
 }
 
-// Fixed-order sum of the per-block parameter partials into dtheta (+=).
-__global__ void __launch_bounds__(256) k_reduce_theta(const double *__restrict__ partial, int nblocks,
-                                                      double s0, double s1, double *__restrict__ dtheta,
-                                                      double *__restrict__ extra) {
-  __shared__ double red[4][256];
-  double acc[4] = {0, 0, 0, 0};
+// Fixed-order sum of the per-block parameter partials into dtheta (+=);
+// scale[i] turns slot i into dJ/dtheta_i (1/D, 1/r0, 1, 1, 1/alpha or 0).
+__global__ void __launch_bounds__(256) k_reduce_theta(const double *__restrict__ partial, int nblocks, ThetaScale sc,
+                                                      double *__restrict__ dtheta, double *__restrict__ extra) {
+  __shared__ double red[kTheta][256];
+  double acc[kTheta] = {0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) acc[i] += partial[(int64_t)b * 8 + i];
+    for (int i = 0; i < kTheta; ++i) acc[i] += partial[(int64_t)b * 8 + i];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) red[i][threadIdx.x] = acc[i];
+  for (int i = 0; i < kTheta; ++i) red[i][threadIdx.x] = acc[i];
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + s];
+      for (int i = 0; i < kTheta; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x < 4) {
-    const double scale = threadIdx.x == 0 ? s0 : (threadIdx.x == 1 ? s1 : 1.0);
+  if (threadIdx.x < kTheta) {
+    const double scale = sc.s[threadIdx.x];
     double v = red[threadIdx.x][0];
     if (extra) {
       v += extra[threadIdx.x];
@@ -222,9 +224,9 @@ void launch_deposit_vjp(hipStream_t st, const Geo &g, const PartPtrs &p, const f
                        lam_x, err);
 }
 
-void launch_reduce_theta(hipStream_t st, const double *partial, int nblocks, double s0, double s1, double *dtheta,
+void launch_reduce_theta(hipStream_t st, const double *partial, int nblocks, const ThetaScale &sc, double *dtheta,
                          double *extra) {
-  hipLaunchKernelGGL(k_reduce_theta, dim3(1), dim3(256), 0, st, partial, nblocks, s0, s1, dtheta, extra);
+  hipLaunchKernelGGL(k_reduce_theta, dim3(1), dim3(256), 0, st, partial, nblocks, sc, dtheta, extra);
 }
 
 }  // namespace pic

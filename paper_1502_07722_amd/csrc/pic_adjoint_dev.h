@@ -72,16 +72,25 @@ __device__ __forceinline__ int corner_node(const Geo &g, const int idx[3], int k
 
 // Eq. (1)-(3) reversed.  mu: cotangent of the reduced force Fh per axis.
 // Returns the cotangents of the gathered reduced density (an) and gradient
-// (aG), and adds the parameter terms: th[0] = sum mu Fh (-> dJ/dD = th0 / D),
-// th[1] = sum mu (s dFh/ds - Fh) (-> dJ/dr0 = th1 / r0), th[2] = dJ/ds_rep,
-// th[3] = dJ/dc_att.  The clamp of g and the density floor have zero
-// derivative where they act.
-template <int ND>
+// (aG), and adds the parameter terms as logarithmic derivatives of the
+// force F = (12 D / r0) Fh taken at fixed physical distances, in units of
+// 12 D / r0: th[0] = sum mu Fh (-> dJ/dD = th0 / D), th[1] = sum mu r0 dF/dr0
+// (-> dJ/dr0 = th1 / r0), th[2] = dJ/ds_rep, th[3] = dJ/dc_att, th[4] = sum mu
+// alpha dF/dalpha (-> dJ/dalpha = th4 / alpha; Morse only).  The clamp of g
+// and the density floor have zero derivative where they act.
+//
+// Per neighbour, with s = r0 / r and the branch multiplier M fixed, r0 dF/dr0
+// = M (s k' + A dk/dA) - Fh.  The Lennard-Jones k = s^7 - s^13 has no A; the
+// Morse k = (A/6)(E - E^2), E = exp(A (1 - 1/s)), A = alpha r0: with t =
+// (A^2/6)(E - 2E^2), k' = t / s^2, A dk/dA = k + t (1 - 1/s), so s k' +
+// A dk/dA = k + t.
+template <int ND, bool GEN = false>
 __device__ __forceinline__ void pair_force_vjp(const Pot &P, float nh, const float G[3], const float mu[3],
-                                               float &an, float aG[3], float th[4]) {
+                                               float &an, float aG[3], float th[5]) {
   an = 0.0f;
   aG[0] = aG[1] = aG[2] = 0.0f;
   if (!(nh > P.nfloor)) return;
+  const bool morse = GEN && P.kind == 1;
   const float q = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(nh) * (1.0f / 3.0f));
   const float rinv = __builtin_amdgcn_rcpf(nh * q);
   const float inv_n = __builtin_amdgcn_rcpf(nh);
@@ -93,16 +102,29 @@ __device__ __forceinline__ void pair_force_vjp(const Pot &P, float nh, const flo
     const bool free_g = graw > -P.gclamp && graw < P.gclamp;
     const float hq = 0.5f * q * g;
     const float sp = q - hq, sm = q + hq;
-    float k_p, dk_p, k_m, dk_m;
-    {
-      const float s2 = sp * sp, s6 = s2 * s2 * s2, s7 = s6 * sp, s12 = s6 * s6;
-      k_p = __builtin_fmaf(-s7, s6, s7);
-      dk_p = __builtin_fmaf(-13.0f, s12, 7.0f * s6);
-    }
-    {
-      const float s2 = sm * sm, s6 = s2 * s2 * s2, s7 = s6 * sm, s12 = s6 * s6;
-      k_m = __builtin_fmaf(-s7, s6, s7);
-      dk_m = __builtin_fmaf(-13.0f, s12, 7.0f * s6);
+    float k_p, dk_p, k_m, dk_m, t_p = 0.0f, t_m = 0.0f, ip = 0.0f, im = 0.0f;
+    if (morse) {
+      const float A2 = 6.0f * P.mA6 * P.mA6;  // A^2 / 6
+      const float Ep = morse_e(P, sp), Em = morse_e(P, sm);
+      ip = __builtin_amdgcn_rcpf(sp);
+      im = __builtin_amdgcn_rcpf(sm);
+      k_p = P.mA6 * __builtin_fmaf(-Ep, Ep, Ep);
+      k_m = P.mA6 * __builtin_fmaf(-Em, Em, Em);
+      t_p = A2 * __builtin_fmaf(-2.0f * Ep, Ep, Ep);
+      t_m = A2 * __builtin_fmaf(-2.0f * Em, Em, Em);
+      dk_p = t_p * ip * ip;
+      dk_m = t_m * im * im;
+    } else {
+      {
+        const float s2 = sp * sp, s6 = s2 * s2 * s2, s7 = s6 * sp, s12 = s6 * s6;
+        k_p = __builtin_fmaf(-s7, s6, s7);
+        dk_p = __builtin_fmaf(-13.0f, s12, 7.0f * s6);
+      }
+      {
+        const float s2 = sm * sm, s6 = s2 * s2 * s2, s7 = s6 * sm, s12 = s6 * s6;
+        k_m = __builtin_fmaf(-s7, s6, s7);
+        dk_m = __builtin_fmaf(-13.0f, s12, 7.0f * s6);
+      }
     }
     const bool rp = sp > 1.0f, rm = sm > 1.0f;  // repulsive branch (r < r0)
     const float Mp = rp ? P.s_rep : P.c_att, Mm = rm ? P.s_rep : P.c_att;
@@ -116,7 +138,14 @@ __device__ __forceinline__ void pair_force_vjp(const Pot &P, float nh, const flo
     an += m * (dFdq * dqdn + dFdg * dgdn);
     aG[d] = m * dFdg * dgdG;
     th[0] += m * Fh;
-    th[1] += m * (A * sp - B * sm - Fh);
+    if (morse) {
+      // r0: M (k + t) per side; alpha: M A dk/dA = M (k + t - t / s)
+      const float tp = Mp * t_p, tm = Mm * t_m;
+      th[1] += m * (tp - tm);
+      th[4] += m * (Fh + (tp - tm) - (tp * ip - tm * im));
+    } else {
+      th[1] += m * (A * sp - B * sm - Fh);
+    }
     th[2] += m * ((rp ? k_p : 0.0f) - (rm ? k_m : 0.0f));
     th[3] += m * ((rp ? 0.0f : k_p) - (rm ? 0.0f : k_m));
   }
@@ -241,11 +270,11 @@ struct PushRecord {
   float sgn[3];
 };
 
-template <int ND>
+template <int ND, bool GEN = false>
 __device__ __forceinline__ uint32_t recompute_push(const Geo &g, const Pot &P, const int idx[3], const float f[3],
                                                    const float v[3], float nh, const float Gp[3], PushRecord &r) {
   float Fh[3];
-  pair_force<ND>(P, nh, Gp, Fh);
+  pair_force<ND, GEN>(P, nh, Gp, Fh);
   const float F[3] = {Fh[0] * P.beta, Fh[1] * P.beta, ND == 3 ? Fh[2] * P.beta : 0.0f};
   float vpre[3], v2[3] = {v[0], v[1], v[2]};
 #pragma unroll
@@ -275,13 +304,13 @@ __device__ __forceinline__ void reverse_drift_kick(const Geo &g, const Pot &P, c
 }
 
 // Both, with the deposit term of step n+1 taken from the global nbar_next.
-template <int ND>
+template <int ND, bool GEN = false>
 __device__ __forceinline__ uint32_t reverse_push(const Geo &g, const Pot &P, const int idx[3], const float f[3],
                                                  const float v[3], int W, float nh, const float Gp[3],
                                                  const float *__restrict__ nbar_next, float ln[3], float lv[3],
                                                  float lf[3], float mu[3]) {
   PushRecord r;
-  const uint32_t e = recompute_push<ND>(g, P, idx, f, v, nh, Gp, r);
+  const uint32_t e = recompute_push<ND, GEN>(g, P, idx, f, v, nh, Gp, r);
   if (nbar_next) deposit_term<ND>(g, nbar_next, r.idx2, r.f2, W, ln);
   reverse_drift_kick<ND>(g, P, r, ln, lv, lf, mu);
   return e;

@@ -169,9 +169,14 @@ int launch_adjoint(hipStream_t st, const Geo &g, const Pot &P, const PartPtrs &p
 void launch_gradient_vjp(hipStream_t st, const Geo &g, const float *Gbar, float *nbar);
 void launch_deposit_vjp(hipStream_t st, const Geo &g, const PartPtrs &p, const float *nbar, float *lam_x,
                         uint32_t *err);
-// dtheta[0..3] += scale * (sum of the block partials + extra[0..3]); extra
-// (nullable) is cleared
-void launch_reduce_theta(hipStream_t st, const double *partial, int nblocks, double s0, double s1, double *dtheta,
+// Parameters of the reverse mode: D, r0, s_rep, c_att, alpha (Morse width).
+constexpr int kTheta = 5;
+struct ThetaScale {
+  double s[kTheta];
+};
+// dtheta[i] += s[i] * (sum of the block partials + extra[i]), i < kTheta;
+// extra (nullable) is cleared
+void launch_reduce_theta(hipStream_t st, const double *partial, int nblocks, const ThetaScale &sc, double *dtheta,
                          double *extra = nullptr);
 
 }  // namespace pic

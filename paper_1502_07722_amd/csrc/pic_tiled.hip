@@ -882,12 +882,13 @@ struct GlobalNext {  // kfac * nbar of step n+1 at a (real) node
 // window), the forward step is recomputed, the deposit term of step n+1 is
 // read at the new position through `next` when has_next, and the cotangents
 // of the gathered density and gradient go back to the block: a3 (node
-// cotangents of the block, first node at frame coordinates B).
-template <int ND, class Dens, class Next>
+// cotangents of the block, first node at frame coordinates B).  GEN: the
+// potential chosen at run time (Lennard-Jones or Morse).
+template <int ND, bool GEN, class Dens, class Next>
 __device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P, const int idx[3], const int l[3],
                                                      const PState &q, const Dens &dens, bool has_next,
                                                      const Next &next, float ln[3], float lvv[3], float lf[3],
-                                                     float th[4], int B[3], float t[3], float &an, float aG[3]) {
+                                                     float th[5], int B[3], float t[3], float &an, float aG[3]) {
   constexpr int K3 = ND == 2 ? 9 : 27;
   float cr[8];
 #pragma unroll
@@ -924,7 +925,7 @@ __device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P,
     }
   }
   PushRecord r;
-  const uint32_t e_push = recompute_push<ND>(g, P, idx, q.f, q.v, nh, Gp, r);
+  const uint32_t e_push = recompute_push<ND, GEN>(g, P, idx, q.f, q.v, nh, Gp, r);
   if (has_next) {
     int l2[3] = {0, 0, 0};
 #pragma unroll
@@ -944,7 +945,7 @@ __device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P,
   }
   float mu[3] = {0.f, 0.f, 0.f};
   reverse_drift_kick<ND>(g, P, r, ln, lvv, lf, mu);
-  pair_force_vjp<ND>(P, nh, Gp, mu, an, aG, th);
+  pair_force_vjp<ND, GEN>(P, nh, Gp, mu, an, aG, th);
 #pragma unroll
   for (int e = 0; e < ND; ++e) lf[e] = __builtin_fmaf(an, dn[e], lf[e]);
 #pragma unroll
@@ -1015,7 +1016,7 @@ __device__ __forceinline__ void block_reduce_add(double v[NF], double *__restric
   }
 }
 
-template <int ND, bool MAXONLY>
+template <int ND, bool MAXONLY, bool GEN>
 __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, const Item *__restrict__ items,
                                                        const int *__restrict__ num_items,
                                                        const long long *__restrict__ Ncur,
@@ -1061,7 +1062,7 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
   const int cap = (int)s.cap;
   const StoreView sv = view_of(s, s);
   uint32_t e_all = 0;
-  float thf[4] = {0.f, 0.f, 0.f, 0.f};  // this thread's parameter terms (chunk / 256 particles at most)
+  float thf[5] = {0.f, 0.f, 0.f, 0.f, 0.f};  // this thread's parameter terms (chunk / 256 particles at most)
   for (int base = it.start; base < it.end; base += blockDim.x) {
     const int p = base + (int)threadIdx.x;
     const bool live = p < it.end;
@@ -1073,16 +1074,16 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
     const bool inside = live && in_window<ND>(g, w, idx, 1, 3, l);
     if (!MAXONLY) wave_append(dlist, dcount, p, live && !inside);  // the global path, in a kernel of its own
     if (inside) {
-      float lf[3] = {0.f, 0.f, 0.f}, th[4] = {0.f, 0.f, 0.f, 0.f}, t[3], an, aG[3];
+      float lf[3] = {0.f, 0.f, 0.f}, th[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, t[3], an, aG[3];
       int B[3];
-      e_all |= adjoint_on_block<ND>(g, P, idx, l, q, dens, nbn != nullptr, next, ln, lvv, lf, th, B, t, an, aG);
+      e_all |= adjoint_on_block<ND, GEN>(g, P, idx, l, q, dens, nbn != nullptr, next, ln, lvv, lf, th, B, t, an, aG);
       if (!MAXONLY) {  // the particle's cotangents and parameter terms, before its node block
 #pragma unroll
         for (int d = 0; d < ND; ++d) lx[d * cap + p] = lf[d];
 #pragma unroll
         for (int d = 0; d < 3; ++d) lv[d * cap + p] = lvv[d];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) thf[i] += th[i];
+        for (int i = 0; i < 5; ++i) thf[i] += th[i];
       }
       float a3[K3];
       block_cotangents<ND>(g, l, B, q.f, t, an, aG, a3);
@@ -1119,14 +1120,14 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
               (float)((double)iv * from_fix));
   }
   if (e_all) atomicOr(err, e_all);
-  double thd[4] = {thf[0], thf[1], thf[2], thf[3]};
-  block_reduce_add<4>(thd, partial + (int64_t)blockIdx.x * 8);  // accumulates over the sweep
+  double thd[5] = {thf[0], thf[1], thf[2], thf[3], thf[4]};
+  block_reduce_add<5>(thd, partial + (int64_t)blockIdx.x * 8);  // accumulates over the sweep
 }
 
 // The reverse step of the particles outside their window: the same block
 // computation on the global densities (folded like the window), scatters as
-// global float atomics; parameter terms into dacc[0..3].
-template <int ND>
+// global float atomics; parameter terms into dacc[0..4].
+template <int ND, bool GEN>
 __global__ void __launch_bounds__(256) k_adjoint_drifters(Pot P, Batch b, Store s, const int *__restrict__ dlist,
                                                           const int *__restrict__ dcount,
                                                           const float *__restrict__ dens_g,
@@ -1150,9 +1151,10 @@ __global__ void __launch_bounds__(256) k_adjoint_drifters(Pot P, Batch b, Store 
     unpack_cell<ND>(sd.tg, q.pc, idx);
     const GlobalDens<ND> dens{dens_g + sd.node_off, &g};
     const GlobalNext<ND> next{nbar_next ? nbar_next + sd.node_off : nullptr, &g};
-    float lf[3] = {0.f, 0.f, 0.f}, th[4] = {0.f, 0.f, 0.f, 0.f}, t[3], an, aG[3], a3[K3];
+    float lf[3] = {0.f, 0.f, 0.f}, th[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, t[3], an, aG[3], a3[K3];
     int B[3];
-    e_all |= adjoint_on_block<ND>(g, P, idx, idx, q, dens, nbar_next != nullptr, next, ln, lvv, lf, th, B, t, an, aG);
+    e_all |= adjoint_on_block<ND, GEN>(g, P, idx, idx, q, dens, nbar_next != nullptr, next, ln, lvv, lf, th, B, t, an,
+                                       aG);
     block_cotangents<ND>(g, idx, B, q.f, t, an, aG, a3);
 #pragma unroll
     for (int a = 0; a < K3; ++a)
@@ -1164,7 +1166,7 @@ __global__ void __launch_bounds__(256) k_adjoint_drifters(Pot P, Batch b, Store 
 #pragma unroll
     for (int d = 0; d < 3; ++d) lv[d * cap + p] = lvv[d];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) atomicAdd(&dacc[i], (double)th[i]);
+    for (int i = 0; i < 5; ++i) atomicAdd(&dacc[i], (double)th[i]);
   }
   if (e_all) atomicOr(err, e_all);
 }
@@ -1343,11 +1345,20 @@ void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot
   const size_t lds = adjoint_lds_bytes(tg, ndim);
   launch_fill32(st, dcount, 1);
   launch_fill32(st, reinterpret_cast<int *>(amax_cur), 1);
-  PIC_ND(ndim, (k_adjoint_tiled<ND, false><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, N, nbar_next,
-                                                                          lx, lv, nbar, dlist, dcount, amax_prev,
-                                                                          amax_cur, partial, err)));
-  PIC_ND(ndim, (k_adjoint_drifters<ND><<<kDriftBlocks, 256, 0, st>>>(P, b, s, dlist, dcount, dens, nbar_next, lx, lv,
-                                                                       nbar, dacc, err)));
+  // GEN: the Morse potential (the context refuses the hexagonal lattice here)
+#define PIC_ADJT(GN)                                                                                              \
+  PIC_ND(ndim, (k_adjoint_tiled<ND, false, GN><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, N,   \
+                                                                              nbar_next, lx, lv, nbar, dlist,     \
+                                                                              dcount, amax_prev, amax_cur,        \
+                                                                              partial, err)));                    \
+  PIC_ND(ndim, (k_adjoint_drifters<ND, GN><<<kDriftBlocks, 256, 0, st>>>(P, b, s, dlist, dcount, dens, nbar_next, \
+                                                                           lx, lv, nbar, dacc, err)))
+  if (P.kind != 0) {
+    PIC_ADJT(true);
+  } else {
+    PIC_ADJT(false);
+  }
+#undef PIC_ADJT
 }
 
 void launch_adjoint_scale(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
@@ -1356,9 +1367,13 @@ void launch_adjoint_scale(hipStream_t st, int ndim, const TileGeo &tg, const Pot
   if (max_items <= 0) return;
   const size_t lds = adjoint_lds_bytes(tg, ndim);
   launch_fill32(st, reinterpret_cast<int *>(amax), 1);
-  PIC_ND(ndim, (k_adjoint_tiled<ND, true><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, N, nbar_next,
-                                                                         lx, lv, nullptr, nullptr, nullptr, amax, amax,
-                                                                         nullptr, nullptr)));
+#define PIC_ADJS(GN)                                                                                            \
+  PIC_ND(ndim, (k_adjoint_tiled<ND, true, GN><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, N,  \
+                                                                             nbar_next, lx, lv, nullptr, nullptr, \
+                                                                             nullptr, amax, amax, nullptr, nullptr)))
+  if (P.kind != 0) PIC_ADJS(true);
+  else PIC_ADJS(false);
+#undef PIC_ADJS
 }
 
 void launch_deposit_vjp_store(hipStream_t st, int ndim, const Batch &b, const Store &s, const float *nbar,

@@ -10,7 +10,12 @@ derivative jumps where a neighbour distance crosses r0 when the two branch
 multipliers differ.  Each derivative is recorded at relative steps 1e-3 and
 1e-4; their difference bounds the FD's own error.
 
-    python tests/golden/make_adjoint_fd.py
+With the argument `morse` it writes adjoint_fd_16cube_morse.json instead:
+the same case with the Morse copper potential (altered: c_att = 0.43, for
+D, s_rep, c_att, the Morse width alpha and the fluence; unaltered: c_att = 1,
+for r0).
+
+    python tests/golden/make_adjoint_fd.py [lj|morse]
 """
 import dataclasses
 import json
@@ -28,7 +33,18 @@ NSTEPS = 400
 FREF = 1.5e4
 
 
-def main():
+FAMILIES = {
+    "lj": ("adjoint_fd_16cube.json",
+           (("altered", W.Potential(c_att=0.27), ("D", "s_rep", "c_att", "F")),
+            ("unaltered", W.Potential(c_att=1.0), ("r0",)))),
+    "morse": ("adjoint_fd_16cube_morse.json",
+              (("altered", W.morse_cu(c_att=0.43), ("D", "s_rep", "c_att", "alpha", "F")),
+               ("unaltered", W.morse_cu(c_att=1.0), ("r0",)))),
+}
+
+
+def main(family="lj"):
+    fname, cases = FAMILIES[family]
     wl = W.cfg_adjoint_3d(n=16, layers=8)
     g, p = wl.grid, wl.parts
     y_s = wl.slab_rows * g.h[2]
@@ -41,9 +57,11 @@ def main():
     out = {"case": "cfg_adjoint_3d(n=16, layers=8)", "particles": int(p.n), "nsteps": NSTEPS, "dt": wl.dt,
            "fluence": FREF, "y_s": y_s, "tau": tau, "potentials": {}}
     t0 = time.time()
-    for name, pot, keys in (("altered", W.Potential(c_att=0.27), ("D", "s_rep", "c_att", "F")),
-                            ("unaltered", W.Potential(c_att=1.0), ("r0",))):
-        rec = {"D": pot.D, "r0": pot.r0, "s_rep": pot.s_rep, "c_att": pot.c_att, "J": J_of(pot), "dJ": {}}
+    for name, pot, keys in cases:
+        rec = {"D": pot.D, "r0": pot.r0, "s_rep": pot.s_rep, "c_att": pot.c_att}
+        if pot.kind == W.KIND_MORSE:
+            rec.update(kind=pot.kind, alpha=pot.alpha)
+        rec.update(J=J_of(pot), dJ={})
         for k in keys:
             vals = {}
             for rel in (1e-3, 1e-4):
@@ -58,9 +76,9 @@ def main():
                 print(name, k, rel, vals[str(rel)], f"{time.time() - t0:.0f}s", flush=True)
             rec["dJ"][k] = vals
         out["potentials"][name] = rec
-    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "adjoint_fd_16cube.json"), "w") as fh:
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), fname), "w") as fh:
         json.dump(out, fh, indent=1)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1] if len(sys.argv) > 1 else "lj")

@@ -13,6 +13,10 @@ Per-array cotangents are compared element by element against 1e-4 of the
 array's largest magnitude (their float-atomic sums carry order noise near
 1e-7 relative).  Whole gradients after 400 steps are held to the 1e-4
 relative target of finite differences.
+
+Both pair potentials run through the same tests: Lennard-Jones and Morse
+(whose width alpha is a fifth parameter; its FD fixture is
+tests/golden/adjoint_fd_16cube_morse.json).
 """
 import json
 import os
@@ -27,7 +31,16 @@ from paper_1502_07722_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_16cube.json")
+GOLDEN_MORSE = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_16cube_morse.json")
 FREF = 1.5e4
+
+
+def _pot(family):
+    return W.Potential(c_att=0.27) if family == "lj" else W.morse_cu(c_att=0.43)
+
+
+def _keys(pot):
+    return ("D", "r0", "s_rep", "c_att") + (("alpha",) if pot.kind == W.KIND_MORSE else ())
 
 
 @pytest.fixture(scope="module")
@@ -62,11 +75,13 @@ def _theta(pot, n):
     """Per-particle parameter leaves: their gradients are each particle's
     contribution, whose absolute sum bounds the rounding of the total."""
     return {k: torch.full((n,), float(getattr(pot, k)), dtype=torch.float64, requires_grad=True)
-            for k in ("D", "r0", "s_rep", "c_att")}
+            for k in _keys(pot)}
 
 
 def _check_theta(dth, th):
-    for i, k in enumerate(("D", "r0", "s_rep", "c_att")):
+    if "alpha" not in th:
+        assert dth[4].item() == 0.0  # no Morse width under Lennard-Jones
+    for i, k in enumerate(th):
         t = th[k].grad.numpy()
         ref, l1 = t.sum(), np.abs(t).sum()
         got = dth[i].item()
@@ -103,10 +118,11 @@ def _ref_state(grid, host):
     return geo, idx, f
 
 
+@pytest.mark.parametrize("family", ["lj", "morse"])
 @pytest.mark.parametrize("nd", [2, 3])
-def test_force_vjp_matches_autograd(B, nd):
+def test_force_vjp_matches_autograd(B, nd, family):
     grid, parts, dt = _case(nd)
-    pot = W.Potential(c_att=0.27)
+    pot = _pot(family)
     ctx = B.Context(grid, pot, dt, parts.n)
     dp = B.DeviceParticles.from_host(parts)
     ctx.start_leapfrog(dp)
@@ -130,10 +146,11 @@ def test_force_vjp_matches_autograd(B, nd):
     _check_theta(dth, th)
 
 
+@pytest.mark.parametrize("family", ["lj", "morse"])
 @pytest.mark.parametrize("nd", [2, 3])
-def test_adjoint_step_matches_autograd(B, nd):
+def test_adjoint_step_matches_autograd(B, nd, family):
     grid, parts, dt = _case(nd)
-    pot = W.Potential(c_att=0.27)
+    pot = _pot(family)
     ctx = B.Context(grid, pot, dt, parts.n)
     dp = B.DeviceParticles.from_host(parts)
     ctx.start_leapfrog(dp)
@@ -199,7 +216,7 @@ def _per_step_gradient(B, grid, parts, pot, dt, nsteps, y_s, tau):
     lam_x = torch.zeros((nd, parts.n), dtype=torch.float32, device="cuda")
     lam_x[ax] = torch.from_numpy((w * s * (1 - s) * grid.h[ax] / tau).astype(np.float32)).cuda()
     lam_v = torch.zeros((3, parts.n), dtype=torch.float32, device="cuda")
-    dth = torch.zeros(4, dtype=torch.float64, device="cuda")
+    dth = torch.zeros(B.NTHETA, dtype=torch.float64, device="cuda")
     nbar_next = None
     for k in range(nsteps - 1, -1, -1):
         node = ctx.pic_deposit(states[k])
@@ -239,3 +256,40 @@ def test_whole_gradient_matches_oracle_finite_differences(B):
     fd_err = abs(un["dJ"]["r0"]["0.001"] - fd)
     print(f"dJ/dr0: adjoint {dth1[1]:.9e} finite difference {fd:.9e} rel {abs(dth1[1] - fd) / abs(fd):.2e}")
     assert abs(dth1[1] - fd) <= 1e-4 * abs(fd) + fd_err, (dth1[1], fd, fd_err)
+
+
+def test_whole_morse_gradient_matches_oracle_finite_differences(B):
+    """The same 400-step sweep with the Morse potential, alpha included."""
+    with open(GOLDEN_MORSE) as fh:
+        gold = json.load(fh)
+    wl = W.cfg_adjoint_3d(n=16, layers=8)
+    grid, parts = wl.grid, wl.parts
+    assert parts.n == gold["particles"]
+    nsteps, y_s, tau = gold["nsteps"], gold["y_s"], gold["tau"]
+    for name, keys in (("altered", ("D", "s_rep", "c_att", "alpha", "F")), ("unaltered", ("r0",))):
+        rec = gold["potentials"][name]
+        pot = W.morse_cu(c_att=rec["c_att"])
+        assert pot.alpha == rec["alpha"] and pot.D == rec["D"]
+        J, dth, dF = _per_step_gradient(B, grid, parts, pot, wl.dt, nsteps, y_s, tau)
+        assert abs(J - rec["J"]) <= 1e-5 * abs(rec["J"]), (J, rec["J"])
+        got = dict(zip(("D", "r0", "s_rep", "c_att", "alpha"), dth))
+        got["F"] = dF
+        for k in keys:
+            fd = rec["dJ"][k]["0.0001"]
+            fd_err = abs(rec["dJ"][k]["0.001"] - fd)
+            print(f"[{name}] dJ/d{k}: adjoint {got[k]:.9e} finite difference {fd:.9e} "
+                  f"rel {abs(got[k] - fd) / abs(fd):.2e}")
+            assert abs(got[k] - fd) <= 1e-4 * abs(fd) + fd_err, (k, got[k], fd, fd_err)
+
+
+def test_reverse_mode_refuses_the_hexagonal_lattice(B):
+    grid, parts, dt = _case(2)
+    ctx = B.Context(grid, W.hcp(), dt, parts.n)
+    dp = B.DeviceParticles.from_host(parts)
+    node = ctx.pic_deposit(dp)
+    lam_x = torch.zeros_like(dp.off)
+    lam_v = torch.zeros_like(dp.vel)
+    with pytest.raises(B.PicError, match="cubic"):
+        ctx.pic_adjoint_step(dp, node, None, lam_x, lam_v)
+    with pytest.raises(B.PicError, match="cubic"):
+        ctx.pic_force_vjp(dp, node, torch.zeros_like(dp.off), lam_x)

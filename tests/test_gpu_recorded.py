@@ -10,7 +10,8 @@ pic_backward_record) and of the torch.autograd Functions built on it.
   on dtheta.
 * The autograd crater gradient on the 16^3, 400-step case with checkpoints
   every 20 steps matches central finite differences of the FP64 C oracle
-  (tests/golden/adjoint_fd_16cube.json) within the 1e-4 target.
+  (tests/golden/adjoint_fd_16cube.json) within the 1e-4 target; with the
+  Morse potential, alpha included, against adjoint_fd_16cube_morse.json.
 """
 import json
 import os
@@ -24,6 +25,7 @@ from paper_1502_07722_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_16cube.json")
+GOLDEN_MORSE = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_16cube_morse.json")
 
 
 @pytest.fixture(scope="module")
@@ -75,12 +77,14 @@ def test_recorded_forward_equals_pic_step(B, nd):
         assert torch.equal(a.cell, x.cell) and torch.equal(a.off, x.off) and torch.equal(a.vel, x.vel)
 
 
-@pytest.mark.parametrize("nd,rebin", [(2, False), (3, False), (2, True), (3, True)])
-def test_recorded_sweep_matches_per_step_chain(B, nd, rebin):
+@pytest.mark.parametrize("nd,rebin,family", [(2, False, "lj"), (3, False, "lj"), (2, True, "lj"), (3, True, "lj"),
+                                             (2, False, "morse"), (3, True, "morse")])
+def test_recorded_sweep_matches_per_step_chain(B, nd, rebin, family):
     """rebin: re-binning at every checkpoint (each segment has its own order,
-    the cotangents are permuted between segments)."""
+    the cotangents are permuted between segments).  family: the pair
+    potential (Morse adds the alpha slot of dtheta)."""
     grid, parts, dt = _case(nd)
-    pot = W.Potential(c_att=0.27)
+    pot = W.Potential(c_att=0.27) if family == "lj" else W.morse_cu(c_att=0.43)
     nsteps, every = 30, 8  # a ragged last segment
     ctx = B.Context(grid, pot, dt, parts.n)
     if rebin:
@@ -98,7 +102,7 @@ def test_recorded_sweep_matches_per_step_chain(B, nd, rebin):
         states.append(dp.clone())
     lam_x, lam_v = _seed_cotangents(grid, states[-1])
     lx_ref, lv_ref = lam_x.clone(), lam_v.clone()
-    dth_ref = torch.zeros(4, dtype=torch.float64, device="cuda")
+    dth_ref = torch.zeros(B.NTHETA, dtype=torch.float64, device="cuda")
     nbar_next = None
     for k in range(nsteps - 1, -1, -1):
         node = ctx.pic_deposit(states[k])
@@ -140,9 +144,10 @@ def test_backward_refuses_a_foreign_record(B):
         ctx.pic_backward_record(dp, rec, lam_x, lam_v)
 
 
-def test_autograd_crater_gradient_matches_oracle_finite_differences(B):
+@pytest.mark.parametrize("family", ["lj", "morse"])
+def test_autograd_crater_gradient_matches_oracle_finite_differences(B, family):
     from paper_1502_07722_amd import autograd as A
-    with open(GOLDEN) as fh:
+    with open(GOLDEN if family == "lj" else GOLDEN_MORSE) as fh:
         gold = json.load(fh)
     wl = W.cfg_adjoint_3d(n=16, layers=8)
     grid, p = wl.grid, wl.parts
@@ -154,9 +159,10 @@ def test_autograd_crater_gradient_matches_oracle_finite_differences(B):
     xi = torch.from_numpy(p.xi).to(dev)
     sig = torch.from_numpy(p.sigma.astype(np.float32)).to(dev)
     wq = torch.from_numpy(p.wq).to(dev)
-    for name, keys in (("altered", ("D", "s_rep", "c_att", "F")), ("unaltered", ("r0",))):
+    extra = ("alpha",) if family == "morse" else ()
+    for name, keys in (("altered", ("D", "s_rep", "c_att", "F") + extra), ("unaltered", ("r0",))):
         rec = gold["potentials"][name]
-        pot = W.Potential(c_att=rec["c_att"])
+        pot = W.Potential(c_att=rec["c_att"]) if family == "lj" else W.morse_cu(c_att=rec["c_att"])
         ctx = B.Context(grid, pot, wl.dt, p.n)
         theta = A.theta_of(pot).requires_grad_(True)
         fl = torch.tensor(fref, dtype=torch.float64, device=dev, requires_grad=True)
