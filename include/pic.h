@@ -221,9 +221,9 @@ int pic_step_nodes(pic_ctx_t *ctx, int64_t *node_w);
  * Phases: 0 deposit (incl. clearing the node sums), 1 density and gradient
  * grid pass, 2 gather+force+push (the dominant kernel: in the tiled step the
  * fused kernel), 3 re-binning by tile, 4 diagnostics reductions, 5 import of
- * the caller's arrays into the binned store and export back, 6 the tiled
- * step's drifter kernel (particles outside their tile window), 7 graph
- * replays (blocks of 6 steps; graphs are not used while timing is on, so
+ * the caller's arrays into the binned store and export back, 6 unused (the
+ * tiled step advances particles outside their tile window inside its fused
+ * kernel, at the end of each work item), 7 graph replays (blocks of 6 steps; graphs are not used while timing is on, so
  * the per-kernel phases above are measured launch by launch). */
 #define PIC_NPHASES 8
 typedef struct pic_timing {

@@ -43,7 +43,7 @@ class pic_diag_t(C.Structure):
 
 
 DIAG_FIELDS = ("ke", "pe", "px", "py", "pz", "wsum", "bond", "step")
-PHASES = ("deposit", "grid", "force_push", "sort", "diag", "import_export", "drifters", "graph")
+PHASES = ("deposit", "grid", "force_push", "sort", "diag", "import_export", "unused", "graph")
 
 
 class pic_tuning_t(C.Structure):

@@ -681,19 +681,13 @@ Drift drift_of(pic_ctx_t *c, int s) {
                c->drift + 2 + ((s + 1) & 1)};
 }
 
-// The launches of one tiled step (fused kernel, then drifters).
+// The launch of one tiled step: one fused kernel (drifters included).
 void enqueue_step(pic_ctx_t *c, const Batch &b, const Store &st, int s, bool diag) {
   long long *Nc = c->n3[s % 3], *Nn = c->n3[(s + 1) % 3], *Nz = c->n3[(s + 2) % 3];
   const Drift dr = drift_of(c, s);
-  {
-    PhaseTimer t(c, 2);
-    launch_step_tiled(c->stream, c->ndim, c->sd[0].tg, c->P, c->dcs[0], b, st, st, c->bb, c->grid_blocks, Nc, Nn,
-                      Nz, dr, c->partial, diag, c->err);
-  }
-  {
-    PhaseTimer t(c, 6);
-    launch_drifters(c->stream, c->ndim, c->P, c->dcs[0], b, st, st, Nc, Nn, dr, c->dacc, diag, c->err);
-  }
+  PhaseTimer t(c, 2);
+  launch_step_tiled(c->stream, c->ndim, c->sd[0].tg, c->P, c->dcs[0], b, st, st, c->bb, c->grid_blocks, Nc, Nn, Nz,
+                    dr, c->partial, diag, c->err);
 }
 
 // Graph of kGraphSteps plain steps starting at a step index that is a
@@ -833,7 +827,7 @@ int step_tiled(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t nsteps, Dia
       for (int k = 0; k < ctx->nslab; ++k) {
         const int nbg = (int)std::max<int64_t>(blocks_of(ctx->sizes[k].nnodes), 1);
         launch_reduce_diag_slab(ctx->stream, ctx->partial, ctx->bb.item_start, ctx->sd[k].tile_off,
-                                ctx->sd[k].tile_off + ctx->sd[k].tg.ntiles, ctx->dacc + 8 * k,
+                                ctx->sd[k].tile_off + ctx->sd[k].tg.ntiles,
                                 ctx->partial_pe + (int64_t)ctx->pe_off[k] * 8, nbg, ds.next() + k, s);
       }
     }
@@ -1333,8 +1327,6 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
       const Store in = slot(k), out = slot(k + 1);
       launch_step_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, ctx->dcs[0], b, in, out, bb, ctx->grid_blocks,
                         Nk(k), Nk(k + 1), Nk(k + 2), dr, ctx->partial, false, ctx->err);
-      launch_drifters(ctx->stream, nd, ctx->P, ctx->dcs[0], b, in, out, Nk(k), Nk(k + 1), dr, ctx->dacc, false,
-                      ctx->err);
     }
     if ((rc = check_launch(ctx, "recompute"))) return rc;
     // reverse steps of the segment

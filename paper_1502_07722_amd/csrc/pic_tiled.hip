@@ -127,46 +127,74 @@ __device__ __forceinline__ int win_centre(const Window &w, int m0, int m1, int m
   return ND == 2 ? m0 + (w.wn[0] - 1) * m1 : m0 + (w.wn[0] - 1) * (m1 + (w.wn[1] - 1) * m2);
 }
 
-// Global (window-free) density and gradient at a particle: the node densities
-// around the two nearest centres per axis, folded like the window (so the
-// values are the same bits as the window's).  Only particles that left their
-// tile window since the last binning come here.
+// Index in a 3^ND block of nodes (per-axis offsets 0..2).
+template <int ND>
+__device__ __forceinline__ constexpr int b3(int a0, int a1, int a2) {
+  return ND == 2 ? a0 + 3 * a1 : a0 + 3 * (a1 + 3 * a2);
+}
+
+// Global (window-free) density and gradient at a particle, folded like the
+// window (so the values are the same bits as the window's).  All nodes come
+// from one 3^ND block, from the lower centre's lower node c0 (folded once
+// per axis): G from the 2^ND nearest centres, whose corners the block holds,
+// and n from the own cell's corners, at block offsets idx - c0 (0 or 1 per
+// axis).  Only particles that left their tile window since the last binning
+// come here.
 template <int ND>
 __device__ __forceinline__ void gather_nodes_global(const Geo &g, const long long *__restrict__ N, const int idx[3],
                                                     const float f[3], float &nh, float Gp[3]) {
-  float cr[8];
-#pragma unroll
-  for (int k = 0; k < (1 << ND); ++k) {
-    int x = fold_node(g, 0, idx[0] + (k & 1)), y = fold_node(g, 1, idx[1] + ((k >> 1) & 1));
-    int z = ND == 3 ? fold_node(g, 2, idx[2] + ((k >> 2) & 1)) : 0;
-    cr[k] = node_density(g, N[node_index<ND>(g, x, y, z)], x, y, z);
-  }
-  nh = interp<ND>(cr, f);
   int c0[3] = {0, 0, 0};
   float t[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int e = 0; e < ND; ++e) centre_stencil(idx[e], f[e], c0[e], t[e]);
-  float Gc[8][3];
+  int ax[3][3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) ax[e][j] = e < ND ? fold_node(g, e, c0[e] + j) : 0;
+  constexpr int K3 = ND == 2 ? 9 : 27;
+  float d3[K3];
+#pragma unroll
+  for (int a = 0; a < K3; ++a) {
+    const int x = ax[0][a % 3], y = ax[1][(a / 3) % 3], z = ND == 3 ? ax[2][a / 9] : 0;
+    d3[a] = node_density(g, N[node_index<ND>(g, x, y, z)], x, y, z);
+  }
+  // all-ones masks of the offsets: the corners are picked by bitwise blends of
+  // values, so the block stays in registers (no indexing by a run-time offset)
+  const uint32_t m0 = idx[0] != c0[0] ? ~0u : 0u, m1 = idx[1] != c0[1] ? ~0u : 0u;
+  const uint32_t m2 = ND == 3 && idx[2] != c0[2] ? ~0u : 0u;
+  auto blend = [](float a, float b, uint32_t m) {  // m ? b : a
+    return __uint_as_float((__float_as_uint(a) & ~m) | (__float_as_uint(b) & m));
+  };
+  float cr[8];
+#pragma unroll
+  for (int k = 0; k < (1 << ND); ++k) {
+    const int b0 = k & 1, b1 = (k >> 1) & 1, b2 = ND == 3 ? (k >> 2) & 1 : 0;
+    const float lo = blend(blend(d3[b3<ND>(b0, b1, b2)], d3[b3<ND>(b0 + 1, b1, b2)], m0),
+                           blend(d3[b3<ND>(b0, b1 + 1, b2)], d3[b3<ND>(b0 + 1, b1 + 1, b2)], m0), m1);
+    if (ND == 3) {
+      const float hi = blend(blend(d3[b3<ND>(b0, b1, b2 + 1)], d3[b3<ND>(b0 + 1, b1, b2 + 1)], m0),
+                             blend(d3[b3<ND>(b0, b1 + 1, b2 + 1)], d3[b3<ND>(b0 + 1, b1 + 1, b2 + 1)], m0), m1);
+      cr[k] = blend(lo, hi, m2);
+    } else {
+      cr[k] = lo;
+    }
+  }
+  nh = interp<ND>(cr, f);
+  float vv[3][8];
 #pragma unroll
   for (int m = 0; m < (1 << ND); ++m) {
-    float c[8];
+    float c[8], Gc[3];
 #pragma unroll
-    for (int k = 0; k < (1 << ND); ++k) {
-      int x = fold_node(g, 0, c0[0] + (m & 1) + (k & 1));
-      int y = fold_node(g, 1, c0[1] + ((m >> 1) & 1) + ((k >> 1) & 1));
-      int z = ND == 3 ? fold_node(g, 2, c0[2] + ((m >> 2) & 1) + ((k >> 2) & 1)) : 0;
-      c[k] = node_density(g, N[node_index<ND>(g, x, y, z)], x, y, z);
-    }
-    centre_gradient<ND>(g, c, Gc[m]);
+    for (int j = 0; j < (1 << ND); ++j)
+      c[j] = d3[b3<ND>((m & 1) + (j & 1), ((m >> 1) & 1) + ((j >> 1) & 1), ND == 3 ? ((m >> 2) & 1) + ((j >> 2) & 1) : 0)];
+    centre_gradient<ND>(g, c, Gc);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) vv[d][m] = Gc[d];
   }
   Gp[2] = 0.0f;
 #pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    float v[8];
-#pragma unroll
-    for (int m = 0; m < (1 << ND); ++m) v[m] = Gc[m][d];
-    Gp[d] = interp<ND>(v, t);
-  }
+  for (int d = 0; d < ND; ++d) Gp[d] = interp<ND>(vv[d], t);
 }
 
 template <int ND>
@@ -572,15 +600,16 @@ __device__ __forceinline__ bool item_window(const Geo &g, const Window &w, const
   return ok;
 }
 
-// The particles of one item whose cells lie in the tile window (drifters are
-// appended to the global list).  Loads for the next round are issued before
-// the current round is computed.
+// The particles of one item whose cells lie in the tile window; the others
+// (drifters) are appended to dlist, the item's own region of the drifter list
+// (as long as the item: it cannot overflow), counted in ndrift (LDS).  Loads
+// for the next round are issued before the current round is computed.
 template <int ND, bool DIAG, bool INTERIOR, bool OUT, bool GEN>
 __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
                                          const StoreView &sv, const Item &it, const Window &w, const float *dens,
                                          const float *Gs, unsigned long long *acc,
-                                         unsigned long long *__restrict__ Nnext, int *__restrict__ olist,
-                                         int *__restrict__ ocount, uint32_t &e_all, double acc6[6]) {
+                                         unsigned long long *__restrict__ Nnext, int *__restrict__ dlist,
+                                         int *ndrift, uint32_t &e_all, double acc6[6]) {
   PState cur, nxt;
   int p = it.start + (int)threadIdx.x;
   load_state<ND, DIAG>(sv, p, p < it.end, cur);
@@ -591,7 +620,7 @@ __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC
     int idx[3], l[3];
     unpack_cell<ND>(tg, cur.pc, idx);
     const bool inside = live && item_window<ND, INTERIOR>(g, w, idx, 1, 3, l);
-    wave_append(olist, ocount, p, live && !inside);
+    wave_append(dlist, ndrift, p, live && !inside);
     if (inside) {
       float cr[8];
 #pragma unroll
@@ -635,11 +664,37 @@ __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC
   }
 }
 
-// Persistent: a fixed grid pulls work items (chunks of one tile of one slab)
-// from an atomic counter until the step's items are done.  Every block also
-// clears its share of the node buffer two steps ahead.
+// A drifter (a particle outside its tile window since the last binning): the
+// same cycle through the global node sums of its slab, folded like the
+// window, so its result is the same bits as inside a window.
 template <int ND, bool DIAG, bool OUT, bool GEN>
-__global__ void __launch_bounds__(256) k_step_tiled(Pot P, DiagC dc, Batch b, Store s, Store o,
+__device__ __forceinline__ void advance_drifter(const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
+                                                const StoreView &sv, int p, const long long *__restrict__ N,
+                                                unsigned long long *__restrict__ Nn, uint32_t &e_all,
+                                                double acc6[6]) {
+  PState q;
+  load_state<ND, DIAG>(sv, p, true, q);
+  int idx[3];
+  unpack_cell<ND>(tg, q.pc, idx);
+  float nh, Gp[3];
+  gather_nodes_global<ND>(g, N, idx, q.f, nh, Gp);
+  uint32_t tq[8];
+  advance_particle<ND, DIAG, false, OUT, GEN>(g, P, dc, tg, sv, p, q.pc, idx, q.f, q.v, q.W, nh, Gp, tq, e_all,
+                                              acc6);
+  deposit_global<ND>(g, Nn, idx, tq);
+}
+
+// Persistent: a fixed grid pulls work items (chunks of one tile of one slab)
+// from an atomic counter until the step's items are done.  Each item ends
+// with its own drifters (a few per item: the context re-bins once they
+// exceed a small fraction of the particles), so one launch is the whole
+// step.  Every block also clears its share of the node buffer two steps
+// ahead.
+// The occupancy bound (waves per SIMD: 7 in 2D, 5 in 3D) is what the item
+// loop needs alone; it keeps the rarely taken drifter path from raising the
+// register count of the whole kernel.
+template <int ND, bool DIAG, bool OUT, bool GEN>
+__global__ void __launch_bounds__(256, ND == 2 ? 7 : 5) k_step_tiled(Pot P, DiagC dc, Batch b, Store s, Store o,
                                                     const Item *__restrict__ items,
                                                     const int *__restrict__ num_items,
                                                     const long long *__restrict__ Ncur,
@@ -647,7 +702,7 @@ __global__ void __launch_bounds__(256) k_step_tiled(Pot P, DiagC dc, Batch b, St
                                                     long long *__restrict__ Nclear, Drift dr,
                                                     double *__restrict__ partial, uint32_t *__restrict__ err) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_item;
+  __shared__ int s_item, s_ndrift;
   clear_share(Nclear, b.nnodes);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *dr.count_next = 0;  // the next step's drifter count and work counter
@@ -657,7 +712,10 @@ __global__ void __launch_bounds__(256) k_step_tiled(Pot P, DiagC dc, Batch b, St
   const StoreView sv = view_of(s, o);
   uint32_t e_all = 0;
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(dr.work, 1);
+    if (threadIdx.x == 0) {
+      s_item = atomicAdd(dr.work, 1);
+      s_ndrift = 0;
+    }
     __syncthreads();
     const int bi = __builtin_amdgcn_readfirstlane(s_item);
     if (bi >= nit) break;
@@ -677,48 +735,21 @@ __global__ void __launch_bounds__(256) k_step_tiled(Pot P, DiagC dc, Batch b, St
 #pragma unroll
     for (int d = 0; d < ND; ++d) interior = interior && w.o[d] >= 0 && w.o[d] + w.wn[d] <= g.n[d] + 1;
     double acc6[6] = {0, 0, 0, 0, 0, 0};
+    int *dlist = dr.list + it.start;  // slots [start, end) of the item
     if (interior)
-      run_item<ND, DIAG, true, OUT, GEN>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dr.list, dr.count, e_all, acc6);
+      run_item<ND, DIAG, true, OUT, GEN>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dlist, &s_ndrift, e_all, acc6);
     else
-      run_item<ND, DIAG, false, OUT, GEN>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dr.list, dr.count, e_all, acc6);
-    __syncthreads();
+      run_item<ND, DIAG, false, OUT, GEN>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dlist, &s_ndrift, e_all, acc6);
+    __syncthreads();  // the window's sums and the item's drifter list are complete
     flush_window<ND>(g, w, acc, Nn);
+    const int ndr = __builtin_amdgcn_readfirstlane(s_ndrift);
+    if (ndr > 0) {
+      if (threadIdx.x == 0) atomicAdd(dr.count, ndr);  // the step's total, for the re-binning policy
+      for (int k = threadIdx.x; k < ndr; k += blockDim.x)
+        advance_drifter<ND, DIAG, OUT, GEN>(g, P, dc, tg, sv, dlist[k], Ncur + sd.node_off, Nn, e_all, acc6);
+    }
     if (DIAG) block_reduce_store<6>(acc6, partial + (int64_t)bi * 8);
     __syncthreads();  // LDS and s_item are reused by the next item
-  }
-  if (e_all) atomicOr(err, e_all);
-}
-
-// Drifters (particles outside their tile window since the last binning):
-// the same cycle through the global node sums of their slab.
-template <int ND, bool DIAG, bool OUT, bool GEN>
-__global__ void __launch_bounds__(256) k_outliers(Pot P, DiagC dc, Batch b, Store s, Store o, Drift dr,
-                                                  const long long *__restrict__ Ncur,
-                                                  unsigned long long *__restrict__ Nnext,
-                                                  double *__restrict__ dacc, uint32_t *__restrict__ err) {
-  const int n = *dr.count;
-  uint32_t e_all = 0;
-  const StoreView sv = view_of(s, o);
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-    const int p = dr.list[k];
-    const int slab = find_slab(b.part_offs, b.nslab, p);
-    const SlabDesc &sd = b.slabs[slab];
-    const Geo g = sd.g;
-    const TileGeo tg = sd.tg;
-    PState q;
-    load_state<ND, DIAG>(sv, p, true, q);
-    int idx[3];
-    unpack_cell<ND>(tg, q.pc, idx);
-    float nh, Gp[3];
-    gather_nodes_global<ND>(g, Ncur + sd.node_off, idx, q.f, nh, Gp);
-    uint32_t tq[8];
-    double acc6[6] = {0, 0, 0, 0, 0, 0};
-    advance_particle<ND, DIAG, false, OUT, GEN>(g, P, dc, tg, sv, p, q.pc, idx, q.f, q.v, q.W, nh, Gp, tq, e_all,
-                                                acc6);
-    deposit_global<ND>(g, Nnext + sd.node_off, idx, tq);
-    if (DIAG)
-#pragma unroll
-      for (int i = 0; i < 6; ++i) atomicAdd(&dacc[slab * 8 + i], acc6[i]);
   }
   if (e_all) atomicOr(err, e_all);
 }
@@ -760,21 +791,17 @@ __global__ void __launch_bounds__(256) k_deposit_tiled(Batch b, Store s, const I
   flush_window<ND>(g, w, acc, Ns);
 }
 
-// One slab's diagnostics: its items' block partials (a contiguous item range),
-// its drifters' accumulator (cleared after reading) and its node energy partials.
+// One slab's diagnostics: its items' block partials (a contiguous item range;
+// each item's drifters are in its partial) and its node energy partials.
 __global__ void __launch_bounds__(256) k_reduce_diag_slab(const double *__restrict__ part_p,
                                                           const int *__restrict__ item_start, int tile_lo,
-                                                          int tile_hi, double *__restrict__ dacc_k,
-                                                          const double *__restrict__ part_g, int nblk_g,
+                                                          int tile_hi, const double *__restrict__ part_g, int nblk_g,
                                                           pic_diag_t *__restrict__ out, int64_t step) {
   const int lo = item_start[tile_lo], hi = item_start[tile_hi];
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int b = lo + threadIdx.x; b < hi; b += blockDim.x)
 #pragma unroll
     for (int i = 0; i < 6; ++i) acc[i] += part_p[(int64_t)b * 8 + i];
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int i = 0; i < 6; ++i) acc[i] += dacc_k[i];
   for (int b = threadIdx.x; b < nblk_g; b += blockDim.x) acc[6] += part_g[(int64_t)b * 8];
   __shared__ double res[8];
   block_reduce_store<7>(acc, res);
@@ -788,8 +815,6 @@ __global__ void __launch_bounds__(256) k_reduce_diag_slab(const double *__restri
     out->bond = res[5];
     out->pe = res[6];
     out->step = step;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) dacc_k[i] = 0.0;
   }
 }
 
@@ -818,11 +843,6 @@ __device__ __forceinline__ void load_adjoint_state(const StoreView &sv, const fl
     a[d] = (on && d < ND) ? lx[d * cap + p] : 0.0f;
     c[d] = on ? lv[d * cap + p] : 0.0f;
   }
-}
-
-template <int ND>
-__device__ __forceinline__ constexpr int b3(int a0, int a1, int a2) {
-  return ND == 2 ? a0 + 3 * a1 : a0 + 3 * (a1 + 3 * a2);
 }
 
 // Node cotangents accumulate in LDS as int64 fixed point: float atomic adds
@@ -1299,30 +1319,9 @@ void launch_step_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P
 #undef PIC_STEP
 }
 
-void launch_drifters(hipStream_t st, int ndim, const Pot &P, const DiagC &dc, const Batch &b, const Store &s,
-                     const Store &o, const long long *Ncur, long long *Nnext, const Drift &dr, double *dacc,
-                     bool diag, uint32_t *err) {
-  unsigned long long *nn = (unsigned long long *)Nnext;
-  const bool out = s.pc != o.pc;
-  const bool gen = P.kind != 0 || P.lattice != 0;
-#define PIC_OUTL(DG, OT, GN) \
-  PIC_ND(ndim, (k_outliers<ND, DG, OT, GN><<<kDriftBlocks, 256, 0, st>>>(P, dc, b, s, o, dr, Ncur, nn, dacc, err)))
-  if (out) {
-    if (gen) PIC_OUTL(false, true, true);
-    else PIC_OUTL(false, true, false);
-  } else if (diag) {
-    if (gen) PIC_OUTL(true, false, true);
-    else PIC_OUTL(true, false, false);
-  } else {
-    if (gen) PIC_OUTL(false, false, true);
-    else PIC_OUTL(false, false, false);
-  }
-#undef PIC_OUTL
-}
-
 void launch_reduce_diag_slab(hipStream_t st, const double *part_p, const int *item_start, int tile_lo, int tile_hi,
-                             double *dacc_k, const double *part_g, int nblk_g, pic_diag_t *out, int64_t step) {
-  k_reduce_diag_slab<<<1, 256, 0, st>>>(part_p, item_start, tile_lo, tile_hi, dacc_k, part_g, nblk_g, out, step);
+                             const double *part_g, int nblk_g, pic_diag_t *out, int64_t step) {
+  k_reduce_diag_slab<<<1, 256, 0, st>>>(part_p, item_start, tile_lo, tile_hi, part_g, nblk_g, out, step);
 }
 
 size_t adjoint_lds_bytes(const TileGeo &tg, int ndim) {
