@@ -1336,11 +1336,10 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
       if (step == nsteps - 1)  // seed the fixed-point scale of the first reverse step
         launch_adjoint_scale(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), bb, (int)max_items, Nk(k),
                              nbar_next, lx, lv, amax_prev);
-      launch_density(ctx->stream, g, Nk(k), ctx->dens);
       launch_fillf(ctx->stream, nb_cur, ctx->nnodes);
-      launch_adjoint_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), bb, (int)max_items, Nk(k),
-                           ctx->dens, nbar_next, lx, lv, nb_cur, ctx->drift + 4, ctx->drift, amax_prev, amax_cur,
-                           ctx->partial, ctx->dacc, ctx->err);
+      launch_adjoint_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), bb, (int)max_items, Nk(k), nbar_next,
+                           lx, lv, nb_cur, ctx->drift + 4, ctx->drift, amax_prev, amax_cur, ctx->partial, ctx->dacc,
+                           ctx->err);
       nbar_next = nb_cur;
       std::swap(nb_cur, nb_other);
       if ((rc = check_launch(ctx, "reverse step"))) return rc;

@@ -848,8 +848,8 @@ __device__ __forceinline__ void load_adjoint_state(const StoreView &sv, const fl
 // Node cotangents accumulate in LDS as int64 fixed point: float atomic adds
 // on LDS are more than an order of magnitude slower than integer ones on this
 // chip.  The scale is a power of two set from the largest single contribution
-// of the previous reverse step (amax_prev, float bits): values up to 256
-// times that fit with 2^11 of headroom for the sum of a node's contributions
+// of the previous reverse step (amax_prev, float bits): values up to 128
+// times that fit with 2^12 of headroom for the sum of a node's contributions
 // and a resolution of 2^-44 of it; a larger value (a sudden jump) takes a
 // global float atomic instead.  MAXONLY: only measure the largest
 // contribution (seeds the scale of the first reverse step).
@@ -859,6 +859,13 @@ __device__ __forceinline__ int adj_scale_exp(uint32_t amax_bits) {
   int e;
   (void)frexpf(m, &e);  // m < 2^e
   return min(max(44 - e, -100), 100);
+}
+
+// v rounded to the nearest int64 (ties to even) for |v| < 2^51, exactly: the
+// FP64 sum with 1.5 * 2^52 holds the integer in its low mantissa bits (three
+// instructions where the generic float-to-int64 conversion takes eleven).
+__device__ __forceinline__ long long fix64(float v) {
+  return __double_as_longlong((double)v + 6755399441055744.0) - 0x4338000000000000ll;
 }
 
 // Node values at frame coordinates: an LDS window (frame = window), or the
@@ -879,10 +886,13 @@ __device__ __forceinline__ int folded_node(const Geo &g, int x, int y, int z) {
 }
 
 template <int ND>
-struct GlobalDens {
-  const float *d;
+struct GlobalDens {  // node density of step n from the node sums (the window's bits)
+  const long long *N;
   const Geo *g;
-  __device__ __forceinline__ float operator()(int x, int y, int z) const { return d[folded_node<ND>(*g, x, y, z)]; }
+  __device__ __forceinline__ float operator()(int x, int y, int z) const {
+    const int a = fold_node(*g, 0, x), b = fold_node(*g, 1, y), c = ND == 3 ? fold_node(*g, 2, z) : 0;
+    return node_density(*g, N[node_index<ND>(*g, a, b, c)], a, b, c);
+  }
 };
 
 template <int ND>
@@ -1052,7 +1062,7 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
   if ((int)blockIdx.x >= *num_items) return;
   const int sexp = MAXONLY ? 0 : adj_scale_exp(*amax_prev);
   const float to_fix = ldexpf(1.0f, sexp);    // exact power of two (sexp within float range)
-  const float lim = ldexpf(1.0f, 52 - sexp);  // larger values: global float atomics
+  const float lim = ldexpf(1.0f, 51 - sexp);  // larger values: global float atomics
   float vmax = 0.0f;
   const Item it = items[blockIdx.x];
   const SlabDesc &sd = b.slabs[it.slab];
@@ -1115,7 +1125,7 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
           if (a3[a] == 0.0f) continue;
           const int ax = B[0] + a % 3, ay = B[1] + (a / 3) % 3, az = ND == 3 ? B[2] + a / 9 : 0;
           if (fabsf(a3[a]) < lim) {
-            atomicAdd(&acc[win_node<ND>(w, ax, ay, az)], (unsigned long long)__float2ll_rn(a3[a] * to_fix));
+            atomicAdd(&acc[win_node<ND>(w, ax, ay, az)], (unsigned long long)fix64(a3[a] * to_fix));
           } else {
             atomicAdd(&nbar[sd.node_off + folded_node<ND>(g, w.o[0] + ax, w.o[1] + ay, w.o[2] + az)], a3[a]);
           }
@@ -1145,12 +1155,12 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
 }
 
 // The reverse step of the particles outside their window: the same block
-// computation on the global densities (folded like the window), scatters as
-// global float atomics; parameter terms into dacc[0..4].
+// computation on the node sums (densities folded like the window's), scatters
+// as global float atomics; parameter terms into dacc[0..4].
 template <int ND, bool GEN>
 __global__ void __launch_bounds__(256) k_adjoint_drifters(Pot P, Batch b, Store s, const int *__restrict__ dlist,
                                                           const int *__restrict__ dcount,
-                                                          const float *__restrict__ dens_g,
+                                                          const long long *__restrict__ Ncur,
                                                           const float *__restrict__ nbar_next,
                                                           float *__restrict__ lx, float *__restrict__ lv,
                                                           float *__restrict__ nbar, double *__restrict__ dacc,
@@ -1169,7 +1179,7 @@ __global__ void __launch_bounds__(256) k_adjoint_drifters(Pot P, Batch b, Store 
     load_adjoint_state<ND>(sv, lx, lv, cap, p, true, q, ln, lvv);
     int idx[3];
     unpack_cell<ND>(sd.tg, q.pc, idx);
-    const GlobalDens<ND> dens{dens_g + sd.node_off, &g};
+    const GlobalDens<ND> dens{Ncur + sd.node_off, &g};
     const GlobalNext<ND> next{nbar_next ? nbar_next + sd.node_off : nullptr, &g};
     float lf[3] = {0.f, 0.f, 0.f}, th[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, t[3], an, aG[3], a3[K3];
     int B[3];
@@ -1336,8 +1346,8 @@ size_t adjoint_lds_bytes(const TileGeo &tg, int ndim) {
 }
 
 void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
-                          const BinBufs &bb, int max_items, const long long *N, const float *dens,
-                          const float *nbar_next, float *lx, float *lv, float *nbar, int *dlist, int *dcount,
+                          const BinBufs &bb, int max_items, const long long *N, const float *nbar_next,
+                          float *lx, float *lv, float *nbar, int *dlist, int *dcount,
                           const uint32_t *amax_prev, uint32_t *amax_cur, double *partial, double *dacc,
                           uint32_t *err) {
   if (max_items <= 0) return;
@@ -1350,7 +1360,7 @@ void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot
                                                                               nbar_next, lx, lv, nbar, dlist,     \
                                                                               dcount, amax_prev, amax_cur,        \
                                                                               partial, err)));                    \
-  PIC_ND(ndim, (k_adjoint_drifters<ND, GN><<<kDriftBlocks, 256, 0, st>>>(P, b, s, dlist, dcount, dens, nbar_next, \
+  PIC_ND(ndim, (k_adjoint_drifters<ND, GN><<<kDriftBlocks, 256, 0, st>>>(P, b, s, dlist, dcount, N, nbar_next,    \
                                                                            lx, lv, nbar, dacc, err)))
   if (P.kind != 0) {
     PIC_ADJT(true);
