@@ -52,6 +52,23 @@ def measured_traffic(workload):
     return rec["traffic_bytes_per_launch"]
 
 
+TUNE_AFTER = 12  # steps a copy of the start state runs before the autotuner probes it
+
+
+def tune(ctx, state):
+    """pic_autotune on a copy of the state advanced TUNE_AFTER steps: a freshly
+    loaded slab has the same particle count in every tile, and the first
+    moves change that (a chunk equal to the count then splits half the
+    tiles into two items).  state: DeviceParticles, or a list for a batch."""
+    if isinstance(state, list):
+        probe = [s.clone() for s in state]
+        ctx.pic_step_batch(probe, TUNE_AFTER)
+    else:
+        probe = state.clone()
+        ctx.pic_step(probe, TUNE_AFTER)
+    return ctx.pic_autotune(probe, 6)
+
+
 def _finite(x):
     """JSON has no NaN: undetermined figures are reported as null."""
     return x if x == x and abs(x) != float("inf") else None
@@ -137,7 +154,7 @@ def run_sweep(steps, warmup, log_fn=log):
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         bctx = B.BatchContext([w.grid for w in wls], pot, dt, [w.parts.n for w in wls], stream=stream)
-        tuning = bctx.pic_autotune(starts, 6)
+        tuning = tune(bctx, starts)
         log_fn(f"autotuned tiling {tuning}")
         batch = [s.clone() for s in starts]
         bctx.pic_step_batch(batch, warmup)
@@ -209,7 +226,7 @@ def run_adjoint(log_fn=log, every=20, steps=None, potential="lj"):
     # plain forward: the same start state, pic_step over nsteps
     dp = B.DeviceParticles(cell.clone(), off0.clone(), (vth + sig[None, :] * xi).contiguous(), wq)
     ctx.start_leapfrog(dp)
-    tuning = ctx.pic_autotune(dp, 6)
+    tuning = tune(ctx, dp)
     log_fn(f"adjoint workload: autotuned tiling {tuning}")
     warm = dp.clone()
     ctx.pic_step(warm, nsteps)  # the same run once untimed: every graph captured
@@ -342,7 +359,7 @@ def run_slab(name, steps, warmup, log_fn=log, variant="lj"):
         dp = B.DeviceParticles.from_host(wl.parts, dev)
         ctx = B.Context(wl.grid, pot, wl.dt, N, device=dev, stream=stream)
         ctx.start_leapfrog(dp)
-        tuning = ctx.pic_autotune(dp, 6)
+        tuning = tune(ctx, dp)
         log_fn(f"{wl.name}: autotuned tiling {tuning}")
         start = dp.clone()
         if warmup:

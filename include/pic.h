@@ -278,7 +278,10 @@ int pic_set_graph(pic_ctx_t *ctx, int32_t on);
  * 4, 8 in 3D; chunk 512 to 16384; halo 2 in 2D, 1 in 3D; re-binning policy
  * unchanged) on the caller's particles for probe_steps steps each, launched
  * step by step (no graph capture inside a probe), timed with events, and
- * keeps the fastest tiling.  The
+ * keeps the fastest tiling.  Tune on a state that has run a few steps: a
+ * freshly loaded lattice puts exactly the same number of particles in every
+ * tile, so a chunk equal to that number looks as good as a larger one until
+ * the first moves split half the tiles into two items.  The
  * particles are copied into the internal store for every probe: the caller's
  * arrays are only read.  Results never depend on the tiling. */
 typedef struct pic_tuning {

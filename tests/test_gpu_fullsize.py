@@ -53,7 +53,10 @@ def test_full_size_nodes_and_sampled_step_match_oracle(B, name):
         dp = B.DeviceParticles.from_host(p)
         ctx = B.Context(g, pot, dt, p.n, stream=stream)
         ctx.start_leapfrog(dp)
-        ctx.pic_autotune(dp, 6)
+        probe = dp.clone()  # tuned like bench.py: on a copy advanced a few steps
+        ctx.pic_step(probe, 12)
+        ctx.pic_autotune(probe, 6)
+        del probe
         ctx.pic_step(dp, 20)
         nodes_dev = ctx.pic_step_nodes()
         nodes = nodes_dev.cpu().numpy()
