@@ -20,7 +20,9 @@ Steps, in the paper's order (Sec. 2, Fig. 1):
   eq. (2)   r(+d) = rbar / (1 - g/2), r(-d) = rbar / (1 + g/2)
   eq. (3)   F = Phi'(r+) - Phi'(r-), Phi' = s_rep U' (r < r0), c_att U' (r >= r0);
             U is Lennard-Jones, or Morse D (e^2 - 2e), e = exp(-alpha (r - r0))
-            (the paper's method takes any pair potential; only U' changes)
+            (the paper's method takes any pair potential; only U' changes);
+            on the hexagonal close-packed lattice the 12 neighbours' pair
+            forces along their directions replace the per-axis pairs
   push      leapfrog: v += F/m dt, x += v dt, carry / wrap / mirror
 Functional: J = sum_p w_p sigmoid((y_p - y_s) / tau) on the normal axis.
 """
@@ -181,9 +183,32 @@ def gather(geo: Geometry, dens, G, idx, f):
     return n_p, Gp
 
 
-def pair_force(theta: dict, n_floor: float, g_clamp: float, n_p, Gp):
+def hcp_neighbours(ndim: int):
+    """Unit vectors to the 12 nearest neighbours of an ideal hexagonal
+    close-packed site (c/a = sqrt(8/3)), in grid axes: the basal plane holds
+    six at 60 degree steps from the x axis; three sit a height sqrt(2/3) above
+    it and three below, over the centres of alternate basal triangles (in-plane
+    distance 1/sqrt(3), at 30 + 120 j degrees).  The c axis is the normal
+    (last) grid axis; in 2D the second basal axis is not resolved and its
+    component is dropped."""
+    out = []
+    for k in range(6):
+        a = math.radians(60.0 * k)
+        out.append((math.cos(a), math.sin(a), 0.0))
+    for h in (1.0, -1.0):
+        for j in range(3):
+            a = math.radians(30.0 + 120.0 * j)
+            out.append((math.cos(a) / math.sqrt(3.0), math.sin(a) / math.sqrt(3.0), h * math.sqrt(2.0 / 3.0)))
+    return [u if ndim == 3 else (u[0], u[2], 0.0) for u in out]
+
+
+def pair_force(theta: dict, n_floor: float, g_clamp: float, n_p, Gp, hcp: bool = False):
     """Eq. (1)-(3) per atom, in newtons; zero where n <= n_floor.  theta holds
-    D, r0, s_rep, c_att and, for the Morse potential, alpha."""
+    D, r0, s_rep, c_att and, for the Morse potential, alpha.  hcp: the 12
+    neighbours of the hexagonal close-packed lattice instead of one pair per
+    axis, each at the midpoint-rule distance 2^(1/6) rbar / (1 - q/2) along
+    its direction u, q = 2^(1/6) grad(rbar).u (clamped); force = sum of the
+    pair forces along u."""
     D, r0, s_rep, c_att = theta["D"], theta["r0"], theta["s_rep"], theta["c_att"]
     live = n_p > n_floor
     n_safe = torch.where(live, n_p, torch.ones_like(n_p) * max(n_floor, 1.0))
@@ -198,6 +223,15 @@ def pair_force(theta: dict, n_floor: float, g_clamp: float, n_p, Gp):
             du = -(12.0 * D / r) * (x6 * x6 - x6)
         return torch.where(r < r0, s_rep * du, c_att * du)
 
+    if hcp:
+        c6 = 2.0 ** (1.0 / 6.0)
+        grad = [(-1.0 / 3.0) * Gd * n_safe ** (-4.0 / 3.0) for Gd in Gp]  # eq. (1), unclamped
+        F = [torch.zeros_like(rbar) for _ in Gp]
+        for u in hcp_neighbours(len(Gp)):
+            q = torch.clamp(c6 * sum(grad[d] * u[d] for d in range(len(Gp))), -g_clamp, g_clamp)
+            f = dphi(c6 * rbar / (1.0 - 0.5 * q))
+            F = [F[d] + f * u[d] for d in range(len(Gp))]
+        return [torch.where(live, Fd, torch.zeros_like(Fd)) for Fd in F]
     F = []
     for Gd in Gp:
         g = (-1.0 / 3.0) * Gd * n_safe ** (-4.0 / 3.0)
@@ -208,12 +242,12 @@ def pair_force(theta: dict, n_floor: float, g_clamp: float, n_p, Gp):
     return F
 
 
-def forces(geo: Geometry, theta, n_floor, g_clamp, idx, f, w):
+def forces(geo: Geometry, theta, n_floor, g_clamp, idx, f, w, hcp: bool = False):
     N = deposit(geo, idx, f, w)
     dens = density(geo, N)
     G = centre_gradient(geo, dens)
     n_p, Gp = gather(geo, dens, G, idx, f)
-    return pair_force(theta, n_floor, g_clamp, n_p, Gp)
+    return pair_force(theta, n_floor, g_clamp, n_p, Gp, hcp)
 
 
 def push(geo: Geometry, dt: float, mass: float, F, idx, f, v):
@@ -249,8 +283,8 @@ def push(geo: Geometry, dt: float, mass: float, F, idx, f, v):
     return idx_new, f_new, v
 
 
-def step(geo, theta, n_floor, g_clamp, dt, mass, idx, f, v, w):
-    F = forces(geo, theta, n_floor, g_clamp, idx, f, w)
+def step(geo, theta, n_floor, g_clamp, dt, mass, idx, f, v, w, hcp: bool = False):
+    F = forces(geo, theta, n_floor, g_clamp, idx, f, w, hcp)
     return push(geo, dt, mass, F, idx, f, v)
 
 
@@ -278,8 +312,7 @@ def crater_objective(grid, pot, dt, nsteps, cell, off, v_thermal, xi, sigma_ref,
     sigma proportional to sqrt(F); v(-1/2) = v0 - F(x0)/m dt/2.  Returns (J,
     theta dict, fluence tensor, final state, initial offsets); theta and
     fluence (and the initial offsets with offsets_grad) are leaves with grad."""
-    if getattr(pot, "lattice", 0) != 0:
-        raise ValueError("the differentiable reference covers the cubic neighbour geometry only")
+    hcp = getattr(pot, "lattice", 0) == 1
     geo, idx, f = unpack(grid, cell, off)
     if offsets_grad:
         f = [t.clone().requires_grad_(True) for t in f]
@@ -294,9 +327,9 @@ def crater_objective(grid, pot, dt, nsteps, cell, off, v_thermal, xi, sigma_ref,
     sig = torch.as_tensor(sigma_ref, dtype=torch.float64) * scale
     v = [torch.as_tensor(v_thermal[d], dtype=torch.float64) + sig * torch.as_tensor(xi[d], dtype=torch.float64)
          for d in range(3)]
-    F0 = forces(geo, theta, pot.n_floor, pot.g_clamp, idx, f, w)
+    F0 = forces(geo, theta, pot.n_floor, pot.g_clamp, idx, f, w, hcp)
     v = [v[d] - 0.5 * F0[d] * (dt / pot.mass) if d < geo.ndim else v[d] for d in range(3)]
     for _ in range(nsteps):
-        idx, f, v = step(geo, theta, pot.n_floor, pot.g_clamp, dt, pot.mass, idx, f, v, w)
+        idx, f, v = step(geo, theta, pot.n_floor, pot.g_clamp, dt, pot.mass, idx, f, v, w, hcp)
     J = functional(geo, idx, f, w, y_s, tau)
     return J, theta, fluence, (idx, f, v), f0

@@ -161,7 +161,45 @@ def test_reference_morse_forward_and_gradients_match_oracle(case):
     assert abs(th1["r0"].grad.item() - fd) <= 2e-6 * abs(fd), (th1["r0"].grad.item(), fd)
 
 
-def test_reference_refuses_hexagonal_geometry():
-    grid, p, dt, y_s, tau = _case2d()
-    with pytest.raises(ValueError):
-        R.crater_objective(grid, W.hcp(), dt, 2, p.cell, p.off, p.v_thermal, p.xi, p.sigma, FREF, p.wq, y_s, tau)
+# The hexagonal close-packed neighbour geometry (12 neighbours along their
+# directions, the clamp on each neighbour's q): the reference's forward
+# against the C oracle, its gradients against central differences of it.
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("kind", ["lj", "morse"])
+def test_reference_hcp_forward_and_gradients_match_oracle(case, kind):
+    grid, p, dt, y_s, tau = CASES[case]()
+    nsteps = 30
+    base = W.Potential() if kind == "lj" else W.morse_cu()
+    pot = W.hcp(base, c_att=0.2)
+    J, th, Fl, _, _ = R.crater_objective(grid, pot, dt, nsteps, p.cell, p.off, p.v_thermal, p.xi, p.sigma,
+                                         FREF, p.wq, y_s, tau)
+    Jc = _oracle_J(grid, p, pot, dt, nsteps, y_s, tau)
+    assert abs(J.item() - Jc) <= 1e-12 * abs(Jc)
+    J.backward()
+    keys = ("D", "s_rep", "c_att") + (("alpha",) if kind == "morse" else ())
+    for k in keys:
+        fd = _fd(lambda x: _oracle_J(grid, p, dataclasses.replace(pot, **{k: x}), dt, nsteps, y_s, tau),
+                 getattr(pot, k), 1e-3)
+        assert abs(th[k].grad.item() - fd) <= 2e-6 * abs(fd), (k, th[k].grad.item(), fd)
+    # the fluence moves a few neighbours' q across the clamp within a 1e-3
+    # step here (the central difference is not monotone in the step there);
+    # at 3e-5 it has converged to 1e-9
+    fd = _fd(lambda x: _oracle_J(grid, p, pot, dt, nsteps, y_s, tau, fluence=x), FREF, 3e-5)
+    assert abs(Fl.grad.item() - fd) <= 2e-6 * abs(fd), (Fl.grad.item(), fd)
+    pot1 = dataclasses.replace(pot, c_att=1.0)
+    J1, th1, _, _, _ = R.crater_objective(grid, pot1, dt, nsteps, p.cell, p.off, p.v_thermal, p.xi, p.sigma,
+                                          FREF, p.wq, y_s, tau)
+    J1.backward()
+    fd = _fd(lambda x: _oracle_J(grid, p, dataclasses.replace(pot1, r0=x), dt, nsteps, y_s, tau), pot1.r0, 1e-4)
+    assert abs(th1["r0"].grad.item() - fd) <= 2e-6 * abs(fd), (th1["r0"].grad.item(), fd)
+
+
+def test_reference_hcp_directions_are_the_oracles():
+    """The reference builds the 12 directions its own way; as a set they are
+    the C oracle's (and so the brute-force lattice's, which pins those)."""
+    for nd in (2, 3):
+        ref = np.array(R.hcp_neighbours(nd))[:, :nd]
+        orc = O.hcp_directions()
+        orc = orc if nd == 3 else orc[:, [0, 2]]
+        for u in ref:
+            assert np.min(np.linalg.norm(orc - u, axis=1)) < 1e-15
