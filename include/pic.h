@@ -320,8 +320,8 @@ int pic_calibrate_catt(const pic_grid_t *grid, const pic_potential_t *pot, doubl
  *                     width, PIC_POT_MORSE only: slot 4 gets +0 under
  *                     Lennard-Jones).  The derivatives in D, r0 and alpha
  *                     hold the other parameters, c_att among them, fixed.
- * Both pair potentials (any pair potential enters eq. (3) through U' alone);
- * the cubic neighbour geometry only (PIC_EINVAL for PIC_LATTICE_HCP).
+ * Both pair potentials (any pair potential enters eq. (3) through U' alone)
+ * and both neighbour geometries (cubic, hexagonal close-packed).
  * Single-slab contexts only.  Stream-ordered and asynchronous; device errors
  * (invalid particles) are reported by the next pic_sync or pic_step.
  * Scatters to nodes use float atomics, so nbar, lam_x and dtheta carry

@@ -1048,14 +1048,11 @@ static ThetaScale theta_scale(const pic_ctx_t *ctx) {
   return ThetaScale{{1.0 / P.D, 1.0 / P.r0, 1.0, 1.0, P.kind == PIC_POT_MORSE ? 1.0 / P.alpha : 0.0}};
 }
 
-static const char *kAdjointLattice = "reverse mode supports the cubic neighbour geometry only";
-
 // Shared tail of the two particle VJPs: nbar gets the gradient transpose, the
 // per-block parameter partials are summed into dtheta.
 static int adjoint_common(pic_ctx_t *ctx, const pic_particles_t *p, const int64_t *node_w, const float *nbar_next,
                           const float *fbar, float *lam_x, float *lam_v, float *nbar, double *dtheta,
                           bool force_only, const char *what) {
-  if (ctx->pot.lattice != PIC_LATTICE_CUBIC) return fail(ctx, PIC_EINVAL, kAdjointLattice);
   if (!node_w) return fail(ctx, PIC_EINVAL, "node_w is NULL");
   if (!nbar) return fail(ctx, PIC_EINVAL, "nbar is NULL");
   if (!dtheta) return fail(ctx, PIC_EINVAL, "dtheta is NULL");
@@ -1256,7 +1253,6 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
                         const void *record, size_t record_bytes, void *scratch, size_t scratch_bytes, float *lam_x,
                         float *lam_v, double *dtheta) {
   if (!ctx) return PIC_EINVAL;
-  if (ctx->pot.lattice != PIC_LATTICE_CUBIC) return fail(ctx, PIC_EINVAL, kAdjointLattice);
   int rc = recorded_ok(ctx, p, nsteps, every);
   if (rc) return rc;
   const RecLayout R = rec_layout(ctx, nsteps, every);

@@ -84,6 +84,74 @@ __device__ __forceinline__ int corner_node(const Geo &g, const int idx[3], int k
 // Morse k = (A/6)(E - E^2), E = exp(A (1 - 1/s)), A = alpha r0: with t =
 // (A^2/6)(E - 2E^2), k' = t / s^2, A dk/dA = k + t (1 - 1/s), so s k' +
 // A dk/dA = k + t.
+// Per-neighbour terms of eq. (3) for the reverse mode: k (reduced U' without
+// the branch multiplier), dk = dk/ds, and t = s^2 dk/ds for Morse (zero for
+// Lennard-Jones, whose r0 term is s k' - k).
+template <bool GEN>
+__device__ __forceinline__ void pair_terms(const Pot &P, float s, float &k, float &dk, float &t) {
+  if (GEN && P.kind == 1) {
+    const float E = morse_e(P, s), is = __builtin_amdgcn_rcpf(s);
+    k = P.mA6 * __builtin_fmaf(-E, E, E);
+    t = (6.0f * P.mA6 * P.mA6) * __builtin_fmaf(-2.0f * E, E, E);
+    dk = t * is * is;
+  } else {
+    const float s2 = s * s, s6 = s2 * s2 * s2, s7 = s6 * s, s12 = s6 * s6;
+    k = __builtin_fmaf(-s7, s6, s7);
+    dk = __builtin_fmaf(-13.0f, s12, 7.0f * s6);
+    t = 0.0f;
+  }
+}
+
+// The hexagonal close-packed force reversed: per neighbour direction v
+// (weight w), q_k = clamp(c g.v), s = (q / c)(1 - q_k / 2), F += w phi'(s) v
+// (c = 2^(1/6); the clamp has zero derivative where it acts).  Same outputs
+// and parameter terms as the cubic case below.
+template <int ND>
+__device__ __forceinline__ void hcp_force_vjp(const Pot &P, float q, float rinv, float inv_n, float dqdn,
+                                              const float G[3], const float mu[3], float &an, float aG[3],
+                                              float th[5]) {
+  const float c6 = 1.12246204831f, qc = q * 0.890898718140339f;  // q / 2^(1/6)
+  float g[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int d = 0; d < ND; ++d) g[d] = (G[d] * rinv) * (-1.0f / 3.0f);
+  const bool morse = P.kind == 1;
+  float dqc = 0.0f, dg[3] = {0.0f, 0.0f, 0.0f};
+  const int n = ND == 3 ? 12 : 10;
+#pragma unroll 1
+  for (int j = 0; j < n; ++j) {
+    const float *v = ND == 3 ? kHcp3[j] : kHcp2[j];
+    float gu = g[0] * v[0] + g[1] * v[1], mk = mu[0] * v[0] + mu[1] * v[1];
+    if (ND == 3) {
+      gu = __builtin_fmaf(g[2], v[2], gu);
+      mk = __builtin_fmaf(mu[2], v[2], mk);
+    }
+    const float cq = c6 * gu;
+    const float qk = fminf(fmaxf(cq, -P.gclamp), P.gclamp);
+    const bool free_q = cq > -P.gclamp && cq < P.gclamp;
+    const float s = qc * __builtin_fmaf(-0.5f, qk, 1.0f);
+    float k, dk, t;
+    pair_terms<true>(P, s, k, dk, t);
+    const bool rep = s > 1.0f;  // repulsive branch (r < r0)
+    const float M = rep ? P.s_rep : P.c_att;
+    const float wm = v[3] * mk, A = M * dk;
+    dqc = __builtin_fmaf(wm * A, __builtin_fmaf(-0.5f, qk, 1.0f), dqc);
+    const float dgu = free_q ? wm * A * (-0.5f * qc) * c6 : 0.0f;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) dg[d] = __builtin_fmaf(dgu, v[d], dg[d]);
+    th[0] += wm * (M * k);
+    th[1] += morse ? wm * (M * t) : wm * (M * (dk * s - k));
+    th[2] += rep ? wm * k : 0.0f;
+    th[3] += rep ? 0.0f : wm * k;
+    if (morse) th[4] += wm * (M * (k + t - t * __builtin_amdgcn_rcpf(s)));
+  }
+  an = dqc * 0.890898718140339f * dqdn;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    an = __builtin_fmaf(dg[d], (-4.0f / 3.0f) * g[d] * inv_n, an);
+    aG[d] = dg[d] * (-1.0f / 3.0f) * rinv;
+  }
+}
+
 template <int ND, bool GEN = false>
 __device__ __forceinline__ void pair_force_vjp(const Pot &P, float nh, const float G[3], const float mu[3],
                                                float &an, float aG[3], float th[5]) {
@@ -95,6 +163,10 @@ __device__ __forceinline__ void pair_force_vjp(const Pot &P, float nh, const flo
   const float rinv = __builtin_amdgcn_rcpf(nh * q);
   const float inv_n = __builtin_amdgcn_rcpf(nh);
   const float dqdn = q * inv_n * (1.0f / 3.0f);
+  if (GEN && P.lattice == 1) {
+    hcp_force_vjp<ND>(P, q, rinv, inv_n, dqdn, G, mu, an, aG, th);
+    return;
+  }
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     const float graw = (G[d] * rinv) * (-1.0f / 3.0f);

@@ -1354,7 +1354,7 @@ void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot
   const size_t lds = adjoint_lds_bytes(tg, ndim);
   launch_fill32(st, dcount, 1);
   launch_fill32(st, reinterpret_cast<int *>(amax_cur), 1);
-  // GEN: the Morse potential (the context refuses the hexagonal lattice here)
+  // GEN: the Morse potential or the hexagonal lattice (runtime choice)
 #define PIC_ADJT(GN)                                                                                              \
   PIC_ND(ndim, (k_adjoint_tiled<ND, false, GN><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, N,   \
                                                                               nbar_next, lx, lv, nbar, dlist,     \
@@ -1362,7 +1362,7 @@ void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot
                                                                               partial, err)));                    \
   PIC_ND(ndim, (k_adjoint_drifters<ND, GN><<<kDriftBlocks, 256, 0, st>>>(P, b, s, dlist, dcount, N, nbar_next,    \
                                                                            lx, lv, nbar, dacc, err)))
-  if (P.kind != 0) {
+  if (P.kind != 0 || P.lattice != 0) {
     PIC_ADJT(true);
   } else {
     PIC_ADJT(false);
@@ -1380,7 +1380,7 @@ void launch_adjoint_scale(hipStream_t st, int ndim, const TileGeo &tg, const Pot
   PIC_ND(ndim, (k_adjoint_tiled<ND, true, GN><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, N,  \
                                                                              nbar_next, lx, lv, nullptr, nullptr, \
                                                                              nullptr, amax, amax, nullptr, nullptr)))
-  if (P.kind != 0) PIC_ADJS(true);
+  if (P.kind != 0 || P.lattice != 0) PIC_ADJS(true);
   else PIC_ADJS(false);
 #undef PIC_ADJS
 }

@@ -13,9 +13,10 @@ multipliers differ.  Each derivative is recorded at relative steps 1e-3 and
 With the argument `morse` it writes adjoint_fd_16cube_morse.json instead:
 the same case with the Morse copper potential (altered: c_att = 0.43, for
 D, s_rep, c_att, the Morse width alpha and the fluence; unaltered: c_att = 1,
-for r0).
+for r0).  With `hcp`, adjoint_fd_16cube_hcp.json: L-J on the hexagonal
+close-packed lattice (altered: c_att = 0.2; unaltered: c_att = 1).
 
-    python tests/golden/make_adjoint_fd.py [lj|morse]
+    python tests/golden/make_adjoint_fd.py [lj|morse|hcp]
 """
 import dataclasses
 import json
@@ -40,6 +41,9 @@ FAMILIES = {
     "morse": ("adjoint_fd_16cube_morse.json",
               (("altered", W.morse_cu(c_att=0.43), ("D", "s_rep", "c_att", "alpha", "F")),
                ("unaltered", W.morse_cu(c_att=1.0), ("r0",)))),
+    "hcp": ("adjoint_fd_16cube_hcp.json",
+            (("altered", W.hcp(c_att=0.2), ("D", "s_rep", "c_att", "F")),
+             ("unaltered", W.hcp(c_att=1.0), ("r0",)))),
 }
 
 
@@ -61,6 +65,8 @@ def main(family="lj"):
         rec = {"D": pot.D, "r0": pot.r0, "s_rep": pot.s_rep, "c_att": pot.c_att}
         if pot.kind == W.KIND_MORSE:
             rec.update(kind=pot.kind, alpha=pot.alpha)
+        if pot.lattice == W.LATTICE_HCP:
+            rec.update(lattice=pot.lattice)
         rec.update(J=J_of(pot), dJ={})
         for k in keys:
             vals = {}

@@ -14,9 +14,10 @@ array's largest magnitude (their float-atomic sums carry order noise near
 1e-7 relative).  Whole gradients after 400 steps are held to the 1e-4
 relative target of finite differences.
 
-Both pair potentials run through the same tests: Lennard-Jones and Morse
-(whose width alpha is a fifth parameter; its FD fixture is
-tests/golden/adjoint_fd_16cube_morse.json).
+Both pair potentials and both neighbour geometries run through the same
+tests: Lennard-Jones and Morse (whose width alpha is a fifth parameter; its
+FD fixture is tests/golden/adjoint_fd_16cube_morse.json), on the cubic and
+the hexagonal close-packed lattice (tests/golden/adjoint_fd_16cube_hcp.json).
 """
 import json
 import os
@@ -32,11 +33,14 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_16cube.json")
 GOLDEN_MORSE = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_16cube_morse.json")
+GOLDEN_HCP = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_16cube_hcp.json")
 FREF = 1.5e4
+FAMILIES = ["lj", "morse", "hcp", "hcp_morse"]
 
 
 def _pot(family):
-    return W.Potential(c_att=0.27) if family == "lj" else W.morse_cu(c_att=0.43)
+    return {"lj": lambda: W.Potential(c_att=0.27), "morse": lambda: W.morse_cu(c_att=0.43),
+            "hcp": lambda: W.hcp(c_att=0.2), "hcp_morse": lambda: W.hcp(W.morse_cu(), c_att=0.3)}[family]()
 
 
 def _keys(pot):
@@ -109,7 +113,7 @@ def _forces_at(geo, th, pot, idx, f, w, node_w):
     dens = R.density(geo, N)
     G = R.centre_gradient(geo, dens)
     n_p, Gp = R.gather(geo, dens, G, idx, f)
-    return R.pair_force(th, pot.n_floor, pot.g_clamp, n_p, Gp)
+    return R.pair_force(th, pot.n_floor, pot.g_clamp, n_p, Gp, hcp=pot.lattice == W.LATTICE_HCP)
 
 
 def _ref_state(grid, host):
@@ -118,7 +122,7 @@ def _ref_state(grid, host):
     return geo, idx, f
 
 
-@pytest.mark.parametrize("family", ["lj", "morse"])
+@pytest.mark.parametrize("family", FAMILIES)
 @pytest.mark.parametrize("nd", [2, 3])
 def test_force_vjp_matches_autograd(B, nd, family):
     grid, parts, dt = _case(nd)
@@ -146,7 +150,7 @@ def test_force_vjp_matches_autograd(B, nd, family):
     _check_theta(dth, th)
 
 
-@pytest.mark.parametrize("family", ["lj", "morse"])
+@pytest.mark.parametrize("family", FAMILIES)
 @pytest.mark.parametrize("nd", [2, 3])
 def test_adjoint_step_matches_autograd(B, nd, family):
     grid, parts, dt = _case(nd)
@@ -282,14 +286,24 @@ def test_whole_morse_gradient_matches_oracle_finite_differences(B):
             assert abs(got[k] - fd) <= 1e-4 * abs(fd) + fd_err, (k, got[k], fd, fd_err)
 
 
-def test_reverse_mode_refuses_the_hexagonal_lattice(B):
-    grid, parts, dt = _case(2)
-    ctx = B.Context(grid, W.hcp(), dt, parts.n)
-    dp = B.DeviceParticles.from_host(parts)
-    node = ctx.pic_deposit(dp)
-    lam_x = torch.zeros_like(dp.off)
-    lam_v = torch.zeros_like(dp.vel)
-    with pytest.raises(B.PicError, match="cubic"):
-        ctx.pic_adjoint_step(dp, node, None, lam_x, lam_v)
-    with pytest.raises(B.PicError, match="cubic"):
-        ctx.pic_force_vjp(dp, node, torch.zeros_like(dp.off), lam_x)
+def test_whole_hcp_gradient_matches_oracle_finite_differences(B):
+    """The same 400-step sweep on the hexagonal close-packed lattice (L-J)."""
+    with open(GOLDEN_HCP) as fh:
+        gold = json.load(fh)
+    wl = W.cfg_adjoint_3d(n=16, layers=8)
+    grid, parts = wl.grid, wl.parts
+    nsteps, y_s, tau = gold["nsteps"], gold["y_s"], gold["tau"]
+    for name, keys in (("altered", ("D", "s_rep", "c_att", "F")), ("unaltered", ("r0",))):
+        rec = gold["potentials"][name]
+        pot = W.hcp(c_att=rec["c_att"])
+        assert pot.r0 == rec["r0"] and rec["lattice"] == W.LATTICE_HCP
+        J, dth, dF = _per_step_gradient(B, grid, parts, pot, wl.dt, nsteps, y_s, tau)
+        assert abs(J - rec["J"]) <= 1e-5 * abs(rec["J"]), (J, rec["J"])
+        got = dict(zip(("D", "r0", "s_rep", "c_att", "alpha"), dth))
+        got["F"] = dF
+        for k in keys:
+            fd = rec["dJ"][k]["0.0001"]
+            fd_err = abs(rec["dJ"][k]["0.001"] - fd)
+            print(f"[{name}] dJ/d{k}: adjoint {got[k]:.9e} finite difference {fd:.9e} "
+                  f"rel {abs(got[k] - fd) / abs(fd):.2e}")
+            assert abs(got[k] - fd) <= 1e-4 * abs(fd) + fd_err, (k, got[k], fd, fd_err)

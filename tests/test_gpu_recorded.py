@@ -11,7 +11,8 @@ pic_backward_record) and of the torch.autograd Functions built on it.
 * The autograd crater gradient on the 16^3, 400-step case with checkpoints
   every 20 steps matches central finite differences of the FP64 C oracle
   (tests/golden/adjoint_fd_16cube.json) within the 1e-4 target; with the
-  Morse potential, alpha included, against adjoint_fd_16cube_morse.json.
+  Morse potential, alpha included, against adjoint_fd_16cube_morse.json; on
+  the hexagonal close-packed lattice against adjoint_fd_16cube_hcp.json.
 """
 import json
 import os
@@ -26,6 +27,7 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_16cube.json")
 GOLDEN_MORSE = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_16cube_morse.json")
+GOLDEN_HCP = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_16cube_hcp.json")
 
 
 @pytest.fixture(scope="module")
@@ -78,13 +80,14 @@ def test_recorded_forward_equals_pic_step(B, nd):
 
 
 @pytest.mark.parametrize("nd,rebin,family", [(2, False, "lj"), (3, False, "lj"), (2, True, "lj"), (3, True, "lj"),
-                                             (2, False, "morse"), (3, True, "morse")])
+                                             (2, False, "morse"), (3, True, "morse"), (2, True, "hcp"),
+                                             (3, False, "hcp")])
 def test_recorded_sweep_matches_per_step_chain(B, nd, rebin, family):
     """rebin: re-binning at every checkpoint (each segment has its own order,
     the cotangents are permuted between segments).  family: the pair
     potential (Morse adds the alpha slot of dtheta)."""
     grid, parts, dt = _case(nd)
-    pot = W.Potential(c_att=0.27) if family == "lj" else W.morse_cu(c_att=0.43)
+    pot = {"lj": W.Potential(c_att=0.27), "morse": W.morse_cu(c_att=0.43), "hcp": W.hcp(c_att=0.2)}[family]
     nsteps, every = 30, 8  # a ragged last segment
     ctx = B.Context(grid, pot, dt, parts.n)
     if rebin:
@@ -144,10 +147,10 @@ def test_backward_refuses_a_foreign_record(B):
         ctx.pic_backward_record(dp, rec, lam_x, lam_v)
 
 
-@pytest.mark.parametrize("family", ["lj", "morse"])
+@pytest.mark.parametrize("family", ["lj", "morse", "hcp"])
 def test_autograd_crater_gradient_matches_oracle_finite_differences(B, family):
     from paper_1502_07722_amd import autograd as A
-    with open(GOLDEN if family == "lj" else GOLDEN_MORSE) as fh:
+    with open({"lj": GOLDEN, "morse": GOLDEN_MORSE, "hcp": GOLDEN_HCP}[family]) as fh:
         gold = json.load(fh)
     wl = W.cfg_adjoint_3d(n=16, layers=8)
     grid, p = wl.grid, wl.parts
@@ -162,7 +165,8 @@ def test_autograd_crater_gradient_matches_oracle_finite_differences(B, family):
     extra = ("alpha",) if family == "morse" else ()
     for name, keys in (("altered", ("D", "s_rep", "c_att", "F") + extra), ("unaltered", ("r0",))):
         rec = gold["potentials"][name]
-        pot = W.Potential(c_att=rec["c_att"]) if family == "lj" else W.morse_cu(c_att=rec["c_att"])
+        pot = {"lj": lambda c: W.Potential(c_att=c), "morse": lambda c: W.morse_cu(c_att=c),
+               "hcp": lambda c: W.hcp(c_att=c)}[family](rec["c_att"])
         ctx = B.Context(grid, pot, wl.dt, p.n)
         theta = A.theta_of(pot).requires_grad_(True)
         fl = torch.tensor(fref, dtype=torch.float64, device=dev, requires_grad=True)
