@@ -988,42 +988,44 @@ __device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P,
 // The cotangents of a particle's gathered density (an) and gradient (aG) on
 // its 3^ND node block: the transpose of the centre-gradient stencil
 // (weights t), then the own cell's corners (offsets f, own lower node l).
+// Both maps are separable over the axes: along axis e a node at block offset
+// a enters the gradient component e with the difference weights
+// D_e = (-(1 - t_e), (1 - t_e) - t_e, t_e) and the other components with the
+// sum weights S_e = (1 - t_e, 1, t_e) (the centre-gradient stencil, then the
+// interpolation between the two nearest centres), and the density with the
+// own cell's linear weights U_e.
 template <int ND>
 __device__ __forceinline__ void block_cotangents(const Geo &g, const int l[3], const int B[3], const float f[3],
                                                  const float t[3], float an, const float aG[3],
                                                  float a3[ND == 2 ? 9 : 27]) {
-  constexpr int K3 = ND == 2 ? 9 : 27;
-#pragma unroll
-  for (int a = 0; a < K3; ++a) a3[a] = 0.0f;
-  float T[8];
-  corner_weights<ND>(t, T);
-#pragma unroll
-  for (int k = 0; k < (1 << ND); ++k) {
-    float wd[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int d = 0; d < ND; ++d) wd[d] = aG[d] * T[k] * g.gam[d];
-#pragma unroll
-    for (int j = 0; j < (1 << ND); ++j) {
-      float v = 0.0f;
-#pragma unroll
-      for (int d = 0; d < ND; ++d) v += ((j >> d) & 1) ? wd[d] : -wd[d];
-      a3[b3<ND>((k & 1) + (j & 1), ((k >> 1) & 1) + ((j >> 1) & 1), ND == 3 ? ((k >> 2) & 1) + ((j >> 2) & 1) : 0)] +=
-          v;
-    }
-  }
-  float u[3][3];
+  float D[3][3], S[3][3], U[3][3];
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
+    const float te = e < ND ? t[e] : 0.0f, ue = 1.0f - te;
+    D[e][0] = -ue;
+    D[e][1] = ue - te;
+    D[e][2] = te;
+    S[e][0] = ue;
+    S[e][1] = 1.0f;
+    S[e][2] = te;
     const int o = e < ND ? l[e] - B[e] : 0;  // own cell's lower node in the block: 0 or 1
     const float fe = e < ND ? f[e] : 0.0f;
-    u[e][0] = o == 0 ? 1.0f - fe : 0.0f;
-    u[e][1] = o == 0 ? fe : 1.0f - fe;
-    u[e][2] = o == 0 ? 0.0f : fe;
+    U[e][0] = o == 0 ? 1.0f - fe : 0.0f;
+    U[e][1] = o == 0 ? fe : 1.0f - fe;
+    U[e][2] = o == 0 ? 0.0f : fe;
   }
+  const float cx = aG[0] * g.gam[0], cy = aG[1] * g.gam[1], cz = ND == 3 ? aG[2] * g.gam[2] : 0.0f;
 #pragma unroll
-  for (int a = 0; a < K3; ++a) {
-    const float sh = u[0][a % 3] * u[1][(a / 3) % 3] * (ND == 3 ? u[2][a / 9] : 1.0f);
-    a3[a] = __builtin_fmaf(an, sh, a3[a]);
+  for (int bc = 0; bc < (ND == 2 ? 3 : 9); ++bc) {
+    const int b = bc % 3, c = bc / 3;
+    const float sz = ND == 3 ? S[2][c] : 1.0f, uz = ND == 3 ? U[2][c] : 1.0f;
+    const float px = cx * (S[1][b] * sz);
+    float pyz = cy * (D[1][b] * sz);
+    if (ND == 3) pyz = __builtin_fmaf(cz, S[1][b] * D[2][c], pyz);
+    const float pn = an * (U[1][b] * uz);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      a3[a + 3 * bc] = __builtin_fmaf(px, D[0][a], __builtin_fmaf(pyz, S[0][a], pn * U[0][a]));
   }
 }
 
