@@ -244,7 +244,7 @@ int pic_get_timing(pic_ctx_t *ctx, pic_timing_t *out);
 /* ---------------------------------------------------------------------------
  * Batches: several independent slabs (e.g. one per absorbed fluence of a
  * damage-threshold sweep) advanced together.  Every step of every slab is one
- * persistent launch of the fused kernel (plus the drifter kernel); steady
+ * persistent launch of the fused kernel (drifters included); steady
  * stretches of steps are replayed from a captured HIP graph.  Each slab's
  * result is bit-identical to advancing it alone.
  * ------------------------------------------------------------------------- */
