@@ -235,8 +235,10 @@ __device__ __forceinline__ void hcp_term(const Pot &P, float qc, const float g[3
 // The 12 neighbours in grid axes: 3D (basal 1, basal 2, c) = (x, y, z); 2D
 // (basal 1, c) = (x, y), the basal-2 axis unresolved, so neighbours that
 // differ only there merge (weights 2) and their out-of-plane forces cancel.
-// Rows: v0, v1, v2, weight.  A loop over the table (not unrolled) keeps the
-// register count of the kernels that carry this path next to the cubic one.
+// Rows: v0, v1, v2, weight.  The loop over the table is unrolled: the
+// kernels that carry this path are instantiations of their own (the general
+// potential / lattice switch), and the 2D step still fits the item loop's
+// occupancy (72 VGPRs, 7 waves per SIMD).
 static __constant__ float kHcp3[12][4] = {
     {1.0f, 0.0f, 0.0f, 1.0f},
     {0.5f, 0.866025403784439f, 0.0f, 1.0f},
@@ -261,7 +263,7 @@ template <int ND>
 __device__ __forceinline__ void hcp_force(const Pot &P, float q, const float g[3], float F[3], float &e, bool bond) {
   const float qc = q * 0.890898718140339f;  // q / 2^(1/6)
   const int n = ND == 3 ? 12 : 10;
-#pragma unroll 1
+#pragma unroll
   for (int k = 0; k < n; ++k) {
     const float *v = ND == 3 ? kHcp3[k] : kHcp2[k];
     hcp_term<ND>(P, qc, g, v[0], v[1], v[2], v[3], F, e, bond);
