@@ -258,6 +258,48 @@ def test_tiled_step_is_bit_identical_to_untiled_and_to_any_tiling(ndim):
         assert np.array_equal(nodes, ctx.pic_deposit(dp).cpu().numpy())
 
 
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_many_drifters_per_item_match_untiled(ndim):
+    """A uniform drift of 0.4 cells per step along the periodic x axis with
+    re-binning off: after a few steps most particles of every work item lie
+    outside their tile window, several 256-particle rounds of drifters per
+    item, which the fused step advances through the global node sums at the
+    end of the item.  Positions, velocities, cells and node sums must still
+    be the untiled path's bits, and the diagnostics its values."""
+    import dataclasses
+    pot = W.Potential(c_att=0.27)
+    if ndim == 2:
+        grid, parts = W.make_slab(2, (64, 48), 20, 24, H, 61, fluence_Jcm2=2.0, R_cells=16)
+        tiling = (8, 1, 1024, 0)
+    else:
+        grid, parts = W.make_slab(3, (16, 16, 20), 10, 8, H, 62, fluence_Jcm2=2.0, R_cells=8)
+        tiling = (4, 1, 512, 0)
+    vel = parts.vel.copy()
+    vel[0] += np.float32(0.4 * H / DT)
+    parts = dataclasses.replace(parts, vel=vel)
+    nsteps = 15
+    banner(f"many drifters {ndim}D N={parts.n}")
+    ref, d_ref, _, _ = _run_config(grid, parts, pot, nsteps, untiled=True, diag_every=5)
+    ctx = B.Context(grid, pot, DT, parts.n)
+    ctx.pic_set_tiling(*tiling)
+    dp = B.DeviceParticles.from_host(parts)
+    ctx.start_leapfrog(dp)
+    ctx.pic_set_timing(True)
+    d_t = ctx.pic_step(dp, nsteps, 5)
+    timing = ctx.pic_get_timing()
+    ctx.pic_set_timing(False)
+    nodes = ctx.pic_step_nodes().cpu().numpy()
+    assert timing["drifters_last"] > 0.5 * parts.n, timing
+    assert timing["drifters_last"] > 256 * timing["items_last"] // 2, timing
+    for x, y in zip(dp.to_host(), ref.to_host()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(nodes, ctx.pic_deposit(dp).cpu().numpy())
+    assert len(d_ref) == len(d_t)
+    for a, b in zip(d_ref, d_t):
+        for k in ("ke", "pe", "px", "py", "pz", "wsum", "bond"):
+            assert a[k] == pytest.approx(b[k], rel=1e-12, abs=1e-30), k
+
+
 def test_tiled_diagnostics_match_untiled():
     pot = W.Potential(c_att=0.27)
     grid, parts = W.make_slab(2, (64, 48), 24, 16, H, 53, fluence_Jcm2=2.0, R_cells=12)
