@@ -428,7 +428,7 @@ def main():
                     help="run a plain 1 GiB device copy first (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the design notes describe how it would shard).", file=sys.stderr)
         sys.exit(2)
     steps = args.steps if args.steps is not None else DEFAULTS[args.workload][0]
