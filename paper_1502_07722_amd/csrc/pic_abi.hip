@@ -1332,7 +1332,7 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
       if (step == nsteps - 1)  // seed the fixed-point scale of the first reverse step
         launch_adjoint_scale(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), bb, (int)max_items, Nk(k),
                              nbar_next, lx, lv, amax_prev);
-      launch_fillf(ctx->stream, nb_cur, ctx->nnodes);
+      launch_clear_reverse(ctx->stream, nb_cur, ctx->nnodes, ctx->drift, amax_cur);
       launch_adjoint_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), bb, (int)max_items, Nk(k), nbar_next,
                            lx, lv, nb_cur, ctx->drift + 4, ctx->drift, amax_prev, amax_cur, ctx->partial, ctx->dacc,
                            ctx->err);

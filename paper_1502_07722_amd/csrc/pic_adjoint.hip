@@ -150,6 +150,18 @@ __global__ void k_fillf(float *__restrict__ a, int64_t n) {
   if (i < n) a[i] = 0.0f;
 }
 
+// The clears of one reverse step in one launch: the step's node cotangents
+// and two counters (drifters, largest contribution).
+__global__ void k_clear_reverse(float *__restrict__ a, int64_t n, int *__restrict__ c1,
+                                uint32_t *__restrict__ c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.0f;
+  if (i == 0) {
+    *c1 = 0;
+    *c2 = 0u;
+  }
+}
+
 // Fixed-order sum of the per-block parameter partials into dtheta (+=);
 // scale[i] turns slot i into dJ/dtheta_i (1/D, 1/r0, 1, 1, 1/alpha or 0).
 __global__ void __launch_bounds__(256) k_reduce_theta(const double *__restrict__ partial, int nblocks, ThetaScale sc,
@@ -186,6 +198,10 @@ static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256
 
 void launch_fillf(hipStream_t st, float *a, int64_t n) {
   if (n > 0) hipLaunchKernelGGL(k_fillf, dim3(blocks_for(n)), dim3(256), 0, st, a, n);
+}
+
+void launch_clear_reverse(hipStream_t st, float *a, int64_t n, int *c1, uint32_t *c2) {
+  hipLaunchKernelGGL(k_clear_reverse, dim3(blocks_for(n > 0 ? n : 1)), dim3(256), 0, st, a, n, c1, c2);
 }
 
 int launch_adjoint(hipStream_t st, const Geo &g, const Pot &P, const PartPtrs &p, const float *dens, const float *G,

@@ -138,8 +138,8 @@ void launch_fill32(hipStream_t s, int *a, int64_t n);
 // reverse mode in the store (pic_tiled.hip); lx [ndim][cap], lv [3][cap]
 size_t adjoint_lds_bytes(const TileGeo &tg, int ndim);
 // partial: per-item parameter sums, ACCUMULATED over the calls (clear once);
-// dens: the global node densities of the step (for particles outside their
-// window)
+// N: the step's node sums; nbar, dcount and amax_cur must be zero on entry
+// (launch_clear_reverse)
 void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
                           const BinBufs &bb, int max_items, const long long *N, const float *nbar_next, float *lx,
                           float *lv, float *nbar, int *dlist, int *dcount, const uint32_t *amax_prev,
@@ -159,6 +159,8 @@ void launch_from_store(hipStream_t st, const Batch &b, const Store &s, int k, co
 
 // reverse mode on caller arrays (pic_adjoint.hip)
 void launch_fillf(hipStream_t st, float *a, int64_t n);
+// a[0..n) = 0, *c1 = 0, *c2 = 0 in one launch
+void launch_clear_reverse(hipStream_t st, float *a, int64_t n, int *c1, uint32_t *c2);
 int launch_adjoint(hipStream_t st, const Geo &g, const Pot &P, const PartPtrs &p, const float *dens, const float *G,
                    const float *nbar_next, const float *fbar, float *lam_x, float *lam_v, float *nbar, float *Gbar,
                    double *partial, uint32_t *err, bool force_only);

@@ -1354,8 +1354,7 @@ void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot
                           uint32_t *err) {
   if (max_items <= 0) return;
   const size_t lds = adjoint_lds_bytes(tg, ndim);
-  launch_fill32(st, dcount, 1);
-  launch_fill32(st, reinterpret_cast<int *>(amax_cur), 1);
+  // dcount and amax_cur start at zero: the caller clears them (with nbar)
   // GEN: the Morse potential or the hexagonal lattice (runtime choice)
 #define PIC_ADJT(GN)                                                                                              \
   PIC_ND(ndim, (k_adjoint_tiled<ND, false, GN><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, N,   \
