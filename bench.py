@@ -193,7 +193,8 @@ def run_adjoint(log_fn=log, every=20, steps=None, potential="lj"):
     steps from v(-1/2).  Gradient = torch.autograd through the crater
     functional: recorded forward (checkpoints every 20 steps) + reverse sweep
     (segment recompute + reverse steps) + the start and heating terms.
-    potential: "lj" (eq. (3)) or "morse" (Morse copper, alpha a parameter)."""
+    potential: "lj" (eq. (3)), "morse" (Morse copper, alpha a parameter) or
+    "hcp" (eq. (3) on the hexagonal close-packed lattice)."""
     import numpy as np
     import torch
     from paper_1502_07722_amd import autograd as A
@@ -204,7 +205,7 @@ def run_adjoint(log_fn=log, every=20, steps=None, potential="lj"):
     wl = W.cfg_adjoint_3d()
     g, p = wl.grid, wl.parts
     log_fn(f"adjoint workload {wl.name}: {p.n} particles, generated in {time.perf_counter() - t0:.1f} s")
-    base = wl.pot if potential == "lj" else W.morse_cu()
+    base = {"lj": wl.pot, "morse": W.morse_cu(), "hcp": W.hcp()}[potential]
     c_att, _ = B.pic_calibrate_catt(g, base, W.N_SOLID, 8)
     pot = dataclasses.replace(base, c_att=c_att)
     nsteps = wl.steps if steps is None else steps
@@ -261,8 +262,10 @@ def run_adjoint(log_fn=log, every=20, steps=None, potential="lj"):
     del ctx
     torch.cuda.empty_cache()
     return {"workload": f"{wl.name}: 128^3 cells, slab 64 layers, 8 ppc, 1.5 J/cm^2, {nsteps} steps, "
-                        f"checkpoint every {every}" + ("" if potential == "lj" else ", Morse potential"),
-            "potential": "lennard-jones" if potential == "lj" else "morse", "c_att": c_att,
+                        f"checkpoint every {every}" + {"lj": "", "morse": ", Morse potential",
+                                                       "hcp": ", hexagonal lattice"}[potential],
+            "potential": {"lj": "lennard-jones", "morse": "morse", "hcp": "lennard-jones, hcp"}[potential],
+            "c_att": c_att,
             "particles": int(p.n), "steps": nsteps, "checkpoint_every": every,
             "tiling": tuning, "forward_s": t_fwd, "recorded_forward_s": t_rec, "backward_s": t_bwd,
             "adjoint_over_forward": t_bwd / t_fwd, "gradient_over_forward": (t_rec + t_bwd) / t_fwd,
@@ -442,6 +445,7 @@ def main():
     if args.workload == "adjoint":
         res = run_adjoint(steps=args.steps)
         res["morse"] = run_adjoint(steps=args.steps, potential="morse")
+        res["hcp"] = run_adjoint(steps=args.steps, potential="hcp")
         out = {"metric": f"adjoint time / forward time ({res['steps']} steps, checkpoint every 20)",
                "value": res["adjoint_over_forward"], "unit": "ratio", "n_gpus": 1, "steps": res["steps"],
                "warmup": 1, "ms_per_step": res["backward_s"] / res["steps"] * 1e3, "higher_is_better": False,
@@ -536,6 +540,7 @@ def main():
     if not args.no_adjoint and args.workload == "large":
         out["adjoint"] = run_adjoint()
         out["adjoint"]["morse"] = run_adjoint(potential="morse")
+        out["adjoint"]["hcp"] = run_adjoint(potential="hcp")
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, pot)
