@@ -9,6 +9,8 @@ tiles), on outputs the FP64 oracle can compute one by one:
 * one more GPU step, for 20,000 sampled particles, matches the oracle's
   eq. (1)-(3) force from those full node sums followed by its leapfrog push
   (FP64): positions to 1e-5 cells, velocities to 1e-5 of the largest speed;
+  on the large slab also with the Morse potential and on the hexagonal
+  close-packed lattice (the variants bench.py times there);
 * on the full 128^3 adjoint workload, the autograd gradient of the crater
   functional agrees with a central difference of the GPU forward itself in
   D and in the fluence (a property that holds at any size).
@@ -42,12 +44,19 @@ def _abs_pos(grid, cell, off):
     return np.stack(out)
 
 
-@pytest.mark.parametrize("name", ["large", "heated", "adjoint3d"])
-def test_full_size_nodes_and_sampled_step_match_oracle(B, name):
+POTENTIALS = {"lj": lambda: W.Potential(c_att=0.27), "morse": lambda: W.morse_cu(c_att=0.43),
+              "hcp": lambda: W.hcp(c_att=0.2)}
+
+
+@pytest.mark.parametrize("name,variant", [("large", "lj"), ("heated", "lj"), ("adjoint3d", "lj"),
+                                          ("large", "morse"), ("large", "hcp")])
+def test_full_size_nodes_and_sampled_step_match_oracle(B, name, variant):
+    """variant: the pair potential and lattice bench.py also times on the
+    large slab (Morse; L-J on the hexagonal close-packed lattice)."""
     wl = W.WORKLOADS[name]()
     g, p, dt = wl.grid, wl.parts, wl.dt
-    pot = W.Potential(c_att=0.27)
-    print(f"[fullsize] {wl.name}: {p.n} particles", flush=True)
+    pot = POTENTIALS[variant]()
+    print(f"[fullsize] {wl.name} ({variant}): {p.n} particles", flush=True)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         dp = B.DeviceParticles.from_host(p)
@@ -89,7 +98,7 @@ def test_full_size_nodes_and_sampled_step_match_oracle(B, name):
             diff[d] -= g.n[d] * np.round(diff[d] / g.n[d])
     perr = np.abs(diff).max()
     verr = np.abs(vel1[:, s] - exp_v).max() / np.abs(exp_v).max()
-    print(f"[fullsize] {wl.name}: position {perr:.2e} cells, velocity {verr:.2e}", flush=True)
+    print(f"[fullsize] {wl.name} ({variant}): position {perr:.2e} cells, velocity {verr:.2e}", flush=True)
     assert perr <= 1e-5 and verr <= 1e-5
 
 
