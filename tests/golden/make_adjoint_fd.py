@@ -14,9 +14,11 @@ With the argument `morse` it writes adjoint_fd_16cube_morse.json instead:
 the same case with the Morse copper potential (altered: c_att = 0.43, for
 D, s_rep, c_att, the Morse width alpha and the fluence; unaltered: c_att = 1,
 for r0).  With `hcp`, adjoint_fd_16cube_hcp.json: L-J on the hexagonal
-close-packed lattice (altered: c_att = 0.2; unaltered: c_att = 1).
+close-packed lattice (altered: c_att = 0.2; unaltered: c_att = 1); with
+`hcp_morse`, adjoint_fd_16cube_hcp_morse.json: Morse on that lattice
+(altered: c_att = 0.3, alpha included; unaltered: c_att = 1).
 
-    python tests/golden/make_adjoint_fd.py [lj|morse|hcp]
+    python tests/golden/make_adjoint_fd.py [lj|morse|hcp|hcp_morse]
 """
 import dataclasses
 import json
@@ -44,6 +46,9 @@ FAMILIES = {
     "hcp": ("adjoint_fd_16cube_hcp.json",
             (("altered", W.hcp(c_att=0.2), ("D", "s_rep", "c_att", "F")),
              ("unaltered", W.hcp(c_att=1.0), ("r0",)))),
+    "hcp_morse": ("adjoint_fd_16cube_hcp_morse.json",
+                  (("altered", W.hcp(W.morse_cu(), c_att=0.3), ("D", "s_rep", "c_att", "alpha", "F")),
+                   ("unaltered", W.hcp(W.morse_cu(), c_att=1.0), ("r0",)))),
 }
 
 

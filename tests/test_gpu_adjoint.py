@@ -34,6 +34,7 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_16cube.json")
 GOLDEN_MORSE = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_16cube_morse.json")
 GOLDEN_HCP = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_16cube_hcp.json")
+GOLDEN_HCP_MORSE = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_16cube_hcp_morse.json")
 FREF = 1.5e4
 FAMILIES = ["lj", "morse", "hcp", "hcp_morse"]
 
@@ -286,16 +287,19 @@ def test_whole_morse_gradient_matches_oracle_finite_differences(B):
             assert abs(got[k] - fd) <= 1e-4 * abs(fd) + fd_err, (k, got[k], fd, fd_err)
 
 
-def test_whole_hcp_gradient_matches_oracle_finite_differences(B):
-    """The same 400-step sweep on the hexagonal close-packed lattice (L-J)."""
-    with open(GOLDEN_HCP) as fh:
+@pytest.mark.parametrize("kind", ["lj", "morse"])
+def test_whole_hcp_gradient_matches_oracle_finite_differences(B, kind):
+    """The same 400-step sweep on the hexagonal close-packed lattice, with the
+    Lennard-Jones and with the Morse potential (alpha included)."""
+    with open(GOLDEN_HCP if kind == "lj" else GOLDEN_HCP_MORSE) as fh:
         gold = json.load(fh)
     wl = W.cfg_adjoint_3d(n=16, layers=8)
     grid, parts = wl.grid, wl.parts
     nsteps, y_s, tau = gold["nsteps"], gold["y_s"], gold["tau"]
-    for name, keys in (("altered", ("D", "s_rep", "c_att", "F")), ("unaltered", ("r0",))):
+    extra = ("alpha",) if kind == "morse" else ()
+    for name, keys in (("altered", ("D", "s_rep", "c_att", "F") + extra), ("unaltered", ("r0",))):
         rec = gold["potentials"][name]
-        pot = W.hcp(c_att=rec["c_att"])
+        pot = W.hcp(None if kind == "lj" else W.morse_cu(), c_att=rec["c_att"])
         assert pot.r0 == rec["r0"] and rec["lattice"] == W.LATTICE_HCP
         J, dth, dF = _per_step_gradient(B, grid, parts, pot, wl.dt, nsteps, y_s, tau)
         assert abs(J - rec["J"]) <= 1e-5 * abs(rec["J"]), (J, rec["J"])

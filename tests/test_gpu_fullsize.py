@@ -9,8 +9,8 @@ tiles), on outputs the FP64 oracle can compute one by one:
 * one more GPU step, for 20,000 sampled particles, matches the oracle's
   eq. (1)-(3) force from those full node sums followed by its leapfrog push
   (FP64): positions to 1e-5 cells, velocities to 1e-5 of the largest speed;
-  on the large slab also with the Morse potential and on the hexagonal
-  close-packed lattice (the variants bench.py times there);
+  on the large slab and the 128^3 3D slab also with the Morse potential and
+  on the hexagonal close-packed lattice (the variants bench.py times);
 * on the full 128^3 adjoint workload, the autograd gradient of the crater
   functional agrees with a central difference of the GPU forward itself in
   D and in the fluence (a property that holds at any size).
@@ -49,7 +49,8 @@ POTENTIALS = {"lj": lambda: W.Potential(c_att=0.27), "morse": lambda: W.morse_cu
 
 
 @pytest.mark.parametrize("name,variant", [("large", "lj"), ("heated", "lj"), ("adjoint3d", "lj"),
-                                          ("large", "morse"), ("large", "hcp")])
+                                          ("large", "morse"), ("large", "hcp"), ("adjoint3d", "morse"),
+                                          ("adjoint3d", "hcp")])
 def test_full_size_nodes_and_sampled_step_match_oracle(B, name, variant):
     """variant: the pair potential and lattice bench.py also times on the
     large slab (Morse; L-J on the hexagonal close-packed lattice)."""
