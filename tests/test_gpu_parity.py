@@ -389,11 +389,13 @@ def _sweep(scale=0.1, nslab=6):
     return [(w.grid, w.parts) for w in wls]
 
 
-def test_batched_step_is_bit_identical_to_each_slab_alone():
+@pytest.mark.parametrize("variant", ["lj", "morse_hcp"])
+def test_batched_step_is_bit_identical_to_each_slab_alone(variant):
     """Slabs of uneven size advanced in one batched context (persistent
     launches over all slabs' items) give every slab exactly the bits it gets
-    alone; per-slab diagnostics agree to FP64 summation order."""
-    pot = W.Potential(c_att=0.27)
+    alone; per-slab diagnostics agree to FP64 summation order.  Also with the
+    general kernels (Morse on the hexagonal lattice)."""
+    pot = W.Potential(c_att=0.27) if variant == "lj" else W.hcp(W.morse_cu(), c_att=0.3)
     slabs = _sweep()
     banner(f"batch of {len(slabs)} slabs, N={[p.n for _, p in slabs]}")
     alone = []
