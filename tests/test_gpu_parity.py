@@ -416,11 +416,13 @@ def test_batched_step_is_bit_identical_to_each_slab_alone(variant):
                 assert a[f] == pytest.approx(b[f], rel=1e-12, abs=1e-30), (k, f)
 
 
-def test_graph_replay_matches_eager_launches():
+@pytest.mark.parametrize("variant", ["lj", "morse_hcp"])
+def test_graph_replay_matches_eager_launches(variant):
     """Graph replays of 6-step blocks, interleaved with eager diagnostic steps
     and several pic_step calls (host syncs in between), reproduce the eager
-    launches bit for bit on a created stream."""
-    pot = W.Potential(c_att=0.27)
+    launches bit for bit on a created stream (also with the general kernels:
+    Morse on the hexagonal lattice)."""
+    pot = W.Potential(c_att=0.27) if variant == "lj" else W.hcp(W.morse_cu(), c_att=0.3)
     grid, parts = W.make_slab(2, (96, 64), 32, 16, H, 61, fluence_Jcm2=2.0, R_cells=20)
     stream = torch.cuda.Stream()
     banner(f"graph replay N={parts.n}")
