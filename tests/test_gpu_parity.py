@@ -105,6 +105,32 @@ def test_deposit_empty_input_zeroes_the_grid():
     ctx.pic_step(dp, 3)
 
 
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_empty_input_on_the_tiled_path(ndim):
+    """No particles on a grid large enough for the tiled path: the fused
+    step, the graph replay, the recorded forward and the reverse sweep run
+    and leave the node sums zero and dtheta zero."""
+    grid = (W.Grid(ndim=2, n=(64, 64), h=(H, H), bc=(0, 1)) if ndim == 2
+            else W.Grid(ndim=3, n=(16, 16, 16), h=(H, H, H), bc=(0, 0, 1)))
+    banner(f"empty tiled {ndim}D")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = B.Context(grid, W.Potential(c_att=0.27), DT, 100, stream=stream)
+        assert ctx.pic_get_tiling()[0] > 0  # the tiled path
+        e = torch.empty(0, dtype=torch.int32, device="cuda")
+        dp = B.DeviceParticles(e, torch.empty((ndim, 0), device="cuda"), torch.empty((3, 0), device="cuda"),
+                               e.clone())
+        diags = ctx.pic_step(dp, 13, 5)
+        assert [d["wsum"] for d in diags] == [0.0, 0.0, 0.0]
+        assert int(ctx.pic_step_nodes().abs().sum()) == 0
+        rec = ctx.pic_forward_record(dp, 12, 4)
+        lam_x = torch.zeros((ndim, 0), device="cuda")
+        lam_v = torch.zeros((3, 0), device="cuda")
+        dth = ctx.pic_backward_record(dp, rec, lam_x, lam_v)
+    stream.synchronize()
+    assert torch.count_nonzero(dth).item() == 0
+
+
 # ------------------------------------------------------------------ force / push, one evaluation
 def force_tolerance(F_ref, pot):
     return 1e-4 * np.abs(F_ref) + 1e-5 * 12 * pot.D / pot.r0
