@@ -681,13 +681,22 @@ Drift drift_of(pic_ctx_t *c, int s) {
                c->drift + 2 + ((s + 1) & 1)};
 }
 
+// Persistent grid of the fused kernel for n particles: the full grid, or
+// fewer blocks when the step cannot have that many work items (at most one
+// per tile plus one per chunk of particles); extra blocks would only find the
+// queue empty, and launching them costs more than the step on a small grid.
+int step_grid(const pic_ctx_t *c, int64_t n) {
+  const int64_t items = (int64_t)c->ntiles + (n + c->chunk - 1) / c->chunk;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(c->grid_blocks, items));
+}
+
 // The launch of one tiled step: one fused kernel (drifters included).
 void enqueue_step(pic_ctx_t *c, const Batch &b, const Store &st, int s, bool diag) {
   long long *Nc = c->n3[s % 3], *Nn = c->n3[(s + 1) % 3], *Nz = c->n3[(s + 2) % 3];
   const Drift dr = drift_of(c, s);
   PhaseTimer t(c, 2);
-  launch_step_tiled(c->stream, c->ndim, c->sd[0].tg, c->P, c->dcs[0], b, st, st, c->bb, c->grid_blocks, Nc, Nn, Nz,
-                    dr, c->partial, diag, c->err);
+  launch_step_tiled(c->stream, c->ndim, c->sd[0].tg, c->P, c->dcs[0], b, st, st, c->bb, step_grid(c, b.nparts), Nc,
+                    Nn, Nz, dr, c->partial, diag, c->err);
 }
 
 // Graph of kGraphSteps plain steps starting at a step index that is a
@@ -1321,7 +1330,7 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
     for (int k = 0; k + 1 < len; ++k) {
       const Drift dr = drift_of(ctx, k);
       const Store in = slot(k), out = slot(k + 1);
-      launch_step_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, ctx->dcs[0], b, in, out, bb, ctx->grid_blocks,
+      launch_step_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, ctx->dcs[0], b, in, out, bb, step_grid(ctx, n),
                         Nk(k), Nk(k + 1), Nk(k + 2), dr, ctx->partial, false, ctx->err);
     }
     if ((rc = check_launch(ctx, "recompute"))) return rc;
