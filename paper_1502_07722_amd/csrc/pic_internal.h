@@ -144,7 +144,6 @@ void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot
                           const BinBufs &bb, int max_items, const long long *N, const float *nbar_next, float *lx,
                           float *lv, float *nbar, int *dlist, int *dcount, const uint32_t *amax_prev,
                           uint32_t *amax_cur, double *partial, double *dacc, uint32_t *err);
-void launch_density(hipStream_t s, const Geo &g, const long long *node, float *dens);
 // largest node-cotangent contribution of a reverse step, measured only (the
 // fixed-point scale of the first reverse step); lx, lv are read only
 void launch_adjoint_scale(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,

@@ -405,10 +405,6 @@ void launch_deposit_atomic(hipStream_t s, const Geo &g, const PartPtrs &pp, long
                            g, pp.n, pp.cell, pp.off, pp.wq, (unsigned long long *)node, err)));
 }
 
-void launch_density(hipStream_t s, const Geo &g, const long long *node, float *dens) {
-  PIC_DISPATCH(g.ndim, (k_density<ND><<<nblocks(g.nnodes), 256, 0, s>>>(g, node, dens)));
-}
-
 void launch_grid(hipStream_t s, const Geo &g, const long long *node, float *dens, float *G) {
   PIC_DISPATCH(g.ndim, (k_density<ND><<<nblocks(g.nnodes), 256, 0, s>>>(g, node, dens)));
   PIC_DISPATCH(g.ndim, (k_gradient<ND><<<nblocks(g.ncells), 256, 0, s>>>(g, dens, G)));
