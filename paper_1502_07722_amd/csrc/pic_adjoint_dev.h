@@ -105,17 +105,25 @@ __device__ __forceinline__ void pair_terms(const Pot &P, float s, float &k, floa
 // The hexagonal close-packed force reversed: per neighbour direction v
 // (weight w), q_k = clamp(c g.v), s = (q / c)(1 - q_k / 2), F += w phi'(s) v
 // (c = 2^(1/6); the clamp has zero derivative where it acts).  Same outputs
-// and parameter terms as the cubic case below.
+// and parameter terms as the cubic case below.  The loop keeps only the sums
+// the outputs need (w_m = w mu.v, A = M dk/ds, M the branch multiplier):
+//   S = sum w_m A s, E = sum of w_m A v over the unclamped q_k,
+//   K_r, K_a = sum w_m k over the repulsive and the attractive branch,
+//   T = sum w_m M t (Morse).
+// s is linear in q (ds/dq = s / q) and dq/dn = q / (3 n), so the density
+// term is S / (3 n); ds/dg = -(q / 2) v on the unclamped directions;
+// sum w_m M k = s_rep K_r + c_att K_a; the Lennard-Jones r0 term
+// M (s dk - k) sums to S - K; for Morse dk = t / s^2, so the width term
+// M (k + t - t / s) sums to K + T - S.
 template <int ND>
-__device__ __forceinline__ void hcp_force_vjp(const Pot &P, float q, float rinv, float inv_n, float dqdn,
-                                              const float G[3], const float mu[3], float &an, float aG[3],
-                                              float th[5]) {
+__device__ __forceinline__ void hcp_force_vjp(const Pot &P, float q, float rinv, float inv_n, const float G[3],
+                                              const float mu[3], float &an, float aG[3], float th[5]) {
   const float c6 = 1.12246204831f, qc = q * 0.890898718140339f;  // q / 2^(1/6)
   float g[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int d = 0; d < ND; ++d) g[d] = (G[d] * rinv) * (-1.0f / 3.0f);
   const bool morse = P.kind == 1;
-  float dqc = 0.0f, dg[3] = {0.0f, 0.0f, 0.0f};
+  float S = 0.0f, T = 0.0f, Kr = 0.0f, Ka = 0.0f, E[3] = {0.0f, 0.0f, 0.0f};
   const int n = ND == 3 ? 12 : 10;
 #pragma unroll 1
   for (int j = 0; j < n; ++j) {
@@ -133,23 +141,30 @@ __device__ __forceinline__ void hcp_force_vjp(const Pot &P, float q, float rinv,
     pair_terms<true>(P, s, k, dk, t);
     const bool rep = s > 1.0f;  // repulsive branch (r < r0)
     const float M = rep ? P.s_rep : P.c_att;
-    const float wm = v[3] * mk, A = M * dk;
-    dqc = __builtin_fmaf(wm * A, __builtin_fmaf(-0.5f, qk, 1.0f), dqc);
-    const float dgu = free_q ? wm * A * (-0.5f * qc) * c6 : 0.0f;
+    const float wm = v[3] * mk, wA = wm * (M * dk), wk = wm * k;
+    S = __builtin_fmaf(wA, s, S);
+    const float wAf = free_q ? wA : 0.0f;
 #pragma unroll
-    for (int d = 0; d < ND; ++d) dg[d] = __builtin_fmaf(dgu, v[d], dg[d]);
-    th[0] += wm * (M * k);
-    th[1] += morse ? wm * (M * t) : wm * (M * (dk * s - k));
-    th[2] += rep ? wm * k : 0.0f;
-    th[3] += rep ? 0.0f : wm * k;
-    if (morse) th[4] += wm * (M * (k + t - t * __builtin_amdgcn_rcpf(s)));
+    for (int d = 0; d < ND; ++d) E[d] = __builtin_fmaf(wAf, v[d], E[d]);
+    Kr += rep ? wk : 0.0f;
+    Ka += rep ? 0.0f : wk;
+    if (morse) T = __builtin_fmaf(wm * M, t, T);
   }
-  an = dqc * 0.890898718140339f * dqdn;
+  an = S * inv_n * (1.0f / 3.0f);
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    an = __builtin_fmaf(dg[d], (-4.0f / 3.0f) * g[d] * inv_n, an);
-    aG[d] = dg[d] * (-1.0f / 3.0f) * rinv;
+    const float dg = (-0.5f * q) * E[d];
+    an = __builtin_fmaf(dg, (-4.0f / 3.0f) * g[d] * inv_n, an);
+    aG[d] = dg * (-1.0f / 3.0f) * rinv;
   }
+  const float K = __builtin_fmaf(P.s_rep, Kr, P.c_att * Ka);
+  // every slot takes one unconditional add (a branch between slots would
+  // make the caller's array addressable memory)
+  th[0] += K;
+  th[1] += morse ? T : S - K;
+  th[2] += Kr;
+  th[3] += Ka;
+  th[4] += morse ? (K + T) - S : 0.0f;
 }
 
 template <int ND, bool GEN = false>
@@ -164,7 +179,7 @@ __device__ __forceinline__ void pair_force_vjp(const Pot &P, float nh, const flo
   const float inv_n = __builtin_amdgcn_rcpf(nh);
   const float dqdn = q * inv_n * (1.0f / 3.0f);
   if (GEN && P.lattice == 1) {
-    hcp_force_vjp<ND>(P, q, rinv, inv_n, dqdn, G, mu, an, aG, th);
+    hcp_force_vjp<ND>(P, q, rinv, inv_n, G, mu, an, aG, th);
     return;
   }
 #pragma unroll
