@@ -42,7 +42,12 @@ __global__ void __launch_bounds__(256) k_adjoint(Geo g, Pot P, int64_t n, const 
                                                  float *__restrict__ lam_v, float *__restrict__ nbar,
                                                  float *__restrict__ Gbar, double *__restrict__ partial,
                                                  uint32_t *__restrict__ err) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // Each wave takes every fourth particle of the block's 256 (blocks are
+  // always 256 threads): particles next to each other in the caller's order,
+  // often of one cell, land in different waves, so fewer lanes of a wave add
+  // into the same node or cell at once.
+  const int t = (int)threadIdx.x;
+  const int64_t p = (int64_t)blockIdx.x * 256 + ((t & 63) << 2 | t >> 6);
   double thd[5] = {0, 0, 0, 0, 0};
   if (p < n) {
     int c = cell[p];
