@@ -278,7 +278,9 @@ int pic_set_graph(pic_ctx_t *ctx, int32_t on);
  * 4, 8 in 3D; chunk 512 to 16384; halo 2 in 2D, 1 in 3D; re-binning policy
  * unchanged) on the caller's particles for probe_steps steps each, launched
  * step by step (no graph capture inside a probe), timed with events, and
- * keeps the fastest tiling.  Tune on a state that has run a few steps: a
+ * keeps the fastest tiling; among the tilings within 1 % of the fastest it
+ * takes the one with the largest chunk (the forward steps cannot tell them
+ * apart; a reverse sweep pays per work item).  Tune on a state that has run a few steps: a
  * freshly loaded lattice puts exactly the same number of particles in every
  * tile, so a chunk equal to that number looks as good as a larger one until
  * the first moves split half the tiles into two items.  The
@@ -287,7 +289,7 @@ int pic_set_graph(pic_ctx_t *ctx, int32_t on);
 typedef struct pic_tuning {
   int32_t tile, halo, chunk;
   int32_t candidates;   /* tilings that were timed */
-  double ms_per_step;   /* best probe, ms per step */
+  double ms_per_step;   /* the kept tiling's probe, ms per step */
 } pic_tuning_t;
 int pic_autotune(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t probe_steps, pic_tuning_t *out);
 

@@ -1411,6 +1411,11 @@ int pic_autotune(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t probe_ste
   ctx->use_graph = false;  // a graph capture per candidate would land inside its timed probe
   float best = 1e30f;
   int best_lt = old_lt, best_c = old_c, tried = 0;
+  struct Probe {
+    float ms;
+    int lt, c;
+  };
+  std::vector<Probe> probes;
   pic_particles_t *pp = const_cast<pic_particles_t *>(parts);
   for (int i = 0; i < 3; ++i) {
     if (i > 0 && lts[i] == lts[i - 1]) continue;
@@ -1424,6 +1429,7 @@ int pic_autotune(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t probe_ste
       rc = step_tiled(ctx, pp, probe_steps, ds, 1, false, &ms);
       if (rc) break;
       ++tried;
+      probes.push_back({ms, lts[i], c});
       if (ms < best) {
         best = ms;
         best_lt = lts[i];
@@ -1442,6 +1448,18 @@ int pic_autotune(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t probe_ste
     }
     if (rc) break;
   }
+  // Among the probes within 1 % of the fastest, take the largest items: the
+  // forward steps cannot tell them apart, while a reverse sweep pays per item
+  // (each flushes its window's node cotangents).
+  float sel = best;
+  for (const Probe &q : probes) {
+    if (q.ms > best * 1.01f) continue;
+    if (q.c > best_c || (q.c == best_c && q.ms < sel)) {
+      best_c = q.c;
+      best_lt = q.lt;
+      sel = q.ms;
+    }
+  }
   ctx->timing = old_timing;
   ctx->use_graph = old_graph;
   ctx->last_nodes = nullptr;
@@ -1455,7 +1473,7 @@ int pic_autotune(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t probe_ste
     out->halo = halo;
     out->chunk = best_c;
     out->candidates = tried;
-    out->ms_per_step = best / probe_steps;
+    out->ms_per_step = sel / probe_steps;
   }
   return read_device_error(ctx);
 }
