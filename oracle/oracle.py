@@ -24,7 +24,7 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain -O2, no fast-math, no FMA target)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
             os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "pic_oracle.h"))):
-        tmp = LIB + ".tmp"
+        tmp = f"{LIB}.tmp{os.getpid()}"  # parallel test workers may build at once
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
                                "-ffp-contract=off", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)

@@ -625,14 +625,13 @@ static double gauss_legendre16(const calib_ctx *c, double a, double b) {
   return r * s;
 }
 
-/* Interval halving until the two halves agree with the whole to an absolute
- * tolerance proportional to the interval length (always terminates). */
-static double adaptive_gl(const calib_ctx *c, double a, double b, double whole, double tol_per_len,
-                          int depth) {
+/* Interval halving until the two halves agree with the whole to 1e-12 of
+ * their magnitudes (at most 18 halvings). */
+static double adaptive_gl(const calib_ctx *c, double a, double b, double whole, int depth) {
   double m = 0.5 * (a + b);
   double l = gauss_legendre16(c, a, m), r = gauss_legendre16(c, m, b);
-  if (depth >= 40 || fabs(l + r - whole) <= tol_per_len * (b - a)) return l + r;
-  return adaptive_gl(c, a, m, l, tol_per_len, depth + 1) + adaptive_gl(c, m, b, r, tol_per_len, depth + 1);
+  if (depth >= 18 || fabs(l + r - whole) <= 1e-12 * (fabs(l) + fabs(r)) + 1e-300) return l + r;
+  return adaptive_gl(c, a, m, l, depth + 1) + adaptive_gl(c, m, b, r, depth + 1);
 }
 
 int orc_calibrate_catt(const orc_grid *gin, const orc_pot *pin, double n_solid, int slab_layers,
@@ -704,16 +703,11 @@ int orc_calibrate_catt(const orc_grid *gin, const orc_pot *pin, double n_solid, 
     rc = ORC_EINVAL;
   } else {
     /* integrate piecewise between the kinks (nodes and centres: every half cell) */
-    double fmax = 0.0;
-    for (int k = 0; k <= nscan; ++k) {
-      double v = fabs(calib_force(&cx, y_lo + (y_end - y_lo) * k / nscan));
-      if (v > fmax) fmax = v;
-    }
     double total = 0.0, a = ys;
     while (a < y_end) {
       double b = floor(a * 2.0 + 1.0) * 0.5;
       if (b > y_end) b = y_end;
-      if (b > a) total += adaptive_gl(&cx, a, b, gauss_legendre16(&cx, a, b), 1e-14 * fmax, 0);
+      if (b > a) total += adaptive_gl(&cx, a, b, gauss_legendre16(&cx, a, b), 0);
       a = b;
     }
     double W = -total * g.h[ax]; /* y in cells -> metres */
