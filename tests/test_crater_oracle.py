@@ -61,7 +61,7 @@ def test_flat_slab_is_uniformly_thick_and_uncratered(ndim, n):
     rho = CR.solid_density(grid, node, NS)
     cols = int(np.prod([grid.n[d] + grid.bc[d] for d in range(ndim - 1)]))
     rows = rho.reshape(-1, cols)
-    assert np.allclose(rows[1:layers], q, rtol=1e-12)
+    assert np.allclose(rows[1:layers], q, rtol=1e-12, atol=0)
     assert np.all(rows[layers + 1:] == 0)
 
 
@@ -81,8 +81,8 @@ def test_carved_hole_2d_closed_form():
     assert np.allclose(t, want, rtol=1e-8, atol=0)
     y_s = layers * H
     r = CR.crater(grid, node, NS, y_s, depth_min=1.0 * H)   # below the edge deficit d/2
-    assert r["ncols"] == w + 1 and r["width"] == pytest.approx((w + 1) * H, rel=1e-15)
-    assert r["depth"] == pytest.approx(d * H, rel=1e-8)
+    assert r["ncols"] == w + 1 and r["width"] == pytest.approx((w + 1) * H, rel=1e-15, abs=0)
+    assert r["depth"] == pytest.approx(d * H, rel=1e-8, abs=0)
     r = CR.crater(grid, node, NS, y_s, depth_min=(d / 2 + 0.5) * H)  # above it
     assert r["ncols"] == w - 1
     r = CR.crater(grid, node, NS, y_s, depth_min=(d + 0.5) * H)  # deeper than the hole
@@ -105,7 +105,7 @@ def test_carved_hole_3d_closed_form():
     y_s = layers * H
     r = CR.crater(grid, node, NS, y_s, depth_min=0.5 * H)  # below the corner deficit d/4
     assert r["ncols"] == (w + 1) ** 2
-    assert r["width"] == pytest.approx(2 * math.sqrt((w + 1) ** 2 * H * H / math.pi), rel=1e-14)
+    assert r["width"] == pytest.approx(2 * math.sqrt((w + 1) ** 2 * H * H / math.pi), rel=1e-14, abs=0)
     r = CR.crater(grid, node, NS, y_s, depth_min=1.5 * H)  # between d/4 and d/2
     assert r["ncols"] == (w - 1) ** 2 + 4 * (w - 1)
     r = CR.crater(grid, node, NS, y_s, depth_min=2.5 * H)  # between d/2 and d
@@ -137,7 +137,7 @@ def test_gas_below_the_cut_off_is_not_counted_and_a_clump_above_is():
                       np.concatenate([p.wq, cw]))
     t2 = CR.column_thickness(grid, node2, NS)
     added = 4 * p.wq[0] * 2.0 ** -20 / (NS * H * grid.depth2d)  # atoms / (n_s x column cross-section)
-    assert t2.sum() - t0.sum() == pytest.approx(added, rel=1e-12)
+    assert t2.sum() - t0.sum() == pytest.approx(added, rel=1e-12, abs=0)
     assert np.array_equal(t2[:7], t0[:7]) and np.array_equal(t2[9:], t0[9:])
 
 
@@ -146,10 +146,10 @@ def test_eq5_inverts_gaussian_crater_widths():
     F = np.array([0.1, 0.2, 0.5, 1.0, 2.0, 5.0]) * 1e4
     G = np.where(F > F_th, a * np.sqrt(np.log(np.maximum(F / F_th, 1.0))), 0.0)
     for f, g in zip(F[G > 0], G[G > 0]):
-        assert CR.threshold_fluence(f, g, a) == pytest.approx(F_th, rel=1e-13)
+        assert CR.threshold_fluence(f, g, a) == pytest.approx(F_th, rel=1e-13, abs=0)
     fixed, fit, a_fit = CR.sweep_threshold(F, G, a)
-    assert fixed == pytest.approx(F_th, rel=1e-13)
-    assert fit == pytest.approx(F_th, rel=1e-10) and a_fit == pytest.approx(a, rel=1e-12)
+    assert fixed == pytest.approx(F_th, rel=1e-13, abs=0)
+    assert fit == pytest.approx(F_th, rel=1e-10, abs=0) and a_fit == pytest.approx(a, rel=1e-12, abs=0)
     assert math.isnan(CR.sweep_threshold(F[:1], G[:1], a)[0])
 
 

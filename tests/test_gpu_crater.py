@@ -136,7 +136,7 @@ def test_empty_grid_and_invalid_arguments(B):
     nodes_dev = torch.zeros(grid.nnodes, dtype=torch.int64, device="cuda")
     res, col_w, rho = _measure(B, ctx, nodes_dev, 3 * H, 0.01, 0.5 * H)
     assert res[0]["ncols"] == 63 and res[0]["depth"] == 3 * H and res[0]["t_max"] == 0.0
-    assert res[0]["width"] == pytest.approx(2 * math.sqrt(63 * H * H / math.pi), rel=1e-15)
+    assert res[0]["width"] == pytest.approx(2 * math.sqrt(63 * H * H / math.pi), rel=1e-15, abs=0)
     assert not col_w.any() and not rho.any()
     check_slab(grid, np.zeros(grid.nnodes, np.int64), res[0], col_w, rho, NS, 3 * H, 0.01, 0.5 * H)
     with pytest.raises(B.PicError):

@@ -22,6 +22,7 @@ if not torch.cuda.is_available():
 from oracle import oracle as O  # noqa: E402
 from paper_1502_07722_amd import binding as B  # noqa: E402
 from paper_1502_07722_amd import workloads as W  # noqa: E402
+from parity_util import check_diagnostics  # noqa: E402
 
 DT = 1e-15
 H = W.H_CELL
@@ -74,7 +75,7 @@ def test_morse_force_and_grid_energy_match_oracle(which):
         print(f"max |dF|/F_scale = {np.abs(F - ref).max() / scale:.3e}, violations {bad.sum()}")
         assert not bad.any()
         _, _, _, diags = O.run(grid, pot, DT, parts.cell, parts.off, parts.vel, parts.wq, 1, diag_every=1)
-        assert pe == pytest.approx(diags[0]["pe"], rel=1e-9)
+        assert pe == pytest.approx(diags[0]["pe"], rel=1e-9, abs=0)
 
 
 @pytest.mark.parametrize("which", ["slab2d", "heated2d", "slab3d"])
@@ -94,6 +95,8 @@ def test_morse_100_steps_match_oracle(which):
     Eo = np.array([d["ke"] + d["pe"] for d in od])
     eerr = np.abs(E - Eo).max() / np.abs(Eo).max()
     print(f"position {perr:.3e} cells, velocity {verr:.3e}, energy {eerr:.3e}")
+    worst = check_diagnostics(gd, od, parts, POT.mass)
+    print(f"momentum {worst['p']:.3e} of sum |w m v|, bond {worst['bond']:.3e}")
     assert perr <= 1e-4 and verr <= 1e-4 and eerr <= 1e-4
 
 
@@ -117,4 +120,4 @@ def test_morse_calibration_matches_oracle():
     grid = W.Grid(ndim=2, n=(4, 64), h=(H, H, H), bc=(0, 1))
     c, w = B.pic_calibrate_catt(grid, W.morse_cu(), W.N_SOLID, 8)
     co, wo, _ = O.calibrate_catt(grid, W.morse_cu(), W.N_SOLID, 8)
-    assert c == pytest.approx(co, rel=1e-9) and w == pytest.approx(wo, rel=1e-9)
+    assert c == pytest.approx(co, rel=1e-9, abs=0) and w == pytest.approx(wo, rel=1e-9, abs=0)

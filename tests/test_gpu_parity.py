@@ -23,6 +23,7 @@ if not torch.cuda.is_available():
 from oracle import oracle as O  # noqa: E402
 from paper_1502_07722_amd import binding as B  # noqa: E402
 from paper_1502_07722_amd import workloads as W  # noqa: E402
+from parity_util import check_diagnostics  # noqa: E402
 
 DT = 1e-15
 H = W.H_CELL
@@ -158,7 +159,7 @@ def test_force_matches_oracle(which):
     assert not bad.any()
     # grid energy of the same deposit (the oracle's step-0 diagnostic)
     _, _, _, diags = O.run(grid, pot, DT, parts.cell, parts.off, parts.vel, parts.wq, 1, diag_every=1)
-    assert pe == pytest.approx(diags[0]["pe"], rel=1e-12)
+    assert pe == pytest.approx(diags[0]["pe"], rel=1e-12, abs=0)
 
 
 def test_push_and_kick_match_oracle():
@@ -222,10 +223,12 @@ def test_100_steps_match_oracle(which):
     eerr = np.abs(E - Eo).max() / np.abs(Eo).max()
     kerr = max(abs(a["ke"] - b["ke"]) / abs(b["ke"]) for a, b in zip(gd, od))
     print(f"position {perr:.3e} cells, velocity {verr:.3e}, energy {eerr:.3e}, KE {kerr:.3e}")
+    worst = check_diagnostics(gd, od, parts, pot.mass)
+    print(f"momentum {worst['p']:.3e} of sum |w m v|, bond {worst['bond']:.3e}")
     assert perr <= 1e-4 and verr <= 1e-4 and eerr <= 1e-4
     for a, b in zip(gd, od):
-        assert a["wsum"] == pytest.approx(b["wsum"], rel=1e-12)
-        assert a["pe"] == pytest.approx(b["pe"], rel=1e-4)
+        assert a["wsum"] == pytest.approx(b["wsum"], rel=1e-12, abs=0)
+        assert a["pe"] == pytest.approx(b["pe"], rel=1e-4, abs=0)
 
 
 def test_step_is_bit_identical_to_separate_calls():
@@ -466,7 +469,7 @@ def test_graph_replay_matches_eager_launches(variant):
     for x, y in zip(out[0][0], out[1][0]):
         assert np.array_equal(x, y)
     for a, b in zip(out[0][1], out[1][1]):
-        assert a["ke"] == pytest.approx(b["ke"], rel=1e-12)
+        assert a["ke"] == pytest.approx(b["ke"], rel=1e-12, abs=0)
 
 
 def test_autotune_reads_only_and_keeps_results_identical():

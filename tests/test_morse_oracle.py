@@ -28,12 +28,12 @@ H = 2e-9
 
 def test_morse_closed_forms():
     D, a, r0 = MORSE.D, MORSE.alpha, MORSE.r0
-    assert O.phi(MORSE, r0) == pytest.approx(-D, rel=1e-15)
+    assert O.phi(MORSE, r0) == pytest.approx(-D, rel=1e-15, abs=0)
     assert O.phi_prime(MORSE, r0) == 0.0
     assert abs(O.phi(MORSE, r0 - math.log(2) / a)) < 1e-14 * D
     for x in (3.0, 5.0, 8.0):  # far tail: U ~ -2 D e^{-a (r - r0)}
         r = r0 + x / a
-        assert O.phi(MORSE, r) == pytest.approx(-2 * D * math.exp(-x) + D * math.exp(-2 * x), rel=1e-13)
+        assert O.phi(MORSE, r) == pytest.approx(-2 * D * math.exp(-x) + D * math.exp(-2 * x), rel=1e-13, abs=0)
     for s_rep, c_att in [(1.0, 1.0), (3.0, 0.27)]:
         pot = W.morse_cu(s_rep=s_rep, c_att=c_att)
         for r in np.linspace(0.7, 3.0, 47) * r0:
@@ -42,7 +42,7 @@ def test_morse_closed_forms():
             d = 1e-7 * r
             fd = (O.phi(pot, r + d) - O.phi(pot, r - d)) / (2 * d)
             assert O.phi_prime(pot, r) == pytest.approx(fd, rel=1e-6, abs=1e-9 * D / r0)
-        assert O.phi(pot, r0 * (1 - 1e-12)) == pytest.approx(O.phi(pot, r0 * (1 + 1e-12)), rel=1e-9)
+        assert O.phi(pot, r0 * (1 - 1e-12)) == pytest.approx(O.phi(pot, r0 * (1 + 1e-12)), rel=1e-9, abs=0)
 
 
 def test_quadrature_reproduces_the_lennard_jones_closed_form():
@@ -51,7 +51,7 @@ def test_quadrature_reproduces_the_lennard_jones_closed_form():
         n0 = pot.r0 ** -3
         for x in (0.05, 0.4, 0.9, 1.0, 1.2, 1.8):
             n = x * n0
-            assert O.energy_density_quad(pot, n) == pytest.approx(O.energy_density(pot, n), rel=1e-11)
+            assert O.energy_density_quad(pot, n) == pytest.approx(O.energy_density(pot, n), rel=1e-11, abs=0)
 
 
 @pytest.mark.parametrize("s_rep,c_att", [(1.0, 1.0), (2.0, 0.3)])
@@ -63,7 +63,7 @@ def test_morse_energy_density_derivative_is_chemical_potential(s_rep, c_att):
         mu = O.phi(pot, rbar) - rbar * O.phi_prime(pot, rbar)
         d = 1e-6 * n
         fd = (O.energy_density(pot, n + d) - O.energy_density(pot, n - d)) / (2 * d)
-        assert fd == pytest.approx(mu, rel=1e-6)
+        assert fd == pytest.approx(mu, rel=1e-6, abs=0)
     assert O.energy_density(pot, 0.0) == 0.0
 
 
@@ -80,7 +80,7 @@ def test_morse_small_gradient_force_is_minus_grad_mu(s_rep, c_att):
         G = 1e-5 * n / pot.r0
         F = O.local_force(pot, 1, n, [G])[0]
         d = 1e-4 * n
-        assert F == pytest.approx(-(mu(n + d) - mu(n - d)) / (2 * d) * G, rel=2e-4)
+        assert F == pytest.approx(-(mu(n + d) - mu(n - d)) / (2 * d) * G, rel=2e-4, abs=0)
 
 
 def test_morse_lattice_is_static_and_compression_pushes_down_the_gradient():
@@ -96,4 +96,4 @@ def test_morse_attractive_correction_converges():
     c8, w8, _ = O.calibrate_catt(grid, MORSE, W.N_SOLID, slab_layers=8)
     c16, w16, _ = O.calibrate_catt(grid, MORSE, W.N_SOLID, slab_layers=16)
     assert 0 < c8 < 1 and w8 > MORSE.D
-    assert c16 == pytest.approx(c8, rel=1e-6)
+    assert c16 == pytest.approx(c8, rel=1e-6, abs=0)

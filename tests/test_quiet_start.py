@@ -22,7 +22,7 @@ def test_unjittered_sub_lattice_deposits_uniform_density(ndim, ppc):
         [grid.n[d] + grid.bc[d] for d in range(ndim - 1)])))
     w_exact = W.N_SOLID * (H ** 3 if ndim == 3 else H * H * 1e-9) / ppc
     q = p.wq[0] * 2.0 ** -20 / w_exact
-    assert np.allclose(dens[1:layers], W.N_SOLID * q, rtol=1e-7)  # the split's floor: < 1 unit in W
+    assert np.allclose(dens[1:layers], W.N_SOLID * q, rtol=1e-7, atol=0)  # the split's floor: < 1 unit in W
 
 
 def test_jitter_stays_inside_the_sub_cell_and_bad_ppc_is_refused():
