@@ -98,7 +98,7 @@ typedef struct pic_grid {
  *                      In 2D the unresolved basal axis carries no gradient and
  *                      its force component is dropped.  Solid density sits at
  *                      the potential minimum when r0 = 2^(1/6) n_solid^(-1/3).
- * The reverse-mode entry points support PIC_POT_LJ on the cubic lattice. */
+ * The reverse-mode entry points support both potentials on both lattices. */
 #define PIC_POT_LJ 0
 #define PIC_POT_MORSE 1
 #define PIC_LATTICE_CUBIC 0

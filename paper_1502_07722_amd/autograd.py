@@ -1,10 +1,14 @@
 """torch.autograd bindings of the hand-written reverse mode.
 
-Two Functions, both thin wrappers of the C ABI (every step of the cycle and of
-its reverse runs in the library's kernels):
+Three Functions, all thin wrappers of the C ABI (every step of the cycle and
+of its reverse runs in the library's kernels):
 
   Force       off(0), theta -> per-atom force (pic_deposit + pic_force);
               backward by pic_force_vjp + pic_deposit_vjp.
+  Kick        v, F -> v + frac F/m dt on the evolved components (pic_kick);
+              the map is the identity in v and a scalar multiple of F, so
+              its VJP onto F is pic_kick itself applied to zero velocities
+              with the velocity cotangent in place of the force.
   Trajectory  off(0), v(-1/2), theta -> off(T), v(T - 1/2) over nsteps
               cycles (pic_forward_record, checkpoints every `every` steps);
               backward by pic_backward_record, which recomputes each segment
@@ -65,6 +69,27 @@ class Force(torch.autograd.Function):
         return lam_x, dth.to(fctx.theta_dev), None, None, None
 
 
+class Kick(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, vel, force, ctx: B.Context, cell, wq, frac: float):
+        n = cell.shape[0]
+        dp = B.DeviceParticles(cell, torch.zeros((ctx.grid.ndim, n), dtype=torch.float32, device=vel.device),
+                               vel.detach().contiguous().clone(), wq)
+        ctx.pic_kick(dp, force.detach().contiguous(), frac)
+        fctx.pic = (ctx, cell, wq, float(frac))
+        return dp.vel
+
+    @staticmethod
+    def backward(fctx, g_vel):
+        ctx, cell, wq, frac = fctx.pic
+        nd, n = ctx.grid.ndim, cell.shape[0]
+        g_vel = g_vel.contiguous().float()
+        dp = B.DeviceParticles(cell, torch.zeros((nd, n), dtype=torch.float32, device=g_vel.device),
+                               torch.zeros((3, n), dtype=torch.float32, device=g_vel.device), wq)
+        ctx.pic_kick(dp, g_vel[:nd].contiguous(), frac)
+        return g_vel, dp.vel[:nd].contiguous(), None, None, None, None
+
+
 def _step_untiled(ctx: B.Context, dp):
     node = ctx.pic_deposit(dp)
     F = ctx.pic_force(dp, node)
@@ -119,14 +144,12 @@ def crater_objective(ctx: B.Context, cell, off0, v_thermal, xi, sigma_ref, fluen
     """J(theta, F) on device tensors (cell int32 [n], off0 float32 [ndim][n],
     v_thermal / xi float32 [3][n], sigma_ref float32 [n], wq int32 [n]);
     fluence is a float64 scalar tensor.  Returns (J, final offsets, cells)."""
-    grid, pot, dt = ctx.grid, ctx.pot, ctx.dt
+    grid = ctx.grid
     nd = grid.ndim
     scale = torch.sqrt(fluence / fluence_ref).float()
     v0 = v_thermal + (sigma_ref * scale)[None, :] * xi
     F0 = Force.apply(off0, theta, ctx, cell, wq)
-    kick = torch.zeros_like(v0)
-    kick[:nd] = F0 * (0.5 * dt / pot.mass)
-    vh = v0 - kick
+    vh = Kick.apply(v0, F0, ctx, cell, wq, -0.5)
     offT, velT, cellT = Trajectory.apply(off0, vh, theta, ctx, cell, wq, nsteps, every)
     ax = nd - 1
     lateral = 1
