@@ -288,13 +288,14 @@ __global__ void __launch_bounds__(256) k_force_push(Geo g, Pot P, DiagC dc, int6
   if (DIAG) block_reduce_store<6>(acc, partial + (int64_t)blockIdx.x * 8);
 }
 
-// Chemical potential mu / D of the Morse potential at reduced density x > 0.
-// Cubic: rho = x^(-1/3) = rbar / r0, mu = M (U - rbar U') / D plus the altered
-// branch's constant above x = 1 (M = c_att below, s_rep above).  Hexagonal:
-// twice that at the neighbour distance a = 2^(1/6) rbar, kink at x = sqrt(2).
-__device__ __forceinline__ double mu_morse(const DiagC &dc, double x) {
+// Chemical potential mu / D of the Morse potential at reduced density x > 0,
+// given t = x^(1/3).  Cubic: rho = 1 / t = rbar / r0, mu = M (U - rbar U') / D
+// plus the altered branch's constant above x = 1 (M = c_att below, s_rep
+// above).  Hexagonal: twice that at the neighbour distance a = 2^(1/6) rbar,
+// kink at x = sqrt(2).
+__device__ __forceinline__ double mu_morse_t(const DiagC &dc, double t) {
   const bool hcp = dc.lattice == 1;
-  const double rho = (hcp ? 1.122462048309373 : 1.0) * pow(x, -1.0 / 3.0);
+  const double rho = (hcp ? 1.122462048309373 : 1.0) / t;
   const double e = exp(-dc.mA * (rho - 1.0));
   const double u = e * (e - 2.0);                 // U / D
   const double du = 2.0 * dc.mA * e * (1.0 - e);  // r0 U'(r) / D
@@ -302,23 +303,40 @@ __device__ __forceinline__ double mu_morse(const DiagC &dc, double x) {
   return rho >= 1.0 ? m * dc.c_att * (u - rho * du) : m * (dc.s_rep * (u - rho * du) + (dc.s_rep - dc.c_att));
 }
 
+// Integral of mu over [a, b] in x, one 16-point Gauss-Legendre panel.
 __device__ __forceinline__ double gauss16(const DiagC &dc, const Quad16 &q, double a, double b) {
   const double h = 0.5 * (b - a), m = 0.5 * (a + b);
   double acc = 0.0;
-  for (int i = 0; i < 16; ++i) acc += q.w[i] * mu_morse(dc, m + h * q.x[i]);
+  for (int i = 0; i < 16; ++i) acc += q.w[i] * mu_morse_t(dc, cbrt(m + h * q.x[i]));
+  return h * acc;
+}
+
+// Integral of mu over [0, b] in t = x^(1/3) (dx = 3 t^2 dt), two 16-point
+// Gauss-Legendre panels: in x the integrand is flat near 0 and turns sharply
+// where the neighbour distance nears r0 (one panel in x is only good to about
+// 1e-6); in t it is smooth (two panels: 4e-13 relative).
+__device__ __forceinline__ double gauss16_cbrt(const DiagC &dc, const Quad16 &q, double b) {
+  const double h = 0.25 * cbrt(b);
+  double acc = 0.0;
+  for (int k = 0; k < 2; ++k) {
+    const double m = (2 * k + 1) * h;
+    for (int i = 0; i < 16; ++i) {
+      const double t = m + h * q.x[i];
+      acc += q.w[i] * 3.0 * t * t * mu_morse_t(dc, t);
+    }
+  }
   return h * acc;
 }
 
 // Energy density of the pair potential in units of D r0^-3 at reduced density x:
 // e'(x) = mu: plain L-J e(x) = 13/5 x^5 - 14/3 x^3, branches switch at x = 1;
-// Morse: the integral of mu from 0 to x (Gauss-Legendre, split at x = 1 where
-// mu has a kink).
+// Morse: the integral of mu from 0 to x, split at x = 1 where mu has a kink.
 __device__ __forceinline__ double eps_hat(const DiagC &dc, const Quad16 &q, double x) {
   const bool hcp = dc.lattice == 1;
   const double xk = hcp ? 1.4142135623730951 : 1.0;  // where the neighbour distance is r0
   if (dc.kind == 1) {
     if (!(x > 0.0)) return 0.0;
-    double e = gauss16(dc, q, 0.0, fmin(x, xk));
+    double e = gauss16_cbrt(dc, q, fmin(x, xk));
     if (x > xk) e += gauss16(dc, q, xk, x);
     return e;
   }
