@@ -2,8 +2,10 @@
 
 One "step" is one full pass of the method over all particles: deposit ->
 density and gradient -> gather -> eq. (1)-(3) force -> leapfrog push (plus
-the diagnostics reductions every 100 steps).  The timed region is
-pic_step(K) with the particles already resident in HBM.  Prints one JSON line.
+the FP64 diagnostics reductions every 100 steps, and on the first and the
+last step of shorter runs).  The timed region is one pic_step(K) call with
+the particles already resident in HBM: import into the binned store, K
+steps, export back to the caller's arrays.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload large|heated|small]
 """
@@ -52,6 +54,12 @@ def measured_traffic(workload):
     return rec["traffic_bytes_per_launch"]
 
 
+def diag_period(steps):
+    """FP64 diagnostics every 100 steps, and at least on the first and the
+    last step of a run (a 20-step run has them on steps 0 and 19)."""
+    return max(1, min(100, steps - 1))
+
+
 TUNE_AFTER = 12  # steps a copy of the start state runs before the autotuner probes it
 
 
@@ -78,14 +86,54 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, pot, seconds_hint=10.0):
-    """The FP64 oracle, single thread, on a bounded window of the same workload:
-    a 256-column strip of the slab through the beam centre, periodic in x."""
-    import numpy as np
+def host_info():
+    """Host cores and CPU model (the CPU baseline's machine)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": usable, "cpu_count": os.cpu_count(), "model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def _time_oracle(g, pot, dt, cell, off, vel, wq, threads, seconds):
+    """Particle-steps/s of the oracle's run on prepared arrays (advanced in
+    place): one step to size the run, then as many steps as fit `seconds`."""
     from oracle import oracle as O
+    t0 = time.perf_counter()
+    O.run(g, pot, dt, cell, off, vel, wq, 1, threads=threads, copy=False)
+    t1 = time.perf_counter() - t0
+    steps = max(1, min(20, int(seconds / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    O.run(g, pot, dt, cell, off, vel, wq, steps, threads=threads, copy=False)
+    return cell.shape[0] * steps / (time.perf_counter() - t0), steps
+
+
+def cpu_baseline(wl, pot, seconds_hint=10.0):
+    """The FP64 oracle as it stands, timed on this host's cores: on all usable
+    cores (its OpenMP build: particles and grid loops split over threads,
+    integer node sums, so the state is the serial one's) on the whole slab,
+    and single-threaded (the serial build the tests use) on a 256-column strip
+    of the same slab through the beam centre, periodic in x.  Each leg runs
+    about `seconds_hint` seconds after a one-step sizing run."""
+    import numpy as np
     from paper_1502_07722_amd import workloads as W
 
     g, p = wl.grid, wl.parts
+    host = host_info()
+    threads = int(host["omp_num_threads"] or host["nproc"] or 1)
+    full = (p.cell.copy(), p.off.astype(np.float64), p.vel.astype(np.float64))
+    rate_all, steps_all = _time_oracle(g, pot, wl.dt, *full, p.wq, threads, seconds_hint)
+    del full
     nx = g.n[0]
     width = min(256, nx)
     x0 = nx // 2 - width // 2
@@ -93,21 +141,17 @@ def cpu_baseline(wl, pot, seconds_hint=10.0):
     rest = p.cell.astype(np.int64) // nx
     sel = (i >= x0) & (i < x0 + width)
     cell = ((i[sel] - x0) + width * rest[sel]).astype(np.int32)
-    off = p.off[:, sel]
-    vel = p.vel[:, sel].astype(np.float64)
-    wq = p.wq[sel]
     gs = W.Grid(ndim=g.ndim, n=(width,) + tuple(g.n[1:]), h=g.h, bc=g.bc, depth2d=g.depth2d)
     nsample = int(cell.shape[0])
-    t0 = time.perf_counter()
-    O.run(gs, pot, wl.dt, cell, off, vel, wq, 1)
-    t1 = time.perf_counter()
-    steps = max(1, min(8, int(seconds_hint / max(t1 - t0, 1e-3))))
-    t0 = time.perf_counter()
-    O.run(gs, pot, wl.dt, cell, off, vel, wq, steps)
-    dt = time.perf_counter() - t0
-    return {"value": nsample * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{width}x{g.n[1]}-cell strip of the same slab through the beam centre "
-                      f"({nsample} particles), {steps} FP64 steps, single thread"}
+    rate_1, steps_1 = _time_oracle(gs, pot, wl.dt, cell, np.ascontiguousarray(p.off[:, sel], dtype=np.float64),
+                                   np.ascontiguousarray(p.vel[:, sel], dtype=np.float64),
+                                   np.ascontiguousarray(p.wq[sel]), 0, seconds_hint)
+    return {"value": rate_all, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"the whole slab ({p.n} particles), {steps_all} FP64 steps, {threads} OpenMP threads",
+            "host": host,
+            "single_thread": {"value": rate_1, "unit": "particle-steps/s", "cores": 1,
+                              "sample": f"{width}x{g.n[1]}-cell strip of the same slab through the beam centre "
+                                        f"({nsample} particles), {steps_1} FP64 steps"}}
 
 
 def run_sweep(steps, warmup, log_fn=log):
@@ -150,12 +194,29 @@ def run_sweep(steps, warmup, log_fn=log):
     t_plain = time.perf_counter() - t0
     del plain_ctx
     log_fn(f"plain loop: {steps} steps x {len(wls)} slabs in {t_plain:.3f} s")
-    # batched
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         bctx = B.BatchContext([w.grid for w in wls], pot, dt, [w.parts.n for w in wls], stream=stream)
         tuning = tune(bctx, starts)
         log_fn(f"autotuned tiling {tuning}")
+        # plain loop with the batched run's tiling and graph replay on a created
+        # stream: the gain from batching alone
+        tctx = [B.Context(w.grid, pot, dt, w.parts.n, stream=stream) for w in wls]
+        for c in tctx:
+            c.pic_set_tiling(tuning["tile"], tuning["halo"], tuning["chunk"], -1)
+        tuned = [s.clone() for s in starts]
+        for c, p in zip(tctx, tuned):
+            c.pic_step(p, warmup)
+        tuned = [s.clone() for s in starts]
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for c, p in zip(tctx, tuned):
+            c.pic_step(p, steps)
+        stream.synchronize()
+        t_tuned = time.perf_counter() - t0
+        del tctx
+        log_fn(f"plain loop, tuned tiles and graphs: {steps} steps x {len(wls)} slabs in {t_tuned:.3f} s")
+        # batched
         batch = [s.clone() for s in starts]
         bctx.pic_step_batch(batch, warmup)
         batch = [s.clone() for s in starts]
@@ -173,12 +234,23 @@ def run_sweep(steps, warmup, log_fn=log):
     log_fn(f"batched: {steps} steps in {t_batch:.3f} s")
     same = all(torch.equal(a.cell, b.cell) and torch.equal(a.off, b.off) and torch.equal(a.vel, b.vel)
                for a, b in zip(plain, batch))
+    same = same and all(torch.equal(a.cell, b.cell) and torch.equal(a.off, b.off) and torch.equal(a.vel, b.vel)
+                        for a, b in zip(tuned, batch))
+    roof = 1.0 / (52 * N + 16 * sum(B.pic_num_nodes(w.grid) for w in wls)) * HBM_PEAK_GBS * 1e9 * N
     return {"workload": f"sweep of {len(wls)} slabs, widths 256-2048, depths 128-512 rows, 16-32 ppc, "
                         f"0.2-5 J/cm^2, {steps} steps",
             "particles": N, "steps": steps,
             "plain_particle_steps_per_s": N * steps / t_plain,
+            "plain_tuned_particle_steps_per_s": N * steps / t_tuned,
             "batched_particle_steps_per_s": N * steps / t_batch,
-            "speedup": t_plain / t_batch, "bit_identical": bool(same), "tuning": tuning,
+            "speedup": t_plain / t_batch, "speedup_over_tuned_plain": t_tuned / t_batch,
+            "roofline_particle_steps_per_s": roof,
+            "speedup_bound": {"value": roof / (N * steps / t_plain),
+                              "note": "batched at 100 % of the 8 TB/s roofline (52 B per particle + 16 B per "
+                                      "node per step) over the measured plain loop: no batching can pass it"},
+            "plain": "one context per slab, per-step launches, default tiles, no graph",
+            "plain_tuned": "one context per slab on a created stream, the batched run's tiling, graph replay",
+            "bit_identical": bool(same), "tuning": tuning,
             "slab_particles": [w.parts.n for w in wls],
             "crater_end_of_run": {"note": f"after {steps} fs the surface has not settled: the measurement path, "
                                           "not a threshold claim",
@@ -355,6 +427,7 @@ def run_slab(name, steps, warmup, log_fn=log, variant="lj"):
     c_att, _ = B.pic_calibrate_catt(wl.grid, base, W.N_SOLID, 8)
     pot = dataclasses.replace(base, c_att=c_att)
     N = wl.parts.n
+    diag_every = diag_period(steps)
     dev = torch.device("cuda:0")
     # a created stream: plain steps replay as HIP graphs there
     stream = torch.cuda.Stream(device=dev)
@@ -366,12 +439,12 @@ def run_slab(name, steps, warmup, log_fn=log, variant="lj"):
         log_fn(f"{wl.name}: autotuned tiling {tuning}")
         start = dp.clone()
         if warmup:
-            ctx.pic_step(dp, warmup, 100)
+            ctx.pic_step(dp, warmup, diag_every)
         dp = start.clone()
         stream.synchronize()
         log_fn(f"{wl.name}: timing {steps} steps")
         t0 = time.perf_counter()
-        diags = ctx.pic_step(dp, steps, 100)
+        diags = ctx.pic_step(dp, steps, diag_every)
         stream.synchronize()
         elapsed = time.perf_counter() - t0
         # the same run again with HIP events on every launch (no graphs):
@@ -380,7 +453,7 @@ def run_slab(name, steps, warmup, log_fn=log, variant="lj"):
         ctx.pic_set_timing(True)
         stream.synchronize()
         t1 = time.perf_counter()
-        ctx.pic_step(dp, steps, 100)
+        ctx.pic_step(dp, steps, diag_every)
         stream.synchronize()
         elapsed_events = time.perf_counter() - t1
         timing = ctx.pic_get_timing()
@@ -403,14 +476,32 @@ def run_slab(name, steps, warmup, log_fn=log, variant="lj"):
                 "bytes_per_node": 16, "avg_launch_ms": avg_s * 1e3,
                 "phases_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in timing.items() if isinstance(v, tuple)},
                 "drifters_last_step": timing.get("drifters_last"), "items_last_step": timing.get("items_last")}
+    one_time_ms = sum(timing.get(k, (0.0, 0))[0] for k in ("import_export", "deposit"))
+    roofline["whole_call"] = {
+        "achieved": launch_bytes * steps / elapsed / 1e9, "frac": launch_bytes * steps / elapsed / 1e9 / HBM_PEAK_GBS,
+        "unit": "GB/s", "one_time_ms": one_time_ms,
+        "steady_particle_steps_per_s": N * steps / max(elapsed - one_time_ms * 1e-3, 1e-9),
+        "basis": "algorithmic bytes x steps / the timed pic_step call (import into the binned store, first "
+                 "deposit, steps, diagnostics, export); one_time_ms: import/export and first deposit (events)"}
     res = {"workload": wl.name + ("" if variant == "lj" else "_" + variant), "particles": N,
            "value": N * steps / elapsed, "ms_per_step": elapsed / steps * 1e3,
            "potential": {"lj": "lennard-jones, cubic", "morse": "morse, cubic", "hcp": "lennard-jones, hcp"}[variant],
            "elapsed_s": elapsed, "roofline": roofline, "c_att": c_att, "tiling": tuning,
-           "ms_per_step_with_events": elapsed_events / steps * 1e3, "crater": crater}
+           "ms_per_step_with_events": elapsed_events / steps * 1e3, "crater": crater, "diag_every": diag_every}
     del ctx, dp, start
     torch.cuda.empty_cache()
     return res, wl, pot, diags
+
+
+def energy_check(diags):
+    """Total energy KE + PE on the first and the last diagnostic step of the
+    timed run, and its change relative to the first step's kinetic energy."""
+    if len(diags) < 2:
+        return None
+    a, b = diags[0], diags[-1]
+    Ea, Eb = a["ke"] + a["pe"], b["ke"] + b["pe"]
+    return {"step_first": int(a["step"]), "step_last": int(b["step"]), "E_first": Ea, "E_last": Eb,
+            "dE_over_KE0": (Eb - Ea) / a["ke"], "KE_first": a["ke"], "KE_last": b["ke"]}
 
 
 def main():
@@ -512,11 +603,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "particles": N, "cells": list(wl.grid.n[:nd]),
                    "ppc": int(round(N / (wl.slab_rows * np.prod(wl.grid.n[: nd - 1])))),
-                   "dt_s": wl.dt, "diag_every": 100, "c_att": c_att, "tiling": res["tiling"],
+                   "dt_s": wl.dt, "diag_every": res["diag_every"], "c_att": c_att, "tiling": res["tiling"],
                    "state": "int32 cell + f32 offsets/velocities, int64 fixed-point deposit"},
         "roofline": roofline,
-        "energy_check": {"E_first": diags[0]["ke"] + diags[0]["pe"], "E_last": diags[-1]["ke"] + diags[-1]["pe"]}
-        if diags else None,
+        "energy_check": energy_check(diags),
     }
     if args.workload == "large" and not args.no_configs:
         # the other single-slab configs, each with its own roofline fraction

@@ -20,15 +20,22 @@ ORC_OK, ORC_EINVAL, ORC_ERANGE, ORC_ECFL, ORC_EOVERFLOW = 0, 1, 2, 3, 4
 W_UNIT = 2.0 ** -20
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA target)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
+LIB_OMP = os.path.join(HERE, "_liboracle_omp.so")
+
+
+def build(force: bool = False, threaded: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA target).
+    threaded: the same source with -fopenmp (its particle and grid loops split
+    over threads), used only to time the oracle on all host cores; the tests
+    use the serial build."""
+    out = LIB_OMP if threaded else LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < max(
             os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "pic_oracle.h"))):
-        tmp = f"{LIB}.tmp{os.getpid()}"  # parallel test workers may build at once
+        tmp = f"{out}.tmp{os.getpid()}"  # parallel test workers may build at once
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
-                               "-ffp-contract=off", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+                               "-ffp-contract=off", *(["-fopenmp"] if threaded else []), "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class _Grid(C.Structure):
@@ -48,43 +55,58 @@ class _Diag(C.Structure):
 
 
 _lib = None
+_lib_omp = None
+
+
+def lib_threaded(threads: int):
+    """The OpenMP build of the oracle with `threads` threads."""
+    global _lib_omp
+    if _lib_omp is None:
+        _lib_omp = C.CDLL(build(threaded=True))
+        _declare(_lib_omp)
+    C.CDLL("libgomp.so.1").omp_set_num_threads(int(threads))
+    return _lib_omp
 
 
 def lib():
     global _lib
     if _lib is None:
         _lib = C.CDLL(build())
-        P = C.POINTER
-        d, i64, i32 = C.c_double, C.c_int64, C.c_int32
-        _lib.orc_num_nodes.restype = i64
-        _lib.orc_num_nodes.argtypes = [P(_Grid)]
-        _lib.orc_num_cells.restype = i64
-        _lib.orc_num_cells.argtypes = [P(_Grid)]
-        _lib.orc_deposit.argtypes = [P(_Grid), i64, P(i32), P(d), P(i32), P(i64), P(d)]
-        _lib.orc_density.argtypes = [P(_Grid), P(d), P(d)]
-        _lib.orc_gradient.argtypes = [P(_Grid), P(d), P(d)]
-        _lib.orc_gather.argtypes = [P(_Grid), P(d), P(d), i32, P(d), P(d), P(d)]
-        _lib.orc_neighbour_distances.argtypes = [P(_Pot), d, d, P(d), P(d)]
-        _lib.orc_local_force.argtypes = [P(_Pot), C.c_int, d, P(d), P(d)]
-        _lib.orc_phi_prime.restype = d
-        _lib.orc_phi_prime.argtypes = [P(_Pot), d]
-        _lib.orc_phi.restype = d
-        _lib.orc_phi.argtypes = [P(_Pot), d]
-        _lib.orc_energy_density.restype = d
-        _lib.orc_energy_density.argtypes = [P(_Pot), d]
-        _lib.orc_hcp_direction.restype = None
-        _lib.orc_hcp_direction.argtypes = [C.c_int, P(d)]
-        _lib.orc_energy_density_quad.restype = d
-        _lib.orc_energy_density_quad.argtypes = [P(_Pot), d]
-        _lib.orc_forces.argtypes = [P(_Grid), P(_Pot), P(d), i64, P(i32), P(d), P(d)]
-        _lib.orc_push_one.argtypes = [P(_Grid), P(_Pot), d, P(d), P(i32), P(d), P(d)]
-        _lib.orc_kick.argtypes = [P(_Grid), P(_Pot), d, d, i64, P(d), P(d)]
-        _lib.orc_run.argtypes = [P(_Grid), P(_Pot), d, i64, P(i32), P(d), P(d), P(i32), C.c_int,
-                                 C.c_int, P(_Diag)]
-        _lib.orc_calibrate_catt.argtypes = [P(_Grid), P(_Pot), d, C.c_int, C.c_int, P(d), P(d), P(d)]
-        _lib.orc_functional.restype = d
-        _lib.orc_functional.argtypes = [P(_Grid), i64, P(i32), P(d), P(i32), d, d]
+        _declare(_lib)
     return _lib
+
+
+def _declare(_lib):
+    P = C.POINTER
+    d, i64, i32 = C.c_double, C.c_int64, C.c_int32
+    _lib.orc_num_nodes.restype = i64
+    _lib.orc_num_nodes.argtypes = [P(_Grid)]
+    _lib.orc_num_cells.restype = i64
+    _lib.orc_num_cells.argtypes = [P(_Grid)]
+    _lib.orc_deposit.argtypes = [P(_Grid), i64, P(i32), P(d), P(i32), P(i64), P(d)]
+    _lib.orc_density.argtypes = [P(_Grid), P(d), P(d)]
+    _lib.orc_gradient.argtypes = [P(_Grid), P(d), P(d)]
+    _lib.orc_gather.argtypes = [P(_Grid), P(d), P(d), i32, P(d), P(d), P(d)]
+    _lib.orc_neighbour_distances.argtypes = [P(_Pot), d, d, P(d), P(d)]
+    _lib.orc_local_force.argtypes = [P(_Pot), C.c_int, d, P(d), P(d)]
+    _lib.orc_phi_prime.restype = d
+    _lib.orc_phi_prime.argtypes = [P(_Pot), d]
+    _lib.orc_phi.restype = d
+    _lib.orc_phi.argtypes = [P(_Pot), d]
+    _lib.orc_energy_density.restype = d
+    _lib.orc_energy_density.argtypes = [P(_Pot), d]
+    _lib.orc_hcp_direction.restype = None
+    _lib.orc_hcp_direction.argtypes = [C.c_int, P(d)]
+    _lib.orc_energy_density_quad.restype = d
+    _lib.orc_energy_density_quad.argtypes = [P(_Pot), d]
+    _lib.orc_forces.argtypes = [P(_Grid), P(_Pot), P(d), i64, P(i32), P(d), P(d)]
+    _lib.orc_push_one.argtypes = [P(_Grid), P(_Pot), d, P(d), P(i32), P(d), P(d)]
+    _lib.orc_kick.argtypes = [P(_Grid), P(_Pot), d, d, i64, P(d), P(d)]
+    _lib.orc_run.argtypes = [P(_Grid), P(_Pot), d, i64, P(i32), P(d), P(d), P(i32), C.c_int,
+                             C.c_int, P(_Diag)]
+    _lib.orc_calibrate_catt.argtypes = [P(_Grid), P(_Pot), d, C.c_int, C.c_int, P(d), P(d), P(d)]
+    _lib.orc_functional.restype = d
+    _lib.orc_functional.argtypes = [P(_Grid), i64, P(i32), P(d), P(i32), d, d]
 
 
 def _ptr(a, ctype):
@@ -252,14 +274,23 @@ def kick(grid, pot, dt, frac, F, vel):
 DIAG_FIELDS = ("ke", "pe", "px", "py", "pz", "wsum", "bond", "step")
 
 
-def run(grid, pot, dt, cell, off, vel, wq, nsteps, diag_every=0, quantized=True):
+def run(grid, pot, dt, cell, off, vel, wq, nsteps, diag_every=0, quantized=True, threads=0, copy=True):
     """Advance a copy of the state nsteps leapfrog cycles (vel = v(n-1/2)).
-    Returns (cell, off, vel, diags) with diags a list of dicts."""
-    cell, off, wq, vel = _state(np.array(cell, copy=True), np.array(off, dtype=np.float64, copy=True),
-                                wq, np.array(vel, dtype=np.float64, copy=True))
+    Returns (cell, off, vel, diags) with diags a list of dicts.  threads > 0
+    runs the OpenMP build with that many threads (same state bits when
+    quantized; diagnostic sums in another order).  copy=False advances
+    cell (int32), off and vel (float64, C-contiguous) in place."""
+    L = lib_threaded(threads) if threads > 0 else lib()
+    if copy:
+        cell, off, vel = np.array(cell, copy=True), np.array(off, dtype=np.float64, copy=True), \
+            np.array(vel, dtype=np.float64, copy=True)
+    elif not (cell.dtype == np.int32 and off.dtype == np.float64 and vel.dtype == np.float64
+              and cell.flags.c_contiguous and off.flags.c_contiguous and vel.flags.c_contiguous):
+        raise ValueError("copy=False needs int32 cell and C-contiguous float64 off and vel")
+    cell, off, wq, vel = _state(cell, off, wq, vel)
     nd = 0 if diag_every <= 0 else (nsteps + diag_every - 1) // diag_every
     diags = (_Diag * max(nd, 1))()
-    rc = lib().orc_run(C.byref(grid_struct(grid, quantized)), C.byref(pot_struct(pot)), float(dt),
+    rc = L.orc_run(C.byref(grid_struct(grid, quantized)), C.byref(pot_struct(pot)), float(dt),
                        cell.shape[0], _ptr(cell, C.c_int32), _ptr(off, C.c_double),
                        _ptr(vel, C.c_double), _ptr(wq, C.c_int32), int(nsteps), int(diag_every),
                        diags if nd > 0 else None)

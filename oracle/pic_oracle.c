@@ -115,13 +115,20 @@ int orc_deposit(const orc_grid *g, int64_t np, const int32_t *cell, const double
   for (int64_t p = 0; p < np; ++p) {
     if (cell[p] < 0 || cell[p] >= nc) { if (own) free(acc); return ORC_ERANGE; }
     if (wq[p] < 0) { if (own) free(acc); return ORC_EOVERFLOW; }
+    for (int d = 0; d < nd; ++d) {
+      double f = off[(int64_t)d * np + p];
+      if (!(f >= 0.0 && f < 1.0)) { if (own) free(acc); return ORC_ERANGE; }
+    }
+  }
+  /* Threaded build only (-fopenmp; the pragmas are inert otherwise): integer
+   * sums are order free, so particles may be split over threads; the FP64
+   * unquantized sums stay in particle order. */
+#pragma omp parallel for schedule(static) if (g->quantized)
+  for (int64_t p = 0; p < np; ++p) {
     int idx[3];
     cell_to_index(g, cell[p], idx);
     double f[3];
-    for (int d = 0; d < nd; ++d) {
-      f[d] = off[(int64_t)d * np + p];
-      if (!(f[d] >= 0.0 && f[d] < 1.0)) { if (own) free(acc); return ORC_ERANGE; }
-    }
+    for (int d = 0; d < nd; ++d) f[d] = off[(int64_t)d * np + p];
     for (int k = 0; k < ncorner; ++k) {
       int a[3] = {idx[0], idx[1], idx[2]};
       for (int d = 0; d < nd; ++d) a[d] += (k >> d) & 1;
@@ -137,6 +144,7 @@ int orc_deposit(const orc_grid *g, int64_t np, const int32_t *cell, const double
           int64_t upper = (part * u) >> 16;
           part = ((k >> d) & 1) ? upper : part - upper;
         }
+#pragma omp atomic
         acc[node] += part;
       } else {
         double wgt = (double)wq[p];
@@ -153,6 +161,7 @@ int orc_deposit(const orc_grid *g, int64_t np, const int32_t *cell, const double
 
 void orc_density(const orc_grid *g, const double *node_f, double *dens) {
   const int64_t nn = orc_num_nodes(g);
+#pragma omp parallel for schedule(static)
   for (int64_t k = 0; k < nn; ++k) dens[k] = node_f[k] * ORC_WUNIT / node_volume(g, k);
 }
 
@@ -167,6 +176,7 @@ void orc_density(const orc_grid *g, const double *node_f, double *dens) {
 void orc_gradient(const orc_grid *g, const double *dens, double *G) {
   const int64_t nc = orc_num_cells(g);
   const int nd = g->ndim, ncorner = 1 << nd;
+#pragma omp parallel for schedule(static)
   for (int64_t c = 0; c < nc; ++c) {
     int idx[3];
     cell_to_index(g, (int32_t)c, idx);
@@ -543,6 +553,8 @@ int orc_run(const orc_grid *g, const orc_pot *p, double dt, int64_t np, int32_t 
     orc_gradient(g, dens, G);
     int want = diag && diag_every > 0 && (s % diag_every) == 0;
     double ke = 0, px = 0, py = 0, pz = 0, ws = 0, bond = 0;
+    int64_t first_bad = np;
+#pragma omp parallel for schedule(static) reduction(+ : ke, px, py, pz, ws, bond) reduction(min : first_bad)
     for (int64_t i = 0; i < np; ++i) {
       double f[3] = {0, 0, 0}, v[3], n_p, G_p[3] = {0, 0, 0}, Fi[3] = {0, 0, 0};
       for (int d = 0; d < nd; ++d) f[d] = off[(int64_t)d * np + i];
@@ -563,13 +575,17 @@ int orc_run(const orc_grid *g, const orc_pot *p, double dt, int64_t np, int32_t 
         ws += w;
         bond += w * local_bond_energy(p, nd, n_p, G_p);
       }
-      rc = orc_push_one(g, p, dt, Fi, &cell[i], f, v);
-      if (rc) break;
+      if (orc_push_one(g, p, dt, Fi, &cell[i], f, v) != ORC_OK) {
+        if (i < first_bad) first_bad = i;
+        continue;
+      }
       for (int d = 0; d < nd; ++d) off[(int64_t)d * np + i] = f[d];
       for (int d = 0; d < 3; ++d) vel[(int64_t)d * np + i] = v[d];
     }
+    if (first_bad < np) rc = ORC_ECFL;
     if (want && rc == ORC_OK) {
       double pe = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : pe)
       for (int64_t k = 0; k < nn; ++k) pe += node_volume(g, k) * orc_energy_density(p, dens[k]);
       orc_diag *o = &diag[di++];
       o->ke = ke; o->pe = pe; o->px = px; o->py = py; o->pz = pz; o->wsum = ws; o->bond = bond;

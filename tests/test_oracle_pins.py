@@ -678,3 +678,22 @@ def test_kinetic_energy_obeys_the_discrete_work_theorem(ndim):
         scale = (w * np.abs(0.5 * (Fa + Fb) * vh).sum(axis=0) * dt).sum()
         assert abs((KE[s + 1] - KE[s]) - (work + corr)) <= 1e-9 * scale
         assert abs(work) > 1e-3 * scale  # a real exchange of energy
+
+
+def test_threaded_oracle_build_gives_the_same_state():
+    """The OpenMP build (used only to time the oracle on all host cores)
+    advances the same state bit for bit with the fixed-point deposit (integer
+    node sums, per-particle updates); its diagnostic sums differ only in
+    summation order."""
+    wl = W.cfg_small_slab()
+    g, p = wl.grid, wl.parts
+    pot = W.Potential(c_att=0.27)
+    vel = p.vel.astype(np.float64)
+    a = O.run(g, pot, 1e-15, p.cell, p.off, vel, p.wq, 12, diag_every=4)
+    b = O.run(g, pot, 1e-15, p.cell, p.off, vel, p.wq, 12, diag_every=4, threads=4)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    for da, db in zip(a[3], b[3]):
+        for k in ("ke", "pe", "bond", "wsum"):
+            assert db[k] == pytest.approx(da[k], rel=1e-12, abs=0)
+        for k in ("px", "py", "pz"):
+            assert abs(db[k] - da[k]) <= 1e-12 * (p.wq * O.W_UNIT * pot.mass * np.abs(vel)).sum()
