@@ -766,7 +766,7 @@ int step_tiled(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t nsteps, Dia
   {
     PhaseTimer t(ctx, 5);
     launch_import(ctx->stream, nd, ctx->sd.data(), cps.data(), ctx->nslab, ctx->bb, b, ctx->chunk, ctx->st[cur],
-                  ctx->err);
+                  ctx->st[1 - cur].oidx, ctx->err);
   }
   if ((rc = check_launch(ctx, "binning"))) return rc;
   if ((rc = read_device_error(ctx))) return rc;
@@ -855,7 +855,7 @@ int step_tiled(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t nsteps, Dia
   }
   if (export_back) {
     PhaseTimer t(ctx, 5);
-    for (int k = 0; k < ctx->nslab; ++k) launch_export(ctx->stream, nd, ctx->sd[k], ctx->st[cur], cps[k]);
+    for (int k = 0; k < ctx->nslab; ++k) launch_export(ctx->stream, nd, ctx->sd[k], ctx->st[cur], ctx->bb, cps[k]);
   }
   ctx->last_nodes = ctx->n3[nsteps % 3];
   ctx->last_step = nsteps - 1;
@@ -1195,7 +1195,8 @@ int pic_forward_record(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, int32
   const Batch b = batch_of(ctx, n);
   ensure_grid_blocks(ctx);
   const PartPtrs cp = ptrs(p);
-  launch_import(ctx->stream, nd, ctx->sd.data(), &cp, 1, ctx->bb, b, ctx->chunk, ctx->st[0], ctx->err);
+  launch_import(ctx->stream, nd, ctx->sd.data(), &cp, 1, ctx->bb, b, ctx->chunk, ctx->st[0], ctx->st[1].oidx,
+                ctx->err);
   if ((rc = check_launch(ctx, "binning"))) return rc;
   if ((rc = read_device_error(ctx))) return rc;
   int cur = 0;
@@ -1248,7 +1249,7 @@ int pic_forward_record(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, int32
     ++since_bin;
   }
   const Store &S = ctx->st[cur];
-  launch_export(ctx->stream, nd, ctx->sd[0], S, cp);
+  launch_export(ctx->stream, nd, ctx->sd[0], S, ctx->bb, cp);
   ctx->last_nodes = ctx->n3[nsteps % 3];
   ctx->last_step = nsteps - 1;
   if ((rc = check_launch(ctx, "export"))) return rc;

@@ -118,11 +118,14 @@ void launch_reduce_diag(hipStream_t s, const double *part_p, int nblk_p, const d
 
 // tiled path (pic_tiled.hip)
 size_t window_lds_bytes(const TileGeo &tg, int ndim);
+// stage: int[store capacity] scratch (not dst's arrays)
 void launch_import(hipStream_t st, int ndim, const SlabDesc *sd_host, const PartPtrs *cp, int nslab,
-                   const BinBufs &bb, const Batch &b, int chunk, const Store &dst, uint32_t *err);
+                   const BinBufs &bb, const Batch &b, int chunk, const Store &dst, int *stage, uint32_t *err);
 void launch_rebin(hipStream_t st, int ndim, const BinBufs &bb, const Batch &b, int chunk, const Store &src,
                   const Store &dst);
-void launch_export(hipStream_t st, int ndim, const SlabDesc &sd, const Store &s, const PartPtrs &cp);
+// s must be binned as bb says (the last import or re-binning)
+void launch_export(hipStream_t st, int ndim, const SlabDesc &sd, const Store &s, const BinBufs &bb,
+                   const PartPtrs &cp);
 void launch_deposit_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Batch &b, const Store &s,
                           const BinBufs &bb, int max_items, long long *N);
 // s: the state read; o: where the next state is written (o == s: in place)

@@ -98,16 +98,42 @@ __device__ __forceinline__ int wave_rank(int *counter, int key, bool active) {
   return out;
 }
 
-// Position of rank r inside a tile of L particles: r -> (r * P) mod L with a
-// prime P that does not divide L (a bijection that spreads same-cell runs).
-__device__ __forceinline__ int scramble(int r, int L) {
-  if (L <= 64) return r;
+// Order of the particles inside a tile: ranks (arrival order at import) are
+// taken in groups of kScrGroup consecutive ranks, and a group of len ranks is
+// permuted by r -> (r * P) mod len with a prime P that does not divide len
+// (a bijection that spreads same-cell runs, so that a wavefront's lanes hold
+// particles of different cells); groups of at most 64 keep their order.  A
+// group fits in LDS, so import and export can permute it there and touch HBM
+// only in whole lines.
+constexpr int kScrGroup = 4096;
+
+__device__ __forceinline__ uint32_t scramble_prime(uint32_t L) {
   const uint32_t primes[3] = {40009u, 50021u, 60013u};
   uint32_t P = primes[0];
-  if ((uint32_t)L % P == 0) P = primes[1];
-  if ((uint32_t)L % P == 0) P = primes[2];
-  return (int)(((uint64_t)(uint32_t)r * P) % (uint64_t)L);
+  if (L % P == 0) P = primes[1];
+  if (L % P == 0) P = primes[2];
+  return P;
 }
+
+// The group's positions of ranks r0, r0 + stride, r0 + 2 stride, ... (r0 <
+// len): q advances by (stride * P) mod len, with one conditional subtraction.
+struct ScrWalk {
+  uint32_t q, step, len;
+  __device__ __forceinline__ ScrWalk(int r0, int stride, int len_) : len((uint32_t)len_) {
+    if (len <= 64) {
+      q = (uint32_t)r0;
+      step = (uint32_t)stride;
+    } else {
+      const uint64_t P = scramble_prime(len);
+      q = (uint32_t)((uint64_t)(uint32_t)r0 * P % len);
+      step = (uint32_t)((uint64_t)(uint32_t)stride * P % len);
+    }
+  }
+  __device__ __forceinline__ void next() {
+    q += step;
+    if (len > 64 && q >= len) q -= len;
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Fused step
@@ -417,24 +443,25 @@ __device__ __forceinline__ int find_slab(const int *__restrict__ offs, int nslab
 // ---------------------------------------------------------------------------
 // Binning: histogram by tile, scan, items, scatter.
 // ---------------------------------------------------------------------------
-// Import: the caller's arrays of one slab (linear cells, validated).
+// Import of the caller's arrays of one slab, in three passes: tile counts;
+// each particle's caller index at the next free rank of its tile (arrival
+// order: a wavefront's lanes of one tile take consecutive ranks, so these
+// writes, and the reads of the last pass, are whole lines whenever the
+// caller's order keeps a tile's particles together); and one block per tile
+// that reads the particles in rank order, permutes each group of ranks in LDS
+// and writes the tile's store slots in order.
+//
+// Only the cell decides the tile: a cell outside the grid is an error and its
+// particle is left out; offsets and weights are checked in the last pass.
 template <int ND>
 __device__ __forceinline__ int import_tile(const SlabDesc &sd, const PartPtrs &cp, int64_t p, int idx[3],
                                            uint32_t *err) {
-  const Geo &g = sd.g;
-  int c = cp.cell[p];
-  float f0 = cp.off[p], f1 = cp.off[cp.n + p], f2 = ND == 3 ? cp.off[2 * cp.n + p] : 0.0f;
-  int W = cp.wq[p];
-  uint32_t e = 0;
-  if (c < 0 || c >= g.ncells) e |= ERR_RANGE;
-  if (!(f0 >= 0.0f && f0 < 1.0f) || !(f1 >= 0.0f && f1 < 1.0f)) e |= ERR_RANGE;
-  if (ND == 3 && !(f2 >= 0.0f && f2 < 1.0f)) e |= ERR_RANGE;
-  if (W < 0) e |= ERR_WEIGHT;
-  if (e) {
-    if (err) atomicOr(err, e);
+  const int c = cp.cell[p];
+  if (c < 0 || c >= sd.g.ncells) {
+    if (err) atomicOr(err, ERR_RANGE);
     return -1;
   }
-  decode_cell<ND>(g, c, idx);
+  decode_cell<ND>(sd.g, c, idx);
   return sd.tile_off + tile_of<ND>(sd.tg, idx);
 }
 
@@ -448,22 +475,87 @@ __global__ void __launch_bounds__(256) k_import_hist(SlabDesc sd, PartPtrs cp, i
 }
 
 template <int ND>
-__global__ void __launch_bounds__(256) k_import_scatter(SlabDesc sd, PartPtrs cp, Store d,
-                                                        const int *__restrict__ counts,
-                                                        const int *__restrict__ starts, int *__restrict__ cursors) {
+__global__ void __launch_bounds__(256) k_import_index(SlabDesc sd, PartPtrs cp, const int *__restrict__ starts,
+                                                      int *__restrict__ cursors, int *__restrict__ stage) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int idx[3];
   int t = p < cp.n ? import_tile<ND>(sd, cp, p, idx, nullptr) : -1;
   int r = wave_rank(cursors, t < 0 ? 0 : t, t >= 0);
-  if (t < 0) return;
-  const int64_t q = starts[t] + scramble(r, counts[t]);  // scrambled once, at import
-  d.pc[q] = pack_cell<ND>(sd.tg, idx);
+  if (t >= 0) stage[starts[t] + r] = (int)p;
+}
+
+// One block per tile of the slab (blockIdx.x = tile within the slab).  Each
+// thread issues the loads of kUnroll ranks before it stores any of them, so
+// a wavefront keeps that many memory requests in flight per field.
+constexpr int kUnroll = 8;
+
+template <int ND>
+__device__ __forceinline__ int import_field(const SlabDesc &sd, const PartPtrs &cp, int k, int64_t p, uint32_t &e) {
+  // field k: 0 packed cell, 1..ND offsets, ND+1..ND+3 velocity, ND+4 weight,
+  // ND+5 caller index
+  if (k == 0) {
+    int idx[3];
+    decode_cell<ND>(sd.g, cp.cell[p], idx);
+    return pack_cell<ND>(sd.tg, idx);
+  }
+  if (k <= ND) {
+    const float f = cp.off[(int64_t)(k - 1) * cp.n + p];
+    if (!(f >= 0.0f && f < 1.0f)) e |= ERR_RANGE;
+    return __float_as_int(f);
+  }
+  if (k <= ND + 3) return __float_as_int(cp.vel[(int64_t)(k - ND - 1) * cp.n + p]);
+  if (k == ND + 4) {
+    const int W = cp.wq[p];
+    if (W < 0) e |= ERR_WEIGHT;
+    return W;
+  }
+  return (int)p;
+}
+
+template <int ND>
+__global__ void __launch_bounds__(256) k_import_gather(SlabDesc sd, PartPtrs cp, Store d,
+                                                       const int *__restrict__ counts,
+                                                       const int *__restrict__ starts,
+                                                       const int *__restrict__ stage, uint32_t *__restrict__ err) {
+  __shared__ int s_p[kScrGroup], s_v[kScrGroup];
+  const int t = sd.tile_off + (int)blockIdx.x;
+  const int L = counts[t], s0 = starts[t];
+  const int tid = threadIdx.x, B = blockDim.x;
+  uint32_t e = 0;
+  for (int g0 = 0; g0 < L; g0 += kScrGroup) {
+    const int len = min(kScrGroup, L - g0);
+    const int64_t base = (int64_t)s0 + g0;
+    for (int r = tid; r < len; r += B) s_p[r] = stage[base + r];
+    __syncthreads();
+    // each field is gathered in rank order, permuted in LDS and written in
+    // slot order
+    for (int k = 0; k < ND + 6; ++k) {
+      ScrWalk w(tid, B, len);
+      for (int r0 = tid; r0 < len; r0 += kUnroll * B) {
+        int v[kUnroll];
 #pragma unroll
-  for (int k = 0; k < ND; ++k) d.off[k * d.cap + q] = cp.off[k * cp.n + p];
+        for (int u = 0; u < kUnroll; ++u) {
+          const int r = r0 + u * B;
+          v[u] = r < len ? import_field<ND>(sd, cp, k, s_p[r], e) : 0;
+        }
 #pragma unroll
-  for (int k = 0; k < 3; ++k) d.vel[k * d.cap + q] = cp.vel[k * cp.n + p];
-  d.wq[q] = cp.wq[p];
-  d.oidx[q] = (int)p;
+        for (int u = 0; u < kUnroll; ++u) {
+          if (r0 + u * B < len) {
+            s_v[w.q] = v[u];
+            w.next();
+          }
+        }
+      }
+      __syncthreads();
+      int *dst = k == 0 ? d.pc
+                 : k <= ND ? reinterpret_cast<int *>(d.off) + (int64_t)(k - 1) * d.cap
+                 : k <= ND + 3 ? reinterpret_cast<int *>(d.vel) + (int64_t)(k - ND - 1) * d.cap
+                 : k == ND + 4 ? d.wq : d.oidx;
+      for (int q = tid; q < len; q += B) dst[base + q] = s_v[q];
+      __syncthreads();
+    }
+  }
+  if (e) atomicOr(err, e);
 }
 
 // Re-binning of the store: the slab of a slot comes from the slot ranges.
@@ -541,33 +633,62 @@ __global__ void __launch_bounds__(1024) k_tile_scan(int ntiles, int chunk, const
   }
 }
 
-__global__ void __launch_bounds__(256) k_tile_items(Batch b, int chunk, const int *__restrict__ counts,
+__global__ void __launch_bounds__(256) k_tile_items(Batch b, const int *__restrict__ counts,
                                                     const int *__restrict__ starts,
                                                     const int *__restrict__ item_start, Item *__restrict__ items) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= b.ntiles) return;
   const int slab = find_slab(b.tile_offs, b.nslab, t);
-  // ceil(c / chunk) items of near-equal size (each at most chunk): equal items
-  // let the persistent grid finish its rounds together
+  // ceil(c / chunk) items of near-equal size (each at most chunk; k_tile_scan
+  // counted them): equal items let the persistent grid finish its rounds
+  // together
   const int c = counts[t], s = starts[t], i0 = item_start[t];
-  const int m = (c + chunk - 1) / chunk;
+  const int m = item_start[t + 1] - i0;
   for (int k = 0; k < m; ++k)
     items[i0 + k] = Item{t, s + (int)((long long)k * c / m), s + (int)((long long)(k + 1) * c / m), slab};
 }
 
 template <int ND>
-__global__ void __launch_bounds__(256) k_export(SlabDesc sd, Store s, PartPtrs cp) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= sd.part_n) return;
-  const int64_t p = sd.part_off + k;
-  const int o = s.oidx[p];
-  int idx[3];
-  unpack_cell<ND>(sd.tg, s.pc[p], idx);
-  cp.cell[o] = encode_cell<ND>(sd.g, idx);
+__global__ void __launch_bounds__(256) k_export(SlabDesc sd, Store s, const int *__restrict__ starts, PartPtrs cp) {
+  __shared__ int s_o[kScrGroup], s_v[kScrGroup];
+  const int t = sd.tile_off + (int)blockIdx.x;
+  const int s0 = starts[t], L = starts[t + 1] - s0;
+  const int tid = threadIdx.x, B = blockDim.x;
+  for (int g0 = 0; g0 < L; g0 += kScrGroup) {
+    const int len = min(kScrGroup, L - g0);
+    const int64_t base = (int64_t)s0 + g0;
+    for (int q = tid; q < len; q += B) s_o[q] = s.oidx[base + q];
+    // field k: 0 cell, 1..ND offsets, ND+1..ND+3 velocity
+    for (int k = 0; k < ND + 4; ++k) {
+      const int *src = k == 0 ? s.pc
+                       : k <= ND ? reinterpret_cast<const int *>(s.off) + (int64_t)(k - 1) * s.cap
+                       : reinterpret_cast<const int *>(s.vel) + (int64_t)(k - ND - 1) * s.cap;
+      for (int q0 = tid; q0 < len; q0 += kUnroll * B) {
+        int v[kUnroll];
 #pragma unroll
-  for (int d = 0; d < ND; ++d) cp.off[d * cp.n + o] = s.off[d * s.cap + p];
+        for (int u = 0; u < kUnroll; ++u) v[u] = q0 + u * B < len ? src[base + q0 + u * B] : 0;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) cp.vel[d * cp.n + o] = s.vel[d * s.cap + p];
+        for (int u = 0; u < kUnroll; ++u)
+          if (q0 + u * B < len) s_v[q0 + u * B] = v[u];
+      }
+      __syncthreads();
+      ScrWalk w(tid, B, len);
+      for (int r = tid; r < len; r += B, w.next()) {
+        const int64_t o = s_o[w.q];
+        const int v = s_v[w.q];
+        if (k == 0) {
+          int idx[3];
+          unpack_cell<ND>(sd.tg, v, idx);
+          cp.cell[o] = encode_cell<ND>(sd.g, idx);
+        } else if (k <= ND) {
+          reinterpret_cast<int *>(cp.off)[(int64_t)(k - 1) * cp.n + o] = v;
+        } else {
+          reinterpret_cast<int *>(cp.vel)[(int64_t)(k - ND - 1) * cp.n + o] = v;
+        }
+      }
+      __syncthreads();
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1268,16 +1389,20 @@ size_t window_lds_bytes(const TileGeo &tg, int ndim) {
   } while (0)
 
 void launch_import(hipStream_t st, int ndim, const SlabDesc *sd_host, const PartPtrs *cp, int nslab,
-                   const BinBufs &bb, const Batch &b, int chunk, const Store &dst, uint32_t *err) {
+                   const BinBufs &bb, const Batch &b, int chunk, const Store &dst, int *stage, uint32_t *err) {
   launch_fill32(st, bb.counts, b.ntiles);
   for (int k = 0; k < nslab; ++k)
     if (cp[k].n > 0) PIC_ND(ndim, (k_import_hist<ND><<<nblk(cp[k].n), 256, 0, st>>>(sd_host[k], cp[k], bb.counts, err)));
   k_tile_scan<<<1, 1024, 0, st>>>(b.ntiles, chunk, bb.counts, bb.starts, bb.item_start, bb.cursors, bb.num_items);
-  k_tile_items<<<nblk(b.ntiles), 256, 0, st>>>(b, chunk, bb.counts, bb.starts, bb.item_start, bb.items);
+  k_tile_items<<<nblk(b.ntiles), 256, 0, st>>>(b, bb.counts, bb.starts, bb.item_start, bb.items);
   for (int k = 0; k < nslab; ++k)
     if (cp[k].n > 0)
-      PIC_ND(ndim, (k_import_scatter<ND><<<nblk(cp[k].n), 256, 0, st>>>(sd_host[k], cp[k], dst, bb.counts, bb.starts,
-                                                                        bb.cursors)));
+      PIC_ND(ndim, (k_import_index<ND><<<nblk(cp[k].n), 256, 0, st>>>(sd_host[k], cp[k], bb.starts, bb.cursors,
+                                                                      stage)));
+  for (int k = 0; k < nslab; ++k)
+    if (cp[k].n > 0 && sd_host[k].tg.ntiles > 0)
+      PIC_ND(ndim, (k_import_gather<ND><<<sd_host[k].tg.ntiles, 256, 0, st>>>(sd_host[k], cp[k], dst, bb.counts,
+                                                                              bb.starts, stage, err)));
 }
 
 void launch_rebin(hipStream_t st, int ndim, const BinBufs &bb, const Batch &b, int chunk, const Store &src,
@@ -1285,14 +1410,15 @@ void launch_rebin(hipStream_t st, int ndim, const BinBufs &bb, const Batch &b, i
   launch_fill32(st, bb.counts, b.ntiles);
   if (b.nparts > 0) PIC_ND(ndim, (k_rebin_hist<ND><<<nblk(b.nparts), 256, 0, st>>>(b, src, bb.counts)));
   k_tile_scan<<<1, 1024, 0, st>>>(b.ntiles, chunk, bb.counts, bb.starts, bb.item_start, bb.cursors, bb.num_items);
-  k_tile_items<<<nblk(b.ntiles), 256, 0, st>>>(b, chunk, bb.counts, bb.starts, bb.item_start, bb.items);
+  k_tile_items<<<nblk(b.ntiles), 256, 0, st>>>(b, bb.counts, bb.starts, bb.item_start, bb.items);
   if (b.nparts > 0)
     PIC_ND(ndim, (k_rebin_scatter<ND><<<nblk(b.nparts), 256, 0, st>>>(b, src, dst, bb.starts, bb.cursors)));
 }
 
-void launch_export(hipStream_t st, int ndim, const SlabDesc &sd, const Store &s, const PartPtrs &cp) {
-  if (sd.part_n <= 0) return;
-  PIC_ND(ndim, (k_export<ND><<<nblk(sd.part_n), 256, 0, st>>>(sd, s, cp)));
+void launch_export(hipStream_t st, int ndim, const SlabDesc &sd, const Store &s, const BinBufs &bb,
+                   const PartPtrs &cp) {
+  if (sd.part_n <= 0 || sd.tg.ntiles <= 0) return;
+  PIC_ND(ndim, (k_export<ND><<<sd.tg.ntiles, 256, 0, st>>>(sd, s, bb.starts, cp)));
 }
 
 void launch_deposit_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Batch &b, const Store &s,
