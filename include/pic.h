@@ -173,6 +173,34 @@ int pic_deposit(pic_ctx_t *ctx, const pic_particles_t *p, int64_t *node_w);
 int pic_force(pic_ctx_t *ctx, const pic_particles_t *p, const int64_t *node_w, float *force,
               pic_diag_t *pe_or_null);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): steps 1-5,
+ * pic_deposit followed by pic_force, for one grid without a context and
+ * without allocating anything.  The node sums, node densities, cell-centred
+ * gradients and the device error word live in one static device array of
+ * PIC_NOALLOC_SCRATCH_BYTES (64 MiB), which each GPU the library runs on holds
+ * until the process ends (pic_init, or else the first call on a device, looks
+ * its address up).  Limit: 12 bytes per node plus 4 ndim bytes per cell must
+ * fit in it (2D grids up to about 3.3 million cells, 3D up to about 2.7
+ * million); larger grids return PIC_ENOSPACE.
+ * Runs on the current device, enqueued on stream (hipStream_t, NULL = the
+ * default stream of that device), stream-ordered and asynchronous.  Results
+ * are bit-identical to pic_deposit and pic_force on a context of the same
+ * grid and potential.
+ * In:  grid and pot as for pic_init; p: device arrays (cell, off, wq; vel is
+ *      not read).
+ * Out: force [ndim][n], N per atom (device, caller-owned).  device_error
+ *      (device word, may be NULL): invalid particles are skipped, and bit 1
+ *      (a cell outside the grid or an offset outside [0, 1)) or bit 4 (a
+ *      negative weight) is OR-ed into it; the caller clears it.
+ * Returns PIC_EINVAL for NULL or invalid arguments, PIC_ENOSPACE as above,
+ * PIC_EHIP if a launch fails.  Every call on a GPU shares that GPU's array:
+ * calls that overlap (other streams or threads) race and must be serialised
+ * by the caller. */
+#define PIC_NOALLOC_SCRATCH_BYTES (64u << 20)
+int pic_force_noalloc(const pic_grid_t *grid, const pic_potential_t *pot, const pic_particles_t *p, float *force,
+                      uint32_t *device_error, void *stream);
+
 /* v += frac * force / m * dt on the evolved components (frac = -1/2 turns
  * initial velocities v(0) into the half-step velocities v(-1/2)). */
 int pic_kick(pic_ctx_t *ctx, pic_particles_t *p, const float *force, double frac);

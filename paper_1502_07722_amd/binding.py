@@ -85,6 +85,8 @@ lib.pic_sync.argtypes = [_vp]
 lib.pic_deposit.argtypes = [_vp, _P(pic_particles_t), _vp]
 lib.pic_force.argtypes = [_vp, _P(pic_particles_t), _vp, _vp, _P(pic_diag_t)]
 lib.pic_kick.argtypes = [_vp, _P(pic_particles_t), _vp, C.c_double]
+lib.pic_force_noalloc.argtypes = [_P(pic_grid_t), _P(pic_potential_t), _P(pic_particles_t), _vp, _vp, _vp]
+NOALLOC_SCRATCH_BYTES = 64 << 20
 lib.pic_push.argtypes = [_vp, _P(pic_particles_t), _vp]
 lib.pic_step.argtypes = [_vp, _P(pic_particles_t), C.c_int32, _P(pic_diag_t), C.c_int32]
 lib.pic_set_timing.argtypes = [_vp, C.c_int32]
@@ -210,6 +212,30 @@ def pic_threshold_fit(fluences, widths, beam_d: float):
     if rc:
         raise PicError(rc, "pic_threshold_fit failed")
     return a.value, b.value, c.value
+
+
+def pic_force_noalloc(grid: W.Grid, pot: W.Potential, parts: DeviceParticles, force=None, device_error=None,
+                      stream=None):
+    """pic_deposit + pic_force without a context, the library's grids in its
+    static scratch array (no allocation by the library).  force: float32
+    [ndim, n] (a new tensor when None); device_error: optional int32 [1]
+    device word (error bits OR-ed in).  Returns force."""
+    dev = parts.cell.device
+    n = parts.n
+    if force is None:
+        force = torch.empty((grid.ndim, n), dtype=torch.float32, device=dev)
+    if not (force.is_cuda and force.is_contiguous() and force.dtype == torch.float32
+            and force.numel() >= grid.ndim * n):
+        raise PicError(PIC_EINVAL, "force must be a contiguous float32 CUDA tensor of ndim * n elements")
+    if device_error is not None and not (device_error.is_cuda and device_error.dtype == torch.int32):
+        raise PicError(PIC_EINVAL, "device_error must be an int32 CUDA tensor")
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    s = parts.struct()
+    rc = lib.pic_force_noalloc(C.byref(grid_t(grid)), C.byref(potential_t(pot)), C.byref(s), _ptr(force),
+                               _ptr(device_error), C.c_void_p(st.cuda_stream))
+    if rc:
+        raise PicError(rc, "pic_force_noalloc failed")
+    return force
 
 
 class Context:

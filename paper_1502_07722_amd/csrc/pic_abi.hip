@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -12,6 +13,14 @@
 #include "pic_internal.h"
 
 using namespace pic;
+
+// The static device array of pic_force_noalloc: node sums, node densities,
+// cell-centred gradients and an error word for one grid.  Each GPU the
+// library runs on holds its own copy until the process ends.  Host code never
+// uses the array's name as an address: noalloc_scratch() looks the device
+// address up once per device (hipGetSymbolAddress, with that device current)
+// and keeps it.
+static __device__ __align__(256) unsigned char scratch[PIC_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -218,6 +227,43 @@ Geo make_geo(const pic_grid_t &g, const pic_potential_t &P, double dt, const Siz
   G.inv_n1 = 1.0 / G.n[1];
   G.kappa = (float)(std::ldexp(1.0, -20) * r3 / V);
   return G;
+}
+
+// Potential constants in the kernels' reduced units (length r0, energy D).
+Pot make_pot(const pic_potential_t &P, double dt) {
+  Pot Q{};
+  const double r3 = P.r0 * P.r0 * P.r0;
+  Q.nfloor = (float)(P.n_floor * r3);
+  Q.gclamp = (float)P.g_clamp;
+  Q.s_rep = (float)P.s_rep;
+  Q.c_att = (float)P.c_att;
+  Q.beta = (float)(12.0 * P.D / P.r0);
+  Q.gv = (float)(dt / P.mass);
+  Q.kind = P.kind;
+  Q.mAl2 = P.kind == PIC_POT_MORSE ? (float)(P.alpha * P.r0 * M_LOG2E) : 0.0f;
+  Q.mA6 = P.kind == PIC_POT_MORSE ? (float)(P.alpha * P.r0 / 6.0) : 0.0f;
+  Q.lattice = P.lattice;
+  return Q;
+}
+
+// The device address of the static scratch array on each device (see its
+// definition at the top of the file).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of the array (out may be NULL: look up only).
+int noalloc_scratch(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PIC_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(::scratch)) != hipSuccess || !ptr) return PIC_EHIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  if (out) *out = g_scratch_ptr[dev];
+  return PIC_OK;
 }
 
 DiagC make_diag(const pic_grid_t &g, const pic_potential_t &P) {
@@ -509,17 +555,8 @@ static int init_common(pic_ctx_t **out, const pic_grid_t *grids_in, int nslab, c
   c->ws = static_cast<char *>(ws);
   c->stream = static_cast<hipStream_t>(stream);
   const pic_potential_t &P = *pot;
-  const double r3 = P.r0 * P.r0 * P.r0;
-  c->P.nfloor = (float)(P.n_floor * r3);
-  c->P.gclamp = (float)P.g_clamp;
-  c->P.s_rep = (float)P.s_rep;
-  c->P.c_att = (float)P.c_att;
-  c->P.beta = (float)(12.0 * P.D / P.r0);
-  c->P.gv = (float)(dt / P.mass);
-  c->P.kind = P.kind;
-  c->P.mAl2 = P.kind == PIC_POT_MORSE ? (float)(P.alpha * P.r0 * M_LOG2E) : 0.0f;
-  c->P.mA6 = P.kind == PIC_POT_MORSE ? (float)(P.alpha * P.r0 / 6.0) : 0.0f;
-  c->P.lattice = P.lattice;
+  c->P = make_pot(P, dt);
+  (void)noalloc_scratch(nullptr);  // look the static scratch array up on this device now
   c->quad = gauss_legendre16();
   int pe = 0;
   for (int k = 0; k < nslab; ++k) {
@@ -1023,6 +1060,40 @@ int pic_force(pic_ctx_t *ctx, const pic_particles_t *p, const int64_t *node_w, f
   std::memset(pe_or_null, 0, sizeof(*pe_or_null));
   pe_or_null->pe = h.pe;
   return PIC_OK;
+}
+
+int pic_force_noalloc(const pic_grid_t *grid_in, const pic_potential_t *pot, const pic_particles_t *p,
+                      float *force, uint32_t *device_error, void *stream) {
+  Sizes sz;
+  if (!grid_sizes(grid_in, &sz, nullptr) || !valid_potential(pot) || !p || p->n < 0) return PIC_EINVAL;
+  if (p->n > 0 && (!p->cell || !p->off || !p->wq || !force)) return PIC_EINVAL;
+  const pic_grid_t grid = normalised(*grid_in);
+  // node sums (int64), node densities (float), cell-centred gradient planes
+  // (float, ndim of them), error word
+  const size_t o_dens = align_up(sizeof(long long) * (size_t)sz.nnodes);
+  const size_t o_G = o_dens + align_up(sizeof(float) * (size_t)sz.nnodes);
+  const size_t o_err = o_G + align_up(sizeof(float) * (size_t)sz.ncells * grid.ndim);
+  if (o_err + kAlign > (size_t)PIC_NOALLOC_SCRATCH_BYTES) return PIC_ENOSPACE;
+  void *base = nullptr;
+  int rc = noalloc_scratch(&base);
+  if (rc) return rc;
+  char *b = static_cast<char *>(base);
+  long long *node = reinterpret_cast<long long *>(b);
+  float *dens = reinterpret_cast<float *>(b + o_dens);
+  float *G = reinterpret_cast<float *>(b + o_G);
+  uint32_t *err = device_error ? device_error : reinterpret_cast<uint32_t *>(b + o_err);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const Geo geo = make_geo(grid, *pot, 0.0, sz);
+  const Pot P = make_pot(*pot, 0.0);
+  const PartPtrs pp = ptrs(p);
+  // the array keeps the previous call's contents: the node sums start at zero
+  // (a fill kernel, so the call can also be captured into a graph)
+  launch_fill64(st, node, sz.nnodes);
+  if (!device_error) launch_clear_word(st, err);
+  launch_deposit_atomic(st, geo, pp, node, err);
+  launch_grid(st, geo, node, dens, G);
+  launch_force(st, geo, P, pp, dens, G, force, err);
+  return hipGetLastError() == hipSuccess ? PIC_OK : PIC_EHIP;
 }
 
 int pic_kick(pic_ctx_t *ctx, pic_particles_t *p, const float *force, double frac) {
