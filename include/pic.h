@@ -405,6 +405,12 @@ int pic_deposit_vjp(pic_ctx_t *ctx, const pic_particles_t *state, const float *n
  * Out: lam_x = complete dJ/d(offset) of the initial state, lam_v =
  *      dJ/dv(-1/2); dtheta (device, 5 doubles) += dJ/d(D, r0, s_rep, c_att,
  *      alpha).
+ * start_kick = f != 0: the recorded run's start velocities came from a kick
+ *      v(-1/2) = v(0) + f F(x0) dt / m of its initial state (f = -1/2 is the
+ *      leapfrog start, pic_kick with frac f).  Its VJP is folded into the
+ *      last reverse step (the same state's force VJP with 1 + f times the
+ *      step's force cotangent), so lam_v = dJ/dv(0) and lam_x and dtheta
+ *      include the terms through F(x0).  0: no start kick.
  * p supplies the particle count (its arrays are not read).  The context, its
  * tiling, nsteps, every and record must be those of the pic_forward_record
  * call, otherwise PIC_EINVAL.  Single-slab contexts on the tiled path only.
@@ -415,7 +421,7 @@ int pic_forward_record(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, int32
                        size_t record_bytes);
 int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps, int32_t every,
                         const void *record, size_t record_bytes, void *scratch, size_t scratch_bytes, float *lam_x,
-                        float *lam_v, double *dtheta);
+                        float *lam_v, double *dtheta, double start_kick);
 
 /* ---------------------------------------------------------------------------
  * Crater measurement (results section, Figs. 3-4 and eq. (5)).  The paper

@@ -1,6 +1,6 @@
 """torch.autograd bindings of the hand-written reverse mode.
 
-Three Functions, all thin wrappers of the C ABI (every step of the cycle and
+Four Functions, all thin wrappers of the C ABI (every step of the cycle and
 of its reverse runs in the library's kernels):
 
   Force       off(0), theta -> per-atom force (pic_deposit + pic_force);
@@ -16,6 +16,12 @@ of its reverse runs in the library's kernels):
               for tiles take the same checkpointed scheme through the
               per-step calls (pic_deposit / pic_force / pic_push forward,
               pic_adjoint_step backward).
+  StartedTrajectory  off(0), v(0), theta -> off(T), v(T - 1/2): the leapfrog
+              start v(-1/2) = v(0) - F(0)/m dt/2 (pic_deposit, pic_force,
+              pic_kick) and a recorded run; backward by pic_backward_record
+              with the start kick's VJP folded into its last reverse step
+              (the force VJP of the initial state is then not a pass of its
+              own).  Tiled contexts; others compose Force, Kick, Trajectory.
 
 theta is a float64 tensor (D, r0, s_rep, c_att, alpha) holding the
 context's potential (alpha: the Morse width; its gradient is zero under
@@ -139,6 +145,28 @@ class Trajectory(torch.autograd.Function):
         return lam_x, lam_v, dth.to(fctx.theta_dev), None, None, None, None, None
 
 
+class StartedTrajectory(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, off0, v0, theta, ctx: B.Context, cell0, wq, nsteps: int, every: int):
+        _check_theta(ctx, theta)
+        dp = B.DeviceParticles(cell0.clone(), off0.detach().contiguous().clone(), v0.detach().contiguous().clone(),
+                               wq)
+        ctx.start_leapfrog(dp)  # v(0) -> v(-1/2): pic_deposit, pic_force, pic_kick(-1/2)
+        rec = ctx.pic_forward_record(dp, nsteps, every)
+        fctx.pic = (ctx, dp, rec)
+        fctx.theta_dev = theta.device
+        fctx.mark_non_differentiable(dp.cell)
+        return dp.off, dp.vel, dp.cell
+
+    @staticmethod
+    def backward(fctx, g_off, g_vel, _g_cell):
+        ctx, dp, rec = fctx.pic
+        lam_x = torch.zeros_like(dp.off) if g_off is None else g_off.contiguous().float().clone()
+        lam_v = torch.zeros_like(dp.vel) if g_vel is None else g_vel.contiguous().float().clone()
+        dth = ctx.pic_backward_record(dp, rec, lam_x, lam_v, start_kick=-0.5)
+        return lam_x, lam_v, dth.to(fctx.theta_dev), None, None, None, None, None
+
+
 def crater_objective(ctx: B.Context, cell, off0, v_thermal, xi, sigma_ref, fluence_ref, fluence, wq, theta,
                      nsteps: int, every: int, y_s: float, tau: float):
     """J(theta, F) on device tensors (cell int32 [n], off0 float32 [ndim][n],
@@ -148,9 +176,12 @@ def crater_objective(ctx: B.Context, cell, off0, v_thermal, xi, sigma_ref, fluen
     nd = grid.ndim
     scale = torch.sqrt(fluence / fluence_ref).float()
     v0 = v_thermal + (sigma_ref * scale)[None, :] * xi
-    F0 = Force.apply(off0, theta, ctx, cell, wq)
-    vh = Kick.apply(v0, F0, ctx, cell, wq, -0.5)
-    offT, velT, cellT = Trajectory.apply(off0, vh, theta, ctx, cell, wq, nsteps, every)
+    if B.lib.pic_record_bytes(ctx.ctx, int(nsteps), int(every)):
+        offT, velT, cellT = StartedTrajectory.apply(off0, v0, theta, ctx, cell, wq, nsteps, every)
+    else:  # untiled context: the start kick and the run as separate Functions
+        F0 = Force.apply(off0, theta, ctx, cell, wq)
+        vh = Kick.apply(v0, F0, ctx, cell, wq, -0.5)
+        offT, velT, cellT = Trajectory.apply(off0, vh, theta, ctx, cell, wq, nsteps, every)
     ax = nd - 1
     lateral = 1
     for d in range(ax):

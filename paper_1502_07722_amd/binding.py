@@ -111,7 +111,7 @@ lib.pic_backward_bytes.argtypes = [_vp, C.c_int32]
 lib.pic_backward_bytes.restype = C.c_size_t
 lib.pic_forward_record.argtypes = [_vp, _P(pic_particles_t), C.c_int32, C.c_int32, _vp, C.c_size_t]
 lib.pic_backward_record.argtypes = [_vp, _P(pic_particles_t), C.c_int32, C.c_int32, _vp, C.c_size_t, _vp,
-                                    C.c_size_t, _vp, _vp, _vp]
+                                    C.c_size_t, _vp, _vp, _vp, C.c_double]
 lib.pic_calibrate_catt.argtypes = [_P(pic_grid_t), _P(pic_potential_t), C.c_double, C.c_int32, _P(C.c_double),
                                    _P(C.c_double)]
 lib.pic_num_columns.restype = C.c_int64
@@ -485,9 +485,11 @@ class Context:
                     "pic_forward_record")
         return {"buf": buf, "ptr": ptr, "bytes": nbytes, "nsteps": int(nsteps), "every": int(every)}
 
-    def pic_backward_record(self, parts: DeviceParticles, record, lam_x, lam_v, dtheta=None):
+    def pic_backward_record(self, parts: DeviceParticles, record, lam_x, lam_v, dtheta=None, start_kick=0.0):
         """Reverse sweep of a recorded run; lam_x and lam_v (caller order) are
-        replaced by the initial-state cotangents.  Returns dtheta (+=)."""
+        replaced by the initial-state cotangents.  start_kick = f folds in a
+        start kick v(-1/2) = v(0) + f F(x0) dt / m (lam_v then is dJ/dv(0)).
+        Returns dtheta (+=)."""
         self._parts_ok(parts)
         self._need(lam_x, self.grid.ndim * parts.n, torch.float32, "lam_x")
         self._need(lam_v, 3 * parts.n, torch.float32, "lam_v")
@@ -499,7 +501,8 @@ class Context:
         s = parts.struct()
         self._check(lib.pic_backward_record(self.ctx, C.byref(s), record["nsteps"], record["every"],
                                             C.c_void_p(record["ptr"]), record["bytes"], C.c_void_p(sptr), nbytes,
-                                            _ptr(lam_x), _ptr(lam_v), _ptr(dtheta)), "pic_backward_record")
+                                            _ptr(lam_x), _ptr(lam_v), _ptr(dtheta), float(start_kick)),
+                    "pic_backward_record")
         del scratch
         return dtheta
 

@@ -243,6 +243,7 @@ Pot make_pot(const pic_potential_t &P, double dt) {
   Q.mAl2 = P.kind == PIC_POT_MORSE ? (float)(P.alpha * P.r0 * M_LOG2E) : 0.0f;
   Q.mA6 = P.kind == PIC_POT_MORSE ? (float)(P.alpha * P.r0 / 6.0) : 0.0f;
   Q.lattice = P.lattice;
+  Q.ks = 1.0f;
   return Q;
 }
 
@@ -1332,8 +1333,9 @@ int pic_forward_record(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, int32
 
 int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps, int32_t every,
                         const void *record, size_t record_bytes, void *scratch, size_t scratch_bytes, float *lam_x,
-                        float *lam_v, double *dtheta) {
+                        float *lam_v, double *dtheta, double start_kick) {
   if (!ctx) return PIC_EINVAL;
+  if (!std::isfinite(start_kick)) return fail(ctx, PIC_EINVAL, "start_kick must be finite");
   int rc = recorded_ok(ctx, p, nsteps, every);
   if (rc) return rc;
   const RecLayout R = rec_layout(ctx, nsteps, every);
@@ -1410,13 +1412,16 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
     for (int k = len - 1; k >= 0; --k) {
       const int step = s0 + k;
       uint32_t *amax_prev = ctx->amax + (step & 1), *amax_cur = ctx->amax + ((step + 1) & 1);
+      // the first step's kick also reverses the start kick of the same state:
+      // its force cotangent is (1 + start_kick) times the step's own
+      Pot P = ctx->P;
+      if (step == 0) P.ks = (float)(1.0 + start_kick);
       if (step == nsteps - 1)  // seed the fixed-point scale of the first reverse step
-        launch_adjoint_scale(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), bb, (int)max_items, Nk(k),
-                             nbar_next, lx, lv, amax_prev);
+        launch_adjoint_scale(ctx->stream, nd, ctx->sd[0].tg, P, b, slot(k), bb, (int)max_items, Nk(k), nbar_next, lx,
+                             lv, amax_prev);
       launch_clear_reverse(ctx->stream, nb_cur, ctx->nnodes, ctx->drift, amax_cur);
-      launch_adjoint_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, b, slot(k), bb, (int)max_items, Nk(k), nbar_next,
-                           lx, lv, nb_cur, ctx->drift + 4, ctx->drift, amax_prev, amax_cur, ctx->partial, ctx->dacc,
-                           ctx->err);
+      launch_adjoint_tiled(ctx->stream, nd, ctx->sd[0].tg, P, b, slot(k), bb, (int)max_items, Nk(k), nbar_next, lx, lv,
+                           nb_cur, ctx->drift + 4, ctx->drift, amax_prev, amax_cur, ctx->partial, ctx->dacc, ctx->err);
       nbar_next = nb_cur;
       std::swap(nb_cur, nb_other);
       if ((rc = check_launch(ctx, "reverse step"))) return rc;

@@ -386,7 +386,7 @@ __device__ __forceinline__ void reverse_drift_kick(const Geo &g, const Pot &P, c
   for (int d = 0; d < ND; ++d) {
     lv[d] = r.sgn[d] * __builtin_fmaf(g.tau[d], ln[d], lv[d]);
     lf[d] = r.sgn[d] * ln[d];
-    mu[d] = (lv[d] * P.gv) * P.beta;
+    mu[d] = ((lv[d] * P.gv) * P.beta) * P.ks;
   }
 }
 

@@ -41,6 +41,9 @@ struct Pot {
   float mAl2;      // Morse: alpha r0 log2(e)
   float mA6;       // Morse: alpha r0 / 6
   int lattice;     // 0 cubic (eqs. (1)-(2) per axis), 1 hexagonal close-packed
+  float ks;        // reverse mode only: scale of the force cotangent of the
+                   // step's kick (1; 1 + f when the step also reverses a start
+                   // kick v(-1/2) = v(0) + f F(x0) dt / m of the same state)
 };
 
 // ---------------------------------------------------------------------------
