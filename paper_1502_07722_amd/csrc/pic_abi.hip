@@ -88,7 +88,7 @@ int64_t tiles_for(const pic_grid_t *g, int lt) {
 }
 
 struct Layout {
-  size_t err, diag, partial, partial_pe, node, dens, G, Gbar, total;
+  size_t err, diag, partial, partial_pe, red, node, dens, G, Gbar, total;
   bool tiled;
   size_t store[2], bins, items, n3[3], drift, dacc, amax, slabs, offs;
   int64_t tiles_max, items_max, cap, nodes, pe_blocks;
@@ -122,6 +122,7 @@ Layout make_layout(const pic_grid_t *grids, int nslab, const int64_t *max_n) {
   L.diag = o; o = align_up(o + sizeof(pic_diag_t) * kDiagCap);
   L.partial = o; o = align_up(o + sizeof(double) * 8 * (size_t)partial_blocks);
   L.partial_pe = o; o = align_up(o + sizeof(double) * 8 * (size_t)L.pe_blocks);
+  L.red = o; o = align_up(o + sizeof(double) * kDiagRedDoubles);
   if (nslab == 1) {
     L.node = o; o = align_up(o + sizeof(long long) * (size_t)L.nodes);
     L.dens = o; o = align_up(o + sizeof(float) * (size_t)L.nodes);
@@ -294,6 +295,7 @@ struct pic_ctx {
   pic_diag_t *diag_dev = nullptr;
   double *partial = nullptr;
   double *partial_pe = nullptr;
+  double *red = nullptr;  // second-level diagnostics sums
   std::vector<int> pe_off;  // first energy-partial block of each slab
   std::string last_error;
   // untiled single-slab path
@@ -569,6 +571,7 @@ static int init_common(pic_ctx_t **out, const pic_grid_t *grids_in, int nslab, c
   c->diag_dev = reinterpret_cast<pic_diag_t *>(c->ws + L.diag);
   c->partial = reinterpret_cast<double *>(c->ws + L.partial);
   c->partial_pe = reinterpret_cast<double *>(c->ws + L.partial_pe);
+  c->red = reinterpret_cast<double *>(c->ws + L.red);
   if (nslab == 1) {
     c->geo = make_geo(grids[0], P, dt, sizes[0]);
     c->node = reinterpret_cast<long long *>(c->ws + L.node);
@@ -875,7 +878,7 @@ int step_tiled(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t nsteps, Dia
         const int nbg = (int)std::max<int64_t>(blocks_of(ctx->sizes[k].nnodes), 1);
         launch_reduce_diag_slab(ctx->stream, ctx->partial, ctx->bb.item_start, ctx->sd[k].tile_off,
                                 ctx->sd[k].tile_off + ctx->sd[k].tg.ntiles,
-                                ctx->partial_pe + (int64_t)ctx->pe_off[k] * 8, nbg, ds.next() + k, s);
+                                ctx->partial_pe + (int64_t)ctx->pe_off[k] * 8, nbg, ctx->red, ds.next() + k, s);
       }
     }
     if ((rc = check_launch(ctx, "tiled step"))) return rc;

@@ -133,8 +133,10 @@ void launch_step_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P
                        const Store &s, const Store &o, const BinBufs &bb, int grid, const long long *Ncur,
                        long long *Nnext, long long *Nclear, const Drift &dr, double *partial, bool diag,
                        uint32_t *err);
+// red: kDiagRedDoubles doubles of scratch
+constexpr int kDiagRedDoubles = 256 * 8;
 void launch_reduce_diag_slab(hipStream_t st, const double *part_p, const int *item_start, int tile_lo, int tile_hi,
-                             const double *part_g, int nblk_g, pic_diag_t *out, int64_t step);
+                             const double *part_g, int nblk_g, double *red, pic_diag_t *out, int64_t step);
 int step_kernel_blocks_per_cu(int ndim, const TileGeo &tg);
 void launch_fill32(hipStream_t s, int *a, int64_t n);
 

@@ -465,29 +465,76 @@ __device__ __forceinline__ int import_tile(const SlabDesc &sd, const PartPtrs &c
   return sd.tile_off + tile_of<ND>(sd.tg, idx);
 }
 
+// The first two passes give each wavefront kWaveRuns x 64 consecutive
+// particles (lane l takes particles c * 64 + l).  When all of them share one
+// tile -- the common case for a caller order that keeps a tile's particles
+// together -- a single atomic counts them or reserves their ranks; otherwise
+// each 64-particle chunk goes through wave_rank (one atomic per distinct
+// tile in the chunk).
+constexpr int kWaveRuns = 4;
+
+__device__ __forceinline__ int64_t import_wave_base() {
+  return ((int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63)) * kWaveRuns;
+}
+
+__device__ __forceinline__ bool one_tile(const int t[kWaveRuns]) {
+  const int t0 = __shfl(t[0], 0, 64);
+  bool same = t0 >= 0;
+#pragma unroll
+  for (int c = 0; c < kWaveRuns; ++c) same = same && t[c] == t0;
+  return __ballot(!same) == 0ull;
+}
+
 template <int ND>
 __global__ void __launch_bounds__(256) k_import_hist(SlabDesc sd, PartPtrs cp, int *__restrict__ counts,
                                                      uint32_t *__restrict__ err) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int idx[3];
-  int t = p < cp.n ? import_tile<ND>(sd, cp, p, idx, err) : -1;
-  wave_rank(counts, t < 0 ? 0 : t, t >= 0);
+  const int64_t p0 = import_wave_base() + (threadIdx.x & 63);
+  int t[kWaveRuns], idx[3];
+#pragma unroll
+  for (int c = 0; c < kWaveRuns; ++c) {
+    const int64_t p = p0 + c * 64;
+    t[c] = p < cp.n ? import_tile<ND>(sd, cp, p, idx, err) : -1;
+  }
+  if (one_tile(t)) {
+    if ((threadIdx.x & 63) == 0) atomicAdd(&counts[t[0]], 64 * kWaveRuns);
+    return;
+  }
+#pragma unroll
+  for (int c = 0; c < kWaveRuns; ++c) wave_rank(counts, t[c] < 0 ? 0 : t[c], t[c] >= 0);
 }
 
 template <int ND>
 __global__ void __launch_bounds__(256) k_import_index(SlabDesc sd, PartPtrs cp, const int *__restrict__ starts,
                                                       int *__restrict__ cursors, int *__restrict__ stage) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int idx[3];
-  int t = p < cp.n ? import_tile<ND>(sd, cp, p, idx, nullptr) : -1;
-  int r = wave_rank(cursors, t < 0 ? 0 : t, t >= 0);
-  if (t >= 0) stage[starts[t] + r] = (int)p;
+  const int lane = threadIdx.x & 63;
+  const int64_t p0 = import_wave_base() + lane;
+  int t[kWaveRuns], idx[3];
+#pragma unroll
+  for (int c = 0; c < kWaveRuns; ++c) {
+    const int64_t p = p0 + c * 64;
+    t[c] = p < cp.n ? import_tile<ND>(sd, cp, p, idx, nullptr) : -1;
+  }
+  if (one_tile(t)) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(&cursors[t[0]], 64 * kWaveRuns);
+    base = __shfl(base, 0, 64) + starts[t[0]];
+#pragma unroll
+    for (int c = 0; c < kWaveRuns; ++c) stage[base + c * 64 + lane] = (int)(p0 + c * 64);
+    return;
+  }
+#pragma unroll
+  for (int c = 0; c < kWaveRuns; ++c) {
+    const int r = wave_rank(cursors, t[c] < 0 ? 0 : t[c], t[c] >= 0);
+    if (t[c] >= 0) stage[starts[t[c]] + r] = (int)(p0 + c * 64);
+  }
 }
 
-// One block per tile of the slab (blockIdx.x = tile within the slab).  Each
-// thread issues the loads of kUnroll ranks before it stores any of them, so
-// a wavefront keeps that many memory requests in flight per field.
-constexpr int kUnroll = 8;
+// One block per tile of the slab (blockIdx.x = tile within the slab), 1024
+// threads.  The fields go through LDS four at a time: each thread loads four
+// fields of each of its ranks before it stores any of them, and a group of
+// 4096 ranks takes two (2D) or three (3D) passes with two barriers each.
+constexpr int kGatherThreads = 1024;
+constexpr int kFieldsPerPass = 4;
 
 template <int ND>
 __device__ __forceinline__ int import_field(const SlabDesc &sd, const PartPtrs &cp, int k, int64_t p, uint32_t &e) {
@@ -513,11 +560,13 @@ __device__ __forceinline__ int import_field(const SlabDesc &sd, const PartPtrs &
 }
 
 template <int ND>
-__global__ void __launch_bounds__(256) k_import_gather(SlabDesc sd, PartPtrs cp, Store d,
-                                                       const int *__restrict__ counts,
-                                                       const int *__restrict__ starts,
-                                                       const int *__restrict__ stage, uint32_t *__restrict__ err) {
-  __shared__ int s_p[kScrGroup], s_v[kScrGroup];
+__global__ void __launch_bounds__(kGatherThreads) k_import_gather(SlabDesc sd, PartPtrs cp, Store d,
+                                                                  const int *__restrict__ counts,
+                                                                  const int *__restrict__ starts,
+                                                                  const int *__restrict__ stage,
+                                                                  uint32_t *__restrict__ err) {
+  __shared__ int s_v[kFieldsPerPass][kScrGroup];
+  constexpr int NF = ND + 6;
   const int t = sd.tile_off + (int)blockIdx.x;
   const int L = counts[t], s0 = starts[t];
   const int tid = threadIdx.x, B = blockDim.x;
@@ -525,33 +574,29 @@ __global__ void __launch_bounds__(256) k_import_gather(SlabDesc sd, PartPtrs cp,
   for (int g0 = 0; g0 < L; g0 += kScrGroup) {
     const int len = min(kScrGroup, L - g0);
     const int64_t base = (int64_t)s0 + g0;
-    for (int r = tid; r < len; r += B) s_p[r] = stage[base + r];
-    __syncthreads();
-    // each field is gathered in rank order, permuted in LDS and written in
-    // slot order
-    for (int k = 0; k < ND + 6; ++k) {
+    for (int k0 = 0; k0 < NF; k0 += kFieldsPerPass) {
+      // gathered in rank order, permuted in LDS ...
       ScrWalk w(tid, B, len);
-      for (int r0 = tid; r0 < len; r0 += kUnroll * B) {
-        int v[kUnroll];
+      for (int r = tid; r < len; r += B, w.next()) {
+        const int64_t p = stage[base + r];
+        int v[kFieldsPerPass];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const int r = r0 + u * B;
-          v[u] = r < len ? import_field<ND>(sd, cp, k, s_p[r], e) : 0;
-        }
+        for (int j = 0; j < kFieldsPerPass; ++j) v[j] = k0 + j < NF ? import_field<ND>(sd, cp, k0 + j, p, e) : 0;
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          if (r0 + u * B < len) {
-            s_v[w.q] = v[u];
-            w.next();
-          }
-        }
+        for (int j = 0; j < kFieldsPerPass; ++j) s_v[j][w.q] = v[j];
       }
       __syncthreads();
-      int *dst = k == 0 ? d.pc
-                 : k <= ND ? reinterpret_cast<int *>(d.off) + (int64_t)(k - 1) * d.cap
-                 : k <= ND + 3 ? reinterpret_cast<int *>(d.vel) + (int64_t)(k - ND - 1) * d.cap
-                 : k == ND + 4 ? d.wq : d.oidx;
-      for (int q = tid; q < len; q += B) dst[base + q] = s_v[q];
+      // ... and written in slot order
+#pragma unroll
+      for (int j = 0; j < kFieldsPerPass; ++j) {
+        const int k = k0 + j;
+        if (k >= NF) break;
+        int *dst = k == 0 ? d.pc
+                   : k <= ND ? reinterpret_cast<int *>(d.off) + (int64_t)(k - 1) * d.cap
+                   : k <= ND + 3 ? reinterpret_cast<int *>(d.vel) + (int64_t)(k - ND - 1) * d.cap
+                   : k == ND + 4 ? d.wq : d.oidx;
+        for (int q = tid; q < len; q += B) dst[base + q] = s_v[j][q];
+      }
       __syncthreads();
     }
   }
@@ -594,43 +639,107 @@ __global__ void __launch_bounds__(256) k_rebin_scatter(Batch b, Store s, Store d
   d.oidx[q] = s.oidx[p];
 }
 
-// Single block: exclusive scans of tile counts -> starts, and of items per
-// tile -> item_start (both with a final total entry); clears the cursors.
-__global__ void __launch_bounds__(1024) k_tile_scan(int ntiles, int chunk, const int *__restrict__ counts,
-                                                    int *__restrict__ starts, int *__restrict__ item_start,
-                                                    int *__restrict__ cursors, int *__restrict__ num_items) {
-  __shared__ long long s_a[1024], s_b[1024];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int per = (ntiles + nt - 1) / nt;
-  const int lo = tid * per, hi = min(ntiles, lo + per);
-  long long a = 0, b = 0;
-  for (int t = lo; t < hi; ++t) {
-    a += counts[t];
-    b += (counts[t] + chunk - 1) / chunk;
+// Exclusive scans of the tile counts -> starts and of the items per tile
+// (ceil(count / chunk)) -> item_start, both with a final total entry, in
+// three launches: per-block sums of 1024 tiles, one block scanning those
+// sums, then per-block scans offset by them (which also clear the cursors).
+// aux: two ints per block of 1024 tiles.
+constexpr int kScanBlock = 1024;
+
+__device__ __forceinline__ int tile_item_count(int c, int chunk) { return (c + chunk - 1) / chunk; }
+
+// Inclusive scan of one value per thread over a block of kScanBlock threads
+// (wavefront prefix sums, then the wavefront totals).
+__device__ __forceinline__ int block_inclusive_scan(int v, int *s_w) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
   }
-  s_a[tid] = a;
-  s_b[tid] = b;
+  if (lane == 63) s_w[wv] = v;
   __syncthreads();
-  for (int o = 1; o < nt; o <<= 1) {  // Hillis-Steele inclusive scan
-    long long va = tid >= o ? s_a[tid - o] : 0, vb = tid >= o ? s_b[tid - o] : 0;
+  if (wv == 0) {
+    int t = lane < kScanBlock / 64 ? s_w[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < kScanBlock / 64; o <<= 1) {
+      const int u = __shfl_up(t, o, 64);
+      if (lane >= o) t += u;
+    }
+    if (lane < kScanBlock / 64) s_w[lane] = t;
+  }
+  __syncthreads();
+  const int r = v + (wv > 0 ? s_w[wv - 1] : 0);
+  __syncthreads();  // s_w is reused by the next scan
+  return r;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_sums(int ntiles, int chunk, const int *__restrict__ counts,
+                                                          int *__restrict__ aux) {
+  __shared__ int s_w[kScanBlock / 64];
+  const int t = blockIdx.x * kScanBlock + threadIdx.x;
+  const int c = t < ntiles ? counts[t] : 0;
+  const int a = block_inclusive_scan(c, s_w);
+  const int b = block_inclusive_scan(tile_item_count(c, chunk), s_w);
+  if (threadIdx.x == kScanBlock - 1) {
+    aux[2 * blockIdx.x] = a;
+    aux[2 * blockIdx.x + 1] = b;
+  }
+}
+
+// One block: exclusive scan of the per-block sums in place, and the totals.
+__global__ void __launch_bounds__(kScanBlock) k_scan_totals(int nblocks, int ntiles, int *__restrict__ aux,
+                                                            int *__restrict__ starts, int *__restrict__ item_start,
+                                                            int *__restrict__ num_items) {
+  __shared__ int s_w[kScanBlock / 64];
+  __shared__ int s_tot[2];
+  int ca = 0, cb = 0;  // carried over chunks of kScanBlock block sums
+  for (int k0 = 0; k0 < nblocks; k0 += kScanBlock) {
+    const int k = k0 + (int)threadIdx.x;
+    const int a = k < nblocks ? aux[2 * k] : 0, b = k < nblocks ? aux[2 * k + 1] : 0;
+    const int ia = block_inclusive_scan(a, s_w), ib = block_inclusive_scan(b, s_w);
+    if (k < nblocks) {
+      aux[2 * k] = ca + ia - a;
+      aux[2 * k + 1] = cb + ib - b;
+    }
+    if (threadIdx.x == kScanBlock - 1) {
+      s_tot[0] = ia;
+      s_tot[1] = ib;
+    }
     __syncthreads();
-    s_a[tid] += va;
-    s_b[tid] += vb;
+    ca += s_tot[0];
+    cb += s_tot[1];
     __syncthreads();
   }
-  long long ra = tid ? s_a[tid - 1] : 0, rb = tid ? s_b[tid - 1] : 0;
-  for (int t = lo; t < hi; ++t) {
-    starts[t] = (int)ra;
-    item_start[t] = (int)rb;
+  if (threadIdx.x == 0) {
+    starts[ntiles] = ca;
+    item_start[ntiles] = cb;
+    *num_items = cb;
+  }
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_apply(int ntiles, int chunk, const int *__restrict__ counts,
+                                                           const int *__restrict__ aux, int *__restrict__ starts,
+                                                           int *__restrict__ item_start, int *__restrict__ cursors) {
+  __shared__ int s_w[kScanBlock / 64];
+  const int t = blockIdx.x * kScanBlock + threadIdx.x;
+  const int c = t < ntiles ? counts[t] : 0, m = tile_item_count(c, chunk);
+  const int ia = block_inclusive_scan(c, s_w), ib = block_inclusive_scan(m, s_w);
+  if (t < ntiles) {
+    starts[t] = aux[2 * blockIdx.x] + ia - c;
+    item_start[t] = aux[2 * blockIdx.x + 1] + ib - m;
     cursors[t] = 0;
-    ra += counts[t];
-    rb += (counts[t] + chunk - 1) / chunk;
   }
-  if (tid == nt - 1) {
-    starts[ntiles] = (int)s_a[nt - 1];
-    item_start[ntiles] = (int)s_b[nt - 1];
-    *num_items = (int)s_b[nt - 1];
-  }
+}
+
+// The three launches; aux lives in the item buffer, which k_tile_items
+// overwrites afterwards (it holds at least one item per tile).
+static void launch_tile_scan(hipStream_t st, int ntiles, int chunk, const BinBufs &bb) {
+  const int nb = std::max(1, (ntiles + kScanBlock - 1) / kScanBlock);
+  int *aux = reinterpret_cast<int *>(bb.items);
+  k_scan_sums<<<nb, kScanBlock, 0, st>>>(ntiles, chunk, bb.counts, aux);
+  k_scan_totals<<<1, kScanBlock, 0, st>>>(nb, ntiles, aux, bb.starts, bb.item_start, bb.num_items);
+  k_scan_apply<<<nb, kScanBlock, 0, st>>>(ntiles, chunk, bb.counts, aux, bb.starts, bb.item_start, bb.cursors);
 }
 
 __global__ void __launch_bounds__(256) k_tile_items(Batch b, const int *__restrict__ counts,
@@ -639,7 +748,7 @@ __global__ void __launch_bounds__(256) k_tile_items(Batch b, const int *__restri
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= b.ntiles) return;
   const int slab = find_slab(b.tile_offs, b.nslab, t);
-  // ceil(c / chunk) items of near-equal size (each at most chunk; k_tile_scan
+  // ceil(c / chunk) items of near-equal size (each at most chunk; the scan
   // counted them): equal items let the persistent grid finish its rounds
   // together
   const int c = counts[t], s = starts[t], i0 = item_start[t];
@@ -647,6 +756,8 @@ __global__ void __launch_bounds__(256) k_tile_items(Batch b, const int *__restri
   for (int k = 0; k < m; ++k)
     items[i0 + k] = Item{t, s + (int)((long long)k * c / m), s + (int)((long long)(k + 1) * c / m), slab};
 }
+
+constexpr int kUnroll = 8;  // loads in flight per thread per field
 
 template <int ND>
 __global__ void __launch_bounds__(256) k_export(SlabDesc sd, Store s, const int *__restrict__ starts, PartPtrs cp) {
@@ -913,17 +1024,31 @@ __global__ void __launch_bounds__(256) k_deposit_tiled(Batch b, Store s, const I
 }
 
 // One slab's diagnostics: its items' block partials (a contiguous item range;
-// each item's drifters are in its partial) and its node energy partials.
-__global__ void __launch_bounds__(256) k_reduce_diag_slab(const double *__restrict__ part_p,
+// each item's drifters are in its partial) and its node energy partials, in
+// two launches: kRedBlocks blocks each sum a fixed share of both lists into
+// red, then one block sums red in a fixed order (deterministic).
+constexpr int kRedBlocks = kDiagRedDoubles / 8;
+
+__global__ void __launch_bounds__(256) k_reduce_diag_part(const double *__restrict__ part_p,
                                                           const int *__restrict__ item_start, int tile_lo,
                                                           int tile_hi, const double *__restrict__ part_g, int nblk_g,
-                                                          pic_diag_t *__restrict__ out, int64_t step) {
+                                                          double *__restrict__ red) {
   const int lo = item_start[tile_lo], hi = item_start[tile_hi];
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int b = lo + threadIdx.x; b < hi; b += blockDim.x)
+  const int stride = gridDim.x * blockDim.x;
+  for (int b = lo + blockIdx.x * blockDim.x + threadIdx.x; b < hi; b += stride)
 #pragma unroll
     for (int i = 0; i < 6; ++i) acc[i] += part_p[(int64_t)b * 8 + i];
-  for (int b = threadIdx.x; b < nblk_g; b += blockDim.x) acc[6] += part_g[(int64_t)b * 8];
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nblk_g; b += stride) acc[6] += part_g[(int64_t)b * 8];
+  block_reduce_store<7>(acc, red + (int64_t)blockIdx.x * 8);
+}
+
+__global__ void __launch_bounds__(256) k_reduce_diag_slab(const double *__restrict__ red, pic_diag_t *__restrict__ out,
+                                                          int64_t step) {
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < kRedBlocks; b += blockDim.x)
+#pragma unroll
+    for (int i = 0; i < 7; ++i) acc[i] += red[(int64_t)b * 8 + i];
   __shared__ double res[8];
   block_reduce_store<7>(acc, res);
   __syncthreads();
@@ -1392,24 +1517,27 @@ void launch_import(hipStream_t st, int ndim, const SlabDesc *sd_host, const Part
                    const BinBufs &bb, const Batch &b, int chunk, const Store &dst, int *stage, uint32_t *err) {
   launch_fill32(st, bb.counts, b.ntiles);
   for (int k = 0; k < nslab; ++k)
-    if (cp[k].n > 0) PIC_ND(ndim, (k_import_hist<ND><<<nblk(cp[k].n), 256, 0, st>>>(sd_host[k], cp[k], bb.counts, err)));
-  k_tile_scan<<<1, 1024, 0, st>>>(b.ntiles, chunk, bb.counts, bb.starts, bb.item_start, bb.cursors, bb.num_items);
+    if (cp[k].n > 0)
+      PIC_ND(ndim, (k_import_hist<ND><<<nblk(cp[k].n, 256 * kWaveRuns), 256, 0, st>>>(sd_host[k], cp[k], bb.counts,
+                                                                                     err)));
+  launch_tile_scan(st, b.ntiles, chunk, bb);
   k_tile_items<<<nblk(b.ntiles), 256, 0, st>>>(b, bb.counts, bb.starts, bb.item_start, bb.items);
   for (int k = 0; k < nslab; ++k)
     if (cp[k].n > 0)
-      PIC_ND(ndim, (k_import_index<ND><<<nblk(cp[k].n), 256, 0, st>>>(sd_host[k], cp[k], bb.starts, bb.cursors,
-                                                                      stage)));
+      PIC_ND(ndim, (k_import_index<ND><<<nblk(cp[k].n, 256 * kWaveRuns), 256, 0, st>>>(sd_host[k], cp[k], bb.starts,
+                                                                                      bb.cursors, stage)));
   for (int k = 0; k < nslab; ++k)
     if (cp[k].n > 0 && sd_host[k].tg.ntiles > 0)
-      PIC_ND(ndim, (k_import_gather<ND><<<sd_host[k].tg.ntiles, 256, 0, st>>>(sd_host[k], cp[k], dst, bb.counts,
-                                                                              bb.starts, stage, err)));
+      PIC_ND(ndim, (k_import_gather<ND><<<sd_host[k].tg.ntiles, kGatherThreads, 0, st>>>(sd_host[k], cp[k], dst,
+                                                                                         bb.counts, bb.starts, stage,
+                                                                                         err)));
 }
 
 void launch_rebin(hipStream_t st, int ndim, const BinBufs &bb, const Batch &b, int chunk, const Store &src,
                   const Store &dst) {
   launch_fill32(st, bb.counts, b.ntiles);
   if (b.nparts > 0) PIC_ND(ndim, (k_rebin_hist<ND><<<nblk(b.nparts), 256, 0, st>>>(b, src, bb.counts)));
-  k_tile_scan<<<1, 1024, 0, st>>>(b.ntiles, chunk, bb.counts, bb.starts, bb.item_start, bb.cursors, bb.num_items);
+  launch_tile_scan(st, b.ntiles, chunk, bb);
   k_tile_items<<<nblk(b.ntiles), 256, 0, st>>>(b, bb.counts, bb.starts, bb.item_start, bb.items);
   if (b.nparts > 0)
     PIC_ND(ndim, (k_rebin_scatter<ND><<<nblk(b.nparts), 256, 0, st>>>(b, src, dst, bb.starts, bb.cursors)));
@@ -1458,8 +1586,9 @@ void launch_step_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P
 }
 
 void launch_reduce_diag_slab(hipStream_t st, const double *part_p, const int *item_start, int tile_lo, int tile_hi,
-                             const double *part_g, int nblk_g, pic_diag_t *out, int64_t step) {
-  k_reduce_diag_slab<<<1, 256, 0, st>>>(part_p, item_start, tile_lo, tile_hi, part_g, nblk_g, out, step);
+                             const double *part_g, int nblk_g, double *red, pic_diag_t *out, int64_t step) {
+  k_reduce_diag_part<<<kRedBlocks, 256, 0, st>>>(part_p, item_start, tile_lo, tile_hi, part_g, nblk_g, red);
+  k_reduce_diag_slab<<<1, 256, 0, st>>>(red, out, step);
 }
 
 size_t adjoint_lds_bytes(const TileGeo &tg, int ndim) {
