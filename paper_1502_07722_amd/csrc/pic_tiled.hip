@@ -142,15 +142,55 @@ struct Window {
   int o[3];   // node coordinate of window node 0 per axis
   int wn[3];  // window nodes per axis (T + 2H + 3)
   int nW, nC; // window nodes, window centres
+  int sy, sz; // node strides along y and z (wn0, wn0 wn1)
+  int cy, cz; // centre strides along y and z ((wn0 - 1), (wn0 - 1)(wn1 - 1))
 };
 
+// Window indices (coordinates are non-negative and small: 24-bit multiplies).
 template <int ND>
 __device__ __forceinline__ int win_node(const Window &w, int a0, int a1, int a2) {
-  return ND == 2 ? a0 + w.wn[0] * a1 : a0 + w.wn[0] * (a1 + w.wn[1] * a2);
+  return ND == 2 ? a0 + __umul24(w.sy, a1) : a0 + __umul24(w.sy, a1) + __umul24(w.sz, a2);
 }
 template <int ND>
 __device__ __forceinline__ int win_centre(const Window &w, int m0, int m1, int m2) {
-  return ND == 2 ? m0 + (w.wn[0] - 1) * m1 : m0 + (w.wn[0] - 1) * (m1 + (w.wn[1] - 1) * m2);
+  return ND == 2 ? m0 + __umul24(w.cy, m1) : m0 + __umul24(w.cy, m1) + __umul24(w.cz, m2);
+}
+// Offset of corner k (bit d set = upper along d) from a cell's lower node /
+// from the lower centre of a centre cube.
+template <int ND>
+__device__ __forceinline__ int node_corner(const Window &w, int k) {
+  return (k & 1) + ((k >> 1) & 1) * w.sy + (ND == 3 ? ((k >> 2) & 1) * w.sz : 0);
+}
+template <int ND>
+__device__ __forceinline__ int centre_corner(const Window &w, int k) {
+  return (k & 1) + ((k >> 1) & 1) * w.cy + (ND == 3 ? ((k >> 2) & 1) * w.cz : 0);
+}
+
+// q = k / d, r = k - q d for 0 <= k < 2^22 and 0 < d < 2^10, from a float
+// reciprocal estimate (off by at most one) and one correction: exact.
+__device__ __forceinline__ int div_small(int k, int d, float inv, int &r) {
+  int q = (int)((float)k * inv);
+  r = k - __umul24(q, d);
+  if (r < 0) {
+    q -= 1;
+    r += d;
+  } else if (r >= d) {
+    q += 1;
+    r -= d;
+  }
+  return q;
+}
+
+// Window coordinates of linear window node k.
+template <int ND>
+__device__ __forceinline__ void win_coords(const Window &w, int k, float inv0, float inv1, int a[3]) {
+  int r = div_small(k, w.wn[0], inv0, a[0]);
+  if (ND == 2) {
+    a[1] = r;
+    a[2] = 0;
+  } else {
+    a[2] = div_small(r, w.wn[1], inv1, a[1]);
+  }
 }
 
 // Index in a 3^ND block of nodes (per-axis offsets 0..2).
@@ -253,6 +293,10 @@ __device__ __forceinline__ Window make_window(const TileGeo &tg, int tile) {
     w.nW *= w.wn[d];
     w.nC *= d < ND ? w.wn[d] - 1 : 1;
   }
+  w.sy = w.wn[0];
+  w.sz = w.wn[0] * w.wn[1];
+  w.cy = w.wn[0] - 1;
+  w.cz = (w.wn[0] - 1) * (w.wn[1] - 1);
   return w;
 }
 
@@ -261,26 +305,27 @@ __device__ __forceinline__ Window make_window(const TileGeo &tg, int tile) {
 template <int ND>
 __device__ __forceinline__ void stage_window(const Geo &g, const Window &w, const long long *__restrict__ N,
                                              float *dens, float *Gs, unsigned long long *acc) {
+  const float inv0 = 1.0f / (float)w.wn[0], inv1 = 1.0f / (float)w.wn[1];
   for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
-    int a0 = k % w.wn[0], r = k / w.wn[0];
-    int a1 = ND == 2 ? r : r % w.wn[1];
-    int a2 = ND == 2 ? 0 : r / w.wn[1];
-    int x = fold_node(g, 0, w.o[0] + a0), y = fold_node(g, 1, w.o[1] + a1);
-    int z = ND == 3 ? fold_node(g, 2, w.o[2] + a2) : 0;
+    int a[3];
+    win_coords<ND>(w, k, inv0, inv1, a);
+    int x = fold_node(g, 0, w.o[0] + a[0]), y = fold_node(g, 1, w.o[1] + a[1]);
+    int z = ND == 3 ? fold_node(g, 2, w.o[2] + a[2]) : 0;
     dens[k] = node_density(g, N[node_index<ND>(g, x, y, z)], x, y, z);
     if (acc) acc[k] = 0ull;
   }
   __syncthreads();
   if (!Gs) return;
-  const int wc0 = w.wn[0] - 1, wc1 = w.wn[1] - 1;
+  const float cinv0 = 1.0f / (float)w.cy, cinv1 = 1.0f / (float)(w.wn[1] - 1);
   for (int m = threadIdx.x; m < w.nC; m += blockDim.x) {
-    int m0 = m % wc0, r = m / wc0;
-    int m1 = ND == 2 ? r : r % wc1;
-    int m2 = ND == 2 ? 0 : r / wc1;
+    int m0, m1, m2 = 0;
+    const int r = div_small(m, w.cy, cinv0, m0);
+    if (ND == 2) m1 = r;
+    else m2 = div_small(r, w.wn[1] - 1, cinv1, m1);
+    const int nb = win_node<ND>(w, m0, m1, m2);
     float c[8], G[3];
 #pragma unroll
-    for (int k = 0; k < (1 << ND); ++k)
-      c[k] = dens[win_node<ND>(w, m0 + (k & 1), m1 + ((k >> 1) & 1), ND == 3 ? m2 + ((k >> 2) & 1) : 0)];
+    for (int k = 0; k < (1 << ND); ++k) c[k] = dens[nb + node_corner<ND>(w, k)];
     centre_gradient<ND>(g, c, G);
 #pragma unroll
     for (int d = 0; d < ND; ++d) Gs[d * w.nC + m] = G[d];  // one plane per component
@@ -291,15 +336,15 @@ __device__ __forceinline__ void stage_window(const Geo &g, const Window &w, cons
 template <int ND>
 __device__ __forceinline__ void flush_window(const Geo &g, const Window &w, const unsigned long long *acc,
                                              unsigned long long *__restrict__ N) {
+  const float inv0 = 1.0f / (float)w.wn[0], inv1 = 1.0f / (float)w.wn[1];
   for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
     unsigned long long v = acc[k];
     if (!v) continue;
-    int a0 = k % w.wn[0], r = k / w.wn[0];
-    int a1 = ND == 2 ? r : r % w.wn[1];
-    int a2 = ND == 2 ? 0 : r / w.wn[1];
+    int a[3];
+    win_coords<ND>(w, k, inv0, inv1, a);
     // deposits only ever land on nodes inside the domain; wrap periodic axes
-    int x = fold_node(g, 0, w.o[0] + a0), y = fold_node(g, 1, w.o[1] + a1);
-    int z = ND == 3 ? fold_node(g, 2, w.o[2] + a2) : 0;
+    int x = fold_node(g, 0, w.o[0] + a[0]), y = fold_node(g, 1, w.o[1] + a[1]);
+    int z = ND == 3 ? fold_node(g, 2, w.o[2] + a[2]) : 0;
     atomicAdd(&N[node_index<ND>(g, x, y, z)], v);
   }
 }
@@ -855,9 +900,9 @@ __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC
     wave_append(dlist, ndrift, p, live && !inside);
     if (inside) {
       float cr[8];
+      const int nb = win_node<ND>(w, l[0], l[1], l[2]);
 #pragma unroll
-      for (int k = 0; k < (1 << ND); ++k)
-        cr[k] = dens[win_node<ND>(w, l[0] + (k & 1), l[1] + ((k >> 1) & 1), ND == 3 ? l[2] + ((k >> 2) & 1) : 0)];
+      for (int k = 0; k < (1 << ND); ++k) cr[k] = dens[nb + node_corner<ND>(w, k)];
       const float nh = interp<ND>(cr, cur.f);
       int c0[3] = {0, 0, 0};
       float t[3] = {0.f, 0.f, 0.f};
@@ -865,10 +910,10 @@ __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC
       for (int e = 0; e < ND; ++e) centre_stencil(l[e], cur.f[e], c0[e], t[e]);
       float Gp[3] = {0.f, 0.f, 0.f};
       float vv[3][8];
+      const int cb = win_centre<ND>(w, c0[0], c0[1], c0[2]);
 #pragma unroll
       for (int k = 0; k < (1 << ND); ++k) {
-        const int m =
-            win_centre<ND>(w, c0[0] + (k & 1), c0[1] + ((k >> 1) & 1), ND == 3 ? c0[2] + ((k >> 2) & 1) : 0);
+        const int m = cb + centre_corner<ND>(w, k);
         // component planes: the x-neighbour centres m, m + 1 are adjacent words
         // (one two-address LDS read per component and corner pair)
 #pragma unroll
@@ -881,12 +926,10 @@ __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC
                                            e_all, acc6);
       // a sub-cell move keeps the new cell inside the deposit window
       if (item_window<ND, INTERIOR>(g, w, idx, 0, 2, l)) {
+        const int db = win_node<ND>(w, l[0], l[1], l[2]);
 #pragma unroll
         for (int k = 0; k < (1 << ND); ++k)
-          if (tq[k])
-            atomicAdd(&acc[win_node<ND>(w, l[0] + (k & 1), l[1] + ((k >> 1) & 1),
-                                        ND == 3 ? l[2] + ((k >> 2) & 1) : 0)],
-                      (unsigned long long)tq[k]);
+          if (tq[k]) atomicAdd(&acc[db + node_corner<ND>(w, k)], (unsigned long long)tq[k]);
       } else {
         deposit_global<ND>(g, Nnext, idx, tq);
       }
@@ -1323,12 +1366,12 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
   if (threadIdx.x == 0) s_amax = 0u;
   const long long *N = Ncur + sd.node_off;
   const float *nbn = nbar_next ? nbar_next + sd.node_off : nullptr;
+  const float inv0 = 1.0f / (float)w.wn[0], inv1 = 1.0f / (float)w.wn[1];
   for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
-    const int a0 = k % w.wn[0], r = k / w.wn[0];
-    const int a1 = ND == 2 ? r : r % w.wn[1];
-    const int a2 = ND == 2 ? 0 : r / w.wn[1];
-    const int x = fold_node(g, 0, w.o[0] + a0), y = fold_node(g, 1, w.o[1] + a1);
-    const int z = ND == 3 ? fold_node(g, 2, w.o[2] + a2) : 0;
+    int a[3];
+    win_coords<ND>(w, k, inv0, inv1, a);
+    const int x = fold_node(g, 0, w.o[0] + a[0]), y = fold_node(g, 1, w.o[1] + a[1]);
+    const int z = ND == 3 ? fold_node(g, 2, w.o[2] + a[2]) : 0;
     const int node = node_index<ND>(g, x, y, z);
     dw[k] = node_density(g, N[node], x, y, z);
     nx[k] = nbn ? node_density(g, 1ll, x, y, z) * nbn[node] : 0.0f;
@@ -1391,10 +1434,9 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
   for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
     const long long iv = (long long)acc[k];
     if (iv == 0) continue;
-    const int a0 = k % w.wn[0], r = k / w.wn[0];
-    const int a1 = ND == 2 ? r : r % w.wn[1];
-    const int a2 = ND == 2 ? 0 : r / w.wn[1];
-    atomicAdd(&nbar[sd.node_off + folded_node<ND>(g, w.o[0] + a0, w.o[1] + a1, w.o[2] + a2)],
+    int a[3];
+    win_coords<ND>(w, k, inv0, inv1, a);
+    atomicAdd(&nbar[sd.node_off + folded_node<ND>(g, w.o[0] + a[0], w.o[1] + a[1], w.o[2] + a[2])],
               (float)((double)iv * from_fix));
   }
   if (e_all) atomicOr(err, e_all);
