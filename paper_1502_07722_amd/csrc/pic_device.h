@@ -88,6 +88,11 @@ __device__ __forceinline__ int node_index(const Geo &g, int a0, int a1, int a2) 
   return ND == 2 ? a0 + g.nn[0] * a1 : a0 + g.nn[0] * (a1 + g.nn[1] * a2);
 }
 
+// Node weight sum as a float: through double, where the sum of the two
+// 32-bit halves is exact below 2^53, so the value is rounded once (and every
+// path converts node sums here, so they all agree beyond that too).
+__device__ __forceinline__ float wsum_float(long long wsum) { return (float)(double)wsum; }
+
 // Reduced density of a stored node: weight sum * kappa, doubled for each
 // reflecting wall the node lies on (half volume there).
 __device__ __forceinline__ float node_density(const Geo &g, long long wsum, int a0, int a1, int a2) {
@@ -95,7 +100,7 @@ __device__ __forceinline__ float node_density(const Geo &g, long long wsum, int 
   if (g.bc[0] && (a0 == 0 || a0 == g.n[0])) k *= 2.0f;
   if (g.bc[1] && (a1 == 0 || a1 == g.n[1])) k *= 2.0f;
   if (g.ndim == 3 && g.bc[2] && (a2 == 0 || a2 == g.n[2])) k *= 2.0f;
-  return (float)wsum * k;
+  return wsum_float(wsum) * k;
 }
 
 // ---------------------------------------------------------------------------
@@ -187,9 +192,10 @@ __device__ __forceinline__ float morse_e(const Pot &P, float s) {
   return __builtin_amdgcn_exp2f(__builtin_fmaf(-P.mAl2, __builtin_amdgcn_rcpf(s), P.mAl2));
 }
 
+// phi'(s) / (12 D / r0) as the branch factor M (s_rep for s > 1, c_att
+// otherwise), returned, times the shape v.
 template <bool GEN = false>
-__device__ __forceinline__ float dphi_hat(const Pot &P, float s) {
-  float v;
+__device__ __forceinline__ float dphi_split(const Pot &P, float s, float &v) {
   if (GEN && P.kind == 1) {
     const float e = morse_e(P, s);
     v = P.mA6 * __builtin_fmaf(-e, e, e);  // (alpha r0 / 6) (e - e^2)
@@ -200,7 +206,14 @@ __device__ __forceinline__ float dphi_hat(const Pot &P, float s) {
     float s7 = s6 * s;
     v = __builtin_fmaf(-s7, s6, s7);  // s^7 - s^13
   }
-  return (s > 1.0f ? P.s_rep : P.c_att) * v;
+  return s > 1.0f ? P.s_rep : P.c_att;
+}
+
+template <bool GEN = false>
+__device__ __forceinline__ float dphi_hat(const Pot &P, float s) {
+  float v;
+  const float M = dphi_split<GEN>(P, s, v);
+  return M * v;
 }
 
 template <bool GEN = false>
@@ -280,8 +293,8 @@ __device__ __forceinline__ void pair_force(const Pot &P, float nh, const float G
   if (bond) *bond = 0.0f;
   if (!(nh > P.nfloor)) return;
   float q = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(nh) * (1.0f / 3.0f));
-  float rinv = __builtin_amdgcn_rcpf(nh * q);
   if (GEN && P.lattice == 1) {
+    const float rinv = __builtin_amdgcn_rcpf(nh * q);
     float g[3] = {0.0f, 0.0f, 0.0f}, e = 0.0f;
 #pragma unroll
     for (int d = 0; d < ND; ++d) g[d] = (G[d] * rinv) * (-1.0f / 3.0f);
@@ -289,15 +302,19 @@ __device__ __forceinline__ void pair_force(const Pot &P, float nh, const float G
     if (bond) *bond = e;
     return;
   }
+  // s+- = q (1 -+ g/2) with g = -(1/3) Gh / (nh q):  q g / 2 = -Gh / (6 nh),
+  // and |g| <= gclamp is |q g / 2| <= q gclamp / 2
+  const float rn6 = __builtin_amdgcn_rcpf(nh) * (-1.0f / 6.0f);
+  const float hc = q * (0.5f * P.gclamp);
   float e = 0.0f;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    float g = (G[d] * rinv) * (-1.0f / 3.0f);
-    g = fminf(fmaxf(g, -P.gclamp), P.gclamp);
-    float hq = 0.5f * q * g;
-    float sp = q - hq;  // +d neighbour (farther when rbar grows towards +d)
-    float sm = q + hq;  // -d neighbour
-    F[d] = dphi_hat<GEN>(P, sp) - dphi_hat<GEN>(P, sm);
+    const float hq = fminf(fmaxf(G[d] * rn6, -hc), hc);
+    const float sp = q - hq;  // +d neighbour (farther when rbar grows towards +d)
+    const float sm = q + hq;  // -d neighbour
+    float vp, vm;
+    const float Mp = dphi_split<GEN>(P, sp, vp), Mm = dphi_split<GEN>(P, sm, vm);
+    F[d] = __builtin_fmaf(Mp, vp, -(Mm * vm));
     if (bond) e += 0.5f * (phi_hat<GEN>(P, sp) + phi_hat<GEN>(P, sm));
   }
   if (bond) *bond = e;
@@ -322,17 +339,19 @@ __device__ __forceinline__ uint32_t push_particle(const Geo &g, const Pot &P, co
     const bool cfl = !(fabsf(df) < 1.0f);
     err |= cfl ? ERR_CFL : 0u;
     df = cfl ? 0.0f : df;
-    const float x = f[d] + df;
-    const bool up = x >= 1.0f, down = x < 0.0f;
-    // carry one cell; a tiny negative x can round x + 1 up to 1: that is the node itself
-    float xc = up ? x - 1.0f : (down ? x + 1.0f : x);
-    int ic = idx[d] + (up ? 1 : (down ? -1 : 0));
-    const bool tie = down && xc >= 1.0f;
+    const float x = f[d] + df;  // in (-1, 2)
+    // carry one cell: x - floor(x) is exact on [0, 2); on (-1, 0) it is x + 1,
+    // which a tiny negative x rounds up to 1: that is the node itself
+    const float fl = floorf(x);
+    float xc = x - fl;
+    int ic = idx[d] + (int)fl;
+    const bool tie = xc >= 1.0f;
     xc = tie ? 0.0f : xc;
     ic = tie ? idx[d] : ic;
     float xn = xc;
     if (!INTERIOR) {
       const int n = g.n[d];
+      const bool up = x >= 1.0f, down = x < 0.0f;
       const bool wall_lo = g.bc[d] && idx[d] == 0 && down;
       const bool wall_hi = g.bc[d] && idx[d] == n - 1 && up;
       if (!g.bc[d]) ic = ic < 0 ? ic + n : (ic >= n ? ic - n : ic);
@@ -345,7 +364,8 @@ __device__ __forceinline__ uint32_t push_particle(const Geo &g, const Pot &P, co
       v[d] = wall ? -v[d] : v[d];
     }
     idx[d] = ic;
-    const bool bad = !(xn >= 0.0f && xn < 1.0f);
+    // xn is never -0 (x - x is +0), so one unsigned compare tests [0, 1) and NaN
+    const bool bad = __float_as_uint(xn) >= 0x3f800000u;
     err |= bad ? ERR_RANGE : 0u;
     f[d] = bad ? 0.0f : xn;
   }

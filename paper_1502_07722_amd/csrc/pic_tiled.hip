@@ -181,18 +181,6 @@ __device__ __forceinline__ int div_small(int k, int d, float inv, int &r) {
   return q;
 }
 
-// Window coordinates of linear window node k.
-template <int ND>
-__device__ __forceinline__ void win_coords(const Window &w, int k, float inv0, float inv1, int a[3]) {
-  int r = div_small(k, w.wn[0], inv0, a[0]);
-  if (ND == 2) {
-    a[1] = r;
-    a[2] = 0;
-  } else {
-    a[2] = div_small(r, w.wn[1], inv1, a[1]);
-  }
-}
-
 // Index in a 3^ND block of nodes (per-axis offsets 0..2).
 template <int ND>
 __device__ __forceinline__ constexpr int b3(int a0, int a1, int a2) {
@@ -300,29 +288,83 @@ __device__ __forceinline__ Window make_window(const TileGeo &tg, int tile) {
   return w;
 }
 
+// Mixed-radix digits (a0, a1, a2) of k = k0, k0 + stride, k0 + 2 stride, ...
+// over radices (r0, r1): each step adds the stride's digits with one
+// conditional carry per digit (k0, stride < 2^22; r0, r1 < 2^10).
+template <int ND>
+struct Walk {
+  int a[3], s[3], r0, r1;
+  __device__ __forceinline__ Walk(int k0, int stride, int r0_, int r1_) : r0(r0_), r1(r1_) {
+    const float i0 = 1.0f / (float)r0, i1 = 1.0f / (float)r1;
+    int q = div_small(k0, r0, i0, a[0]);
+    int t = div_small(stride, r0, i0, s[0]);
+    if (ND == 2) {
+      a[1] = q;
+      s[1] = t;
+      a[2] = s[2] = 0;
+    } else {
+      a[2] = div_small(q, r1, i1, a[1]);
+      s[2] = div_small(t, r1, i1, s[1]);
+    }
+  }
+  __device__ __forceinline__ void next() {
+    a[0] += s[0];
+    const int c0 = a[0] >= r0 ? 1 : 0;
+    a[0] -= c0 ? r0 : 0;
+    a[1] += s[1] + c0;
+    if (ND == 3) {
+      const int c1 = a[1] >= r1 ? 1 : 0;
+      a[1] -= c1 ? r1 : 0;
+      a[2] += s[2] + c1;
+    }
+  }
+};
+
+// Uniform properties of a window: every window node is a stored node as it
+// stands (no periodic wrap or mirror), and none lies on a reflecting wall.
+template <int ND>
+__device__ __forceinline__ void window_flags(const Geo &g, const Window &w, bool &nofold, bool &nowall) {
+  nofold = true;
+  nowall = true;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    nofold = nofold && w.o[d] >= 0 && w.o[d] + w.wn[d] <= g.nn[d];
+    nowall = nowall && (!g.bc[d] || (w.o[d] > 0 && w.o[d] + w.wn[d] - 1 < g.n[d]));
+  }
+}
+
+// Stored node of window node a (folded like the global path).
+template <int ND>
+__device__ __forceinline__ void window_node(const Geo &g, const Window &w, const int a[3], bool nofold, int x[3]) {
+  if (nofold) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) x[d] = d < ND ? w.o[d] + a[d] : 0;
+  } else {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) x[d] = d < ND ? fold_node(g, d, w.o[d] + a[d]) : 0;
+  }
+}
+
 // Stage the window: densities of the window nodes (folded like the global
 // path) and the centre gradients between them; clear the accumulator.
 template <int ND>
 __device__ __forceinline__ void stage_window(const Geo &g, const Window &w, const long long *__restrict__ N,
                                              float *dens, float *Gs, unsigned long long *acc) {
-  const float inv0 = 1.0f / (float)w.wn[0], inv1 = 1.0f / (float)w.wn[1];
-  for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
-    int a[3];
-    win_coords<ND>(w, k, inv0, inv1, a);
-    int x = fold_node(g, 0, w.o[0] + a[0]), y = fold_node(g, 1, w.o[1] + a[1]);
-    int z = ND == 3 ? fold_node(g, 2, w.o[2] + a[2]) : 0;
-    dens[k] = node_density(g, N[node_index<ND>(g, x, y, z)], x, y, z);
+  bool nofold, nowall;
+  window_flags<ND>(g, w, nofold, nowall);
+  Walk<ND> it((int)threadIdx.x, (int)blockDim.x, w.wn[0], w.wn[1]);
+  for (int k = threadIdx.x; k < w.nW; k += blockDim.x, it.next()) {
+    int x[3];
+    window_node<ND>(g, w, it.a, nofold, x);
+    const long long v = N[node_index<ND>(g, x[0], x[1], x[2])];
+    dens[k] = nowall ? wsum_float(v) * g.kappa : node_density(g, v, x[0], x[1], x[2]);
     if (acc) acc[k] = 0ull;
   }
   __syncthreads();
   if (!Gs) return;
-  const float cinv0 = 1.0f / (float)w.cy, cinv1 = 1.0f / (float)(w.wn[1] - 1);
-  for (int m = threadIdx.x; m < w.nC; m += blockDim.x) {
-    int m0, m1, m2 = 0;
-    const int r = div_small(m, w.cy, cinv0, m0);
-    if (ND == 2) m1 = r;
-    else m2 = div_small(r, w.wn[1] - 1, cinv1, m1);
-    const int nb = win_node<ND>(w, m0, m1, m2);
+  Walk<ND> ic((int)threadIdx.x, (int)blockDim.x, w.cy, w.wn[1] - 1);
+  for (int m = threadIdx.x; m < w.nC; m += blockDim.x, ic.next()) {
+    const int nb = win_node<ND>(w, ic.a[0], ic.a[1], ic.a[2]);
     float c[8], G[3];
 #pragma unroll
     for (int k = 0; k < (1 << ND); ++k) c[k] = dens[nb + node_corner<ND>(w, k)];
@@ -336,16 +378,16 @@ __device__ __forceinline__ void stage_window(const Geo &g, const Window &w, cons
 template <int ND>
 __device__ __forceinline__ void flush_window(const Geo &g, const Window &w, const unsigned long long *acc,
                                              unsigned long long *__restrict__ N) {
-  const float inv0 = 1.0f / (float)w.wn[0], inv1 = 1.0f / (float)w.wn[1];
-  for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
-    unsigned long long v = acc[k];
+  bool nofold, nowall;
+  window_flags<ND>(g, w, nofold, nowall);
+  Walk<ND> it((int)threadIdx.x, (int)blockDim.x, w.wn[0], w.wn[1]);
+  for (int k = threadIdx.x; k < w.nW; k += blockDim.x, it.next()) {
+    const unsigned long long v = acc[k];
     if (!v) continue;
-    int a[3];
-    win_coords<ND>(w, k, inv0, inv1, a);
     // deposits only ever land on nodes inside the domain; wrap periodic axes
-    int x = fold_node(g, 0, w.o[0] + a[0]), y = fold_node(g, 1, w.o[1] + a[1]);
-    int z = ND == 3 ? fold_node(g, 2, w.o[2] + a[2]) : 0;
-    atomicAdd(&N[node_index<ND>(g, x, y, z)], v);
+    int x[3];
+    window_node<ND>(g, w, it.a, nofold, x);
+    atomicAdd(&N[node_index<ND>(g, x[0], x[1], x[2])], v);
   }
 }
 
@@ -382,17 +424,21 @@ struct StoreView {
   float *vel_o[3];     // is recorded)
 };
 
+// OUT false: in place (o is s), so the outputs are the inputs' own pointers
+// (one set of pointer registers).
+template <bool OUT = true>
 __device__ __forceinline__ StoreView view_of(const Store &s, const Store &o) {
+  const Store &w = OUT ? o : s;
   StoreView v;
   v.pc = s.pc;
   v.wq = s.wq;
-  v.pc_o = o.pc;
+  v.pc_o = w.pc;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     v.off[d] = s.off + d * s.cap;
     v.vel[d] = s.vel + d * s.cap;
-    v.off_o[d] = o.off + d * o.cap;
-    v.vel_o[d] = o.vel + d * o.cap;
+    v.off_o[d] = w.off + d * w.cap;
+    v.vel_o[d] = w.vel + d * w.cap;
   }
   return v;
 }
@@ -413,6 +459,19 @@ struct PState {
   float v[3];
   int W;
 };
+
+// Loads of a slot inside the store (lanes past the item's end read its last
+// slot and ignore it): no branch.
+template <int ND, bool DIAG>
+__device__ __forceinline__ void load_state_any(const StoreView &sv, int p, PState &q) {
+  q.pc = at(sv.pc, p);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    q.f[d] = d < ND ? at(sv.off[d], p) : 0.0f;
+    q.v[d] = d < ND || (ND == 2 && DIAG) ? at(sv.vel[d], p) : 0.0f;
+  }
+  q.W = at(sv.wq, p);
+}
 
 template <int ND, bool DIAG>
 __device__ __forceinline__ void load_state(const StoreView &sv, int p, bool live, PState &q) {
@@ -889,10 +948,11 @@ __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC
                                          int *ndrift, uint32_t &e_all, double acc6[6]) {
   PState cur, nxt;
   int p = it.start + (int)threadIdx.x;
-  load_state<ND, DIAG>(sv, p, p < it.end, cur);
+  const int last = it.end - 1;
+  load_state_any<ND, DIAG>(sv, min(p, last), cur);
   for (int base = it.start; base < it.end; base += blockDim.x) {
     const int pn = p + (int)blockDim.x;
-    load_state<ND, DIAG>(sv, pn, pn < it.end, nxt);
+    load_state_any<ND, DIAG>(sv, min(pn, last), nxt);
     const bool live = p < it.end;
     int idx[3], l[3];
     unpack_cell<ND>(tg, cur.pc, idx);
@@ -928,8 +988,7 @@ __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC
       if (item_window<ND, INTERIOR>(g, w, idx, 0, 2, l)) {
         const int db = win_node<ND>(w, l[0], l[1], l[2]);
 #pragma unroll
-        for (int k = 0; k < (1 << ND); ++k)
-          if (tq[k]) atomicAdd(&acc[db + node_corner<ND>(w, k)], (unsigned long long)tq[k]);
+        for (int k = 0; k < (1 << ND); ++k) atomicAdd(&acc[db + node_corner<ND>(w, k)], (unsigned long long)tq[k]);
       } else {
         deposit_global<ND>(g, Nnext, idx, tq);
       }
@@ -969,7 +1028,7 @@ __device__ __forceinline__ void advance_drifter(const Geo &g, const Pot &P, cons
 // loop needs alone; it keeps the rarely taken drifter path from raising the
 // register count of the whole kernel.
 template <int ND, bool DIAG, bool OUT, bool GEN>
-__global__ void __launch_bounds__(256, ND == 2 ? 7 : 5) k_step_tiled(Pot P, DiagC dc, Batch b, Store s, Store o,
+__global__ void __launch_bounds__(256, ND == 2 ? 7 : 4) k_step_tiled(Pot P, DiagC dc, Batch b, Store s, Store o,
                                                     const Item *__restrict__ items,
                                                     const int *__restrict__ num_items,
                                                     const long long *__restrict__ Ncur,
@@ -984,7 +1043,7 @@ __global__ void __launch_bounds__(256, ND == 2 ? 7 : 5) k_step_tiled(Pot P, Diag
     *dr.work_next = 0;
   }
   const int nit = *num_items;
-  const StoreView sv = view_of(s, o);
+  const StoreView sv = view_of<OUT>(s, o);
   uint32_t e_all = 0;
   for (;;) {
     if (threadIdx.x == 0) {
@@ -1366,16 +1425,19 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
   if (threadIdx.x == 0) s_amax = 0u;
   const long long *N = Ncur + sd.node_off;
   const float *nbn = nbar_next ? nbar_next + sd.node_off : nullptr;
-  const float inv0 = 1.0f / (float)w.wn[0], inv1 = 1.0f / (float)w.wn[1];
-  for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
-    int a[3];
-    win_coords<ND>(w, k, inv0, inv1, a);
-    const int x = fold_node(g, 0, w.o[0] + a[0]), y = fold_node(g, 1, w.o[1] + a[1]);
-    const int z = ND == 3 ? fold_node(g, 2, w.o[2] + a[2]) : 0;
-    const int node = node_index<ND>(g, x, y, z);
-    dw[k] = node_density(g, N[node], x, y, z);
-    nx[k] = nbn ? node_density(g, 1ll, x, y, z) * nbn[node] : 0.0f;
-    acc[k] = 0ull;
+  bool nofold, nowall;
+  window_flags<ND>(g, w, nofold, nowall);
+  {
+    Walk<ND> wk((int)threadIdx.x, (int)blockDim.x, w.wn[0], w.wn[1]);
+    for (int k = threadIdx.x; k < w.nW; k += blockDim.x, wk.next()) {
+      int x[3];
+      window_node<ND>(g, w, wk.a, nofold, x);
+      const int node = node_index<ND>(g, x[0], x[1], x[2]);
+      const float kf = nowall ? g.kappa : node_density(g, 1ll, x[0], x[1], x[2]);
+      dw[k] = nowall ? wsum_float(N[node]) * g.kappa : node_density(g, N[node], x[0], x[1], x[2]);
+      nx[k] = nbn ? kf * nbn[node] : 0.0f;
+      acc[k] = 0ull;
+    }
   }
   __syncthreads();
   const WinRead<ND> dens{dw, w.wn[0], w.wn[0] * w.wn[1]};
@@ -1431,13 +1493,13 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
   if (threadIdx.x == 0) atomicMax(amax_cur, s_amax);
   if (MAXONLY) return;
   const double from_fix = ldexp(1.0, -sexp);
-  for (int k = threadIdx.x; k < w.nW; k += blockDim.x) {
+  Walk<ND> wk((int)threadIdx.x, (int)blockDim.x, w.wn[0], w.wn[1]);
+  for (int k = threadIdx.x; k < w.nW; k += blockDim.x, wk.next()) {
     const long long iv = (long long)acc[k];
     if (iv == 0) continue;
-    int a[3];
-    win_coords<ND>(w, k, inv0, inv1, a);
-    atomicAdd(&nbar[sd.node_off + folded_node<ND>(g, w.o[0] + a[0], w.o[1] + a[1], w.o[2] + a[2])],
-              (float)((double)iv * from_fix));
+    int x[3];
+    window_node<ND>(g, w, wk.a, nofold, x);
+    atomicAdd(&nbar[sd.node_off + node_index<ND>(g, x[0], x[1], x[2])], (float)((double)iv * from_fix));
   }
   if (e_all) atomicOr(err, e_all);
   double thd[5] = {thf[0], thf[1], thf[2], thf[3], thf[4]};
