@@ -235,6 +235,16 @@ int pic_step(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, pic_diag_t *dia
  * rejected too. */
 int pic_set_tiling(pic_ctx_t *ctx, int32_t tile, int32_t halo, int32_t chunk, int32_t sort_every);
 
+/* pic_set_tiling with tiles that are shorter along the last axis (y in 2D, z
+ * in 3D): tile cells along every other axis, tile_last cells along the last,
+ * a power of two from the smallest tile edge (2D 8, 3D 4) up to tile.  A
+ * flatter 3D tile has a smaller window in LDS, so more blocks share a CU.
+ * pic_set_tiling(ctx, t, ...) is pic_set_tile_shape(ctx, t, t, ...).  Same
+ * checks and errors as pic_set_tiling; on an error the previous tiling is
+ * kept. */
+int pic_set_tile_shape(pic_ctx_t *ctx, int32_t tile, int32_t tile_last, int32_t halo, int32_t chunk,
+                       int32_t sort_every);
+
 /* 1: make pic_step use the untiled kernels (separate deposit, grid pass and
  * gather+force+push launches per step); 0: the tiled fused step (default). */
 int pic_set_path(pic_ctx_t *ctx, int32_t untiled);
@@ -294,16 +304,23 @@ int pic_init_batch(pic_ctx_t **out, const pic_grid_t *grids, int32_t nslab, cons
 int pic_step_batch(pic_ctx_t *ctx, pic_particles_t *parts, int32_t nsteps, pic_diag_t *diag,
                    int32_t diag_every);
 
-/* Current tiling (any output pointer may be NULL). */
+/* Current tiling (any output pointer may be NULL); tile is the edge along
+ * every axis but the last. */
 int pic_get_tiling(pic_ctx_t *ctx, int32_t *tile, int32_t *halo, int32_t *chunk, int32_t *sort_every);
+
+/* Current tile edges: along every axis but the last, and along the last
+ * (either pointer may be NULL). */
+int pic_get_tile_shape(pic_ctx_t *ctx, int32_t *tile, int32_t *tile_last);
 
 /* 1 (default): replay blocks of 6 plain steps (no diagnostics, no re-binning
  * decision) from captured HIP graphs; 0: launch every step.  Graphs are only
  * captured on a context bound to a created stream (never the NULL stream). */
 int pic_set_graph(pic_ctx_t *ctx, int32_t on);
 
-/* Autotuner: probes tile edge x chunk candidates (tile 8, 16, 32 in 2D and
- * 4, 8 in 3D; chunk 512 to 16384; halo 2 in 2D, 1 in 3D; re-binning policy
+/* Autotuner: probes tile shape x chunk candidates (square tiles of 8, 16, 32
+ * cells in 2D; 4^3, 8^3 and 8 x 8 x 4 cells in 3D; chunk 512 to 16384, plus
+ * chunks whose work items fill whole rounds of the persistent grid; halo 2 in
+ * 2D, 1 in 3D; re-binning policy
  * unchanged) on the caller's particles for probe_steps steps each, launched
  * step by step (no graph capture inside a probe), timed with events, and
  * keeps the fastest tiling; among the tilings within 1 % of the fastest it
@@ -318,6 +335,7 @@ typedef struct pic_tuning {
   int32_t tile, halo, chunk;
   int32_t candidates;   /* tilings that were timed */
   double ms_per_step;   /* the kept tiling's probe, ms per step */
+  int32_t tile_last;    /* the kept tile edge along the last axis */
 } pic_tuning_t;
 int pic_autotune(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t probe_steps, pic_tuning_t *out);
 

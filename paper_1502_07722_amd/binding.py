@@ -48,7 +48,7 @@ PHASES = ("deposit", "grid", "force_push", "sort", "diag", "import_export", "unu
 
 class pic_tuning_t(C.Structure):
     _fields_ = [("tile", C.c_int32), ("halo", C.c_int32), ("chunk", C.c_int32), ("candidates", C.c_int32),
-                ("ms_per_step", C.c_double)]
+                ("ms_per_step", C.c_double), ("tile_last", C.c_int32)]
 
 
 class pic_timing_t(C.Structure):
@@ -92,6 +92,8 @@ lib.pic_step.argtypes = [_vp, _P(pic_particles_t), C.c_int32, _P(pic_diag_t), C.
 lib.pic_set_timing.argtypes = [_vp, C.c_int32]
 lib.pic_set_tiling.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
 lib.pic_get_tiling.argtypes = [_vp, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32), _P(C.c_int32)]
+lib.pic_set_tile_shape.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+lib.pic_get_tile_shape.argtypes = [_vp, _P(C.c_int32), _P(C.c_int32)]
 lib.pic_set_graph.argtypes = [_vp, C.c_int32]
 lib.pic_autotune.argtypes = [_vp, _P(pic_particles_t), C.c_int32, _P(pic_tuning_t)]
 lib.pic_workspace_bytes_batch.restype = C.c_size_t
@@ -333,14 +335,23 @@ class Context:
         self._check(lib.pic_get_tiling(self.ctx, *[C.byref(x) for x in v]), "pic_get_tiling")
         return tuple(x.value for x in v)
 
+    def pic_set_tile_shape(self, tile: int, tile_last: int, halo: int, chunk: int, sort_every: int):
+        self._check(lib.pic_set_tile_shape(self.ctx, tile, tile_last, halo, chunk, sort_every),
+                    "pic_set_tile_shape")
+
+    def pic_get_tile_shape(self):
+        v = [C.c_int32() for _ in range(2)]
+        self._check(lib.pic_get_tile_shape(self.ctx, *[C.byref(x) for x in v]), "pic_get_tile_shape")
+        return tuple(x.value for x in v)
+
     def pic_autotune(self, parts, probe_steps: int = 10):
         """parts: one DeviceParticles (single slab) or a list (batch)."""
         plist = parts if isinstance(parts, (list, tuple)) else [parts]
         arr = (pic_particles_t * len(plist))(*[p.struct() for p in plist])
         t = pic_tuning_t()
         self._check(lib.pic_autotune(self.ctx, arr, int(probe_steps), C.byref(t)), "pic_autotune")
-        return {"tile": t.tile, "halo": t.halo, "chunk": t.chunk, "candidates": t.candidates,
-                "ms_per_step": t.ms_per_step}
+        return {"tile": t.tile, "tile_last": t.tile_last, "halo": t.halo, "chunk": t.chunk,
+                "candidates": t.candidates, "ms_per_step": t.ms_per_step}
 
     def pic_set_graph(self, on: bool):
         self._check(lib.pic_set_graph(self.ctx, 1 if on else 0), "pic_set_graph")

@@ -307,7 +307,7 @@ struct pic_ctx {
   bool force_untiled = false;
   // tiled path
   bool tiled = false;
-  int lt = 4, halo = 2, chunk = 8192, sort_every = -1;
+  int lt = 4, ltl = 4, halo = 2, chunk = 8192, sort_every = -1;  // ltl: tile edge exponent, last axis
   std::vector<SlabDesc> sd;  // host copy of the slab table
   SlabDesc *sd_dev = nullptr;
   int *part_offs_dev = nullptr, *tile_offs_dev = nullptr;
@@ -438,16 +438,19 @@ static void drop_graphs(pic_ctx_t *c) {
   c->graph_key.clear();
 }
 
-// Apply a tiling to every slab (tile edge 2^lt cells, halo, chunk, re-binning
-// period) and upload the slab table.
-static int apply_tiling(pic_ctx_t *c, int lt, int halo, int chunk, int sort_every) {
+// Apply a tiling to every slab (tiles of 2^lt cells along every axis but the
+// last and 2^ltl along the last, halo, chunk, re-binning period) and upload
+// the slab table.
+static int apply_tiling(pic_ctx_t *c, int lt, int ltl, int halo, int chunk, int sort_every) {
   const int nd = c->ndim;
   if (lt < min_tile_log2(nd) || lt > max_tile_log2(nd)) return fail(c, PIC_EINVAL, "tile edge out of range");
+  if (ltl < min_tile_log2(nd) || ltl > lt)
+    return fail(c, PIC_EINVAL, "last-axis tile edge out of range (smallest tile edge .. tile)");
   if (halo < 1 || halo > 4) return fail(c, PIC_EINVAL, "halo must be 1..4 cells");
   if (chunk < kMinChunk || chunk > kMaxChunk) return fail(c, PIC_EINVAL, "chunk out of range");
   if (sort_every < -1) return fail(c, PIC_EINVAL, "sort_every must be >= -1");
   TileGeo T{};
-  for (int d = 0; d < 3; ++d) T.lt[d] = d < nd ? lt : 0;
+  for (int d = 0; d < 3; ++d) T.lt[d] = d < nd - 1 ? lt : (d == nd - 1 ? ltl : 0);
   T.H = halo;
   T.chunk = chunk;
   T.pshift[0] = 0;
@@ -462,14 +465,14 @@ static int apply_tiling(pic_ctx_t *c, int lt, int halo, int chunk, int sort_ever
   for (int k = 0; k < c->nslab; ++k) {
     const pic_grid_t &g = c->grids[k];
     for (int d = 0; d < nd; ++d)  // periodic axes must hold a whole window (single-wrap window coordinates)
-      if (!g.bc[d] && g.n[d] < (1 << lt) + 2 * halo + 3)
+      if (!g.bc[d] && g.n[d] < (1 << T.lt[d]) + 2 * halo + 3)
         return fail(c, PIC_EINVAL, "a periodic axis is shorter than the tile window");
     SlabDesc &s = sd[k];
     s.g = make_geo(g, c->pot, c->dt, c->sizes[k]);
     s.tg = T;
     s.tg.ntiles = 1;
     for (int d = 0; d < 3; ++d) {
-      s.tg.tn[d] = d < nd ? (g.n[d] + (1 << lt) - 1) >> lt : 1;
+      s.tg.tn[d] = d < nd ? (g.n[d] + (1 << T.lt[d]) - 1) >> T.lt[d] : 1;
       s.tg.ntiles *= s.tg.tn[d];
     }
     s.node_off = nodes;
@@ -483,6 +486,7 @@ static int apply_tiling(pic_ctx_t *c, int lt, int halo, int chunk, int sort_ever
   c->ntiles = tiles;
   c->nnodes = nodes;
   c->lt = lt;
+  c->ltl = ltl;
   c->halo = halo;
   c->chunk = chunk;
   c->sort_every = sort_every;
@@ -612,10 +616,10 @@ static int init_common(pic_ctx_t **out, const pic_grid_t *grids_in, int nslab, c
     // default tiling: 16^2 (2D) / 8^3 (3D) tiles, smaller where a periodic axis is short
     int rc = PIC_EINVAL;
     if (c->ndim == 2) {
-      for (int lt = 4; lt >= 3 && rc && rc != PIC_EHIP; --lt) rc = apply_tiling(c, lt, 2, 8192, -1);
-      if (rc && rc != PIC_EHIP) rc = apply_tiling(c, 3, 1, 8192, -1);
+      for (int lt = 4; lt >= 3 && rc && rc != PIC_EHIP; --lt) rc = apply_tiling(c, lt, lt, 2, 8192, -1);
+      if (rc && rc != PIC_EHIP) rc = apply_tiling(c, 3, 3, 1, 8192, -1);
     } else {
-      for (int lt = 3; lt >= 2 && rc && rc != PIC_EHIP; --lt) rc = apply_tiling(c, lt, 1, 4096, -1);
+      for (int lt = 3; lt >= 2 && rc && rc != PIC_EHIP; --lt) rc = apply_tiling(c, lt, lt, 1, 4096, -1);
     }
     if (rc == PIC_EHIP) {
       delete c;
@@ -743,7 +747,7 @@ void enqueue_step(pic_ctx_t *c, const Batch &b, const Store &st, int s, bool dia
 // Graph of kGraphSteps plain steps starting at a step index that is a
 // multiple of kGraphSteps (node buffers cycle with period 3, counters 2).
 int graph_for(pic_ctx_t *c, const Batch &b, int cur, hipGraphExec_t *out) {
-  std::vector<int64_t> key = {b.nparts, c->lt, c->halo, c->chunk, c->grid_blocks, c->nslab};
+  std::vector<int64_t> key = {b.nparts, c->lt, c->ltl, c->halo, c->chunk, c->grid_blocks, c->nslab};
   for (const SlabDesc &s : c->sd) {
     key.push_back(s.part_off);
     key.push_back(s.part_n);
@@ -983,20 +987,30 @@ int pic_get_timing(pic_ctx_t *ctx, pic_timing_t *out) {
   return PIC_OK;
 }
 
-int pic_set_tiling(pic_ctx_t *ctx, int32_t tile, int32_t halo, int32_t chunk, int32_t sort_every) {
+static int edge_log2(int32_t e) {
+  int l = 0;
+  while (l < 30 && (1 << l) < e) ++l;
+  return e >= 1 && (1 << l) == e ? l : -1;
+}
+
+int pic_set_tile_shape(pic_ctx_t *ctx, int32_t tile, int32_t tile_last, int32_t halo, int32_t chunk,
+                       int32_t sort_every) {
   if (!ctx) return PIC_EINVAL;
   if (!ctx->tiled) return fail(ctx, PIC_EINVAL, "this grid uses the untiled path");
-  int lt = 0;
-  while ((1 << lt) < tile) ++lt;
-  if (tile < 1 || (1 << lt) != tile) return fail(ctx, PIC_EINVAL, "tile edge must be a power of two");
-  const int old_lt = ctx->lt, old_h = ctx->halo, old_c = ctx->chunk, old_s = ctx->sort_every;
-  int rc = apply_tiling(ctx, lt, halo, chunk, sort_every);
+  const int lt = edge_log2(tile), ltl = edge_log2(tile_last);
+  if (lt < 0 || ltl < 0) return fail(ctx, PIC_EINVAL, "tile edges must be powers of two");
+  const int old_lt = ctx->lt, old_l = ctx->ltl, old_h = ctx->halo, old_c = ctx->chunk, old_s = ctx->sort_every;
+  int rc = apply_tiling(ctx, lt, ltl, halo, chunk, sort_every);
   if (rc && rc != PIC_EHIP) {
     std::string why = ctx->last_error;
-    apply_tiling(ctx, old_lt, old_h, old_c, old_s);  // keep the previous (valid) tiling
+    apply_tiling(ctx, old_lt, old_l, old_h, old_c, old_s);  // keep the previous (valid) tiling
     ctx->last_error = why;
   }
   return rc;
+}
+
+int pic_set_tiling(pic_ctx_t *ctx, int32_t tile, int32_t halo, int32_t chunk, int32_t sort_every) {
+  return pic_set_tile_shape(ctx, tile, tile, halo, chunk, sort_every);
 }
 
 int pic_get_tiling(pic_ctx_t *ctx, int32_t *tile, int32_t *halo, int32_t *chunk, int32_t *sort_every) {
@@ -1006,6 +1020,14 @@ int pic_get_tiling(pic_ctx_t *ctx, int32_t *tile, int32_t *halo, int32_t *chunk,
   if (halo) *halo = ctx->halo;
   if (chunk) *chunk = ctx->chunk;
   if (sort_every) *sort_every = ctx->sort_every;
+  return PIC_OK;
+}
+
+int pic_get_tile_shape(pic_ctx_t *ctx, int32_t *tile, int32_t *tile_last) {
+  if (!ctx) return PIC_EINVAL;
+  if (!ctx->tiled) return fail(ctx, PIC_EINVAL, "this grid uses the untiled path");
+  if (tile) *tile = 1 << ctx->lt;
+  if (tile_last) *tile_last = 1 << ctx->ltl;
   return PIC_OK;
 }
 
@@ -1240,7 +1262,7 @@ static int recorded_ok(pic_ctx_t *c, const pic_particles_t *p, int nsteps, int e
 }
 
 static std::vector<int64_t> rec_key_of(const pic_ctx_t *c, int64_t n, int nsteps, int every, const void *rec) {
-  return {n, nsteps, every, c->lt, c->halo, c->chunk, (int64_t)reinterpret_cast<uintptr_t>(rec)};
+  return {n, nsteps, every, c->lt, c->ltl, c->halo, c->chunk, (int64_t)reinterpret_cast<uintptr_t>(rec)};
 }
 
 size_t pic_record_bytes(pic_ctx_t *ctx, int32_t nsteps, int32_t every) {
@@ -1483,36 +1505,45 @@ int pic_autotune(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t probe_ste
   if (rc) return rc;
   const int nd = ctx->ndim;
   const int halo = nd == 2 ? 2 : 1;
-  const int lts[3] = {nd == 2 ? 3 : 2, nd == 2 ? 4 : 3, nd == 2 ? 5 : 3};
+  // tile shapes (edge exponents: all axes but the last, last axis): square
+  // 8, 16, 32 in 2D; 4^3, 8^3 and 8 x 8 x 4 in 3D (a flatter window that
+  // leaves LDS for more blocks per CU)
+  struct Shape {
+    int lt, ltl;
+  };
+  const Shape shapes2[3] = {{3, 3}, {4, 4}, {5, 5}}, shapes3[3] = {{2, 2}, {3, 3}, {3, 2}};
+  const Shape *shapes = nd == 2 ? shapes2 : shapes3;
   const int chunks[6] = {512, 1024, 2048, 4096, 8192, 16384};
-  const int old_lt = ctx->lt, old_h = ctx->halo, old_c = ctx->chunk, old_s = ctx->sort_every;
+  const int old_lt = ctx->lt, old_l = ctx->ltl, old_h = ctx->halo, old_c = ctx->chunk, old_s = ctx->sort_every;
   const bool old_timing = ctx->timing, old_graph = ctx->use_graph;
   ctx->timing = false;
   ctx->use_graph = false;  // a graph capture per candidate would land inside its timed probe
   float best = 1e30f;
-  int best_lt = old_lt, best_c = old_c, tried = 0;
+  int best_c = old_c, tried = 0;
+  Shape best_s{old_lt, old_l};
   struct Probe {
     float ms;
-    int lt, c;
+    Shape sh;
+    int c;
   };
   std::vector<Probe> probes;
   pic_particles_t *pp = const_cast<pic_particles_t *>(parts);
   for (int i = 0; i < 3; ++i) {
-    if (i > 0 && lts[i] == lts[i - 1]) continue;
+    const Shape sh = shapes[i];
     std::vector<int> cand(chunks, chunks + 6);
     for (size_t ci = 0; ci < cand.size(); ++ci) {
       const int c = cand[ci];
-      if (apply_tiling(ctx, lts[i], halo, c, old_s)) continue;  // does not fit this grid
+      if (apply_tiling(ctx, sh.lt, sh.ltl, halo, c, old_s)) continue;  // does not fit this grid
       DiagSink ds{ctx, nullptr, 0};
       float ms = 0.f;
       // the store is scratch: the caller's arrays are read, never written
       rc = step_tiled(ctx, pp, probe_steps, ds, 1, false, &ms);
       if (rc) break;
       ++tried;
-      probes.push_back({ms, lts[i], c});
+      probes.push_back({ms, sh, c});
       if (ms < best) {
         best = ms;
-        best_lt = lts[i];
+        best_s = sh;
         best_c = c;
       }
       if (ci == 0) {
@@ -1536,24 +1567,26 @@ int pic_autotune(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t probe_ste
     if (q.ms > best * 1.01f) continue;
     if (q.c > best_c || (q.c == best_c && q.ms < sel)) {
       best_c = q.c;
-      best_lt = q.lt;
+      best_s = q.sh;
       sel = q.ms;
     }
   }
   ctx->timing = old_timing;
   ctx->use_graph = old_graph;
   ctx->last_nodes = nullptr;
-  int rc2 = apply_tiling(ctx, rc || !tried ? old_lt : best_lt, rc || !tried ? old_h : halo,
-                         rc || !tried ? old_c : best_c, old_s);
+  const bool keep_old = rc || !tried;
+  int rc2 = apply_tiling(ctx, keep_old ? old_lt : best_s.lt, keep_old ? old_l : best_s.ltl, keep_old ? old_h : halo,
+                         keep_old ? old_c : best_c, old_s);
   if (rc) return rc;
   if (rc2) return rc2;
   if (!tried) return fail(ctx, PIC_EINVAL, "no tiling fits this grid");
   if (out) {
-    out->tile = 1 << best_lt;
+    out->tile = 1 << best_s.lt;
     out->halo = halo;
     out->chunk = best_c;
     out->candidates = tried;
     out->ms_per_step = sel / probe_steps;
+    out->tile_last = 1 << best_s.ltl;
   }
   return read_device_error(ctx);
 }

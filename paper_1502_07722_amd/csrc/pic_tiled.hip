@@ -1193,6 +1193,23 @@ __device__ __forceinline__ void load_adjoint_state(const StoreView &sv, const fl
   }
 }
 
+// A particle's state and cotangents, loaded from a slot inside the store
+// (lanes past the item's end read its last slot and ignore it).
+struct AdjLoad {
+  PState q;
+  float ln[3], lv[3];
+};
+template <int ND>
+__device__ __forceinline__ void load_adjoint_any(const StoreView &sv, const float *__restrict__ lx,
+                                                 const float *__restrict__ lv, int cap, int p, AdjLoad &a) {
+  load_state_any<ND, true>(sv, p, a.q);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    a.ln[d] = d < ND ? lx[d * cap + p] : 0.0f;
+    a.lv[d] = lv[d * cap + p];
+  }
+}
+
 // Node cotangents accumulate in LDS as int64 fixed point: float atomic adds
 // on LDS are more than an order of magnitude slower than integer ones on this
 // chip.  The scale is a power of two set from the largest single contribution
@@ -1397,7 +1414,7 @@ __device__ __forceinline__ void block_reduce_add(double v[NF], double *__restric
 }
 
 template <int ND, bool MAXONLY, bool GEN>
-__global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, const Item *__restrict__ items,
+__global__ void __launch_bounds__(256, 4) k_adjoint_tiled(Pot P, Batch b, Store s, const Item *__restrict__ items,
                                                        const int *__restrict__ num_items,
                                                        const long long *__restrict__ Ncur,
                                                        const float *__restrict__ nbar_next, float *__restrict__ lx,
@@ -1446,12 +1463,17 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
   const StoreView sv = view_of(s, s);
   uint32_t e_all = 0;
   float thf[5] = {0.f, 0.f, 0.f, 0.f, 0.f};  // this thread's parameter terms (chunk / 256 particles at most)
+  // loads for the next round are issued before the current round is computed
+  const int last = it.end - 1;
+  AdjLoad cur, nxt;
+  load_adjoint_any<ND>(sv, lx, lv, cap, min(it.start + (int)threadIdx.x, last), cur);
   for (int base = it.start; base < it.end; base += blockDim.x) {
     const int p = base + (int)threadIdx.x;
     const bool live = p < it.end;
-    PState q;
-    float ln[3], lvv[3];
-    load_adjoint_state<ND>(sv, lx, lv, cap, p, live, q, ln, lvv);
+    load_adjoint_any<ND>(sv, lx, lv, cap, min(p + (int)blockDim.x, last), nxt);
+    const PState q = cur.q;
+    float ln[3] = {cur.ln[0], cur.ln[1], cur.ln[2]}, lvv[3] = {cur.lv[0], cur.lv[1], cur.lv[2]};
+    cur = nxt;
     int idx[3], l[3];
     unpack_cell<ND>(tg, q.pc, idx);
     const bool inside = live && in_window<ND>(g, w, idx, 1, 3, l);
@@ -1470,17 +1492,26 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(Pot P, Batch b, Store s, 
       }
       float a3[K3];
       block_cotangents<ND>(g, l, B, q.f, t, an, aG, a3);
+      float pmax = 0.0f;  // this particle's largest contribution
 #pragma unroll
-      for (int a = 0; a < K3; ++a) vmax = fmaxf(vmax, fabsf(a3[a]));
+      for (int a = 0; a < K3; ++a) pmax = fmaxf(pmax, fabsf(a3[a]));
+      vmax = fmaxf(vmax, pmax);
       if (!MAXONLY) {
+        const int nb = win_node<ND>(w, B[0], B[1], B[2]);
+        if (pmax < lim) {  // the common case: every contribution in fixed point, no branch per node
 #pragma unroll
-        for (int a = 0; a < K3; ++a) {
-          if (a3[a] == 0.0f) continue;
-          const int ax = B[0] + a % 3, ay = B[1] + (a / 3) % 3, az = ND == 3 ? B[2] + a / 9 : 0;
-          if (fabsf(a3[a]) < lim) {
-            atomicAdd(&acc[win_node<ND>(w, ax, ay, az)], (unsigned long long)fix64(a3[a] * to_fix));
-          } else {
-            atomicAdd(&nbar[sd.node_off + folded_node<ND>(g, w.o[0] + ax, w.o[1] + ay, w.o[2] + az)], a3[a]);
+          for (int a = 0; a < K3; ++a)
+            atomicAdd(&acc[nb + win_node<ND>(w, a % 3, (a / 3) % 3, ND == 3 ? a / 9 : 0)],
+                      (unsigned long long)fix64(a3[a] * to_fix));
+        } else {
+#pragma unroll
+          for (int a = 0; a < K3; ++a) {
+            const int ax = B[0] + a % 3, ay = B[1] + (a / 3) % 3, az = ND == 3 ? B[2] + a / 9 : 0;
+            if (fabsf(a3[a]) < lim) {
+              atomicAdd(&acc[win_node<ND>(w, ax, ay, az)], (unsigned long long)fix64(a3[a] * to_fix));
+            } else {
+              atomicAdd(&nbar[sd.node_off + folded_node<ND>(g, w.o[0] + ax, w.o[1] + ay, w.o[2] + az)], a3[a]);
+            }
           }
         }
       }

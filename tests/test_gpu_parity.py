@@ -250,8 +250,12 @@ def test_step_is_bit_identical_to_separate_calls():
 
 
 def _run_config(grid, parts, pot, nsteps, tiling=None, untiled=False, diag_every=0):
+    """tiling: (tile, halo, chunk, sort_every) or (tile, tile_last, halo,
+    chunk, sort_every)."""
     ctx = B.Context(grid, pot, DT, parts.n)
-    if tiling:
+    if tiling and len(tiling) == 5:
+        ctx.pic_set_tile_shape(*tiling)
+    elif tiling:
         ctx.pic_set_tiling(*tiling)
     ctx.pic_set_path(untiled)
     dp = B.DeviceParticles.from_host(parts)
@@ -270,10 +274,10 @@ def test_tiled_step_is_bit_identical_to_untiled_and_to_any_tiling(ndim):
     pot = W.Potential(c_att=0.27)
     if ndim == 2:
         grid, parts = W.make_slab(2, (80, 72), 36, 24, H, 51, fluence_Jcm2=4.0, R_cells=20)
-        tilings = [(16, 2, 8192, 32), (8, 1, 1024, 0), (32, 3, 4096, 7)]
+        tilings = [(16, 2, 8192, 32), (8, 1, 1024, 0), (32, 3, 4096, 7), (32, 8, 2, 2048, 9)]
     else:
         grid, parts = W.make_slab(3, (20, 18, 24), 12, 8, H, 52, fluence_Jcm2=4.0, R_cells=10)
-        tilings = [(8, 1, 4096, 16), (4, 1, 1024, 0), (4, 2, 2048, 3)]
+        tilings = [(8, 1, 4096, 16), (4, 1, 1024, 0), (4, 2, 2048, 3), (8, 4, 1, 1024, 0), (8, 4, 2, 4096, 5)]
     nsteps = 60
     banner(f"tiled vs untiled {ndim}D N={parts.n}")
     ref, _, _, _ = _run_config(grid, parts, pot, nsteps, untiled=True)
@@ -398,6 +402,24 @@ def test_device_errors_are_reported():
     ctx.pic_step(B.DeviceParticles.from_host(parts), 2)
 
 
+def test_tile_shape_checks_keep_the_previous_tiling():
+    grid = W.Grid(ndim=3, n=(24, 24, 24), h=(H, H, H), bc=(0, 0, 1))
+    parts = random_particles(grid, 2000, 7, edge=False)
+    ctx = B.Context(grid, W.Potential(), DT, parts.n)
+    ctx.pic_set_tile_shape(8, 4, 1, 2048, -1)
+    assert ctx.pic_get_tile_shape() == (8, 4) and ctx.pic_get_tiling()[:3] == (8, 1, 2048)
+    for bad in ((8, 16, 1, 2048, -1),   # longer along the last axis
+                (8, 2, 1, 2048, -1),    # below the smallest 3D edge
+                (8, 6, 1, 2048, -1),    # not a power of two
+                (16, 8, 1, 2048, -1)):  # window beyond LDS / the tile range
+        with pytest.raises(B.PicError) as e:
+            ctx.pic_set_tile_shape(*bad)
+        assert e.value.code == B.PIC_EINVAL, bad
+        assert ctx.pic_get_tile_shape() == (8, 4) and ctx.pic_get_tiling()[:3] == (8, 1, 2048)
+    ctx.pic_set_tiling(4, 1, 1024, 0)
+    assert ctx.pic_get_tile_shape() == (4, 4)
+
+
 def test_binding_refuses_undersized_buffers():
     grid = W.Grid(ndim=2, n=(16, 16), h=(H, H), bc=(0, 1))
     parts = random_particles(grid, 100, 6, edge=False)
@@ -484,6 +506,7 @@ def test_autotune_reads_only_and_keeps_results_identical():
         assert np.array_equal(x, y)  # probes never write the caller's arrays
     assert tuning["candidates"] >= 4 and tuning["tile"] in (8, 16, 32)
     assert ctx.pic_get_tiling()[:3] == (tuning["tile"], tuning["halo"], tuning["chunk"])
+    assert ctx.pic_get_tile_shape() == (tuning["tile"], tuning["tile_last"])
     ctx.pic_step(dp, 20)
     ref_ctx = B.Context(grid, pot, DT, parts.n)
     ref = B.DeviceParticles.from_host(parts)

@@ -79,20 +79,23 @@ def test_recorded_forward_equals_pic_step(B, nd):
         assert torch.equal(a.cell, x.cell) and torch.equal(a.off, x.off) and torch.equal(a.vel, x.vel)
 
 
-@pytest.mark.parametrize("nd,rebin,family", [(2, False, "lj"), (3, False, "lj"), (2, True, "lj"), (3, True, "lj"),
-                                             (2, False, "morse"), (3, True, "morse"), (2, True, "hcp"),
-                                             (3, False, "hcp")])
-def test_recorded_sweep_matches_per_step_chain(B, nd, rebin, family):
+@pytest.mark.parametrize("nd,rebin,family,flat", [(2, False, "lj", False), (3, False, "lj", False),
+                                                  (2, True, "lj", False), (3, True, "lj", False),
+                                                  (2, False, "morse", False), (3, True, "morse", False),
+                                                  (2, True, "hcp", False), (3, False, "hcp", False),
+                                                  (3, False, "lj", True), (3, True, "hcp", True)])
+def test_recorded_sweep_matches_per_step_chain(B, nd, rebin, family, flat):
     """rebin: re-binning at every checkpoint (each segment has its own order,
     the cotangents are permuted between segments).  family: the pair
-    potential (Morse adds the alpha slot of dtheta)."""
+    potential (Morse adds the alpha slot of dtheta).  flat: tiles half as
+    long along the last axis (a flatter reverse-step window)."""
     grid, parts, dt = _case(nd)
     pot = {"lj": W.Potential(c_att=0.27), "morse": W.morse_cu(c_att=0.43), "hcp": W.hcp(c_att=0.2)}[family]
     nsteps, every = 30, 8  # a ragged last segment
     ctx = B.Context(grid, pot, dt, parts.n)
-    if rebin:
-        t, h, c, _ = ctx.pic_get_tiling()
-        ctx.pic_set_tiling(t, h, c, 5)
+    t, h, c, s = ctx.pic_get_tiling()
+    ctx.pic_set_tile_shape(t, t // 2 if flat else t, h, c, 5 if rebin else s)
+    assert ctx.pic_get_tile_shape() == (t, t // 2 if flat else t)
     dp = B.DeviceParticles.from_host(parts)
     ctx.start_leapfrog(dp)
     start = dp.clone()
