@@ -326,10 +326,12 @@ __device__ __forceinline__ void pair_force(const Pot &P, float nh, const float G
 // ---------------------------------------------------------------------------
 // INTERIOR: the caller guarantees the particle is at least one cell away from
 // every wall and from the periodic seam, so no mirror or wrap can occur; the
-// carry arithmetic is the same, so both variants give the same bits.
+// carry arithmetic is the same, so both variants give the same bits.  edges
+// (uniform across the wavefront): bit d clear = the same guarantee along axis
+// d alone, whose wall and wrap code is then skipped.
 template <int ND, bool INTERIOR = false>
 __device__ __forceinline__ uint32_t push_particle(const Geo &g, const Pot &P, const float F[3],
-                                                  int idx[3], float f[3], float v[3]) {
+                                                  int idx[3], float f[3], float v[3], uint32_t edges = 7u) {
   uint32_t err = 0;
 #pragma unroll
   for (int d = 0; d < ND; ++d) v[d] = __builtin_fmaf(F[d], P.gv, v[d]);
@@ -349,7 +351,7 @@ __device__ __forceinline__ uint32_t push_particle(const Geo &g, const Pot &P, co
     xc = tie ? 0.0f : xc;
     ic = tie ? idx[d] : ic;
     float xn = xc;
-    if (!INTERIOR) {
+    if (!INTERIOR && ((edges >> d) & 1u)) {
       const int n = g.n[d];
       const bool up = x >= 1.0f, down = x < 0.0f;
       const bool wall_lo = g.bc[d] && idx[d] == 0 && down;

@@ -201,17 +201,30 @@ __device__ __forceinline__ void gather_nodes_global(const Geo &g, const long lon
   float t[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int e = 0; e < ND; ++e) centre_stencil(idx[e], f[e], c0[e], t[e]);
-  int ax[3][3];
+  // a block away from the domain's edges needs no fold and no wall factor
+  bool plain = true;
 #pragma unroll
-  for (int e = 0; e < 3; ++e)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) ax[e][j] = e < ND ? fold_node(g, e, c0[e] + j) : 0;
+  for (int e = 0; e < ND; ++e) plain = plain && c0[e] >= 1 && c0[e] + 2 < g.n[e];
   constexpr int K3 = ND == 2 ? 9 : 27;
   float d3[K3];
+  if (plain) {
+    const int b = node_index<ND>(g, c0[0], c0[1], c0[2]);
 #pragma unroll
-  for (int a = 0; a < K3; ++a) {
-    const int x = ax[0][a % 3], y = ax[1][(a / 3) % 3], z = ND == 3 ? ax[2][a / 9] : 0;
-    d3[a] = node_density(g, N[node_index<ND>(g, x, y, z)], x, y, z);
+    for (int a = 0; a < K3; ++a) {
+      const int o = a % 3 + g.nn[0] * ((a / 3) % 3 + (ND == 3 ? g.nn[1] * (a / 9) : 0));
+      d3[a] = wsum_float(N[b + o]) * g.kappa;
+    }
+  } else {
+    int ax[3][3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) ax[e][j] = e < ND ? fold_node(g, e, c0[e] + j) : 0;
+#pragma unroll
+    for (int a = 0; a < K3; ++a) {
+      const int x = ax[0][a % 3], y = ax[1][(a / 3) % 3], z = ND == 3 ? ax[2][a / 9] : 0;
+      d3[a] = node_density(g, N[node_index<ND>(g, x, y, z)], x, y, z);
+    }
   }
   // all-ones masks of the offsets: the corners are picked by bitwise blends of
   // values, so the block stays in registers (no indexing by a run-time offset)
@@ -399,16 +412,30 @@ __device__ __forceinline__ void clear_share(long long *__restrict__ Z, int nnode
 }
 
 // Window coordinates of a cell; returns true if inside [lo, hi] on every axis.
+// edges: bit d clear = the window does not reach the periodic seam along d,
+// where a plain difference is then exact.
 template <int ND>
 __device__ __forceinline__ bool in_window(const Geo &g, const Window &w, const int idx[3], int lo, int hi_off,
-                                          int l[3]) {
+                                          int l[3], uint32_t edges = 7u) {
   bool ok = true;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    l[d] = window_coord(g, d, idx[d], w.o[d], lo);
+    l[d] = ((edges >> d) & 1u) ? window_coord(g, d, idx[d], w.o[d], lo) : idx[d] - w.o[d];
     ok = ok && l[d] >= lo && l[d] <= w.wn[d] - hi_off;
   }
   return ok;
+}
+
+// Axes along which a tile window reaches a reflecting wall or the periodic
+// seam (bit d): a particle of the item loop stays a cell away from both along
+// the other axes, so it never mirrors or wraps there.
+template <int ND>
+__device__ __forceinline__ uint32_t window_edges(const Geo &g, const Window &w) {
+  uint32_t e = 0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+    if (!(w.o[d] >= 0 && w.o[d] + w.wn[d] <= g.n[d] + 1)) e |= 1u << d;
+  return e;
 }
 
 
@@ -499,7 +526,7 @@ template <int ND, bool DIAG, bool INTERIOR, bool OUT, bool GEN>
 __device__ __forceinline__ void advance_particle(const Geo &g, const Pot &P, const DiagC &dc, const TileGeo &tg,
                                                  const StoreView &sv, int p, int pc, int idx[3], float f[3],
                                                  float v[3], int W, float nh, const float Gp[3], uint32_t tq[8],
-                                                 uint32_t &err, double acc6[6]) {
+                                                 uint32_t &err, double acc6[6], uint32_t edges = 7u) {
   float Fh[3], bond = 0.0f;
   pair_force<ND, GEN>(P, nh, Gp, Fh, DIAG ? &bond : nullptr);
   float F[3] = {Fh[0] * P.beta, Fh[1] * P.beta, ND == 3 ? Fh[2] * P.beta : 0.0f};
@@ -516,7 +543,7 @@ __device__ __forceinline__ void advance_particle(const Geo &g, const Pot &P, con
     acc6[4] += wgt;
     acc6[5] += wgt * (double)bond * dc.D;
   }
-  err |= push_particle<ND, INTERIOR>(g, P, F, idx, f, v);
+  err |= push_particle<ND, INTERIOR>(g, P, F, idx, f, v, edges);
   const int pc2 = pack_cell<ND>(tg, idx);
   if (pc2 != pc || OUT) at(sv.pc_o, p) = pc2;
 #pragma unroll
@@ -925,8 +952,8 @@ __device__ __forceinline__ void wave_append(int *list, int *count, int value, bo
 // touches the periodic seam, so a plain difference is exact there.
 template <int ND, bool INTERIOR>
 __device__ __forceinline__ bool item_window(const Geo &g, const Window &w, const int idx[3], int lo, int hi_off,
-                                            int l[3]) {
-  if (!INTERIOR) return in_window<ND>(g, w, idx, lo, hi_off, l);
+                                            int l[3], uint32_t edges) {
+  if (!INTERIOR) return in_window<ND>(g, w, idx, lo, hi_off, l, edges);
   bool ok = true;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
@@ -945,7 +972,7 @@ __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC
                                          const StoreView &sv, const Item &it, const Window &w, const float *dens,
                                          const float *Gs, unsigned long long *acc,
                                          unsigned long long *__restrict__ Nnext, int *__restrict__ dlist,
-                                         int *ndrift, uint32_t &e_all, double acc6[6]) {
+                                         int *ndrift, uint32_t &e_all, double acc6[6], uint32_t edges) {
   PState cur, nxt;
   int p = it.start + (int)threadIdx.x;
   const int last = it.end - 1;
@@ -956,7 +983,7 @@ __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC
     const bool live = p < it.end;
     int idx[3], l[3];
     unpack_cell<ND>(tg, cur.pc, idx);
-    const bool inside = live && item_window<ND, INTERIOR>(g, w, idx, 1, 3, l);
+    const bool inside = live && item_window<ND, INTERIOR>(g, w, idx, 1, 3, l, edges);
     wave_append(dlist, ndrift, p, live && !inside);
     if (inside) {
       float cr[8];
@@ -983,9 +1010,9 @@ __device__ __forceinline__ void run_item(const Geo &g, const Pot &P, const DiagC
       for (int d = 0; d < ND; ++d) Gp[d] = interp<ND>(vv[d], t);
       uint32_t tq[8];
       advance_particle<ND, DIAG, INTERIOR, OUT, GEN>(g, P, dc, tg, sv, p, cur.pc, idx, cur.f, cur.v, cur.W, nh, Gp, tq,
-                                           e_all, acc6);
+                                                     e_all, acc6, edges);
       // a sub-cell move keeps the new cell inside the deposit window
-      if (item_window<ND, INTERIOR>(g, w, idx, 0, 2, l)) {
+      if (item_window<ND, INTERIOR>(g, w, idx, 0, 2, l, edges)) {
         const int db = win_node<ND>(w, l[0], l[1], l[2]);
 #pragma unroll
         for (int k = 0; k < (1 << ND); ++k) atomicAdd(&acc[db + node_corner<ND>(w, k)], (unsigned long long)tq[k]);
@@ -1064,16 +1091,17 @@ __global__ void __launch_bounds__(256, ND == 2 ? 7 : 4) k_step_tiled(Pot P, Diag
     unsigned long long *Nn = Nnext + sd.node_off;
     stage_window<ND>(g, w, Ncur + sd.node_off, dens, Gs, acc);  // ends with a barrier
     // interior windows: no wall and no periodic seam within reach of any
-    // particle the item loop handles
-    bool interior = true;
-#pragma unroll
-    for (int d = 0; d < ND; ++d) interior = interior && w.o[d] >= 0 && w.o[d] + w.wn[d] <= g.n[d] + 1;
+    // particle the item loop handles; otherwise only the axes in edges
+    // need the wall and wrap code
+    const uint32_t edges = __builtin_amdgcn_readfirstlane(window_edges<ND>(g, w));
     double acc6[6] = {0, 0, 0, 0, 0, 0};
     int *dlist = dr.list + it.start;  // slots [start, end) of the item
-    if (interior)
-      run_item<ND, DIAG, true, OUT, GEN>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dlist, &s_ndrift, e_all, acc6);
+    if (!edges)
+      run_item<ND, DIAG, true, OUT, GEN>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dlist, &s_ndrift, e_all, acc6,
+                                         edges);
     else
-      run_item<ND, DIAG, false, OUT, GEN>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dlist, &s_ndrift, e_all, acc6);
+      run_item<ND, DIAG, false, OUT, GEN>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dlist, &s_ndrift, e_all, acc6,
+                                          edges);
     __syncthreads();  // the window's sums and the item's drifter list are complete
     flush_window<ND>(g, w, acc, Nn);
     const int ndr = __builtin_amdgcn_readfirstlane(s_ndrift);
