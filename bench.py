@@ -203,7 +203,7 @@ def run_sweep(steps, warmup, log_fn=log):
         # stream: the gain from batching alone
         tctx = [B.Context(w.grid, pot, dt, w.parts.n, stream=stream) for w in wls]
         for c in tctx:
-            c.pic_set_tiling(tuning["tile"], tuning["halo"], tuning["chunk"], -1)
+            c.pic_set_tile_shape(tuning["tile"], tuning["tile_last"], tuning["halo"], tuning["chunk"], -1)
         tuned = [s.clone() for s in starts]
         for c, p in zip(tctx, tuned):
             c.pic_step(p, warmup)

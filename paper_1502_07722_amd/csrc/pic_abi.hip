@@ -726,13 +726,15 @@ Drift drift_of(pic_ctx_t *c, int s) {
                c->drift + 2 + ((s + 1) & 1)};
 }
 
+// Most work items of a binning of n particles: one per tile plus one per chunk.
+int64_t max_items_of(const pic_ctx_t *c, int64_t n) { return (int64_t)c->ntiles + (n + c->chunk - 1) / c->chunk; }
+
 // Persistent grid of the fused kernel for n particles: the full grid, or
-// fewer blocks when the step cannot have that many work items (at most one
-// per tile plus one per chunk of particles); extra blocks would only find the
-// queue empty, and launching them costs more than the step on a small grid.
+// fewer blocks when the step cannot have that many work items; extra blocks
+// would only find the queue empty, and launching them costs more than the
+// step on a small grid.
 int step_grid(const pic_ctx_t *c, int64_t n) {
-  const int64_t items = (int64_t)c->ntiles + (n + c->chunk - 1) / c->chunk;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(c->grid_blocks, items));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(c->grid_blocks, max_items_of(c, n)));
 }
 
 // The launch of one tiled step: one fused kernel (drifters included).
@@ -815,7 +817,7 @@ int step_tiled(pic_ctx_t *ctx, const pic_particles_t *parts, int32_t nsteps, Dia
   }
   if ((rc = check_launch(ctx, "binning"))) return rc;
   if ((rc = read_device_error(ctx))) return rc;
-  const int64_t max_items = (int64_t)ctx->ntiles + (n + ctx->chunk - 1) / ctx->chunk;
+  const int64_t max_items = max_items_of(ctx, n);
   launch_fill64(ctx->stream, ctx->n3[0], ctx->nnodes);
   launch_fill64(ctx->stream, ctx->n3[1], ctx->nnodes);
   launch_fill32(ctx->stream, ctx->drift, 4);
@@ -1297,7 +1299,7 @@ int pic_forward_record(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, int32
   if ((rc = check_launch(ctx, "binning"))) return rc;
   if ((rc = read_device_error(ctx))) return rc;
   int cur = 0;
-  const int64_t max_items = (int64_t)ctx->ntiles + (n + ctx->chunk - 1) / ctx->chunk;
+  const int64_t max_items = max_items_of(ctx, n);
   launch_fill64(ctx->stream, ctx->n3[0], ctx->nnodes);
   launch_fill64(ctx->stream, ctx->n3[1], ctx->nnodes);
   launch_fill32(ctx->stream, ctx->drift, 4);
@@ -1391,7 +1393,7 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
   ensure_grid_blocks(ctx);
   ctx->last_nodes = nullptr;
   drop_graphs(ctx);
-  const int64_t max_items = (int64_t)ctx->ntiles + (n + ctx->chunk - 1) / ctx->chunk;
+  const int64_t max_items = max_items_of(ctx, n);
   // checkpoint j's binning: a store whose wq / oidx are the record's, and its items
   auto ref_of = [&](int j) {
     Store S = ctx->st[0];

@@ -1063,7 +1063,7 @@ __global__ void __launch_bounds__(256, ND == 2 ? 7 : 4) k_step_tiled(Pot P, Diag
                                                     long long *__restrict__ Nclear, Drift dr,
                                                     double *__restrict__ partial, uint32_t *__restrict__ err) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_item, s_ndrift;
+  __shared__ int s_item[2], s_ndrift;
   clear_share(Nclear, b.nnodes);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *dr.count_next = 0;  // the next step's drifter count and work counter
@@ -1072,15 +1072,17 @@ __global__ void __launch_bounds__(256, ND == 2 ? 7 : 4) k_step_tiled(Pot P, Diag
   const int nit = *num_items;
   const StoreView sv = view_of<OUT>(s, o);
   uint32_t e_all = 0;
-  for (;;) {
-    if (threadIdx.x == 0) {
-      s_item = atomicAdd(dr.work, 1);
-      s_ndrift = 0;
-    }
-    __syncthreads();
-    const int bi = __builtin_amdgcn_readfirstlane(s_item);
-    if (bi >= nit) break;
-    const Item it = items[bi];
+  // The first item of block k is item k (no atomic at the start of the
+  // launch, when every block would ask at once); the following ones come
+  // from the counter (offset by the grid), each fetched before the flush of
+  // the item before it.  The fetched index alternates between two LDS slots
+  // (a slot is rewritten only after every thread has passed the barrier that
+  // follows its read).
+  int pick = blockIdx.x;
+  for (int round = 0;; ++round) {
+    if (pick >= nit) break;
+    if (threadIdx.x == 0) s_ndrift = 0;  // visible after the window staging's barriers
+    const Item it = items[pick];
     const SlabDesc &sd = b.slabs[it.slab];
     const Geo g = sd.g;
     const TileGeo tg = sd.tg;
@@ -1103,6 +1105,10 @@ __global__ void __launch_bounds__(256, ND == 2 ? 7 : 4) k_step_tiled(Pot P, Diag
       run_item<ND, DIAG, false, OUT, GEN>(g, P, dc, tg, sv, it, w, dens, Gs, acc, Nn, dlist, &s_ndrift, e_all, acc6,
                                           edges);
     __syncthreads();  // the window's sums and the item's drifter list are complete
+    // the next index, fetched before this item's flush and drifters, which
+    // overlap the atomic's latency
+    int next = 0;
+    if (threadIdx.x == 0) next = (int)gridDim.x + atomicAdd(dr.work, 1);
     flush_window<ND>(g, w, acc, Nn);
     const int ndr = __builtin_amdgcn_readfirstlane(s_ndrift);
     if (ndr > 0) {
@@ -1110,8 +1116,10 @@ __global__ void __launch_bounds__(256, ND == 2 ? 7 : 4) k_step_tiled(Pot P, Diag
       for (int k = threadIdx.x; k < ndr; k += blockDim.x)
         advance_drifter<ND, DIAG, OUT, GEN>(g, P, dc, tg, sv, dlist[k], Ncur + sd.node_off, Nn, e_all, acc6);
     }
-    if (DIAG) block_reduce_store<6>(acc6, partial + (int64_t)bi * 8);
-    __syncthreads();  // LDS and s_item are reused by the next item
+    if (DIAG) block_reduce_store<6>(acc6, partial + (int64_t)pick * 8);
+    if (threadIdx.x == 0) s_item[round & 1] = next;
+    __syncthreads();  // LDS is reused by the next item; the next index is visible
+    pick = __builtin_amdgcn_readfirstlane(s_item[round & 1]);
   }
   if (e_all) atomicOr(err, e_all);
 }
