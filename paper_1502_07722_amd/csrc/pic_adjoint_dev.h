@@ -357,9 +357,11 @@ struct PushRecord {
   float sgn[3];
 };
 
+// edges: as push_particle's (bit d clear = no wall or wrap within reach along d)
 template <int ND, bool GEN = false>
 __device__ __forceinline__ uint32_t recompute_push(const Geo &g, const Pot &P, const int idx[3], const float f[3],
-                                                   const float v[3], float nh, const float Gp[3], PushRecord &r) {
+                                                   const float v[3], float nh, const float Gp[3], PushRecord &r,
+                                                   uint32_t edges = 7u) {
   float Fh[3];
   pair_force<ND, GEN>(P, nh, Gp, Fh);
   const float F[3] = {Fh[0] * P.beta, Fh[1] * P.beta, ND == 3 ? Fh[2] * P.beta : 0.0f};
@@ -370,7 +372,7 @@ __device__ __forceinline__ uint32_t recompute_push(const Geo &g, const Pot &P, c
     r.idx2[d] = idx[d];
     r.f2[d] = f[d];
   }
-  const uint32_t e = push_particle<ND>(g, P, F, r.idx2, r.f2, v2);
+  const uint32_t e = push_particle<ND>(g, P, F, r.idx2, r.f2, v2, edges);
 #pragma unroll
   for (int d = 0; d < 3; ++d) r.sgn[d] = (d < ND && v2[d] != vpre[d]) ? -1.0f : 1.0f;
   return e;

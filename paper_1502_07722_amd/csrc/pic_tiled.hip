@@ -1319,7 +1319,8 @@ template <int ND, bool GEN, class Dens, class Next>
 __device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P, const int idx[3], const int l[3],
                                                      const PState &q, const Dens &dens, bool has_next,
                                                      const Next &next, float ln[3], float lvv[3], float lf[3],
-                                                     float th[5], int B[3], float t[3], float &an, float aG[3]) {
+                                                     float th[5], int B[3], float t[3], float &an, float aG[3],
+                                                     uint32_t edges = 7u) {
   constexpr int K3 = ND == 2 ? 9 : 27;
   float cr[8];
 #pragma unroll
@@ -1356,7 +1357,7 @@ __device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P,
     }
   }
   PushRecord r;
-  const uint32_t e_push = recompute_push<ND, GEN>(g, P, idx, q.f, q.v, nh, Gp, r);
+  const uint32_t e_push = recompute_push<ND, GEN>(g, P, idx, q.f, q.v, nh, Gp, r, edges);
   if (has_next) {
     int l2[3] = {0, 0, 0};
 #pragma unroll
@@ -1499,6 +1500,8 @@ __global__ void __launch_bounds__(256, 4) k_adjoint_tiled(Pot P, Batch b, Store 
   const StoreView sv = view_of(s, s);
   uint32_t e_all = 0;
   float thf[5] = {0.f, 0.f, 0.f, 0.f, 0.f};  // this thread's parameter terms (chunk / 256 particles at most)
+  // axes along which the window reaches a wall or the periodic seam (uniform)
+  const uint32_t edges = __builtin_amdgcn_readfirstlane(window_edges<ND>(g, w));
   // loads for the next round are issued before the current round is computed
   const int last = it.end - 1;
   AdjLoad cur, nxt;
@@ -1512,12 +1515,13 @@ __global__ void __launch_bounds__(256, 4) k_adjoint_tiled(Pot P, Batch b, Store 
     cur = nxt;
     int idx[3], l[3];
     unpack_cell<ND>(tg, q.pc, idx);
-    const bool inside = live && in_window<ND>(g, w, idx, 1, 3, l);
+    const bool inside = live && in_window<ND>(g, w, idx, 1, 3, l, edges);
     if (!MAXONLY) wave_append(dlist, dcount, p, live && !inside);  // the global path, in a kernel of its own
     if (inside) {
       float lf[3] = {0.f, 0.f, 0.f}, th[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, t[3], an, aG[3];
       int B[3];
-      e_all |= adjoint_on_block<ND, GEN>(g, P, idx, l, q, dens, nbn != nullptr, next, ln, lvv, lf, th, B, t, an, aG);
+      e_all |= adjoint_on_block<ND, GEN>(g, P, idx, l, q, dens, nbn != nullptr, next, ln, lvv, lf, th, B, t, an, aG,
+                                         edges);
       if (!MAXONLY) {  // the particle's cotangents and parameter terms, before its node block
 #pragma unroll
         for (int d = 0; d < ND; ++d) lx[d * cap + p] = lf[d];
