@@ -141,7 +141,7 @@ int step_kernel_blocks_per_cu(int ndim, const TileGeo &tg);
 void launch_fill32(hipStream_t s, int *a, int64_t n);
 
 // reverse mode in the store (pic_tiled.hip); lx [ndim][cap], lv [3][cap]
-size_t adjoint_lds_bytes(const TileGeo &tg, int ndim);
+size_t adjoint_lds_bytes(const TileGeo &tg, int ndim, bool planes);
 // partial: per-item parameter sums, ACCUMULATED over the calls (clear once);
 // N: the step's node sums; nbar, dcount and amax_cur must be zero on entry
 // (launch_clear_reverse)

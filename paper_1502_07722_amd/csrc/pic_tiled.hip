@@ -358,6 +358,24 @@ __device__ __forceinline__ void window_node(const Geo &g, const Window &w, const
   }
 }
 
+// The centre gradients of a staged window (the same function and inputs as
+// every other path: the same bits), one plane per component; ends with a
+// barrier.
+template <int ND>
+__device__ __forceinline__ void stage_gradients(const Geo &g, const Window &w, const float *dens, float *Gs) {
+  Walk<ND> ic((int)threadIdx.x, (int)blockDim.x, w.cy, w.wn[1] - 1);
+  for (int m = threadIdx.x; m < w.nC; m += blockDim.x, ic.next()) {
+    const int nb = win_node<ND>(w, ic.a[0], ic.a[1], ic.a[2]);
+    float c[8], G[3];
+#pragma unroll
+    for (int k = 0; k < (1 << ND); ++k) c[k] = dens[nb + node_corner<ND>(w, k)];
+    centre_gradient<ND>(g, c, G);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) Gs[d * w.nC + m] = G[d];  // one plane per component
+  }
+  __syncthreads();
+}
+
 // Stage the window: densities of the window nodes (folded like the global
 // path) and the centre gradients between them; clear the accumulator.
 template <int ND>
@@ -374,18 +392,7 @@ __device__ __forceinline__ void stage_window(const Geo &g, const Window &w, cons
     if (acc) acc[k] = 0ull;
   }
   __syncthreads();
-  if (!Gs) return;
-  Walk<ND> ic((int)threadIdx.x, (int)blockDim.x, w.cy, w.wn[1] - 1);
-  for (int m = threadIdx.x; m < w.nC; m += blockDim.x, ic.next()) {
-    const int nb = win_node<ND>(w, ic.a[0], ic.a[1], ic.a[2]);
-    float c[8], G[3];
-#pragma unroll
-    for (int k = 0; k < (1 << ND); ++k) c[k] = dens[nb + node_corner<ND>(w, k)];
-    centre_gradient<ND>(g, c, G);
-#pragma unroll
-    for (int d = 0; d < ND; ++d) Gs[d * w.nC + m] = G[d];  // one plane per component
-  }
-  __syncthreads();
+  if (Gs) stage_gradients<ND>(g, w, dens, Gs);
 }
 
 template <int ND>
@@ -1286,6 +1293,22 @@ __device__ __forceinline__ int folded_node(const Geo &g, int x, int y, int z) {
   return node_index<ND>(g, fold_node(g, 0, x), fold_node(g, 1, y), ND == 3 ? fold_node(g, 2, z) : 0);
 }
 
+// Centre gradients of the 2^ND nearest centres: read from the window's planes
+// (kPlanes), or built by the reverse step from its 3^ND node block.
+template <int ND>
+struct WinCentres {
+  static constexpr bool kPlanes = true;
+  const float *G;
+  int nC, cy, cz;
+  __device__ __forceinline__ float operator()(int d, int m0, int m1, int m2) const {
+    return G[d * nC + m0 + cy * m1 + (ND == 3 ? cz * m2 : 0)];
+  }
+};
+struct NoCentres {
+  static constexpr bool kPlanes = false;
+  __device__ __forceinline__ float operator()(int, int, int, int) const { return 0.0f; }
+};
+
 template <int ND>
 struct GlobalDens {  // node density of step n from the node sums (the window's bits)
   const long long *N;
@@ -1315,12 +1338,12 @@ struct GlobalNext {  // kfac * nbar of step n+1 at a (real) node
 // of the gathered density and gradient go back to the block: a3 (node
 // cotangents of the block, first node at frame coordinates B).  GEN: the
 // potential chosen at run time (Lennard-Jones or Morse).
-template <int ND, bool GEN, class Dens, class Next>
+template <int ND, bool GEN, class Dens, class Next, class Cent = NoCentres>
 __device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P, const int idx[3], const int l[3],
                                                      const PState &q, const Dens &dens, bool has_next,
                                                      const Next &next, float ln[3], float lvv[3], float lf[3],
                                                      float th[5], int B[3], float t[3], float &an, float aG[3],
-                                                     uint32_t edges = 7u) {
+                                                     uint32_t edges = 7u, const Cent &cent = Cent{}) {
   constexpr int K3 = ND == 2 ? 9 : 27;
   float cr[8];
 #pragma unroll
@@ -1335,20 +1358,28 @@ __device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P,
   for (int e = 0; e < ND; ++e) centre_stencil(l[e], q.f[e], B[e], t[e]);
   float Gp[3] = {0.f, 0.f, 0.f}, dG[3][3];
   {
-    float d3[K3];
-#pragma unroll
-    for (int a = 0; a < K3; ++a) d3[a] = dens(B[0] + a % 3, B[1] + (a / 3) % 3, ND == 3 ? B[2] + a / 9 : 0);
     float vv[3][8];
+    if constexpr (Cent::kPlanes) {
 #pragma unroll
-    for (int k = 0; k < (1 << ND); ++k) {
-      float c[8], Gc[3];
+      for (int k = 0; k < (1 << ND); ++k)
 #pragma unroll
-      for (int j = 0; j < (1 << ND); ++j)
-        c[j] = d3[b3<ND>((k & 1) + (j & 1), ((k >> 1) & 1) + ((j >> 1) & 1),
-                         ND == 3 ? ((k >> 2) & 1) + ((j >> 2) & 1) : 0)];
-      centre_gradient<ND>(g, c, Gc);
+        for (int d = 0; d < ND; ++d)
+          vv[d][k] = cent(d, B[0] + (k & 1), B[1] + ((k >> 1) & 1), ND == 3 ? B[2] + ((k >> 2) & 1) : 0);
+    } else {
+      float d3[K3];
 #pragma unroll
-      for (int d = 0; d < ND; ++d) vv[d][k] = Gc[d];
+      for (int a = 0; a < K3; ++a) d3[a] = dens(B[0] + a % 3, B[1] + (a / 3) % 3, ND == 3 ? B[2] + a / 9 : 0);
+#pragma unroll
+      for (int k = 0; k < (1 << ND); ++k) {
+        float c[8], Gc[3];
+#pragma unroll
+        for (int j = 0; j < (1 << ND); ++j)
+          c[j] = d3[b3<ND>((k & 1) + (j & 1), ((k >> 1) & 1) + ((j >> 1) & 1),
+                           ND == 3 ? ((k >> 2) & 1) + ((j >> 2) & 1) : 0)];
+        centre_gradient<ND>(g, c, Gc);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) vv[d][k] = Gc[d];
+      }
     }
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
@@ -1450,7 +1481,10 @@ __device__ __forceinline__ void block_reduce_add(double v[NF], double *__restric
   }
 }
 
-template <int ND, bool MAXONLY, bool GEN>
+// PLANES: the window also holds the centre-gradient planes (staged once per
+// item, as in the forward step) and each particle reads its 2^ND centres'
+// gradients from them instead of building them from its 3^ND node block.
+template <int ND, bool MAXONLY, bool GEN, bool PLANES>
 __global__ void __launch_bounds__(256, 4) k_adjoint_tiled(Pot P, Batch b, Store s, const Item *__restrict__ items,
                                                        const int *__restrict__ num_items,
                                                        const long long *__restrict__ Ncur,
@@ -1494,8 +1528,11 @@ __global__ void __launch_bounds__(256, 4) k_adjoint_tiled(Pot P, Batch b, Store 
     }
   }
   __syncthreads();
+  float *Gs = nx + w.nW;  // [ND][nC] when PLANES
+  if (PLANES) stage_gradients<ND>(g, w, dw, Gs);
   const WinRead<ND> dens{dw, w.wn[0], w.wn[0] * w.wn[1]};
   const WinRead<ND> next{nx, w.wn[0], w.wn[0] * w.wn[1]};
+  const WinCentres<ND> cent{Gs, w.nC, w.cy, w.cz};
   const int cap = (int)s.cap;
   const StoreView sv = view_of(s, s);
   uint32_t e_all = 0;
@@ -1520,8 +1557,12 @@ __global__ void __launch_bounds__(256, 4) k_adjoint_tiled(Pot P, Batch b, Store 
     if (inside) {
       float lf[3] = {0.f, 0.f, 0.f}, th[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, t[3], an, aG[3];
       int B[3];
-      e_all |= adjoint_on_block<ND, GEN>(g, P, idx, l, q, dens, nbn != nullptr, next, ln, lvv, lf, th, B, t, an, aG,
-                                         edges);
+      if (PLANES)
+        e_all |= adjoint_on_block<ND, GEN>(g, P, idx, l, q, dens, nbn != nullptr, next, ln, lvv, lf, th, B, t, an, aG,
+                                           edges, cent);
+      else
+        e_all |= adjoint_on_block<ND, GEN>(g, P, idx, l, q, dens, nbn != nullptr, next, ln, lvv, lf, th, B, t, an, aG,
+                                           edges);
       if (!MAXONLY) {  // the particle's cotangents and parameter terms, before its node block
 #pragma unroll
         for (int d = 0; d < ND; ++d) lx[d * cap + p] = lf[d];
@@ -1766,16 +1807,20 @@ void launch_reduce_diag_slab(hipStream_t st, const double *part_p, const int *it
   k_reduce_diag_slab<<<1, 256, 0, st>>>(red, out, step);
 }
 
-size_t adjoint_lds_bytes(const TileGeo &tg, int ndim) {
+size_t adjoint_lds_bytes(const TileGeo &tg, int ndim, bool planes) {
   size_t nW = 1, nC = 1;
   for (int d = 0; d < ndim; ++d) {
     size_t wn = (size_t)(1 << tg.lt[d]) + 2 * tg.H + 3;
     nW *= wn;
     nC *= wn - 1;
   }
-  (void)nC;
-  return nW * (8 + 4 + 4);
+  return nW * (8 + 4 + 4) + (planes ? nC * 4 * (size_t)ndim : 0);
 }
+
+// The reverse step reads centre planes when they still leave room for 4
+// blocks per CU (the kernel's occupancy bound); a larger window keeps its
+// occupancy and builds the gradients from each particle's node block.
+static bool adjoint_planes(const TileGeo &tg, int ndim) { return adjoint_lds_bytes(tg, ndim, true) <= 40 * 1024; }
 
 void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
                           const BinBufs &bb, int max_items, const long long *N, const float *nbar_next,
@@ -1783,20 +1828,25 @@ void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot
                           const uint32_t *amax_prev, uint32_t *amax_cur, double *partial, double *dacc,
                           uint32_t *err) {
   if (max_items <= 0) return;
-  const size_t lds = adjoint_lds_bytes(tg, ndim);
+  const bool planes = adjoint_planes(tg, ndim);
+  const size_t lds = adjoint_lds_bytes(tg, ndim, planes);
   // dcount and amax_cur start at zero: the caller clears them (with nbar)
   // GEN: the Morse potential or the hexagonal lattice (runtime choice)
-#define PIC_ADJT(GN)                                                                                              \
-  PIC_ND(ndim, (k_adjoint_tiled<ND, false, GN><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, N,   \
-                                                                              nbar_next, lx, lv, nbar, dlist,     \
-                                                                              dcount, amax_prev, amax_cur,        \
-                                                                              partial, err)));                    \
-  PIC_ND(ndim, (k_adjoint_drifters<ND, GN><<<kDriftBlocks, 256, 0, st>>>(P, b, s, dlist, dcount, N, nbar_next,    \
-                                                                           lx, lv, nbar, dacc, err)))
+#define PIC_ADJT(GN, PL)                                                                                          \
+  PIC_ND(ndim, (k_adjoint_tiled<ND, false, GN, PL><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, \
+                                                                                  N, nbar_next, lx, lv, nbar,    \
+                                                                                  dlist, dcount, amax_prev,      \
+                                                                                  amax_cur, partial, err)))
   if (P.kind != 0 || P.lattice != 0) {
-    PIC_ADJT(true);
+    if (planes) PIC_ADJT(true, true);
+    else PIC_ADJT(true, false);
+    PIC_ND(ndim, (k_adjoint_drifters<ND, true><<<kDriftBlocks, 256, 0, st>>>(P, b, s, dlist, dcount, N, nbar_next, lx,
+                                                                             lv, nbar, dacc, err)));
   } else {
-    PIC_ADJT(false);
+    if (planes) PIC_ADJT(false, true);
+    else PIC_ADJT(false, false);
+    PIC_ND(ndim, (k_adjoint_drifters<ND, false><<<kDriftBlocks, 256, 0, st>>>(P, b, s, dlist, dcount, N, nbar_next,
+                                                                              lx, lv, nbar, dacc, err)));
   }
 #undef PIC_ADJT
 }
@@ -1805,12 +1855,13 @@ void launch_adjoint_scale(hipStream_t st, int ndim, const TileGeo &tg, const Pot
                           const BinBufs &bb, int max_items, const long long *N, const float *nbar_next, float *lx,
                           float *lv, uint32_t *amax) {
   if (max_items <= 0) return;
-  const size_t lds = adjoint_lds_bytes(tg, ndim);
+  const size_t lds = adjoint_lds_bytes(tg, ndim, false);
   launch_fill32(st, reinterpret_cast<int *>(amax), 1);
-#define PIC_ADJS(GN)                                                                                            \
-  PIC_ND(ndim, (k_adjoint_tiled<ND, true, GN><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, N,  \
-                                                                             nbar_next, lx, lv, nullptr, nullptr, \
-                                                                             nullptr, amax, amax, nullptr, nullptr)))
+#define PIC_ADJS(GN)                                                                                                \
+  PIC_ND(ndim, (k_adjoint_tiled<ND, true, GN, false><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, \
+                                                                                    N, nbar_next, lx, lv, nullptr,  \
+                                                                                    nullptr, nullptr, amax, amax,   \
+                                                                                    nullptr, nullptr)))
   if (P.kind != 0 || P.lattice != 0) PIC_ADJS(true);
   else PIC_ADJS(false);
 #undef PIC_ADJS
