@@ -2,12 +2,14 @@
 // for gfx950.
 //
 // A context advances one or more independent slabs (grids).  Particles live
-// in an internal structure-of-arrays store binned by tile (a block of T^ND
-// cells of one slab).  Within a tile the order is scrambled once, at import,
-// by a multiplicative permutation, so that the lanes of a wavefront hold
-// particles of different cells (few same-address LDS atomics in the deposit).
-// A work item is a chunk of one tile's particles.  Each step is one
-// persistent launch whose blocks pull items from an atomic counter; per item:
+// in an internal structure-of-arrays store binned by tile (a block of cells
+// of one slab, shorter along the last axis if the tiling asks for it).
+// Within a tile the order is permuted once, at import (2D: a multiplicative
+// scramble; 3D: layers of one particle per cell), so that the lanes of a
+// wavefront hold particles of different cells (few same-address LDS atomics
+// in the deposit).  A work item is a chunk of one tile's particles.  Each
+// step is one persistent launch: block k starts with item k and takes the
+// rest from an atomic counter; per item:
 //   1. stage the node densities of the tile plus a halo (window) from the
 //      int64 node sums of this step into LDS, and the cell-centred gradients;
 //   2. for each particle: gather density and gradient (LDS), eq. (1)-(3)
@@ -16,10 +18,11 @@
 //   3. flush the accumulator into the next step's node sums (global int64
 //      atomics); every block also clears its share of the node buffer of the
 //      step after next.
-// Particles that drifted outside their window since the last binning go to a
-// list that a second small kernel advances through the global node sums with
-// the same arithmetic (same bits).  The int64 sums make the result
-// independent of order, tiling, binning period and batching.
+// Particles that drifted outside their window since the last binning go to
+// the item's drifter list, which the block advances at the end of the item
+// through the global node sums with the same arithmetic (same bits).  The
+// int64 sums make the result independent of order, tiling, binning period
+// and batching.
 #include "pic_internal.h"
 #include "pic_adjoint_dev.h"
 
@@ -1091,15 +1094,15 @@ __device__ __forceinline__ void advance_drifter(const Geo &g, const Pot &P, cons
   deposit_global<ND>(g, Nn, idx, tq);
 }
 
-// Persistent: a fixed grid pulls work items (chunks of one tile of one slab)
-// from an atomic counter until the step's items are done.  Each item ends
-// with its own drifters (a few per item: the context re-bins once they
-// exceed a small fraction of the particles), so one launch is the whole
-// step.  Every block also clears its share of the node buffer two steps
-// ahead.
-// The occupancy bound (waves per SIMD: 7 in 2D, 5 in 3D) is what the item
-// loop needs alone; it keeps the rarely taken drifter path from raising the
-// register count of the whole kernel.
+// Persistent: a fixed grid works through the step's work items (chunks of
+// one tile of one slab) until they are done.  Each item ends with its own
+// drifters (a few per item: the context re-bins once they exceed a small
+// fraction of the particles), so one launch is the whole step.  Every block
+// also clears its share of the node buffer two steps ahead.
+// The occupancy bound (waves per SIMD: 7 in 2D; 4 in 3D, where the window's
+// LDS allows 3-5 blocks per CU and more waves would spill registers in the
+// item loop) is what the item loop needs alone; it keeps the rarely taken
+// drifter path from raising the register count of the whole kernel.
 template <int ND, bool DIAG, bool OUT, bool GEN>
 __global__ void __launch_bounds__(256, ND == 2 ? 7 : 4) k_step_tiled(Pot P, DiagC dc, Batch b, Store s, Store o,
                                                     const Item *__restrict__ items,
