@@ -236,6 +236,7 @@ Pot make_pot(const pic_potential_t &P, double dt) {
   const double r3 = P.r0 * P.r0 * P.r0;
   Q.nfloor = (float)(P.n_floor * r3);
   Q.gclamp = (float)P.g_clamp;
+  Q.hgclamp = 0.5f * Q.gclamp;
   Q.s_rep = (float)P.s_rep;
   Q.c_att = (float)P.c_att;
   Q.beta = (float)(12.0 * P.D / P.r0);
@@ -243,6 +244,7 @@ Pot make_pot(const pic_potential_t &P, double dt) {
   Q.kind = P.kind;
   Q.mAl2 = P.kind == PIC_POT_MORSE ? (float)(P.alpha * P.r0 * M_LOG2E) : 0.0f;
   Q.mA6 = P.kind == PIC_POT_MORSE ? (float)(P.alpha * P.r0 / 6.0) : 0.0f;
+  Q.mAt = 6.0f * Q.mA6 * Q.mA6;
   Q.lattice = P.lattice;
   Q.ks = 1.0f;
   return Q;

@@ -92,7 +92,7 @@ __device__ __forceinline__ void pair_terms(const Pot &P, float s, float &k, floa
   if (GEN && P.kind == 1) {
     const float E = morse_e(P, s), is = __builtin_amdgcn_rcpf(s);
     k = P.mA6 * __builtin_fmaf(-E, E, E);
-    t = (6.0f * P.mA6 * P.mA6) * __builtin_fmaf(-2.0f * E, E, E);
+    t = P.mAt * __builtin_fmaf(-2.0f * E, E, E);
     dk = t * is * is;
   } else {
     const float s2 = s * s, s6 = s2 * s2 * s2, s7 = s6 * s, s12 = s6 * s6;
@@ -182,23 +182,28 @@ __device__ __forceinline__ void pair_force_vjp(const Pot &P, float nh, const flo
     hcp_force_vjp<ND>(P, q, rinv, inv_n, G, mu, an, aG, th);
     return;
   }
+  // the forward's algebra: s+- = q -+ hq with hq = q g / 2 = -Gh / (6 nh),
+  // clamped at +-hc, hc = q gclamp / 2.  F(q, hq) = M+ k(s+) - M- k(s-):
+  // dF/dq = A - B and dF/dhq = -(A + B) with A = M+ k'(s+), B = M- k'(s-).
+  // Free hq: dhq/dnh = -hq / nh, dhq/dGh = -1 / (6 nh); clamped hq = +-hc:
+  // dhq/dnh = (hq / q) dq/dnh, dhq/dGh = 0.
+  const float rn6 = inv_n * (-1.0f / 6.0f);
+  const float hc = q * P.hgclamp;
+  const float dqq = inv_n * (1.0f / 3.0f);  // (dq/dnh) / q
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    const float graw = (G[d] * rinv) * (-1.0f / 3.0f);
-    const float g = fminf(fmaxf(graw, -P.gclamp), P.gclamp);
-    const bool free_g = graw > -P.gclamp && graw < P.gclamp;
-    const float hq = 0.5f * q * g;
+    const float hraw = G[d] * rn6;
+    const float hq = fminf(fmaxf(hraw, -hc), hc);
+    const bool free_h = hraw > -hc && hraw < hc;
     const float sp = q - hq, sm = q + hq;
-    float k_p, dk_p, k_m, dk_m, t_p = 0.0f, t_m = 0.0f, ip = 0.0f, im = 0.0f;
+    float k_p, dk_p, k_m, dk_m, t_p = 0.0f, t_m = 0.0f;
     if (morse) {
-      const float A2 = 6.0f * P.mA6 * P.mA6;  // A^2 / 6
       const float Ep = morse_e(P, sp), Em = morse_e(P, sm);
-      ip = __builtin_amdgcn_rcpf(sp);
-      im = __builtin_amdgcn_rcpf(sm);
       k_p = P.mA6 * __builtin_fmaf(-Ep, Ep, Ep);
       k_m = P.mA6 * __builtin_fmaf(-Em, Em, Em);
-      t_p = A2 * __builtin_fmaf(-2.0f * Ep, Ep, Ep);
-      t_m = A2 * __builtin_fmaf(-2.0f * Em, Em, Em);
+      t_p = P.mAt * __builtin_fmaf(-2.0f * Ep, Ep, Ep);
+      t_m = P.mAt * __builtin_fmaf(-2.0f * Em, Em, Em);
+      const float ip = __builtin_amdgcn_rcpf(sp), im = __builtin_amdgcn_rcpf(sm);
       dk_p = t_p * ip * ip;
       dk_m = t_m * im * im;
     } else {
@@ -216,25 +221,26 @@ __device__ __forceinline__ void pair_force_vjp(const Pot &P, float nh, const flo
     const bool rp = sp > 1.0f, rm = sm > 1.0f;  // repulsive branch (r < r0)
     const float Mp = rp ? P.s_rep : P.c_att, Mm = rm ? P.s_rep : P.c_att;
     const float A = Mp * dk_p, B = Mm * dk_m;
-    const float Fh = Mp * k_p - Mm * k_m;
-    const float dFdq = A * (1.0f - 0.5f * g) - B * (1.0f + 0.5f * g);
-    const float dFdg = -0.5f * q * (A + B);
-    const float dgdn = free_g ? (-4.0f / 3.0f) * g * inv_n : 0.0f;
-    const float dgdG = free_g ? (-1.0f / 3.0f) * rinv : 0.0f;
+    const float Fh = __builtin_fmaf(Mp, k_p, -(Mm * k_m));
+    const float ApB = A + B, AmB = A - B;
+    const float dhdn = free_h ? -hq * inv_n : hq * dqq;
     const float m = mu[d];
-    an += m * (dFdq * dqdn + dFdg * dgdn);
-    aG[d] = m * dFdg * dgdG;
-    th[0] += m * Fh;
+    an = __builtin_fmaf(m, __builtin_fmaf(AmB, dqdn, -(ApB * dhdn)), an);
+    aG[d] = free_h ? (m * -ApB) * rn6 : 0.0f;
+    th[0] = __builtin_fmaf(m, Fh, th[0]);
+    const float Ws = __builtin_fmaf(A, sp, -(B * sm));  // M s dk/ds, + side minus - side
     if (morse) {
-      // r0: M (k + t) per side; alpha: M A dk/dA = M (k + t - t / s)
-      const float tp = Mp * t_p, tm = Mm * t_m;
-      th[1] += m * (tp - tm);
-      th[4] += m * (Fh + (tp - tm) - (tp * ip - tm * im));
+      // r0: M (k + t) per side; alpha: M A dk/dA = M (k + t - t / s), t / s = s dk/ds
+      const float tpm = Mp * t_p - Mm * t_m;
+      th[1] = __builtin_fmaf(m, tpm, th[1]);
+      th[4] = __builtin_fmaf(m, (Fh + tpm) - Ws, th[4]);
     } else {
-      th[1] += m * (A * sp - B * sm - Fh);
+      th[1] = __builtin_fmaf(m, Ws - Fh, th[1]);
     }
-    th[2] += m * ((rp ? k_p : 0.0f) - (rm ? k_m : 0.0f));
-    th[3] += m * ((rp ? 0.0f : k_p) - (rm ? 0.0f : k_m));
+    // the repulsive and attractive shares of k+ - k-
+    const float krep = (rp ? k_p : 0.0f) - (rm ? k_m : 0.0f);
+    th[2] = __builtin_fmaf(m, krep, th[2]);
+    th[3] = __builtin_fmaf(m, (k_p - k_m) - krep, th[3]);
   }
 }
 

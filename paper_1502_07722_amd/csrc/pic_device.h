@@ -33,6 +33,7 @@ struct Geo {
 struct Pot {
   float nfloor;    // n_floor r0^3
   float gclamp;
+  float hgclamp;   // gclamp / 2
   float s_rep;
   float c_att;
   float beta;      // 12 D / r0: reduced force -> newtons
@@ -40,6 +41,7 @@ struct Pot {
   int kind;        // pair potential: 0 Lennard-Jones eq. (3), 1 Morse
   float mAl2;      // Morse: alpha r0 log2(e)
   float mA6;       // Morse: alpha r0 / 6
+  float mAt;       // Morse: 6 mA6^2 = (alpha r0)^2 / 6
   int lattice;     // 0 cubic (eqs. (1)-(2) per axis), 1 hexagonal close-packed
   float ks;        // reverse mode only: scale of the force cotangent of the
                    // step's kick (1; 1 + f when the step also reverses a start
@@ -305,7 +307,7 @@ __device__ __forceinline__ void pair_force(const Pot &P, float nh, const float G
   // s+- = q (1 -+ g/2) with g = -(1/3) Gh / (nh q):  q g / 2 = -Gh / (6 nh),
   // and |g| <= gclamp is |q g / 2| <= q gclamp / 2
   const float rn6 = __builtin_amdgcn_rcpf(nh) * (-1.0f / 6.0f);
-  const float hc = q * (0.5f * P.gclamp);
+  const float hc = q * P.hgclamp;
   float e = 0.0f;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
