@@ -935,11 +935,14 @@ __global__ void __launch_bounds__(256) k_tile_items(Batch b, const int *__restri
     items[i0 + k] = Item{t, s + (int)((long long)k * c / m), s + (int)((long long)(k + 1) * c / m), slab};
 }
 
-constexpr int kUnroll = 8;  // loads in flight per thread per field
-
+// The inverse of the import gather: one 1024-thread block per tile, four
+// fields per pass through LDS, each group's caller indices loaded once.
 template <int ND>
-__global__ void __launch_bounds__(256) k_export(SlabDesc sd, Store s, const int *__restrict__ starts, PartPtrs cp) {
-  __shared__ int s_o[kScrGroup], s_v[kScrGroup];
+__global__ void __launch_bounds__(kGatherThreads) k_export(SlabDesc sd, Store s, const int *__restrict__ starts,
+                                                           PartPtrs cp) {
+  __shared__ int s_o[kScrGroup];
+  __shared__ int s_v[kFieldsPerPass][kScrGroup];
+  constexpr int NF = ND + 4;  // field k: 0 cell, 1..ND offsets, ND+1..ND+3 velocity
   const int t = sd.tile_off + (int)blockIdx.x;
   const int s0 = starts[t], L = starts[t + 1] - s0;
   const int tile_cells = 1 << (sd.tg.lt[0] + sd.tg.lt[1] + (ND == 3 ? sd.tg.lt[2] : 0));
@@ -948,33 +951,40 @@ __global__ void __launch_bounds__(256) k_export(SlabDesc sd, Store s, const int 
     const int len = min(kScrGroup, L - g0);
     const int64_t base = (int64_t)s0 + g0;
     for (int q = tid; q < len; q += B) s_o[q] = s.oidx[base + q];
-    // field k: 0 cell, 1..ND offsets, ND+1..ND+3 velocity
-    for (int k = 0; k < ND + 4; ++k) {
-      const int *src = k == 0 ? s.pc
-                       : k <= ND ? reinterpret_cast<const int *>(s.off) + (int64_t)(k - 1) * s.cap
-                       : reinterpret_cast<const int *>(s.vel) + (int64_t)(k - ND - 1) * s.cap;
-      for (int q0 = tid; q0 < len; q0 += kUnroll * B) {
-        int v[kUnroll];
+    for (int k0 = 0; k0 < NF; k0 += kFieldsPerPass) {
+      // slots read in order ...
+      for (int q = tid; q < len; q += B) {
+        int v[kFieldsPerPass];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) v[u] = q0 + u * B < len ? src[base + q0 + u * B] : 0;
+        for (int j = 0; j < kFieldsPerPass; ++j) {
+          const int k = k0 + j;
+          const int *src = k == 0 ? s.pc
+                           : k <= ND ? reinterpret_cast<const int *>(s.off) + (int64_t)(k - 1) * s.cap
+                                     : reinterpret_cast<const int *>(s.vel) + (int64_t)(k - ND - 1) * s.cap;
+          v[j] = k < NF ? src[base + q] : 0;
+        }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-          if (q0 + u * B < len) s_v[q0 + u * B] = v[u];
+        for (int j = 0; j < kFieldsPerPass; ++j) s_v[j][q] = v[j];
       }
       __syncthreads();
+      // ... and written in rank order, i.e. in runs of caller indices
       TileOrder<ND> w(tid, B, len, L, tile_cells);
       for (int r = tid; r < len; r += B, w.next()) {
         const int q = w.pos();
         const int64_t o = s_o[q];
-        const int v = s_v[q];
-        if (k == 0) {
-          int idx[3];
-          unpack_cell<ND>(sd.tg, v, idx);
-          cp.cell[o] = encode_cell<ND>(sd.g, idx);
-        } else if (k <= ND) {
-          reinterpret_cast<int *>(cp.off)[(int64_t)(k - 1) * cp.n + o] = v;
-        } else {
-          reinterpret_cast<int *>(cp.vel)[(int64_t)(k - ND - 1) * cp.n + o] = v;
+#pragma unroll
+        for (int j = 0; j < kFieldsPerPass; ++j) {
+          const int k = k0 + j, v = s_v[j][q];
+          if (k >= NF) break;
+          if (k == 0) {
+            int idx[3];
+            unpack_cell<ND>(sd.tg, v, idx);
+            cp.cell[o] = encode_cell<ND>(sd.g, idx);
+          } else if (k <= ND) {
+            reinterpret_cast<int *>(cp.off)[(int64_t)(k - 1) * cp.n + o] = v;
+          } else {
+            reinterpret_cast<int *>(cp.vel)[(int64_t)(k - ND - 1) * cp.n + o] = v;
+          }
         }
       }
       __syncthreads();
@@ -1804,7 +1814,7 @@ void launch_rebin(hipStream_t st, int ndim, const BinBufs &bb, const Batch &b, i
 void launch_export(hipStream_t st, int ndim, const SlabDesc &sd, const Store &s, const BinBufs &bb,
                    const PartPtrs &cp) {
   if (sd.part_n <= 0 || sd.tg.ntiles <= 0) return;
-  PIC_ND(ndim, (k_export<ND><<<sd.tg.ntiles, 256, 0, st>>>(sd, s, bb.starts, cp)));
+  PIC_ND(ndim, (k_export<ND><<<sd.tg.ntiles, kGatherThreads, 0, st>>>(sd, s, bb.starts, cp)));
 }
 
 void launch_deposit_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Batch &b, const Store &s,
