@@ -189,7 +189,8 @@ def test_autograd_crater_gradient_matches_oracle_finite_differences(B, family):
 def test_autograd_on_a_grid_too_small_for_tiles(B):
     """A 6^3 grid has no 3D tiling: the Trajectory Function takes the
     checkpointed per-step chain; its gradient matches the differentiable FP64
-    reference (oracle/autograd_ref.py)."""
+    reference (oracle/autograd_ref.py) within 1e-4 relative (measured
+    2.0e-6 to 5.0e-5)."""
     from oracle import autograd_ref as R
     from paper_1502_07722_amd import autograd as A
     wl = W.cfg_adjoint_3d(n=6, layers=3)
@@ -216,6 +217,6 @@ def test_autograd_on_a_grid_too_small_for_tiles(B):
         for k in keys:
             i = A.THETA_KEYS.index(k)
             ref = th[k].grad.item()
-            assert abs(theta.grad[i].item() - ref) <= 1e-3 * abs(ref), (k, theta.grad[i].item(), ref)
+            assert abs(theta.grad[i].item() - ref) <= 1e-4 * abs(ref), (k, theta.grad[i].item(), ref)
         if c_att != 1.0:
-            assert abs(fl.grad.item() - flr.grad.item()) <= 1e-3 * abs(flr.grad.item())
+            assert abs(fl.grad.item() - flr.grad.item()) <= 1e-4 * abs(flr.grad.item())
