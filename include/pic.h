@@ -435,6 +435,18 @@ int pic_deposit_vjp(pic_ctx_t *ctx, const pic_particles_t *state, const float *n
  * Synchronises and reports device errors. */
 size_t pic_record_bytes(pic_ctx_t *ctx, int32_t nsteps, int32_t every);
 size_t pic_backward_bytes(pic_ctx_t *ctx, int32_t every);
+
+/* all = 1: later records keep every state of the run and the node sums of
+ * every step, not only the checkpoints (checkpoints still set where the run
+ * may re-bin): pic_forward_record writes each step's output straight into
+ * the record, and pic_backward_record recomputes nothing, so the sweep is
+ * the reverse steps alone.  The record grows to about nsteps x (16 + 4 ndim)
+ * bytes per particle slot plus (nsteps + 2) x 8 bytes per node (pic_record_bytes
+ * and pic_backward_bytes report the sizes for the current setting); the
+ * gradient is the same up to the order of float atomic sums.  0 (default):
+ * checkpoints only.  A record must be replayed under the setting it was
+ * written with, otherwise pic_backward_record returns PIC_EINVAL. */
+int pic_set_record_states(pic_ctx_t *ctx, int32_t all);
 int pic_forward_record(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, int32_t every, void *record,
                        size_t record_bytes);
 int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps, int32_t every,

@@ -116,14 +116,21 @@ class Trajectory(torch.autograd.Function):
                 if s % every == 0:
                     rec.append(dp.clone())
                 _step_untiled(ctx, dp)
-        fctx.pic = (ctx, dp, rec, int(nsteps), int(every))
+        # the outputs go through save_for_backward: kept on fctx they would
+        # form a reference cycle that holds the record until the next
+        # garbage collection
+        fctx.save_for_backward(dp.off, dp.vel, dp.cell)
+        fctx.pic = (ctx, wq, rec, int(nsteps), int(every))
         fctx.theta_dev = theta.device
         fctx.mark_non_differentiable(dp.cell)
         return dp.off, dp.vel, dp.cell
 
     @staticmethod
     def backward(fctx, g_off, g_vel, _g_cell):
-        ctx, dp, rec, nsteps, every = fctx.pic
+        ctx, wq, rec, nsteps, every = fctx.pic
+        fctx.pic = None  # the record is released as soon as the sweep has run
+        off, vel, cell = fctx.saved_tensors
+        dp = B.DeviceParticles(cell, off, vel, wq)
         lam_x = torch.zeros_like(dp.off) if g_off is None else g_off.contiguous().float().clone()
         lam_v = torch.zeros_like(dp.vel) if g_vel is None else g_vel.contiguous().float().clone()
         if isinstance(rec, dict):
@@ -153,14 +160,18 @@ class StartedTrajectory(torch.autograd.Function):
                                wq)
         ctx.start_leapfrog(dp)  # v(0) -> v(-1/2): pic_deposit, pic_force, pic_kick(-1/2)
         rec = ctx.pic_forward_record(dp, nsteps, every)
-        fctx.pic = (ctx, dp, rec)
+        fctx.save_for_backward(dp.off, dp.vel, dp.cell)  # no reference cycle (see Trajectory)
+        fctx.pic = (ctx, wq, rec)
         fctx.theta_dev = theta.device
         fctx.mark_non_differentiable(dp.cell)
         return dp.off, dp.vel, dp.cell
 
     @staticmethod
     def backward(fctx, g_off, g_vel, _g_cell):
-        ctx, dp, rec = fctx.pic
+        ctx, wq, rec = fctx.pic
+        fctx.pic = None
+        off, vel, cell = fctx.saved_tensors
+        dp = B.DeviceParticles(cell, off, vel, wq)
         lam_x = torch.zeros_like(dp.off) if g_off is None else g_off.contiguous().float().clone()
         lam_v = torch.zeros_like(dp.vel) if g_vel is None else g_vel.contiguous().float().clone()
         dth = ctx.pic_backward_record(dp, rec, lam_x, lam_v, start_kick=-0.5)

@@ -95,6 +95,7 @@ lib.pic_get_tiling.argtypes = [_vp, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32),
 lib.pic_set_tile_shape.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
 lib.pic_get_tile_shape.argtypes = [_vp, _P(C.c_int32), _P(C.c_int32)]
 lib.pic_set_graph.argtypes = [_vp, C.c_int32]
+lib.pic_set_record_states.argtypes = [_vp, C.c_int32]
 lib.pic_autotune.argtypes = [_vp, _P(pic_particles_t), C.c_int32, _P(pic_tuning_t)]
 lib.pic_workspace_bytes_batch.restype = C.c_size_t
 lib.pic_workspace_bytes_batch.argtypes = [_P(pic_grid_t), C.c_int32, _P(C.c_int64)]
@@ -355,6 +356,11 @@ class Context:
 
     def pic_set_graph(self, on: bool):
         self._check(lib.pic_set_graph(self.ctx, 1 if on else 0), "pic_set_graph")
+
+    def pic_set_record_states(self, all_states: bool):
+        """True: records keep every state and node sum (no recompute in the
+        reverse sweep, records about nsteps x a state); False: checkpoints only."""
+        self._check(lib.pic_set_record_states(self.ctx, 1 if all_states else 0), "pic_set_record_states")
 
     def pic_set_path(self, untiled: bool):
         self._check(lib.pic_set_path(self.ctx, 1 if untiled else 0), "pic_set_path")

@@ -330,6 +330,7 @@ struct pic_ctx {
   // recorded trajectories (reverse mode)
   std::vector<int64_t> rec_key;  // configuration of the last pic_forward_record
   std::vector<char> rec_rebinned;  // checkpoints whose binning differs from the previous one
+  bool rec_all = false;            // records keep every state and node sum (no recompute)
   // graph replay of steady steps
   bool use_graph = true;
   hipGraphExec_t graph[2]{};
@@ -1049,6 +1050,12 @@ int pic_set_graph(pic_ctx_t *ctx, int32_t on) {
   return PIC_OK;
 }
 
+int pic_set_record_states(pic_ctx_t *ctx, int32_t all) {
+  if (!ctx) return PIC_EINVAL;
+  ctx->rec_all = all != 0;
+  return PIC_OK;
+}
+
 static int single_slab(pic_ctx_t *ctx) {
   return ctx->nslab == 1 ? PIC_OK : fail(ctx, PIC_EINVAL, "this call needs a single-slab context");
 }
@@ -1216,10 +1223,14 @@ int pic_deposit_vjp(pic_ctx_t *ctx, const pic_particles_t *state, const float *n
 // Record (device, caller-owned): one entry per checkpoint, each with the
 // state (pc, off, vel), the binning it was taken under (wq, oidx, work items,
 // their count).  Recorded runs re-bin only at checkpoints, so every segment
-// between two checkpoints keeps one binning.
+// between two checkpoints keeps one binning.  A record that keeps every
+// state holds the states of each checkpoint's whole segment (seg of them,
+// the first being the checkpoint's), and after the entries the node sums of
+// every step (nsteps + 2: the last two are the final step's deposit and
+// clear targets), so that the reverse sweep recomputes nothing.
 struct RecLayout {
-  size_t state, wq, oidx, items, nitems, stride, total;
-  int nck;
+  size_t state, wq, oidx, items, nitems, stride, nodes, node_stride, total;
+  int nck, seg;
 };
 
 static size_t state_bytes_of(int nd, int64_t cap) { return align_up((size_t)cap * 4 * (1 + nd + 3)); }
@@ -1228,14 +1239,17 @@ static RecLayout rec_layout(const pic_ctx_t *c, int nsteps, int every) {
   RecLayout R{};
   const int64_t cap = c->cap;
   R.nck = (nsteps + every - 1) / every;
+  R.seg = c->rec_all ? std::min(every, nsteps) : 1;
   size_t o = 0;
-  R.state = o; o += state_bytes_of(c->ndim, cap);
+  R.state = o; o += state_bytes_of(c->ndim, cap) * (size_t)R.seg;
   R.wq = o; o = align_up(o + 4 * (size_t)cap);
   R.oidx = o; o = align_up(o + 4 * (size_t)cap);
   R.items = o; o = align_up(o + sizeof(Item) * (size_t)c->items_cap);
   R.nitems = o; o = align_up(o + sizeof(int));
   R.stride = o;
-  R.total = o * (size_t)R.nck;
+  R.nodes = o * (size_t)R.nck;
+  R.node_stride = align_up(8 * (size_t)c->nnodes);
+  R.total = R.nodes + (c->rec_all ? R.node_stride * (size_t)(nsteps + 2) : 0);
   return R;
 }
 
@@ -1266,7 +1280,8 @@ static int recorded_ok(pic_ctx_t *c, const pic_particles_t *p, int nsteps, int e
 }
 
 static std::vector<int64_t> rec_key_of(const pic_ctx_t *c, int64_t n, int nsteps, int every, const void *rec) {
-  return {n, nsteps, every, c->lt, c->ltl, c->halo, c->chunk, (int64_t)reinterpret_cast<uintptr_t>(rec)};
+  return {n,        nsteps,   every, c->lt, c->ltl, c->halo, c->chunk, (int64_t)reinterpret_cast<uintptr_t>(rec),
+          c->rec_all};
 }
 
 size_t pic_record_bytes(pic_ctx_t *ctx, int32_t nsteps, int32_t every) {
@@ -1274,11 +1289,18 @@ size_t pic_record_bytes(pic_ctx_t *ctx, int32_t nsteps, int32_t every) {
   return rec_layout(ctx, nsteps, every).total;
 }
 
+// Backward scratch: a segment's recomputed states and node sums (not with a
+// record that keeps every state), then the cotangents.
+static size_t segment_scratch_bytes(const pic_ctx_t *c, int every) {
+  if (c->rec_all) return 0;
+  return state_bytes_of(c->ndim, c->cap) * (size_t)every + align_up(8 * (size_t)c->nnodes) * (size_t)(every + 1);
+}
+
 size_t pic_backward_bytes(pic_ctx_t *ctx, int32_t every) {
   if (!ctx || !ctx->tiled || ctx->nslab != 1 || every < 1) return 0;
   const size_t cap = (size_t)ctx->cap, nn = (size_t)ctx->nnodes;
-  return state_bytes_of(ctx->ndim, ctx->cap) * (size_t)every + align_up(8 * nn) * (size_t)(every + 1) +
-         align_up(4 * cap * ctx->ndim) + align_up(4 * cap * 3) + 2 * align_up(4 * nn);
+  return segment_scratch_bytes(ctx, every) + align_up(4 * cap * ctx->ndim) + align_up(4 * cap * 3) +
+         2 * align_up(4 * nn);
 }
 
 int pic_forward_record(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, int32_t every, void *record,
@@ -1302,10 +1324,16 @@ int pic_forward_record(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, int32
   if ((rc = read_device_error(ctx))) return rc;
   int cur = 0;
   const int64_t max_items = max_items_of(ctx, n);
-  launch_fill64(ctx->stream, ctx->n3[0], ctx->nnodes);
-  launch_fill64(ctx->stream, ctx->n3[1], ctx->nnodes);
+  // node sums of step s: the three rotating buffers, or the record's own
+  auto Ns = [&](int s) {
+    return ctx->rec_all ? reinterpret_cast<long long *>(rec + R.nodes + R.node_stride * (size_t)s)
+                        : ctx->n3[s % 3];
+  };
+  launch_fill64(ctx->stream, Ns(0), ctx->nnodes);
+  launch_fill64(ctx->stream, Ns(1), ctx->nnodes);
   launch_fill32(ctx->stream, ctx->drift, 4);
-  launch_deposit_tiled(ctx->stream, nd, ctx->sd[0].tg, b, ctx->st[cur], ctx->bb, (int)max_items, ctx->n3[0]);
+  launch_deposit_tiled(ctx->stream, nd, ctx->sd[0].tg, b, ctx->st[cur], ctx->bb, (int)max_items, Ns(0));
+  const size_t sb = state_bytes_of(nd, ctx->cap);
   std::vector<char> rebinned(R.nck, 0);
   int since_bin = 0;
   for (int32_t s = 0; s < nsteps; ++s) {
@@ -1345,12 +1373,30 @@ int pic_forward_record(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, int32
         e = hipMemcpyAsync(ck + R.nitems, ctx->bb.num_items, sizeof(int), hipMemcpyDeviceToDevice, ctx->stream);
       if ((rc = hip_check(ctx, e, "save checkpoint"))) return rc;
     }
-    enqueue_step(ctx, b, ctx->st[cur], s, false);
+    if (ctx->rec_all) {
+      // step k of segment j reads its state from the record (the checkpoint
+      // itself from the working store) and writes the next one there; the
+      // segment's last step writes the working store, which the next
+      // checkpoint may re-bin
+      const int j = s / every, k = s - j * every, len = std::min(every, nsteps - j * every);
+      char *seg = rec + R.stride * j + R.state;
+      const Store &W = ctx->st[cur];
+      const Store in = k == 0 ? W : state_at(ctx, seg + sb * (size_t)k, W);
+      const Store out = k + 1 < len ? state_at(ctx, seg + sb * (size_t)(k + 1), W) : W;
+      launch_step_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, ctx->dcs[0], b, in, out, ctx->bb, step_grid(ctx, n),
+                        Ns(s), Ns(s + 1), Ns(s + 2), drift_of(ctx, s), ctx->partial, false, ctx->err);
+    } else {
+      enqueue_step(ctx, b, ctx->st[cur], s, false);
+    }
     if ((rc = check_launch(ctx, "recorded step"))) return rc;
     ++since_bin;
   }
   const Store &S = ctx->st[cur];
   launch_export(ctx->stream, nd, ctx->sd[0], S, ctx->bb, cp);
+  if (ctx->rec_all &&
+      (rc = hip_check(ctx, hipMemcpyAsync(ctx->n3[nsteps % 3], Ns(nsteps), 8 * (size_t)ctx->nnodes,
+                                          hipMemcpyDeviceToDevice, ctx->stream), "final node sums")))
+    return rc;
   ctx->last_nodes = ctx->n3[nsteps % 3];
   ctx->last_step = nsteps - 1;
   if ((rc = check_launch(ctx, "export"))) return rc;
@@ -1381,12 +1427,12 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
   const size_t nn = (size_t)ctx->nnodes;
   char *rec = const_cast<char *>(static_cast<const char *>(record));
   char *scr = static_cast<char *>(scratch);
-  // scratch: states of one segment, node sums of one segment (+1), cotangents
+  // scratch: states of one segment, node sums of one segment (+1) (neither
+  // with a record that keeps every state), cotangents
   const size_t sb = state_bytes_of(nd, cap);
   char *traj = scr;
-  long long *N0 = reinterpret_cast<long long *>(traj + sb * (size_t)every);
-  auto Nk = [&](int k) { return reinterpret_cast<long long *>(reinterpret_cast<char *>(N0) + align_up(8 * nn) * k); };
-  float *lx = reinterpret_cast<float *>(reinterpret_cast<char *>(N0) + align_up(8 * nn) * (size_t)(every + 1));
+  char *N0 = traj + sb * (size_t)every;
+  float *lx = reinterpret_cast<float *>(scr + segment_scratch_bytes(ctx, every));
   float *lv = reinterpret_cast<float *>(reinterpret_cast<char *>(lx) + align_up(4 * (size_t)cap * nd));
   float *nbA = reinterpret_cast<float *>(reinterpret_cast<char *>(lv) + align_up(4 * (size_t)cap * 3));
   float *nbB = reinterpret_cast<float *>(reinterpret_cast<char *>(nbA) + align_up(4 * nn));
@@ -1422,21 +1468,28 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
     const int s0 = j * every, len = std::min(every, nsteps - s0);
     const Store ref = ref_of(j);
     const BinBufs bb = bins_of(j);
+    char *seg = rec + R.stride * j + R.state;
     auto slot = [&](int k) {
-      return k == 0 ? state_at(ctx, rec + R.stride * j + R.state, ref) : state_at(ctx, traj + sb * k, ref);
+      return k == 0 || ctx->rec_all ? state_at(ctx, seg + sb * (size_t)k, ref) : state_at(ctx, traj + sb * k, ref);
     };
-    // recompute the segment's states (out of place) and node sums
-    launch_fill64(ctx->stream, Nk(0), ctx->nnodes);
-    if (len > 1) launch_fill64(ctx->stream, Nk(1), ctx->nnodes);
-    launch_fill32(ctx->stream, ctx->drift, 4);
-    launch_deposit_tiled(ctx->stream, nd, ctx->sd[0].tg, b, slot(0), bb, (int)max_items, Nk(0));
-    for (int k = 0; k + 1 < len; ++k) {
-      const Drift dr = drift_of(ctx, k);
-      const Store in = slot(k), out = slot(k + 1);
-      launch_step_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, ctx->dcs[0], b, in, out, bb, step_grid(ctx, n),
-                        Nk(k), Nk(k + 1), Nk(k + 2), dr, ctx->partial, false, ctx->err);
+    auto Nk = [&](int k) {
+      return reinterpret_cast<long long *>(ctx->rec_all ? rec + R.nodes + R.node_stride * (size_t)(s0 + k)
+                                                        : N0 + align_up(8 * nn) * k);
+    };
+    if (!ctx->rec_all) {
+      // recompute the segment's states (out of place) and node sums
+      launch_fill64(ctx->stream, Nk(0), ctx->nnodes);
+      if (len > 1) launch_fill64(ctx->stream, Nk(1), ctx->nnodes);
+      launch_fill32(ctx->stream, ctx->drift, 4);
+      launch_deposit_tiled(ctx->stream, nd, ctx->sd[0].tg, b, slot(0), bb, (int)max_items, Nk(0));
+      for (int k = 0; k + 1 < len; ++k) {
+        const Drift dr = drift_of(ctx, k);
+        const Store in = slot(k), out = slot(k + 1);
+        launch_step_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, ctx->dcs[0], b, in, out, bb, step_grid(ctx, n),
+                          Nk(k), Nk(k + 1), Nk(k + 2), dr, ctx->partial, false, ctx->err);
+      }
+      if ((rc = check_launch(ctx, "recompute"))) return rc;
     }
-    if ((rc = check_launch(ctx, "recompute"))) return rc;
     // reverse steps of the segment
     for (int k = len - 1; k >= 0; --k) {
       const int step = s0 + k;

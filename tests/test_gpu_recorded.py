@@ -60,39 +60,51 @@ def _seed_cotangents(grid, dp):
     return lam_x, lam_v
 
 
-@pytest.mark.parametrize("nd", [2, 3])
-def test_recorded_forward_equals_pic_step(B, nd):
+@pytest.mark.parametrize("nd,all_states", [(2, False), (3, False), (2, True), (3, True)])
+def test_recorded_forward_equals_pic_step(B, nd, all_states):
+    """all_states: the record keeps every state (each step writes its output
+    into the record) instead of checkpoints only."""
     grid, parts, dt = _case(nd)
     pot = W.Potential(c_att=0.27)
     ctx = B.Context(grid, pot, dt, parts.n)
+    ctx.pic_set_record_states(all_states)
     a = B.DeviceParticles.from_host(parts)
     ctx.start_leapfrog(a)
     b = a.clone()
     c = a.clone()
     ctx.pic_step(a, 37)
+    node_a = ctx.pic_step_nodes()
     ctx.pic_forward_record(b, 37, 10)
+    node_b = ctx.pic_step_nodes()
     t, h, ch, _ = ctx.pic_get_tiling()
     ctx.pic_set_tiling(t, h, ch, 3)  # re-binning at every checkpoint
     ctx.pic_forward_record(c, 37, 10)
     torch.cuda.synchronize()
     for x in (b, c):
         assert torch.equal(a.cell, x.cell) and torch.equal(a.off, x.off) and torch.equal(a.vel, x.vel)
+    assert torch.equal(node_a, node_b)
 
 
-@pytest.mark.parametrize("nd,rebin,family,flat", [(2, False, "lj", False), (3, False, "lj", False),
-                                                  (2, True, "lj", False), (3, True, "lj", False),
-                                                  (2, False, "morse", False), (3, True, "morse", False),
-                                                  (2, True, "hcp", False), (3, False, "hcp", False),
-                                                  (3, False, "lj", True), (3, True, "hcp", True)])
-def test_recorded_sweep_matches_per_step_chain(B, nd, rebin, family, flat):
+@pytest.mark.parametrize("nd,rebin,family,flat,all_states",
+                         [(2, False, "lj", False, False), (3, False, "lj", False, False),
+                          (2, True, "lj", False, False), (3, True, "lj", False, False),
+                          (2, False, "morse", False, False), (3, True, "morse", False, False),
+                          (2, True, "hcp", False, False), (3, False, "hcp", False, False),
+                          (3, False, "lj", True, False), (3, True, "hcp", True, False),
+                          (2, True, "lj", False, True), (3, True, "lj", False, True),
+                          (3, False, "morse", False, True), (3, True, "hcp", True, True)])
+def test_recorded_sweep_matches_per_step_chain(B, nd, rebin, family, flat, all_states):
     """rebin: re-binning at every checkpoint (each segment has its own order,
     the cotangents are permuted between segments).  family: the pair
     potential (Morse adds the alpha slot of dtheta).  flat: tiles half as
-    long along the last axis (a flatter reverse-step window)."""
+    long along the last axis (a flatter reverse-step window).  all_states:
+    the record keeps every state and node sum, and the sweep recomputes
+    nothing."""
     grid, parts, dt = _case(nd)
     pot = {"lj": W.Potential(c_att=0.27), "morse": W.morse_cu(c_att=0.43), "hcp": W.hcp(c_att=0.2)}[family]
     nsteps, every = 30, 8  # a ragged last segment
     ctx = B.Context(grid, pot, dt, parts.n)
+    ctx.pic_set_record_states(all_states)
     t, h, c, s = ctx.pic_get_tiling()
     ctx.pic_set_tile_shape(t, t // 2 if flat else t, h, c, 5 if rebin else s)
     assert ctx.pic_get_tile_shape() == (t, t // 2 if flat else t)
@@ -145,13 +157,34 @@ def test_backward_refuses_a_foreign_record(B):
     bad = dict(rec, nsteps=11)
     with pytest.raises(B.PicError):
         ctx.pic_backward_record(dp, bad, lam_x, lam_v)
+    ctx.pic_set_record_states(True)  # a record replayed under the other setting
+    with pytest.raises(B.PicError):
+        ctx.pic_backward_record(dp, rec, lam_x, lam_v)
+    ctx.pic_set_record_states(False)
     ctx.pic_set_tiling(4, 1, 2048, -1)  # a different tiling invalidates the record
     with pytest.raises(B.PicError):
         ctx.pic_backward_record(dp, rec, lam_x, lam_v)
 
 
-@pytest.mark.parametrize("family", ["lj", "morse", "hcp"])
-def test_autograd_crater_gradient_matches_oracle_finite_differences(B, family):
+def test_record_sizes_of_both_settings(B):
+    """A record that keeps every state holds nsteps states (one per step,
+    the ragged last segment's included) and nsteps + 2 node sums; the
+    backward scratch then holds the cotangents only."""
+    grid, parts, dt = _case(3)
+    ctx = B.Context(grid, W.Potential(c_att=0.27), dt, parts.n)
+    nsteps, every = 30, 8
+    ck = B.lib.pic_record_bytes(ctx.ctx, nsteps, every)
+    scr = B.lib.pic_backward_bytes(ctx.ctx, every)
+    ctx.pic_set_record_states(True)
+    full = B.lib.pic_record_bytes(ctx.ctx, nsteps, every)
+    scr_full = B.lib.pic_backward_bytes(ctx.ctx, every)
+    nodes = B.pic_num_nodes(grid)
+    assert full - ck >= (nsteps - 4) * 28 * parts.n + (nsteps + 2) * 8 * nodes
+    assert scr - scr_full >= every * 28 * parts.n + (every + 1) * 8 * nodes
+
+
+@pytest.mark.parametrize("family,all_states", [("lj", False), ("morse", False), ("hcp", False), ("lj", True)])
+def test_autograd_crater_gradient_matches_oracle_finite_differences(B, family, all_states):
     from paper_1502_07722_amd import autograd as A
     with open({"lj": GOLDEN, "morse": GOLDEN_MORSE, "hcp": GOLDEN_HCP}[family]) as fh:
         gold = json.load(fh)
@@ -171,6 +204,7 @@ def test_autograd_crater_gradient_matches_oracle_finite_differences(B, family):
         pot = {"lj": lambda c: W.Potential(c_att=c), "morse": lambda c: W.morse_cu(c_att=c),
                "hcp": lambda c: W.hcp(c_att=c)}[family](rec["c_att"])
         ctx = B.Context(grid, pot, wl.dt, p.n)
+        ctx.pic_set_record_states(all_states)
         theta = A.theta_of(pot).requires_grad_(True)
         fl = torch.tensor(fref, dtype=torch.float64, device=dev, requires_grad=True)
         J, _, _ = A.crater_objective(ctx, cell, off0, vth, xi, sig, fref, fl, wq, theta, nsteps, 20, y_s, tau)
