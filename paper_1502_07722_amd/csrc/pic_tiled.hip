@@ -1553,7 +1553,12 @@ __global__ void __launch_bounds__(256, 4) k_adjoint_tiled(Pot P, Batch b, Store 
   const int sexp = MAXONLY ? 0 : adj_scale_exp(*amax_prev);
   const float to_fix = ldexpf(1.0f, sexp);    // exact power of two (sexp within float range)
   const float lim = ldexpf(1.0f, 51 - sexp);  // larger values: global float atomics
-  float vmax = 0.0f;
+  // the block cotangents are built from inputs scaled by to_fix, which scales
+  // every contribution exactly (a power of two): fixed point without a
+  // multiply per node; lim_s = lim * to_fix
+  constexpr float lim_s = 2251799813685248.0f;  // 2^51
+  float vmax = 0.0f;    // largest contribution, scaled by to_fix (fixed-point particles)
+  float vmax_u = 0.0f;  // largest contribution, unscaled (the other particles)
   const Item it = items[blockIdx.x];
   const SlabDesc &sd = b.slabs[it.slab];
   const Geo g = sd.g;
@@ -1624,33 +1629,40 @@ __global__ void __launch_bounds__(256, 4) k_adjoint_tiled(Pot P, Batch b, Store 
         for (int i = 0; i < 5; ++i) thf[i] += th[i];
       }
       float a3[K3];
-      block_cotangents<ND>(g, l, B, q.f, t, an, aG, a3);
-      float pmax = 0.0f;  // this particle's largest contribution
+      {
+        const float aGs[3] = {aG[0] * to_fix, aG[1] * to_fix, aG[2] * to_fix};
+        block_cotangents<ND>(g, l, B, q.f, t, an * to_fix, aGs, a3);
+      }
+      float pmax = 0.0f;  // this particle's largest contribution (scaled; inf when the scaling overflowed)
 #pragma unroll
       for (int a = 0; a < K3; ++a) pmax = fmaxf(pmax, fabsf(a3[a]));
-      vmax = fmaxf(vmax, pmax);
-      if (!MAXONLY) {
+      if (MAXONLY) {
+        vmax = fmaxf(vmax, pmax);  // to_fix = 1
+      } else if (pmax < lim_s) {  // the common case: every contribution in fixed point, no branch per node
+        vmax = fmaxf(vmax, pmax);
         const int nb = win_node<ND>(w, B[0], B[1], B[2]);
-        if (pmax < lim) {  // the common case: every contribution in fixed point, no branch per node
 #pragma unroll
-          for (int a = 0; a < K3; ++a)
-            atomicAdd(&acc[nb + win_node<ND>(w, a % 3, (a / 3) % 3, ND == 3 ? a / 9 : 0)],
-                      (unsigned long long)fix64(a3[a] * to_fix));
-        } else {
+        for (int a = 0; a < K3; ++a)
+          atomicAdd(&acc[nb + win_node<ND>(w, a % 3, (a / 3) % 3, ND == 3 ? a / 9 : 0)],
+                    (unsigned long long)fix64(a3[a]));
+      } else {
+        // the contributions again, unscaled: some exceed the fixed-point range
+        block_cotangents<ND>(g, l, B, q.f, t, an, aG, a3);
 #pragma unroll
-          for (int a = 0; a < K3; ++a) {
-            const int ax = B[0] + a % 3, ay = B[1] + (a / 3) % 3, az = ND == 3 ? B[2] + a / 9 : 0;
-            if (fabsf(a3[a]) < lim) {
-              atomicAdd(&acc[win_node<ND>(w, ax, ay, az)], (unsigned long long)fix64(a3[a] * to_fix));
-            } else {
-              atomicAdd(&nbar[sd.node_off + folded_node<ND>(g, w.o[0] + ax, w.o[1] + ay, w.o[2] + az)], a3[a]);
-            }
+        for (int a = 0; a < K3; ++a) {
+          vmax_u = fmaxf(vmax_u, fabsf(a3[a]));
+          const int ax = B[0] + a % 3, ay = B[1] + (a / 3) % 3, az = ND == 3 ? B[2] + a / 9 : 0;
+          if (fabsf(a3[a]) < lim) {
+            atomicAdd(&acc[win_node<ND>(w, ax, ay, az)], (unsigned long long)fix64(a3[a] * to_fix));
+          } else {
+            atomicAdd(&nbar[sd.node_off + folded_node<ND>(g, w.o[0] + ax, w.o[1] + ay, w.o[2] + az)], a3[a]);
           }
         }
       }
     }
   }
   // largest single contribution of this block (the next step's scale)
+  vmax = fmaxf(vmax * ldexpf(1.0f, -sexp), vmax_u);
   for (int o = 32; o > 0; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o, 64));
   if ((threadIdx.x & 63) == 0) atomicMax(&s_amax, __float_as_uint(vmax));
   __syncthreads();
