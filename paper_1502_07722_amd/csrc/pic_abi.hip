@@ -1336,33 +1336,44 @@ int pic_forward_record(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, int32
   const size_t sb = state_bytes_of(nd, ctx->cap);
   std::vector<char> rebinned(R.nck, 0);
   int since_bin = 0;
+  // state s of a record that keeps every state: slot k of checkpoint j's
+  // segment (s = j every + k), with the binning of the working store
+  auto rec_state = [&](int s) {
+    const int j = s / every;
+    return state_at(ctx, rec + R.stride * j + R.state + sb * (size_t)(s - j * every), ctx->st[cur]);
+  };
   for (int32_t s = 0; s < nsteps; ++s) {
     if (s % every == 0) {
       const int j = s / every;
+      // the state before step s: the working store, or (every state kept,
+      // s > 0) already the record's, written there by step s - 1
+      const bool in_rec = ctx->rec_all && s > 0;
+      const Store src = in_rec ? rec_state(s) : ctx->st[cur];
       // re-bin at a checkpoint: always with a fixed re-binning period, and
       // with the adaptive one once more than n / kDriftFraction particles
       // left their window in the previous step
+      bool rebin = false;
       if (s > 0 && ctx->sort_every > 0) {
-        launch_rebin(ctx->stream, nd, ctx->bb, b, ctx->chunk, ctx->st[cur], ctx->st[1 - cur]);
-        cur = 1 - cur;
-        since_bin = 0;
-        rebinned[j] = 1;
+        rebin = true;
       } else if (s > 0 && ctx->sort_every < 0) {
         int h = 0;
         if ((rc = hip_check(ctx, hipMemcpyAsync(&h, ctx->drift + ((s - 1) & 1), sizeof(int),
                                                 hipMemcpyDeviceToHost, ctx->stream), "drifter count")))
           return rc;
         if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "stream synchronize"))) return rc;
-        if ((int64_t)h * kDriftFraction > n || since_bin >= kMaxBinPeriod) {
-          launch_rebin(ctx->stream, nd, ctx->bb, b, ctx->chunk, ctx->st[cur], ctx->st[1 - cur]);
-          cur = 1 - cur;
-          since_bin = 0;
-          rebinned[j] = 1;
-        }
+        rebin = (int64_t)h * kDriftFraction > n || since_bin >= kMaxBinPeriod;
+      }
+      if (rebin) {
+        launch_rebin(ctx->stream, nd, ctx->bb, b, ctx->chunk, src, ctx->st[1 - cur]);
+        cur = 1 - cur;
+        since_bin = 0;
+        rebinned[j] = 1;
       }
       char *ck = rec + R.stride * j;
       const Store &S = ctx->st[cur];
-      if ((rc = copy_state(ctx, state_at(ctx, ck + R.state, S), S))) return rc;
+      // the checkpoint's state: copied unless step s - 1 wrote it there and
+      // the binning is unchanged
+      if ((!in_rec || rebin) && (rc = copy_state(ctx, state_at(ctx, ck + R.state, S), S))) return rc;
       hipError_t e = hipMemcpyAsync(ck + R.wq, S.wq, 4 * (size_t)ctx->cap, hipMemcpyDeviceToDevice, ctx->stream);
       if (e == hipSuccess)
         e = hipMemcpyAsync(ck + R.oidx, S.oidx, 4 * (size_t)ctx->cap, hipMemcpyDeviceToDevice, ctx->stream);
@@ -1374,17 +1385,13 @@ int pic_forward_record(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, int32
       if ((rc = hip_check(ctx, e, "save checkpoint"))) return rc;
     }
     if (ctx->rec_all) {
-      // step k of segment j reads its state from the record (the checkpoint
-      // itself from the working store) and writes the next one there; the
-      // segment's last step writes the working store, which the next
-      // checkpoint may re-bin
-      const int j = s / every, k = s - j * every, len = std::min(every, nsteps - j * every);
-      char *seg = rec + R.stride * j + R.state;
-      const Store &W = ctx->st[cur];
-      const Store in = k == 0 ? W : state_at(ctx, seg + sb * (size_t)k, W);
-      const Store out = k + 1 < len ? state_at(ctx, seg + sb * (size_t)(k + 1), W) : W;
-      launch_step_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, ctx->dcs[0], b, in, out, ctx->bb, step_grid(ctx, n),
-                        Ns(s), Ns(s + 1), Ns(s + 2), drift_of(ctx, s), ctx->partial, false, ctx->err);
+      // step s reads state s from the record and writes state s + 1 there
+      // (the next checkpoint re-bins it in place of a copy when it must);
+      // the last step writes the working store, which is exported
+      const Store out = s + 1 < nsteps ? rec_state(s + 1) : ctx->st[cur];
+      launch_step_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, ctx->dcs[0], b, rec_state(s), out, ctx->bb,
+                        step_grid(ctx, n), Ns(s), Ns(s + 1), Ns(s + 2), drift_of(ctx, s), ctx->partial, false,
+                        ctx->err);
     } else {
       enqueue_step(ctx, b, ctx->st[cur], s, false);
     }
