@@ -166,6 +166,39 @@ def test_backward_refuses_a_foreign_record(B):
         ctx.pic_backward_record(dp, rec, lam_x, lam_v)
 
 
+@pytest.mark.parametrize("nsteps,every,sort_every", [(5, 8, None), (6, 1, None), (1, 1, None), (13, 4, 2)])
+def test_every_state_record_matches_checkpoints(B, nsteps, every, sort_every):
+    """Degenerate segment shapes of a record that keeps every state: fewer
+    steps than the checkpoint interval, one step per checkpoint, a single
+    step, and re-binning at every checkpoint (sort_every 2: the checkpoint
+    re-bins the state the previous step wrote into the record).  The final
+    state is the same bits as with checkpoints only, and the sweep agrees
+    to the order of float atomic sums."""
+    grid, parts, dt = _case(3)
+    ctx = B.Context(grid, W.Potential(c_att=0.27), dt, parts.n)
+    if sort_every is not None:
+        t, h, c, _ = ctx.pic_get_tiling()
+        ctx.pic_set_tiling(t, h, c, sort_every)
+    dp = B.DeviceParticles.from_host(parts)
+    ctx.start_leapfrog(dp)
+    out = {}
+    for all_states in (False, True):
+        ctx.pic_set_record_states(all_states)
+        x = dp.clone()
+        rec = ctx.pic_forward_record(x, nsteps, every)
+        lam_x, lam_v = _seed_cotangents(grid, x)
+        dth = ctx.pic_backward_record(x, rec, lam_x, lam_v)
+        torch.cuda.synchronize()
+        out[all_states] = (x, lam_x, lam_v, dth)
+    (a, ax_, av, ath), (b, bx, bv, bth) = out[False], out[True]
+    assert torch.equal(a.cell, b.cell) and torch.equal(a.off, b.off) and torch.equal(a.vel, b.vel)
+    for u, v in ((ax_, bx), (av, bv)):
+        u, v = u.double().cpu().numpy(), v.double().cpu().numpy()
+        assert np.abs(u - v).max() <= 1e-4 * max(np.abs(u).max(), 1e-30)
+    ath, bth = ath.cpu().numpy(), bth.cpu().numpy()
+    assert np.all(np.abs(ath - bth) <= 1e-5 * np.abs(ath) + 1e-12), (ath, bth)
+
+
 def test_record_sizes_of_both_settings(B):
     """A record that keeps every state holds nsteps states (one per step,
     the ragged last segment's included) and nsteps + 2 node sums; the
