@@ -1509,8 +1509,20 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
         launch_adjoint_scale(ctx->stream, nd, ctx->sd[0].tg, P, b, slot(k), bb, (int)max_items, Nk(k), nbar_next, lx,
                              lv, amax_prev);
       launch_clear_reverse(ctx->stream, nb_cur, ctx->nnodes, ctx->drift, amax_cur);
+      // the state after this step in this segment's binning: the segment's
+      // next slot, or the next checkpoint's state unless that one was re-binned
+      Store after;
+      const Store *known = nullptr;
+      if (k + 1 < len) {
+        after = slot(k + 1);
+        known = &after;
+      } else if (j + 1 < R.nck && !ctx->rec_rebinned[j + 1]) {
+        after = state_at(ctx, rec + R.stride * (j + 1) + R.state, ref);
+        known = &after;
+      }
       launch_adjoint_tiled(ctx->stream, nd, ctx->sd[0].tg, P, b, slot(k), bb, (int)max_items, Nk(k), nbar_next, lx, lv,
-                           nb_cur, ctx->drift + 4, ctx->drift, amax_prev, amax_cur, ctx->partial, ctx->dacc, ctx->err);
+                           nb_cur, ctx->drift + 4, ctx->drift, amax_prev, amax_cur, ctx->partial, ctx->dacc, ctx->err,
+                           known);
       nbar_next = nb_cur;
       std::swap(nb_cur, nb_other);
       if ((rc = check_launch(ctx, "reverse step"))) return rc;

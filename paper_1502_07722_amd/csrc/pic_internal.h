@@ -145,10 +145,13 @@ size_t adjoint_lds_bytes(const TileGeo &tg, int ndim, bool planes);
 // partial: per-item parameter sums, ACCUMULATED over the calls (clear once);
 // N: the step's node sums; nbar, dcount and amax_cur must be zero on entry
 // (launch_clear_reverse)
+// next: the state after this step in the same binning (its cells and
+// offsets, written by the forward), or null: the push is then recomputed
 void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
                           const BinBufs &bb, int max_items, const long long *N, const float *nbar_next, float *lx,
                           float *lv, float *nbar, int *dlist, int *dcount, const uint32_t *amax_prev,
-                          uint32_t *amax_cur, double *partial, double *dacc, uint32_t *err);
+                          uint32_t *amax_cur, double *partial, double *dacc, uint32_t *err,
+                          const Store *next = nullptr);
 // largest node-cotangent contribution of a reverse step, measured only (the
 // fixed-point scale of the first reverse step); lx, lv are read only
 void launch_adjoint_scale(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,

@@ -26,6 +26,8 @@
 #include "pic_internal.h"
 #include "pic_adjoint_dev.h"
 
+#include <type_traits>
+
 namespace pic {
 
 // ---------------------------------------------------------------------------
@@ -1293,15 +1295,24 @@ __device__ __forceinline__ void load_adjoint_state(const StoreView &sv, const fl
 struct AdjLoad {
   PState q;
   float ln[3], lv[3];
+  int pcn;      // KNOWN: the next state's cell word and offsets
+  float fn[3];
 };
-template <int ND>
+template <int ND, bool KNOWN = false>
 __device__ __forceinline__ void load_adjoint_any(const StoreView &sv, const float *__restrict__ lx,
-                                                 const float *__restrict__ lv, int cap, int p, AdjLoad &a) {
+                                                 const float *__restrict__ lv, int cap, int p, AdjLoad &a,
+                                                 const int *__restrict__ pc_next = nullptr,
+                                                 const float *__restrict__ off_next = nullptr) {
   load_state_any<ND, true>(sv, p, a.q);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     a.ln[d] = d < ND ? lx[d * cap + p] : 0.0f;
     a.lv[d] = lv[d * cap + p];
+  }
+  if (KNOWN) {
+    a.pcn = pc_next[p];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) a.fn[d] = d < ND ? off_next[d * cap + p] : 0.0f;
   }
 }
 
@@ -1395,7 +1406,8 @@ __device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P,
                                                      const PState &q, const Dens &dens, bool has_next,
                                                      const Next &next, float ln[3], float lvv[3], float lf[3],
                                                      float th[5], int B[3], float t[3], float &an, float aG[3],
-                                                     uint32_t edges = 7u, const Cent &cent = Cent{}) {
+                                                     uint32_t edges = 7u, const Cent &cent = Cent{},
+                                                     const PushRecord *known = nullptr) {
   constexpr int K3 = ND == 2 ? 9 : 27;
   float cr[8];
 #pragma unroll
@@ -1440,7 +1452,9 @@ __device__ __forceinline__ uint32_t adjoint_on_block(const Geo &g, const Pot &P,
     }
   }
   PushRecord r;
-  const uint32_t e_push = recompute_push<ND, GEN>(g, P, idx, q.f, q.v, nh, Gp, r, edges);
+  uint32_t e_push = 0;
+  if (known) r = *known;  // the forward's own result, read from the next state
+  else e_push = recompute_push<ND, GEN>(g, P, idx, q.f, q.v, nh, Gp, r, edges);
   if (has_next) {
     int l2[3] = {0, 0, 0};
 #pragma unroll
@@ -1536,6 +1550,12 @@ __device__ __forceinline__ void block_reduce_add(double v[NF], double *__restric
 // PLANES: the window also holds the centre-gradient planes (staged once per
 // item, as in the forward step) and each particle reads its 2^ND centres'
 // gradients from them instead of building them from its 3^ND node block.
+// pc_next, off_next: the state after the step in the same binning, or null.
+// Given, the items whose window reaches no reflecting wall (where nothing can
+// reflect) read each particle's push from it instead of recomputing it: the
+// new cell and offset are the forward's own bits.  The two kinds of item run
+// separate copies of the particle loop, so that neither carries the other's
+// registers.
 template <int ND, bool MAXONLY, bool GEN, bool PLANES>
 __global__ void __launch_bounds__(256, 4) k_adjoint_tiled(Pot P, Batch b, Store s, const Item *__restrict__ items,
                                                        const int *__restrict__ num_items,
@@ -1545,7 +1565,9 @@ __global__ void __launch_bounds__(256, 4) k_adjoint_tiled(Pot P, Batch b, Store 
                                                        int *__restrict__ dlist, int *__restrict__ dcount,
                                                        const uint32_t *__restrict__ amax_prev,
                                                        uint32_t *__restrict__ amax_cur,
-                                                       double *__restrict__ partial, uint32_t *__restrict__ err) {
+                                                       double *__restrict__ partial, uint32_t *__restrict__ err,
+                                                       const int *__restrict__ pc_next,
+                                                       const float *__restrict__ off_next) {
   constexpr int K3 = ND == 2 ? 9 : 27;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t s_amax;
@@ -1564,6 +1586,12 @@ __global__ void __launch_bounds__(256, 4) k_adjoint_tiled(Pot P, Batch b, Store 
   const Geo g = sd.g;
   const TileGeo tg = sd.tg;
   const Window w = make_window<ND>(tg, it.tile - sd.tile_off);
+  // axes along which the window reaches a wall or the periodic seam (uniform)
+  const uint32_t edges = __builtin_amdgcn_readfirstlane(window_edges<ND>(g, w));
+  uint32_t walls = 0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) walls |= g.bc[d] ? (1u << d) : 0u;
+  const bool known = !MAXONLY && pc_next != nullptr && (edges & walls) == 0u;
   unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);  // [nW] node cotangent, fixed point
   float *dw = reinterpret_cast<float *>(acc + w.nW);  // [nW] node densities of step n
   float *nx = dw + w.nW;                              // [nW] kfac * nbar of step n+1
@@ -1594,18 +1622,20 @@ __global__ void __launch_bounds__(256, 4) k_adjoint_tiled(Pot P, Batch b, Store 
   const StoreView sv = view_of(s, s);
   uint32_t e_all = 0;
   float thf[5] = {0.f, 0.f, 0.f, 0.f, 0.f};  // this thread's parameter terms (chunk / 256 particles at most)
-  // axes along which the window reaches a wall or the periodic seam (uniform)
-  const uint32_t edges = __builtin_amdgcn_readfirstlane(window_edges<ND>(g, w));
   // loads for the next round are issued before the current round is computed
   const int last = it.end - 1;
+  auto particle_loop = [&](auto known_tag) {
+  constexpr bool KNOWN = decltype(known_tag)::value;
   AdjLoad cur, nxt;
-  load_adjoint_any<ND>(sv, lx, lv, cap, min(it.start + (int)threadIdx.x, last), cur);
+  load_adjoint_any<ND, KNOWN>(sv, lx, lv, cap, min(it.start + (int)threadIdx.x, last), cur, pc_next, off_next);
   for (int base = it.start; base < it.end; base += blockDim.x) {
     const int p = base + (int)threadIdx.x;
     const bool live = p < it.end;
-    load_adjoint_any<ND>(sv, lx, lv, cap, min(p + (int)blockDim.x, last), nxt);
+    load_adjoint_any<ND, KNOWN>(sv, lx, lv, cap, min(p + (int)blockDim.x, last), nxt, pc_next, off_next);
     const PState q = cur.q;
     float ln[3] = {cur.ln[0], cur.ln[1], cur.ln[2]}, lvv[3] = {cur.lv[0], cur.lv[1], cur.lv[2]};
+    const int pcn = cur.pcn;
+    const float fn[3] = {cur.fn[0], cur.fn[1], cur.fn[2]};
     cur = nxt;
     int idx[3], l[3];
     unpack_cell<ND>(tg, q.pc, idx);
@@ -1614,12 +1644,23 @@ __global__ void __launch_bounds__(256, 4) k_adjoint_tiled(Pot P, Batch b, Store 
     if (inside) {
       float lf[3] = {0.f, 0.f, 0.f}, th[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, t[3], an, aG[3];
       int B[3];
+      // KNOWN: the new cell and offset are the forward's own bits, and
+      // nothing reflects
+      PushRecord kr;
+      if (KNOWN) {
+        unpack_cell<ND>(tg, pcn, kr.idx2);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          kr.f2[d] = fn[d];
+          kr.sgn[d] = 1.0f;
+        }
+      }
       if (PLANES)
         e_all |= adjoint_on_block<ND, GEN>(g, P, idx, l, q, dens, nbn != nullptr, next, ln, lvv, lf, th, B, t, an, aG,
-                                           edges, cent);
+                                           edges, cent, KNOWN ? &kr : nullptr);
       else
         e_all |= adjoint_on_block<ND, GEN>(g, P, idx, l, q, dens, nbn != nullptr, next, ln, lvv, lf, th, B, t, an, aG,
-                                           edges);
+                                           edges, NoCentres{}, KNOWN ? &kr : nullptr);
       if (!MAXONLY) {  // the particle's cotangents and parameter terms, before its node block
 #pragma unroll
         for (int d = 0; d < ND; ++d) lx[d * cap + p] = lf[d];
@@ -1661,6 +1702,9 @@ __global__ void __launch_bounds__(256, 4) k_adjoint_tiled(Pot P, Batch b, Store 
       }
     }
   }
+  };
+  if (known) particle_loop(std::true_type{});
+  else particle_loop(std::false_type{});
   // largest single contribution of this block (the next step's scale)
   vmax = fmaxf(vmax * ldexpf(1.0f, -sexp), vmax_u);
   for (int o = 32; o > 0; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o, 64));
@@ -1890,7 +1934,9 @@ void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot
                           const BinBufs &bb, int max_items, const long long *N, const float *nbar_next,
                           float *lx, float *lv, float *nbar, int *dlist, int *dcount,
                           const uint32_t *amax_prev, uint32_t *amax_cur, double *partial, double *dacc,
-                          uint32_t *err) {
+                          uint32_t *err, const Store *next) {
+  const int *pc_next = next ? next->pc : nullptr;
+  const float *off_next = next ? next->off : nullptr;
   if (max_items <= 0) return;
   const bool planes = adjoint_planes(tg, ndim);
   const size_t lds = adjoint_lds_bytes(tg, ndim, planes);
@@ -1900,7 +1946,8 @@ void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot
   PIC_ND(ndim, (k_adjoint_tiled<ND, false, GN, PL><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, \
                                                                                   N, nbar_next, lx, lv, nbar,    \
                                                                                   dlist, dcount, amax_prev,      \
-                                                                                  amax_cur, partial, err)))
+                                                                                  amax_cur, partial, err,        \
+                                                                                  pc_next, off_next)))
   if (P.kind != 0 || P.lattice != 0) {
     if (planes) PIC_ADJT(true, true);
     else PIC_ADJT(true, false);
@@ -1925,7 +1972,8 @@ void launch_adjoint_scale(hipStream_t st, int ndim, const TileGeo &tg, const Pot
   PIC_ND(ndim, (k_adjoint_tiled<ND, true, GN, false><<<max_items, 256, lds, st>>>(P, b, s, bb.items, bb.num_items, \
                                                                                     N, nbar_next, lx, lv, nullptr,  \
                                                                                     nullptr, nullptr, amax, amax,   \
-                                                                                    nullptr, nullptr)))
+                                                                                    nullptr, nullptr, nullptr,      \
+                                                                                    nullptr)))
   if (P.kind != 0 || P.lattice != 0) PIC_ADJS(true);
   else PIC_ADJS(false);
 #undef PIC_ADJS
