@@ -1300,7 +1300,7 @@ size_t pic_backward_bytes(pic_ctx_t *ctx, int32_t every) {
   if (!ctx || !ctx->tiled || ctx->nslab != 1 || every < 1) return 0;
   const size_t cap = (size_t)ctx->cap, nn = (size_t)ctx->nnodes;
   return segment_scratch_bytes(ctx, every) + align_up(4 * cap * ctx->ndim) + align_up(4 * cap * 3) +
-         2 * align_up(4 * nn);
+         3 * align_up(4 * nn);
 }
 
 int pic_forward_record(pic_ctx_t *ctx, pic_particles_t *p, int32_t nsteps, int32_t every, void *record,
@@ -1441,8 +1441,12 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
   char *N0 = traj + sb * (size_t)every;
   float *lx = reinterpret_cast<float *>(scr + segment_scratch_bytes(ctx, every));
   float *lv = reinterpret_cast<float *>(reinterpret_cast<char *>(lx) + align_up(4 * (size_t)cap * nd));
-  float *nbA = reinterpret_cast<float *>(reinterpret_cast<char *>(lv) + align_up(4 * (size_t)cap * 3));
-  float *nbB = reinterpret_cast<float *>(reinterpret_cast<char *>(nbA) + align_up(4 * nn));
+  // node cotangents of three consecutive reverse steps: each step reads the
+  // later step's, accumulates its own and clears the earlier step's
+  float *nb3[3];
+  nb3[0] = reinterpret_cast<float *>(reinterpret_cast<char *>(lv) + align_up(4 * (size_t)cap * 3));
+  nb3[1] = reinterpret_cast<float *>(reinterpret_cast<char *>(nb3[0]) + align_up(4 * nn));
+  nb3[2] = reinterpret_cast<float *>(reinterpret_cast<char *>(nb3[1]) + align_up(4 * nn));
   if ((rc = bind_counts(ctx, p))) return rc;
   const Batch b = batch_of(ctx, n);
   ensure_grid_blocks(ctx);
@@ -1470,7 +1474,10 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
   launch_fill64(ctx->stream, reinterpret_cast<long long *>(ctx->partial), 8 * max_items);
   const Geo &g = ctx->geo;
   const float *nbar_next = nullptr;
-  float *nb_cur = nbA, *nb_other = nbB;
+  // the first reverse step's node cotangents and counters start at zero; each
+  // later step's are cleared by the step before it
+  launch_clear_reverse(ctx->stream, nb3[(nsteps - 1) % 3], ctx->nnodes, ctx->drift, ctx->amax + (nsteps & 1));
+  launch_fill32(ctx->stream, ctx->drift + 1, 1);
   for (int j = R.nck - 1; j >= 0; --j) {
     const int s0 = j * every, len = std::min(every, nsteps - s0);
     const Store ref = ref_of(j);
@@ -1495,6 +1502,8 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
         launch_step_tiled(ctx->stream, nd, ctx->sd[0].tg, ctx->P, ctx->dcs[0], b, in, out, bb, step_grid(ctx, n),
                           Nk(k), Nk(k + 1), Nk(k + 2), dr, ctx->partial, false, ctx->err);
       }
+      // the recompute's drifter counters are the reverse steps' too
+      launch_fill32(ctx->stream, ctx->drift, 2);
       if ((rc = check_launch(ctx, "recompute"))) return rc;
     }
     // reverse steps of the segment
@@ -1508,7 +1517,8 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
       if (step == nsteps - 1)  // seed the fixed-point scale of the first reverse step
         launch_adjoint_scale(ctx->stream, nd, ctx->sd[0].tg, P, b, slot(k), bb, (int)max_items, Nk(k), nbar_next, lx,
                              lv, amax_prev);
-      launch_clear_reverse(ctx->stream, nb_cur, ctx->nnodes, ctx->drift, amax_cur);
+      float *nb_cur = nb3[step % 3];
+      int *dcount = ctx->drift + (step & 1);
       // the state after this step in this segment's binning: the segment's
       // next slot, or the next checkpoint's state unless that one was re-binned
       Store after;
@@ -1520,11 +1530,12 @@ int pic_backward_record(pic_ctx_t *ctx, const pic_particles_t *p, int32_t nsteps
         after = state_at(ctx, rec + R.stride * (j + 1) + R.state, ref);
         known = &after;
       }
+      const bool more = step > 0;  // the next reverse step's buffers: cleared by this one
       launch_adjoint_tiled(ctx->stream, nd, ctx->sd[0].tg, P, b, slot(k), bb, (int)max_items, Nk(k), nbar_next, lx, lv,
-                           nb_cur, ctx->drift + 4, ctx->drift, amax_prev, amax_cur, ctx->partial, ctx->dacc, ctx->err,
-                           known);
+                           nb_cur, ctx->drift + 4, dcount, amax_prev, amax_cur, ctx->partial, ctx->dacc, ctx->err,
+                           known, more ? nb3[(step + 2) % 3] : nullptr, ctx->nnodes,
+                           more ? ctx->drift + ((step + 1) & 1) : nullptr, more ? amax_prev : nullptr);
       nbar_next = nb_cur;
-      std::swap(nb_cur, nb_other);
       if ((rc = check_launch(ctx, "reverse step"))) return rc;
     }
     // into the previous segment's order (through the caller's order, with

@@ -144,14 +144,18 @@ void launch_fill32(hipStream_t s, int *a, int64_t n);
 size_t adjoint_lds_bytes(const TileGeo &tg, int ndim, bool planes);
 // partial: per-item parameter sums, ACCUMULATED over the calls (clear once);
 // N: the step's node sums; nbar, dcount and amax_cur must be zero on entry
-// (launch_clear_reverse)
+// (launch_clear_reverse, or the previous reverse step's clears below)
 // next: the state after this step in the same binning (its cells and
 // offsets, written by the forward), or null: the push is then recomputed
+// nbar_clear [nclear], dcount_clear, amax_clear (or null): the next reverse
+// step's nbar, dcount and amax_cur, zeroed by this step's kernels; none may
+// alias a buffer this step reads or writes
 void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,
                           const BinBufs &bb, int max_items, const long long *N, const float *nbar_next, float *lx,
                           float *lv, float *nbar, int *dlist, int *dcount, const uint32_t *amax_prev,
                           uint32_t *amax_cur, double *partial, double *dacc, uint32_t *err,
-                          const Store *next = nullptr);
+                          const Store *next = nullptr, float *nbar_clear = nullptr, int64_t nclear = 0,
+                          int *dcount_clear = nullptr, uint32_t *amax_clear = nullptr);
 // largest node-cotangent contribution of a reverse step, measured only (the
 // fixed-point scale of the first reverse step); lx, lv are read only
 void launch_adjoint_scale(hipStream_t st, int ndim, const TileGeo &tg, const Pot &P, const Batch &b, const Store &s,

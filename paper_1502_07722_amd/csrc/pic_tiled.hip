@@ -1550,6 +1550,8 @@ __device__ __forceinline__ void block_reduce_add(double v[NF], double *__restric
 // PLANES: the window also holds the centre-gradient planes (staged once per
 // item, as in the forward step) and each particle reads its 2^ND centres'
 // gradients from them instead of building them from its 3^ND node block.
+// nbar_clear (nclear floats, or null): the next reverse step's node
+// cotangents, zeroed here a share per block (nothing of this step reads them).
 // pc_next, off_next: the state after the step in the same binning, or null.
 // Given, the items whose window reaches no reflecting wall (where nothing can
 // reflect) read each particle's push from it instead of recomputing it: the
@@ -1567,10 +1569,16 @@ __global__ void __launch_bounds__(256, 4) k_adjoint_tiled(Pot P, Batch b, Store 
                                                        uint32_t *__restrict__ amax_cur,
                                                        double *__restrict__ partial, uint32_t *__restrict__ err,
                                                        const int *__restrict__ pc_next,
-                                                       const float *__restrict__ off_next) {
+                                                       const float *__restrict__ off_next,
+                                                       float *__restrict__ nbar_clear, int64_t nclear) {
   constexpr int K3 = ND == 2 ? 9 : 27;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t s_amax;
+  if (nbar_clear) {
+    const int64_t share = (nclear + gridDim.x - 1) / gridDim.x, lo = (int64_t)blockIdx.x * share;
+    const int64_t hi = min(nclear, lo + share);
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) nbar_clear[k] = 0.0f;
+  }
   if ((int)blockIdx.x >= *num_items) return;
   const int sexp = MAXONLY ? 0 : adj_scale_exp(*amax_prev);
   const float to_fix = ldexpf(1.0f, sexp);    // exact power of two (sexp within float range)
@@ -1730,14 +1738,21 @@ __global__ void __launch_bounds__(256, 4) k_adjoint_tiled(Pot P, Batch b, Store 
 // computation on the node sums (densities folded like the window's), scatters
 // as global float atomics; parameter terms into dacc[0..4].
 template <int ND, bool GEN>
+// dcount_clear, amax_clear (or null): the next reverse step's drifter count
+// and largest-contribution slot, zeroed here (neither is read in this launch).
 __global__ void __launch_bounds__(256) k_adjoint_drifters(Pot P, Batch b, Store s, const int *__restrict__ dlist,
                                                           const int *__restrict__ dcount,
                                                           const long long *__restrict__ Ncur,
                                                           const float *__restrict__ nbar_next,
                                                           float *__restrict__ lx, float *__restrict__ lv,
                                                           float *__restrict__ nbar, double *__restrict__ dacc,
-                                                          uint32_t *__restrict__ err) {
+                                                          uint32_t *__restrict__ err, int *__restrict__ dcount_clear,
+                                                          uint32_t *__restrict__ amax_clear) {
   constexpr int K3 = ND == 2 ? 9 : 27;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (dcount_clear) *dcount_clear = 0;
+    if (amax_clear) *amax_clear = 0u;
+  }
   const int n = *dcount;
   const int cap = (int)s.cap;
   const StoreView sv = view_of(s, s);
@@ -1934,7 +1949,8 @@ void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot
                           const BinBufs &bb, int max_items, const long long *N, const float *nbar_next,
                           float *lx, float *lv, float *nbar, int *dlist, int *dcount,
                           const uint32_t *amax_prev, uint32_t *amax_cur, double *partial, double *dacc,
-                          uint32_t *err, const Store *next) {
+                          uint32_t *err, const Store *next, float *nbar_clear, int64_t nclear, int *dcount_clear,
+                          uint32_t *amax_clear) {
   const int *pc_next = next ? next->pc : nullptr;
   const float *off_next = next ? next->off : nullptr;
   if (max_items <= 0) return;
@@ -1947,17 +1963,20 @@ void launch_adjoint_tiled(hipStream_t st, int ndim, const TileGeo &tg, const Pot
                                                                                   N, nbar_next, lx, lv, nbar,    \
                                                                                   dlist, dcount, amax_prev,      \
                                                                                   amax_cur, partial, err,        \
-                                                                                  pc_next, off_next)))
+                                                                                  pc_next, off_next, nbar_clear, \
+                                                                                  nclear)))
   if (P.kind != 0 || P.lattice != 0) {
     if (planes) PIC_ADJT(true, true);
     else PIC_ADJT(true, false);
     PIC_ND(ndim, (k_adjoint_drifters<ND, true><<<kDriftBlocks, 256, 0, st>>>(P, b, s, dlist, dcount, N, nbar_next, lx,
-                                                                             lv, nbar, dacc, err)));
+                                                                             lv, nbar, dacc, err, dcount_clear,
+                                                                             amax_clear)));
   } else {
     if (planes) PIC_ADJT(false, true);
     else PIC_ADJT(false, false);
     PIC_ND(ndim, (k_adjoint_drifters<ND, false><<<kDriftBlocks, 256, 0, st>>>(P, b, s, dlist, dcount, N, nbar_next,
-                                                                              lx, lv, nbar, dacc, err)));
+                                                                              lx, lv, nbar, dacc, err, dcount_clear,
+                                                                              amax_clear)));
   }
 #undef PIC_ADJT
 }
@@ -1973,7 +1992,7 @@ void launch_adjoint_scale(hipStream_t st, int ndim, const TileGeo &tg, const Pot
                                                                                     N, nbar_next, lx, lv, nullptr,  \
                                                                                     nullptr, nullptr, amax, amax,   \
                                                                                     nullptr, nullptr, nullptr,      \
-                                                                                    nullptr)))
+                                                                                    nullptr, nullptr, 0)))
   if (P.kind != 0 || P.lattice != 0) PIC_ADJS(true);
   else PIC_ADJS(false);
 #undef PIC_ADJS
