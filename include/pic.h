@@ -415,8 +415,9 @@ int pic_deposit_vjp(pic_ctx_t *ctx, const pic_particles_t *state, const float *n
  * pic_backward_record then runs the whole reverse sweep for that run: for
  * each checkpoint segment, from the last, it recomputes the segment's states
  * and node sums out of place into scratch (pic_backward_bytes() bytes,
- * caller-owned device memory, 256-byte aligned) and applies the reverse step
- * of pic_adjoint_step to each, last step first.
+ * caller-owned device memory, 256-byte aligned; a record that keeps every
+ * state, pic_set_record_states, has them already) and applies the reverse
+ * step of pic_adjoint_step to each, last step first.
  * In:  lam_x [ndim][n] = dJ/d(offset) of the final state, lam_v [3][n] =
  *      dJ/dv(nsteps - 1/2) (caller order; J must not depend on the final
  *      node densities).
