@@ -81,6 +81,9 @@ def test_null_context_calls_fail_cleanly():
     assert B.lib.pic_deposit(None, C.byref(s), None) == B.PIC_EINVAL
     assert B.lib.pic_step(None, C.byref(s), 1, None, 0) == B.PIC_EINVAL
     assert B.lib.pic_sync(None) == B.PIC_EINVAL
+    assert B.lib.pic_set_record_states(None, 1) == B.PIC_EINVAL
+    assert B.lib.pic_record_bytes(None, 10, 2) == 0
+    assert B.lib.pic_backward_bytes(None, 2) == 0
     assert B.lib.pic_last_error(None) == b"context is NULL"
 
 
