@@ -117,8 +117,9 @@ def test_full_size_gradient_matches_gpu_central_difference(B):
     sig = torch.from_numpy(p.sigma.astype(np.float32)).to(dev)
     wq = torch.from_numpy(p.wq).to(dev)
 
-    def J_of(pot, F, grad=False):
+    def J_of(pot, F, grad=False, all_states=False):
         ctx = B.Context(g, pot, wl.dt, p.n)
+        ctx.pic_set_record_states(all_states)
         theta = A.theta_of(pot).requires_grad_(grad)
         fl = torch.tensor(F, dtype=torch.float64, device=dev, requires_grad=grad)
         J, _, _ = A.crater_objective(ctx, cell, off0, vth, xi, sig, fref, fl, wq, theta, nsteps, every, y_s, tau)
@@ -137,3 +138,7 @@ def test_full_size_gradient_matches_gpu_central_difference(B):
           f"dJ/dF adjoint {dJdF:.6e} GPU central difference {fdF:.6e}", flush=True)
     assert abs(dJdD - fdD) <= 2e-3 * abs(fdD)
     assert abs(dJdF - fdF) <= 2e-3 * abs(fdF)
+    # a record that keeps every state: the same sweep without recompute, equal
+    # up to the order of float atomic sums
+    _, aD, aF = J_of(pot, fref, grad=True, all_states=True)
+    assert abs(aD - dJdD) <= 1e-5 * abs(dJdD) and abs(aF - dJdF) <= 1e-5 * abs(dJdF), (aD, dJdD, aF, dJdF)
