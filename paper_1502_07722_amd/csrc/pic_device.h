@@ -233,22 +233,6 @@ __device__ __forceinline__ float phi_hat(const Pot &P, float s) {
   return s > 1.0f ? __builtin_fmaf(P.s_rep, u, P.s_rep - P.c_att) : P.c_att * u;
 }
 
-// Hexagonal close-packed neighbour k along grid direction v (weight w: the
-// number of the 12 neighbours with this in-plane direction): q_k = c g.v with
-// c = 2^(1/6), clamped; s = r0 / d = (q / c) (1 - q_k / 2).
-template <int ND>
-__device__ __forceinline__ void hcp_term(const Pot &P, float qc, const float g[3], float v0, float v1, float v2,
-                                         float w, float F[3], float &e, bool bond) {
-  float gu = g[0] * v0 + g[1] * v1;
-  if (ND == 3) gu = __builtin_fmaf(g[2], v2, gu);
-  float qk = fminf(fmaxf(1.12246204831f * gu, -P.gclamp), P.gclamp);
-  float s = qc * __builtin_fmaf(-0.5f, qk, 1.0f);
-  float f = w * dphi_hat<true>(P, s);
-  F[0] = __builtin_fmaf(f, v0, F[0]);
-  F[1] = __builtin_fmaf(f, v1, F[1]);
-  if (ND == 3) F[2] = __builtin_fmaf(f, v2, F[2]);
-  if (bond) e = __builtin_fmaf(0.5f * w, phi_hat<true>(P, s), e);
-}
 
 // The 12 neighbours in grid axes: 3D (basal 1, basal 2, c) = (x, y, z); 2D
 // (basal 1, c) = (x, y), the basal-2 axis unresolved, so neighbours that
@@ -277,14 +261,43 @@ static __constant__ float kHcp2[10][4] = {
     {0.0f, 0.816496580927726f, 0.0f, 1.0f},   {0.5f, -0.816496580927726f, 0.0f, 1.0f},
     {-0.5f, -0.816496580927726f, 0.0f, 1.0f}, {0.0f, -0.816496580927726f, 0.0f, 1.0f}};
 
+// Hexagonal close-packed neighbour k along grid direction v (weight w: the
+// number of the 12 neighbours with this in-plane direction): q_k = c g.v with
+// c = 2^(1/6), clamped; s = r0 / d = (q / c) (1 - q_k / 2).
 template <int ND>
 __device__ __forceinline__ void hcp_force(const Pot &P, float q, const float g[3], float F[3], float &e, bool bond) {
   const float qc = q * 0.890898718140339f;  // q / 2^(1/6)
-  const int n = ND == 3 ? 12 : 10;
+  // The neighbours come in pairs that share most of their arithmetic: v and
+  // -v (2D, and the basal plane in 3D), whose projections are opposite and
+  // whose forces add as (f+ - f-) v; and, out of the 3D basal plane, mirror
+  // images (v0, v1, +-v2), which share g0 v0 + g1 v1 and add as
+  // ((f+ + f-) v0, (f+ + f-) v1, (f+ - f-) v2).  The first rows of the pairs:
+  // 3D 0, 1, 2 (partners 3, 4, 5: -v), 6, 7, 8 (partners 9, 10, 11: mirror);
+  // 2D 0, 2, 4, 5, 6 (partners 1, 3, 8, 7, 9: -v).
+  const int npairs = ND == 3 ? 6 : 5;
 #pragma unroll
-  for (int k = 0; k < n; ++k) {
-    const float *v = ND == 3 ? kHcp3[k] : kHcp2[k];
-    hcp_term<ND>(P, qc, g, v[0], v[1], v[2], v[3], F, e, bond);
+  for (int k = 0; k < npairs; ++k) {
+    const float *v = ND == 3 ? kHcp3[k < 3 ? k : k + 3] : kHcp2[k < 2 ? 2 * k : k + 2];
+    const float w = v[3];
+    const bool mirror = ND == 3 && k >= 3;  // v2 != 0: the partner is (v0, v1, -v2)
+    const float a = g[0] * v[0] + g[1] * v[1];
+    const float c = ND == 3 ? g[2] * v[2] : 0.0f;
+    const float gp = mirror ? a + c : a, gm = mirror ? a - c : -a;
+    const float qp = fminf(fmaxf(1.12246204831f * gp, -P.gclamp), P.gclamp);
+    const float qm = fminf(fmaxf(1.12246204831f * gm, -P.gclamp), P.gclamp);
+    const float sp = qc * __builtin_fmaf(-0.5f, qp, 1.0f), sm = qc * __builtin_fmaf(-0.5f, qm, 1.0f);
+    const float fp = w * dphi_hat<true>(P, sp), fm = w * dphi_hat<true>(P, sm);
+    if (mirror) {
+      const float fs = fp + fm;
+      F[0] = __builtin_fmaf(fs, v[0], F[0]);
+      F[1] = __builtin_fmaf(fs, v[1], F[1]);
+      F[2] = __builtin_fmaf(fp - fm, v[2], F[2]);
+    } else {
+      const float fd = fp - fm;
+      F[0] = __builtin_fmaf(fd, v[0], F[0]);
+      F[1] = __builtin_fmaf(fd, v[1], F[1]);
+    }
+    if (bond) e = __builtin_fmaf(0.5f * w, phi_hat<true>(P, sp) + phi_hat<true>(P, sm), e);
   }
 }
 
